@@ -1,0 +1,175 @@
+"""Pins of the oracle's preconditioner (Sec. 4.2: eq. PJ and the exact
+elimination of the particle blocks), FGMRES solve and parameter gradients."""
+import numpy as np
+import pytest
+
+import oracle as O
+import p4d_inputs as pi
+
+
+def tiny(seed=0, sigma_log=0.5, nx=4, ny=4, nz=6, nr=(4, 5)):
+    return pi.make_custom(nx, ny, nz, nr, seed=seed, sigma_log=sigma_log,
+                          na=2, ns=2, corr_cells=2.0)
+
+
+def schur_blocks(p, A):
+    """Dense blocks of A split into macro (y) and particle (s) unknowns."""
+    nm = p.offsets[3]
+    return A[:nm, :nm], A[:nm, nm:], A[nm:, :nm], A[nm:, nm:]
+
+
+def field_ranges(p):
+    o = p.offsets
+    return [(o[0], o[1]), (o[1], o[2]), (o[2], o[3])]
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_schur_preconditioner_is_exact_block_ldu(seed, transpose):
+    """With direct block solves (single-level grids), P^-1 of mode SCHUR is
+    the inverse of [[St + Ays Ass^-1 Asy, Ays], [Asy, Ass]] with St the
+    field-block diagonal of the exact Schur complement
+    S = Ayy - Ays Ass^-1 Asy, all blocks taken from the assembled A."""
+    p = tiny(seed)
+    orc = O.Oracle(p).setup(pc=O.PC_SCHUR)
+    A = orc.dense()
+    Ayy, Ays, Asy, Ass = schur_blocks(p, A)
+    S = Ayy - Ays @ np.linalg.solve(Ass, Asy)
+    St = np.zeros_like(S)
+    for a, b in field_ranges(p):
+        St[a:b, a:b] = S[a:b, a:b]
+    P = np.block([[St + Ays @ np.linalg.solve(Ass, Asy), Ays], [Asy, Ass]])
+    if transpose:
+        P = P.T
+    r = np.random.default_rng(seed + 10).standard_normal(p.N)
+    z = orc.apply_pc(r, transpose)
+    ref = np.linalg.solve(P, r)
+    assert np.allclose(z, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_block_jacobi_is_eq_PJ(transpose):
+    """Mode BJ with direct block solves applies diag(A_phis, A_phie, A_ce,
+    A_cs)^-1 (eq. PJ)."""
+    p = tiny(3)
+    orc = O.Oracle(p).setup(pc=O.PC_BJ)
+    A = orc.dense()
+    PJ = np.zeros_like(A)
+    o = p.offsets
+    for a, b in [(o[0], o[1]), (o[1], o[2]), (o[2], o[3]), (o[3], o[5])]:
+        PJ[a:b, a:b] = A[a:b, a:b]
+    if transpose:
+        PJ = PJ.T
+    r = np.random.default_rng(1).standard_normal(p.N)
+    ref = np.linalg.solve(PJ, r)
+    assert np.allclose(orc.apply_pc(r, transpose), ref, atol=1e-10 * np.abs(ref).max())
+
+
+def test_preconditioner_transpose_identity():
+    """<P^-1 x, y> = <x, P^-T y> with multilevel V-cycles."""
+    p = pi.make_custom(10, 9, 30, (6, 8), seed=5, sigma_log=1.0, corr_cells=3.0)
+    orc = O.Oracle(p).setup()
+    assert orc.mg_levels(2)[0][0] == (10, 9, 30) and len(orc.mg_levels(2)) >= 2
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        x, y = rng.standard_normal(p.N), rng.standard_normal(p.N)
+        assert orc.apply_pc(x) @ y == pytest.approx(x @ orc.apply_pc(y, True), rel=1e-11)
+
+
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ])
+@pytest.mark.parametrize("coarse_max", [512, 20])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_L1_solution_matches_dense_lu(pc, coarse_max, transpose):
+    p = tiny(7, nx=5, ny=4, nz=8, nr=(4, 6))
+    orc = O.Oracle(p).setup(pc=pc, rtol=1e-11, coarse_max=coarse_max, maxit=3000)
+    A = orc.dense(transpose)
+    x, info = orc.solve(p.b, transpose)
+    ref = np.linalg.solve(A, p.b)
+    assert info.status == 0
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_L2_manufactured_solution():
+    """x* smooth in the macro fields and quadratic in rho; b = A x*.  (cond(A)
+    is ~1e7 here, so residuals below ~1e-11 are not attainable.)"""
+    p = pi.make_config(1)
+    orc = O.Oracle(p).setup(rtol=1e-10)
+    h = p.h
+    k = np.repeat(np.arange(p.nz), p.nx * p.ny)
+    j = np.tile(np.repeat(np.arange(p.ny), p.nx), p.nz)
+    i = np.tile(np.arange(p.nx), p.ny * p.nz)
+    X, Y, Z = i * h, j * h, k * h
+    xs = np.zeros(p.N)
+    o = p.offsets
+    elec = (k < p.na) | (k >= p.na + p.ns)
+    phis = np.cos(np.pi * X) * np.cos(np.pi * Y) * (1 + Z)
+    xs[o[0]:o[1]] = phis[elec]
+    xs[o[0]:o[0] + p.nx * p.ny] = 0.0            # grounded layer
+    xs[o[1]:o[2]] = np.cos(2 * X) * np.sin(Y + 1) * np.cos(3 * Z)
+    xs[o[2]:o[3]] = 1 + 0.2 * np.cos(np.pi * Z)
+    for el, nn, off in ((0, p.n_ea, o[3]), (1, p.n_ec, o[4])):
+        rho = O.radial_mesh(p.nr[el], p.theta_bar[el])
+        base = 0.5 + 0.1 * np.arange(nn) / nn
+        xs[off:off + p.nr[el] * nn] = (base[None, :] + 0.3 * rho[:, None] ** 2).reshape(-1)
+    b = orc.apply(xs)
+    x, info = orc.solve(b)
+    assert info.status == 0
+    # relative error <= cond(A) * rtol; measured ~2e-5 at this rtol
+    assert np.linalg.norm(x - xs) <= 1e-4 * np.linalg.norm(xs)
+    # per field too; the error sits in the near-null modes (e.g. a constant
+    # shift of c_e, whose only control is the small storage term)
+    o = p.offsets
+    for a, b2 in zip(o[:-1], o[1:]):
+        if b2 > a:
+            assert np.linalg.norm(x[a:b2] - xs[a:b2]) <= 1e-4 * np.linalg.norm(xs[a:b2])
+
+
+def test_zero_rhs_and_iteration_cap():
+    p = tiny(2)
+    orc = O.Oracle(p).setup()
+    x, info = orc.solve(np.zeros(p.N))
+    assert info.status == 0 and info.iters == 0 and not x.any()
+    orc.setup(maxit=2)
+    x, info = orc.solve(p.b)
+    assert info.status == 1 and info.iters == 2
+
+
+def test_schur_mode_beats_block_jacobi_on_C1():
+    p = pi.make_config(1)
+    o1 = O.Oracle(p).setup(pc=O.PC_SCHUR)
+    x1, i1 = o1.solve(p.b)
+    o2 = O.Oracle(p).setup(pc=O.PC_BJ)
+    x2, i2 = o2.solve(p.b)
+    assert i1.status == 0 and i2.status == 0
+    assert i1.iters < i2.iters
+    assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x1)
+
+
+def test_J2_gradient_matches_finite_differences():
+    """dJ/dsigma and dJ/dDs from the adjoint (A^T lambda = w) against central
+    differences of forward solves, J = mean phi_s on the cathode top face."""
+    p = pi.make_custom(6, 5, 13, (6, 5), seed=8, sigma_log=1.0, corr_cells=3.0)
+    w = pi.functional_weights(p)
+
+    def J(sigma, Ds):
+        o = O.Oracle(p.with_(sigma=sigma, Ds=tuple(Ds))).setup(rtol=1e-11, maxit=4000)
+        x, info = o.solve(p.b)
+        return w @ x
+
+    orc = O.Oracle(p).setup(rtol=1e-11, maxit=4000)
+    x, _ = orc.solve(p.b)
+    lam, _ = orc.solve(w, transpose=True)
+    gs, gD = orc.gradient(x, lam)
+    lay = np.repeat(np.array([0 if k + 1 < p.na else (1 if k >= p.na + p.ns else -1)
+                              for k in range(p.nz - 1)]), (p.nx - 1) * (p.ny - 1))
+    assert np.all(gs[lay < 0] == 0.0)
+    rng = np.random.default_rng(3)
+    hstep = 1e-6
+    sig0, D0 = p.sigma.copy(), np.array(p.Ds)
+    for _ in range(3):
+        v = rng.standard_normal(p.n_elem)
+        vD = rng.standard_normal(2)
+        fd = (J(sig0 * (1 + hstep * v), D0 * (1 + hstep * vD)) -
+              J(sig0 * (1 - hstep * v), D0 * (1 - hstep * vD))) / (2 * hstep)
+        ad = gs @ (sig0 * v) + gD @ (D0 * vD)
+        assert ad == pytest.approx(fd, rel=2e-5, abs=1e-12)
