@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of one linearized pseudo-4D DFN Jacobian solve on one MI355X.
+
+Workload: the homogeneous cube cell, 64 x 64 x 192 nodes (anode / separator /
+cathode 80 / 32 / 80 layers), 20 radial points per particle, N = 15,335,424
+unknowns; FP64 restarted FGMRES(30) with the particle-Schur block
+preconditioner to a true relative residual of 1e-8.  One step = preconditioner
+setup + solve (what each Newton step of a simulation has to pay), with the
+inputs already resident in device memory.
+
+Prints one JSON line: the metric is DOF*iter/s = N * iterations / step time.
+Extra fields report the FP32-preconditioned solve on the same input and on the
+lognormal-conductivity cube, the adjoint solve with gradients, per-kernel
+times and bandwidths measured with HIP events inside the timed region, and the
+CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(s, b, opts, steps, warmup, profile_mask=0):
+    import torch
+    from paper_2602_07225_amd import _lib as L
+    for _ in range(warmup):
+        s.setup(**opts)
+        s.solve(b)
+    torch.cuda.synchronize()
+    if profile_mask:
+        L.p4d_profile(s.ctx, profile_mask)
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.setup(**opts)
+        x, info = s.solve(b)
+        iters += info.iters
+        if info.status != 0:
+            raise RuntimeError(f"solve did not converge: status {info.status}")
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prof = {}
+    if profile_mask:
+        for k, name in L.KERNEL_CLASSES.items():
+            ms, n, by = L.p4d_profile_read(s.ctx, k)
+            if n:
+                prof[name] = {"ms_total": ms, "launches": n, "avg_us": 1e3 * ms / n,
+                              "bytes_per_launch": by / n,
+                              "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
+        L.p4d_profile(s.ctx, 0)
+    return x, info, iters, t, prof
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import p4d_inputs as pi
+    from paper_2602_07225_amd import P4DSolver
+    from paper_2602_07225_amd import _lib as L
+
+    torch.cuda.set_device(0)
+    p = pi.make_config(2)
+    N = p.N
+    log(f"[bench] C2 N={N}: building solver")
+    s = P4DSolver(p, restart=30)
+    b = torch.as_tensor(p.b, device="cuda")
+    fp64 = dict(pc=L.P4D_PC_SCHUR, pc_prec=L.P4D_FP64, rtol=1e-8, restart=30)
+    mask = sum(1 << k for k in L.KERNEL_CLASSES)
+    x64, info, iters, t, prof = timed_steps(s, b, fp64, args.steps, args.warmup, mask)
+    ms_step = 1e3 * t / args.steps
+    value = N * iters / t
+    log(f"[bench] FP64: {iters / args.steps:.1f} it/step, {ms_step:.2f} ms/step, "
+        f"{value:.3e} DOF*iter/s")
+
+    # dominant kernel class of the timed region
+    dom = max(prof, key=lambda k: prof[k]["ms_total"]) if prof else None
+    roofline = None
+    if dom:
+        d = prof[dom]
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                    "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]}
+
+    # setup and solve split (one extra, untimed-in-the-headline run)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.setup(**fp64)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    extras = {"setup_ms": 1e3 * t_setup,
+              "solve_ms": ms_step - 1e3 * t_setup,
+              "iters_per_solve": iters / args.steps,
+              "solve_only_DOF_iter_per_s": N * iters / args.steps / max(1e-9, (t / args.steps - t_setup)),
+              "kernels": prof}
+
+    if not args.no_extras:
+        # FP32 preconditioner (radial eliminations + V-cycles) and FP32 Z basis
+        fp32 = dict(fp64, pc_prec=L.P4D_FP32, z_fp32=1)
+        x32, i32, it32, t32, _ = timed_steps(s, b, fp32, args.steps, 1)
+        err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+        extras["fp32_precond_C2"] = {"ms_per_step": 1e3 * t32 / args.steps,
+                                     "iters_per_solve": it32 / args.steps,
+                                     "DOF_iter_per_s": N * it32 / t32,
+                                     "rel_err_vs_fp64_gpu": err,
+                                     "speedup_vs_fp64": t / t32}
+        log(f"[bench] FP32-PC C2: {1e3 * t32 / args.steps:.2f} ms/step, {it32 / args.steps:.1f} it")
+        # lognormal cube, both precisions
+        p3 = pi.make_config(3)
+        s3 = P4DSolver(p3, restart=30)
+        b3 = torch.as_tensor(p3.b, device="cuda")
+        xa, ia, ita, ta, _ = timed_steps(s3, b3, fp64, args.steps, 1)
+        xb, ib, itb, tb, _ = timed_steps(s3, b3, fp32, args.steps, 1)
+        extras["C3_lognormal"] = {
+            "fp64": {"ms_per_step": 1e3 * ta / args.steps, "iters_per_solve": ita / args.steps},
+            "fp32_precond": {"ms_per_step": 1e3 * tb / args.steps, "iters_per_solve": itb / args.steps,
+                             "rel_err_vs_fp64_gpu":
+                                 (torch.linalg.norm(xb - xa) / torch.linalg.norm(xa)).item()},
+            "speedup_fp32_vs_fp64": ta / tb}
+        log(f"[bench] C3: fp64 {1e3 * ta / args.steps:.2f} ms, fp32 {1e3 * tb / args.steps:.2f} ms")
+        del s3
+        # adjoint solve + gradients on C2 (J = mean phi_s on the cathode top face)
+        w = torch.as_tensor(pi.functional_weights(p), device="cuda")
+        s.setup(**fp64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, ia = s.solve_adjoint(w)
+        gs, gD = s.gradient(x64, lam)
+        torch.cuda.synchronize()
+        extras["adjoint_C2"] = {"ms": 1e3 * (time.perf_counter() - t0), "iters": ia.iters,
+                                "status": ia.status}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        log("[bench] CPU oracle: one full C2 solve")
+        t0 = time.perf_counter()
+        orc = O.Oracle(p).setup(rtol=1e-8)
+        xo, io = orc.solve(p.b)
+        tc = time.perf_counter() - t0
+        err = float(np.linalg.norm(x64.cpu().numpy() - xo) / np.linalg.norm(xo))
+        cpu = {"value": N * io.iters / tc, "unit": "DOF*iter/s", "cores": O.num_threads(),
+               "kind": "oracle",
+               "sample": f"one full C2 solve (setup + {io.iters} FGMRES iterations to rtol 1e-8), "
+                         f"{tc:.1f} s",
+               "gpu_vs_oracle_rel_err": err}
+        log(f"[bench] oracle: {tc:.1f} s, {io.iters} it, rel err gpu vs oracle {err:.2e}")
+
+    out = {
+        "metric": "P4D Jacobian solve time & DOF*iter/s; FP32-precond vs FP64; HBM GB/s",
+        "value": value,
+        "unit": "DOF*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "homogeneous cube cell 64x64x192 nodes, Nr=20, 15,335,424 DOF; "
+                               "FP64 FGMRES(30) + particle-Schur block preconditioner to rtol 1e-8; "
+                               "step = setup + solve",
+                   "nodes": [p.nx, p.ny, p.nz], "layers": [p.na, p.ns, p.nc], "nr": list(p.nr),
+                   "dof": N, "restart": 30, "rtol": 1e-8, "pc": "schur"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

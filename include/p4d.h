@@ -1,0 +1,205 @@
+/*
+ * p4d.h -- C ABI of the MI355X (gfx950) solver for one linearized pseudo-4D
+ * DFN (Doyle-Fuller-Newman) Jacobian system, after arXiv 2602.07225
+ * ("Scalable Preconditioners for the Pseudo-4D DFN Lithium-ion Battery
+ * Model").
+ *
+ * The system (paper Sec. 4.1, eq. blocks) couples, on a structured Q1 hex
+ * node grid, the solid potential phi_s (electrode nodes), the electrolyte
+ * potential phi_e and concentration c_e (all nodes) with one radial particle
+ * concentration profile c_s of N_r points per electrode node (Sec. 3.1,
+ * eq. FD).  It is solved by restarted flexible GMRES (Sec. 4.2) with a block
+ * preconditioner: exact tridiagonal eliminations of the particle blocks
+ * (element-wise block Jacobi, Sec. 4.2), coupled back to the macro fields
+ * through the particle surface, and one multigrid V-cycle per
+ * electrode-level field.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are DEVICE pointers (HIP global memory) of the GPU
+ *    that is current when the call is made; all other pointers are host
+ *    pointers.  Device arrays are FP64 unless stated otherwise.
+ *  - Every call only enqueues work on `stream` (a hipStream_t, passed as
+ *    void* so this header needs no HIP include) except where stated: calls
+ *    that must read device results (setup, solve) synchronize that stream.
+ *  - The caller owns all memory it passes in.  The library keeps no pointer
+ *    to caller arrays after a call returns, except the workspace given to
+ *    p4d_set_workspace, which must stay valid and untouched until the
+ *    context is destroyed or another workspace is set.
+ *  - Errors are reported by status codes only; argument checks happen before
+ *    any device work is enqueued.  p4d_last_error() gives a message.
+ *  - A context is not thread safe; calls on one context (or on contexts
+ *    sharing a workspace) must not overlap.
+ *
+ * Global vector layout (length N, paper block order phi_s, phi_e, c_e, c_s,
+ * eq. blocks):
+ *    [ phi_s (n_e) | phi_e (n_nodes) | c_e (n_nodes) |
+ *      c_s anode  (N_r,a x n_ea, index r*n_ea + j) |
+ *      c_s cathode(N_r,c x n_ec, index r*n_ec + j) ]
+ *  node id n = i + nx*(j + ny*k); the anode holds node layers k < na, the
+ *  separator na <= k < na+ns, the cathode the rest; phi_s and c_s list the
+ *  anode nodes then the cathode nodes, each in node-id order; the first
+ *  nx*ny phi_s entries (layer k = 0, the grounded face Gamma_n, eq. Dirichlet)
+ *  are identity rows.  Element e = i + (nx-1)*(j + (ny-1)*k) spans node
+ *  layers k, k+1 and is an electrode element only if both layers are.
+ */
+#ifndef P4D_H
+#define P4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    P4D_OK = 0,
+    P4D_NOT_CONVERGED = 1,      /* iteration cap reached; x holds the last iterate */
+    P4D_BREAKDOWN = 2,          /* Krylov breakdown without convergence            */
+    P4D_ERR_INVALID_ARG = -1,   /* bad pointer, size or option; nothing enqueued   */
+    P4D_ERR_OOM = -2,           /* workspace too small                             */
+    P4D_ERR_HIP = -3,           /* a HIP runtime call failed                       */
+    P4D_ERR_STATE = -4,         /* call out of order (e.g. solve before setup)     */
+    P4D_ERR_NONFINITE = -5      /* NaN/Inf met in the right-hand side or residual  */
+} p4d_status;
+
+typedef enum {
+    P4D_PC_SCHUR = 0,   /* particle blocks eliminated exactly, field-block diagonal
+                           of the Schur complement to the V-cycles                 */
+    P4D_PC_BJ = 1       /* block Jacobi, paper eq. (PJ)                            */
+} p4d_pc_type;
+
+typedef enum { P4D_FP64 = 0, P4D_FP32 = 1 } p4d_prec;
+
+/* Problem geometry and scalars, all nondimensional.  The particle radius is
+ * scaled to 1; Ds = D_s dt / R_s^2; theta_bar = last/first radial interval. */
+typedef struct {
+    int32_t nx, ny, nz;        /* node counts, nx, ny >= 2, nz >= 5              */
+    int32_t na, ns;            /* anode and separator node layers (na >= 2)      */
+    int32_t nr[2];             /* radial points per particle, anode/cathode, 3..64 */
+    double Ds[2];              /* particle diffusivity, anode/cathode            */
+    double theta_bar[2];       /* radial grading, (0, 1]                          */
+    double dt;                 /* backward-Euler step                             */
+    double chi;                /* diffusion-potential factor 2(1 - t+)            */
+    double tc;                 /* electrolyte source factor (1 - t+)              */
+    double lambda_c;           /* scale of the surface coupling                   */
+    double eps_elec, eps_sep;  /* porosity in electrode and separator elements    */
+} p4d_problem_desc;
+
+typedef struct {
+    int32_t pc;            /* p4d_pc_type                                         */
+    int32_t pc_prec;       /* p4d_prec of the preconditioner (radial + V-cycle)   */
+    int32_t restart;       /* FGMRES restart length m, 1..64                      */
+    int32_t maxit;         /* cap on total inner iterations                       */
+    int32_t cheb_degree;   /* Chebyshev smoothing degree, 1..4 (default 2)        */
+    int32_t coarse_max;    /* dense coarse solve at <= this many nodes, 8..1024   */
+    int32_t cgs2;          /* 1: Gram-Schmidt applied twice                       */
+    int32_t z_fp32;        /* 1: store the preconditioned basis Z in FP32         */
+    double rtol;           /* stop when ||b - A x|| <= rtol ||b||                 */
+} p4d_solve_opts;
+
+typedef struct {
+    int32_t iters, restarts, status;
+    double relres_est;     /* Givens estimate at exit                             */
+    double relres_true;    /* true residual ||b - A x|| / ||b|| at exit           */
+    double t_setup_ms, t_solve_ms;
+} p4d_solve_info;
+
+typedef struct p4d_ctx p4d_ctx;
+
+/* Fill opts with the defaults: SCHUR, FP64, restart 30, maxit 1000, Chebyshev
+ * degree 2, coarse_max 512, one Gram-Schmidt pass, FP64 Z, rtol 1e-8.       */
+void p4d_default_opts(p4d_solve_opts *opts);
+
+/* Create a context for the problem `desc` on the current device.  Computes
+ * the per-electrode radial tables (mesh after Remark 3.1, rows of eq. L0, L1,
+ * L2, LR; the shared factorization of the backward-Euler radial matrix).
+ * Errors: INVALID_ARG for inconsistent sizes.                               */
+p4d_status p4d_create(const p4d_problem_desc *desc, p4d_ctx **out);
+void p4d_destroy(p4d_ctx *ctx);
+
+/* Sizes: n_dof = N; offsets[0..5] = start of phi_s, phi_e, c_e, c_s anode,
+ * c_s cathode, and N.  n_elem = (nx-1)(ny-1)(nz-1), n_e = electrode nodes.  */
+p4d_status p4d_vector_size(const p4d_ctx *ctx, int64_t *n_dof, int64_t offsets[6],
+                           int64_t *n_elem, int64_t *n_e);
+
+/* Bytes of device workspace needed for the given options (NULL = defaults;
+ * the largest restart and precision that will be used must be passed).     */
+p4d_status p4d_workspace_size(const p4d_ctx *ctx, const p4d_solve_opts *opts,
+                              size_t *bytes);
+/* Hand the context a device workspace of at least p4d_workspace_size(opts)
+ * bytes; opts (NULL = defaults) are the options it was sized for and fix its
+ * layout: later solves may use a restart length up to opts->restart; a
+ * workspace sized with z_fp32 = 1 holds only an FP32 Z basis, one sized with
+ * z_fp32 = 0 holds either; a setup with another pc_prec or coarse_max re-lays
+ * the preconditioner part if it still fits.  Invalidates earlier uploads and
+ * setup.                                                                    */
+p4d_status p4d_set_workspace(p4d_ctx *ctx, void *d_work, size_t bytes,
+                             const p4d_solve_opts *opts);
+
+/* Copy the linearization coefficients into the workspace (assemble/upload
+ * the Jacobian, Sec. 4.1).  d_sigma, d_kappa: per element, solid and
+ * electrolyte conductivity (sigma is read on electrode elements only);
+ * d_g, d_s, d_e: per electrode node (phi_s order), derivatives of the
+ * reaction term a*i_n (Butler-Volmer, Sec. 2.4) with respect to the
+ * overpotential, the particle surface concentration and c_e.              */
+p4d_status p4d_upload(p4d_ctx *ctx, const double *d_sigma, const double *d_kappa,
+                      const double *d_g, const double *d_s, const double *d_e,
+                      void *stream);
+
+/* Build the preconditioner (surface-coupling weights, Galerkin multigrid
+ * hierarchies, Chebyshev bounds, dense coarse inverses).  Synchronizes.    */
+p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
+
+/* d_y = A d_x, or A^T d_x if transpose (eq. blocks).  d_x, d_y: length N,
+ * must not alias.  Needs p4d_upload.                                       */
+p4d_status p4d_apply_operator(p4d_ctx *ctx, int transpose, const double *d_x,
+                              double *d_y, void *stream);
+
+/* d_z = P^-1 d_r (P^-T if transpose) with the preconditioner of the last
+ * p4d_setup (in its precision; d_r and d_z stay FP64).  Needs p4d_setup.   */
+p4d_status p4d_apply_preconditioner(p4d_ctx *ctx, int transpose, const double *d_r,
+                                    double *d_z, void *stream);
+
+/* Solve A x = b by restarted flexible GMRES from x0 = 0 (d_x is output only).
+ * Synchronizes `stream`.  Returns OK, NOT_CONVERGED (x = last iterate),
+ * BREAKDOWN, NONFINITE or an error.  opts: NULL = those of p4d_setup; the
+ * preconditioner options (pc, pc_prec, cheb_degree, coarse_max) must match
+ * the last setup.  info may be NULL.                                       */
+p4d_status p4d_solve(p4d_ctx *ctx, const double *d_b, double *d_x,
+                     const p4d_solve_opts *opts, p4d_solve_info *info, void *stream);
+
+/* Adjoint solve A^T lambda = g with the transposed operator and transposed
+ * preconditioner (same algorithm as p4d_solve).                            */
+p4d_status p4d_solve_adjoint(p4d_ctx *ctx, const double *d_g, double *d_lambda,
+                             const p4d_solve_opts *opts, p4d_solve_info *info,
+                             void *stream);
+
+/* Gradients of J = w.x for A x = b, given x and lambda = A^-T w:
+ * dJ/dp = -lambda^T (dA/dp) x.  d_dsigma: per element (zero on separator
+ * elements); d_dDs: 2 values (anode, cathode), derivative with respect to Ds.
+ * Both are device arrays.                                                  */
+p4d_status p4d_param_gradient(p4d_ctx *ctx, const double *d_x, const double *d_lambda,
+                              double *d_dsigma, double *d_dDs, void *stream);
+
+/* Kernel timing with HIP events recorded on `stream` around every launch of
+ * the kernel classes in `class_mask` (bit 1 << p4d_kernel_class; 0 switches
+ * timing off and clears the totals).                                       */
+typedef enum {
+    P4D_K_OPERATOR = 1, P4D_K_MDOT = 2, P4D_K_ORTH = 3, P4D_K_RADIAL = 4,
+    P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_COUNT = 7
+} p4d_kernel_class;
+p4d_status p4d_profile(p4d_ctx *ctx, int class_mask);
+/* For one class: total_ms = summed kernel durations, launches, and bytes =
+ * algorithmic bytes of those launches (the data each launch must read and
+ * write once).                                                              */
+p4d_status p4d_profile_read(p4d_ctx *ctx, int kernel_class, double *total_ms,
+                            int64_t *launches, double *bytes);
+
+const char *p4d_status_string(p4d_status s);
+const char *p4d_last_error(const p4d_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* P4D_H */

@@ -98,8 +98,13 @@ def lib():
         L.orc_chebyshev.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, _dp]
         L.orc_gershgorin.argtypes = [C.c_int, C.c_int, C.c_int, _dp]
         L.orc_gershgorin.restype = C.c_double
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _p(a: np.ndarray):

@@ -1,0 +1,264 @@
+"""ctypes binding of ``libp4d.so`` (the C ABI in ``include/p4d.h``).
+
+Argument marshalling only: torch tensors are passed as raw device pointers,
+the current HIP stream as ``void*``.  Function names equal the C ones.  There
+is no fallback: if the library is missing or fails to load, every call
+raises."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libp4d.so")
+
+P4D_OK = 0
+P4D_NOT_CONVERGED = 1
+P4D_BREAKDOWN = 2
+P4D_ERR_INVALID_ARG = -1
+P4D_ERR_OOM = -2
+P4D_ERR_HIP = -3
+P4D_ERR_STATE = -4
+P4D_ERR_NONFINITE = -5
+
+P4D_PC_SCHUR = 0
+P4D_PC_BJ = 1
+P4D_FP64 = 0
+P4D_FP32 = 1
+
+P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY = range(1, 7)
+KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "orth",
+                  P4D_K_RADIAL: "radial", P4D_K_SMOOTH0: "smooth0", P4D_K_ZY: "zy"}
+
+EXPORTED = [
+    "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
+    "p4d_set_workspace", "p4d_upload", "p4d_setup", "p4d_apply_operator",
+    "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
+    "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error",
+    "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_workspace_size",
+    "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_solve",
+    "p4d_batch_autotune",
+]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("na", C.c_int32), ("ns", C.c_int32), ("nr", C.c_int32 * 2),
+                ("Ds", C.c_double * 2), ("theta_bar", C.c_double * 2),
+                ("dt", C.c_double), ("chi", C.c_double), ("tc", C.c_double),
+                ("lambda_c", C.c_double), ("eps_elec", C.c_double), ("eps_sep", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("pc", C.c_int32), ("pc_prec", C.c_int32), ("restart", C.c_int32),
+                ("maxit", C.c_int32), ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
+                ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
+                ("relres_est", C.c_double), ("relres_true", C.c_double),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class P4DError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"p4d status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                               "(the solver has no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.p4d_default_opts.argtypes = [C.POINTER(SolveOpts)]
+        L.p4d_default_opts.restype = None
+        L.p4d_create.argtypes = [C.POINTER(ProblemDesc), C.POINTER(vp)]
+        L.p4d_destroy.argtypes = [vp]
+        L.p4d_destroy.restype = None
+        L.p4d_vector_size.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.p4d_workspace_size.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
+        L.p4d_set_workspace.argtypes = [vp, vp, C.c_size_t, C.POINTER(SolveOpts)]
+        L.p4d_upload.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.p4d_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
+        L.p4d_apply_operator.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.p4d_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.p4d_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.p4d_solve_adjoint.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.p4d_param_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.p4d_profile.argtypes = [vp, C.c_int]
+        L.p4d_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.p4d_status_string.argtypes = [C.c_int]
+        L.p4d_status_string.restype = C.c_char_p
+        L.p4d_last_error.argtypes = [vp]
+        L.p4d_last_error.restype = C.c_char_p
+        for name in ["p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
+                     "p4d_upload", "p4d_setup", "p4d_apply_operator", "p4d_apply_preconditioner",
+                     "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
+                     "p4d_profile_read"]:
+            getattr(L, name).restype = C.c_int
+        if hasattr(L, "p4d_batch_create"):
+            _bind_batch(L)
+        _lib = L
+    return _lib
+
+
+def _bind_batch(L):
+    vp = C.c_void_p
+    L.p4d_batch_create.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(vp)]
+    L.p4d_batch_destroy.argtypes = [vp]
+    L.p4d_batch_destroy.restype = None
+    L.p4d_batch_workspace_size.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
+    L.p4d_batch_set_workspace.argtypes = [vp, vp, C.c_size_t, C.POINTER(SolveOpts)]
+    L.p4d_batch_upload.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    L.p4d_batch_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
+    L.p4d_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
+                                  C.POINTER(SolveInfo), vp]
+    L.p4d_batch_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    for name in ["p4d_batch_create", "p4d_batch_workspace_size", "p4d_batch_set_workspace",
+                 "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_solve", "p4d_batch_autotune"]:
+        getattr(L, name).restype = C.c_int
+
+
+def check(status, ctx=None, what=""):
+    """Raise on negative statuses; return the status otherwise."""
+    if status < 0:
+        msg = lib().p4d_status_string(status).decode()
+        if ctx:
+            msg += ": " + lib().p4d_last_error(ctx).decode()
+        raise P4DError(status, f"{what}: {msg}")
+    return status
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().p4d_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def desc_from(p) -> ProblemDesc:
+    """ProblemDesc from any object with the fields of the problem description
+    (nx, ny, nz, na, ns, nr, Ds, theta_bar, dt, chi, tc, lambda_c, eps_elec,
+    eps_sep)."""
+    d = ProblemDesc()
+    d.nx, d.ny, d.nz, d.na, d.ns = p.nx, p.ny, p.nz, p.na, p.ns
+    d.nr[0], d.nr[1] = p.nr
+    d.Ds[0], d.Ds[1] = p.Ds
+    d.theta_bar[0], d.theta_bar[1] = p.theta_bar
+    d.dt, d.chi, d.tc, d.lambda_c = p.dt, p.chi, p.tc, p.lambda_c
+    d.eps_elec, d.eps_sep = p.eps_elec, p.eps_sep
+    return d
+
+
+def ptr(t) -> int:
+    """Device pointer of a torch tensor (contiguous, on the GPU)."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous GPU tensor")
+    return t.data_ptr()
+
+
+def stream_ptr(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# ---- thin same-name wrappers ------------------------------------------------
+def p4d_create(desc: ProblemDesc) -> int:
+    h = C.c_void_p()
+    check(lib().p4d_create(C.byref(desc), C.byref(h)), None, "p4d_create")
+    return h.value
+
+
+def p4d_destroy(ctx: int) -> None:
+    lib().p4d_destroy(ctx)
+
+
+def p4d_vector_size(ctx: int):
+    n = C.c_int64()
+    offs = (C.c_int64 * 6)()
+    ne, nel = C.c_int64(), C.c_int64()
+    check(lib().p4d_vector_size(ctx, C.byref(n), offs, C.byref(nel), C.byref(ne)), ctx,
+          "p4d_vector_size")
+    return n.value, list(offs), nel.value, ne.value
+
+
+def p4d_workspace_size(ctx: int, opts: SolveOpts | None = None) -> int:
+    b = C.c_size_t()
+    check(lib().p4d_workspace_size(ctx, C.byref(opts) if opts else None, C.byref(b)), ctx,
+          "p4d_workspace_size")
+    return b.value
+
+
+def p4d_set_workspace(ctx: int, d_work: int, nbytes: int, opts: SolveOpts | None = None):
+    return check(lib().p4d_set_workspace(ctx, d_work, nbytes, C.byref(opts) if opts else None),
+                 ctx, "p4d_set_workspace")
+
+
+def p4d_upload(ctx, sigma, kappa, g, s, e, stream=None):
+    return check(lib().p4d_upload(ctx, ptr(sigma), ptr(kappa), ptr(g), ptr(s), ptr(e),
+                                  stream_ptr(stream)), ctx, "p4d_upload")
+
+
+def p4d_setup(ctx, opts: SolveOpts | None = None, stream=None):
+    return check(lib().p4d_setup(ctx, C.byref(opts) if opts else None, stream_ptr(stream)),
+                 ctx, "p4d_setup")
+
+
+def p4d_apply_operator(ctx, transpose, x, y, stream=None):
+    return check(lib().p4d_apply_operator(ctx, int(transpose), ptr(x), ptr(y),
+                                          stream_ptr(stream)), ctx, "p4d_apply_operator")
+
+
+def p4d_apply_preconditioner(ctx, transpose, r, z, stream=None):
+    return check(lib().p4d_apply_preconditioner(ctx, int(transpose), ptr(r), ptr(z),
+                                                stream_ptr(stream)), ctx,
+                 "p4d_apply_preconditioner")
+
+
+def p4d_solve(ctx, b, x, opts: SolveOpts | None = None, stream=None):
+    info = SolveInfo()
+    st = check(lib().p4d_solve(ctx, ptr(b), ptr(x), C.byref(opts) if opts else None,
+                               C.byref(info), stream_ptr(stream)), ctx, "p4d_solve")
+    return st, info
+
+
+def p4d_solve_adjoint(ctx, g, lam, opts: SolveOpts | None = None, stream=None):
+    info = SolveInfo()
+    st = check(lib().p4d_solve_adjoint(ctx, ptr(g), ptr(lam), C.byref(opts) if opts else None,
+                                       C.byref(info), stream_ptr(stream)), ctx,
+               "p4d_solve_adjoint")
+    return st, info
+
+
+def p4d_param_gradient(ctx, x, lam, dsigma, dDs, stream=None):
+    return check(lib().p4d_param_gradient(ctx, ptr(x), ptr(lam), ptr(dsigma), ptr(dDs),
+                                          stream_ptr(stream)), ctx, "p4d_param_gradient")
+
+
+def p4d_profile(ctx, class_mask: int):
+    return check(lib().p4d_profile(ctx, class_mask), ctx, "p4d_profile")
+
+
+def p4d_profile_read(ctx, kernel_class: int):
+    ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+    check(lib().p4d_profile_read(ctx, kernel_class, C.byref(ms), C.byref(n), C.byref(by)), ctx,
+          "p4d_profile_read")
+    return ms.value, n.value, by.value

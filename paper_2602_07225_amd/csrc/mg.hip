@@ -1,0 +1,590 @@
+// Geometric Galerkin multigrid for the electrode-level blocks (in place of
+// the paper's BoomerAMG V-cycle, Sec. 4.2).  Four node boxes are processed
+// together in every launch: phi_s anode (layers 1..na-1, the grounded layer
+// eliminated), phi_s cathode, phi_e and c_e.  Each box operator is the
+// field-block diagonal of the Schur complement,
+//   S_f = A_diff,ff + diag(omega_j a_f,j b_f,j),
+// applied matrix-free from element coefficients on the finest level and as
+// a stored 27-point Galerkin stencil S_{l+1} = P^T S_l P on coarser levels.
+// Smoother: Chebyshev on D^-1 S over [lmax/4, lmax] (lmax: Gershgorin bound),
+// one fused kernel per step.  Coarsening per direction keeps the even indices
+// plus the last one; P is tensor-product linear interpolation.
+#include "p4d_device.hpp"
+
+namespace p4d {
+
+// ---------------------------------------------------------------------------
+// 1D transfer helpers for 'even indices plus the last' coarsening of n points
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int coarse_n(int n) { return n <= 2 ? n : n / 2 + 1; }
+
+// coarse points (and weights) that fine point i interpolates from
+__device__ inline int coarse_of(int n, int i, int I[2], double w[2])
+{
+    if (n <= 2) { I[0] = i; w[0] = 1.0; return 1; }
+    if (!(i & 1)) { I[0] = i >> 1; w[0] = 1.0; return 1; }
+    if (i == n - 1) { I[0] = n / 2; w[0] = 1.0; return 1; }
+    I[0] = (i - 1) >> 1; w[0] = 0.5;
+    I[1] = (i + 1) >> 1; w[1] = 0.5;
+    return 2;
+}
+// fine points (and weights) that interpolate from coarse point I
+__device__ inline int fine_of(int n, int I, int f[3], double w[3])
+{
+    if (n <= 2) { f[0] = I; w[0] = 1.0; return 1; }
+    const int nc = n / 2 + 1;
+    const int c = (I == nc - 1) ? n - 1 : 2 * I;
+    int cnt = 0;
+    f[cnt] = c; w[cnt] = 1.0; cnt++;
+    if (c - 1 >= 0 && ((c - 1) & 1) && c - 1 != n - 1) { f[cnt] = c - 1; w[cnt] = 0.5; cnt++; }
+    if (c + 1 <= n - 1 && ((c + 1) & 1) && c + 1 != n - 1) { f[cnt] = c + 1; w[cnt] = 0.5; cnt++; }
+    return cnt;
+}
+
+template <typename T>
+__device__ inline int find_box(const LevelBatch<T> &lb, int b)
+{
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < 4; t++)
+        if (t < lb.nbox && b >= lb.a[t].blk0) q = t;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Level 0: matrix-free operator from element coefficients
+// ---------------------------------------------------------------------------
+template <typename T, bool RESID_ONLY>
+__global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb)
+{
+    const int bx = find_box(lb, blockIdx.x);
+    const LevelArgs<T> &A = lb.a[bx];
+    const int lbk = blockIdx.x - A.blk0;
+    const int nblk = (A.n + kBlock - 1) / kBlock;
+    const int n = xcd_block(lbk, nblk) * kBlock + threadIdx.x;
+    if (n >= A.n) return;
+    const int i = n % A.nx, t = n / A.nx;
+    const int j = t % A.ny, kl = t / A.ny;
+    const int k = kl + A.k0;
+    using R = T;
+    R cK[8], cM[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+        const bool ok = ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 && ek >= A.ek_lo &&
+                        ek <= A.ek_hi;
+        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+        cK[e] = ok ? (R)A.cK[id] : R(0);
+        cM[e] = (ok && A.mass) ? (R)(elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : R(0);
+    }
+    R X[27];
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
+                        (kl + dz >= 0) && (kl + dz < A.nz);
+        X[o] = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : R(0);
+    }
+    R Sx = q1_stiff(cK, X) + A.dcorr[n] * X[13];
+    if (A.mass) Sx += q1_mass(cM, X);
+    const R r = A.b[n] - Sx;
+    if (RESID_ONLY) {
+        A.rout[n] = r;
+        return;
+    }
+    R d = (R)A.c2 * A.invd[n] * r;
+    if (A.c1 != 0.0) d += (R)A.c1 * A.din[n];
+    A.xout[n] = X[13] + d;
+    if (A.dout) A.dout[n] = d;
+}
+
+template <typename T>
+void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only,
+                    hipStream_t st)
+{
+    if (resid_only)
+        hipLaunchKernelGGL((k_smooth0<T, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb);
+    else
+        hipLaunchKernelGGL((k_smooth0<T, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb);
+}
+template void launch_smooth0<double>(const Geom &, const LevelBatch<double> &, int, int, hipStream_t);
+template void launch_smooth0<float>(const Geom &, const LevelBatch<float> &, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Levels >= 1: stored 27-point stencil
+// ---------------------------------------------------------------------------
+template <typename T, bool RESID_ONLY>
+__global__ __launch_bounds__(kBlock) void k_smooth(LevelBatch<T> lb)
+{
+    const int bx = find_box(lb, blockIdx.x);
+    const LevelArgs<T> &A = lb.a[bx];
+    const int lbk = blockIdx.x - A.blk0;
+    const int nblk = (A.n + kBlock - 1) / kBlock;
+    const int n = xcd_block(lbk, nblk) * kBlock + threadIdx.x;
+    if (n >= A.n) return;
+    const int i = n % A.nx, t = n / A.nx;
+    const int j = t % A.ny, kl = t / A.ny;
+    T Sx = T(0), xc = T(0);
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
+                        (kl + dz >= 0) && (kl + dz < A.nz);
+        const T xv = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : T(0);
+        Sx += A.S[(long long)o * A.n + n] * xv;
+        if (o == 13) xc = xv;
+    }
+    const T r = A.b[n] - Sx;
+    if (RESID_ONLY) {
+        A.rout[n] = r;
+        return;
+    }
+    T d = (T)A.c2 * A.invd[n] * r;
+    if (A.c1 != 0.0) d += (T)A.c1 * A.din[n];
+    A.xout[n] = xc + d;
+    if (A.dout) A.dout[n] = d;
+}
+
+template <typename T>
+void launch_smooth(const LevelBatch<T> &lb, int nblk, int resid_only, hipStream_t st)
+{
+    if (resid_only)
+        hipLaunchKernelGGL((k_smooth<T, true>), dim3(nblk), dim3(kBlock), 0, st, lb);
+    else
+        hipLaunchKernelGGL((k_smooth<T, false>), dim3(nblk), dim3(kBlock), 0, st, lb);
+}
+template void launch_smooth<double>(const LevelBatch<double> &, int, int, hipStream_t);
+template void launch_smooth<float>(const LevelBatch<float> &, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Transfers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline int find_tbox(const TransferBatch<T> &tb, int b)
+{
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < 4; t++)
+        if (t < tb.nbox && b >= tb.a[t].blk0) q = t;
+    return q;
+}
+
+// b_c = P^T r_f; also the first Chebyshev iterate x_c1 = c2 D_c^-1 b_c
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(TransferBatch<T> tb)
+{
+    const int bx = find_tbox(tb, blockIdx.x);
+    const TransferArgs<T> &A = tb.a[bx];
+    const int nc = A.cx * A.cy * A.cz;
+    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    if (n >= nc) return;
+    const int I = n % A.cx, t = n / A.cx;
+    const int J = t % A.cy, K = t / A.cy;
+    int fi[3], fj[3], fk[3];
+    double wi[3], wj[3], wk[3];
+    const int ni = fine_of(A.fx, I, fi, wi);
+    const int nj = fine_of(A.fy, J, fj, wj);
+    const int nk = fine_of(A.fz, K, fk, wk);
+    double acc = 0.0;
+    for (int c = 0; c < nk; c++)
+        for (int bq = 0; bq < nj; bq++) {
+            const long long row = (long long)A.fx * (fj[bq] + (long long)A.fy * fk[c]);
+            double part = 0.0;
+            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.rf[row + fi[a]];
+            acc += wj[bq] * wk[c] * part;
+        }
+    const T bc = (T)acc;
+    A.bc[n] = bc;
+    if (A.xc1) A.xc1[n] = (T)A.c2c * A.invdc[n] * bc;
+}
+
+// x_f += P x_c
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(TransferBatch<T> tb)
+{
+    const int bx = find_tbox(tb, blockIdx.x);
+    const TransferArgs<T> &A = tb.a[bx];
+    const int nf = A.fx * A.fy * A.fz;
+    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    if (n >= nf) return;
+    const int i = n % A.fx, t = n / A.fx;
+    const int j = t % A.fy, k = t / A.fy;
+    int Ci[2], Cj[2], Ck[2];
+    double wi[2], wj[2], wk[2];
+    const int ni = coarse_of(A.fx, i, Ci, wi);
+    const int nj = coarse_of(A.fy, j, Cj, wj);
+    const int nk = coarse_of(A.fz, k, Ck, wk);
+    double acc = 0.0;
+    for (int c = 0; c < nk; c++)
+        for (int bq = 0; bq < nj; bq++) {
+            const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
+            double part = 0.0;
+            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.xc[row + Ci[a]];
+            acc += wj[bq] * wk[c] * part;
+        }
+    A.xf[n] = (T)((double)A.xf[n] + acc);
+}
+
+template <typename T>
+void launch_restrict(const TransferBatch<T> &tb, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk), dim3(kBlock), 0, st, tb);
+}
+template <typename T>
+void launch_prolong(const TransferBatch<T> &tb, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_prolong<T>), dim3(nblk), dim3(kBlock), 0, st, tb);
+}
+template void launch_restrict<double>(const TransferBatch<double> &, int, hipStream_t);
+template void launch_restrict<float>(const TransferBatch<float> &, int, hipStream_t);
+template void launch_prolong<double>(const TransferBatch<double> &, int, hipStream_t);
+template void launch_prolong<float>(const TransferBatch<float> &, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Coarsest level: x = A^-1 b with the dense inverse, always in FP64
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse(CoarseBatch<T> cb)
+{
+    __shared__ double bl[1024];
+    const int box = blockIdx.y;
+    if (box >= cb.nbox) return;
+    const CoarseArgs<T> &A = cb.a[box];
+    const int n = A.n;
+    for (int q = threadIdx.x; q < n; q += kBlock) bl[q] = (double)A.b[q];
+    __syncthreads();
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= n) return;
+    double acc = 0.0;
+    for (int c = 0; c < n; c++) acc += A.Ainv[(long long)c * n + row] * bl[c];
+    A.x[row] = (T)acc;
+}
+
+template <typename T>
+void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st)
+{
+    int nmax = 1;
+    for (int b = 0; b < cb.nbox; b++) nmax = cb.a[b].n > nmax ? cb.a[b].n : nmax;
+    hipLaunchKernelGGL((k_coarse<T>), dim3((nmax + kBlock - 1) / kBlock, cb.nbox), dim3(kBlock),
+                       0, st, cb);
+}
+template void launch_coarse<double>(const CoarseBatch<double> &, hipStream_t);
+template void launch_coarse<float>(const CoarseBatch<float> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Setup kernels (FP64)
+// ---------------------------------------------------------------------------
+// per element: h sigma (electrode elements only), h kappa; per electrode node:
+// the lumped weight m_j = (h^3/8) * #(electrode elements containing j)
+__global__ __launch_bounds__(kBlock) void k_setup_nodes(Geom g, const double *__restrict__ sigma,
+                                                        const double *__restrict__ kappa,
+                                                        double *__restrict__ sigh,
+                                                        double *__restrict__ kaph,
+                                                        double *__restrict__ mm)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < g.nelem) {
+        const long long u = t / (g.nx - 1);
+        const int ek = (int)(u / (g.ny - 1));
+        sigh[t] = elem_mat(g, ek) >= 0 ? g.h * sigma[t] : 0.0;
+        kaph[t] = g.h * kappa[t];
+    }
+    if (t < g.ne) {
+        const int el = t < g.nea ? 0 : 1;
+        const long long jl = el == 0 ? t : t - g.nea;
+        const int i = (int)(jl % g.nx);
+        const long long u = jl / g.nx;
+        const int j = (int)(u % g.ny);
+        const int k = (int)(u / g.ny) + (el == 0 ? 0 : g.na + g.ns);
+        const int cx = (i > 0) + (i < g.nx - 1), cy = (j > 0) + (j < g.ny - 1);
+        int cz = 0;
+        if (k - 1 >= 0 && elem_mat(g, k - 1) == el) cz++;
+        if (k < g.nz - 1 && elem_mat(g, k) == el) cz++;
+        mm[t] = g.h * g.h * g.h / 8.0 * (double)(cx * cy * cz);
+    }
+}
+
+void launch_setup_nodes(const Geom &g, const RadialTab *, const double *sigma, const double *kappa,
+                        double *sigh, double *kaph, double *mm, hipStream_t st)
+{
+    const long long n = g.nelem > g.ne ? g.nelem : g.ne;
+    hipLaunchKernelGGL(k_setup_nodes, dim3((int)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       g, sigma, kappa, sigh, kaph, mm);
+}
+
+// omega_j = 1 / (1 + Gamma s_j tau0) (Sherman-Morrison: 1 - Gamma s_j (A_ss,j^-1)_NN)
+__global__ __launch_bounds__(kBlock) void k_omega(Geom g, const RadialTab *__restrict__ tabs,
+                                                  const double *__restrict__ ss, int schur,
+                                                  double *__restrict__ om)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.ne) return;
+    const RadialTab &T = tabs[t < g.nea ? 0 : 1];
+    om[t] = schur ? 1.0 / (1.0 + T.Gamma * ss[t] * T.tau0) : 1.0;
+}
+
+void launch_omega(const Geom &g, const RadialTab *tabs, const double *ss, int schur, double *om,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_omega, dim3((int)((g.ne + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, g,
+                       tabs, ss, schur, om);
+}
+
+// diagonal reaction correction of the box operators, macro layout:
+// phi_s, phi_e: omega m g; c_e: -omega tc m e (zero off the electrodes)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dcorr(Geom g, const double *__restrict__ gg,
+                                                  const double *__restrict__ ee,
+                                                  const double *__restrict__ mm,
+                                                  const double *__restrict__ om, T *__restrict__ dc)
+{
+    const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.nnode) return;
+    const int k = (int)(n / ((long long)g.nx * g.ny));
+    const int el = node_mat(g, k);
+    double dpe = 0.0, dce = 0.0;
+    if (el >= 0) {
+        const long long je = (el == 0 ? 0 : g.nea) + n - (long long)(el == 0 ? 0 : g.na + g.ns) * g.nx * g.ny;
+        const double w = om[je] * mm[je];
+        dpe = w * gg[je];
+        dce = -g.tc * w * ee[je];
+        dc[je] = (T)(k == 0 ? 0.0 : dpe);
+    }
+    dc[g.off_pe + n] = (T)dpe;
+    dc[g.off_ce + n] = (T)dce;
+}
+
+template <typename T>
+void launch_dcorr(const Geom &g, const double *gg, const double *ee, const double *mm,
+                  const double *omega, T *dcorr0, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_dcorr<T>), dim3((int)((g.nnode + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, g, gg, ee, mm, omega, dcorr0);
+}
+template void launch_dcorr<double>(const Geom &, const double *, const double *, const double *,
+                                   const double *, double *, hipStream_t);
+template void launch_dcorr<float>(const Geom &, const double *, const double *, const double *,
+                                  const double *, float *, hipStream_t);
+
+// 27-point stencil (SoA [27][n]) of the level-0 operator of one box
+__global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, int ek_lo, int ek_hi,
+                                                      int mass, const double *__restrict__ cK,
+                                                      const double *__restrict__ dcorr,
+                                                      double *__restrict__ S)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const int nb = g.nx * g.ny * nzb;
+    if (n >= nb) return;
+    const int i = n % g.nx, t = n / g.nx;
+    const int j = t % g.ny, kl = t / g.ny;
+    const int k = kl + k0;
+    double row[27];
+#pragma unroll
+    for (int o = 0; o < 27; o++) row[o] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+        const bool ok = ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 && ek >= ek_lo &&
+                        ek <= ek_hi;
+        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+        const double c = ok ? cK[id] : 0.0;
+        const double cm = (ok && mass) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+        const int a = (1 - ex) | ((1 - ey) << 1) | ((1 - ez) << 2);
+#pragma unroll
+        for (int bb = 0; bb < 8; bb++) {
+            const int dx = ex - 1 + (bb & 1), dy = ey - 1 + ((bb >> 1) & 1), dz = ez - 1 + ((bb >> 2) & 1);
+            const int d = popc3(a ^ bb);
+            const double kab = d == 0 ? 1.0 / 3.0 : (d == 1 ? 0.0 : -1.0 / 12.0);
+            const double mab = d == 0 ? 8.0 / 216 : d == 1 ? 4.0 / 216 : d == 2 ? 2.0 / 216 : 1.0 / 216;
+            const bool in = (kl + dz >= 0) && (kl + dz < nzb);
+            if (in) row[nb_index(dx, dy, dz)] += c * kab + cm * mab;
+        }
+    }
+    row[13] += dcorr[n];
+#pragma unroll
+    for (int o = 0; o < 27; o++) S[(long long)o * nb + n] = row[o];
+}
+
+void launch_assemble0(const Geom &g, int, int nz, int k0, int ek_lo, int ek_hi, int mass,
+                      const double *cK, const double *dcorr, double *S, hipStream_t st)
+{
+    const int nb = g.nx * g.ny * nz;
+    hipLaunchKernelGGL(k_assemble0, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, nz,
+                       k0, ek_lo, ek_hi, mass, cK, dcorr, S);
+}
+
+// Galerkin coarse stencil: S_c(I, J) = sum_{i,j} P(i,I) S(i,j) P(j,J), gathered
+// per coarse row I; per-thread accumulators live in LDS.
+constexpr int kRapBlock = 64;
+__global__ __launch_bounds__(kRapBlock) void k_rap(int fx, int fy, int fz,
+                                                   const double *__restrict__ Sf,
+                                                   double *__restrict__ Sc)
+{
+    __shared__ double acc[kRapBlock * 27];
+    const int cx = coarse_n(fx), cy = coarse_n(fy), cz = coarse_n(fz);
+    const int nc = cx * cy * cz, nf = fx * fy * fz;
+    const int n = blockIdx.x * kRapBlock + threadIdx.x;
+    double *my = acc + threadIdx.x * 27;
+    for (int o = 0; o < 27; o++) my[o] = 0.0;
+    if (n < nc) {
+        const int I = n % cx, t = n / cx;
+        const int J = t % cy, K = t / cy;
+        int fi[3], fj[3], fk[3];
+        double wi[3], wj[3], wk[3];
+        const int ni = fine_of(fx, I, fi, wi);
+        const int nj = fine_of(fy, J, fj, wj);
+        const int nk = fine_of(fz, K, fk, wk);
+        for (int c = 0; c < nk; c++)
+            for (int bq = 0; bq < nj; bq++)
+                for (int a = 0; a < ni; a++) {
+                    const double w = wi[a] * wj[bq] * wk[c];
+                    const int i = fi[a], j = fj[bq], k = fk[c];
+                    const long long row = i + (long long)fx * (j + (long long)fy * k);
+                    for (int o = 0; o < 27; o++) {
+                        const double s = Sf[(long long)o * nf + row];
+                        if (s == 0.0) continue;
+                        const int ii = i + o % 3 - 1, jj = j + (o / 3) % 3 - 1, kk = k + o / 9 - 1;
+                        int Ci[2], Cj[2], Ck[2];
+                        double vi[2], vj[2], vk[2];
+                        const int mi = coarse_of(fx, ii, Ci, vi);
+                        const int mj = coarse_of(fy, jj, Cj, vj);
+                        const int mk = coarse_of(fz, kk, Ck, vk);
+                        for (int c2 = 0; c2 < mk; c2++)
+                            for (int b2 = 0; b2 < mj; b2++)
+                                for (int a2 = 0; a2 < mi; a2++) {
+                                    const int ox = Ci[a2] - I, oy = Cj[b2] - J, oz = Ck[c2] - K;
+                                    // nested coarsening keeps the product within
+                                    // the 27-point pattern; guard regardless
+                                    if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1)
+                                        continue;
+                                    my[nb_index(ox, oy, oz)] += w * s * vi[a2] * vj[b2] * vk[c2];
+                                }
+                    }
+                }
+        for (int o = 0; o < 27; o++) Sc[(long long)o * nc + n] = my[o];
+    }
+}
+
+void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, hipStream_t st)
+{
+    const int nc = coarse_n(fx) * coarse_n(fy) * coarse_n(fz);
+    hipLaunchKernelGGL(k_rap, dim3((nc + kRapBlock - 1) / kRapBlock), dim3(kRapBlock), 0, st, fx,
+                       fy, fz, Sf, Sc);
+}
+
+// inverse diagonal and per-block maxima of the Gershgorin ratio sum|s_ij|/s_ii
+__global__ __launch_bounds__(kBlock) void k_diag(int n, const double *__restrict__ S,
+                                                 double *__restrict__ invd,
+                                                 double *__restrict__ part)
+{
+    __shared__ double red[4];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double ratio = 0.0;
+    if (t < n) {
+        double sum = 0.0;
+        for (int o = 0; o < 27; o++) sum += fabs(S[(long long)o * n + t]);
+        const double dg = S[13LL * n + t];
+        invd[t] = 1.0 / dg;
+        ratio = sum / dg;
+    }
+    const double m = block_max(ratio, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_final(const double *__restrict__ part, int nblk,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) m = fmax(m, part[b]);
+    m = block_max(m, red);
+    if (threadIdx.x == 0) *out = m;
+}
+
+void launch_diag(int n, const double *S, double *invd, double *part, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(kBlock), 0, st, n, S, invd, part);
+}
+void launch_max_final(const double *part, int nblk, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, st, part, nblk, out);
+}
+
+// dense symmetric matrix (row-major) from a stencil, symmetrized
+__global__ __launch_bounds__(kBlock) void k_dense(int nx, int ny, int nz,
+                                                  const double *__restrict__ S,
+                                                  double *__restrict__ A)
+{
+    const int n = nx * ny * nz;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long long)n * n) return;
+    const int r = (int)(t / n), c = (int)(t % n);
+    auto entry = [&](int row, int col) -> double {
+        const int i = row % nx, u = row / nx, j = u % ny, k = u / ny;
+        const int ci = col % nx, cu = col / nx, cj = cu % ny, ck = cu / ny;
+        const int dx = ci - i, dy = cj - j, dz = ck - k;
+        if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return 0.0;
+        return S[(long long)nb_index(dx, dy, dz) * n + row];
+    };
+    A[t] = 0.5 * (entry(r, c) + entry(c, r));
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one
+// workgroup; result written column-major (== row-major for the symmetric
+// inverse).
+__global__ __launch_bounds__(1024) void k_invert(int n, double *__restrict__ A,
+                                                 double *__restrict__ Ainv)
+{
+    __shared__ double rowp[1024];
+    __shared__ double colp[1024];
+    for (int p = 0; p < n; p++) {
+        __syncthreads();
+        const double d = 1.0 / A[(long long)p * n + p];
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            rowp[q] = A[(long long)p * n + q] * d;
+            colp[q] = A[(long long)q * n + p];
+        }
+        __syncthreads();
+        for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) {
+            const int i = (int)(t / n), j = (int)(t % n);
+            double v;
+            if (i == p && j == p) v = d;
+            else if (i == p) v = rowp[j];
+            else if (j == p) v = -colp[i] * d;
+            else v = A[t] - colp[i] * rowp[j];
+            A[t] = v;
+        }
+    }
+    __syncthreads();
+    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) Ainv[t] = A[t];
+}
+
+void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *A, hipStream_t st)
+{
+    const long long n = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_dense, dim3((int)((n * n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
+                       ny, nz, S, A);
+}
+void launch_invert(int n, double *A, double *Ainv, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_invert, dim3(1), dim3(1024), 0, st, n, A, Ainv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cast(long long n, const double *__restrict__ s,
+                                                 T *__restrict__ d)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) d[t] = (T)s[t];
+}
+template <typename T>
+void launch_cast(long long n, const double *src, T *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_cast<T>), dim3((int)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, n,
+                       src, dst);
+}
+template void launch_cast<double>(long long, const double *, double *, hipStream_t);
+template void launch_cast<float>(long long, const double *, float *, hipStream_t);
+
+}  // namespace p4d

@@ -1,0 +1,1081 @@
+// C ABI of the solver (include/p4d.h): context and workspace management,
+// the per-electrode radial tables, preconditioner setup and application,
+// and the restarted flexible GMRES driver.  All per-node, per-element and
+// per-DOF work runs in the HIP kernels of operator.hip, radial.hip, mg.hip
+// and krylov.hip; the host only computes O(N_r) radial tables, O(levels)
+// Chebyshev coefficients and the (m+1) x m Hessenberg least-squares problem.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/p4d.h"
+#include "p4d_internal.hpp"
+
+using namespace p4d;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0, n = 0;
+    double lmax = 0.0;
+    double *S64 = nullptr;   // persistent FP64 Galerkin stencil (levels >= 1)
+    void *S = nullptr;       // stencil in the preconditioner precision
+    void *invd = nullptr, *b = nullptr, *xa = nullptr, *xb = nullptr, *d = nullptr, *r = nullptr;
+    double *Ainv = nullptr;  // coarsest level
+};
+
+struct Box {
+    int nlev = 0;
+    int k0 = 0, ek_lo = 0, ek_hi = 0, mass = 0;
+    long long off = 0;       // offset of level 0 in the macro layout
+    const double *cK = nullptr;
+    Level lev[kMaxLevels];
+};
+
+struct Prof {
+    int mask = 0;
+    std::vector<hipEvent_t> ev;   // pairs
+    std::vector<double> bytes;    // per pair
+    std::vector<int> cls;         // per pair
+    int used = 0;
+    double total_ms[P4D_K_COUNT] = {}, total_bytes[P4D_K_COUNT] = {};
+    long long launches[P4D_K_COUNT] = {};
+};
+
+}  // namespace
+
+struct p4d_ctx {
+    p4d_problem_desc desc{};
+    Geom g{};
+    RadialTab tabs_h[2];
+    std::string err;
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    p4d_solve_opts ws_opts{};
+    // device arrays
+    RadialTab *tabs = nullptr;
+    double *sigh = nullptr, *kaph = nullptr, *gg = nullptr, *ss = nullptr, *ee = nullptr,
+           *mm = nullptr, *omega = nullptr;
+    double *red = nullptr;         // partial sums
+    size_t red_len = 0;
+    double *hdev = nullptr, *cdev = nullptr, *invbeta = nullptr, *ydev = nullptr, *scal = nullptr;
+    // preconditioner
+    int uploaded = 0, pc_ready = 0;
+    p4d_solve_opts pc{};
+    int prec = 0;                  // 0 FP64, 1 FP32
+    Box box[4];
+    void *b0 = nullptr, *x0a = nullptr, *x0b = nullptr, *d0 = nullptr, *r0 = nullptr,
+         *invd0 = nullptr, *dcorr0 = nullptr;
+    char *scratch = nullptr;       // Krylov basis region, also setup scratch
+    size_t scratch_bytes = 0;
+    double *hhost = nullptr;       // pinned host staging
+    Prof prof;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static p4d_status fail(p4d_ctx *c, p4d_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+static p4d_status hipchk(p4d_ctx *c, hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return P4D_OK;
+    return fail(c, P4D_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(c, call)                                            \
+    do {                                                           \
+        p4d_status _s = hipchk((c), (call), #call);                \
+        if (_s != P4D_OK) return _s;                               \
+    } while (0)
+
+static int coarse_n_h(int n) { return n <= 2 ? n : n / 2 + 1; }
+
+// Geometric radial mesh on [0, 1] with Delta_{i+1} = q Delta_i and
+// Delta_{N-1} / Delta_1 = theta_bar (Sec. 3.1, after Remark 3.1).
+static void radial_table(const p4d_problem_desc &d, int el, RadialTab &T)
+{
+    const int N = d.nr[el];
+    std::vector<double> rho(N), dr(N - 1);
+    const double q = std::pow(d.theta_bar[el], 1.0 / (N - 2));
+    double s = 0.0, f = 1.0;
+    for (int i = 0; i < N - 1; i++) { s += f; f *= q; }
+    f = 1.0 / s;
+    rho[0] = 0.0;
+    for (int i = 0; i < N - 1; i++) { dr[i] = f; rho[i + 1] = rho[i] + f; f *= q; }
+    rho[N - 1] = 1.0;
+    for (int i = 0; i < N - 1; i++) dr[i] = rho[i + 1] - rho[i];
+    // L_h rows for unit diffusivity: centre eq. (L0), interior eq. (L1)+(L2),
+    // surface eq. (LR) without the flux term.
+    std::memset(&T, 0, sizeof(T));
+    T.N = N;
+    std::vector<double> lo(N, 0.0), di(N, 0.0), up(N, 0.0);
+    di[0] = -6.0 / (dr[0] * dr[0]);
+    up[0] = 6.0 / (dr[0] * dr[0]);
+    for (int i = 1; i < N - 1; i++) {
+        const double hm = dr[i - 1], hp = dr[i], th = hp / hm;
+        const double a1 = 2.0 / (rho[i] * hp * (1.0 + th));   // first-derivative part
+        const double a2 = 2.0 / (hp * hm * (1.0 + th));       // second-derivative part
+        lo[i] = -th * th * a1 + th * a2;
+        di[i] = -(1.0 - th * th) * a1 - (1.0 + th) * a2;
+        up[i] = a1 + a2;
+    }
+    const double hl = dr[N - 2];
+    lo[N - 1] = 2.0 / (hl * hl);
+    di[N - 1] = -2.0 / (hl * hl);
+    // surface coupling: the flux term 2 i_n/(F dr)(1 + dr/R) of eq. (LR), with
+    // the sign of eq. (particleBC2), enters R_cs,N with +Gamma
+    T.Gamma = d.lambda_c * 2.0 * (1.0 + hl) / hl;
+    const double D = d.Ds[el];
+    for (int i = 0; i < N; i++) {
+        T.hsub[i] = lo[i];
+        T.hdia[i] = di[i];
+        T.hsup[i] = up[i];
+        T.tsub[i] = -D * lo[i];
+        T.tdia[i] = 1.0 / d.dt - D * di[i];
+        T.tsup[i] = -D * up[i];
+    }
+    T.tsub[0] = 0.0;
+    T.tsup[N - 1] = 0.0;
+    // T0 = L U (unit lower bidiagonal L, U with diagonal piv and T0's
+    // superdiagonal); T0^T = L' U' has the same pivots.
+    T.piv[0] = T.tdia[0];
+    for (int i = 1; i < N; i++) {
+        T.l[i] = T.tsub[i] / T.piv[i - 1];
+        T.lT[i] = T.tsup[i - 1] / T.piv[i - 1];
+        T.piv[i] = T.tdia[i] - T.l[i] * T.tsup[i - 1];
+    }
+    for (int i = 0; i < N; i++) T.ipiv[i] = 1.0 / T.piv[i];
+    T.tau0 = 1.0 / T.piv[N - 1];   // (T0^-1)_{NN}
+}
+
+static void fill_geom(const p4d_problem_desc &d, Geom &g)
+{
+    g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.na = d.na; g.ns = d.ns;
+    g.nc = d.nz - d.na - d.ns;
+    g.nr[0] = d.nr[0]; g.nr[1] = d.nr[1];
+    g.nnode = (long long)d.nx * d.ny * d.nz;
+    g.nelem = (long long)(d.nx - 1) * (d.ny - 1) * (d.nz - 1);
+    g.nea = (long long)d.nx * d.ny * d.na;
+    g.nec = (long long)d.nx * d.ny * g.nc;
+    g.ne = g.nea + g.nec;
+    g.off_pe = g.ne;
+    g.off_ce = g.ne + g.nnode;
+    g.off_cs[0] = g.off_ce + g.nnode;
+    g.off_cs[1] = g.off_cs[0] + (long long)d.nr[0] * g.nea;
+    g.N = g.off_cs[1] + (long long)d.nr[1] * g.nec;
+    g.Nm = g.off_cs[0];
+    g.h = 1.0 / (d.nz - 1);
+    g.dt = d.dt;
+    g.chi = d.chi;
+    g.tc = d.tc;
+    const double h3 = g.h * g.h * g.h;
+    g.mass_elec = d.eps_elec * h3 / d.dt;
+    g.mass_sep = d.eps_sep * h3 / d.dt;
+}
+
+// level dims of the four multigrid boxes
+static void box_dims(const p4d_ctx *c, int b, int coarse_max, int *nlev, int dims[][3])
+{
+    const Geom &g = c->g;
+    int nz = b == 0 ? g.na - 1 : (b == 1 ? g.nc : g.nz);
+    int d0[3] = {g.nx, g.ny, nz};
+    int L = 0;
+    for (;;) {
+        dims[L][0] = d0[0]; dims[L][1] = d0[1]; dims[L][2] = d0[2];
+        const long long n = (long long)d0[0] * d0[1] * d0[2];
+        const int cx = coarse_n_h(d0[0]), cy = coarse_n_h(d0[1]), cz = coarse_n_h(d0[2]);
+        L++;
+        if (n <= coarse_max || (long long)cx * cy * cz == n || L == kMaxLevels) break;
+        d0[0] = cx; d0[1] = cy; d0[2] = cz;
+    }
+    *nlev = L;
+}
+
+// Carves the workspace (base == nullptr: sizing only).  Returns bytes.
+static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
+{
+    const Geom &g = c->g;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    const size_t ts = o.pc_prec == P4D_FP32 ? sizeof(float) : sizeof(double);
+    c->tabs = (RadialTab *)take(2 * sizeof(RadialTab));
+    c->sigh = (double *)take(8 * g.nelem);
+    c->kaph = (double *)take(8 * g.nelem);
+    c->gg = (double *)take(8 * g.ne);
+    c->ss = (double *)take(8 * g.ne);
+    c->ee = (double *)take(8 * g.ne);
+    c->mm = (double *)take(8 * g.ne);
+    c->omega = (double *)take(8 * g.ne);
+    // reduction partials: streaming (kRedBlocks x 64), operator, gradient
+    size_t rl = (size_t)kRedBlocks * 64;
+    const size_t opb = (size_t)operator_blocks(g) + 1;
+    const size_t grb = 2 * (size_t)(((g.nelem > g.ne ? g.nelem : g.ne) + kBlock - 1) / kBlock) + 2;
+    rl = rl > opb ? rl : opb;
+    rl = rl > grb ? rl : grb;
+    c->red_len = rl;
+    c->red = (double *)take(8 * rl);
+    c->hdev = (double *)take(8 * 256);
+    c->cdev = (double *)take(8 * 256);
+    c->invbeta = (double *)take(8 * 128);
+    c->ydev = (double *)take(8 * 128);
+    c->scal = (double *)take(8 * 128);
+    const long long Nm = g.Nm;
+    c->b0 = take(ts * Nm);
+    c->x0a = take(ts * Nm);
+    c->x0b = take(ts * Nm);
+    c->d0 = take(ts * Nm);
+    c->r0 = take(ts * Nm);
+    c->invd0 = take(ts * Nm);
+    c->dcorr0 = take(ts * Nm);
+    const long long layer = (long long)g.nx * g.ny;
+    size_t setup_need = 0;
+    for (int b = 0; b < 4; b++) {
+        Box &B = c->box[b];
+        int dims[kMaxLevels][3];
+        box_dims(c, b, o.coarse_max, &B.nlev, dims);
+        B.k0 = b == 0 ? 1 : (b == 1 ? g.na + g.ns : 0);
+        B.ek_lo = b == 0 ? 0 : (b == 1 ? g.na + g.ns : 0);
+        B.ek_hi = b == 0 ? g.na - 2 : g.nz - 2;
+        B.mass = b == 3;
+        B.off = b == 0 ? layer : (b == 1 ? g.nea : (b == 2 ? g.off_pe : g.off_ce));
+        B.cK = b <= 1 ? c->sigh : c->kaph;
+        for (int l = 0; l < B.nlev; l++) {
+            Level &L = B.lev[l];
+            L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
+            L.n = L.nx * L.ny * L.nz;
+            if (l == 0) {
+                auto at = [&](void *p) -> void * {
+                    return base ? (void *)((char *)p + ts * B.off) : nullptr;
+                };
+                L.b = at(c->b0); L.xa = at(c->x0a); L.xb = at(c->x0b); L.d = at(c->d0);
+                L.r = at(c->r0); L.invd = at(c->invd0);
+                L.S64 = nullptr; L.S = nullptr;
+            } else {
+                L.S64 = (double *)take(8 * 27 * (size_t)L.n);
+                L.S = ts == 8 ? (void *)L.S64 : (void *)take(ts * 27 * (size_t)L.n);
+                L.invd = take(ts * L.n);
+                L.b = take(ts * L.n);
+                L.xa = take(ts * L.n);
+                L.xb = take(ts * L.n);
+                L.d = take(ts * L.n);
+                L.r = take(ts * L.n);
+            }
+            if (l == B.nlev - 1) {
+                L.Ainv = (double *)take(8 * (size_t)L.n * L.n);
+                setup_need = setup_need > 8 * (size_t)L.n * L.n ? setup_need : 8 * (size_t)L.n * L.n;
+            }
+        }
+    }
+    // setup scratch: level-0 FP64 stencils of all boxes + FP64 dcorr and
+    // inverse diagonal + dense coarse matrix
+    size_t s0 = 0;
+    for (int b = 0; b < 4; b++) s0 += align_up(8 * 27 * (size_t)c->box[b].lev[0].n);
+    size_t n1max = 0;
+    for (int b = 0; b < 4; b++)
+        if (c->box[b].nlev > 1 && (size_t)c->box[b].lev[1].n > n1max) n1max = c->box[b].lev[1].n;
+    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(setup_need);
+    // Krylov basis
+    const int m = o.restart;
+    const size_t zs = o.z_fp32 ? sizeof(float) : sizeof(double);
+    const size_t kry = align_up(8 * (size_t)(m + 1) * g.N) + align_up(zs * (size_t)m * g.N);
+    c->scratch_bytes = kry > s0 ? kry : s0;
+    c->scratch = take(c->scratch_bytes);
+    return off;
+}
+
+static bool opts_valid(const p4d_solve_opts &o, std::string &why)
+{
+    if (o.pc != P4D_PC_SCHUR && o.pc != P4D_PC_BJ) { why = "pc"; return false; }
+    if (o.pc_prec != P4D_FP64 && o.pc_prec != P4D_FP32) { why = "pc_prec"; return false; }
+    if (o.restart < 1 || o.restart > kMaxRestart) { why = "restart must be in 1..64"; return false; }
+    if (o.maxit < 0) { why = "maxit"; return false; }
+    if (o.cheb_degree < 1 || o.cheb_degree > 4) { why = "cheb_degree must be in 1..4"; return false; }
+    if (o.coarse_max < 8 || o.coarse_max > 1024) { why = "coarse_max must be in 8..1024"; return false; }
+    if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) { why = "rtol must be in (0,1)"; return false; }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// profiling: event pairs around launches of one kernel class
+// ---------------------------------------------------------------------------
+static void prof_harvest(p4d_ctx *c)
+{
+    Prof &P = c->prof;
+    for (int i = 0; i < P.used; i++) {
+        hipEventSynchronize(P.ev[2 * i + 1]);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]);
+        P.total_ms[P.cls[i]] += ms;
+        P.total_bytes[P.cls[i]] += P.bytes[i];
+        P.launches[P.cls[i]]++;
+    }
+    P.used = 0;
+}
+struct ProfScope {
+    p4d_ctx *c;
+    bool on;
+    hipStream_t st;
+    ProfScope(p4d_ctx *c_, int cls, double bytes, hipStream_t s) : c(c_), on(false), st(s)
+    {
+        Prof &P = c->prof;
+        if (!(P.mask & (1 << cls))) return;
+        if (P.used * 2 + 2 > (int)P.ev.size()) prof_harvest(c);
+        P.bytes[P.used] = bytes;
+        P.cls[P.used] = cls;
+        hipEventRecord(P.ev[2 * P.used], st);
+        on = true;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        Prof &P = c->prof;
+        hipEventRecord(P.ev[2 * P.used + 1], st);
+        P.used++;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// operator
+// ---------------------------------------------------------------------------
+template <typename TX>
+static void apply_op(p4d_ctx *c, int transpose, const TX *x, double *y, const double *b,
+                     double *partial, hipStream_t st)
+{
+    const Geom &g = c->g;
+    const double bytes = (double)sizeof(TX) * g.N + 8.0 * g.N + (b ? 8.0 * g.N : 0.0) +
+                         16.0 * g.nelem + 32.0 * g.ne;
+    ProfScope ps(c, P4D_K_OPERATOR, bytes, st);
+    launch_operator<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, x, y, b,
+                        partial, transpose, st);
+}
+
+// ---------------------------------------------------------------------------
+// multigrid V-cycle over the four boxes, level by level
+// ---------------------------------------------------------------------------
+namespace {
+struct ChebCoef {
+    double c1[5], c2[5];   // per step t = 1..deg (index t)
+};
+ChebCoef cheb_coef(double lmax, int deg)
+{
+    ChebCoef C{};
+    const double lmin = lmax / 4.0;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    C.c1[1] = 0.0;
+    C.c2[1] = 1.0 / theta;
+    for (int t = 2; t <= deg; t++) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        C.c1[t] = rn * rho;
+        C.c2[t] = 2.0 * rn / delta;
+        rho = rn;
+    }
+    return C;
+}
+}  // namespace
+
+template <typename T>
+struct VState {
+    int xcur[4][kMaxLevels];   // 0: xa, 1: xb holds the current iterate
+};
+
+template <typename T>
+static T *lvx(Level &L, int which) { return (T *)(which ? L.xb : L.xa); }
+
+template <typename T>
+static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int nb, int step,
+                        int post, hipStream_t st)
+{
+    // step index t (1-based); post-smoothing step 1 starts from a nonzero x
+    LevelBatch<T> lb{};
+    lb.nbox = nb;
+    int blk = 0;
+    for (int q = 0; q < nb; q++) {
+        const int b = boxes[q];
+        Box &B = c->box[b];
+        Level &L = B.lev[l];
+        const ChebCoef C = cheb_coef(L.lmax, c->pc.cheb_degree);
+        LevelArgs<T> &A = lb.a[q];
+        A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
+        A.blk0 = blk;
+        blk += (L.n + kBlock - 1) / kBlock;
+        A.k0 = B.k0; A.ek_lo = B.ek_lo; A.ek_hi = B.ek_hi; A.mass = B.mass;
+        A.cK = B.cK;
+        A.S = (const T *)L.S;
+        A.invd = (const T *)L.invd;
+        A.dcorr = l == 0 ? (const T *)c->dcorr0 + B.off : nullptr;
+        A.b = (const T *)L.b;
+        const int cur = vs.xcur[b][l];
+        A.xin = lvx<T>(L, cur);
+        A.xout = lvx<T>(L, 1 - cur);
+        A.c1 = C.c1[step];
+        A.c2 = C.c2[step];
+        // direction: after the fused first pre-smoothing step it equals x
+        A.din = (!post && step == 2) ? lvx<T>(L, cur) : (const T *)L.d;
+        A.dout = step < c->pc.cheb_degree ? (T *)L.d : nullptr;
+        A.rout = nullptr;
+        vs.xcur[b][l] = 1 - cur;
+    }
+    if (l == 0) {
+        ProfScope ps(c, P4D_K_SMOOTH0, 0.0, st);
+        launch_smooth0<T>(c->g, lb, blk, 0, st);
+    } else {
+        launch_smooth<T>(lb, blk, 0, st);
+    }
+}
+
+template <typename T>
+static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int nb,
+                          hipStream_t st)
+{
+    LevelBatch<T> lb{};
+    lb.nbox = nb;
+    int blk = 0;
+    for (int q = 0; q < nb; q++) {
+        const int b = boxes[q];
+        Box &B = c->box[b];
+        Level &L = B.lev[l];
+        LevelArgs<T> &A = lb.a[q];
+        A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
+        A.blk0 = blk;
+        blk += (L.n + kBlock - 1) / kBlock;
+        A.k0 = B.k0; A.ek_lo = B.ek_lo; A.ek_hi = B.ek_hi; A.mass = B.mass;
+        A.cK = B.cK;
+        A.S = (const T *)L.S;
+        A.invd = (const T *)L.invd;
+        A.dcorr = l == 0 ? (const T *)c->dcorr0 + B.off : nullptr;
+        A.b = (const T *)L.b;
+        A.xin = lvx<T>(L, vs.xcur[b][l]);
+        A.rout = (T *)L.r;
+    }
+    if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, st);
+    else launch_smooth<T>(lb, blk, 1, st);
+}
+
+template <typename T>
+static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
+{
+    int act[4], na = 0, crs[4], nc = 0;
+    for (int b = 0; b < 4; b++) {
+        if (c->box[b].nlev - 1 > l) act[na++] = b;
+        else if (c->box[b].nlev - 1 == l) crs[nc++] = b;
+    }
+    if (nc) {
+        CoarseBatch<T> cb{};
+        cb.nbox = nc;
+        for (int q = 0; q < nc; q++) {
+            Level &L = c->box[crs[q]].lev[l];
+            cb.a[q].n = L.n;
+            cb.a[q].Ainv = L.Ainv;
+            cb.a[q].b = (const T *)L.b;
+            cb.a[q].x = (T *)L.xa;
+            vs.xcur[crs[q]][l] = 0;
+        }
+        launch_coarse<T>(cb, st);
+    }
+    if (!na) return;
+    const int deg = c->pc.cheb_degree;
+    for (int t = 2; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 0, st);
+    residual_step<T>(c, vs, l, act, na, st);
+    {   // restriction (+ first smoothing iterate of the coarse level)
+        TransferBatch<T> tb{};
+        tb.nbox = na;
+        int blk = 0;
+        for (int q = 0; q < na; q++) {
+            Box &B = c->box[act[q]];
+            Level &F = B.lev[l], &Cl = B.lev[l + 1];
+            TransferArgs<T> &A = tb.a[q];
+            A.fx = F.nx; A.fy = F.ny; A.fz = F.nz;
+            A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz;
+            A.blk0 = blk;
+            blk += (Cl.n + kBlock - 1) / kBlock;
+            A.rf = (const T *)F.r;
+            A.bc = (T *)Cl.b;
+            const bool coarsest = (l + 1 == B.nlev - 1);
+            A.xc1 = coarsest ? nullptr : (T *)Cl.xa;
+            A.invdc = (const T *)Cl.invd;
+            A.c2c = coarsest ? 0.0 : cheb_coef(Cl.lmax, deg).c2[1];
+            vs.xcur[act[q]][l + 1] = 0;
+        }
+        launch_restrict<T>(tb, blk, st);
+    }
+    vcycle_level<T>(c, vs, l + 1, st);
+    {   // prolongation and correction
+        TransferBatch<T> tb{};
+        tb.nbox = na;
+        int blk = 0;
+        for (int q = 0; q < na; q++) {
+            Box &B = c->box[act[q]];
+            Level &F = B.lev[l], &Cl = B.lev[l + 1];
+            TransferArgs<T> &A = tb.a[q];
+            A.fx = F.nx; A.fy = F.ny; A.fz = F.nz;
+            A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz;
+            A.blk0 = blk;
+            blk += (F.n + kBlock - 1) / kBlock;
+            A.xc = lvx<T>(Cl, vs.xcur[act[q]][l + 1]);
+            A.xf = lvx<T>(F, vs.xcur[act[q]][l]);
+        }
+        launch_prolong<T>(tb, blk, st);
+    }
+    for (int t = 1; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 1, st);
+}
+
+// z = P^-1 (rscale r), or P^-T
+template <typename T, typename TZ>
+static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+                       hipStream_t st)
+{
+    const Geom &g = c->g;
+    const int schur = c->pc.pc == P4D_PC_SCHUR;
+    double c2box[4];
+    for (int b = 0; b < 4; b++) c2box[b] = cheb_coef(c->box[b].lev[0].lmax, c->pc.cheb_degree).c2[1];
+    const double rbytes = 8.0 * g.N + 32.0 * g.ne + 3.0 * sizeof(T) * g.Nm;
+    {
+        ProfScope ps(c, P4D_K_RADIAL, rbytes, st);
+        launch_rad_fwd<T>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, r, rscale, (T *)c->b0,
+                          (T *)c->x0a, (const T *)c->invd0, c2box, transpose, schur, st);
+    }
+    VState<T> vs{};
+    for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
+    vcycle_level<T>(c, vs, 0, st);
+    // all boxes' final level-0 iterates must sit in one array for rad_back:
+    // copy the boxes that ended in the other buffer
+    const int ref = vs.xcur[2][0];
+    for (int b = 0; b < 4; b++) {
+        if (vs.xcur[b][0] != ref) {
+            Level &L = c->box[b].lev[0];
+            hipMemcpyAsync(lvx<T>(L, ref), lvx<T>(L, 1 - ref), sizeof(T) * L.n,
+                           hipMemcpyDeviceToDevice, st);
+        }
+    }
+    const T *x0 = (const T *)(ref ? c->x0b : c->x0a);
+    {
+        ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + sizeof(T) * g.Nm +
+                                          sizeof(TZ) * g.N + 32.0 * g.ne, st);
+        launch_rad_back<T, TZ>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, r, rscale, x0, z, transpose,
+                               schur, st);
+    }
+}
+
+template <typename TZ>
+static void apply_pc(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+                     hipStream_t st)
+{
+    if (c->prec == 1) apply_pc_t<float, TZ>(c, transpose, r, rscale, z, st);
+    else apply_pc_t<double, TZ>(c, transpose, r, rscale, z, st);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+template <typename T>
+static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
+{
+    const Geom &g = c->g;
+    const int schur = c->pc.pc == P4D_PC_SCHUR;
+    launch_omega(g, c->tabs, c->ss, schur, c->omega, st);
+    // scratch: FP64 stencils of level 0, FP64 dcorr / inverse diagonal, dense
+    char *sp = c->scratch;
+    auto take = [&](size_t bytes) { char *p = sp; sp += align_up(bytes); return p; };
+    double *S0[4];
+    for (int b = 0; b < 4; b++) S0[b] = (double *)take(8 * 27 * (size_t)c->box[b].lev[0].n);
+    double *dc64 = (double *)take(8 * (size_t)g.Nm);
+    double *id64 = (double *)take(8 * (size_t)g.Nm);
+    size_t n1max = 0;
+    for (int b = 0; b < 4; b++)
+        if (c->box[b].nlev > 1 && (size_t)c->box[b].lev[1].n > n1max) n1max = c->box[b].lev[1].n;
+    double *idl = (double *)take(8 * (n1max ? n1max : 1));   // FP64 inverse diagonal, l >= 1
+    double *dense = (double *)sp;
+    launch_dcorr<double>(g, c->gg, c->ee, c->mm, c->omega, dc64, st);
+    launch_cast<T>(g.Nm, dc64, (T *)c->dcorr0, st);
+    // inverse diagonal of level 0 defaults to 0 outside the boxes (the
+    // grounded layer of phi_s)
+    HIPCHK(c, hipMemsetAsync(id64, 0, 8 * (size_t)g.Nm, st));
+    for (int b = 0; b < 4; b++) {
+        Box &B = c->box[b];
+        for (int l = 0; l < B.nlev; l++) {
+            Level &L = B.lev[l];
+            const double *Sl;
+            if (l == 0) {
+                launch_assemble0(g, b, L.nz, B.k0, B.ek_lo, B.ek_hi, B.mass, B.cK, dc64 + B.off,
+                                 S0[b], st);
+                Sl = S0[b];
+            } else {
+                const Level &F = B.lev[l - 1];
+                launch_rap(F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, L.S64, st);
+                Sl = L.S64;
+                if (sizeof(T) != 8) launch_cast<T>(27LL * L.n, L.S64, (T *)L.S, st);
+            }
+            const int nblk = (L.n + kBlock - 1) / kBlock;
+            double *idst = l == 0 ? id64 + B.off : idl;   // FP64 inverse diagonal
+            launch_diag(L.n, Sl, idst, c->red, nblk, st);
+            launch_max_final(c->red, nblk, c->scal + 16 * b + l, st);
+            if (l > 0) launch_cast<T>(L.n, idl, (T *)L.invd, st);
+            if (l == B.nlev - 1) {
+                if (L.n > 1024) return fail(c, P4D_ERR_INVALID_ARG, "coarsest grid above 1024 nodes");
+                launch_dense_from_stencil(L.nx, L.ny, L.nz, Sl, dense, st);
+                launch_invert(L.n, dense, L.Ainv, st);
+            }
+        }
+    }
+    launch_cast<T>(g.Nm, id64, (T *)c->invd0, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal, 8 * 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int b = 0; b < 4; b++)
+        for (int l = 0; l < c->box[b].nlev; l++) {
+            const double lm = c->hhost[16 * b + l];
+            if (!(lm > 0.0) || !std::isfinite(lm))
+                return fail(c, P4D_ERR_NONFINITE, "non-positive or non-finite Gershgorin bound");
+            c->box[b].lev[l].lmax = lm;
+        }
+    return P4D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES (Saad's flexible variant, right preconditioned, restarted)
+// ---------------------------------------------------------------------------
+template <typename TZ>
+static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
+                         const p4d_solve_opts &o, p4d_solve_info *info, hipStream_t st)
+{
+    const Geom &g = c->g;
+    const long long N = g.N;
+    const int m = o.restart;
+    double *V = (double *)c->scratch;
+    TZ *Z = (TZ *)(c->scratch + align_up(8 * (size_t)(m + 1) * N));
+    double *red = c->red;
+    const int sb = stream_blocks(N);
+    const int ob = operator_blocks(g);
+    double *hh = c->hhost;           // device-to-host staging
+    double *hout = c->hhost + 256;   // host-to-device staging
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m), hc(m + 2),
+        beta(m + 1);
+    p4d_solve_info inf{};
+    auto t0 = std::chrono::steady_clock::now();
+
+    // ||b||
+    launch_dot_partial(N, b, b, red, sb, st);
+    launch_norm_final(red, sb, c->hdev, nullptr, st);
+    HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const double bnorm = hh[0];
+    HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)N, st));
+    if (!std::isfinite(bnorm)) {
+        HIPCHK(c, hipStreamSynchronize(st));
+        return fail(c, P4D_ERR_NONFINITE, "non-finite right-hand side");
+    }
+    p4d_status status = P4D_NOT_CONVERGED;
+    int total = 0;
+    bool first = true;
+    if (bnorm == 0.0) {
+        status = P4D_OK;
+        goto done;
+    }
+    for (;;) {
+        // r = b - A x into V_0 (x = 0 in the first cycle: r = b)
+        if (first) {
+            HIPCHK(c, hipMemcpyAsync(V, b, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
+            hout[0] = 1.0 / bnorm;
+            HIPCHK(c, hipMemcpyAsync(c->invbeta, hout, 8, hipMemcpyHostToDevice, st));
+            beta[0] = bnorm;
+            first = false;
+        } else {
+            apply_op<double>(c, transpose, x, V, b, red, st);
+            launch_norm_final(red, ob, c->hdev + 200, c->invbeta, st);
+            HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            prof_harvest(c);
+            beta[0] = hh[0];
+        }
+        inf.relres_true = beta[0] / bnorm;
+        if (!std::isfinite(beta[0])) { status = P4D_ERR_NONFINITE; break; }
+        if (beta[0] <= o.rtol * bnorm) { status = P4D_OK; break; }
+        if (total >= o.maxit) { status = P4D_NOT_CONVERGED; break; }
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta[0];
+        int kused = 0;
+        bool breakdown = false, nonfinite = false;
+        for (int k = 0; k < m; k++) {
+            double *vk = V + (long long)k * N;
+            TZ *zk = Z + (long long)k * N;
+            apply_pc<TZ>(c, transpose, vk, 1.0 / beta[k], zk, st);
+            double *w = V + (long long)(k + 1) * N;
+            apply_op<TZ>(c, transpose, zk, w, nullptr, nullptr, st);
+            const int nv = k + 1;
+            const int passes = o.cgs2 ? 2 : 1;
+            for (int p = 0; p < passes; p++) {
+                {
+                    ProfScope ps(c, P4D_K_MDOT, 8.0 * (nv + 1) * N, st);
+                    launch_mdot(N, w, V, N, nv, red, sb, st);
+                }
+                launch_mdot_final(nv, red, sb, c->invbeta, c->hdev + 64 * p, c->cdev, st);
+                {
+                    ProfScope ps(c, P4D_K_ORTH, 8.0 * (nv + 2) * N, st);
+                    launch_orth(N, w, V, N, nv, c->cdev, red, sb, st);
+                }
+            }
+            launch_norm_final(red, sb, c->hdev + 128, c->invbeta + k + 1, st);
+            HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8 * 129, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            prof_harvest(c);
+            for (int i = 0; i <= k; i++) hc[i] = hh[i] + (o.cgs2 ? hh[64 + i] : 0.0);
+            const double hn = hh[128];
+            hc[k + 1] = hn;
+            double colnorm = 0.0;
+            for (int i = 0; i <= k + 1; i++) colnorm += hc[i] * hc[i];
+            colnorm = std::sqrt(colnorm);
+            if (!std::isfinite(colnorm)) { nonfinite = true; break; }
+            for (int i = 0; i < k; i++) {
+                const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = t;
+            }
+            const double den = std::sqrt(hc[k] * hc[k] + hc[k + 1] * hc[k + 1]);
+            cs[k] = hc[k] / den;
+            sn[k] = hc[k + 1] / den;
+            hc[k] = den;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            for (int i = 0; i <= k; i++) H[(size_t)i * m + k] = hc[i];
+            total++;
+            kused = k + 1;
+            beta[k + 1] = hn;
+            inf.relres_est = std::fabs(gv[k + 1]) / bnorm;
+            if (hn <= 1e-14 * colnorm) { breakdown = true; break; }
+            if (std::fabs(gv[k + 1]) <= o.rtol * bnorm || total >= o.maxit) break;
+        }
+        if (nonfinite) { status = P4D_ERR_NONFINITE; break; }
+        for (int i = kused - 1; i >= 0; i--) {
+            double v = gv[i];
+            for (int j = i + 1; j < kused; j++) v -= H[(size_t)i * m + j] * yv[j];
+            yv[i] = v / H[(size_t)i * m + i];
+        }
+        // the previous host-to-device copy from hout has completed: every
+        // iteration synchronizes the stream before this point
+        for (int i = 0; i < kused; i++) hout[i] = yv[i];
+        HIPCHK(c, hipMemcpyAsync(c->ydev, hout, 8 * kused, hipMemcpyHostToDevice, st));
+        {
+            ProfScope ps(c, P4D_K_ZY, (8.0 * 2 + sizeof(TZ) * kused) * N, st);
+            launch_zy<TZ>(N, x, Z, N, kused, c->ydev, st);
+        }
+        inf.restarts++;
+        if (breakdown) {
+            apply_op<double>(c, transpose, x, V, b, red, st);
+            launch_norm_final(red, ob, c->hdev + 200, nullptr, st);
+            HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            inf.relres_true = hh[0] / bnorm;
+            status = inf.relres_true <= o.rtol ? P4D_OK : P4D_BREAKDOWN;
+            break;
+        }
+    }
+done:
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    prof_harvest(c);
+    inf.iters = total;
+    inf.status = status;
+    inf.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    if (status == P4D_ERR_NONFINITE) c->err = "non-finite value during the solve";
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void p4d_default_opts(p4d_solve_opts *o)
+{
+    if (!o) return;
+    o->pc = P4D_PC_SCHUR;
+    o->pc_prec = P4D_FP64;
+    o->restart = 30;
+    o->maxit = 1000;
+    o->cheb_degree = 2;
+    o->coarse_max = 512;
+    o->cgs2 = 0;
+    o->z_fp32 = 0;
+    o->rtol = 1e-8;
+}
+
+const char *p4d_status_string(p4d_status s)
+{
+    switch (s) {
+    case P4D_OK: return "ok";
+    case P4D_NOT_CONVERGED: return "not converged";
+    case P4D_BREAKDOWN: return "breakdown";
+    case P4D_ERR_INVALID_ARG: return "invalid argument";
+    case P4D_ERR_OOM: return "workspace too small";
+    case P4D_ERR_HIP: return "HIP error";
+    case P4D_ERR_STATE: return "call out of order";
+    case P4D_ERR_NONFINITE: return "non-finite value";
+    }
+    return "unknown";
+}
+
+const char *p4d_last_error(const p4d_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
+{
+    if (!d || !out) return P4D_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int nc = d->nz - d->na - d->ns;
+    if (d->nx < 2 || d->ny < 2 || d->nz < 5 || d->na < 2 || d->ns < 1 || nc < 2)
+        return P4D_ERR_INVALID_ARG;
+    for (int el = 0; el < 2; el++) {
+        if (d->nr[el] < 3 || d->nr[el] > kMaxNr) return P4D_ERR_INVALID_ARG;
+        if (!(d->Ds[el] > 0.0) || !(d->theta_bar[el] > 0.0) || d->theta_bar[el] > 1.0)
+            return P4D_ERR_INVALID_ARG;
+    }
+    if (!(d->dt > 0.0) || !std::isfinite(d->chi) || !std::isfinite(d->tc) ||
+        !std::isfinite(d->lambda_c) || !(d->eps_elec > 0.0) || !(d->eps_sep > 0.0))
+        return P4D_ERR_INVALID_ARG;
+    if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return P4D_ERR_INVALID_ARG;
+    p4d_ctx *c = new p4d_ctx();
+    c->desc = *d;
+    fill_geom(*d, c->g);
+    radial_table(*d, 0, c->tabs_h[0]);
+    radial_table(*d, 1, c->tabs_h[1]);
+    if (hipHostMalloc((void **)&c->hhost, 8 * 512, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return P4D_ERR_HIP;
+    }
+    c->prof.ev.resize(2 * 512);
+    c->prof.bytes.resize(512);
+    c->prof.cls.resize(512);
+    for (auto &e : c->prof.ev) hipEventCreate(&e);
+    p4d_default_opts(&c->ws_opts);
+    *out = c;
+    return P4D_OK;
+}
+
+void p4d_destroy(p4d_ctx *c)
+{
+    if (!c) return;
+    for (auto &e : c->prof.ev) hipEventDestroy(e);
+    if (c->hhost) hipHostFree(c->hhost);
+    delete c;
+}
+
+p4d_status p4d_vector_size(const p4d_ctx *c, int64_t *n_dof, int64_t offsets[6], int64_t *n_elem,
+                           int64_t *n_e)
+{
+    if (!c) return P4D_ERR_INVALID_ARG;
+    if (n_dof) *n_dof = c->g.N;
+    if (offsets) {
+        offsets[0] = 0; offsets[1] = c->g.off_pe; offsets[2] = c->g.off_ce;
+        offsets[3] = c->g.off_cs[0]; offsets[4] = c->g.off_cs[1]; offsets[5] = c->g.N;
+    }
+    if (n_elem) *n_elem = c->g.nelem;
+    if (n_e) *n_e = c->g.ne;
+    return P4D_OK;
+}
+
+p4d_status p4d_workspace_size(const p4d_ctx *cc, const p4d_solve_opts *opts, size_t *bytes)
+{
+    if (!cc || !bytes) return P4D_ERR_INVALID_ARG;
+    p4d_ctx *c = const_cast<p4d_ctx *>(cc);
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    // sizing must not disturb a configured context
+    p4d_ctx tmp;
+    tmp.desc = c->desc;
+    tmp.g = c->g;
+    *bytes = carve(&tmp, o, nullptr) + kAlign;
+    return P4D_OK;
+}
+
+static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o);
+
+p4d_status p4d_set_workspace(p4d_ctx *c, void *d_work, size_t bytes, const p4d_solve_opts *opts)
+{
+    if (!c || !d_work) return P4D_ERR_INVALID_ARG;
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    c->ws = (char *)d_work;
+    c->ws_bytes = bytes;
+    c->uploaded = 0;
+    c->pc_ready = 0;
+    return ensure_layout(c, o);
+}
+
+static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o)
+{
+    if (!c->ws) return fail(c, P4D_ERR_STATE, "no workspace");
+    char *base = (char *)align_up((size_t)c->ws);
+    p4d_ctx probe;
+    probe.desc = c->desc;
+    probe.g = c->g;
+    const size_t need = carve(&probe, o, nullptr);
+    if (need + (size_t)(base - c->ws) > c->ws_bytes)
+        return fail(c, P4D_ERR_OOM, "workspace too small for these options");
+    carve(c, o, base);
+    c->ws_opts = o;
+    return P4D_OK;
+}
+
+p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, const double *g,
+                      const double *s, const double *e, void *stream)
+{
+    if (!c || !sigma || !kappa || !g || !s || !e) return P4D_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (!c->ws) return fail(c, P4D_ERR_STATE, "p4d_set_workspace first");
+    HIPCHK(c, hipMemcpyAsync(c->tabs, c->tabs_h, sizeof(c->tabs_h), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->gg, g, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->ss, s, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->ee, e, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
+    launch_setup_nodes(c->g, c->tabs, sigma, kappa, c->sigh, c->kaph, c->mm, st);
+    HIPCHK(c, hipGetLastError());
+    // the host copy of the radial tables must outlive the async copy
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->uploaded = 1;
+    c->pc_ready = 0;
+    return P4D_OK;
+}
+
+p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
+{
+    if (!c) return P4D_ERR_INVALID_ARG;
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    // keep the Krylov sizing of the layout (it is set by the workspace size
+    // the caller asked for); the preconditioner part must match o
+    p4d_solve_opts lay = c->ws_opts;
+    lay.pc_prec = o.pc_prec;
+    lay.coarse_max = o.coarse_max;
+    if (o.restart > lay.restart) lay.restart = o.restart;
+    const bool relayout = lay.pc_prec != c->ws_opts.pc_prec || lay.coarse_max != c->ws_opts.coarse_max ||
+                          lay.restart != c->ws_opts.restart || lay.z_fp32 != c->ws_opts.z_fp32;
+    if (relayout) {
+        // coefficient arrays sit at the start of every layout, so they
+        // survive a change of the preconditioner part
+        p4d_status rs = ensure_layout(c, lay);
+        if (rs != P4D_OK) return rs;
+    }
+    c->pc = o;
+    c->prec = o.pc_prec == P4D_FP32 ? 1 : 0;
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    p4d_status s = c->prec ? setup_t<float>(c, st) : setup_t<double>(c, st);
+    if (s != P4D_OK) return s;
+    (void)t0;
+    c->pc_ready = 1;
+    return P4D_OK;
+}
+
+p4d_status p4d_apply_operator(p4d_ctx *c, int transpose, const double *x, double *y, void *stream)
+{
+    if (!c || !x || !y || x == y) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    apply_op<double>(c, transpose, x, y, nullptr, nullptr, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+p4d_status p4d_apply_preconditioner(p4d_ctx *c, int transpose, const double *r, double *z,
+                                    void *stream)
+{
+    if (!c || !r || !z || r == z) return P4D_ERR_INVALID_ARG;
+    if (!c->pc_ready) return fail(c, P4D_ERR_STATE, "p4d_setup first");
+    apply_pc<double>(c, transpose, r, 1.0, z, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+static p4d_status solve_common(p4d_ctx *c, int transpose, const double *b, double *x,
+                               const p4d_solve_opts *opts, p4d_solve_info *info, void *stream)
+{
+    if (!c || !b || !x || b == x) return P4D_ERR_INVALID_ARG;
+    if (!c->pc_ready) return fail(c, P4D_ERR_STATE, "p4d_setup first");
+    p4d_solve_opts o = opts ? *opts : c->pc;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    if (o.pc != c->pc.pc || o.pc_prec != c->pc.pc_prec || o.cheb_degree != c->pc.cheb_degree ||
+        o.coarse_max != c->pc.coarse_max)
+        return fail(c, P4D_ERR_STATE, "preconditioner options differ from the last setup");
+    if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
+        return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
+    hipStream_t st = (hipStream_t)stream;
+    if (o.z_fp32) return fgmres<float>(c, transpose, b, x, o, info, st);
+    return fgmres<double>(c, transpose, b, x, o, info, st);
+}
+
+p4d_status p4d_solve(p4d_ctx *c, const double *b, double *x, const p4d_solve_opts *opts,
+                     p4d_solve_info *info, void *stream)
+{
+    return solve_common(c, 0, b, x, opts, info, stream);
+}
+
+p4d_status p4d_solve_adjoint(p4d_ctx *c, const double *g, double *lam, const p4d_solve_opts *opts,
+                             p4d_solve_info *info, void *stream)
+{
+    return solve_common(c, 1, g, lam, opts, info, stream);
+}
+
+p4d_status p4d_param_gradient(p4d_ctx *c, const double *x, const double *lam, double *dsigma,
+                              double *dDs, void *stream)
+{
+    if (!c || !x || !lam || !dsigma || !dDs) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    hipStream_t st = (hipStream_t)stream;
+    launch_grad(c->g, c->tabs, x, lam, dsigma, c->red, st);
+    const long long n = c->g.nelem > c->g.ne ? c->g.nelem : c->g.ne;
+    launch_grad_final(c->red, (int)((n + kBlock - 1) / kBlock), dDs, st);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+p4d_status p4d_profile(p4d_ctx *c, int mask)
+{
+    if (!c || mask < 0 || mask >= (1 << P4D_K_COUNT)) return P4D_ERR_INVALID_ARG;
+    prof_harvest(c);
+    c->prof.mask = mask;
+    for (int k = 0; k < P4D_K_COUNT; k++) {
+        c->prof.total_ms[k] = 0.0;
+        c->prof.total_bytes[k] = 0.0;
+        c->prof.launches[k] = 0;
+    }
+    return P4D_OK;
+}
+
+p4d_status p4d_profile_read(p4d_ctx *c, int cls, double *total_ms, int64_t *launches,
+                            double *bytes)
+{
+    if (!c || cls < 1 || cls >= P4D_K_COUNT) return P4D_ERR_INVALID_ARG;
+    prof_harvest(c);
+    if (total_ms) *total_ms = c->prof.total_ms[cls];
+    if (launches) *launches = c->prof.launches[cls];
+    if (bytes) *bytes = c->prof.total_bytes[cls];
+    return P4D_OK;
+}
+
+}  // extern "C"

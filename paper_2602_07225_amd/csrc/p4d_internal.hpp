@@ -1,0 +1,174 @@
+// Internal declarations of the gfx950 solver library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p4d {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxNr = 64;           // radial points per particle
+constexpr int kMaxRestart = 64;      // FGMRES restart length
+constexpr int kMaxLevels = 16;
+constexpr int kRedBlocks = 2048;     // partial-sum slots of the streaming reductions
+
+// Structured grid and model scalars, passed by value to every kernel.
+struct Geom {
+    int nx, ny, nz, na, ns, nc;
+    int nr[2];
+    long long nnode, nelem, nea, nec, ne;
+    long long off_pe, off_ce, off_cs[2], N, Nm;
+    double h, dt, chi, tc;
+    double mass_elec, mass_sep;      // eps * h^3 / dt per element material
+};
+
+__host__ __device__ inline int elem_mat(const Geom &g, int kk)
+{
+    return kk + 1 < g.na ? 0 : (kk >= g.na + g.ns ? 1 : -1);
+}
+__host__ __device__ inline int node_mat(const Geom &g, int k)
+{
+    return k < g.na ? 0 : (k >= g.na + g.ns ? 1 : -1);
+}
+
+// Per-electrode radial tables (T0 = I/dt - L_h and its shared factorizations).
+struct RadialTab {
+    int N;
+    double Gamma;                    // surface coupling factor (flux term of eq. LR)
+    double tau0;                     // (T0^-1)_{NN}
+    double tsub[kMaxNr], tdia[kMaxNr], tsup[kMaxNr];   // rows of T0
+    double l[kMaxNr], ipiv[kMaxNr], piv[kMaxNr];       // T0 = L U, unit L multipliers
+    double lT[kMaxNr];                                 // T0^T = L' U' (same pivots)
+    double hsub[kMaxNr], hdia[kMaxNr], hsup[kMaxNr];   // dL_h/dDs
+};
+
+// One multigrid level of one box, as seen by a batched launch.
+template <typename T>
+struct LevelArgs {
+    int nx, ny, nz, n;
+    int blk0;                        // first workgroup of this box in the launch
+    int k0;                          // level 0: global node layer of local layer 0
+    int ek_lo, ek_hi;                // level 0: element layers taking part
+    int mass;                        // level 0: add the c_e storage term
+    const double *cK;                // level 0: element coefficient (x h)
+    const T *S;                      // level >= 1: stencil, SoA [27][n]
+    const T *invd;                   // inverse diagonal
+    const T *dcorr;                  // level 0: diagonal reaction correction
+    const T *b;
+    const T *xin;
+    T *xout;
+    const T *din;
+    T *dout;
+    T *rout;
+    double c1, c2;                   // Chebyshev step: d' = c1 d + c2 D^-1 r
+};
+
+template <typename T>
+struct LevelBatch {
+    int nbox;
+    LevelArgs<T> a[4];
+};
+
+// Restriction / prolongation between level l (fine) and l+1 (coarse).
+template <typename T>
+struct TransferArgs {
+    int fx, fy, fz, cx, cy, cz;
+    int blk0;
+    const T *rf;                     // fine residual (restriction)
+    T *bc;                           // coarse right-hand side (restriction)
+    T *xc1;                          // coarse first smoothing iterate, may be null
+    const T *invdc;                  // coarse inverse diagonal
+    double c2c;                      // coarse first-step coefficient
+    const T *xc;                     // coarse solution (prolongation)
+    T *xf;                           // fine iterate, updated in place
+};
+template <typename T>
+struct TransferBatch {
+    int nbox;
+    TransferArgs<T> a[4];
+};
+
+template <typename T>
+struct CoarseArgs {
+    int n;
+    const double *Ainv;              // dense inverse, column-major
+    const T *b;
+    T *x;
+};
+template <typename T>
+struct CoarseBatch {
+    int nbox;
+    CoarseArgs<T> a[4];
+};
+
+// ---- launchers (each defined beside its kernels) ---------------------------
+// operator.hip
+template <typename TX>
+void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh,
+                     const double *kaph, const double *gg, const double *ss, const double *ee,
+                     const double *mm, const TX *x, double *y, const double *b,
+                     double *partial, int transpose, hipStream_t st);
+int operator_blocks(const Geom &g);
+void launch_grad(const Geom &g, const RadialTab *tabs, const double *x, const double *lam,
+                 double *dsigma, double *partial, hipStream_t st);
+void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t st);
+
+// radial.hip
+template <typename T>
+void launch_rad_fwd(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
+                    const double *ee, const double *mm, const double *r, double rscale,
+                    T *b0, T *x1, const T *invd0, const double c2box[4], int transpose,
+                    int schur, hipStream_t st);
+template <typename T, typename TZ>
+void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
+                     const double *ee, const double *mm, const double *r, double rscale,
+                     const T *x0, TZ *z, int transpose, int schur, hipStream_t st);
+
+// mg.hip
+template <typename T>
+void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only,
+                    hipStream_t st);
+template <typename T>
+void launch_smooth(const LevelBatch<T> &lb, int nblk, int resid_only, hipStream_t st);
+template <typename T>
+void launch_restrict(const TransferBatch<T> &tb, int nblk, hipStream_t st);
+template <typename T>
+void launch_prolong(const TransferBatch<T> &tb, int nblk, hipStream_t st);
+template <typename T>
+void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st);
+void launch_assemble0(const Geom &g, int box, int nz, int k0, int ek_lo, int ek_hi, int mass,
+                      const double *cK, const double *dcorr, double *S, hipStream_t st);
+void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, hipStream_t st);
+void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
+                 hipStream_t st);
+void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);
+void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *A,
+                               hipStream_t st);
+void launch_invert(int n, double *A, double *Ainv, hipStream_t st);
+void launch_setup_nodes(const Geom &g, const RadialTab *tabs, const double *sigma,
+                        const double *kappa, double *sigh, double *kaph, double *mm,
+                        hipStream_t st);
+template <typename T>
+void launch_dcorr(const Geom &g, const double *gg, const double *ee, const double *mm,
+                  const double *omega, T *dcorr0, hipStream_t st);
+void launch_omega(const Geom &g, const RadialTab *tabs, const double *ss, int schur,
+                  double *omega, hipStream_t st);
+template <typename T>
+void launch_cast(long long n, const double *src, T *dst, hipStream_t st);
+
+// krylov.hip
+int stream_blocks(long long n);
+void launch_mdot(long long n, const double *w, const double *V, long long ldv, int nv,
+                 double *partial, int nblk, hipStream_t st);
+void launch_mdot_final(int nv, const double *partial, int nblk, const double *invbeta,
+                       double *h, double *c, hipStream_t st);
+void launch_orth(long long n, double *w, const double *V, long long ldv, int nv,
+                 const double *c, double *partial, int nblk, hipStream_t st);
+void launch_norm_final(const double *partial, int nblk, double *beta_out, double *invbeta_out,
+                       hipStream_t st);
+template <typename TZ>
+void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const double *y,
+               hipStream_t st);
+void launch_dot_partial(long long n, const double *a, const double *b, double *partial,
+                        int nblk, hipStream_t st);
+
+}  // namespace p4d

@@ -1,0 +1,96 @@
+"""Torch-facing wrapper of one solver context: owns the device workspace
+(a torch uint8 tensor) and forwards every call to the C ABI."""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+class P4DSolver:
+    """One linearized P4D-DFN Jacobian on the current GPU.
+
+    ``prob`` is any object carrying the problem description fields and the
+    coefficient arrays ``sigma, kappa`` (per element) and ``g, s, e`` (per
+    electrode node), as numpy arrays or torch tensors."""
+
+    def __init__(self, prob, restart: int = 30, z_fp32: bool = False, pc_prec: int = L.P4D_FP64,
+                 coarse_max: int = 512, device: str = "cuda"):
+        self.device = torch.device(device)
+        self.desc = L.desc_from(prob)
+        self.ctx = L.p4d_create(self.desc)
+        self.N, self.offsets, self.n_elem, self.n_e = L.p4d_vector_size(self.ctx)
+        self.ws_opts = L.default_opts(restart=restart, z_fp32=int(z_fp32), pc_prec=pc_prec,
+                                      coarse_max=coarse_max)
+        nbytes = L.p4d_workspace_size(self.ctx, self.ws_opts)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)
+        self.upload(prob.sigma, prob.kappa, prob.g, prob.s, prob.e)
+        self.opts = None
+
+    def _dev(self, a):
+        if isinstance(a, torch.Tensor):
+            return a.to(self.device, torch.float64).contiguous()
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    def upload(self, sigma, kappa, g, s, e):
+        arrs = [self._dev(a) for a in (sigma, kappa, g, s, e)]
+        assert arrs[0].numel() == self.n_elem and arrs[1].numel() == self.n_elem
+        assert all(a.numel() == self.n_e for a in arrs[2:])
+        L.p4d_upload(self.ctx, *arrs)
+        self.opts = None
+
+    def setup(self, **kw):
+        o = L.default_opts(**kw)
+        L.p4d_setup(self.ctx, o)
+        self.opts = o
+        return self
+
+    def apply(self, x, transpose=False):
+        x = self._dev(x)
+        y = torch.empty_like(x)
+        L.p4d_apply_operator(self.ctx, transpose, x, y)
+        return y
+
+    def apply_pc(self, r, transpose=False):
+        r = self._dev(r)
+        z = torch.empty_like(r)
+        L.p4d_apply_preconditioner(self.ctx, transpose, r, z)
+        return z
+
+    def _opts(self, kw):
+        if self.opts is None:
+            raise RuntimeError("call setup() first")
+        o = L.SolveOpts.from_buffer_copy(self.opts)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def solve(self, b, **kw):
+        b = self._dev(b)
+        x = torch.empty_like(b)
+        st, info = L.p4d_solve(self.ctx, b, x, self._opts(kw))
+        return x, info
+
+    def solve_adjoint(self, g, **kw):
+        g = self._dev(g)
+        lam = torch.empty_like(g)
+        st, info = L.p4d_solve_adjoint(self.ctx, g, lam, self._opts(kw))
+        return lam, info
+
+    def gradient(self, x, lam):
+        ds = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+        dD = torch.empty(2, dtype=torch.float64, device=self.device)
+        L.p4d_param_gradient(self.ctx, self._dev(x), self._dev(lam), ds, dD)
+        return ds, dD
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.p4d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
