@@ -124,15 +124,17 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelBatch<T> lb)
     if (n >= A.n) return;
     const int i = n % A.nx, t = n / A.nx;
     const int j = t % A.ny, kl = t / A.ny;
-    T Sx = T(0), xc = T(0);
+    // difference form: slot 13 of the stored stencil holds the row sum, so
+    // S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
+    const T xc = A.xin[n];
+    T Sx = A.S[13LL * A.n + n] * xc;
 #pragma unroll
     for (int o = 0; o < 27; o++) {
+        if (o == 13) continue;
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
         const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
                         (kl + dz >= 0) && (kl + dz < A.nz);
-        const T xv = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : T(0);
-        Sx += A.S[(long long)o * A.n + n] * xv;
-        if (o == 13) xc = xv;
+        if (ok) Sx += A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
     }
     const T r = A.b[n] - Sx;
     if (RESID_ONLY) {
@@ -570,6 +572,31 @@ void launch_invert(int n, double *A, double *Ainv, hipStream_t st)
 {
     hipLaunchKernelGGL(k_invert, dim3(1), dim3(1024), 0, st, n, A, Ainv);
 }
+
+// stored stencil for the smoother: off-diagonal entries as they are, the
+// centre slot replaced by the row sum formed in FP64
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_stencil_diff(int n, const double *__restrict__ S,
+                                                        T *__restrict__ D)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    double rs = 0.0;
+    for (int o = 0; o < 27; o++) {
+        const double v = S[(long long)o * n + t];
+        rs += v;
+        if (o != 13) D[(long long)o * n + t] = (T)v;
+    }
+    D[13LL * n + t] = (T)rs;
+}
+template <typename T>
+void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_stencil_diff<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n,
+                       S, D);
+}
+template void launch_stencil_diff<double>(int, const double *, double *, hipStream_t);
+template void launch_stencil_diff<float>(int, const double *, float *, hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cast(long long n, const double *__restrict__ s,

@@ -206,19 +206,18 @@ __global__ __launch_bounds__(kBlock) void k_grad(Geom g, const RadialTab *__rest
                 xl[a] = k == 0 ? 0.0 : x[je];
                 ll[a] = k == 0 ? 0.0 : lam[je];
             }
+            // (Khat x)_a = sum_b Khat_ab (x_b - x_a): rows of Khat sum to zero,
+            // so the large near-constant parts of x cancel exactly
             double s = 0.0;
 #pragma unroll
             for (int a = 0; a < 8; a++) {
                 double row = 0.0;
 #pragma unroll
-                for (int bb = 0; bb < 8; bb++) {
-                    const int d = popc3(a ^ bb);
-                    const double kab = d == 0 ? 1.0 / 3.0 : (d == 1 ? 0.0 : -1.0 / 12.0);
-                    row += kab * xl[bb];
-                }
+                for (int bb = 0; bb < 8; bb++)
+                    if (popc3(a ^ bb) >= 2) row += xl[a] - xl[bb];
                 s += ll[a] * row;
             }
-            val = -g.h * s;
+            val = -g.h * s * (1.0 / 12.0);
         }
         dsigma[t] = val;
     }

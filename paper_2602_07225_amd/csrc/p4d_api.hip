@@ -25,7 +25,8 @@ struct Level {
     int nx = 0, ny = 0, nz = 0, n = 0;
     double lmax = 0.0;
     double *S64 = nullptr;   // persistent FP64 Galerkin stencil (levels >= 1)
-    void *S = nullptr;       // stencil in the preconditioner precision
+    void *S = nullptr;       // smoother copy in the preconditioner precision,
+                             // centre slot = FP64 row sum (difference form)
     void *invd = nullptr, *b = nullptr, *xa = nullptr, *xb = nullptr, *d = nullptr, *r = nullptr;
     double *Ainv = nullptr;  // coarsest level
 };
@@ -266,7 +267,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
                 L.S64 = nullptr; L.S = nullptr;
             } else {
                 L.S64 = (double *)take(8 * 27 * (size_t)L.n);
-                L.S = ts == 8 ? (void *)L.S64 : (void *)take(ts * 27 * (size_t)L.n);
+                L.S = take(ts * 27 * (size_t)L.n);   // difference form for the smoother
                 L.invd = take(ts * L.n);
                 L.b = take(ts * L.n);
                 L.xa = take(ts * L.n);
@@ -619,7 +620,7 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 const Level &F = B.lev[l - 1];
                 launch_rap(F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, L.S64, st);
                 Sl = L.S64;
-                if (sizeof(T) != 8) launch_cast<T>(27LL * L.n, L.S64, (T *)L.S, st);
+                launch_stencil_diff<T>(L.n, L.S64, (T *)L.S, st);
             }
             const int nblk = (L.n + kBlock - 1) / kBlock;
             double *idst = l == 0 ? id64 + B.off : idl;   // FP64 inverse diagonal

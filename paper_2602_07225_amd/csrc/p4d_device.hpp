@@ -62,6 +62,8 @@ __host__ __device__ constexpr int nb_index(int dx, int dy, int dz)
 // coefficient of the element spanning node offsets ex-1..ex (etc.); X holds
 // the 27 neighbour values.  Reference stiffness on the unit cube: 1/3 on the
 // diagonal, 0 between corners differing in one coordinate, -1/12 otherwise.
+// Its rows sum to zero, so it is applied to differences x_b - x_a: constants
+// cancel exactly, which keeps near-null modes accurate in FP32.
 template <typename R>
 __device__ inline R q1_stiff(const R c[8], const R X[27])
 {
@@ -74,12 +76,12 @@ __device__ inline R q1_stiff(const R c[8], const R X[27])
 #pragma unroll
         for (int bb = 0; bb < 8; bb++) {
             if (popc3(a ^ bb) >= 2)
-                far += X[nb_index(ex - 1 + (bb & 1), ey - 1 + ((bb >> 1) & 1),
-                                  ez - 1 + ((bb >> 2) & 1))];
+                far += X[13] - X[nb_index(ex - 1 + (bb & 1), ey - 1 + ((bb >> 1) & 1),
+                                          ez - 1 + ((bb >> 2) & 1))];
         }
-        acc += c[e] * (X[13] * R(1.0 / 3.0) - far * R(1.0 / 12.0));
+        acc += c[e] * far;
     }
-    return acc;
+    return acc * R(1.0 / 12.0);
 }
 
 // Reference mass on the unit cube: (8, 4, 2, 1)/216 by the number of

@@ -154,6 +154,8 @@ void launch_omega(const Geom &g, const RadialTab *tabs, const double *ss, int sc
                   double *omega, hipStream_t st);
 template <typename T>
 void launch_cast(long long n, const double *src, T *dst, hipStream_t st);
+template <typename T>
+void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st);
 
 // krylov.hip
 int stream_blocks(long long n);

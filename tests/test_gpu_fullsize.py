@@ -39,7 +39,10 @@ def test_C2_preconditioner_full():
     r = np.random.default_rng(6).standard_normal(p.N)
     errs = field_errors(p, to_np(s.apply_pc(to_dev(r))), orc.apply_pc(r))
     say("  errors", {k: f"{v:.1e}" for k, v in errs.items()})
-    assert max(errs.values()) <= 1e-10
+    # The field operators given to the V-cycles have condition ~1e7 here
+    # (constant-mode eigenvalue ~ omega m g ~ h^3 against stiffness ~ h), so
+    # FP64 results that differ only in summation order agree to ~1e-16 * 1e7.
+    assert max(errs.values()) <= 1e-8
 
 
 def test_C2_solve_full():
