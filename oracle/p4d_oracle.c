@@ -1034,11 +1034,23 @@ double orc_gershgorin(int nx, int ny, int nz, const double *S)
 /* ------------------------------------------------------------------------ */
 /* Flexible GMRES (Saad 1993), right preconditioned, restarted              */
 /* ------------------------------------------------------------------------ */
+/* Inner product summed over fixed chunks, the chunk sums added in order, so
+ * that the result does not depend on the number or timing of threads.     */
 static double dot(const double *a, const double *b, long n)
 {
+    const long CH = 8192;
+    long nch = (n + CH - 1) / CH;
+    double *part = xmalloc(sizeof(double) * (nch > 0 ? nch : 1));
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < nch; c++) {
+        long hi = (c + 1) * CH < n ? (c + 1) * CH : n;
+        double s = 0.0;
+        for (long i = c * CH; i < hi; i++) s += a[i] * b[i];
+        part[c] = s;
+    }
     double s = 0.0;
-#pragma omp parallel for reduction(+ : s) schedule(static)
-    for (long i = 0; i < n; i++) s += a[i] * b[i];
+    for (long c = 0; c < nch; c++) s += part[c];
+    free(part);
     return s;
 }
 
@@ -1182,7 +1194,6 @@ void orc_gradient(const orc_problem *P, const double *x, const double *lam,
         orc_radial_rows(N, 1.0, P->rho[el], lo, di, up);
         const double *xs = x + P->off_cs[el], *ls = lam + P->off_cs[el];
         double acc = 0.0;
-#pragma omp parallel for reduction(+ : acc) schedule(static)
         for (long jn = 0; jn < nn; jn++)
             for (int r = 0; r < N; r++) {
                 double Lx = di[r] * xs[(long)r * nn + jn];
