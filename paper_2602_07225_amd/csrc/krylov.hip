@@ -41,8 +41,10 @@ __global__ __launch_bounds__(kBlock) void k_mdot(long long n, const double *__re
         }
     }
     __syncthreads();
+    // partial sums stored [q][block] so that the final reduction reads them
+    // contiguously
     if (threadIdx.x < nv)
-        partial[(long long)blockIdx.x * kPStride + threadIdx.x] =
+        partial[(long long)threadIdx.x * gridDim.x + blockIdx.x] =
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
@@ -59,22 +61,20 @@ void launch_mdot(long long n, const double *w, const double *V, long long ldv, i
 #undef P4D_MD
 }
 
-// h_q = invbeta_q * sum_b partial[b][q];  c_q = h_q * invbeta_q
+// h_q = invbeta_q * sum_b partial[q][b];  c_q = h_q * invbeta_q; one
+// workgroup per q
 __global__ __launch_bounds__(kBlock) void k_mdot_final(int nv, const double *__restrict__ partial,
                                                        int nblk, const double *__restrict__ invbeta,
                                                        double *__restrict__ h,
                                                        double *__restrict__ c)
 {
-    __shared__ double red[4][kPStride];
-    const int q = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    __shared__ double red[4];
+    const int q = blockIdx.x;
     double s = 0.0;
-    if (q < nv)
-        for (int b = grp; b < nblk; b += 4) s += partial[(long long)b * kPStride + q];
-    red[grp][q] = s;
-    __syncthreads();
-    if (threadIdx.x < nv) {
-        const double tot = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
-        const double hq = tot * invbeta[q];
+    for (int b = threadIdx.x; b < nblk; b += kBlock) s += partial[(long long)q * nblk + b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        const double hq = s * invbeta[q];
         h[q] = hq;
         c[q] = hq * invbeta[q];
     }
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot_final(int nv, const double *__r
 void launch_mdot_final(int nv, const double *partial, int nblk, const double *invbeta, double *h,
                        double *c, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mdot_final, dim3(1), dim3(kBlock), 0, st, nv, partial, nblk, invbeta, h, c);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(kBlock), 0, st, nv, partial, nblk, invbeta, h, c);
 }
 
 template <int KMAX>

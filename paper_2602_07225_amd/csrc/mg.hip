@@ -66,36 +66,35 @@ __global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb)
     const int i = n % A.nx, t = n / A.nx;
     const int j = t % A.ny, kl = t / A.ny;
     const int k = kl + A.k0;
-    using R = T;
-    R cK[8], cM[8];
+    double cK[8], cM[8];
 #pragma unroll
     for (int e = 0; e < 8; e++) {
         const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
         const bool ok = ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 && ek >= A.ek_lo &&
                         ek <= A.ek_hi;
         const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
-        cK[e] = ok ? (R)A.cK[id] : R(0);
-        cM[e] = (ok && A.mass) ? (R)(elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : R(0);
+        cK[e] = ok ? A.cK[id] : 0.0;
+        cM[e] = (ok && A.mass) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
     }
-    R X[27];
+    double X[27];
 #pragma unroll
     for (int o = 0; o < 27; o++) {
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
         const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
                         (kl + dz >= 0) && (kl + dz < A.nz);
-        X[o] = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : R(0);
+        X[o] = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : 0.0;
     }
-    R Sx = q1_stiff(cK, X) + A.dcorr[n] * X[13];
+    double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
     if (A.mass) Sx += q1_mass(cM, X);
-    const R r = A.b[n] - Sx;
+    const double r = (double)A.b[n] - Sx;
     if (RESID_ONLY) {
-        A.rout[n] = r;
+        A.rout[n] = (T)r;
         return;
     }
-    R d = (R)A.c2 * A.invd[n] * r;
-    if (A.c1 != 0.0) d += (R)A.c1 * A.din[n];
+    double d = A.c2 * (double)A.invd[n] * r;
+    if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
     A.xout[n] = X[13] + d;
-    if (A.dout) A.dout[n] = d;
+    if (A.dout) A.dout[n] = (T)d;
 }
 
 template <typename T>
@@ -126,25 +125,26 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelBatch<T> lb)
     const int j = t % A.ny, kl = t / A.ny;
     // difference form: slot 13 of the stored stencil holds the row sum, so
     // S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
-    const T xc = A.xin[n];
-    T Sx = A.S[13LL * A.n + n] * xc;
+    const double xc = A.xin[n];
+    double Sx = (double)A.S[13LL * A.n + n] * xc;
 #pragma unroll
     for (int o = 0; o < 27; o++) {
         if (o == 13) continue;
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
         const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
                         (kl + dz >= 0) && (kl + dz < A.nz);
-        if (ok) Sx += A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
+        if (ok)
+            Sx += (double)A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
     }
-    const T r = A.b[n] - Sx;
+    const double r = (double)A.b[n] - Sx;
     if (RESID_ONLY) {
-        A.rout[n] = r;
+        A.rout[n] = (T)r;
         return;
     }
-    T d = (T)A.c2 * A.invd[n] * r;
-    if (A.c1 != 0.0) d += (T)A.c1 * A.din[n];
+    double d = A.c2 * (double)A.invd[n] * r;
+    if (A.c1 != 0.0) d += A.c1 * (A.din_x ? xc : (double)A.din[n]);
     A.xout[n] = xc + d;
-    if (A.dout) A.dout[n] = d;
+    if (A.dout) A.dout[n] = (T)d;
 }
 
 template <typename T>
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(TransferBatch<T> tb)
         }
     const T bc = (T)acc;
     A.bc[n] = bc;
-    if (A.xc1) A.xc1[n] = (T)A.c2c * A.invdc[n] * bc;
+    if (A.xc1) A.xc1[n] = A.c2c * (double)A.invdc[n] * (double)bc;
 }
 
 // x_f += P x_c
@@ -221,10 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong(TransferBatch<T> tb)
         for (int bq = 0; bq < nj; bq++) {
             const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
             double part = 0.0;
-            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.xc[row + Ci[a]];
+            for (int a = 0; a < ni; a++) part += wi[a] * A.xc[row + Ci[a]];
             acc += wj[bq] * wk[c] * part;
         }
-    A.xf[n] = (T)((double)A.xf[n] + acc);
+    A.xf[n] += acc;
 }
 
 template <typename T>
@@ -248,18 +248,26 @@ template void launch_prolong<float>(const TransferBatch<float> &, int, hipStream
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(CoarseBatch<T> cb)
 {
+    // 64 rows per workgroup; the 4 waves split the columns, then add up
     __shared__ double bl[1024];
+    __shared__ double part[4][64];
     const int box = blockIdx.y;
     if (box >= cb.nbox) return;
     const CoarseArgs<T> &A = cb.a[box];
     const int n = A.n;
+    if (blockIdx.x * 64 >= n) return;
     for (int q = threadIdx.x; q < n; q += kBlock) bl[q] = (double)A.b[q];
     __syncthreads();
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row >= n) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = blockIdx.x * 64 + lane;
     double acc = 0.0;
-    for (int c = 0; c < n; c++) acc += A.Ainv[(long long)c * n + row] * bl[c];
-    A.x[row] = (T)acc;
+    if (row < n) {
+#pragma unroll 4
+        for (int c = w; c < n; c += 4) acc += A.Ainv[(long long)c * n + row] * bl[c];
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < n) A.x[row] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 template <typename T>
@@ -267,8 +275,7 @@ void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st)
 {
     int nmax = 1;
     for (int b = 0; b < cb.nbox; b++) nmax = cb.a[b].n > nmax ? cb.a[b].n : nmax;
-    hipLaunchKernelGGL((k_coarse<T>), dim3((nmax + kBlock - 1) / kBlock, cb.nbox), dim3(kBlock),
-                       0, st, cb);
+    hipLaunchKernelGGL((k_coarse<T>), dim3((nmax + 63) / 64, cb.nbox), dim3(kBlock), 0, st, cb);
 }
 template void launch_coarse<double>(const CoarseBatch<double> &, hipStream_t);
 template void launch_coarse<float>(const CoarseBatch<float> &, hipStream_t);
@@ -416,63 +423,80 @@ void launch_assemble0(const Geom &g, int, int nz, int k0, int ek_lo, int ek_hi, 
                        k0, ek_lo, ek_hi, mass, cK, dcorr, S);
 }
 
-// Galerkin coarse stencil: S_c(I, J) = sum_{i,j} P(i,I) S(i,j) P(j,J), gathered
-// per coarse row I; per-thread accumulators live in LDS.
-constexpr int kRapBlock = 64;
-__global__ __launch_bounds__(kRapBlock) void k_rap(int fx, int fy, int fz,
-                                                   const double *__restrict__ Sf,
-                                                   double *__restrict__ Sc)
+// Galerkin coarse stencil S_c = P^T S P with P = P_x (x) P_y (x) P_z, done as
+// three 1D Galerkin coarsenings (along x, then y, then z): each keeps the
+// 27-point pattern and needs 3 x 27 x 2 products per output row instead of
+// the 27 x 27 x 8 of the direct triple product.
+template <int AX>
+__global__ __launch_bounds__(kBlock) void k_rap1d(int nx, int ny, int nz,
+                                                  const double *__restrict__ Sf,
+                                                  double *__restrict__ Sc)
 {
-    __shared__ double acc[kRapBlock * 27];
-    const int cx = coarse_n(fx), cy = coarse_n(fy), cz = coarse_n(fz);
-    const int nc = cx * cy * cz, nf = fx * fy * fz;
-    const int n = blockIdx.x * kRapBlock + threadIdx.x;
-    double *my = acc + threadIdx.x * 27;
-    for (int o = 0; o < 27; o++) my[o] = 0.0;
-    if (n < nc) {
-        const int I = n % cx, t = n / cx;
-        const int J = t % cy, K = t / cy;
-        int fi[3], fj[3], fk[3];
-        double wi[3], wj[3], wk[3];
-        const int ni = fine_of(fx, I, fi, wi);
-        const int nj = fine_of(fy, J, fj, wj);
-        const int nk = fine_of(fz, K, fk, wk);
-        for (int c = 0; c < nk; c++)
-            for (int bq = 0; bq < nj; bq++)
-                for (int a = 0; a < ni; a++) {
-                    const double w = wi[a] * wj[bq] * wk[c];
-                    const int i = fi[a], j = fj[bq], k = fk[c];
-                    const long long row = i + (long long)fx * (j + (long long)fy * k);
-                    for (int o = 0; o < 27; o++) {
-                        const double s = Sf[(long long)o * nf + row];
-                        if (s == 0.0) continue;
-                        const int ii = i + o % 3 - 1, jj = j + (o / 3) % 3 - 1, kk = k + o / 9 - 1;
-                        int Ci[2], Cj[2], Ck[2];
-                        double vi[2], vj[2], vk[2];
-                        const int mi = coarse_of(fx, ii, Ci, vi);
-                        const int mj = coarse_of(fy, jj, Cj, vj);
-                        const int mk = coarse_of(fz, kk, Ck, vk);
-                        for (int c2 = 0; c2 < mk; c2++)
-                            for (int b2 = 0; b2 < mj; b2++)
-                                for (int a2 = 0; a2 < mi; a2++) {
-                                    const int ox = Ci[a2] - I, oy = Cj[b2] - J, oz = Ck[c2] - K;
-                                    // nested coarsening keeps the product within
-                                    // the 27-point pattern; guard regardless
-                                    if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1)
-                                        continue;
-                                    my[nb_index(ox, oy, oz)] += w * s * vi[a2] * vj[b2] * vk[c2];
-                                }
-                    }
+    // input dims (nx, ny, nz); output coarse along axis AX
+    const int fa = AX == 0 ? nx : (AX == 1 ? ny : nz);
+    const int ca = coarse_n(fa);
+    const int ox = AX == 0 ? ca : nx, oy = AX == 1 ? ca : ny, oz = AX == 2 ? ca : nz;
+    const int no = ox * oy * oz, nf = nx * ny * nz;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= no) return;
+    const int I0 = n % ox, t = n / ox, J0 = t % oy, K0 = t / oy;
+    const int Ia = AX == 0 ? I0 : (AX == 1 ? J0 : K0);   // coarse index along AX
+    int fi[3];
+    double wf[3];
+    const int nfi = fine_of(fa, Ia, fi, wf);
+    double acc[27];
+#pragma unroll
+    for (int o = 0; o < 27; o++) acc[o] = 0.0;
+    for (int q = 0; q < nfi; q++) {
+        const int f = fi[q];
+        const int i = AX == 0 ? f : I0, j = AX == 1 ? f : J0, k = AX == 2 ? f : K0;
+        const long long row = i + (long long)nx * (j + (long long)ny * k);
+#pragma unroll
+        for (int da = -1; da <= 1; da++) {
+            const int g2 = f + da;                 // fine neighbour along AX
+            if (g2 < 0 || g2 >= fa) continue;
+            int Cj[2];
+            double vj[2];
+            const int nc = coarse_of(fa, g2, Cj, vj);
+#pragma unroll
+            for (int m = 0; m < 9; m++) {          // offsets along the other two axes
+                const int d1 = m % 3 - 1, d2 = m / 3 - 1;
+                const int dx = AX == 0 ? da : d1;
+                const int dy = AX == 0 ? d1 : (AX == 1 ? da : d2);
+                const int dz = AX == 2 ? da : d2;
+                const double sv = Sf[(long long)nb_index(dx, dy, dz) * nf + row];
+                if (sv == 0.0) continue;
+                for (int c = 0; c < nc; c++) {
+                    const int off = Cj[c] - Ia;
+                    if (off < -1 || off > 1) continue;
+                    const int ex = AX == 0 ? off : d1;
+                    const int ey = AX == 0 ? d1 : (AX == 1 ? off : d2);
+                    const int ez = AX == 2 ? off : d2;
+                    const double v = wf[q] * sv * vj[c];
+                    // compile-time slot except for the coarse offset
+                    if (off == -1) acc[nb_index(AX == 0 ? -1 : ex, AX == 1 ? -1 : ey, AX == 2 ? -1 : ez)] += v;
+                    else if (off == 0) acc[nb_index(AX == 0 ? 0 : ex, AX == 1 ? 0 : ey, AX == 2 ? 0 : ez)] += v;
+                    else acc[nb_index(AX == 0 ? 1 : ex, AX == 1 ? 1 : ey, AX == 2 ? 1 : ez)] += v;
                 }
-        for (int o = 0; o < 27; o++) Sc[(long long)o * nc + n] = my[o];
+            }
+        }
     }
+#pragma unroll
+    for (int o = 0; o < 27; o++) Sc[(long long)o * no + n] = acc[o];
 }
 
-void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, hipStream_t st)
+void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, double *tmp, hipStream_t st)
 {
-    const int nc = coarse_n(fx) * coarse_n(fy) * coarse_n(fz);
-    hipLaunchKernelGGL(k_rap, dim3((nc + kRapBlock - 1) / kRapBlock), dim3(kRapBlock), 0, st, fx,
-                       fy, fz, Sf, Sc);
+    const int cx = coarse_n(fx), cy = coarse_n(fy), cz = coarse_n(fz);
+    double *t1 = tmp;                                   // (cx, fy, fz)
+    double *t2 = tmp + 27LL * cx * fy * fz;             // (cx, cy, fz)
+    const int n1 = cx * fy * fz, n2 = cx * cy * fz, n3 = cx * cy * cz;
+    hipLaunchKernelGGL(k_rap1d<0>, dim3((n1 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fx, fy,
+                       fz, Sf, t1);
+    hipLaunchKernelGGL(k_rap1d<1>, dim3((n2 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, cx, fy,
+                       fz, t1, t2);
+    hipLaunchKernelGGL(k_rap1d<2>, dim3((n3 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, cx, cy,
+                       fz, t2, Sc);
 }
 
 // inverse diagonal and per-block maxima of the Gershgorin ratio sum|s_ij|/s_ii
@@ -532,14 +556,18 @@ __global__ __launch_bounds__(kBlock) void k_dense(int nx, int ny, int nz,
     A[t] = 0.5 * (entry(r, c) + entry(c, r));
 }
 
-// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting), one
-// workgroup; result written column-major (== row-major for the symmetric
+// In-place Gauss-Jordan inversion of SPD matrices (no pivoting), one
+// workgroup per matrix; each wave sweeps rows, its lanes the columns.  The
+// result is written column-major (equal to row-major for the symmetric
 // inverse).
-__global__ __launch_bounds__(1024) void k_invert(int n, double *__restrict__ A,
-                                                 double *__restrict__ Ainv)
+__global__ __launch_bounds__(1024) void k_invert(InvBatch ib)
 {
     __shared__ double rowp[1024];
     __shared__ double colp[1024];
+    const int box = blockIdx.x;
+    const int n = ib.n[box];
+    double *A = ib.A[box];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     for (int p = 0; p < n; p++) {
         __syncthreads();
         const double d = 1.0 / A[(long long)p * n + p];
@@ -548,18 +576,20 @@ __global__ __launch_bounds__(1024) void k_invert(int n, double *__restrict__ A,
             colp[q] = A[(long long)q * n + p];
         }
         __syncthreads();
-        for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) {
-            const int i = (int)(t / n), j = (int)(t % n);
-            double v;
-            if (i == p && j == p) v = d;
-            else if (i == p) v = rowp[j];
-            else if (j == p) v = -colp[i] * d;
-            else v = A[t] - colp[i] * rowp[j];
-            A[t] = v;
+        for (int i = wave; i < n; i += nw) {
+            const double ci = colp[i];
+            double *Ai = A + (long long)i * n;
+            for (int j = lane; j < n; j += 64) {
+                double v;
+                if (i == p) v = j == p ? d : rowp[j];
+                else v = j == p ? -ci * d : Ai[j] - ci * rowp[j];
+                Ai[j] = v;
+            }
         }
     }
     __syncthreads();
-    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) Ainv[t] = A[t];
+    double *out = ib.Ainv[box];
+    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) out[t] = A[t];
 }
 
 void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *A, hipStream_t st)
@@ -568,9 +598,9 @@ void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *
     hipLaunchKernelGGL(k_dense, dim3((int)((n * n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
                        ny, nz, S, A);
 }
-void launch_invert(int n, double *A, double *Ainv, hipStream_t st)
+void launch_invert(const InvBatch &ib, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_invert, dim3(1), dim3(1024), 0, st, n, A, Ainv);
+    hipLaunchKernelGGL(k_invert, dim3(ib.nbox), dim3(1024), 0, st, ib);
 }
 
 // stored stencil for the smoother: off-diagonal entries as they are, the

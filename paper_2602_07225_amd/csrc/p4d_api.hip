@@ -236,8 +236,8 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->scal = (double *)take(8 * 128);
     const long long Nm = g.Nm;
     c->b0 = take(ts * Nm);
-    c->x0a = take(ts * Nm);
-    c->x0b = take(ts * Nm);
+    c->x0a = take(8 * Nm);          // iterates are FP64 in every mode
+    c->x0b = take(8 * Nm);
     c->d0 = take(ts * Nm);
     c->r0 = take(ts * Nm);
     c->invd0 = take(ts * Nm);
@@ -259,25 +259,25 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
             L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
             L.n = L.nx * L.ny * L.nz;
             if (l == 0) {
-                auto at = [&](void *p) -> void * {
-                    return base ? (void *)((char *)p + ts * B.off) : nullptr;
+                auto at = [&](void *p, size_t es) -> void * {
+                    return base ? (void *)((char *)p + es * B.off) : nullptr;
                 };
-                L.b = at(c->b0); L.xa = at(c->x0a); L.xb = at(c->x0b); L.d = at(c->d0);
-                L.r = at(c->r0); L.invd = at(c->invd0);
+                L.b = at(c->b0, ts); L.xa = at(c->x0a, 8); L.xb = at(c->x0b, 8);
+                L.d = at(c->d0, ts); L.r = at(c->r0, ts); L.invd = at(c->invd0, ts);
                 L.S64 = nullptr; L.S = nullptr;
             } else {
                 L.S64 = (double *)take(8 * 27 * (size_t)L.n);
                 L.S = take(ts * 27 * (size_t)L.n);   // difference form for the smoother
                 L.invd = take(ts * L.n);
                 L.b = take(ts * L.n);
-                L.xa = take(ts * L.n);
-                L.xb = take(ts * L.n);
+                L.xa = take(8 * (size_t)L.n);
+                L.xb = take(8 * (size_t)L.n);
                 L.d = take(ts * L.n);
                 L.r = take(ts * L.n);
             }
             if (l == B.nlev - 1) {
                 L.Ainv = (double *)take(8 * (size_t)L.n * L.n);
-                setup_need = setup_need > 8 * (size_t)L.n * L.n ? setup_need : 8 * (size_t)L.n * L.n;
+                setup_need += align_up(8 * (size_t)L.n * L.n);   // dense copy per box
             }
         }
     }
@@ -285,10 +285,19 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     // inverse diagonal + dense coarse matrix
     size_t s0 = 0;
     for (int b = 0; b < 4; b++) s0 += align_up(8 * 27 * (size_t)c->box[b].lev[0].n);
-    size_t n1max = 0;
-    for (int b = 0; b < 4; b++)
-        if (c->box[b].nlev > 1 && (size_t)c->box[b].lev[1].n > n1max) n1max = c->box[b].lev[1].n;
-    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(setup_need);
+    size_t n1max = 0, rapmax = 0;
+    for (int b = 0; b < 4; b++) {
+        const Box &B = c->box[b];
+        if (B.nlev > 1 && (size_t)B.lev[1].n > n1max) n1max = B.lev[1].n;
+        for (int l = 0; l + 1 < B.nlev; l++) {
+            const Level &F = B.lev[l];
+            const size_t cx = coarse_n_h(F.nx), cy = coarse_n_h(F.ny);
+            const size_t t = 27 * (cx * F.ny * F.nz + cx * cy * F.nz);
+            rapmax = t > rapmax ? t : rapmax;
+        }
+    }
+    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(8 * rapmax) +
+          align_up(setup_need);
     // Krylov basis
     const int m = o.restart;
     const size_t zs = o.z_fp32 ? sizeof(float) : sizeof(double);
@@ -395,8 +404,7 @@ struct VState {
     int xcur[4][kMaxLevels];   // 0: xa, 1: xb holds the current iterate
 };
 
-template <typename T>
-static T *lvx(Level &L, int which) { return (T *)(which ? L.xb : L.xa); }
+static double *lvx(Level &L, int which) { return (double *)(which ? L.xb : L.xa); }
 
 template <typename T>
 static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int nb, int step,
@@ -422,12 +430,15 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
         A.dcorr = l == 0 ? (const T *)c->dcorr0 + B.off : nullptr;
         A.b = (const T *)L.b;
         const int cur = vs.xcur[b][l];
-        A.xin = lvx<T>(L, cur);
-        A.xout = lvx<T>(L, 1 - cur);
+        A.xin = lvx(L, cur);
+        A.xout = lvx(L, 1 - cur);
         A.c1 = C.c1[step];
         A.c2 = C.c2[step];
         // direction: after the fused first pre-smoothing step it equals x
-        A.din = (!post && step == 2) ? lvx<T>(L, cur) : (const T *)L.d;
+        // after the fused first pre-smoothing step (from x = 0) the direction
+        // equals the iterate itself
+        A.din = (const T *)L.d;
+        A.din_x = (!post && step == 2) ? 1 : 0;
         A.dout = step < c->pc.cheb_degree ? (T *)L.d : nullptr;
         A.rout = nullptr;
         vs.xcur[b][l] = 1 - cur;
@@ -461,7 +472,7 @@ static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, in
         A.invd = (const T *)L.invd;
         A.dcorr = l == 0 ? (const T *)c->dcorr0 + B.off : nullptr;
         A.b = (const T *)L.b;
-        A.xin = lvx<T>(L, vs.xcur[b][l]);
+        A.xin = lvx(L, vs.xcur[b][l]);
         A.rout = (T *)L.r;
     }
     if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, st);
@@ -484,7 +495,7 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             cb.a[q].n = L.n;
             cb.a[q].Ainv = L.Ainv;
             cb.a[q].b = (const T *)L.b;
-            cb.a[q].x = (T *)L.xa;
+            cb.a[q].x = (double *)L.xa;
             vs.xcur[crs[q]][l] = 0;
         }
         launch_coarse<T>(cb, st);
@@ -508,7 +519,7 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             A.rf = (const T *)F.r;
             A.bc = (T *)Cl.b;
             const bool coarsest = (l + 1 == B.nlev - 1);
-            A.xc1 = coarsest ? nullptr : (T *)Cl.xa;
+            A.xc1 = coarsest ? nullptr : (double *)Cl.xa;
             A.invdc = (const T *)Cl.invd;
             A.c2c = coarsest ? 0.0 : cheb_coef(Cl.lmax, deg).c2[1];
             vs.xcur[act[q]][l + 1] = 0;
@@ -528,8 +539,8 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz;
             A.blk0 = blk;
             blk += (F.n + kBlock - 1) / kBlock;
-            A.xc = lvx<T>(Cl, vs.xcur[act[q]][l + 1]);
-            A.xf = lvx<T>(F, vs.xcur[act[q]][l]);
+            A.xc = lvx(Cl, vs.xcur[act[q]][l + 1]);
+            A.xf = lvx(F, vs.xcur[act[q]][l]);
         }
         launch_prolong<T>(tb, blk, st);
     }
@@ -549,7 +560,7 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
     {
         ProfScope ps(c, P4D_K_RADIAL, rbytes, st);
         launch_rad_fwd<T>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, r, rscale, (T *)c->b0,
-                          (T *)c->x0a, (const T *)c->invd0, c2box, transpose, schur, st);
+                          (double *)c->x0a, (const T *)c->invd0, c2box, transpose, schur, st);
     }
     VState<T> vs{};
     for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
@@ -560,11 +571,11 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
     for (int b = 0; b < 4; b++) {
         if (vs.xcur[b][0] != ref) {
             Level &L = c->box[b].lev[0];
-            hipMemcpyAsync(lvx<T>(L, ref), lvx<T>(L, 1 - ref), sizeof(T) * L.n,
+            hipMemcpyAsync(lvx(L, ref), lvx(L, 1 - ref), sizeof(double) * L.n,
                            hipMemcpyDeviceToDevice, st);
         }
     }
-    const T *x0 = (const T *)(ref ? c->x0b : c->x0a);
+    const double *x0 = (const double *)(ref ? c->x0b : c->x0a);
     {
         ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + sizeof(T) * g.Nm +
                                           sizeof(TZ) * g.N + 32.0 * g.ne, st);
@@ -601,7 +612,18 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     for (int b = 0; b < 4; b++)
         if (c->box[b].nlev > 1 && (size_t)c->box[b].lev[1].n > n1max) n1max = c->box[b].lev[1].n;
     double *idl = (double *)take(8 * (n1max ? n1max : 1));   // FP64 inverse diagonal, l >= 1
-    double *dense = (double *)sp;
+    size_t rapmax = 0;
+    for (int b = 0; b < 4; b++) {
+        const Box &B = c->box[b];
+        for (int l = 0; l + 1 < B.nlev; l++) {
+            const Level &F = B.lev[l];
+            const size_t cx = coarse_n_h(F.nx), cy = coarse_n_h(F.ny);
+            const size_t t = 27 * (cx * F.ny * F.nz + cx * cy * F.nz);
+            rapmax = t > rapmax ? t : rapmax;
+        }
+    }
+    double *raptmp = (double *)take(8 * (rapmax ? rapmax : 1));
+    InvBatch ib{};
     launch_dcorr<double>(g, c->gg, c->ee, c->mm, c->omega, dc64, st);
     launch_cast<T>(g.Nm, dc64, (T *)c->dcorr0, st);
     // inverse diagonal of level 0 defaults to 0 outside the boxes (the
@@ -618,7 +640,7 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 Sl = S0[b];
             } else {
                 const Level &F = B.lev[l - 1];
-                launch_rap(F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, L.S64, st);
+                launch_rap(F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, L.S64, raptmp, st);
                 Sl = L.S64;
                 launch_stencil_diff<T>(L.n, L.S64, (T *)L.S, st);
             }
@@ -629,11 +651,16 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
             if (l > 0) launch_cast<T>(L.n, idl, (T *)L.invd, st);
             if (l == B.nlev - 1) {
                 if (L.n > 1024) return fail(c, P4D_ERR_INVALID_ARG, "coarsest grid above 1024 nodes");
+                double *dense = (double *)take(8 * (size_t)L.n * L.n);
                 launch_dense_from_stencil(L.nx, L.ny, L.nz, Sl, dense, st);
-                launch_invert(L.n, dense, L.Ainv, st);
+                ib.n[ib.nbox] = L.n;
+                ib.A[ib.nbox] = dense;
+                ib.Ainv[ib.nbox] = L.Ainv;
+                ib.nbox++;
             }
         }
     }
+    launch_invert(ib, st);
     launch_cast<T>(g.Nm, id64, (T *)c->invd0, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal, 8 * 64, hipMemcpyDeviceToHost, st));

@@ -41,7 +41,10 @@ struct RadialTab {
     double hsub[kMaxNr], hdia[kMaxNr], hsup[kMaxNr];   // dL_h/dDs
 };
 
-// One multigrid level of one box, as seen by a batched launch.
+// One multigrid level of one box, as seen by a batched launch.  Iterates x
+// are FP64 in every precision mode (their near-null component can exceed the
+// rest by 1e4..1e6, which FP32 storage would not resolve); T is the storage
+// type of everything else.
 template <typename T>
 struct LevelArgs {
     int nx, ny, nz, n;
@@ -54,12 +57,14 @@ struct LevelArgs {
     const T *invd;                   // inverse diagonal
     const T *dcorr;                  // level 0: diagonal reaction correction
     const T *b;
-    const T *xin;
-    T *xout;
+    const double *xin;
+    double *xout;
     const T *din;
     T *dout;
     T *rout;
     double c1, c2;                   // Chebyshev step: d' = c1 d + c2 D^-1 r
+    int din_x;                       // 1: the previous direction equals x (first
+                                     // step from x = 0), read it from xin
 };
 
 template <typename T>
@@ -75,11 +80,11 @@ struct TransferArgs {
     int blk0;
     const T *rf;                     // fine residual (restriction)
     T *bc;                           // coarse right-hand side (restriction)
-    T *xc1;                          // coarse first smoothing iterate, may be null
+    double *xc1;                     // coarse first smoothing iterate, may be null
     const T *invdc;                  // coarse inverse diagonal
     double c2c;                      // coarse first-step coefficient
-    const T *xc;                     // coarse solution (prolongation)
-    T *xf;                           // fine iterate, updated in place
+    const double *xc;                // coarse solution (prolongation)
+    double *xf;                      // fine iterate, updated in place
 };
 template <typename T>
 struct TransferBatch {
@@ -92,7 +97,7 @@ struct CoarseArgs {
     int n;
     const double *Ainv;              // dense inverse, column-major
     const T *b;
-    T *x;
+    double *x;
 };
 template <typename T>
 struct CoarseBatch {
@@ -116,12 +121,12 @@ void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t
 template <typename T>
 void launch_rad_fwd(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
                     const double *ee, const double *mm, const double *r, double rscale,
-                    T *b0, T *x1, const T *invd0, const double c2box[4], int transpose,
+                    T *b0, double *x1, const T *invd0, const double c2box[4], int transpose,
                     int schur, hipStream_t st);
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
                      const double *ee, const double *mm, const double *r, double rscale,
-                     const T *x0, TZ *z, int transpose, int schur, hipStream_t st);
+                     const double *x0, TZ *z, int transpose, int schur, hipStream_t st);
 
 // mg.hip
 template <typename T>
@@ -137,13 +142,21 @@ template <typename T>
 void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st);
 void launch_assemble0(const Geom &g, int box, int nz, int k0, int ek_lo, int ek_hi, int mass,
                       const double *cK, const double *dcorr, double *S, hipStream_t st);
-void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, hipStream_t st);
+// Galerkin product P^T S P as three 1D coarsenings (x, y, z); tmp needs
+// 27 * (cx*fy*fz + cx*cy*fz) doubles
+void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, double *tmp, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
 void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);
 void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *A,
                                hipStream_t st);
-void launch_invert(int n, double *A, double *Ainv, hipStream_t st);
+struct InvBatch {
+    int nbox;
+    int n[4];
+    double *A[4];
+    double *Ainv[4];
+};
+void launch_invert(const InvBatch &ib, hipStream_t st);
 void launch_setup_nodes(const Geom &g, const RadialTab *tabs, const double *sigma,
                         const double *kappa, double *sigh, double *kaph, double *mm,
                         hipStream_t st);

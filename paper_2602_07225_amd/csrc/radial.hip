@@ -21,7 +21,7 @@ template <typename T, bool TRANS, bool SCHUR>
 __global__ __launch_bounds__(kBlock) void k_rad_fwd(
     Geom g, const RadialTab *__restrict__ tabs, const double *__restrict__ gg,
     const double *__restrict__ ss, const double *__restrict__ ee, const double *__restrict__ mm,
-    const double *__restrict__ r, double rscale, T *__restrict__ b0, T *__restrict__ x1,
+    const double *__restrict__ r, double rscale, T *__restrict__ b0, double *__restrict__ x1,
     const T *__restrict__ invd0, double c2a, double c2c, double c2e, double c2ce)
 {
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -65,19 +65,19 @@ __global__ __launch_bounds__(kBlock) void k_rad_fwd(
         }
         const T bps = (T)rps;
         b0[je] = bps;
-        if (!dir) x1[je] = (T)(el == 0 ? c2a : c2c) * invd0[je] * bps;
+        if (!dir) x1[je] = (el == 0 ? c2a : c2c) * (double)invd0[je] * (double)bps;
     }
     const T bpe = (T)rpe, bce = (T)rce;
     b0[g.off_pe + n] = bpe;
     b0[g.off_ce + n] = bce;
-    x1[g.off_pe + n] = (T)c2e * invd0[g.off_pe + n] * bpe;
-    x1[g.off_ce + n] = (T)c2ce * invd0[g.off_ce + n] * bce;
+    x1[g.off_pe + n] = c2e * (double)invd0[g.off_pe + n] * (double)bpe;
+    x1[g.off_ce + n] = c2ce * (double)invd0[g.off_ce + n] * (double)bce;
 }
 
 template <typename T>
 void launch_rad_fwd(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
                     const double *ee, const double *mm, const double *r, double rscale, T *b0,
-                    T *x1, const T *invd0, const double c2box[4], int transpose, int schur,
+                    double *x1, const T *invd0, const double c2box[4], int transpose, int schur,
                     hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
@@ -98,20 +98,20 @@ template void launch_rad_fwd<double>(const Geom &, const RadialTab *, const doub
                                      const double *, int, int, hipStream_t);
 template void launch_rad_fwd<float>(const Geom &, const RadialTab *, const double *,
                                     const double *, const double *, const double *,
-                                    const double *, double, float *, float *, const float *,
+                                    const double *, double, float *, double *, const float *,
                                     const double *, int, int, hipStream_t);
 
 template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
 __global__ __launch_bounds__(kBlock) void k_rad_back(
     Geom g, const RadialTab *__restrict__ tabs, const double *__restrict__ gg,
     const double *__restrict__ ss, const double *__restrict__ ee, const double *__restrict__ mm,
-    const double *__restrict__ r, double rscale, const T *__restrict__ x0, TZ *__restrict__ z)
+    const double *__restrict__ r, double rscale, const double *__restrict__ x0, TZ *__restrict__ z)
 {
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
     const int k = (int)(n / ((long long)g.nx * g.ny));
-    const double zpe = (double)x0[g.off_pe + n];
-    const double zce = (double)x0[g.off_ce + n];
+    const double zpe = x0[g.off_pe + n];
+    const double zce = x0[g.off_ce + n];
     z[g.off_pe + n] = (TZ)zpe;
     z[g.off_ce + n] = (TZ)zce;
     const int el = node_mat(g, k);
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_rad_back(
     const long long klo = el == 0 ? 0 : g.na + g.ns;
     const long long je = base + n - klo * g.nx * g.ny;
     const bool dir = (k == 0);
-    const double zps = dir ? r[je] * rscale : (double)x0[je];
+    const double zps = dir ? r[je] * rscale : x0[je];
     z[je] = (TZ)zps;
     const RadialTab &Tb = tabs[el];
     const int N = Tb.N;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_rad_back(
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
                      const double *ee, const double *mm, const double *r, double rscale,
-                     const T *x0, TZ *z, int transpose, int schur, hipStream_t st)
+                     const double *x0, TZ *z, int transpose, int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
     const int nrm = g.nr[0] > g.nr[1] ? g.nr[0] : g.nr[1];
@@ -196,11 +196,11 @@ template void launch_rad_back<double, double>(const Geom &, const RadialTab *, c
                                               int, int, hipStream_t);
 template void launch_rad_back<float, double>(const Geom &, const RadialTab *, const double *,
                                              const double *, const double *, const double *,
-                                             const double *, double, const float *, double *,
+                                             const double *, double, const double *, double *,
                                              int, int, hipStream_t);
 template void launch_rad_back<float, float>(const Geom &, const RadialTab *, const double *,
                                             const double *, const double *, const double *,
-                                            const double *, double, const float *, float *, int,
+                                            const double *, double, const double *, float *, int,
                                             int, hipStream_t);
 template void launch_rad_back<double, float>(const Geom &, const RadialTab *, const double *,
                                              const double *, const double *, const double *,
