@@ -108,7 +108,7 @@ typedef struct {
 typedef struct p4d_ctx p4d_ctx;
 
 /* Fill opts with the defaults: SCHUR, FP64, restart 30, maxit 1000, Chebyshev
- * degree 2, coarse_max 512, one Gram-Schmidt pass, FP64 Z, rtol 1e-8.       */
+ * degree 2, coarse_max 64, one Gram-Schmidt pass, FP64 Z, rtol 1e-8.        */
 void p4d_default_opts(p4d_solve_opts *opts);
 
 /* Create a context for the problem `desc` on the current device.  Computes

@@ -223,7 +223,7 @@ class Oracle:
 
     # -- preconditioner --------------------------------------------------------
     def setup(self, pc=PC_SCHUR, restart=30, maxit=1000, rtol=1e-8, cgs2=False,
-              coarse_max=512, cheb_degree=2):
+              coarse_max=64, cheb_degree=2):
         o = Opts()
         o.pc, o.restart, o.maxit, o.cgs2 = pc, restart, maxit, int(cgs2)
         o.rtol, o.coarse_max, o.cheb_degree = rtol, coarse_max, cheb_degree

@@ -598,9 +598,44 @@ void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *
     hipLaunchKernelGGL(k_dense, dim3((int)((n * n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
                        ny, nz, S, A);
 }
+// Same elimination with the matrix resident in LDS (n <= kInvLds).
+constexpr int kInvLds = 80;
+__global__ __launch_bounds__(1024) void k_invert_lds(InvBatch ib)
+{
+    __shared__ double M[kInvLds * kInvLds];
+    __shared__ double rowp[kInvLds], colp[kInvLds];
+    const int box = blockIdx.x;
+    const int n = ib.n[box];
+    const int nn = n * n;
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) M[t] = ib.A[box][t];
+    for (int p = 0; p < n; p++) {
+        __syncthreads();
+        const double d = 1.0 / M[p * n + p];
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            rowp[q] = M[p * n + q] * d;
+            colp[q] = M[q * n + p];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+            const int i = t / n, j = t - i * n;
+            double v;
+            if (i == p) v = j == p ? d : rowp[j];
+            else v = j == p ? -colp[i] * d : M[t] - colp[i] * rowp[j];
+            M[t] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) ib.Ainv[box][t] = M[t];
+}
+
 void launch_invert(const InvBatch &ib, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_invert, dim3(ib.nbox), dim3(1024), 0, st, ib);
+    int nmax = 0;
+    for (int b = 0; b < ib.nbox; b++) nmax = ib.n[b] > nmax ? ib.n[b] : nmax;
+    if (nmax <= kInvLds)
+        hipLaunchKernelGGL(k_invert_lds, dim3(ib.nbox), dim3(1024), 0, st, ib);
+    else
+        hipLaunchKernelGGL(k_invert, dim3(ib.nbox), dim3(1024), 0, st, ib);
 }
 
 // stored stencil for the smoother: off-diagonal entries as they are, the

@@ -444,7 +444,15 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
         vs.xcur[b][l] = 1 - cur;
     }
     if (l == 0) {
-        ProfScope ps(c, P4D_K_SMOOTH0, 0.0, st);
+        // algorithmic bytes: x read and written (FP64), b, D^-1, reaction
+        // diagonal (+ direction in/out) in T, one element coefficient per node
+        double bytes = 0.0;
+        for (int q = 0; q < nb; q++) {
+            const LevelArgs<T> &A = lb.a[q];
+            const double per = 16.0 + 8.0 + sizeof(T) * (3 + (A.c1 != 0.0 && !A.din_x) + (A.dout != nullptr));
+            bytes += per * A.n;
+        }
+        ProfScope ps(c, P4D_K_SMOOTH0, bytes, st);
         launch_smooth0<T>(c->g, lb, blk, 0, st);
     } else {
         launch_smooth<T>(lb, blk, 0, st);
@@ -839,7 +847,7 @@ void p4d_default_opts(p4d_solve_opts *o)
     o->restart = 30;
     o->maxit = 1000;
     o->cheb_degree = 2;
-    o->coarse_max = 512;
+    o->coarse_max = 64;
     o->cgs2 = 0;
     o->z_fp32 = 0;
     o->rtol = 1e-8;

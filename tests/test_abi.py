@@ -67,5 +67,5 @@ def test_invalid_descriptions_rejected_on_host(L):
 def test_default_options(L):
     from paper_2602_07225_amd import _lib
     o = _lib.default_opts()
-    assert (o.pc, o.pc_prec, o.restart, o.maxit, o.cheb_degree, o.coarse_max) == (0, 0, 30, 1000, 2, 512)
+    assert (o.pc, o.pc_prec, o.restart, o.maxit, o.cheb_degree, o.coarse_max) == (0, 0, 30, 1000, 2, 64)
     assert o.rtol == 1e-8

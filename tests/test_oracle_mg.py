@@ -108,9 +108,9 @@ def test_hierarchy_shapes(shape):
         lv = orc.mg_levels(box)
         for (d0, _), (d1, _) in zip(lv[:-1], lv[1:]):
             assert d1 == tuple(n if n <= 2 else n // 2 + 1 for n in d0)
-            assert d0[0] * d0[1] * d0[2] > 512
+            assert d0[0] * d0[1] * d0[2] > 64      # default coarse_max
         last = lv[-1][0]
-        assert last[0] * last[1] * last[2] <= 512 or len(lv) == 1
+        assert last[0] * last[1] * last[2] <= 64 or len(lv) == 1
 
 
 @pytest.mark.parametrize("shape", [(10, 9, 30), (16, 16, 48)])
