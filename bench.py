@@ -153,6 +153,32 @@ def main():
         extras["adjoint_C2"] = {"ms": 1e3 * (time.perf_counter() - t0), "iters": ia.iters,
                                 "status": ia.status}
 
+    if not args.no_extras:
+        # large cell: forward + adjoint solves and gradients (68 M unknowns)
+        p5 = pi.make_config(5)
+        s5 = P4DSolver(p5, restart=30)
+        b5 = torch.as_tensor(p5.b, device="cuda")
+        w5 = torch.as_tensor(pi.functional_weights(p5), device="cuda")
+        s5.setup(**fp64)
+        s5.solve(b5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s5.setup(**fp64)
+        x5, f5 = s5.solve(b5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        l5, a5 = s5.solve_adjoint(w5)
+        g5, gD5 = s5.gradient(x5, l5)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        extras["C5_forward_adjoint"] = {
+            "dof": p5.N, "forward_ms": 1e3 * (t1 - t0), "forward_iters": f5.iters,
+            "adjoint_plus_gradient_ms": 1e3 * (t2 - t1), "adjoint_iters": a5.iters,
+            "DOF_iter_per_s_forward": p5.N * f5.iters / (t1 - t0)}
+        log(f"[bench] C5: forward {1e3 * (t1 - t0):.1f} ms ({f5.iters} it), adjoint+grad "
+            f"{1e3 * (t2 - t1):.1f} ms ({a5.iters} it)")
+        del s5, x5, l5, g5
+
     cpu = None
     if not args.no_cpu:
         import oracle as O

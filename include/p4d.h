@@ -147,6 +147,12 @@ p4d_status p4d_upload(p4d_ctx *ctx, const double *d_sigma, const double *d_kappa
                       const double *d_g, const double *d_s, const double *d_e,
                       void *stream);
 
+/* Replace the particle diffusivities Ds[2] (host array, anode/cathode) of the
+ * problem: recomputes the radial tables (eq. FD rows and their shared
+ * factorization) and copies them to the device on `stream`; invalidates the
+ * last setup.                                                               */
+p4d_status p4d_set_diffusivity(p4d_ctx *ctx, const double Ds[2], void *stream);
+
 /* Build the preconditioner (surface-coupling weights, Galerkin multigrid
  * hierarchies, Chebyshev bounds, dense coarse inverses).  Synchronizes.    */
 p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);

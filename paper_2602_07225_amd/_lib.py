@@ -32,7 +32,7 @@ KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "o
 
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
-    "p4d_set_workspace", "p4d_upload", "p4d_setup", "p4d_apply_operator",
+    "p4d_set_workspace", "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
     "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
     "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error",
     "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_workspace_size",
@@ -93,6 +93,7 @@ def lib():
         L.p4d_set_workspace.argtypes = [vp, vp, C.c_size_t, C.POINTER(SolveOpts)]
         L.p4d_upload.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.p4d_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
+        L.p4d_set_diffusivity.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.p4d_apply_operator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
@@ -106,7 +107,8 @@ def lib():
         L.p4d_last_error.argtypes = [vp]
         L.p4d_last_error.restype = C.c_char_p
         for name in ["p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
-                     "p4d_upload", "p4d_setup", "p4d_apply_operator", "p4d_apply_preconditioner",
+                     "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
+                     "p4d_apply_preconditioner",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
                      "p4d_profile_read"]:
             getattr(L, name).restype = C.c_int
@@ -215,6 +217,12 @@ def p4d_set_workspace(ctx: int, d_work: int, nbytes: int, opts: SolveOpts | None
 def p4d_upload(ctx, sigma, kappa, g, s, e, stream=None):
     return check(lib().p4d_upload(ctx, ptr(sigma), ptr(kappa), ptr(g), ptr(s), ptr(e),
                                   stream_ptr(stream)), ctx, "p4d_upload")
+
+
+def p4d_set_diffusivity(ctx, Ds, stream=None):
+    arr = (C.c_double * 2)(float(Ds[0]), float(Ds[1]))
+    return check(lib().p4d_set_diffusivity(ctx, arr, stream_ptr(stream)), ctx,
+                 "p4d_set_diffusivity")
 
 
 def p4d_setup(ctx, opts: SolveOpts | None = None, stream=None):

@@ -52,62 +52,117 @@ __device__ inline int find_box(const LevelBatch<T> &lb, int b)
 }
 
 // ---------------------------------------------------------------------------
-// Level 0: matrix-free operator from element coefficients
+// Level 0: matrix-free operator from element coefficients, 2.5D tiled.
+// A workgroup owns a TX x TY tile of an x-y plane and marches through a chunk
+// of CZ node layers; three planes of x (with a one-node halo) and two layers
+// of element coefficients sit in LDS rings, so every value is read from
+// memory once per tile and the 27-point neighbourhood comes from LDS.
 // ---------------------------------------------------------------------------
+constexpr int kTileMax = 64;                 // TX <= 64, TX * TY = kBlock
+
 template <typename T, bool RESID_ONLY>
-__global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb)
+__global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb, int TX, int CZ)
 {
+    const int TY = kBlock / TX;
+    const int PX = TX + 2, PY = TY + 2;           // x plane with halo
+    const int EX = TX + 1, EY = TY + 1;           // element tile
+    // largest plane over TX in {16, 32, 64}: 66 x 6; largest element tile 65 x 5
+    __shared__ double xp[3][396];
+    __shared__ double ck[2][325];
     const int bx = find_box(lb, blockIdx.x);
     const LevelArgs<T> &A = lb.a[bx];
-    const int lbk = blockIdx.x - A.blk0;
-    const int nblk = (A.n + kBlock - 1) / kBlock;
-    const int n = xcd_block(lbk, nblk) * kBlock + threadIdx.x;
-    if (n >= A.n) return;
-    const int i = n % A.nx, t = n / A.nx;
-    const int j = t % A.ny, kl = t / A.ny;
-    const int k = kl + A.k0;
-    double cK[8], cM[8];
+    const int ntx = (A.nx + TX - 1) / TX, nty = (A.ny + TY - 1) / TY, nch = (A.nz + CZ - 1) / CZ;
+    const int nt = ntx * nty * nch;
+    const int tile = xcd_block(blockIdx.x - A.blk0, nt);
+    const int tix = tile % ntx, tiy = (tile / ntx) % nty, tch = tile / (ntx * nty);
+    const int i0 = tix * TX, j0 = tiy * TY, k0l = tch * CZ;
+    const int k1l = k0l + CZ < A.nz ? k0l + CZ : A.nz;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < A.nx && j < A.ny;
+    const int planeN = A.nx * A.ny;
+
+    // x plane kl (box-local) into ring slot s, zero outside the box
+    auto load_plane = [&](int kl, int slot) {
+        for (int q = threadIdx.x; q < PX * PY; q += kBlock) {
+            const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
+            const bool ok = kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny;
+            xp[slot][q] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
+        }
+    };
+    // element layer between box-local node layers kl and kl+1
+    auto load_elems = [&](int kl, int slot) {
+        const int ek = kl + A.k0;   // global element layer
+        const bool lay = ek >= A.ek_lo && ek <= A.ek_hi;
+        for (int q = threadIdx.x; q < EX * EY; q += kBlock) {
+            const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
+            const bool ok = lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
+            ck[slot][q] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+        }
+    };
+    load_plane(k0l - 1, (k0l + 2) % 3);
+    load_plane(k0l, k0l % 3);
+    load_elems(k0l - 1, (k0l + 1) & 1);
+    for (int kl = k0l; kl < k1l; kl++) {
+        load_plane(kl + 1, (kl + 1) % 3);
+        load_elems(kl, kl & 1);
+        __syncthreads();
+        if (own) {
+            const int n = i + A.nx * j + planeN * kl;
+            double X[27];
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
-        const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
-        const bool ok = ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 && ek >= A.ek_lo &&
-                        ek <= A.ek_hi;
-        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
-        cK[e] = ok ? A.cK[id] : 0.0;
-        cM[e] = (ok && A.mass) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
-    }
-    double X[27];
+            for (int dz = -1; dz <= 1; dz++) {
+                const double *P = xp[(kl + dz + 3) % 3];
 #pragma unroll
-    for (int o = 0; o < 27; o++) {
-        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
-                        (kl + dz >= 0) && (kl + dz < A.nz);
-        X[o] = ok ? A.xin[n + dx + A.nx * (dy + A.ny * dz)] : 0.0;
+                for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; dx++)
+                        X[nb_index(dx, dy, dz)] = P[(tx + 1 + dx) + PX * (ty + 1 + dy)];
+            }
+            double cK[8], cM[8];
+            const int k = kl + A.k0;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                cK[e] = ck[(kl - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
+                const int ek = k - 1 + ez;
+                cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+            }
+            double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
+            if (A.mass) Sx += q1_mass(cM, X);
+            const double r = (double)A.b[n] - Sx;
+            if (RESID_ONLY) {
+                A.rout[n] = (T)r;
+            } else {
+                double d = A.c2 * (double)A.invd[n] * r;
+                if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
+                A.xout[n] = X[13] + d;
+                if (A.dout) A.dout[n] = (T)d;
+            }
+        }
+        __syncthreads();
     }
-    double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
-    if (A.mass) Sx += q1_mass(cM, X);
-    const double r = (double)A.b[n] - Sx;
-    if (RESID_ONLY) {
-        A.rout[n] = (T)r;
-        return;
-    }
-    double d = A.c2 * (double)A.invd[n] * r;
-    if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
-    A.xout[n] = X[13] + d;
-    if (A.dout) A.dout[n] = (T)d;
+}
+
+int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ)
+{
+    const int TY = kBlock / TX;
+    return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + CZ - 1) / CZ);
 }
 
 template <typename T>
-void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only,
-                    hipStream_t st)
+void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
+                    int CZ, hipStream_t st)
 {
     if (resid_only)
-        hipLaunchKernelGGL((k_smooth0<T, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb);
+        hipLaunchKernelGGL((k_smooth0<T, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
     else
-        hipLaunchKernelGGL((k_smooth0<T, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb);
+        hipLaunchKernelGGL((k_smooth0<T, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
 }
-template void launch_smooth0<double>(const Geom &, const LevelBatch<double> &, int, int, hipStream_t);
-template void launch_smooth0<float>(const Geom &, const LevelBatch<float> &, int, int, hipStream_t);
+template void launch_smooth0<double>(const Geom &, const LevelBatch<double> &, int, int, int, int,
+                                     hipStream_t);
+template void launch_smooth0<float>(const Geom &, const LevelBatch<float> &, int, int, int, int,
+                                    hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Levels >= 1: stored 27-point stencil

@@ -77,6 +77,7 @@ struct p4d_ctx {
     char *scratch = nullptr;       // Krylov basis region, also setup scratch
     size_t scratch_bytes = 0;
     double *hhost = nullptr;       // pinned host staging
+    int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     Prof prof;
 };
 
@@ -157,6 +158,13 @@ static void radial_table(const p4d_problem_desc &d, int el, RadialTab &T)
     }
     for (int i = 0; i < N; i++) T.ipiv[i] = 1.0 / T.piv[i];
     T.tau0 = 1.0 / T.piv[N - 1];   // (T0^-1)_{NN}
+    // T0^-1 e_N and T0^-T e_N: forward elimination of e_N leaves e_N, then
+    // back substitution with U (superdiagonal tsup) or U' (tsub shifted)
+    T.tN[N - 1] = T.tNT[N - 1] = T.ipiv[N - 1];
+    for (int i = N - 2; i >= 0; i--) {
+        T.tN[i] = -T.tsup[i] * T.tN[i + 1] * T.ipiv[i];
+        T.tNT[i] = -T.tsub[i + 1] * T.tNT[i + 1] * T.ipiv[i];
+    }
 }
 
 static void fill_geom(const p4d_problem_desc &d, Geom &g)
@@ -422,7 +430,8 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
         LevelArgs<T> &A = lb.a[q];
         A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
         A.blk0 = blk;
-        blk += (L.n + kBlock - 1) / kBlock;
+        blk += l == 0 ? smooth0_tiles(L.nx, L.ny, L.nz, c->tile_tx, c->tile_cz)
+                      : (L.n + kBlock - 1) / kBlock;
         A.k0 = B.k0; A.ek_lo = B.ek_lo; A.ek_hi = B.ek_hi; A.mass = B.mass;
         A.cK = B.cK;
         A.S = (const T *)L.S;
@@ -453,7 +462,7 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
             bytes += per * A.n;
         }
         ProfScope ps(c, P4D_K_SMOOTH0, bytes, st);
-        launch_smooth0<T>(c->g, lb, blk, 0, st);
+        launch_smooth0<T>(c->g, lb, blk, 0, c->tile_tx, c->tile_cz, st);
     } else {
         launch_smooth<T>(lb, blk, 0, st);
     }
@@ -473,7 +482,8 @@ static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, in
         LevelArgs<T> &A = lb.a[q];
         A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
         A.blk0 = blk;
-        blk += (L.n + kBlock - 1) / kBlock;
+        blk += l == 0 ? smooth0_tiles(L.nx, L.ny, L.nz, c->tile_tx, c->tile_cz)
+                      : (L.n + kBlock - 1) / kBlock;
         A.k0 = B.k0; A.ek_lo = B.ek_lo; A.ek_hi = B.ek_hi; A.mass = B.mass;
         A.cK = B.cK;
         A.S = (const T *)L.S;
@@ -483,7 +493,7 @@ static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, in
         A.xin = lvx(L, vs.xcur[b][l]);
         A.rout = (T *)L.r;
     }
-    if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, st);
+    if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, c->tile_tx, c->tile_cz, st);
     else launch_smooth<T>(lb, blk, 1, st);
 }
 
@@ -587,8 +597,8 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
     {
         ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + sizeof(T) * g.Nm +
                                           sizeof(TZ) * g.N + 32.0 * g.ne, st);
-        launch_rad_back<T, TZ>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, r, rscale, x0, z, transpose,
-                               schur, st);
+        launch_rad_back<T, TZ>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, c->omega, r, rscale, x0, z,
+                               transpose, schur, st);
     }
 }
 
@@ -895,6 +905,8 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
         delete c;
         return P4D_ERR_HIP;
     }
+    c->tile_tx = d->nx >= 48 ? 64 : (d->nx >= 24 ? 32 : 16);
+    c->tile_cz = 8;
     c->prof.ev.resize(2 * 512);
     c->prof.bytes.resize(512);
     c->prof.cls.resize(512);
@@ -990,6 +1002,23 @@ p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, cons
     // the host copy of the radial tables must outlive the async copy
     HIPCHK(c, hipStreamSynchronize(st));
     c->uploaded = 1;
+    c->pc_ready = 0;
+    return P4D_OK;
+}
+
+p4d_status p4d_set_diffusivity(p4d_ctx *c, const double Ds[2], void *stream)
+{
+    if (!c || !Ds || !(Ds[0] > 0.0) || !(Ds[1] > 0.0)) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    hipStream_t st = (hipStream_t)stream;
+    // the previous copy of the tables may still be in flight
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->desc.Ds[0] = Ds[0];
+    c->desc.Ds[1] = Ds[1];
+    radial_table(c->desc, 0, c->tabs_h[0]);
+    radial_table(c->desc, 1, c->tabs_h[1]);
+    HIPCHK(c, hipMemcpyAsync(c->tabs, c->tabs_h, sizeof(c->tabs_h), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
     c->pc_ready = 0;
     return P4D_OK;
 }

@@ -38,6 +38,7 @@ struct RadialTab {
     double tsub[kMaxNr], tdia[kMaxNr], tsup[kMaxNr];   // rows of T0
     double l[kMaxNr], ipiv[kMaxNr], piv[kMaxNr];       // T0 = L U, unit L multipliers
     double lT[kMaxNr];                                 // T0^T = L' U' (same pivots)
+    double tN[kMaxNr], tNT[kMaxNr];                    // T0^-1 e_N and T0^-T e_N
     double hsub[kMaxNr], hdia[kMaxNr], hsup[kMaxNr];   // dL_h/dDs
 };
 
@@ -125,13 +126,17 @@ void launch_rad_fwd(const Geom &g, const RadialTab *tabs, const double *gg, cons
                     int schur, hipStream_t st);
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
-                     const double *ee, const double *mm, const double *r, double rscale,
+                     const double *ee, const double *mm, const double *omega, const double *r,
+                     double rscale,
                      const double *x0, TZ *z, int transpose, int schur, hipStream_t st);
 
 // mg.hip
+// level-0 smoother, 2.5D tiles of TX x (256/TX) nodes and CZ layers;
+// TX in {16, 32, 64}
 template <typename T>
-void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only,
-                    hipStream_t st);
+void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
+                    int CZ, hipStream_t st);
+int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ);
 template <typename T>
 void launch_smooth(const LevelBatch<T> &lb, int nblk, int resid_only, hipStream_t st);
 template <typename T>

@@ -101,11 +101,16 @@ template void launch_rad_fwd<float>(const Geom &, const RadialTab *, const doubl
                                     const double *, double, float *, double *, const float *,
                                     const double *, int, int, hipStream_t);
 
+// z_s,j = A_ss,j^-1 r_s,j - delta_j A_ss,j^-1 e_N, and by Sherman-Morrison
+// A_ss,j^-1 e_N = omega_j T0^-1 e_N: the elimination in precision T only
+// sees r_s, while delta_j, which carries the large near-null part of z_y, is
+// applied in FP64 with the precomputed T0^-1 e_N.
 template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
 __global__ __launch_bounds__(kBlock) void k_rad_back(
     Geom g, const RadialTab *__restrict__ tabs, const double *__restrict__ gg,
     const double *__restrict__ ss, const double *__restrict__ ee, const double *__restrict__ mm,
-    const double *__restrict__ r, double rscale, const double *__restrict__ x0, TZ *__restrict__ z)
+    const double *__restrict__ om, const double *__restrict__ r, double rscale,
+    const double *__restrict__ x0, TZ *__restrict__ z)
 {
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
@@ -128,13 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_rad_back(
     const double *rs = r + g.off_cs[el] + (je - base);
     TZ *zs = z + g.off_cs[el] + (je - base);
     const double sj = ss[je];
-    double delta = 0.0;
+    double dw = 0.0;   // delta_j * omega_j
     if (SCHUR) {
         const double m = mm[je];
+        double delta;
         if (!TRANS)
             delta = Tb.Gamma * ((dir ? 0.0 : gg[je]) * zps - gg[je] * zpe + ee[je] * zce);
         else
             delta = sj * ((dir ? 0.0 : m) * zps - m * zpe - g.tc * m * zce);
+        dw = delta * om[je];
     }
     // forward elimination; the register array is only indexed by unrolled
     // constants, the last entry is carried separately
@@ -149,30 +156,29 @@ __global__ __launch_bounds__(kBlock) void k_rad_back(
             ylast = y[q];
         }
     }
-    // last entry: subtract delta (exactly what the forward elimination does
-    // to an e_N right-hand side), divide by the node's last pivot
-    T zn = (T)(((double)ylast - delta) / (Tb.piv[N - 1] + Tb.Gamma * sj));
-    zs[(long long)(N - 1) * nn] = (TZ)zn;
+    T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+    zs[(long long)(N - 1) * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]));
 #pragma unroll
     for (int q = NRMAX - 2; q >= 0; q--) {
         if (q < N - 1) {
             const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
             zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
-            zs[(long long)q * nn] = (TZ)zn;
+            zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
         }
     }
 }
 
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
-                     const double *ee, const double *mm, const double *r, double rscale,
-                     const double *x0, TZ *z, int transpose, int schur, hipStream_t st)
+                     const double *ee, const double *mm, const double *om, const double *r,
+                     double rscale, const double *x0, TZ *z, int transpose, int schur,
+                     hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
     const int nrm = g.nr[0] > g.nr[1] ? g.nr[0] : g.nr[1];
 #define P4D_RB(NR, TR, SC)                                                                      \
     hipLaunchKernelGGL((k_rad_back<T, TZ, NR, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, tabs, \
-                       gg, ss, ee, mm, r, rscale, x0, z)
+                       gg, ss, ee, mm, om, r, rscale, x0, z)
 #define P4D_RB2(NR)                                          \
     do {                                                     \
         if (schur) {                                         \
@@ -191,19 +197,19 @@ void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, con
 #undef P4D_RB
 }
 template void launch_rad_back<double, double>(const Geom &, const RadialTab *, const double *,
-                                              const double *, const double *, const double *,
+                                              const double *, const double *, const double *, const double *,
                                               const double *, double, const double *, double *,
                                               int, int, hipStream_t);
 template void launch_rad_back<float, double>(const Geom &, const RadialTab *, const double *,
-                                             const double *, const double *, const double *,
+                                             const double *, const double *, const double *, const double *,
                                              const double *, double, const double *, double *,
                                              int, int, hipStream_t);
 template void launch_rad_back<float, float>(const Geom &, const RadialTab *, const double *,
-                                            const double *, const double *, const double *,
+                                            const double *, const double *, const double *, const double *,
                                             const double *, double, const double *, float *, int,
                                             int, hipStream_t);
 template void launch_rad_back<double, float>(const Geom &, const RadialTab *, const double *,
-                                             const double *, const double *, const double *,
+                                             const double *, const double *, const double *, const double *,
                                              const double *, double, const double *, float *,
                                              int, int, hipStream_t);
 

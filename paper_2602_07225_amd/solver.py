@@ -38,6 +38,14 @@ class P4DSolver:
         assert arrs[0].numel() == self.n_elem and arrs[1].numel() == self.n_elem
         assert all(a.numel() == self.n_e for a in arrs[2:])
         L.p4d_upload(self.ctx, *arrs)
+        # kept for re-uploads with a new sigma (differentiable solves)
+        self._kappa, self._g, self._s, self._e = arrs[1:]
+        self.opts = None
+
+    def set_diffusivity(self, Ds):
+        """Particle diffusivities (nondimensional, anode/cathode)."""
+        L.p4d_set_diffusivity(self.ctx, Ds)
+        self.desc.Ds[0], self.desc.Ds[1] = float(Ds[0]), float(Ds[1])
         self.opts = None
 
     def setup(self, **kw):
