@@ -9,146 +9,24 @@
 // Smoother: Chebyshev on D^-1 S over [lmax/4, lmax] (lmax: Gershgorin bound),
 // one fused kernel per step.  Coarsening per direction keeps the even indices
 // plus the last one; P is tensor-product linear interpolation.
-#include "p4d_device.hpp"
+#include "p4d_kernels.hpp"
 
 namespace p4d {
 
 // ---------------------------------------------------------------------------
-// 1D transfer helpers for 'even indices plus the last' coarsening of n points
+// Single-cell kernels: all four boxes of one V-cycle stage per launch
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int coarse_n(int n) { return n <= 2 ? n : n / 2 + 1; }
-
-// coarse points (and weights) that fine point i interpolates from
-__device__ inline int coarse_of(int n, int i, int I[2], double w[2])
-{
-    if (n <= 2) { I[0] = i; w[0] = 1.0; return 1; }
-    if (!(i & 1)) { I[0] = i >> 1; w[0] = 1.0; return 1; }
-    if (i == n - 1) { I[0] = n / 2; w[0] = 1.0; return 1; }
-    I[0] = (i - 1) >> 1; w[0] = 0.5;
-    I[1] = (i + 1) >> 1; w[1] = 0.5;
-    return 2;
-}
-// fine points (and weights) that interpolate from coarse point I
-__device__ inline int fine_of(int n, int I, int f[3], double w[3])
-{
-    if (n <= 2) { f[0] = I; w[0] = 1.0; return 1; }
-    const int nc = n / 2 + 1;
-    const int c = (I == nc - 1) ? n - 1 : 2 * I;
-    int cnt = 0;
-    f[cnt] = c; w[cnt] = 1.0; cnt++;
-    if (c - 1 >= 0 && ((c - 1) & 1) && c - 1 != n - 1) { f[cnt] = c - 1; w[cnt] = 0.5; cnt++; }
-    if (c + 1 <= n - 1 && ((c + 1) & 1) && c + 1 != n - 1) { f[cnt] = c + 1; w[cnt] = 0.5; cnt++; }
-    return cnt;
-}
-
-template <typename T>
-__device__ inline int find_box(const LevelBatch<T> &lb, int b)
-{
-    int q = 0;
-#pragma unroll
-    for (int t = 1; t < 4; t++)
-        if (t < lb.nbox && b >= lb.a[t].blk0) q = t;
-    return q;
-}
-
-// ---------------------------------------------------------------------------
-// Level 0: matrix-free operator from element coefficients, 2.5D tiled.
-// A workgroup owns a TX x TY tile of an x-y plane and marches through a chunk
-// of CZ node layers; three planes of x (with a one-node halo) and two layers
-// of element coefficients sit in LDS rings, so every value is read from
-// memory once per tile and the 27-point neighbourhood comes from LDS.
-// ---------------------------------------------------------------------------
-constexpr int kTileMax = 64;                 // TX <= 64, TX * TY = kBlock
-
 template <typename T, bool RESID_ONLY>
 __global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb, int TX, int CZ)
 {
-    const int TY = kBlock / TX;
-    const int PX = TX + 2, PY = TY + 2;           // x plane with halo
-    const int EX = TX + 1, EY = TY + 1;           // element tile
-    // largest plane over TX in {16, 32, 64}: 66 x 6; largest element tile 65 x 5
-    __shared__ double xp[3][396];
-    __shared__ double ck[2][325];
+    __shared__ Smooth0Lds L;
     const int bx = find_box(lb, blockIdx.x);
     const LevelArgs<T> &A = lb.a[bx];
-    const int ntx = (A.nx + TX - 1) / TX, nty = (A.ny + TY - 1) / TY, nch = (A.nz + CZ - 1) / CZ;
-    const int nt = ntx * nty * nch;
-    const int tile = xcd_block(blockIdx.x - A.blk0, nt);
-    const int tix = tile % ntx, tiy = (tile / ntx) % nty, tch = tile / (ntx * nty);
-    const int i0 = tix * TX, j0 = tiy * TY, k0l = tch * CZ;
-    const int k1l = k0l + CZ < A.nz ? k0l + CZ : A.nz;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int i = i0 + tx, j = j0 + ty;
-    const bool own = i < A.nx && j < A.ny;
-    const int planeN = A.nx * A.ny;
-
-    // x plane kl (box-local) into ring slot s, zero outside the box
-    auto load_plane = [&](int kl, int slot) {
-        for (int q = threadIdx.x; q < PX * PY; q += kBlock) {
-            const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
-            const bool ok = kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny;
-            xp[slot][q] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
-        }
-    };
-    // element layer between box-local node layers kl and kl+1
-    auto load_elems = [&](int kl, int slot) {
-        const int ek = kl + A.k0;   // global element layer
-        const bool lay = ek >= A.ek_lo && ek <= A.ek_hi;
-        for (int q = threadIdx.x; q < EX * EY; q += kBlock) {
-            const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
-            const bool ok = lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
-            ck[slot][q] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
-        }
-    };
-    load_plane(k0l - 1, (k0l + 2) % 3);
-    load_plane(k0l, k0l % 3);
-    load_elems(k0l - 1, (k0l + 1) & 1);
-    for (int kl = k0l; kl < k1l; kl++) {
-        load_plane(kl + 1, (kl + 1) % 3);
-        load_elems(kl, kl & 1);
-        __syncthreads();
-        if (own) {
-            const int n = i + A.nx * j + planeN * kl;
-            double X[27];
-#pragma unroll
-            for (int dz = -1; dz <= 1; dz++) {
-                const double *P = xp[(kl + dz + 3) % 3];
-#pragma unroll
-                for (int dy = -1; dy <= 1; dy++)
-#pragma unroll
-                    for (int dx = -1; dx <= 1; dx++)
-                        X[nb_index(dx, dy, dz)] = P[(tx + 1 + dx) + PX * (ty + 1 + dy)];
-            }
-            double cK[8], cM[8];
-            const int k = kl + A.k0;
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-                cK[e] = ck[(kl - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
-                const int ek = k - 1 + ez;
-                cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
-            }
-            double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
-            if (A.mass) Sx += q1_mass(cM, X);
-            const double r = (double)A.b[n] - Sx;
-            if (RESID_ONLY) {
-                A.rout[n] = (T)r;
-            } else {
-                double d = A.c2 * (double)A.invd[n] * r;
-                if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
-                A.xout[n] = X[13] + d;
-                if (A.dout) A.dout[n] = (T)d;
-            }
-        }
-        __syncthreads();
-    }
+    const int nt = smooth0_box_tiles(A.nx, A.ny, A.nz, TX, CZ);
+    smooth0_tile<T, RESID_ONLY>(g, A, xcd_block(blockIdx.x - A.blk0, nt), TX, CZ, L);
 }
 
-int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ)
-{
-    const int TY = kBlock / TX;
-    return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + CZ - 1) / CZ);
-}
+int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ) { return smooth0_box_tiles(nx, ny, nz, TX, CZ); }
 
 template <typename T>
 void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
@@ -164,42 +42,13 @@ template void launch_smooth0<double>(const Geom &, const LevelBatch<double> &, i
 template void launch_smooth0<float>(const Geom &, const LevelBatch<float> &, int, int, int, int,
                                     hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Levels >= 1: stored 27-point stencil
-// ---------------------------------------------------------------------------
 template <typename T, bool RESID_ONLY>
 __global__ __launch_bounds__(kBlock) void k_smooth(LevelBatch<T> lb)
 {
     const int bx = find_box(lb, blockIdx.x);
     const LevelArgs<T> &A = lb.a[bx];
-    const int lbk = blockIdx.x - A.blk0;
     const int nblk = (A.n + kBlock - 1) / kBlock;
-    const int n = xcd_block(lbk, nblk) * kBlock + threadIdx.x;
-    if (n >= A.n) return;
-    const int i = n % A.nx, t = n / A.nx;
-    const int j = t % A.ny, kl = t / A.ny;
-    // difference form: slot 13 of the stored stencil holds the row sum, so
-    // S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
-    const double xc = A.xin[n];
-    double Sx = (double)A.S[13LL * A.n + n] * xc;
-#pragma unroll
-    for (int o = 0; o < 27; o++) {
-        if (o == 13) continue;
-        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
-                        (kl + dz >= 0) && (kl + dz < A.nz);
-        if (ok)
-            Sx += (double)A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
-    }
-    const double r = (double)A.b[n] - Sx;
-    if (RESID_ONLY) {
-        A.rout[n] = (T)r;
-        return;
-    }
-    double d = A.c2 * (double)A.invd[n] * r;
-    if (A.c1 != 0.0) d += A.c1 * (A.din_x ? xc : (double)A.din[n]);
-    A.xout[n] = xc + d;
-    if (A.dout) A.dout[n] = (T)d;
+    smooth_block<T, RESID_ONLY>(A, xcd_block(blockIdx.x - A.blk0, nblk));
 }
 
 template <typename T>
@@ -213,75 +62,18 @@ void launch_smooth(const LevelBatch<T> &lb, int nblk, int resid_only, hipStream_
 template void launch_smooth<double>(const LevelBatch<double> &, int, int, hipStream_t);
 template void launch_smooth<float>(const LevelBatch<float> &, int, int, hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Transfers
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ inline int find_tbox(const TransferBatch<T> &tb, int b)
-{
-    int q = 0;
-#pragma unroll
-    for (int t = 1; t < 4; t++)
-        if (t < tb.nbox && b >= tb.a[t].blk0) q = t;
-    return q;
-}
-
-// b_c = P^T r_f; also the first Chebyshev iterate x_c1 = c2 D_c^-1 b_c
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(TransferBatch<T> tb)
 {
-    const int bx = find_tbox(tb, blockIdx.x);
-    const TransferArgs<T> &A = tb.a[bx];
-    const int nc = A.cx * A.cy * A.cz;
-    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
-    if (n >= nc) return;
-    const int I = n % A.cx, t = n / A.cx;
-    const int J = t % A.cy, K = t / A.cy;
-    int fi[3], fj[3], fk[3];
-    double wi[3], wj[3], wk[3];
-    const int ni = fine_of(A.fx, I, fi, wi);
-    const int nj = fine_of(A.fy, J, fj, wj);
-    const int nk = fine_of(A.fz, K, fk, wk);
-    double acc = 0.0;
-    for (int c = 0; c < nk; c++)
-        for (int bq = 0; bq < nj; bq++) {
-            const long long row = (long long)A.fx * (fj[bq] + (long long)A.fy * fk[c]);
-            double part = 0.0;
-            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.rf[row + fi[a]];
-            acc += wj[bq] * wk[c] * part;
-        }
-    const T bc = (T)acc;
-    A.bc[n] = bc;
-    if (A.xc1) A.xc1[n] = A.c2c * (double)A.invdc[n] * (double)bc;
+    const int bx = find_box(tb, blockIdx.x);
+    restrict_block<T>(tb.a[bx], blockIdx.x - tb.a[bx].blk0);
 }
-
-// x_f += P x_c
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(TransferBatch<T> tb)
 {
-    const int bx = find_tbox(tb, blockIdx.x);
-    const TransferArgs<T> &A = tb.a[bx];
-    const int nf = A.fx * A.fy * A.fz;
-    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
-    if (n >= nf) return;
-    const int i = n % A.fx, t = n / A.fx;
-    const int j = t % A.fy, k = t / A.fy;
-    int Ci[2], Cj[2], Ck[2];
-    double wi[2], wj[2], wk[2];
-    const int ni = coarse_of(A.fx, i, Ci, wi);
-    const int nj = coarse_of(A.fy, j, Cj, wj);
-    const int nk = coarse_of(A.fz, k, Ck, wk);
-    double acc = 0.0;
-    for (int c = 0; c < nk; c++)
-        for (int bq = 0; bq < nj; bq++) {
-            const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
-            double part = 0.0;
-            for (int a = 0; a < ni; a++) part += wi[a] * A.xc[row + Ci[a]];
-            acc += wj[bq] * wk[c] * part;
-        }
-    A.xf[n] += acc;
+    const int bx = find_box(tb, blockIdx.x);
+    prolong_block<T>(tb.a[bx], blockIdx.x - tb.a[bx].blk0);
 }
-
 template <typename T>
 void launch_restrict(const TransferBatch<T> &tb, int nblk, hipStream_t st)
 {
@@ -297,32 +89,14 @@ template void launch_restrict<float>(const TransferBatch<float> &, int, hipStrea
 template void launch_prolong<double>(const TransferBatch<double> &, int, hipStream_t);
 template void launch_prolong<float>(const TransferBatch<float> &, int, hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Coarsest level: x = A^-1 b with the dense inverse, always in FP64
-// ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse(CoarseBatch<T> cb)
 {
-    // 64 rows per workgroup; the 4 waves split the columns, then add up
-    __shared__ double bl[1024];
-    __shared__ double part[4][64];
+    __shared__ CoarseLds L;
     const int box = blockIdx.y;
     if (box >= cb.nbox) return;
-    const CoarseArgs<T> &A = cb.a[box];
-    const int n = A.n;
-    if (blockIdx.x * 64 >= n) return;
-    for (int q = threadIdx.x; q < n; q += kBlock) bl[q] = (double)A.b[q];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int row = blockIdx.x * 64 + lane;
-    double acc = 0.0;
-    if (row < n) {
-#pragma unroll 4
-        for (int c = w; c < n; c += 4) acc += A.Ainv[(long long)c * n + row] * bl[c];
-    }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0 && row < n) A.x[row] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (blockIdx.x * 64 >= cb.a[box].n) return;
+    coarse_block<T>(cb.a[box], blockIdx.x, L);
 }
 
 template <typename T>

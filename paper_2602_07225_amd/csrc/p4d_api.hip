@@ -13,6 +13,7 @@
 
 #include "../../include/p4d.h"
 #include "p4d_internal.hpp"
+#include "p4d_kernels.hpp"
 
 using namespace p4d;
 
@@ -572,33 +573,30 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
 {
     const Geom &g = c->g;
     const int schur = c->pc.pc == P4D_PC_SCHUR;
-    double c2box[4];
-    for (int b = 0; b < 4; b++) c2box[b] = cheb_coef(c->box[b].lev[0].lmax, c->pc.cheb_degree).c2[1];
-    const double rbytes = 8.0 * g.N + 32.0 * g.ne + 3.0 * sizeof(T) * g.Nm;
+    RadArgs R{};
+    R.tabs = c->tabs;
+    R.gg = c->gg; R.ss = c->ss; R.ee = c->ee; R.mm = c->mm; R.om = c->omega;
+    R.r = r;
+    R.rscale = rscale;
+    R.b0 = c->b0;
+    R.x1 = (double *)c->x0a;
+    R.invd0 = c->invd0;
+    for (int b = 0; b < 4; b++) R.c2box[b] = cheb_coef(c->box[b].lev[0].lmax, c->pc.cheb_degree).c2[1];
+    const double rbytes = 8.0 * g.N + 32.0 * g.ne + (sizeof(T) * 2 + 8.0) * g.Nm;
     {
         ProfScope ps(c, P4D_K_RADIAL, rbytes, st);
-        launch_rad_fwd<T>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, r, rscale, (T *)c->b0,
-                          (double *)c->x0a, (const T *)c->invd0, c2box, transpose, schur, st);
+        launch_rad_fwd<T>(g, R, transpose, schur, st);
     }
     VState<T> vs{};
     for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
     vcycle_level<T>(c, vs, 0, st);
-    // all boxes' final level-0 iterates must sit in one array for rad_back:
-    // copy the boxes that ended in the other buffer
-    const int ref = vs.xcur[2][0];
-    for (int b = 0; b < 4; b++) {
-        if (vs.xcur[b][0] != ref) {
-            Level &L = c->box[b].lev[0];
-            hipMemcpyAsync(lvx(L, ref), lvx(L, 1 - ref), sizeof(double) * L.n,
-                           hipMemcpyDeviceToDevice, st);
-        }
-    }
-    const double *x0 = (const double *)(ref ? c->x0b : c->x0a);
+    // each box's final level-0 iterate (the two buffers alternate)
+    for (int b = 0; b < 4; b++) R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
+    R.z = z;
     {
-        ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + sizeof(T) * g.Nm +
-                                          sizeof(TZ) * g.N + 32.0 * g.ne, st);
-        launch_rad_back<T, TZ>(g, c->tabs, c->gg, c->ss, c->ee, c->mm, c->omega, r, rscale, x0, z,
-                               transpose, schur, st);
+        ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + 8.0 * g.Nm +
+                                          sizeof(TZ) * g.N + 40.0 * g.ne, st);
+        launch_rad_back<T, TZ>(g, R, transpose, schur, st);
     }
 }
 

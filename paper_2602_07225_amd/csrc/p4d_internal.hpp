@@ -118,17 +118,13 @@ void launch_grad(const Geom &g, const RadialTab *tabs, const double *x, const do
                  double *dsigma, double *partial, hipStream_t st);
 void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t st);
 
-// radial.hip
+// radial.hip (RadArgs in p4d_kernels.hpp)
+struct RadArgs;
 template <typename T>
-void launch_rad_fwd(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
-                    const double *ee, const double *mm, const double *r, double rscale,
-                    T *b0, double *x1, const T *invd0, const double c2box[4], int transpose,
-                    int schur, hipStream_t st);
+void launch_rad_fwd(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st);
 template <typename T, typename TZ>
-void launch_rad_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
-                     const double *ee, const double *mm, const double *omega, const double *r,
-                     double rscale,
-                     const double *x0, TZ *z, int transpose, int schur, hipStream_t st);
+void launch_rad_back(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st);
+int rad_nrmax(const Geom &g);
 
 // mg.hip
 // level-0 smoother, 2.5D tiles of TX x (256/TX) nodes and CZ layers;

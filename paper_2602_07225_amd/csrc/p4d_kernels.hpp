@@ -1,0 +1,532 @@
+// Block-level device functions of the operator and the preconditioner.  The
+// single-cell kernels (operator.hip, radial.hip, mg.hip) and the persistent
+// batched preconditioner (batch.hip) call the same functions, each for one
+// workgroup-sized unit of work given by an explicit block or tile index.
+#pragma once
+#include "p4d_device.hpp"
+
+namespace p4d {
+
+// ---------------------------------------------------------------------------
+// 1D transfer helpers for 'even indices plus the last' coarsening of n points
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int coarse_n(int n) { return n <= 2 ? n : n / 2 + 1; }
+
+// coarse points (and weights) that fine point i interpolates from
+__device__ inline int coarse_of(int n, int i, int I[2], double w[2])
+{
+    if (n <= 2) { I[0] = i; w[0] = 1.0; return 1; }
+    if (!(i & 1)) { I[0] = i >> 1; w[0] = 1.0; return 1; }
+    if (i == n - 1) { I[0] = n / 2; w[0] = 1.0; return 1; }
+    I[0] = (i - 1) >> 1; w[0] = 0.5;
+    I[1] = (i + 1) >> 1; w[1] = 0.5;
+    return 2;
+}
+// fine points (and weights) that interpolate from coarse point I
+__device__ inline int fine_of(int n, int I, int f[3], double w[3])
+{
+    if (n <= 2) { f[0] = I; w[0] = 1.0; return 1; }
+    const int nc = n / 2 + 1;
+    const int c = (I == nc - 1) ? n - 1 : 2 * I;
+    int cnt = 0;
+    f[cnt] = c; w[cnt] = 1.0; cnt++;
+    if (c - 1 >= 0 && ((c - 1) & 1) && c - 1 != n - 1) { f[cnt] = c - 1; w[cnt] = 0.5; cnt++; }
+    if (c + 1 <= n - 1 && ((c + 1) & 1) && c + 1 != n - 1) { f[cnt] = c + 1; w[cnt] = 0.5; cnt++; }
+    return cnt;
+}
+
+template <typename B>
+__device__ inline int find_box(const B &bt, int b)
+{
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < 4; t++)
+        if (t < bt.nbox && b >= bt.a[t].blk0) q = t;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 smoother, 2.5D tiled.  A workgroup owns a TX x TY tile of an x-y
+// plane and marches through a chunk of CZ node layers; three planes of x
+// (with a one-node halo) and two layers of element coefficients sit in LDS
+// rings, so every value is read from memory once per tile and the 27-point
+// neighbourhood comes from LDS.  TX in {16, 32, 64}, TY = 256 / TX.
+// ---------------------------------------------------------------------------
+constexpr int kXpLds = 396;   // largest plane with halo: 66 x 6
+constexpr int kCkLds = 325;   // largest element tile: 65 x 5
+struct Smooth0Lds {
+    double xp[3][kXpLds];
+    double ck[2][kCkLds];
+};
+
+__host__ __device__ inline int smooth0_box_tiles(int nx, int ny, int nz, int TX, int CZ)
+{
+    const int TY = kBlock / TX;
+    return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + CZ - 1) / CZ);
+}
+
+template <typename T, bool RESID_ONLY>
+__device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int tile, int TX, int CZ,
+                                    Smooth0Lds &L)
+{
+    const int TY = kBlock / TX;
+    const int PX = TX + 2, PY = TY + 2;
+    const int EX = TX + 1, EY = TY + 1;
+    const int ntx = (A.nx + TX - 1) / TX, nty = (A.ny + TY - 1) / TY;
+    const int tix = tile % ntx, tiy = (tile / ntx) % nty, tch = tile / (ntx * nty);
+    const int i0 = tix * TX, j0 = tiy * TY, k0l = tch * CZ;
+    const int k1l = k0l + CZ < A.nz ? k0l + CZ : A.nz;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < A.nx && j < A.ny;
+    const int planeN = A.nx * A.ny;
+
+    auto load_plane = [&](int kl, int slot) {
+        for (int q = threadIdx.x; q < PX * PY; q += kBlock) {
+            const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
+            const bool ok = kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny;
+            L.xp[slot][q] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
+        }
+    };
+    auto load_elems = [&](int kl, int slot) {
+        const int ek = kl + A.k0;
+        const bool lay = ek >= A.ek_lo && ek <= A.ek_hi;
+        for (int q = threadIdx.x; q < EX * EY; q += kBlock) {
+            const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
+            const bool ok = lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
+            L.ck[slot][q] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+        }
+    };
+    load_plane(k0l - 1, (k0l + 2) % 3);
+    load_plane(k0l, k0l % 3);
+    load_elems(k0l - 1, (k0l + 1) & 1);
+    for (int kl = k0l; kl < k1l; kl++) {
+        load_plane(kl + 1, (kl + 1) % 3);
+        load_elems(kl, kl & 1);
+        __syncthreads();
+        if (own) {
+            const int n = i + A.nx * j + planeN * kl;
+            double X[27];
+#pragma unroll
+            for (int dz = -1; dz <= 1; dz++) {
+                const double *P = L.xp[(kl + dz + 3) % 3];
+#pragma unroll
+                for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; dx++)
+                        X[nb_index(dx, dy, dz)] = P[(tx + 1 + dx) + PX * (ty + 1 + dy)];
+            }
+            double cK[8], cM[8];
+            const int k = kl + A.k0;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                cK[e] = L.ck[(kl - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
+                const int ek = k - 1 + ez;
+                cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+            }
+            double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
+            if (A.mass) Sx += q1_mass(cM, X);
+            const double r = (double)A.b[n] - Sx;
+            if (RESID_ONLY) {
+                A.rout[n] = (T)r;
+            } else {
+                double d = A.c2 * (double)A.invd[n] * r;
+                if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
+                A.xout[n] = X[13] + d;
+                if (A.dout) A.dout[n] = (T)d;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Levels >= 1: stored 27-point stencil, difference form (slot 13 holds the
+// row sum): S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
+// ---------------------------------------------------------------------------
+template <typename T, bool RESID_ONLY>
+__device__ inline void smooth_block(const LevelArgs<T> &A, int blk)
+{
+    const int n = blk * kBlock + threadIdx.x;
+    if (n >= A.n) return;
+    const int i = n % A.nx, t = n / A.nx;
+    const int j = t % A.ny, kl = t / A.ny;
+    const double xc = A.xin[n];
+    double Sx = (double)A.S[13LL * A.n + n] * xc;
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        if (o == 13) continue;
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
+                        (kl + dz >= 0) && (kl + dz < A.nz);
+        if (ok)
+            Sx += (double)A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
+    }
+    const double r = (double)A.b[n] - Sx;
+    if (RESID_ONLY) {
+        A.rout[n] = (T)r;
+        return;
+    }
+    double d = A.c2 * (double)A.invd[n] * r;
+    if (A.c1 != 0.0) d += A.c1 * (A.din_x ? xc : (double)A.din[n]);
+    A.xout[n] = xc + d;
+    if (A.dout) A.dout[n] = (T)d;
+}
+
+// b_c = P^T r_f; also the first Chebyshev iterate x_c1 = c2 D_c^-1 b_c
+template <typename T>
+__device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
+{
+    const int nc = A.cx * A.cy * A.cz;
+    const int n = blk * kBlock + threadIdx.x;
+    if (n >= nc) return;
+    const int I = n % A.cx, t = n / A.cx;
+    const int J = t % A.cy, K = t / A.cy;
+    int fi[3], fj[3], fk[3];
+    double wi[3], wj[3], wk[3];
+    const int ni = fine_of(A.fx, I, fi, wi);
+    const int nj = fine_of(A.fy, J, fj, wj);
+    const int nk = fine_of(A.fz, K, fk, wk);
+    double acc = 0.0;
+    for (int c = 0; c < nk; c++)
+        for (int bq = 0; bq < nj; bq++) {
+            const long long row = (long long)A.fx * (fj[bq] + (long long)A.fy * fk[c]);
+            double part = 0.0;
+            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.rf[row + fi[a]];
+            acc += wj[bq] * wk[c] * part;
+        }
+    const T bc = (T)acc;
+    A.bc[n] = bc;
+    if (A.xc1) A.xc1[n] = A.c2c * (double)A.invdc[n] * (double)bc;
+}
+
+// x_f += P x_c
+template <typename T>
+__device__ inline void prolong_block(const TransferArgs<T> &A, int blk)
+{
+    const int nf = A.fx * A.fy * A.fz;
+    const int n = blk * kBlock + threadIdx.x;
+    if (n >= nf) return;
+    const int i = n % A.fx, t = n / A.fx;
+    const int j = t % A.fy, k = t / A.fy;
+    int Ci[2], Cj[2], Ck[2];
+    double wi[2], wj[2], wk[2];
+    const int ni = coarse_of(A.fx, i, Ci, wi);
+    const int nj = coarse_of(A.fy, j, Cj, wj);
+    const int nk = coarse_of(A.fz, k, Ck, wk);
+    double acc = 0.0;
+    for (int c = 0; c < nk; c++)
+        for (int bq = 0; bq < nj; bq++) {
+            const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
+            double part = 0.0;
+            for (int a = 0; a < ni; a++) part += wi[a] * A.xc[row + Ci[a]];
+            acc += wj[bq] * wk[c] * part;
+        }
+    A.xf[n] += acc;
+}
+
+// Coarsest level, 64 rows of x = A^-1 b per workgroup (FP64); the 4 waves
+// split the columns, then add up.
+struct CoarseLds {
+    double bl[1024];
+    double part[4][64];
+};
+template <typename T>
+__device__ inline void coarse_block(const CoarseArgs<T> &A, int rowblk, CoarseLds &L)
+{
+    const int n = A.n;
+    for (int q = threadIdx.x; q < n; q += kBlock) L.bl[q] = (double)A.b[q];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = rowblk * 64 + lane;
+    double acc = 0.0;
+    if (row < n) {
+#pragma unroll 4
+        for (int c = w; c < n; c += 4) acc += A.Ainv[(long long)c * n + row] * L.bl[c];
+    }
+    L.part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < n)
+        A.x[row] = (L.part[0][lane] + L.part[1][lane]) + (L.part[2][lane] + L.part[3][lane]);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Particle blocks (Sec. 4.2: one tridiagonal system per point, inverted
+// exactly).  A_ss,j = T0 + Gamma s_j e_N e_N^T shares the LU of T0; only the
+// last pivot depends on the node.
+// ---------------------------------------------------------------------------
+struct RadArgs {
+    const RadialTab *tabs;
+    const double *gg, *ss, *ee, *mm, *om;
+    const double *r;
+    double rscale;
+    void *b0;            // T, macro layout
+    double *x1;          // first Chebyshev iterate of each box
+    const void *invd0;   // T
+    double c2box[4];
+    const double *x0[4]; // final level-0 iterates per box (rad_back)
+    void *z;             // TZ, output
+};
+
+// zeta_j = (A_ss,j^-1 r_s,j)_N; r~_y = r_y - a_y s_j zeta_j (transposed:
+// r_y - Gamma b_y zeta_j); written in precision T with the first Chebyshev
+// iterate of each box.
+template <typename T, bool TRANS, bool SCHUR>
+__device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, int blk)
+{
+    const long long n = (long long)blk * kBlock + threadIdx.x;
+    if (n >= g.nnode) return;
+    T *b0 = (T *)R.b0;
+    const T *invd0 = (const T *)R.invd0;
+    const double *r = R.r;
+    const double rscale = R.rscale;
+    const int k = (int)(n / ((long long)g.nx * g.ny));
+    double rpe = r[g.off_pe + n] * rscale;
+    double rce = r[g.off_ce + n] * rscale;
+    const int el = node_mat(g, k);
+    if (el >= 0) {
+        const long long base = el == 0 ? 0 : g.nea;
+        const long long klo = el == 0 ? 0 : g.na + g.ns;
+        const long long je = base + n - klo * g.nx * g.ny;
+        const bool dir = (k == 0);
+        double rps = r[je] * rscale;
+        if (SCHUR) {
+            const RadialTab &Tb = R.tabs[el];
+            const int N = Tb.N;
+            const long long nn = el == 0 ? g.nea : g.nec;
+            const double *rs = r + g.off_cs[el] + (je - base);
+            T y = (T)(rs[0] * rscale);
+            for (int q = 1; q < N; q++) {
+                const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+                y = (T)(rs[(long long)q * nn] * rscale) - lq * y;
+            }
+            const double sj = R.ss[je];
+            const T pivN = (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+            const double zeta = (double)(y / pivN);
+            const double m = R.mm[je];
+            if (!TRANS) {   // a_y s_j zeta, a_y = (m, -m, -tc m)
+                const double f = sj * zeta;
+                if (!dir) rps -= m * f;
+                rpe += m * f;
+                rce += g.tc * m * f;
+            } else {        // Gamma b_y zeta, b_y = (g, -g, e)
+                const double f = Tb.Gamma * zeta;
+                const double gj = R.gg[je];
+                if (!dir) rps -= gj * f;
+                rpe += gj * f;
+                rce -= R.ee[je] * f;
+            }
+        }
+        const T bps = (T)rps;
+        b0[je] = bps;
+        if (!dir) R.x1[je] = (el == 0 ? R.c2box[0] : R.c2box[1]) * (double)invd0[je] * (double)bps;
+    }
+    const T bpe = (T)rpe, bce = (T)rce;
+    b0[g.off_pe + n] = bpe;
+    b0[g.off_ce + n] = bce;
+    R.x1[g.off_pe + n] = R.c2box[2] * (double)invd0[g.off_pe + n] * (double)bpe;
+    R.x1[g.off_ce + n] = R.c2box[3] * (double)invd0[g.off_ce + n] * (double)bce;
+}
+
+// z_s,j = A_ss,j^-1 r_s,j - delta_j A_ss,j^-1 e_N, and by Sherman-Morrison
+// A_ss,j^-1 e_N = omega_j T0^-1 e_N: the elimination in precision T only
+// sees r_s, while delta_j = Gamma b_y . z_y (transposed s_j a_y . z_y),
+// which carries the large near-null part of z_y, is applied in FP64.
+template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
+__device__ inline void rad_back_block(const Geom &g, const RadArgs &R, int blk)
+{
+    const long long n = (long long)blk * kBlock + threadIdx.x;
+    if (n >= g.nnode) return;
+    TZ *z = (TZ *)R.z;
+    const double *r = R.r;
+    const double rscale = R.rscale;
+    const int k = (int)(n / ((long long)g.nx * g.ny));
+    const int el = node_mat(g, k);
+    const double zpe = R.x0[2][g.off_pe + n];
+    const double zce = R.x0[3][g.off_ce + n];
+    z[g.off_pe + n] = (TZ)zpe;
+    z[g.off_ce + n] = (TZ)zce;
+    if (el < 0) return;
+    const long long base = el == 0 ? 0 : g.nea;
+    const long long klo = el == 0 ? 0 : g.na + g.ns;
+    const long long je = base + n - klo * g.nx * g.ny;
+    const bool dir = (k == 0);
+    const double zps = dir ? r[je] * rscale : R.x0[el][je];
+    z[je] = (TZ)zps;
+    const RadialTab &Tb = R.tabs[el];
+    const int N = Tb.N;
+    const long long nn = el == 0 ? g.nea : g.nec;
+    const double *rs = r + g.off_cs[el] + (je - base);
+    TZ *zs = z + g.off_cs[el] + (je - base);
+    const double sj = R.ss[je];
+    double dw = 0.0;   // delta_j * omega_j
+    if (SCHUR) {
+        const double m = R.mm[je];
+        double delta;
+        if (!TRANS)
+            delta = Tb.Gamma * ((dir ? 0.0 : R.gg[je]) * zps - R.gg[je] * zpe + R.ee[je] * zce);
+        else
+            delta = sj * ((dir ? 0.0 : m) * zps - m * zpe - g.tc * m * zce);
+        dw = delta * R.om[je];
+    }
+    // forward elimination; the register array is only indexed by unrolled
+    // constants, the last entry is carried separately
+    T y[NRMAX];
+    y[0] = (T)(rs[0] * rscale);
+    T ylast = y[0];
+#pragma unroll
+    for (int q = 1; q < NRMAX; q++) {
+        if (q < N) {
+            const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+            y[q] = (T)(rs[(long long)q * nn] * rscale) - lq * y[q - 1];
+            ylast = y[q];
+        }
+    }
+    T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+    zs[(long long)(N - 1) * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]));
+#pragma unroll
+    for (int q = NRMAX - 2; q >= 0; q--) {
+        if (q < N - 1) {
+            const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
+            zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
+            zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The operator y = A x (or A^T x, or b - A x) for the nodes of one block,
+// with the sum of squares of what the thread writes (paper Sec. 4.1,
+// eq. blocks; see operator.hip).
+// ---------------------------------------------------------------------------
+struct OpArgs {
+    const RadialTab *tabs;
+    const double *sigh, *kaph, *gg, *ss, *ee, *mm;
+    const void *x;       // TX
+    double *y;
+    const double *b;     // b - A x when not null
+};
+
+template <typename TX>
+__device__ inline double ldx(const TX *p) { return (double)*p; }
+
+template <typename TX>
+__device__ inline void load_nb(const Geom &g, const TX *f, long long n, int i, int j, int k,
+                               double X[27])
+{
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = (i + dx >= 0) && (i + dx < g.nx) && (j + dy >= 0) && (j + dy < g.ny) &&
+                        (k + dz >= 0) && (k + dz < g.nz);
+        X[o] = ok ? ldx(f + n + dx + (long long)g.nx * (dy + (long long)g.ny * dz)) : 0.0;
+    }
+}
+
+template <typename TX, bool TRANS, bool RESID>
+__device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
+{
+    const TX *x = (const TX *)O.x;
+    double *y = O.y;
+    const double *b = O.b;
+    double sq = 0.0;
+    const int i = (int)(n % g.nx);
+    const long long t = n / g.nx;
+    const int j = (int)(t % g.ny), k = (int)(t / g.ny);
+    double ck[8], cs[8], cm[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+        const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                        ek < g.nz - 1;
+        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+        ck[e] = ok ? O.kaph[id] : 0.0;
+        cs[e] = ok ? O.sigh[id] : 0.0;
+        cm[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+    }
+    double X[27];
+    load_nb(g, x + g.off_pe, n, i, j, k, X);
+    const double Kpe = q1_stiff(ck, X);
+    const double xpe = X[13];
+    load_nb(g, x + g.off_ce, n, i, j, k, X);
+    const double Kce = q1_stiff(ck, X);
+    const double Mce = q1_mass(cm, X);
+    const double xce = X[13];
+    double ype, yce;
+    if (!TRANS) {
+        ype = Kpe + g.chi * Kce;
+        yce = Mce + Kce;
+    } else {
+        ype = Kpe;
+        yce = Mce + Kce + g.chi * Kpe;
+    }
+    const int el = node_mat(g, k);
+    if (el >= 0) {
+        const long long base = el == 0 ? 0 : g.nea;
+        const int klo = el == 0 ? 0 : g.na + g.ns;
+        const int khi = el == 0 ? g.na - 1 : g.nz - 1;
+        const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
+        const bool dir = (k == 0);
+        // phi_s neighbours: same electrode, grounded layer as a zero column
+#pragma unroll
+        for (int o = 0; o < 27; o++) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            const bool ok = (i + dx >= 0) && (i + dx < g.nx) && (j + dy >= 0) && (j + dy < g.ny) &&
+                            (k + dz >= klo) && (k + dz <= khi) && (k + dz != 0);
+            X[o] = ok ? ldx(x + je + dx + (long long)g.nx * (dy + (long long)g.ny * dz)) : 0.0;
+        }
+        const double xps = ldx(x + je);
+        const RadialTab &T = O.tabs[el];
+        const int N = T.N;
+        const long long nn = el == 0 ? g.nea : g.nec;
+        const long long jl = je - base;
+        const TX *xs = x + g.off_cs[el] + jl;
+        double *ys = y + g.off_cs[el] + jl;
+        const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
+        const double xsN = ldx(xs + (long long)(N - 1) * nn);
+        // a = (m, -m, -tc m, Gamma) rows, b = (g, -g, e, s) columns
+        const double a0 = dir ? 0.0 : m, b0 = dir ? 0.0 : gj;
+        double q, r0, r1, r2, r3;
+        if (!TRANS) {
+            q = b0 * X[13] - gj * xpe + ej * xce + sj * xsN;
+            r0 = a0; r1 = -m; r2 = -g.tc * m; r3 = T.Gamma;
+        } else {
+            q = a0 * X[13] - m * xpe - g.tc * m * xce + T.Gamma * xsN;
+            r0 = b0; r1 = -gj; r2 = ej; r3 = sj;
+        }
+        double yps = dir ? xps : q1_stiff(cs, X) + r0 * q;
+        ype += r1 * q;
+        yce += r2 * q;
+        if (RESID) yps = b[je] - yps;
+        y[je] = yps;
+        sq += yps * yps;
+        double xm = 0.0, x0 = ldx(xs);
+        for (int r = 0; r < N; r++) {
+            const double xp = r < N - 1 ? ldx(xs + (long long)(r + 1) * nn) : 0.0;
+            double v;
+            if (!TRANS)
+                v = T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
+            else
+                v = T.tdia[r] * x0 + (r > 0 ? T.tsup[r - 1] : 0.0) * xm +
+                    (r < N - 1 ? T.tsub[r + 1] : 0.0) * xp;
+            if (r == N - 1) v += r3 * q;
+            if (RESID) v = b[g.off_cs[el] + jl + (long long)r * nn] - v;
+            ys[(long long)r * nn] = v;
+            sq += v * v;
+            xm = x0;
+            x0 = xp;
+        }
+    }
+    if (RESID) {
+        ype = b[g.off_pe + n] - ype;
+        yce = b[g.off_ce + n] - yce;
+    }
+    y[g.off_pe + n] = ype;
+    y[g.off_ce + n] = yce;
+    sq += ype * ype + yce * yce;
+    return sq;
+}
+
+}  // namespace p4d
