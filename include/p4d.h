@@ -193,7 +193,7 @@ p4d_status p4d_param_gradient(p4d_ctx *ctx, const double *d_x, const double *d_l
  * timing off and clears the totals).                                       */
 typedef enum {
     P4D_K_OPERATOR = 1, P4D_K_MDOT = 2, P4D_K_ORTH = 3, P4D_K_RADIAL = 4,
-    P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_COUNT = 7
+    P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_BATCH_PC = 7, P4D_K_COUNT = 8
 } p4d_kernel_class;
 p4d_status p4d_profile(p4d_ctx *ctx, int class_mask);
 /* For one class: total_ms = summed kernel durations, launches, and bytes =
@@ -204,6 +204,74 @@ p4d_status p4d_profile_read(p4d_ctx *ctx, int kernel_class, double *total_ms,
 
 const char *p4d_status_string(p4d_status s);
 const char *p4d_last_error(const p4d_ctx *ctx);
+
+/* Level-0 smoother tile autotuning: times one Chebyshev step over the four
+ * multigrid boxes for each tile shape TX x (256/TX) nodes by CZ layers,
+ * TX in {16, 32, 64}, CZ in {4, 8, 16}, and keeps the fastest for this
+ * context.  Needs p4d_setup; synchronizes `stream`; only preconditioner
+ * buffers are written.  tile (host, may be NULL) receives {TX, CZ}.        */
+p4d_status p4d_autotune(p4d_ctx *ctx, void *stream, int32_t tile[2]);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves: up to 64 independent cells, each with its own mesh, radial
+ * sizes, coefficients and right-hand side, solved together by FGMRES
+ * iterating in lockstep.  Per Arnoldi step the preconditioner of every
+ * iterating cell is applied by one launch per stage depth (stage d of all
+ * cells in one work list of tiles and blocks; the same stages and arithmetic
+ * as the single-cell path), followed by batched operator, Gram-Schmidt and
+ * norm kernels over the table of cells.  A cell that converges stops
+ * iterating; the others go on.  Each cell is a full context
+ * (p4d_batch_cell), so every single-cell call also works on it.
+ *
+ * Sequence: p4d_batch_create, p4d_batch_workspace_size,
+ * p4d_batch_set_workspace, p4d_batch_upload (each cell), p4d_batch_setup,
+ * optionally p4d_batch_autotune, then p4d_batch_solve any number of times.
+ * -------------------------------------------------------------------------*/
+typedef struct p4d_batch p4d_batch;
+
+/* descs: host array of ncells problem descriptions, 1 <= ncells <= 64.      */
+p4d_status p4d_batch_create(const p4d_problem_desc *descs, int32_t ncells, p4d_batch **out);
+void p4d_batch_destroy(p4d_batch *batch);
+/* The context of one cell (owned by the batch; valid until it is destroyed). */
+p4d_status p4d_batch_cell(p4d_batch *batch, int32_t cell, p4d_ctx **out);
+/* Bytes of device workspace for all cells (their contexts' workspaces) plus
+ * the batch tables, for the options `opts` (NULL: defaults).                */
+p4d_status p4d_batch_workspace_size(const p4d_batch *batch, const p4d_solve_opts *opts,
+                                    size_t *bytes);
+/* Carves d_work (device, caller-owned, kept until destroy or the next call)
+ * into the cells' workspaces and the batch tables.  OOM if too small.       */
+p4d_status p4d_batch_set_workspace(p4d_batch *batch, void *d_work, size_t bytes,
+                                   const p4d_solve_opts *opts);
+/* p4d_upload for one cell (device arrays sized for that cell).              */
+p4d_status p4d_batch_upload(p4d_batch *batch, int32_t cell, const double *d_sigma,
+                            const double *d_kappa, const double *d_g, const double *d_s,
+                            const double *d_e, void *stream);
+/* p4d_setup of every cell with the same options; these must keep the
+ * preconditioner precision, coarse size and Z precision of the workspace
+ * options and a restart no larger (STATE otherwise).                        */
+p4d_status p4d_batch_setup(p4d_batch *batch, const p4d_solve_opts *opts, void *stream);
+/* p4d_autotune for each distinct cell geometry; tiles (host, may be NULL)
+ * receives {TX, CZ} per cell.                                               */
+p4d_status p4d_batch_autotune(p4d_batch *batch, void *stream, int32_t *tiles);
+/* Solves A_i x_i = b_i for every cell i.  d_b, d_x: host arrays of ncells
+ * device pointers (vectors of each cell's length N_i, global layout above).
+ * infos (host, may be NULL): ncells entries; t_solve_ms is the time of the
+ * whole batch.  Returns OK when every cell converged, else the status of the
+ * first cell that did not (each cell's own status is in infos).
+ * Synchronizes `stream` once per Arnoldi step.                              */
+p4d_status p4d_batch_solve(p4d_batch *batch, const double *const *d_b, double *const *d_x,
+                           const p4d_solve_opts *opts, p4d_solve_info *infos, void *stream);
+/* mode 0 (default): batched stage launches; mode 1: the single-cell
+ * preconditioner launches, cell after cell (a reference for mode 0).        */
+p4d_status p4d_batch_set_pc_mode(p4d_batch *batch, int32_t mode);
+/* Kernel timing of the batched launches, as p4d_profile / p4d_profile_read;
+ * P4D_K_BATCH_PC times all preconditioner launches of one Arnoldi step
+ * together and counts their level-0 and particle bytes (coarse levels not
+ * counted).                                                                 */
+p4d_status p4d_batch_profile(p4d_batch *batch, int class_mask);
+p4d_status p4d_batch_profile_read(p4d_batch *batch, int kernel_class, double *total_ms,
+                                  int64_t *launches, double *bytes);
+const char *p4d_batch_last_error(const p4d_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -8,8 +8,8 @@ marshals torch tensors to its C ABI (``include/p4d.h``)."""
 from . import _lib
 from ._lib import (P4D_FP32, P4D_FP64, P4D_PC_BJ, P4D_PC_SCHUR, P4DError, default_opts,
                    desc_from)
-from .solver import P4DSolver
+from .solver import P4DBatch, P4DSolver
 from .autograd import P4DSolve, solve
 
-__all__ = ["_lib", "P4DSolver", "P4DSolve", "solve", "P4DError", "default_opts", "desc_from", "P4D_PC_SCHUR",
+__all__ = ["_lib", "P4DSolver", "P4DBatch", "P4DSolve", "solve", "P4DError", "default_opts", "desc_from", "P4D_PC_SCHUR",
            "P4D_PC_BJ", "P4D_FP64", "P4D_FP32"]

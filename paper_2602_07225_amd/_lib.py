@@ -26,18 +26,21 @@ P4D_PC_BJ = 1
 P4D_FP64 = 0
 P4D_FP32 = 1
 
-P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY = range(1, 7)
+(P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY,
+ P4D_K_BATCH_PC) = range(1, 8)
 KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "orth",
-                  P4D_K_RADIAL: "radial", P4D_K_SMOOTH0: "smooth0", P4D_K_ZY: "zy"}
+                  P4D_K_RADIAL: "radial", P4D_K_SMOOTH0: "smooth0", P4D_K_ZY: "zy",
+                  P4D_K_BATCH_PC: "batch_pc"}
 
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
     "p4d_set_workspace", "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
     "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
-    "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error",
-    "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_workspace_size",
-    "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_solve",
-    "p4d_batch_autotune",
+    "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
+    "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_cell", "p4d_batch_workspace_size",
+    "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_autotune",
+    "p4d_batch_solve", "p4d_batch_set_pc_mode", "p4d_batch_profile", "p4d_batch_profile_read",
+    "p4d_batch_last_error",
 ]
 
 
@@ -106,14 +109,14 @@ def lib():
         L.p4d_status_string.restype = C.c_char_p
         L.p4d_last_error.argtypes = [vp]
         L.p4d_last_error.restype = C.c_char_p
-        for name in ["p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
+        L.p4d_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+        for name in ["p4d_autotune", "p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
                      "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
                      "p4d_apply_preconditioner",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
                      "p4d_profile_read"]:
             getattr(L, name).restype = C.c_int
-        if hasattr(L, "p4d_batch_create"):
-            _bind_batch(L)
+        _bind_batch(L)
         _lib = L
     return _lib
 
@@ -123,24 +126,35 @@ def _bind_batch(L):
     L.p4d_batch_create.argtypes = [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(vp)]
     L.p4d_batch_destroy.argtypes = [vp]
     L.p4d_batch_destroy.restype = None
+    L.p4d_batch_cell.argtypes = [vp, C.c_int32, C.POINTER(vp)]
     L.p4d_batch_workspace_size.argtypes = [vp, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
     L.p4d_batch_set_workspace.argtypes = [vp, vp, C.c_size_t, C.POINTER(SolveOpts)]
     L.p4d_batch_upload.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
     L.p4d_batch_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
+    L.p4d_batch_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.p4d_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
                                   C.POINTER(SolveInfo), vp]
-    L.p4d_batch_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
-    for name in ["p4d_batch_create", "p4d_batch_workspace_size", "p4d_batch_set_workspace",
-                 "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_solve", "p4d_batch_autotune"]:
+    L.p4d_batch_set_pc_mode.argtypes = [vp, C.c_int32]
+    L.p4d_batch_profile.argtypes = [vp, C.c_int]
+    L.p4d_batch_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.p4d_batch_last_error.argtypes = [vp]
+    L.p4d_batch_last_error.restype = C.c_char_p
+    for name in ["p4d_batch_create", "p4d_batch_cell", "p4d_batch_workspace_size",
+                 "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup",
+                 "p4d_batch_autotune", "p4d_batch_solve", "p4d_batch_set_pc_mode",
+                 "p4d_batch_profile", "p4d_batch_profile_read"]:
         getattr(L, name).restype = C.c_int
 
 
-def check(status, ctx=None, what=""):
+def check(status, ctx=None, what="", batch=None):
     """Raise on negative statuses; return the status otherwise."""
     if status < 0:
         msg = lib().p4d_status_string(status).decode()
         if ctx:
             msg += ": " + lib().p4d_last_error(ctx).decode()
+        if batch:
+            msg += ": " + lib().p4d_batch_last_error(batch).decode()
         raise P4DError(status, f"{what}: {msg}")
     return status
 
@@ -270,3 +284,88 @@ def p4d_profile_read(ctx, kernel_class: int):
     check(lib().p4d_profile_read(ctx, kernel_class, C.byref(ms), C.byref(n), C.byref(by)), ctx,
           "p4d_profile_read")
     return ms.value, n.value, by.value
+
+
+def p4d_autotune(ctx, stream=None):
+    tile = (C.c_int32 * 2)()
+    check(lib().p4d_autotune(ctx, stream_ptr(stream), tile), ctx, "p4d_autotune")
+    return tile[0], tile[1]
+
+
+# ---- batched solves ------------------------------------------------------------
+def p4d_batch_create(descs) -> int:
+    arr = (ProblemDesc * len(descs))(*descs)
+    h = C.c_void_p()
+    check(lib().p4d_batch_create(arr, len(descs), C.byref(h)), None, "p4d_batch_create")
+    return h.value
+
+
+def p4d_batch_destroy(batch: int) -> None:
+    lib().p4d_batch_destroy(batch)
+
+
+def p4d_batch_cell(batch: int, cell: int) -> int:
+    h = C.c_void_p()
+    check(lib().p4d_batch_cell(batch, cell, C.byref(h)), None, "p4d_batch_cell", batch)
+    return h.value
+
+
+def p4d_batch_workspace_size(batch: int, opts: SolveOpts | None = None) -> int:
+    b = C.c_size_t()
+    check(lib().p4d_batch_workspace_size(batch, C.byref(opts) if opts else None, C.byref(b)),
+          None, "p4d_batch_workspace_size", batch)
+    return b.value
+
+
+def p4d_batch_set_workspace(batch, d_work: int, nbytes: int, opts: SolveOpts | None = None):
+    return check(lib().p4d_batch_set_workspace(batch, d_work, nbytes,
+                                               C.byref(opts) if opts else None),
+                 None, "p4d_batch_set_workspace", batch)
+
+
+def p4d_batch_upload(batch, cell, sigma, kappa, g, s, e, stream=None):
+    return check(lib().p4d_batch_upload(batch, cell, ptr(sigma), ptr(kappa), ptr(g), ptr(s),
+                                        ptr(e), stream_ptr(stream)),
+                 None, "p4d_batch_upload", batch)
+
+
+def p4d_batch_setup(batch, opts: SolveOpts | None = None, stream=None):
+    return check(lib().p4d_batch_setup(batch, C.byref(opts) if opts else None,
+                                       stream_ptr(stream)), None, "p4d_batch_setup", batch)
+
+
+def p4d_batch_autotune(batch, ncells, stream=None):
+    tiles = (C.c_int32 * (2 * ncells))()
+    check(lib().p4d_batch_autotune(batch, stream_ptr(stream), tiles), None,
+          "p4d_batch_autotune", batch)
+    return [(tiles[2 * i], tiles[2 * i + 1]) for i in range(ncells)]
+
+
+def p4d_batch_solve(batch, bs, xs, opts: SolveOpts | None = None, stream=None):
+    n = len(bs)
+    bp = (C.c_void_p * n)(*[ptr(b) for b in bs])
+    xp = (C.c_void_p * n)(*[ptr(x) for x in xs])
+    infos = (SolveInfo * n)()
+    st = check(lib().p4d_batch_solve(batch, bp, xp, C.byref(opts) if opts else None, infos,
+                                     stream_ptr(stream)), None, "p4d_batch_solve", batch)
+    return st, list(infos)
+
+
+def p4d_batch_set_pc_mode(batch, mode: int):
+    return check(lib().p4d_batch_set_pc_mode(batch, int(mode)), None, "p4d_batch_set_pc_mode",
+                 batch)
+
+
+def p4d_batch_profile(batch, class_mask: int):
+    return check(lib().p4d_batch_profile(batch, class_mask), None, "p4d_batch_profile", batch)
+
+
+def p4d_batch_profile_read(batch, kernel_class: int):
+    ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+    check(lib().p4d_batch_profile_read(batch, kernel_class, C.byref(ms), C.byref(n),
+                                       C.byref(by)), None, "p4d_batch_profile_read", batch)
+    return ms.value, n.value, by.value
+
+
+def p4d_batch_last_error(batch) -> str:
+    return lib().p4d_batch_last_error(batch).decode()

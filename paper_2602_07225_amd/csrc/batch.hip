@@ -1,0 +1,408 @@
+// Batched solves of many independent cells of uneven size in lockstep:
+//  - the preconditioner of every iterating cell in one launch per stage
+//    depth;
+//  - batched operator and Krylov streaming kernels over a table of cells.
+//
+// Every cell's preconditioner application is a fixed sequence of stages
+// (particle forward elimination, the V-cycle stages of its four boxes level
+// by level, particle back-substitution), recorded once with the same
+// schedule as the single-cell path.  A stage splits into workgroup-sized
+// units (tiles, 256-node blocks, 64-row blocks).  Stage d of all cells forms
+// one work list, larger cells first; one launch runs that list, one unit per
+// workgroup, so the launches of one application are ordered by the stream
+// and no workgroup ever waits for another.
+//
+// Each unit computes exactly what the single-cell kernels compute for the
+// same block or tile (the same device functions), so a cell solved in a
+// batch follows the same arithmetic as the cell solved alone.
+#include "p4d_batch.hpp"
+
+namespace p4d {
+
+// ---------------------------------------------------------------------------
+// Batched preconditioner stages
+// ---------------------------------------------------------------------------
+union PLds {
+    Smooth0Lds s0;
+    CoarseLds co;
+};
+
+__device__ inline int find_pos(const int *ustart, int npos, int item)
+{
+    int lo = 0, hi = npos - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ustart[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T, typename TZ, int NRMAX>
+__device__ inline void run_unit(const PStage<T> &S, const PCell &C, int k, int transpose, int unit,
+                                PLds &lds)
+{
+    const Geom &g = C.g;
+    switch (S.kind) {
+    case SK_RADF: {
+        const double *r = C.V + (long long)k * g.N;
+        const double rs = C.invbeta[k];
+        if (C.schur) {
+            if (transpose) rad_fwd_block<T, true, true>(g, C.R, r, rs, unit);
+            else rad_fwd_block<T, false, true>(g, C.R, r, rs, unit);
+        } else {
+            rad_fwd_block<T, false, false>(g, C.R, r, rs, unit);
+        }
+        break;
+    }
+    case SK_RADB: {
+        const double *r = C.V + (long long)k * g.N;
+        const double rs = C.invbeta[k];
+        TZ *z = (TZ *)C.Z + (long long)k * g.N;
+        if (C.schur) {
+            if (transpose) rad_back_block<T, TZ, NRMAX, true, true>(g, C.R, r, rs, z, unit);
+            else rad_back_block<T, TZ, NRMAX, false, true>(g, C.R, r, rs, z, unit);
+        } else {
+            if (transpose) rad_back_block<T, TZ, NRMAX, true, false>(g, C.R, r, rs, z, unit);
+            else rad_back_block<T, TZ, NRMAX, false, false>(g, C.R, r, rs, z, unit);
+        }
+        break;
+    }
+    case SK_SM0:
+    case SK_SM0R: {
+        const LevelArgs<T> &A = S.u.lb.a[find_box(S.u.lb, unit)];
+        if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, unit - A.blk0, S.TX, S.CZ, lds.s0);
+        else smooth0_tile<T, true>(g, A, unit - A.blk0, S.TX, S.CZ, lds.s0);
+        break;
+    }
+    case SK_SM:
+    case SK_SMR: {
+        const LevelArgs<T> &A = S.u.lb.a[find_box(S.u.lb, unit)];
+        if (S.kind == SK_SM) smooth_block<T, false>(A, unit - A.blk0);
+        else smooth_block<T, true>(A, unit - A.blk0);
+        break;
+    }
+    case SK_RESTRICT: {
+        const TransferArgs<T> &A = S.u.tb.a[find_box(S.u.tb, unit)];
+        restrict_block<T>(A, unit - A.blk0);
+        break;
+    }
+    case SK_PROLONG: {
+        const TransferArgs<T> &A = S.u.tb.a[find_box(S.u.tb, unit)];
+        prolong_block<T>(A, unit - A.blk0);
+        break;
+    }
+    case SK_COARSE: {
+        const int box = unit / S.aux, rb = unit % S.aux;
+        if (box < S.u.cb.nbox && rb * 64 < S.u.cb.a[box].n) coarse_block<T>(S.u.cb.a[box], rb, lds.co);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// one unit of the work list of one stage depth per workgroup
+template <typename T, typename TZ, int NRMAX>
+__global__ __launch_bounds__(kBlock) void k_batch_stage(StageRun run)
+{
+    __shared__ PLds lds;
+    const int item = run.item0 + xcd_block(blockIdx.x, gridDim.x);
+    const int pos = run.pos0 + find_pos(run.ustart + run.pos0, run.npos, item);
+    const PStage<T> &S = ((const PStage<T> *)run.stages)[run.order[pos]];
+    if (!((run.active >> S.cell) & 1ULL)) return;   // the cell is not iterating
+    run_unit<T, TZ, NRMAX>(S, run.cells[S.cell], run.k, run.transpose, item - run.ustart[pos], lds);
+}
+
+template <typename T, typename TZ>
+void launch_batch_stage(const StageRun &run, int nrmax, hipStream_t st)
+{
+    if (run.nitems <= 0) return;
+#define P4D_BS(NR) hipLaunchKernelGGL((k_batch_stage<T, TZ, NR>), dim3(run.nitems), dim3(kBlock), 0, st, run)
+    switch (nrmax) {
+    case 8: P4D_BS(8); break;
+    case 16: P4D_BS(16); break;
+    case 32: P4D_BS(32); break;
+    default: P4D_BS(64); break;
+    }
+#undef P4D_BS
+}
+#define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, hipStream_t);
+P4D_INST(double, double)
+P4D_INST(float, double)
+P4D_INST(double, float)
+P4D_INST(float, float)
+#undef P4D_INST
+
+// ---------------------------------------------------------------------------
+// Batched operator and Krylov streaming kernels.  The workgroups of the
+// cells follow each other in the grid (offsets in the cell table); those of
+// cells outside the active mask return at once.  Per cell, the partition of
+// the work and the order of every reduction are those of the single-cell
+// kernels.
+// ---------------------------------------------------------------------------
+__device__ inline int find_cell(const BCell *cells, int ncells, int b, bool op)
+{
+    int lo = 0, hi = ncells - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((op ? cells[mid].op_blk0 : cells[mid].st_blk0) <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// RESID: V_0 = b - A x with per-workgroup sums of squares; otherwise
+// V_{k+1} = A Z_k
+template <typename TX, bool TRANS, bool RESID>
+__global__ __launch_bounds__(kBlock) void k_bop(const BCell *__restrict__ cells, int ncells,
+                                                unsigned long long active, int k)
+{
+    __shared__ double red[4];
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = find_cell(cells, ncells, gb, true);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int lb = gb - C.op_blk0;
+    const long long n = (long long)lb * kBlock + threadIdx.x;
+    OpArgs O = C.op;
+    if (RESID) {
+        O.x = C.x;
+        O.y = C.V;
+        O.b = C.b;
+    } else {
+        O.x = (const TX *)C.Z + (long long)k * C.g.N;
+        O.y = C.V + (long long)(k + 1) * C.g.N;
+        O.b = nullptr;
+    }
+    double sq = 0.0;
+    if (n < C.g.nnode) sq = operator_node<TX, TRANS, RESID>(C.g, O, n);
+    if (RESID) {
+        const double s = block_sum(sq, red);
+        if (threadIdx.x == 0) C.red[lb] = s;
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bmdot(const BCell *__restrict__ cells, int ncells,
+                                                  unsigned long long active, int k)
+{
+    __shared__ double red[4][KMAX];
+    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
+    const long long N = C.g.N;
+    const int nv = k + 1;
+    const double *__restrict__ V = C.V;
+    const double *__restrict__ w = V + (long long)(k + 1) * N;
+    double acc[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; q++) acc[q] = 0.0;
+    for (long long i = (long long)lb * kBlock + threadIdx.x; i < N; i += (long long)nb * kBlock) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < KMAX; q++)
+            if (q < nv) acc[q] += wi * V[(long long)q * N + i];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < KMAX; q++) {
+        if (q < nv) {
+            const double s = wave_sum(acc[q]);
+            if (lane == 0) red[wv][q] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv)
+        C.red[(long long)threadIdx.x * nb + lb] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// grid (nv, ncells): h_q = invbeta_q * sum_b partial[q][b], c_q = h_q * invbeta_q
+__global__ __launch_bounds__(kBlock) void k_bmdot_final(const BCell *__restrict__ cells,
+                                                        unsigned long long active, int pass)
+{
+    __shared__ double red[4];
+    const int q = blockIdx.x, c = blockIdx.y;
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int nb = C.st_nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += C.red[(long long)q * nb + b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        const double hq = s * C.invbeta[q];
+        C.h[64 * pass + q] = hq;
+        C.coef[q] = hq * C.invbeta[q];
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_borth(const BCell *__restrict__ cells, int ncells,
+                                                  unsigned long long active, int k)
+{
+    __shared__ double red[4];
+    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
+    const long long N = C.g.N;
+    const int nv = k + 1;
+    const double *__restrict__ V = C.V;
+    double *__restrict__ w = C.V + (long long)(k + 1) * N;
+    double cq[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; q++) cq[q] = q < nv ? C.coef[q] : 0.0;
+    double sq = 0.0;
+    for (long long i = (long long)lb * kBlock + threadIdx.x; i < N; i += (long long)nb * kBlock) {
+        double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < KMAX; q++)
+            if (q < nv) wi -= cq[q] * V[(long long)q * N + i];
+        w[i] = wi;
+        sq += wi * wi;
+    }
+    const double s = block_sum(sq, red);
+    if (threadIdx.x == 0) C.red[lb] = s;
+}
+
+// grid ncells: beta = sqrt(sum of the cell's partials) into h[128] and
+// 1/beta into invbeta[slot] (0 when beta = 0); op = 1 reduces the operator
+// partials
+__global__ __launch_bounds__(kBlock) void k_bnorm_final(const BCell *__restrict__ cells,
+                                                        unsigned long long active, int slot, int op)
+{
+    __shared__ double red[4];
+    const int c = blockIdx.x;
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int nb = op ? C.op_nblk : C.st_nblk;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += C.red[b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        const double bt = sqrt(s);
+        C.h[128] = bt;
+        C.invbeta[slot] = bt > 0.0 ? 1.0 / bt : 0.0;
+    }
+}
+
+template <typename TZ, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_bzy(const BCell *__restrict__ cells, int ncells,
+                                                unsigned long long active)
+{
+    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
+    const long long N = C.g.N;
+    const int nv = *C.kused;
+    double yq[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; q++) yq[q] = q < nv ? C.y[q] : 0.0;
+    const TZ *__restrict__ Z = (const TZ *)C.Z;
+    double *__restrict__ x = C.x;
+    for (long long i = (long long)lb * kBlock + threadIdx.x; i < N; i += (long long)nb * kBlock) {
+        double xi = x[i];
+#pragma unroll
+        for (int q = 0; q < KMAX; q++)
+            if (q < nv) xi += yq[q] * (double)Z[(long long)q * N + i];
+        x[i] = xi;
+    }
+}
+
+// per cell: partial sums of ||b||^2, x = 0, V_0 = b
+__global__ __launch_bounds__(kBlock) void k_bstart(const BCell *__restrict__ cells, int ncells)
+{
+    __shared__ double red[4];
+    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const BCell &C = cells[c];
+    const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
+    const long long N = C.g.N;
+    double s = 0.0;
+    for (long long i = (long long)lb * kBlock + threadIdx.x; i < N; i += (long long)nb * kBlock) {
+        const double bi = C.b[i];
+        s += bi * bi;
+        C.x[i] = 0.0;
+        C.V[i] = bi;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) C.red[lb] = s;
+}
+
+void launch_bstart(const BCell *cells, int ncells, int nblk_st, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bstart, dim3(nblk_st), dim3(kBlock), 0, st, cells, ncells);
+}
+
+template <typename TZ>
+void launch_bop(const BCell *cells, int ncells, unsigned long long active, int k, int resid,
+                int transpose, int nblk_op, hipStream_t st)
+{
+#define P4D_BO(TXT, TR, RS) \
+    hipLaunchKernelGGL((k_bop<TXT, TR, RS>), dim3(nblk_op), dim3(kBlock), 0, st, cells, ncells, active, k)
+    if (resid) {
+        if (transpose) P4D_BO(double, true, true);
+        else P4D_BO(double, false, true);
+    } else {
+        if (transpose) P4D_BO(TZ, true, false);
+        else P4D_BO(TZ, false, false);
+    }
+#undef P4D_BO
+}
+template void launch_bop<double>(const BCell *, int, unsigned long long, int, int, int, int, hipStream_t);
+template void launch_bop<float>(const BCell *, int, unsigned long long, int, int, int, int, hipStream_t);
+
+void launch_bmdot(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
+                  int pass, hipStream_t st)
+{
+    const int nv = k + 1;
+#define P4D_BM(K) \
+    hipLaunchKernelGGL((k_bmdot<K>), dim3(nblk_st), dim3(kBlock), 0, st, cells, ncells, active, k)
+    if (nv <= 4) P4D_BM(4);
+    else if (nv <= 8) P4D_BM(8);
+    else if (nv <= 16) P4D_BM(16);
+    else if (nv <= 32) P4D_BM(32);
+    else P4D_BM(64);
+#undef P4D_BM
+    hipLaunchKernelGGL(k_bmdot_final, dim3(nv, ncells), dim3(kBlock), 0, st, cells, active, pass);
+}
+
+void launch_borth(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
+                  hipStream_t st)
+{
+    const int nv = k + 1;
+#define P4D_BR(K) \
+    hipLaunchKernelGGL((k_borth<K>), dim3(nblk_st), dim3(kBlock), 0, st, cells, ncells, active, k)
+    if (nv <= 4) P4D_BR(4);
+    else if (nv <= 8) P4D_BR(8);
+    else if (nv <= 16) P4D_BR(16);
+    else if (nv <= 32) P4D_BR(32);
+    else P4D_BR(64);
+#undef P4D_BR
+}
+
+void launch_bnorm_final(const BCell *cells, int ncells, unsigned long long active, int slot, int op,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bnorm_final, dim3(ncells), dim3(kBlock), 0, st, cells, active, slot, op);
+}
+
+template <typename TZ>
+void launch_bzy(const BCell *cells, int ncells, unsigned long long active, int kmax, int nblk_st,
+                hipStream_t st)
+{
+#define P4D_BZ(K) \
+    hipLaunchKernelGGL((k_bzy<TZ, K>), dim3(nblk_st), dim3(kBlock), 0, st, cells, ncells, active)
+    if (kmax <= 4) P4D_BZ(4);
+    else if (kmax <= 8) P4D_BZ(8);
+    else if (kmax <= 16) P4D_BZ(16);
+    else if (kmax <= 32) P4D_BZ(32);
+    else P4D_BZ(64);
+#undef P4D_BZ
+}
+template void launch_bzy<double>(const BCell *, int, unsigned long long, int, int, hipStream_t);
+template void launch_bzy<float>(const BCell *, int, unsigned long long, int, int, hipStream_t);
+
+}  // namespace p4d

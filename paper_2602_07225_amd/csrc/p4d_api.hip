@@ -4,6 +4,7 @@
 // per-DOF work runs in the HIP kernels of operator.hip, radial.hip, mg.hip
 // and krylov.hip; the host only computes O(N_r) radial tables, O(levels)
 // Chebyshev coefficients and the (m+1) x m Hessenberg least-squares problem.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -12,8 +13,7 @@
 #include <vector>
 
 #include "../../include/p4d.h"
-#include "p4d_internal.hpp"
-#include "p4d_kernels.hpp"
+#include "p4d_batch.hpp"
 
 using namespace p4d;
 
@@ -80,6 +80,11 @@ struct p4d_ctx {
     double *hhost = nullptr;       // pinned host staging
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     Prof prof;
+    // record mode: the preconditioner schedule is appended to a stage list
+    // (std::vector<PStage<T>>) instead of being launched
+    void *rec = nullptr;
+    int rec_cell = 0;
+    RadArgs rec_R{};
 };
 
 // ---------------------------------------------------------------------------
@@ -331,9 +336,8 @@ static bool opts_valid(const p4d_solve_opts &o, std::string &why)
 // ---------------------------------------------------------------------------
 // profiling: event pairs around launches of one kernel class
 // ---------------------------------------------------------------------------
-static void prof_harvest(p4d_ctx *c)
+static void prof_harvest(Prof &P)
 {
-    Prof &P = c->prof;
     for (int i = 0; i < P.used; i++) {
         hipEventSynchronize(P.ev[2 * i + 1]);
         float ms = 0.f;
@@ -344,15 +348,36 @@ static void prof_harvest(p4d_ctx *c)
     }
     P.used = 0;
 }
+static void prof_init(Prof &P)
+{
+    P.ev.resize(2 * 512);
+    P.bytes.resize(512);
+    P.cls.resize(512);
+    for (auto &e : P.ev) hipEventCreate(&e);
+}
+static void prof_free(Prof &P)
+{
+    for (auto &e : P.ev) hipEventDestroy(e);
+    P.ev.clear();
+}
+static void prof_reset(Prof &P, int mask)
+{
+    prof_harvest(P);
+    P.mask = mask;
+    for (int k = 0; k < P4D_K_COUNT; k++) {
+        P.total_ms[k] = 0.0;
+        P.total_bytes[k] = 0.0;
+        P.launches[k] = 0;
+    }
+}
 struct ProfScope {
-    p4d_ctx *c;
+    Prof &P;
     bool on;
     hipStream_t st;
-    ProfScope(p4d_ctx *c_, int cls, double bytes, hipStream_t s) : c(c_), on(false), st(s)
+    ProfScope(Prof &P_, int cls, double bytes, hipStream_t s) : P(P_), on(false), st(s)
     {
-        Prof &P = c->prof;
         if (!(P.mask & (1 << cls))) return;
-        if (P.used * 2 + 2 > (int)P.ev.size()) prof_harvest(c);
+        if (P.used * 2 + 2 > (int)P.ev.size()) prof_harvest(P);
         P.bytes[P.used] = bytes;
         P.cls[P.used] = cls;
         hipEventRecord(P.ev[2 * P.used], st);
@@ -361,7 +386,6 @@ struct ProfScope {
     ~ProfScope()
     {
         if (!on) return;
-        Prof &P = c->prof;
         hipEventRecord(P.ev[2 * P.used + 1], st);
         P.used++;
     }
@@ -377,7 +401,7 @@ static void apply_op(p4d_ctx *c, int transpose, const TX *x, double *y, const do
     const Geom &g = c->g;
     const double bytes = (double)sizeof(TX) * g.N + 8.0 * g.N + (b ? 8.0 * g.N : 0.0) +
                          16.0 * g.nelem + 32.0 * g.ne;
-    ProfScope ps(c, P4D_K_OPERATOR, bytes, st);
+    ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
     launch_operator<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, x, y, b,
                         partial, transpose, st);
 }
@@ -414,6 +438,21 @@ struct VState {
 };
 
 static double *lvx(Level &L, int which) { return (double *)(which ? L.xb : L.xa); }
+
+template <typename T>
+static PStage<T> &rec_stage(p4d_ctx *c, int kind, int nunits)
+{
+    auto &v = *(std::vector<PStage<T>> *)c->rec;
+    v.emplace_back();
+    PStage<T> &S = v.back();
+    std::memset((void *)&S, 0, sizeof(S));
+    S.kind = kind;
+    S.cell = c->rec_cell;
+    S.nunits = nunits;
+    S.TX = c->tile_tx;
+    S.CZ = c->tile_cz;
+    return S;
+}
 
 template <typename T>
 static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int nb, int step,
@@ -453,6 +492,10 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
         A.rout = nullptr;
         vs.xcur[b][l] = 1 - cur;
     }
+    if (c->rec) {
+        rec_stage<T>(c, l == 0 ? SK_SM0 : SK_SM, blk).u.lb = lb;
+        return;
+    }
     if (l == 0) {
         // algorithmic bytes: x read and written (FP64), b, D^-1, reaction
         // diagonal (+ direction in/out) in T, one element coefficient per node
@@ -462,7 +505,7 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
             const double per = 16.0 + 8.0 + sizeof(T) * (3 + (A.c1 != 0.0 && !A.din_x) + (A.dout != nullptr));
             bytes += per * A.n;
         }
-        ProfScope ps(c, P4D_K_SMOOTH0, bytes, st);
+        ProfScope ps(c->prof, P4D_K_SMOOTH0, bytes, st);
         launch_smooth0<T>(c->g, lb, blk, 0, c->tile_tx, c->tile_cz, st);
     } else {
         launch_smooth<T>(lb, blk, 0, st);
@@ -494,7 +537,8 @@ static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, in
         A.xin = lvx(L, vs.xcur[b][l]);
         A.rout = (T *)L.r;
     }
-    if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, c->tile_tx, c->tile_cz, st);
+    if (c->rec) rec_stage<T>(c, l == 0 ? SK_SM0R : SK_SMR, blk).u.lb = lb;
+    else if (l == 0) launch_smooth0<T>(c->g, lb, blk, 1, c->tile_tx, c->tile_cz, st);
     else launch_smooth<T>(lb, blk, 1, st);
 }
 
@@ -517,7 +561,16 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             cb.a[q].x = (double *)L.xa;
             vs.xcur[crs[q]][l] = 0;
         }
-        launch_coarse<T>(cb, st);
+        if (c->rec) {
+            int nmax = 1;
+            for (int q = 0; q < nc; q++) nmax = cb.a[q].n > nmax ? cb.a[q].n : nmax;
+            const int rows = (nmax + 63) / 64;
+            PStage<T> &S = rec_stage<T>(c, SK_COARSE, rows * nc);
+            S.aux = rows;
+            S.u.cb = cb;
+        } else {
+            launch_coarse<T>(cb, st);
+        }
     }
     if (!na) return;
     const int deg = c->pc.cheb_degree;
@@ -543,7 +596,8 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             A.c2c = coarsest ? 0.0 : cheb_coef(Cl.lmax, deg).c2[1];
             vs.xcur[act[q]][l + 1] = 0;
         }
-        launch_restrict<T>(tb, blk, st);
+        if (c->rec) rec_stage<T>(c, SK_RESTRICT, blk).u.tb = tb;
+        else launch_restrict<T>(tb, blk, st);
     }
     vcycle_level<T>(c, vs, l + 1, st);
     {   // prolongation and correction
@@ -561,9 +615,23 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
             A.xc = lvx(Cl, vs.xcur[act[q]][l + 1]);
             A.xf = lvx(F, vs.xcur[act[q]][l]);
         }
-        launch_prolong<T>(tb, blk, st);
+        if (c->rec) rec_stage<T>(c, SK_PROLONG, blk).u.tb = tb;
+        else launch_prolong<T>(tb, blk, st);
     }
     for (int t = 1; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 1, st);
+}
+
+// fixed part of the particle-block arguments
+static RadArgs rad_args(const p4d_ctx *c)
+{
+    RadArgs R{};
+    R.tabs = c->tabs;
+    R.gg = c->gg; R.ss = c->ss; R.ee = c->ee; R.mm = c->mm; R.om = c->omega;
+    R.b0 = c->b0;
+    R.x1 = (double *)c->x0a;
+    R.invd0 = c->invd0;
+    for (int b = 0; b < 4; b++) R.c2box[b] = cheb_coef(c->box[b].lev[0].lmax, c->pc.cheb_degree).c2[1];
+    return R;
 }
 
 // z = P^-1 (rscale r), or P^-T
@@ -573,31 +641,27 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
 {
     const Geom &g = c->g;
     const int schur = c->pc.pc == P4D_PC_SCHUR;
-    RadArgs R{};
-    R.tabs = c->tabs;
-    R.gg = c->gg; R.ss = c->ss; R.ee = c->ee; R.mm = c->mm; R.om = c->omega;
-    R.r = r;
-    R.rscale = rscale;
-    R.b0 = c->b0;
-    R.x1 = (double *)c->x0a;
-    R.invd0 = c->invd0;
-    for (int b = 0; b < 4; b++) R.c2box[b] = cheb_coef(c->box[b].lev[0].lmax, c->pc.cheb_degree).c2[1];
-    const double rbytes = 8.0 * g.N + 32.0 * g.ne + (sizeof(T) * 2 + 8.0) * g.Nm;
-    {
-        ProfScope ps(c, P4D_K_RADIAL, rbytes, st);
-        launch_rad_fwd<T>(g, R, transpose, schur, st);
+    const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
+    RadArgs R = rad_args(c);
+    if (c->rec) {
+        rec_stage<T>(c, SK_RADF, nb);
+    } else {
+        ProfScope ps(c->prof, P4D_K_RADIAL, 8.0 * g.N + 32.0 * g.ne + (sizeof(T) * 2 + 8.0) * g.Nm, st);
+        launch_rad_fwd<T>(g, R, r, rscale, transpose, schur, st);
     }
     VState<T> vs{};
     for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
     vcycle_level<T>(c, vs, 0, st);
     // each box's final level-0 iterate (the two buffers alternate)
     for (int b = 0; b < 4; b++) R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
-    R.z = z;
-    {
-        ProfScope ps(c, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + 8.0 * g.Nm +
-                                          sizeof(TZ) * g.N + 40.0 * g.ne, st);
-        launch_rad_back<T, TZ>(g, R, transpose, schur, st);
+    if (c->rec) {
+        rec_stage<T>(c, SK_RADB, nb);
+        c->rec_R = R;
+        return;
     }
+    ProfScope ps(c->prof, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 8.0 * g.ne + 8.0 * g.Nm +
+                                           sizeof(TZ) * g.N + 40.0 * g.ne, st);
+    launch_rad_back<T, TZ>(g, R, r, rscale, z, transpose, schur, st);
 }
 
 template <typename TZ>
@@ -744,7 +808,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             launch_norm_final(red, ob, c->hdev + 200, c->invbeta, st);
             HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
-            prof_harvest(c);
+            prof_harvest(c->prof);
             beta[0] = hh[0];
         }
         inf.relres_true = beta[0] / bnorm;
@@ -765,19 +829,19 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             const int passes = o.cgs2 ? 2 : 1;
             for (int p = 0; p < passes; p++) {
                 {
-                    ProfScope ps(c, P4D_K_MDOT, 8.0 * (nv + 1) * N, st);
+                    ProfScope ps(c->prof, P4D_K_MDOT, 8.0 * (nv + 1) * N, st);
                     launch_mdot(N, w, V, N, nv, red, sb, st);
                 }
                 launch_mdot_final(nv, red, sb, c->invbeta, c->hdev + 64 * p, c->cdev, st);
                 {
-                    ProfScope ps(c, P4D_K_ORTH, 8.0 * (nv + 2) * N, st);
+                    ProfScope ps(c->prof, P4D_K_ORTH, 8.0 * (nv + 2) * N, st);
                     launch_orth(N, w, V, N, nv, c->cdev, red, sb, st);
                 }
             }
             launch_norm_final(red, sb, c->hdev + 128, c->invbeta + k + 1, st);
             HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8 * 129, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
-            prof_harvest(c);
+            prof_harvest(c->prof);
             for (int i = 0; i <= k; i++) hc[i] = hh[i] + (o.cgs2 ? hh[64 + i] : 0.0);
             const double hn = hh[128];
             hc[k + 1] = hn;
@@ -815,7 +879,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         for (int i = 0; i < kused; i++) hout[i] = yv[i];
         HIPCHK(c, hipMemcpyAsync(c->ydev, hout, 8 * kused, hipMemcpyHostToDevice, st));
         {
-            ProfScope ps(c, P4D_K_ZY, (8.0 * 2 + sizeof(TZ) * kused) * N, st);
+            ProfScope ps(c->prof, P4D_K_ZY, (8.0 * 2 + sizeof(TZ) * kused) * N, st);
             launch_zy<TZ>(N, x, Z, N, kused, c->ydev, st);
         }
         inf.restarts++;
@@ -832,7 +896,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
 done:
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
-    prof_harvest(c);
+    prof_harvest(c->prof);
     inf.iters = total;
     inf.status = status;
     inf.t_solve_ms =
@@ -905,10 +969,7 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
     }
     c->tile_tx = d->nx >= 48 ? 64 : (d->nx >= 24 ? 32 : 16);
     c->tile_cz = 8;
-    c->prof.ev.resize(2 * 512);
-    c->prof.bytes.resize(512);
-    c->prof.cls.resize(512);
-    for (auto &e : c->prof.ev) hipEventCreate(&e);
+    prof_init(c->prof);
     p4d_default_opts(&c->ws_opts);
     *out = c;
     return P4D_OK;
@@ -917,7 +978,7 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
 void p4d_destroy(p4d_ctx *c)
 {
     if (!c) return;
-    for (auto &e : c->prof.ev) hipEventDestroy(e);
+    prof_free(c->prof);
     if (c->hhost) hipHostFree(c->hhost);
     delete c;
 }
@@ -1120,13 +1181,7 @@ p4d_status p4d_param_gradient(p4d_ctx *c, const double *x, const double *lam, do
 p4d_status p4d_profile(p4d_ctx *c, int mask)
 {
     if (!c || mask < 0 || mask >= (1 << P4D_K_COUNT)) return P4D_ERR_INVALID_ARG;
-    prof_harvest(c);
-    c->prof.mask = mask;
-    for (int k = 0; k < P4D_K_COUNT; k++) {
-        c->prof.total_ms[k] = 0.0;
-        c->prof.total_bytes[k] = 0.0;
-        c->prof.launches[k] = 0;
-    }
+    prof_reset(c->prof, mask);
     return P4D_OK;
 }
 
@@ -1134,11 +1189,748 @@ p4d_status p4d_profile_read(p4d_ctx *c, int cls, double *total_ms, int64_t *laun
                             double *bytes)
 {
     if (!c || cls < 1 || cls >= P4D_K_COUNT) return P4D_ERR_INVALID_ARG;
-    prof_harvest(c);
+    prof_harvest(c->prof);
     if (total_ms) *total_ms = c->prof.total_ms[cls];
     if (launches) *launches = c->prof.launches[cls];
     if (bytes) *bytes = c->prof.total_bytes[cls];
     return P4D_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Tile autotuning of the level-0 smoother: every candidate shape is timed on
+// one Chebyshev step over the four boxes of this context and the fastest is
+// kept.  The step writes only preconditioner buffers, which every
+// preconditioner application overwrites before reading.
+// ---------------------------------------------------------------------------
+template <typename T>
+static p4d_status tune_tiles_t(p4d_ctx *c, hipStream_t st)
+{
+    static const int txs[3] = {16, 32, 64}, czs[3] = {4, 8, 16};
+    const int boxes[4] = {0, 1, 2, 3};
+    const int mask = c->prof.mask;
+    c->prof.mask = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(c, P4D_ERR_HIP, "hipEventCreate");
+    }
+    float best = 0.f;
+    int btx = c->tile_tx, bcz = c->tile_cz;
+    hipError_t he = hipSuccess;
+    for (int a = 0; a < 3 && he == hipSuccess; a++)
+        for (int q = 0; q < 3 && he == hipSuccess; q++) {
+            c->tile_tx = txs[a];
+            c->tile_cz = czs[q];
+            VState<T> vs{};
+            smooth_step<T>(c, vs, 0, boxes, 4, 1, 1, st);   // warm-up
+            hipEventRecord(e0, st);
+            for (int rep = 0; rep < 4; rep++) smooth_step<T>(c, vs, 0, boxes, 4, 1, 1, st);
+            hipEventRecord(e1, st);
+            he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he == hipSuccess && (best == 0.f || ms < best)) {
+                best = ms;
+                btx = txs[a];
+                bcz = czs[q];
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tile_tx = btx;
+    c->tile_cz = bcz;
+    c->prof.mask = mask;
+    if (he != hipSuccess) return hipchk(c, he, "smoother tile timing");
+    return hipchk(c, hipGetLastError(), "smoother tile timing");
+}
+
+static p4d_status tune_tiles(p4d_ctx *c, hipStream_t st)
+{
+    return c->prec ? tune_tiles_t<float>(c, st) : tune_tiles_t<double>(c, st);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: independent cells, each a full context with its own slice
+// of the batch workspace, iterate FGMRES in lockstep.  Per Arnoldi step there
+// are the preconditioner launches for all iterating cells (one per stage
+// depth), then
+// batched operator, Gram-Schmidt and norm launches, and one device-to-host
+// copy of every cell's Hessenberg column; the Givens updates run on the host
+// per cell exactly as in the single-cell driver.
+// ---------------------------------------------------------------------------
+struct p4d_batch {
+    int n = 0;
+    std::vector<p4d_ctx *> cell;
+    std::string err;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    p4d_solve_opts ws_opts{};
+    int ready = 0;                  // workspace carved
+    // device tables
+    BCell *bcell = nullptr;
+    PCell *pcell = nullptr;
+    void *stages = nullptr;
+    int *order = nullptr, *ustart = nullptr;
+    double *hb = nullptr;           // per cell 256 values (h, norms)
+    double *yb = nullptr;           // per cell 64 least-squares coefficients
+    int *kused = nullptr;
+    // pinned host mirrors
+    double *hb_h = nullptr, *yb_h = nullptr;
+    int *kused_h = nullptr;
+    // recorded schedule
+    int recorded = 0, rec_prec = -1;
+    int nstages = 0, nrmax = 8;
+    std::vector<int> dpos, ditem;   // per stage depth: first queue position and first unit (+ end)
+    std::vector<double> pc_bytes;   // per cell: level-0 and particle bytes of one application
+    int pc_mode = 0;                // 0: batched stage launches, 1: per-cell launches
+    Prof prof;
+};
+
+static p4d_status bfail(p4d_batch *B, p4d_status s, const std::string &msg)
+{
+    if (B) B->err = msg;
+    return s;
+}
+#define BHIPCHK(B, call)                                                              \
+    do {                                                                              \
+        hipError_t _e = (call);                                                       \
+        if (_e != hipSuccess)                                                         \
+            return bfail((B), P4D_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+static size_t batch_carve(p4d_batch *B, const p4d_solve_opts &o, char *base, p4d_status *st)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    };
+    *st = P4D_OK;
+    for (int i = 0; i < B->n; i++) {
+        p4d_ctx *c = B->cell[i];
+        p4d_ctx probe;
+        probe.desc = c->desc;
+        probe.g = c->g;
+        const size_t need = carve(&probe, o, nullptr);
+        char *p = take(need);
+        if (base) {
+            c->ws = p;
+            c->ws_bytes = need;
+            c->uploaded = 0;
+            c->pc_ready = 0;
+            const p4d_status s = ensure_layout(c, o);
+            if (s != P4D_OK) {
+                *st = s;
+                B->err = "cell " + std::to_string(i) + ": " + c->err;
+            }
+        }
+    }
+    const size_t maxst = (size_t)B->n * kMaxStagesPerCell;
+    static_assert(sizeof(PStage<double>) >= sizeof(PStage<float>), "stage size");
+    B->bcell = (BCell *)take(sizeof(BCell) * B->n);
+    B->pcell = (PCell *)take(sizeof(PCell) * B->n);
+    B->stages = take(sizeof(PStage<double>) * maxst);
+    B->order = (int *)take(4 * maxst);
+    B->ustart = (int *)take(4 * maxst);
+    B->hb = (double *)take(8 * 256 * (size_t)B->n);
+    B->yb = (double *)take(8 * 64 * (size_t)B->n);
+    B->kused = (int *)take(4 * (size_t)B->n);
+    return off;
+}
+
+template <typename T>
+static double stage_bytes(const PStage<T> &S, const Geom &g)
+{
+    double bytes = 0.0;
+    switch (S.kind) {
+    case SK_RADF:
+        return 8.0 * g.N + 32.0 * g.ne + (sizeof(T) * 2 + 8.0) * g.Nm;
+    case SK_RADB:
+        return 8.0 * (g.N - g.Nm) + 8.0 * g.ne + 8.0 * g.Nm + 8.0 * g.N + 40.0 * g.ne;
+    case SK_SM0:
+        for (int q = 0; q < S.u.lb.nbox; q++) {
+            const LevelArgs<T> &A = S.u.lb.a[q];
+            bytes += (16.0 + 8.0 + sizeof(T) * (3 + (A.c1 != 0.0 && !A.din_x) + (A.dout != nullptr))) * A.n;
+        }
+        return bytes;
+    case SK_SM0R:
+        for (int q = 0; q < S.u.lb.nbox; q++) bytes += (8.0 + 8.0 + sizeof(T) * 3) * S.u.lb.a[q].n;
+        return bytes;
+    default:
+        return 0.0;   // coarse levels: not counted
+    }
+}
+
+// Records every cell's preconditioner schedule and builds the work lists:
+// one per stage depth d (stage d of every cell that has one, larger cells
+// first), stored one after the other.
+template <typename T>
+static p4d_status batch_record(p4d_batch *B)
+{
+    const int n = B->n;
+    std::vector<std::vector<PStage<T>>> per(n);
+    B->pc_bytes.assign(n, 0.0);
+    B->nrmax = 8;
+    for (int i = 0; i < n; i++) {
+        p4d_ctx *c = B->cell[i];
+        c->rec = &per[i];
+        c->rec_cell = i;
+        apply_pc_t<T, double>(c, 0, nullptr, 0.0, (double *)nullptr, nullptr);
+        c->rec = nullptr;
+        if ((int)per[i].size() > kMaxStagesPerCell)
+            return bfail(B, P4D_ERR_INVALID_ARG, "too many preconditioner stages in a cell");
+        for (const PStage<T> &S : per[i]) B->pc_bytes[i] += stage_bytes(S, c->g);
+        const int nr = rad_nrmax(c->g);
+        B->nrmax = nr > B->nrmax ? nr : B->nrmax;
+    }
+    std::vector<PStage<T>> all;
+    std::vector<int> base(n);
+    size_t depth = 0;
+    for (int i = 0; i < n; i++) {
+        base[i] = (int)all.size();
+        all.insert(all.end(), per[i].begin(), per[i].end());
+        depth = per[i].size() > depth ? per[i].size() : depth;
+    }
+    std::vector<int> bysize(n);
+    for (int i = 0; i < n; i++) bysize[i] = i;
+    std::stable_sort(bysize.begin(), bysize.end(),
+                     [&](int a, int b) { return B->cell[a]->g.N > B->cell[b]->g.N; });
+    std::vector<int> order, ustart;
+    B->dpos.clear();
+    B->ditem.clear();
+    long long items = 0;
+    for (size_t d = 0; d < depth; d++) {
+        B->dpos.push_back((int)order.size());
+        B->ditem.push_back((int)items);
+        for (int i : bysize)
+            if (d < per[i].size()) {
+                order.push_back(base[i] + (int)d);
+                ustart.push_back((int)items);
+                items += per[i][d].nunits;
+            }
+        if (items >= (1LL << 31) - (1LL << 20)) return bfail(B, P4D_ERR_INVALID_ARG, "work list too long");
+    }
+    B->dpos.push_back((int)order.size());
+    B->ditem.push_back((int)items);
+    BHIPCHK(B, hipMemcpy(B->stages, all.data(), sizeof(PStage<T>) * all.size(), hipMemcpyHostToDevice));
+    BHIPCHK(B, hipMemcpy(B->order, order.data(), 4 * order.size(), hipMemcpyHostToDevice));
+    BHIPCHK(B, hipMemcpy(B->ustart, ustart.data(), 4 * ustart.size(), hipMemcpyHostToDevice));
+    B->nstages = (int)all.size();
+    B->recorded = 1;
+    B->rec_prec = B->cell[0]->prec;
+    return P4D_OK;
+}
+
+namespace {
+struct CellRun {
+    std::vector<double> H, cs, sn, gv, yv, hc, beta;
+    double bnorm = 0.0;
+    int total = 0, kused = 0;
+    bool done = false, first = true, in_cycle = false, breakdown = false, nonfinite = false;
+    p4d_status status = P4D_NOT_CONVERGED;
+    p4d_solve_info inf{};
+};
+}  // namespace
+
+template <typename T, typename TZ>
+static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const *bv,
+                               double *const *xv, const p4d_solve_opts &o, p4d_solve_info *infos,
+                               hipStream_t st)
+{
+    const int n = B->n, m = o.restart;
+    auto t0 = std::chrono::steady_clock::now();
+    // cell tables for this solve
+    std::vector<BCell> bc(n);
+    std::vector<PCell> pcl(n);
+    int opb = 0, stb = 0;
+    for (int i = 0; i < n; i++) {
+        p4d_ctx *c = B->cell[i];
+        const Geom &g = c->g;
+        BCell &C = bc[i];
+        std::memset((void *)&C, 0, sizeof(C));
+        C.g = g;
+        C.op = OpArgs{c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, nullptr, nullptr, nullptr};
+        C.op_blk0 = opb;
+        C.op_nblk = operator_blocks(g);
+        opb += C.op_nblk;
+        C.st_blk0 = stb;
+        C.st_nblk = stream_blocks(g.N);
+        stb += C.st_nblk;
+        C.V = (double *)c->scratch;
+        C.Z = c->scratch + align_up(8 * (size_t)(m + 1) * g.N);
+        C.x = xv[i];
+        C.b = bv[i];
+        C.red = c->red;
+        C.h = B->hb + 256 * (size_t)i;
+        C.coef = c->cdev;
+        C.invbeta = c->invbeta;
+        C.y = B->yb + 64 * (size_t)i;
+        C.kused = B->kused + i;
+        PCell &P = pcl[i];
+        std::memset((void *)&P, 0, sizeof(P));
+        P.g = g;
+        P.R = c->rec_R;
+        P.V = C.V;
+        P.Z = C.Z;
+        P.invbeta = c->invbeta;
+        P.schur = c->pc.pc == P4D_PC_SCHUR;
+    }
+    BHIPCHK(B, hipStreamSynchronize(st));
+    BHIPCHK(B, hipMemcpy(B->bcell, bc.data(), sizeof(BCell) * n, hipMemcpyHostToDevice));
+    BHIPCHK(B, hipMemcpy(B->pcell, pcl.data(), sizeof(PCell) * n, hipMemcpyHostToDevice));
+
+    std::vector<CellRun> S(n);
+    for (auto &R : S) {
+        R.H.assign((size_t)(m + 1) * m, 0.0);
+        R.cs.assign(m, 0.0); R.sn.assign(m, 0.0); R.gv.assign(m + 1, 0.0);
+        R.yv.assign(m, 0.0); R.hc.assign(m + 2, 0.0); R.beta.assign(m + 1, 0.0);
+    }
+    const size_t hcopy = 8 * 256 * (size_t)n;
+    auto fetch = [&]() -> p4d_status {
+        BHIPCHK(B, hipMemcpyAsync(B->hb_h, B->hb, hcopy, hipMemcpyDeviceToHost, st));
+        BHIPCHK(B, hipStreamSynchronize(st));
+        prof_harvest(B->prof);
+        return P4D_OK;
+    };
+    auto sum_n = [&](unsigned long long mk, double per_cell_factor, bool stream_len) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++)
+            if ((mk >> i) & 1ULL) s += per_cell_factor * (stream_len ? (double)B->cell[i]->g.N : 1.0);
+        return s;
+    };
+    const unsigned long long all = n == 64 ? ~0ULL : ((1ULL << n) - 1);
+    p4d_status ps;
+    // ||b||, x = 0, V_0 = b
+    launch_bstart(B->bcell, n, stb, st);
+    launch_bnorm_final(B->bcell, n, all, 0, 0, st);
+    if ((ps = fetch()) != P4D_OK) return ps;
+    for (int i = 0; i < n; i++) {
+        CellRun &R = S[i];
+        R.bnorm = B->hb_h[256 * i + 128];
+        if (!std::isfinite(R.bnorm)) { R.status = P4D_ERR_NONFINITE; R.done = true; }
+        else if (R.bnorm == 0.0) { R.status = P4D_OK; R.done = true; }
+    }
+    for (;;) {
+        // true residual of the cells that finished a cycle: V_0 = b - A x
+        unsigned long long rmask = 0;
+        for (int i = 0; i < n; i++)
+            if (!S[i].done && !S[i].first) rmask |= 1ULL << i;
+        if (rmask) {
+            {
+                double bytes = 0.0;
+                for (int i = 0; i < n; i++)
+                    if ((rmask >> i) & 1ULL) {
+                        const Geom &g = B->cell[i]->g;
+                        bytes += 24.0 * g.N + 16.0 * g.nelem + 32.0 * g.ne;
+                    }
+                ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
+                launch_bop<double>(B->bcell, n, rmask, 0, 1, transpose, opb, st);
+            }
+            launch_bnorm_final(B->bcell, n, rmask, 0, 1, st);
+            if ((ps = fetch()) != P4D_OK) return ps;
+        }
+        unsigned long long act = 0;
+        for (int i = 0; i < n; i++) {
+            CellRun &R = S[i];
+            if (R.done) continue;
+            const double beta0 = R.first ? R.bnorm : B->hb_h[256 * i + 128];
+            R.first = false;
+            R.inf.relres_true = beta0 / R.bnorm;
+            if (R.breakdown) {
+                R.status = R.inf.relres_true <= o.rtol ? P4D_OK : P4D_BREAKDOWN;
+                R.done = true;
+                continue;
+            }
+            if (!std::isfinite(beta0)) { R.status = P4D_ERR_NONFINITE; R.done = true; continue; }
+            if (beta0 <= o.rtol * R.bnorm) { R.status = P4D_OK; R.done = true; continue; }
+            if (R.total >= o.maxit) { R.status = P4D_NOT_CONVERGED; R.done = true; continue; }
+            std::fill(R.gv.begin(), R.gv.end(), 0.0);
+            R.gv[0] = beta0;
+            R.beta[0] = beta0;
+            R.kused = 0;
+            R.in_cycle = true;
+            act |= 1ULL << i;
+        }
+        if (!act) break;
+        const unsigned long long cyc = act;
+        for (int k = 0; k < m && act; k++) {
+            {
+                double bytes = 0.0;
+                for (int i = 0; i < n; i++)
+                    if ((act >> i) & 1ULL) bytes += B->pc_bytes[i];
+                ProfScope pr(B->prof, P4D_K_BATCH_PC, bytes, st);
+                if (B->pc_mode == 0) {
+                    StageRun run{};
+                    run.stages = B->stages;
+                    run.cells = B->pcell;
+                    run.order = B->order;
+                    run.ustart = B->ustart;
+                    run.transpose = transpose;
+                    run.k = k;
+                    run.active = act;
+                    for (size_t d = 0; d + 1 < B->dpos.size(); d++) {
+                        run.pos0 = B->dpos[d];
+                        run.npos = B->dpos[d + 1] - B->dpos[d];
+                        run.item0 = B->ditem[d];
+                        run.nitems = B->ditem[d + 1] - B->ditem[d];
+                        launch_batch_stage<T, TZ>(run, B->nrmax, st);
+                    }
+                } else {
+                    for (int i = 0; i < n; i++)
+                        if ((act >> i) & 1ULL) {
+                            p4d_ctx *c = B->cell[i];
+                            apply_pc_t<T, TZ>(c, transpose, bc[i].V + (long long)k * c->g.N,
+                                              1.0 / S[i].beta[k],
+                                              (TZ *)bc[i].Z + (long long)k * c->g.N, st);
+                        }
+                }
+            }
+            {
+                double bytes = 0.0;
+                for (int i = 0; i < n; i++)
+                    if ((act >> i) & 1ULL) {
+                        const Geom &g = B->cell[i]->g;
+                        bytes += (sizeof(TZ) + 8.0) * g.N + 16.0 * g.nelem + 32.0 * g.ne;
+                    }
+                ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
+                launch_bop<TZ>(B->bcell, n, act, k, 0, transpose, opb, st);
+            }
+            const int nv = k + 1;
+            const int passes = o.cgs2 ? 2 : 1;
+            for (int p = 0; p < passes; p++) {
+                {
+                    ProfScope pr(B->prof, P4D_K_MDOT, sum_n(act, 8.0 * (nv + 1), true), st);
+                    launch_bmdot(B->bcell, n, act, k, stb, p, st);
+                }
+                ProfScope pr(B->prof, P4D_K_ORTH, sum_n(act, 8.0 * (nv + 2), true), st);
+                launch_borth(B->bcell, n, act, k, stb, st);
+            }
+            launch_bnorm_final(B->bcell, n, act, k + 1, 0, st);
+            if ((ps = fetch()) != P4D_OK) return ps;
+            for (int i = 0; i < n; i++) {
+                if (!((act >> i) & 1ULL)) continue;
+                CellRun &R = S[i];
+                const double *hh = B->hb_h + 256 * (size_t)i;
+                std::vector<double> &hc = R.hc;
+                for (int q = 0; q <= k; q++) hc[q] = hh[q] + (o.cgs2 ? hh[64 + q] : 0.0);
+                const double hn = hh[128];
+                hc[k + 1] = hn;
+                double colnorm = 0.0;
+                for (int q = 0; q <= k + 1; q++) colnorm += hc[q] * hc[q];
+                colnorm = std::sqrt(colnorm);
+                if (!std::isfinite(colnorm)) {
+                    R.nonfinite = true;
+                    act &= ~(1ULL << i);
+                    continue;
+                }
+                for (int q = 0; q < k; q++) {
+                    const double t = R.cs[q] * hc[q] + R.sn[q] * hc[q + 1];
+                    hc[q + 1] = -R.sn[q] * hc[q] + R.cs[q] * hc[q + 1];
+                    hc[q] = t;
+                }
+                const double den = std::sqrt(hc[k] * hc[k] + hc[k + 1] * hc[k + 1]);
+                R.cs[k] = hc[k] / den;
+                R.sn[k] = hc[k + 1] / den;
+                hc[k] = den;
+                R.gv[k + 1] = -R.sn[k] * R.gv[k];
+                R.gv[k] = R.cs[k] * R.gv[k];
+                for (int q = 0; q <= k; q++) R.H[(size_t)q * m + k] = hc[q];
+                R.total++;
+                R.kused = k + 1;
+                R.beta[k + 1] = hn;
+                R.inf.relres_est = std::fabs(R.gv[k + 1]) / R.bnorm;
+                if (hn <= 1e-14 * colnorm) {
+                    R.breakdown = true;
+                    act &= ~(1ULL << i);
+                } else if (std::fabs(R.gv[k + 1]) <= o.rtol * R.bnorm || R.total >= o.maxit) {
+                    act &= ~(1ULL << i);
+                }
+            }
+        }
+        // x += Z y for the cells of this cycle
+        unsigned long long zmask = 0;
+        int kmax = 1;
+        for (int i = 0; i < n; i++) {
+            if (!((cyc >> i) & 1ULL)) continue;
+            CellRun &R = S[i];
+            R.in_cycle = false;
+            if (R.nonfinite) {
+                R.status = P4D_ERR_NONFINITE;
+                R.done = true;
+                continue;
+            }
+            const int ku = R.kused;
+            for (int q = ku - 1; q >= 0; q--) {
+                double v = R.gv[q];
+                for (int j = q + 1; j < ku; j++) v -= R.H[(size_t)q * m + j] * R.yv[j];
+                R.yv[q] = v / R.H[(size_t)q * m + q];
+            }
+            for (int q = 0; q < 64; q++) B->yb_h[64 * i + q] = q < ku ? R.yv[q] : 0.0;
+            B->kused_h[i] = ku;
+            kmax = ku > kmax ? ku : kmax;
+            R.inf.restarts++;
+            zmask |= 1ULL << i;
+        }
+        if (zmask) {
+            // the previous copies from these staging buffers have completed:
+            // every step synchronizes the stream
+            BHIPCHK(B, hipMemcpyAsync(B->yb, B->yb_h, 8 * 64 * (size_t)n, hipMemcpyHostToDevice, st));
+            BHIPCHK(B, hipMemcpyAsync(B->kused, B->kused_h, 4 * (size_t)n, hipMemcpyHostToDevice, st));
+            double bytes = 0.0;
+            for (int i = 0; i < n; i++)
+                if ((zmask >> i) & 1ULL) bytes += (16.0 + sizeof(TZ) * S[i].kused) * B->cell[i]->g.N;
+            ProfScope pr(B->prof, P4D_K_ZY, bytes, st);
+            launch_bzy<TZ>(B->bcell, n, zmask, kmax, stb, st);
+        }
+    }
+    BHIPCHK(B, hipGetLastError());
+    BHIPCHK(B, hipStreamSynchronize(st));
+    prof_harvest(B->prof);
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    p4d_status overall = P4D_OK;
+    for (int i = 0; i < n; i++) {
+        CellRun &R = S[i];
+        R.inf.iters = R.total;
+        R.inf.status = R.status;
+        R.inf.t_solve_ms = ms;
+        if (infos) infos[i] = R.inf;
+        if (R.status != P4D_OK && overall == P4D_OK) overall = R.status;
+    }
+    if (overall != P4D_OK) B->err = std::string("a cell ended with: ") + p4d_status_string(overall);
+    return overall;
+}
+
+extern "C" {
+
+p4d_status p4d_autotune(p4d_ctx *c, void *stream, int32_t tile[2])
+{
+    if (!c) return P4D_ERR_INVALID_ARG;
+    if (!c->pc_ready) return fail(c, P4D_ERR_STATE, "p4d_setup first");
+    const p4d_status s = tune_tiles(c, (hipStream_t)stream);
+    if (tile) {
+        tile[0] = c->tile_tx;
+        tile[1] = c->tile_cz;
+    }
+    return s;
+}
+
+p4d_status p4d_batch_create(const p4d_problem_desc *descs, int32_t ncells, p4d_batch **out)
+{
+    if (!descs || !out || ncells < 1 || ncells > kMaxBatch) return P4D_ERR_INVALID_ARG;
+    *out = nullptr;
+    p4d_batch *B = new p4d_batch();
+    B->n = ncells;
+    for (int i = 0; i < ncells; i++) {
+        p4d_ctx *c = nullptr;
+        const p4d_status s = p4d_create(&descs[i], &c);
+        if (s != P4D_OK) {
+            for (p4d_ctx *q : B->cell) p4d_destroy(q);
+            delete B;
+            return s;
+        }
+        B->cell.push_back(c);
+    }
+    if (hipHostMalloc((void **)&B->hb_h, 8 * (256 * (size_t)ncells + 1), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&B->yb_h, 8 * 64 * (size_t)ncells, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&B->kused_h, 4 * (size_t)ncells, hipHostMallocDefault) != hipSuccess) {
+        if (B->hb_h) hipHostFree(B->hb_h);
+        if (B->yb_h) hipHostFree(B->yb_h);
+        for (p4d_ctx *q : B->cell) p4d_destroy(q);
+        delete B;
+        return P4D_ERR_HIP;
+    }
+    prof_init(B->prof);
+    p4d_default_opts(&B->ws_opts);
+    *out = B;
+    return P4D_OK;
+}
+
+void p4d_batch_destroy(p4d_batch *B)
+{
+    if (!B) return;
+    for (p4d_ctx *c : B->cell) p4d_destroy(c);
+    if (B->hb_h) hipHostFree(B->hb_h);
+    if (B->yb_h) hipHostFree(B->yb_h);
+    if (B->kused_h) hipHostFree(B->kused_h);
+    prof_free(B->prof);
+    delete B;
+}
+
+p4d_status p4d_batch_cell(p4d_batch *B, int32_t cell, p4d_ctx **out)
+{
+    if (!B || !out || cell < 0 || cell >= B->n) return P4D_ERR_INVALID_ARG;
+    *out = B->cell[cell];
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_workspace_size(const p4d_batch *Bc, const p4d_solve_opts *opts, size_t *bytes)
+{
+    if (!Bc || !bytes) return P4D_ERR_INVALID_ARG;
+    p4d_batch *B = const_cast<p4d_batch *>(Bc);
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return bfail(B, P4D_ERR_INVALID_ARG, why);
+    p4d_status s;
+    // sizing only: no pointer of the batch or its cells changes
+    p4d_batch probe;
+    probe.n = B->n;
+    probe.cell = B->cell;
+    *bytes = batch_carve(&probe, o, nullptr, &s) + kAlign;
+    probe.cell.clear();
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_set_workspace(p4d_batch *B, void *d_work, size_t bytes, const p4d_solve_opts *opts)
+{
+    if (!B || !d_work) return P4D_ERR_INVALID_ARG;
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return bfail(B, P4D_ERR_INVALID_ARG, why);
+    char *base = (char *)align_up((size_t)d_work);
+    p4d_status s;
+    p4d_batch probe;
+    probe.n = B->n;
+    probe.cell = B->cell;
+    const size_t need = batch_carve(&probe, o, nullptr, &s);
+    probe.cell.clear();
+    if (need + (size_t)(base - (char *)d_work) > bytes)
+        return bfail(B, P4D_ERR_OOM, "workspace too small for these options");
+    B->ws = (char *)d_work;
+    B->ws_bytes = bytes;
+    B->ready = 0;
+    B->recorded = 0;
+    batch_carve(B, o, base, &s);
+    if (s != P4D_OK) return s;
+    B->ws_opts = o;
+    B->ready = 1;
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_upload(p4d_batch *B, int32_t cell, const double *sigma, const double *kappa,
+                            const double *g, const double *s, const double *e, void *stream)
+{
+    if (!B || cell < 0 || cell >= B->n) return P4D_ERR_INVALID_ARG;
+    if (!B->ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_set_workspace first");
+    const p4d_status st = p4d_upload(B->cell[cell], sigma, kappa, g, s, e, stream);
+    if (st != P4D_OK) B->err = "cell " + std::to_string(cell) + ": " + B->cell[cell]->err;
+    B->recorded = 0;
+    return st;
+}
+
+p4d_status p4d_batch_setup(p4d_batch *B, const p4d_solve_opts *opts, void *stream)
+{
+    if (!B) return P4D_ERR_INVALID_ARG;
+    if (!B->ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_set_workspace first");
+    p4d_solve_opts o = B->ws_opts;
+    if (opts) o = *opts;
+    if (o.pc_prec != B->ws_opts.pc_prec || o.coarse_max != B->ws_opts.coarse_max ||
+        o.restart > B->ws_opts.restart || (!o.z_fp32 && B->ws_opts.z_fp32))
+        return bfail(B, P4D_ERR_STATE, "options differ from those the workspace was carved for");
+    B->recorded = 0;
+    for (int i = 0; i < B->n; i++) {
+        const p4d_status s = p4d_setup(B->cell[i], &o, stream);
+        if (s != P4D_OK) return bfail(B, s, "cell " + std::to_string(i) + ": " + B->cell[i]->err);
+    }
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_autotune(p4d_batch *B, void *stream, int32_t *tiles)
+{
+    if (!B) return P4D_ERR_INVALID_ARG;
+    for (int i = 0; i < B->n; i++)
+        if (!B->cell[i]->pc_ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_setup first");
+    // one timing per distinct level-0 geometry
+    for (int i = 0; i < B->n; i++) {
+        p4d_ctx *c = B->cell[i];
+        int same = -1;
+        for (int j = 0; j < i && same < 0; j++) {
+            const Geom &a = B->cell[j]->g, &b = c->g;
+            if (a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.na == b.na && a.ns == b.ns) same = j;
+        }
+        if (same >= 0) {
+            c->tile_tx = B->cell[same]->tile_tx;
+            c->tile_cz = B->cell[same]->tile_cz;
+        } else {
+            const p4d_status s = tune_tiles(c, (hipStream_t)stream);
+            if (s != P4D_OK) return bfail(B, s, "cell " + std::to_string(i) + ": " + c->err);
+        }
+        if (tiles) {
+            tiles[2 * i] = c->tile_tx;
+            tiles[2 * i + 1] = c->tile_cz;
+        }
+    }
+    B->recorded = 0;
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_solve(p4d_batch *B, const double *const *d_b, double *const *d_x,
+                           const p4d_solve_opts *opts, p4d_solve_info *infos, void *stream)
+{
+    if (!B || !d_b || !d_x) return P4D_ERR_INVALID_ARG;
+    for (int i = 0; i < B->n; i++)
+        if (!d_b[i] || !d_x[i] || d_b[i] == d_x[i]) return bfail(B, P4D_ERR_INVALID_ARG, "null or aliased vectors");
+    if (!B->ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_set_workspace first");
+    p4d_ctx *c0 = B->cell[0];
+    for (int i = 0; i < B->n; i++)
+        if (!B->cell[i]->pc_ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_setup first");
+    p4d_solve_opts o = opts ? *opts : c0->pc;
+    std::string why;
+    if (!opts_valid(o, why)) return bfail(B, P4D_ERR_INVALID_ARG, why);
+    for (int i = 0; i < B->n; i++) {
+        const p4d_ctx *c = B->cell[i];
+        if (o.pc != c->pc.pc || o.pc_prec != c->pc.pc_prec || o.cheb_degree != c->pc.cheb_degree ||
+            o.coarse_max != c->pc.coarse_max)
+            return bfail(B, P4D_ERR_STATE, "preconditioner options differ from the last setup");
+        if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
+            return bfail(B, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (!B->recorded || B->rec_prec != c0->prec) {
+        const p4d_status s = c0->prec ? batch_record<float>(B) : batch_record<double>(B);
+        if (s != P4D_OK) return s;
+    }
+    if (c0->prec) {
+        if (o.z_fp32) return batch_fgmres<float, float>(B, 0, d_b, d_x, o, infos, st);
+        return batch_fgmres<float, double>(B, 0, d_b, d_x, o, infos, st);
+    }
+    if (o.z_fp32) return batch_fgmres<double, float>(B, 0, d_b, d_x, o, infos, st);
+    return batch_fgmres<double, double>(B, 0, d_b, d_x, o, infos, st);
+}
+
+p4d_status p4d_batch_set_pc_mode(p4d_batch *B, int32_t mode)
+{
+    if (!B || (mode != 0 && mode != 1)) return P4D_ERR_INVALID_ARG;
+    B->pc_mode = mode;
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_profile(p4d_batch *B, int mask)
+{
+    if (!B || mask < 0 || mask >= (1 << P4D_K_COUNT)) return P4D_ERR_INVALID_ARG;
+    prof_reset(B->prof, mask);
+    return P4D_OK;
+}
+
+p4d_status p4d_batch_profile_read(p4d_batch *B, int cls, double *total_ms, int64_t *launches,
+                                  double *bytes)
+{
+    if (!B || cls < 1 || cls >= P4D_K_COUNT) return P4D_ERR_INVALID_ARG;
+    prof_harvest(B->prof);
+    if (total_ms) *total_ms = B->prof.total_ms[cls];
+    if (launches) *launches = B->prof.launches[cls];
+    if (bytes) *bytes = B->prof.total_bytes[cls];
+    return P4D_OK;
+}
+
+const char *p4d_batch_last_error(const p4d_batch *B) { return B ? B->err.c_str() : "null batch"; }
 
 }  // extern "C"

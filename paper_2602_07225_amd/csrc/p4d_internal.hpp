@@ -121,9 +121,11 @@ void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t
 // radial.hip (RadArgs in p4d_kernels.hpp)
 struct RadArgs;
 template <typename T>
-void launch_rad_fwd(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st);
+void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rscale, int transpose,
+                    int schur, hipStream_t st);
 template <typename T, typename TZ>
-void launch_rad_back(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st);
+void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
+                     int transpose, int schur, hipStream_t st);
 int rad_nrmax(const Geom &g);
 
 // mg.hip

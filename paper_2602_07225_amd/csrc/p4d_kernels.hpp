@@ -22,17 +22,26 @@ __device__ inline int coarse_of(int n, int i, int I[2], double w[2])
     I[1] = (i + 1) >> 1; w[1] = 0.5;
     return 2;
 }
-// fine points (and weights) that interpolate from coarse point I
+// fine points (and weights) that interpolate from coarse point I, in the
+// order: the coincident point, its odd left neighbour, its odd right
+// neighbour (selects instead of a running index keep the arrays in registers)
 __device__ inline int fine_of(int n, int I, int f[3], double w[3])
 {
-    if (n <= 2) { f[0] = I; w[0] = 1.0; return 1; }
+    if (n <= 2) {
+        f[0] = f[1] = f[2] = I;
+        w[0] = 1.0; w[1] = w[2] = 0.0;
+        return 1;
+    }
     const int nc = n / 2 + 1;
     const int c = (I == nc - 1) ? n - 1 : 2 * I;
-    int cnt = 0;
-    f[cnt] = c; w[cnt] = 1.0; cnt++;
-    if (c - 1 >= 0 && ((c - 1) & 1) && c - 1 != n - 1) { f[cnt] = c - 1; w[cnt] = 0.5; cnt++; }
-    if (c + 1 <= n - 1 && ((c + 1) & 1) && c + 1 != n - 1) { f[cnt] = c + 1; w[cnt] = 0.5; cnt++; }
-    return cnt;
+    const bool lft = c - 1 >= 0 && ((c - 1) & 1) && c - 1 != n - 1;
+    const bool rgt = c + 1 <= n - 1 && ((c + 1) & 1) && c + 1 != n - 1;
+    f[0] = c; w[0] = 1.0;
+    f[1] = lft ? c - 1 : (rgt ? c + 1 : c);
+    w[1] = (lft || rgt) ? 0.5 : 0.0;
+    f[2] = (lft && rgt) ? c + 1 : c;
+    w[2] = (lft && rgt) ? 0.5 : 0.0;
+    return 1 + (int)lft + (int)rgt;
 }
 
 template <typename B>
@@ -188,14 +197,22 @@ __device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
     const int ni = fine_of(A.fx, I, fi, wi);
     const int nj = fine_of(A.fy, J, fj, wj);
     const int nk = fine_of(A.fz, K, fk, wk);
+    // fixed trip counts, so that the index arrays stay in registers
     double acc = 0.0;
-    for (int c = 0; c < nk; c++)
-        for (int bq = 0; bq < nj; bq++) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        if (c >= nk) break;
+#pragma unroll
+        for (int bq = 0; bq < 3; bq++) {
+            if (bq >= nj) break;
             const long long row = (long long)A.fx * (fj[bq] + (long long)A.fy * fk[c]);
             double part = 0.0;
-            for (int a = 0; a < ni; a++) part += wi[a] * (double)A.rf[row + fi[a]];
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+                if (a < ni) part += wi[a] * (double)A.rf[row + fi[a]];
             acc += wj[bq] * wk[c] * part;
         }
+    }
     const T bc = (T)acc;
     A.bc[n] = bc;
     if (A.xc1) A.xc1[n] = A.c2c * (double)A.invdc[n] * (double)bc;
@@ -216,13 +233,20 @@ __device__ inline void prolong_block(const TransferArgs<T> &A, int blk)
     const int nj = coarse_of(A.fy, j, Cj, wj);
     const int nk = coarse_of(A.fz, k, Ck, wk);
     double acc = 0.0;
-    for (int c = 0; c < nk; c++)
-        for (int bq = 0; bq < nj; bq++) {
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        if (c >= nk) break;
+#pragma unroll
+        for (int bq = 0; bq < 2; bq++) {
+            if (bq >= nj) break;
             const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
             double part = 0.0;
-            for (int a = 0; a < ni; a++) part += wi[a] * A.xc[row + Ci[a]];
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+                if (a < ni) part += wi[a] * A.xc[row + Ci[a]];
             acc += wj[bq] * wk[c] * part;
         }
+    }
     A.xf[n] += acc;
 }
 
@@ -260,28 +284,24 @@ __device__ inline void coarse_block(const CoarseArgs<T> &A, int rowblk, CoarseLd
 struct RadArgs {
     const RadialTab *tabs;
     const double *gg, *ss, *ee, *mm, *om;
-    const double *r;
-    double rscale;
     void *b0;            // T, macro layout
     double *x1;          // first Chebyshev iterate of each box
     const void *invd0;   // T
     double c2box[4];
     const double *x0[4]; // final level-0 iterates per box (rad_back)
-    void *z;             // TZ, output
 };
 
 // zeta_j = (A_ss,j^-1 r_s,j)_N; r~_y = r_y - a_y s_j zeta_j (transposed:
 // r_y - Gamma b_y zeta_j); written in precision T with the first Chebyshev
 // iterate of each box.
 template <typename T, bool TRANS, bool SCHUR>
-__device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, int blk)
+__device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const double *r, double rscale,
+                                     int blk)
 {
     const long long n = (long long)blk * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
     T *b0 = (T *)R.b0;
     const T *invd0 = (const T *)R.invd0;
-    const double *r = R.r;
-    const double rscale = R.rscale;
     const int k = (int)(n / ((long long)g.nx * g.ny));
     double rpe = r[g.off_pe + n] * rscale;
     double rce = r[g.off_ce + n] * rscale;
@@ -335,13 +355,11 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, int blk)
 // sees r_s, while delta_j = Gamma b_y . z_y (transposed s_j a_y . z_y),
 // which carries the large near-null part of z_y, is applied in FP64.
 template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
-__device__ inline void rad_back_block(const Geom &g, const RadArgs &R, int blk)
+__device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const double *r, double rscale,
+                                      TZ *z, int blk)
 {
     const long long n = (long long)blk * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
-    TZ *z = (TZ *)R.z;
-    const double *r = R.r;
-    const double rscale = R.rscale;
     const int k = (int)(n / ((long long)g.nx * g.ny));
     const int el = node_mat(g, k);
     const double zpe = R.x0[2][g.off_pe + n];

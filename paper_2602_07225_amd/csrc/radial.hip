@@ -10,17 +10,18 @@
 namespace p4d {
 
 template <typename T, bool TRANS, bool SCHUR>
-__global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R)
+__global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R, const double *r, double rscale)
 {
-    rad_fwd_block<T, TRANS, SCHUR>(g, R, blockIdx.x);
+    rad_fwd_block<T, TRANS, SCHUR>(g, R, r, rscale, blockIdx.x);
 }
 
 template <typename T>
-void launch_rad_fwd(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st)
+void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rscale, int transpose,
+                    int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
 #define P4D_RF(TR, SC) \
-    hipLaunchKernelGGL((k_rad_fwd<T, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R)
+    hipLaunchKernelGGL((k_rad_fwd<T, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R, r, rscale)
     if (schur) {
         if (transpose) P4D_RF(true, true); else P4D_RF(false, true);
     } else {
@@ -28,13 +29,16 @@ void launch_rad_fwd(const Geom &g, const RadArgs &R, int transpose, int schur, h
     }
 #undef P4D_RF
 }
-template void launch_rad_fwd<double>(const Geom &, const RadArgs &, int, int, hipStream_t);
-template void launch_rad_fwd<float>(const Geom &, const RadArgs &, int, int, hipStream_t);
+template void launch_rad_fwd<double>(const Geom &, const RadArgs &, const double *, double, int, int,
+                                     hipStream_t);
+template void launch_rad_fwd<float>(const Geom &, const RadArgs &, const double *, double, int, int,
+                                    hipStream_t);
 
 template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
-__global__ __launch_bounds__(kBlock) void k_rad_back(Geom g, RadArgs R)
+__global__ __launch_bounds__(kBlock) void k_rad_back(Geom g, RadArgs R, const double *r, double rscale,
+                                                    TZ *z)
 {
-    rad_back_block<T, TZ, NRMAX, TRANS, SCHUR>(g, R, blockIdx.x);
+    rad_back_block<T, TZ, NRMAX, TRANS, SCHUR>(g, R, r, rscale, z, blockIdx.x);
 }
 
 int rad_nrmax(const Geom &g)
@@ -44,11 +48,12 @@ int rad_nrmax(const Geom &g)
 }
 
 template <typename T, typename TZ>
-void launch_rad_back(const Geom &g, const RadArgs &R, int transpose, int schur, hipStream_t st)
+void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
+                     int transpose, int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
 #define P4D_RB(NR, TR, SC) \
-    hipLaunchKernelGGL((k_rad_back<T, TZ, NR, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R)
+    hipLaunchKernelGGL((k_rad_back<T, TZ, NR, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R, r, rscale, z)
 #define P4D_RB2(NR)                                  \
     do {                                             \
         if (schur) {                                 \
@@ -68,9 +73,13 @@ void launch_rad_back(const Geom &g, const RadArgs &R, int transpose, int schur, 
 #undef P4D_RB2
 #undef P4D_RB
 }
-template void launch_rad_back<double, double>(const Geom &, const RadArgs &, int, int, hipStream_t);
-template void launch_rad_back<float, double>(const Geom &, const RadArgs &, int, int, hipStream_t);
-template void launch_rad_back<double, float>(const Geom &, const RadArgs &, int, int, hipStream_t);
-template void launch_rad_back<float, float>(const Geom &, const RadArgs &, int, int, hipStream_t);
+template void launch_rad_back<double, double>(const Geom &, const RadArgs &, const double *, double,
+                                                double *, int, int, hipStream_t);
+template void launch_rad_back<float, double>(const Geom &, const RadArgs &, const double *, double,
+                                                double *, int, int, hipStream_t);
+template void launch_rad_back<double, float>(const Geom &, const RadArgs &, const double *, double,
+                                                float *, int, int, hipStream_t);
+template void launch_rad_back<float, float>(const Geom &, const RadArgs &, const double *, double,
+                                                float *, int, int, hipStream_t);
 
 }  // namespace p4d

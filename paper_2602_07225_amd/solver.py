@@ -102,3 +102,108 @@ class P4DSolver:
             self.close()
         except Exception:
             pass
+
+
+class P4DBatch:
+    """Independent cells of uneven mesh and radial sizes solved together:
+    FGMRES in lockstep; per Arnoldi step, one preconditioner launch per stage
+    depth for all iterating cells (``p4d_batch_*`` in the C ABI).
+
+    ``probs``: objects with the problem description fields and coefficient
+    arrays, one per cell (at most 64)."""
+
+    def __init__(self, probs, restart: int = 30, z_fp32: bool = False,
+                 pc_prec: int = L.P4D_FP32, coarse_max: int = 64, device: str = "cuda"):
+        self.device = torch.device(device)
+        self.n = len(probs)
+        self.descs = [L.desc_from(p) for p in probs]
+        self.batch = L.p4d_batch_create(self.descs)
+        self.cells = [L.p4d_batch_cell(self.batch, i) for i in range(self.n)]
+        sizes = [L.p4d_vector_size(c) for c in self.cells]
+        self.N = [s[0] for s in sizes]
+        self.n_elem = [s[2] for s in sizes]
+        self.n_e = [s[3] for s in sizes]
+        self.ws_opts = L.default_opts(restart=restart, z_fp32=int(z_fp32), pc_prec=pc_prec,
+                                      coarse_max=coarse_max)
+        nbytes = L.p4d_batch_workspace_size(self.batch, self.ws_opts)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        L.p4d_batch_set_workspace(self.batch, self.ws.data_ptr(), nbytes, self.ws_opts)
+        for i, p in enumerate(probs):
+            self.upload(i, p.sigma, p.kappa, p.g, p.s, p.e)
+        self.opts = None
+
+    def _dev(self, a):
+        if isinstance(a, torch.Tensor):
+            return a.to(self.device, torch.float64).contiguous()
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    def upload(self, i, sigma, kappa, g, s, e):
+        arrs = [self._dev(a) for a in (sigma, kappa, g, s, e)]
+        assert arrs[0].numel() == self.n_elem[i] and arrs[1].numel() == self.n_elem[i]
+        assert all(a.numel() == self.n_e[i] for a in arrs[2:])
+        L.p4d_batch_upload(self.batch, i, *arrs)
+        torch.cuda.current_stream().synchronize()
+        self.opts = None
+
+    def setup(self, **kw):
+        o = L.SolveOpts.from_buffer_copy(self.ws_opts)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        L.p4d_batch_setup(self.batch, o)
+        self.opts = o
+        return self
+
+    def autotune(self):
+        """Level-0 smoother tiles per distinct cell geometry: [(TX, CZ)] per cell."""
+        return L.p4d_batch_autotune(self.batch, self.n)
+
+    def _opts(self, kw):
+        if self.opts is None:
+            raise RuntimeError("call setup() first")
+        o = L.SolveOpts.from_buffer_copy(self.opts)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def solve(self, bs, **kw):
+        """x_i = A_i^-1 b_i for all cells; returns (list of x, list of SolveInfo)."""
+        bs = [self._dev(b) for b in bs]
+        assert len(bs) == self.n and all(b.numel() == n for b, n in zip(bs, self.N))
+        xs = [torch.empty_like(b) for b in bs]
+        _, infos = L.p4d_batch_solve(self.batch, bs, xs, self._opts(kw))
+        return xs, infos
+
+    def solve_cell(self, i, b, **kw):
+        """The same cell solved alone (single-cell driver on the cell's context)."""
+        b = self._dev(b)
+        x = torch.empty_like(b)
+        _, info = L.p4d_solve(self.cells[i], b, x, self._opts(kw))
+        return x, info
+
+    def apply(self, i, x):
+        x = self._dev(x)
+        y = torch.empty_like(x)
+        L.p4d_apply_operator(self.cells[i], 0, x, y)
+        return y
+
+    def set_pc_mode(self, mode: int):
+        """0: batched stage launches (default); 1: per-cell launches."""
+        L.p4d_batch_set_pc_mode(self.batch, mode)
+
+    def profile(self, class_mask: int):
+        L.p4d_batch_profile(self.batch, class_mask)
+
+    def profile_read(self, kernel_class: int):
+        return L.p4d_batch_profile_read(self.batch, kernel_class)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            torch.cuda.synchronize()
+            L.p4d_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
