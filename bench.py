@@ -10,9 +10,9 @@ inputs already resident in device memory.
 
 Prints one JSON line: the metric is DOF*iter/s = N * iterations / step time.
 Extra fields report the FP32-preconditioned solve on the same input and on the
-lognormal-conductivity cube, the adjoint solve with gradients, per-kernel
-times and bandwidths measured with HIP events inside the timed region, and the
-CPU oracle timed on the host.
+lognormal-conductivity cube, the adjoint solve with gradients, the batched
+solve of 64 uneven cells, per-kernel times and bandwidths measured with HIP
+events inside the timed region, and the CPU oracle timed on the host.
 """
 import argparse
 import json
@@ -59,6 +59,62 @@ def timed_steps(s, b, opts, steps, warmup, profile_mask=0):
                               "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
         L.p4d_profile(s.ctx, 0)
     return x, info, iters, t, prof
+
+
+def bench_batch(steps):
+    """64 independent cells of uneven size (sides 16..48, N_r in {8, 16, 32}),
+    FP32 preconditioner with autotuned smoother tiles, FGMRES(30) to 1e-8 in
+    lockstep.  Solve time per batch with the batched stage launches and with
+    per-cell launches of the same kernels; setup timed separately."""
+    import torch
+    import p4d_inputs as pi
+    from paper_2602_07225_amd import P4DBatch
+    from paper_2602_07225_amd import _lib as L
+    cells = pi.make_batch(64)
+    ntot = sum(p.N for p in cells)
+    log(f"[bench] C4: {len(cells)} cells, {ntot} DOF")
+    B = P4DBatch(cells, pc_prec=L.P4D_FP32)
+    bs = [torch.as_tensor(p.b, device="cuda") for p in cells]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.setup(rtol=1e-8)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    tiles = B.autotune()
+    out = {"cells": len(cells), "dof_total": ntot, "setup_ms": 1e3 * t_setup,
+           "tiles": sorted(set(tiles))}
+    for mode, name in ((0, "batched_stage_launches"), (1, "per_cell_launches")):
+        B.set_pc_mode(mode)
+        B.solve(bs)
+        torch.cuda.synchronize()
+        if mode == 0:
+            B.profile(sum(1 << k for k in L.KERNEL_CLASSES))
+        t0 = time.perf_counter()
+        dof_it = 0
+        for _ in range(steps):
+            _, infos = B.solve(bs)
+            dof_it += sum(p.N * i.iters for p, i in zip(cells, infos))
+            if any(i.status != 0 for i in infos):
+                raise RuntimeError("a batched cell did not converge")
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"solve_ms": 1e3 * t / steps, "DOF_iter_per_s": dof_it / t,
+                     "iters_min_max": [min(i.iters for i in infos), max(i.iters for i in infos)]}
+        if mode == 0:
+            kern = {}
+            for k, kn in L.KERNEL_CLASSES.items():
+                ms, n, by = B.profile_read(k)
+                if n:
+                    kern[kn] = {"ms_total": ms, "launch_groups": n, "avg_us": 1e3 * ms / n,
+                                "GBps": (by / 1e9) / (ms / 1e3) if ms > 0 else None}
+            out[name]["kernels"] = kern
+            B.profile(0)
+        log(f"[bench] C4 {name}: {1e3 * t / steps:.1f} ms/solve, {dof_it / t:.3e} DOF*iter/s")
+    B.set_pc_mode(0)
+    out["speedup_batched_vs_per_cell"] = (out["per_cell_launches"]["solve_ms"] /
+                                          out["batched_stage_launches"]["solve_ms"])
+    B.close()
+    return out
 
 
 def main():
@@ -178,6 +234,9 @@ def main():
         log(f"[bench] C5: forward {1e3 * (t1 - t0):.1f} ms ({f5.iters} it), adjoint+grad "
             f"{1e3 * (t2 - t1):.1f} ms ({a5.iters} it)")
         del s5, x5, l5, g5
+
+    if not args.no_extras:
+        extras["C4_batch_64_cells"] = bench_batch(args.steps)
 
     cpu = None
     if not args.no_cpu:

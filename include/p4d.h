@@ -207,8 +207,9 @@ const char *p4d_last_error(const p4d_ctx *ctx);
 
 /* Level-0 smoother tile autotuning: times one Chebyshev step over the four
  * multigrid boxes for each tile shape TX x (256/TX) nodes by CZ layers,
- * TX in {16, 32, 64}, CZ in {4, 8, 16}, and keeps the fastest for this
- * context.  Needs p4d_setup; synchronizes `stream`; only preconditioner
+ * TX in {16, 32, 64}, 2 <= CZ <= 16, and keeps the fastest for this context
+ * (without it, CZ is chosen from the grid and the number of resident
+ * workgroups).  Needs p4d_setup; synchronizes `stream`; only preconditioner
  * buffers are written.  tile (host, may be NULL) receives {TX, CZ}.        */
 p4d_status p4d_autotune(p4d_ctx *ctx, void *stream, int32_t tile[2]);
 

@@ -48,10 +48,10 @@ __device__ inline void run_unit(const PStage<T> &S, const PCell &C, int k, int t
         const double *r = C.V + (long long)k * g.N;
         const double rs = C.invbeta[k];
         if (C.schur) {
-            if (transpose) rad_fwd_block<T, true, true>(g, C.R, r, rs, unit);
-            else rad_fwd_block<T, false, true>(g, C.R, r, rs, unit);
+            if (transpose) rad_fwd_block<T, NRMAX, true, true>(g, C.R, r, rs, unit);
+            else rad_fwd_block<T, NRMAX, false, true>(g, C.R, r, rs, unit);
         } else {
-            rad_fwd_block<T, false, false>(g, C.R, r, rs, unit);
+            rad_fwd_block<T, NRMAX, false, false>(g, C.R, r, rs, unit);
         }
         break;
     }
@@ -119,12 +119,7 @@ void launch_batch_stage(const StageRun &run, int nrmax, hipStream_t st)
 {
     if (run.nitems <= 0) return;
 #define P4D_BS(NR) hipLaunchKernelGGL((k_batch_stage<T, TZ, NR>), dim3(run.nitems), dim3(kBlock), 0, st, run)
-    switch (nrmax) {
-    case 8: P4D_BS(8); break;
-    case 16: P4D_BS(16); break;
-    case 32: P4D_BS(32); break;
-    default: P4D_BS(64); break;
-    }
+    P4D_NR_SWITCH(nrmax, P4D_BS)
 #undef P4D_BS
 }
 #define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, hipStream_t);
@@ -154,7 +149,7 @@ __device__ inline int find_cell(const BCell *cells, int ncells, int b, bool op)
 
 // RESID: V_0 = b - A x with per-workgroup sums of squares; otherwise
 // V_{k+1} = A Z_k
-template <typename TX, bool TRANS, bool RESID>
+template <typename TX, int NRMAX, bool TRANS, bool RESID>
 __global__ __launch_bounds__(kBlock) void k_bop(const BCell *__restrict__ cells, int ncells,
                                                 unsigned long long active, int k)
 {
@@ -176,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_bop(const BCell *__restrict__ cells,
         O.b = nullptr;
     }
     double sq = 0.0;
-    if (n < C.g.nnode) sq = operator_node<TX, TRANS, RESID>(C.g, O, n);
+    if (n < C.g.nnode) sq = operator_node<TX, NRMAX, TRANS, RESID>(C.g, O, n);
     if (RESID) {
         const double s = block_sum(sq, red);
         if (threadIdx.x == 0) C.red[lb] = s;
@@ -338,21 +333,29 @@ void launch_bstart(const BCell *cells, int ncells, int nblk_st, hipStream_t st)
 
 template <typename TZ>
 void launch_bop(const BCell *cells, int ncells, unsigned long long active, int k, int resid,
-                int transpose, int nblk_op, hipStream_t st)
+                int transpose, int nblk_op, int nrmax, hipStream_t st)
 {
-#define P4D_BO(TXT, TR, RS) \
-    hipLaunchKernelGGL((k_bop<TXT, TR, RS>), dim3(nblk_op), dim3(kBlock), 0, st, cells, ncells, active, k)
-    if (resid) {
-        if (transpose) P4D_BO(double, true, true);
-        else P4D_BO(double, false, true);
-    } else {
-        if (transpose) P4D_BO(TZ, true, false);
-        else P4D_BO(TZ, false, false);
-    }
+#define P4D_BO(TXT, NR, TR, RS)                                                                  \
+    hipLaunchKernelGGL((k_bop<TXT, NR, TR, RS>), dim3(nblk_op), dim3(kBlock), 0, st, cells, ncells, \
+                       active, k)
+#define P4D_BO2(NR)                                           \
+    do {                                                      \
+        if (resid) {                                          \
+            if (transpose) P4D_BO(double, NR, true, true);    \
+            else P4D_BO(double, NR, false, true);             \
+        } else {                                              \
+            if (transpose) P4D_BO(TZ, NR, true, false);       \
+            else P4D_BO(TZ, NR, false, false);                \
+        }                                                     \
+    } while (0)
+    P4D_NR_SWITCH(nrmax, P4D_BO2)
+#undef P4D_BO2
 #undef P4D_BO
 }
-template void launch_bop<double>(const BCell *, int, unsigned long long, int, int, int, int, hipStream_t);
-template void launch_bop<float>(const BCell *, int, unsigned long long, int, int, int, int, hipStream_t);
+template void launch_bop<double>(const BCell *, int, unsigned long long, int, int, int, int, int,
+                                 hipStream_t);
+template void launch_bop<float>(const BCell *, int, unsigned long long, int, int, int, int, int,
+                                hipStream_t);
 
 void launch_bmdot(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
                   int pass, hipStream_t st)

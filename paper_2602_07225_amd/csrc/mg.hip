@@ -28,6 +28,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb, in
 
 int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ) { return smooth0_box_tiles(nx, ny, nz, TX, CZ); }
 
+// workgroups of the level-0 smoother resident at once on the current device
+int smooth0_slots()
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_smooth0<double, false>,
+                                                     kBlock, 0) != hipSuccess)
+        return 1024;
+    return (per < 1 ? 1 : per) * (ncu < 1 ? 1 : ncu);
+}
+
 template <typename T>
 void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
                     int CZ, hipStream_t st)
@@ -254,78 +266,99 @@ void launch_assemble0(const Geom &g, int, int nz, int k0, int ek_lo, int ek_hi, 
 
 // Galerkin coarse stencil S_c = P^T S P with P = P_x (x) P_y (x) P_z, done as
 // three 1D Galerkin coarsenings (along x, then y, then z): each keeps the
-// 27-point pattern and needs 3 x 27 x 2 products per output row instead of
-// the 27 x 27 x 8 of the direct triple product.
-template <int AX>
-__global__ __launch_bounds__(kBlock) void k_rap1d(int nx, int ny, int nz,
-                                                  const double *__restrict__ Sf,
-                                                  double *__restrict__ Sc)
+// 27-point pattern.  Along the coarsened axis, coarse row I gathers the fine
+// rows g1 in {c-1, c, c+1} around its fine point c, each with weight
+// P(g1, I), and the fine couplings g1 -> g1 + da land on coarse offsets dJ
+// with weight P(g1 + da, I + dJ); all loops have fixed trip counts and the
+// weights are computed by selects, so there is no divergent branching.
+
+// 1D interpolation weight P(g, J) of the 'even indices plus the last' rule
+__device__ inline double pweight(int n, int g, int J)
 {
-    // input dims (nx, ny, nz); output coarse along axis AX
+    if (g < 0 || g >= n) return 0.0;
+    if (n <= 2) return g == J ? 1.0 : 0.0;
+    if (!(g & 1)) return (g >> 1) == J ? 1.0 : 0.0;
+    if (g == n - 1) return (n >> 1) == J ? 1.0 : 0.0;
+    return ((g - 1) >> 1) == J || ((g + 1) >> 1) == J ? 0.5 : 0.0;
+}
+
+// stencil slot of offset a along axis AX and (d1, d2) along the other two
+template <int AX>
+__device__ constexpr int slot_ax(int a, int d1, int d2)
+{
+    return nb_index(AX == 0 ? a : d1, AX == 0 ? d1 : (AX == 1 ? a : d2), AX == 2 ? a : d2);
+}
+
+template <int AX>
+__global__ __launch_bounds__(kBlock) void k_rap1d(RapBatch rb)
+{
+    const RapArgs &A = rb.a[find_box(rb, blockIdx.x)];
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
     const int fa = AX == 0 ? nx : (AX == 1 ? ny : nz);
     const int ca = coarse_n(fa);
     const int ox = AX == 0 ? ca : nx, oy = AX == 1 ? ca : ny, oz = AX == 2 ? ca : nz;
     const int no = ox * oy * oz, nf = nx * ny * nz;
-    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
     if (n >= no) return;
     const int I0 = n % ox, t = n / ox, J0 = t % oy, K0 = t / oy;
     const int Ia = AX == 0 ? I0 : (AX == 1 ? J0 : K0);   // coarse index along AX
-    int fi[3];
-    double wf[3];
-    const int nfi = fine_of(fa, Ia, fi, wf);
+    const int c = fa <= 2 ? Ia : (Ia == ca - 1 ? fa - 1 : 2 * Ia);
     double acc[27];
 #pragma unroll
     for (int o = 0; o < 27; o++) acc[o] = 0.0;
-    for (int q = 0; q < nfi; q++) {
-        const int f = fi[q];
-        const int i = AX == 0 ? f : I0, j = AX == 1 ? f : J0, k = AX == 2 ? f : K0;
+#pragma unroll 1
+    for (int q = 0; q < 3; q++) {   // one fine row at a time keeps 27 loads in flight
+        const int g1 = c - 1 + q;
+        const double w1 = pweight(fa, g1, Ia);
+        const int gc = g1 < 0 ? 0 : (g1 >= fa ? fa - 1 : g1);   // any valid row when w1 = 0
+        const int i = AX == 0 ? gc : I0, j = AX == 1 ? gc : J0, k = AX == 2 ? gc : K0;
         const long long row = i + (long long)nx * (j + (long long)ny * k);
+        const double *__restrict__ S = A.Sf;
+        double sv[27];
+#pragma unroll
+        for (int o = 0; o < 27; o++) sv[o] = S[(long long)o * nf + row];
 #pragma unroll
         for (int da = -1; da <= 1; da++) {
-            const int g2 = f + da;                 // fine neighbour along AX
-            if (g2 < 0 || g2 >= fa) continue;
-            int Cj[2];
-            double vj[2];
-            const int nc = coarse_of(fa, g2, Cj, vj);
+            double W[3];
 #pragma unroll
-            for (int m = 0; m < 9; m++) {          // offsets along the other two axes
+            for (int dJ = -1; dJ <= 1; dJ++) W[dJ + 1] = w1 * pweight(fa, g1 + da, Ia + dJ);
+#pragma unroll
+            for (int m = 0; m < 9; m++) {
                 const int d1 = m % 3 - 1, d2 = m / 3 - 1;
-                const int dx = AX == 0 ? da : d1;
-                const int dy = AX == 0 ? d1 : (AX == 1 ? da : d2);
-                const int dz = AX == 2 ? da : d2;
-                const double sv = Sf[(long long)nb_index(dx, dy, dz) * nf + row];
-                if (sv == 0.0) continue;
-                for (int c = 0; c < nc; c++) {
-                    const int off = Cj[c] - Ia;
-                    if (off < -1 || off > 1) continue;
-                    const int ex = AX == 0 ? off : d1;
-                    const int ey = AX == 0 ? d1 : (AX == 1 ? off : d2);
-                    const int ez = AX == 2 ? off : d2;
-                    const double v = wf[q] * sv * vj[c];
-                    // compile-time slot except for the coarse offset
-                    if (off == -1) acc[nb_index(AX == 0 ? -1 : ex, AX == 1 ? -1 : ey, AX == 2 ? -1 : ez)] += v;
-                    else if (off == 0) acc[nb_index(AX == 0 ? 0 : ex, AX == 1 ? 0 : ey, AX == 2 ? 0 : ez)] += v;
-                    else acc[nb_index(AX == 0 ? 1 : ex, AX == 1 ? 1 : ey, AX == 2 ? 1 : ez)] += v;
-                }
+                const double v = sv[slot_ax<AX>(da, d1, d2)];
+#pragma unroll
+                for (int dJ = -1; dJ <= 1; dJ++) acc[slot_ax<AX>(dJ, d1, d2)] += W[dJ + 1] * v;
             }
         }
     }
 #pragma unroll
-    for (int o = 0; o < 27; o++) Sc[(long long)o * no + n] = acc[o];
+    for (int o = 0; o < 27; o++) A.Sc[(long long)o * no + n] = acc[o];
 }
 
-void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, double *tmp, hipStream_t st)
+// P^T S P for up to four boxes at once; job b needs job.tmp with room for
+// 27 * (cx*fy*fz + cx*cy*fz) doubles
+void launch_rap(const RapJob *jobs, int njobs, hipStream_t st)
 {
-    const int cx = coarse_n(fx), cy = coarse_n(fy), cz = coarse_n(fz);
-    double *t1 = tmp;                                   // (cx, fy, fz)
-    double *t2 = tmp + 27LL * cx * fy * fz;             // (cx, cy, fz)
-    const int n1 = cx * fy * fz, n2 = cx * cy * fz, n3 = cx * cy * cz;
-    hipLaunchKernelGGL(k_rap1d<0>, dim3((n1 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fx, fy,
-                       fz, Sf, t1);
-    hipLaunchKernelGGL(k_rap1d<1>, dim3((n2 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, cx, fy,
-                       fz, t1, t2);
-    hipLaunchKernelGGL(k_rap1d<2>, dim3((n3 + kBlock - 1) / kBlock), dim3(kBlock), 0, st, cx, cy,
-                       fz, t2, Sc);
+    RapBatch r[3] = {};
+    int blk[3] = {0, 0, 0};
+    for (int a = 0; a < 3; a++) r[a].nbox = njobs;
+    for (int b = 0; b < njobs; b++) {
+        const RapJob &J = jobs[b];
+        const int cx = coarse_n(J.fx), cy = coarse_n(J.fy), cz = coarse_n(J.fz);
+        double *t1 = J.tmp;                                  // (cx, fy, fz)
+        double *t2 = J.tmp + 27LL * cx * J.fy * J.fz;        // (cx, cy, fz)
+        const int n1 = cx * J.fy * J.fz, n2 = cx * cy * J.fz, n3 = cx * cy * cz;
+        r[0].a[b] = RapArgs{J.fx, J.fy, J.fz, blk[0], J.Sf, t1};
+        r[1].a[b] = RapArgs{cx, J.fy, J.fz, blk[1], t1, t2};
+        r[2].a[b] = RapArgs{cx, cy, J.fz, blk[2], t2, J.Sc};
+        blk[0] += (n1 + kBlock - 1) / kBlock;
+        blk[1] += (n2 + kBlock - 1) / kBlock;
+        blk[2] += (n3 + kBlock - 1) / kBlock;
+    }
+    if (!njobs) return;
+    hipLaunchKernelGGL(k_rap1d<0>, dim3(blk[0]), dim3(kBlock), 0, st, r[0]);
+    hipLaunchKernelGGL(k_rap1d<1>, dim3(blk[1]), dim3(kBlock), 0, st, r[1]);
+    hipLaunchKernelGGL(k_rap1d<2>, dim3(blk[2]), dim3(kBlock), 0, st, r[2]);
 }
 
 // inverse diagonal and per-block maxima of the Gershgorin ratio sum|s_ij|/s_ii
@@ -479,9 +512,9 @@ __global__ __launch_bounds__(kBlock) void k_stencil_diff(int n, const double *__
     for (int o = 0; o < 27; o++) {
         const double v = S[(long long)o * n + t];
         rs += v;
-        if (o != 13) D[(long long)o * n + t] = (T)v;
+        if (o > 13) D[(long long)(o - 13) * n + t] = (T)v;
     }
-    D[13LL * n + t] = (T)rs;
+    D[t] = (T)rs;
 }
 template <typename T>
 void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st)

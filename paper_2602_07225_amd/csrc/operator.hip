@@ -12,14 +12,14 @@
 
 namespace p4d {
 
-template <typename TX, bool TRANS, bool RESID>
+template <typename TX, int NRMAX, bool TRANS, bool RESID>
 __global__ __launch_bounds__(kBlock) void k_operator(Geom g, OpArgs O, double *__restrict__ partial)
 {
     __shared__ double red[4];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)lb * kBlock + threadIdx.x;
     double sq = 0.0;
-    if (n < g.nnode) sq = operator_node<TX, TRANS, RESID>(g, O, n);
+    if (n < g.nnode) sq = operator_node<TX, NRMAX, TRANS, RESID>(g, O, n);
     if (partial) {
         const double s = block_sum(sq, red);
         if (threadIdx.x == 0) partial[lb] = s;
@@ -36,13 +36,20 @@ void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, c
 {
     const int nb = operator_blocks(g);
     OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, x, y, b};
-#define P4D_OP(TR, RS) \
-    hipLaunchKernelGGL((k_operator<TX, TR, RS>), dim3(nb), dim3(kBlock), 0, st, g, O, partial)
-    if (!transpose) {
-        if (b) P4D_OP(false, true); else P4D_OP(false, false);
-    } else {
-        if (b) P4D_OP(true, true); else P4D_OP(true, false);
-    }
+#define P4D_OP(NR, TR, RS) \
+    hipLaunchKernelGGL((k_operator<TX, NR, TR, RS>), dim3(nb), dim3(kBlock), 0, st, g, O, partial)
+#define P4D_OP2(NR)                                        \
+    do {                                                   \
+        if (!transpose) {                                  \
+            if (b) P4D_OP(NR, false, true);                \
+            else P4D_OP(NR, false, false);                 \
+        } else {                                           \
+            if (b) P4D_OP(NR, true, true);                 \
+            else P4D_OP(NR, true, false);                  \
+        }                                                  \
+    } while (0)
+    P4D_NR_SWITCH(rad_nrmax(g), P4D_OP2)
+#undef P4D_OP2
 #undef P4D_OP
 }
 template void launch_operator<double>(const Geom &, const RadialTab *, const double *,

@@ -79,6 +79,7 @@ struct p4d_ctx {
     size_t scratch_bytes = 0;
     double *hhost = nullptr;       // pinned host staging
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
+    int tiles_tuned = 0;           // set by the autotuner; else chosen at layout time
     Prof prof;
     // record mode: the preconditioner schedule is appended to a stage list
     // (std::vector<PStage<T>>) instead of being launched
@@ -281,7 +282,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
                 L.S64 = nullptr; L.S = nullptr;
             } else {
                 L.S64 = (double *)take(8 * 27 * (size_t)L.n);
-                L.S = take(ts * 27 * (size_t)L.n);   // difference form for the smoother
+                L.S = take(ts * 14 * (size_t)L.n);   // upper half, difference form
                 L.invd = take(ts * L.n);
                 L.b = take(ts * L.n);
                 L.xa = take(8 * (size_t)L.n);
@@ -310,7 +311,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
             rapmax = t > rapmax ? t : rapmax;
         }
     }
-    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(8 * rapmax) +
+    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(8 * 4 * rapmax) +
           align_up(setup_need);
     // Krylov basis
     const int m = o.restart;
@@ -702,16 +703,32 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
             rapmax = t > rapmax ? t : rapmax;
         }
     }
-    double *raptmp = (double *)take(8 * (rapmax ? rapmax : 1));
+    double *raptmp = (double *)take(8 * 4 * (rapmax ? rapmax : 1));   // one slice per box
     InvBatch ib{};
     launch_dcorr<double>(g, c->gg, c->ee, c->mm, c->omega, dc64, st);
     launch_cast<T>(g.Nm, dc64, (T *)c->dcorr0, st);
     // inverse diagonal of level 0 defaults to 0 outside the boxes (the
     // grounded layer of phi_s)
     HIPCHK(c, hipMemsetAsync(id64, 0, 8 * (size_t)g.Nm, st));
-    for (int b = 0; b < 4; b++) {
-        Box &B = c->box[b];
-        for (int l = 0; l < B.nlev; l++) {
+    int maxlev = 0;
+    for (int b = 0; b < 4; b++) maxlev = c->box[b].nlev > maxlev ? c->box[b].nlev : maxlev;
+    for (int l = 0; l < maxlev; l++) {
+        if (l > 0) {   // Galerkin products of this level, all boxes in one batch
+            RapJob jobs[4];
+            int nj = 0;
+            for (int b = 0; b < 4; b++) {
+                Box &B = c->box[b];
+                if (B.nlev <= l) continue;
+                const Level &F = B.lev[l - 1];
+                jobs[nj] = RapJob{F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, B.lev[l].S64,
+                                  raptmp + (size_t)nj * rapmax};
+                nj++;
+            }
+            launch_rap(jobs, nj, st);
+        }
+        for (int b = 0; b < 4; b++) {
+            Box &B = c->box[b];
+            if (B.nlev <= l) continue;
             Level &L = B.lev[l];
             const double *Sl;
             if (l == 0) {
@@ -719,8 +736,6 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                                  S0[b], st);
                 Sl = S0[b];
             } else {
-                const Level &F = B.lev[l - 1];
-                launch_rap(F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, L.S64, raptmp, st);
                 Sl = L.S64;
                 launch_stencil_diff<T>(L.n, L.S64, (T *)L.S, st);
             }
@@ -1031,6 +1046,29 @@ p4d_status p4d_set_workspace(p4d_ctx *c, void *d_work, size_t bytes, const p4d_s
     return ensure_layout(c, o);
 }
 
+// Default level-0 smoother tiles: TX by the grid width, and the layer depth
+// CZ that minimizes (rounds of resident workgroups) x (CZ + 2 halo planes),
+// so that the last round of tiles is not nearly empty.
+static void default_tiles(p4d_ctx *c)
+{
+    const int nx = c->g.nx;
+    c->tile_tx = nx >= 48 ? 64 : (nx >= 24 ? 32 : 16);
+    const long long slots = smooth0_slots();
+    long long best = -1;
+    for (int cz = 2; cz <= 16; cz++) {
+        long long tiles = 0;
+        for (int b = 0; b < 4; b++) {
+            const Level &L = c->box[b].lev[0];
+            tiles += smooth0_tiles(L.nx, L.ny, L.nz, c->tile_tx, cz);
+        }
+        const long long cost = ((tiles + slots - 1) / slots) * (cz + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            c->tile_cz = cz;
+        }
+    }
+}
+
 static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o)
 {
     if (!c->ws) return fail(c, P4D_ERR_STATE, "no workspace");
@@ -1043,6 +1081,7 @@ static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o)
         return fail(c, P4D_ERR_OOM, "workspace too small for these options");
     carve(c, o, base);
     c->ws_opts = o;
+    if (!c->tiles_tuned) default_tiles(c);
     return P4D_OK;
 }
 
@@ -1207,7 +1246,7 @@ p4d_status p4d_profile_read(p4d_ctx *c, int cls, double *total_ms, int64_t *laun
 template <typename T>
 static p4d_status tune_tiles_t(p4d_ctx *c, hipStream_t st)
 {
-    static const int txs[3] = {16, 32, 64}, czs[3] = {4, 8, 16};
+    static const int txs[3] = {16, 32, 64};
     const int boxes[4] = {0, 1, 2, 3};
     const int mask = c->prof.mask;
     c->prof.mask = 0;
@@ -1221,9 +1260,9 @@ static p4d_status tune_tiles_t(p4d_ctx *c, hipStream_t st)
     int btx = c->tile_tx, bcz = c->tile_cz;
     hipError_t he = hipSuccess;
     for (int a = 0; a < 3 && he == hipSuccess; a++)
-        for (int q = 0; q < 3 && he == hipSuccess; q++) {
+        for (int cz = 2; cz <= 16 && he == hipSuccess; cz++) {
             c->tile_tx = txs[a];
-            c->tile_cz = czs[q];
+            c->tile_cz = cz;
             VState<T> vs{};
             smooth_step<T>(c, vs, 0, boxes, 4, 1, 1, st);   // warm-up
             hipEventRecord(e0, st);
@@ -1235,13 +1274,14 @@ static p4d_status tune_tiles_t(p4d_ctx *c, hipStream_t st)
             if (he == hipSuccess && (best == 0.f || ms < best)) {
                 best = ms;
                 btx = txs[a];
-                bcz = czs[q];
+                bcz = cz;
             }
         }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     c->tile_tx = btx;
     c->tile_cz = bcz;
+    c->tiles_tuned = 1;
     c->prof.mask = mask;
     if (he != hipSuccess) return hipchk(c, he, "smoother tile timing");
     return hipchk(c, hipGetLastError(), "smoother tile timing");
@@ -1528,7 +1568,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                         bytes += 24.0 * g.N + 16.0 * g.nelem + 32.0 * g.ne;
                     }
                 ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
-                launch_bop<double>(B->bcell, n, rmask, 0, 1, transpose, opb, st);
+                launch_bop<double>(B->bcell, n, rmask, 0, 1, transpose, opb, B->nrmax, st);
             }
             launch_bnorm_final(B->bcell, n, rmask, 0, 1, st);
             if ((ps = fetch()) != P4D_OK) return ps;
@@ -1597,7 +1637,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                         bytes += (sizeof(TZ) + 8.0) * g.N + 16.0 * g.nelem + 32.0 * g.ne;
                     }
                 ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
-                launch_bop<TZ>(B->bcell, n, act, k, 0, transpose, opb, st);
+                launch_bop<TZ>(B->bcell, n, act, k, 0, transpose, opb, B->nrmax, st);
             }
             const int nv = k + 1;
             const int passes = o.cgs2 ? 2 : 1;

@@ -87,7 +87,7 @@ struct BCell {
 void launch_bstart(const BCell *cells, int ncells, int nblk_st, hipStream_t st);
 template <typename TZ>
 void launch_bop(const BCell *cells, int ncells, unsigned long long active, int k, int resid,
-                int transpose, int nblk_op, hipStream_t st);
+                int transpose, int nblk_op, int nrmax, hipStream_t st);
 void launch_bmdot(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
                   int pass, hipStream_t st);
 void launch_borth(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,

@@ -54,7 +54,7 @@ struct LevelArgs {
     int ek_lo, ek_hi;                // level 0: element layers taking part
     int mass;                        // level 0: add the c_e storage term
     const double *cK;                // level 0: element coefficient (x h)
-    const T *S;                      // level >= 1: stencil, SoA [27][n]
+    const T *S;                      // level >= 1: upper-half stencil, SoA [14][n]
     const T *invd;                   // inverse diagonal
     const T *dcorr;                  // level 0: diagonal reaction correction
     const T *b;
@@ -126,7 +126,17 @@ void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rsc
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
                      int transpose, int schur, hipStream_t st);
+// size class of the per-thread radial register arrays: the largest N_r of
+// the two electrodes rounded up to 8, 16, 24, 32 or 64
 int rad_nrmax(const Geom &g);
+#define P4D_NR_SWITCH(nr, M)   \
+    switch (nr) {              \
+    case 8: M(8); break;       \
+    case 16: M(16); break;     \
+    case 24: M(24); break;     \
+    case 32: M(32); break;     \
+    default: M(64); break;     \
+    }
 
 // mg.hip
 // level-0 smoother, 2.5D tiles of TX x (256/TX) nodes and CZ layers;
@@ -135,6 +145,7 @@ template <typename T>
 void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
                     int CZ, hipStream_t st);
 int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ);
+int smooth0_slots();
 template <typename T>
 void launch_smooth(const LevelBatch<T> &lb, int nblk, int resid_only, hipStream_t st);
 template <typename T>
@@ -145,9 +156,25 @@ template <typename T>
 void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st);
 void launch_assemble0(const Geom &g, int box, int nz, int k0, int ek_lo, int ek_hi, int mass,
                       const double *cK, const double *dcorr, double *S, hipStream_t st);
-// Galerkin product P^T S P as three 1D coarsenings (x, y, z); tmp needs
-// 27 * (cx*fy*fz + cx*cy*fz) doubles
-void launch_rap(int fx, int fy, int fz, const double *Sf, double *Sc, double *tmp, hipStream_t st);
+// Galerkin product P^T S P as three 1D coarsenings (x, y, z), for up to four
+// boxes per launch; tmp of each job needs 27 * (cx*fy*fz + cx*cy*fz) doubles
+struct RapArgs {
+    int nx, ny, nz;          // input dims of this 1D coarsening
+    int blk0;
+    const double *Sf;
+    double *Sc;
+};
+struct RapBatch {
+    int nbox;
+    RapArgs a[4];
+};
+struct RapJob {
+    int fx, fy, fz;
+    const double *Sf;
+    double *Sc;
+    double *tmp;
+};
+void launch_rap(const RapJob *jobs, int njobs, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
 void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);

@@ -90,31 +90,82 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
     const bool own = i < A.nx && j < A.ny;
     const int planeN = A.nx * A.ny;
 
-    auto load_plane = [&](int kl, int slot) {
-        for (int q = threadIdx.x; q < PX * PY; q += kBlock) {
+    // One plane of x with its halo (PX*PY <= 2*kBlock values) and one layer
+    // of element coefficients (EX*EY <= 2*kBlock) per workgroup: each thread
+    // holds at most two of each.  They are fetched into registers one layer
+    // ahead and written to LDS after the layer that used the slot is done,
+    // so the global loads overlap the arithmetic of the previous layer.
+    double px[2], pc[2];
+    auto fetch_plane = [&](int kl) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
             const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
-            const bool ok = kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny;
-            L.xp[slot][q] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
+            const bool ok = q < PX * PY && kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 &&
+                            jj < A.ny;
+            px[h] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
         }
     };
-    auto load_elems = [&](int kl, int slot) {
+    auto store_plane = [&](int slot) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            if (q < PX * PY) L.xp[slot][q] = px[h];
+        }
+    };
+    auto fetch_elems = [&](int kl) {
         const int ek = kl + A.k0;
         const bool lay = ek >= A.ek_lo && ek <= A.ek_hi;
-        for (int q = threadIdx.x; q < EX * EY; q += kBlock) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
             const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
-            const bool ok = lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
-            L.ck[slot][q] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+            const bool ok = q < EX * EY && lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
+            pc[h] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
         }
     };
-    load_plane(k0l - 1, (k0l + 2) % 3);
-    load_plane(k0l, k0l % 3);
-    load_elems(k0l - 1, (k0l + 1) & 1);
-    for (int kl = k0l; kl < k1l; kl++) {
-        load_plane(kl + 1, (kl + 1) % 3);
-        load_elems(kl, kl & 1);
-        __syncthreads();
+    auto store_elems = [&](int slot) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            if (q < EX * EY) L.ck[slot][q] = pc[h];
+        }
+    };
+    // per-node data of a layer (right-hand side, reaction diagonal, inverse
+    // diagonal, previous direction), also fetched one layer ahead
+    double nb[4] = {0.0, 0.0, 0.0, 0.0};
+    auto fetch_node = [&](int kl) {
+        const int n = i + A.nx * j + planeN * kl;
         if (own) {
-            const int n = i + A.nx * j + planeN * kl;
+            nb[0] = (double)A.b[n];
+            nb[1] = (double)A.dcorr[n];
+            if (!RESID_ONLY) {
+                nb[2] = (double)A.invd[n];
+                if (A.c1 != 0.0 && !A.din_x) nb[3] = (double)A.din[n];
+            }
+        }
+    };
+    fetch_plane(k0l - 1);
+    store_plane((k0l + 2) % 3);
+    fetch_plane(k0l);
+    store_plane(k0l % 3);
+    fetch_elems(k0l - 1);
+    store_elems((k0l + 1) & 1);
+    fetch_plane(k0l + 1);
+    fetch_elems(k0l);
+    fetch_node(k0l);
+    for (int kl = k0l; kl < k1l; kl++) {
+        store_plane((kl + 1) % 3);
+        store_elems(kl & 1);
+        const int n = i + A.nx * j + planeN * kl;
+        const double bn = nb[0], dcn = nb[1], idn = nb[2], dnn = nb[3];
+        __syncthreads();
+        if (kl + 1 < k1l) {
+            fetch_plane(kl + 2);
+            fetch_elems(kl + 1);
+            fetch_node(kl + 1);
+        }
+        if (own) {
             double X[27];
 #pragma unroll
             for (int dz = -1; dz <= 1; dz++) {
@@ -134,14 +185,14 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
                 const int ek = k - 1 + ez;
                 cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
             }
-            double Sx = q1_stiff(cK, X) + (double)A.dcorr[n] * X[13];
+            double Sx = q1_stiff(cK, X) + dcn * X[13];
             if (A.mass) Sx += q1_mass(cM, X);
-            const double r = (double)A.b[n] - Sx;
+            const double r = bn - Sx;
             if (RESID_ONLY) {
                 A.rout[n] = (T)r;
             } else {
-                double d = A.c2 * (double)A.invd[n] * r;
-                if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : (double)A.din[n]);
+                double d = A.c2 * idn * r;
+                if (A.c1 != 0.0) d += A.c1 * (A.din_x ? X[13] : dnn);
                 A.xout[n] = X[13] + d;
                 if (A.dout) A.dout[n] = (T)d;
             }
@@ -151,8 +202,11 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
 }
 
 // ---------------------------------------------------------------------------
-// Levels >= 1: stored 27-point stencil, difference form (slot 13 holds the
-// row sum): S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
+// Levels >= 1: Galerkin stencil of a symmetric operator, stored by its upper
+// half in difference form: slot 0 holds the row sum, slot 1 + u the coupling
+// to the neighbour at stencil offset 14 + u; the coupling to a neighbour at
+// a lower offset o is that neighbour's coupling at offset 26 - o.
+//   S x = rowsum x_i + sum_{j != i} s_ij (x_j - x_i)
 // ---------------------------------------------------------------------------
 template <typename T, bool RESID_ONLY>
 __device__ inline void smooth_block(const LevelArgs<T> &A, int blk)
@@ -161,16 +215,29 @@ __device__ inline void smooth_block(const LevelArgs<T> &A, int blk)
     if (n >= A.n) return;
     const int i = n % A.nx, t = n / A.nx;
     const int j = t % A.ny, kl = t / A.ny;
-    const double xc = A.xin[n];
-    double Sx = (double)A.S[13LL * A.n + n] * xc;
+    // all coefficients and neighbours are loaded before any arithmetic (a
+    // missing neighbour's index is clamped to the node, its term skipped),
+    // so the loads are in flight together
+    T sv[27];
+    double xv[27];
+    bool okv[27];
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        okv[o] = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
+                 (kl + dz >= 0) && (kl + dz < A.nz);
+        const int nbr = okv[o] ? n + dx + A.nx * (dy + A.ny * dz) : n;
+        xv[o] = A.xin[nbr];
+        if (o > 13) sv[o] = A.S[(long long)(o - 13) * A.n + n];
+        else if (o < 13) sv[o] = A.S[(long long)(13 - o) * A.n + nbr];
+        else sv[o] = A.S[n];
+    }
+    const double xc = xv[13];
+    double Sx = (double)sv[13] * xc;
 #pragma unroll
     for (int o = 0; o < 27; o++) {
         if (o == 13) continue;
-        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        const bool ok = (i + dx >= 0) && (i + dx < A.nx) && (j + dy >= 0) && (j + dy < A.ny) &&
-                        (kl + dz >= 0) && (kl + dz < A.nz);
-        if (ok)
-            Sx += (double)A.S[(long long)o * A.n + n] * (A.xin[n + dx + A.nx * (dy + A.ny * dz)] - xc);
+        if (okv[o]) Sx += (double)sv[o] * (xv[o] - xc);
     }
     const double r = (double)A.b[n] - Sx;
     if (RESID_ONLY) {
@@ -294,7 +361,7 @@ struct RadArgs {
 // zeta_j = (A_ss,j^-1 r_s,j)_N; r~_y = r_y - a_y s_j zeta_j (transposed:
 // r_y - Gamma b_y zeta_j); written in precision T with the first Chebyshev
 // iterate of each box.
-template <typename T, bool TRANS, bool SCHUR>
+template <typename T, int NRMAX, bool TRANS, bool SCHUR>
 __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const double *r, double rscale,
                                      int blk)
 {
@@ -317,10 +384,18 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
             const int N = Tb.N;
             const long long nn = el == 0 ? g.nea : g.nec;
             const double *rs = r + g.off_cs[el] + (je - base);
-            T y = (T)(rs[0] * rscale);
-            for (int q = 1; q < N; q++) {
-                const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
-                y = (T)(rs[(long long)q * nn] * rscale) - lq * y;
+            // all radial values first (indices clamped to the last point), so
+            // the loads are in flight together
+            double rv[NRMAX];
+#pragma unroll
+            for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
+            T y = (T)(rv[0] * rscale);
+#pragma unroll
+            for (int q = 1; q < NRMAX; q++) {
+                if (q < N) {
+                    const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+                    y = (T)(rv[q] * rscale) - lq * y;
+                }
             }
             const double sj = R.ss[je];
             const T pivN = (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
@@ -389,16 +464,20 @@ __device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const dou
             delta = sj * ((dir ? 0.0 : m) * zps - m * zpe - g.tc * m * zce);
         dw = delta * R.om[je];
     }
-    // forward elimination; the register array is only indexed by unrolled
-    // constants, the last entry is carried separately
+    // forward elimination; the register arrays are only indexed by unrolled
+    // constants, the last entry is carried separately; all radial values are
+    // loaded first (indices clamped to the last point)
+    double rv[NRMAX];
+#pragma unroll
+    for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
     T y[NRMAX];
-    y[0] = (T)(rs[0] * rscale);
+    y[0] = (T)(rv[0] * rscale);
     T ylast = y[0];
 #pragma unroll
     for (int q = 1; q < NRMAX; q++) {
         if (q < N) {
             const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
-            y[q] = (T)(rs[(long long)q * nn] * rscale) - lq * y[q - 1];
+            y[q] = (T)(rv[q] * rscale) - lq * y[q - 1];
             ylast = y[q];
         }
     }
@@ -443,7 +522,7 @@ __device__ inline void load_nb(const Geom &g, const TX *f, long long n, int i, i
     }
 }
 
-template <typename TX, bool TRANS, bool RESID>
+template <typename TX, int NRMAX, bool TRANS, bool RESID>
 __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
 {
     const TX *x = (const TX *)O.x;
@@ -503,7 +582,14 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         const TX *xs = x + g.off_cs[el] + jl;
         double *ys = y + g.off_cs[el] + jl;
         const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
-        const double xsN = ldx(xs + (long long)(N - 1) * nn);
+        // the particle column, loaded at once (indices clamped to the last point)
+        double xr[NRMAX];
+#pragma unroll
+        for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+        double xsN = xr[0];
+#pragma unroll
+        for (int r = 1; r < NRMAX; r++)
+            if (r == N - 1) xsN = xr[r];
         // a = (m, -m, -tc m, Gamma) rows, b = (g, -g, e, s) columns
         const double a0 = dir ? 0.0 : m, b0 = dir ? 0.0 : gj;
         double q, r0, r1, r2, r3;
@@ -520,21 +606,23 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         if (RESID) yps = b[je] - yps;
         y[je] = yps;
         sq += yps * yps;
-        double xm = 0.0, x0 = ldx(xs);
-        for (int r = 0; r < N; r++) {
-            const double xp = r < N - 1 ? ldx(xs + (long long)(r + 1) * nn) : 0.0;
-            double v;
-            if (!TRANS)
-                v = T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
-            else
-                v = T.tdia[r] * x0 + (r > 0 ? T.tsup[r - 1] : 0.0) * xm +
-                    (r < N - 1 ? T.tsub[r + 1] : 0.0) * xp;
-            if (r == N - 1) v += r3 * q;
-            if (RESID) v = b[g.off_cs[el] + jl + (long long)r * nn] - v;
-            ys[(long long)r * nn] = v;
-            sq += v * v;
-            xm = x0;
-            x0 = xp;
+#pragma unroll
+        for (int r = 0; r < NRMAX; r++) {
+            if (r < N) {
+                const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
+                const double x0 = xr[r];
+                const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
+                double v;
+                if (!TRANS)
+                    v = T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
+                else
+                    v = T.tdia[r] * x0 + (r > 0 ? T.tsup[r > 0 ? r - 1 : 0] : 0.0) * xm +
+                        (r < N - 1 ? T.tsub[r + 1 < NRMAX ? r + 1 : r] : 0.0) * xp;
+                if (r == N - 1) v += r3 * q;
+                if (RESID) v = b[g.off_cs[el] + jl + (long long)r * nn] - v;
+                ys[(long long)r * nn] = v;
+                sq += v * v;
+            }
         }
     }
     if (RESID) {

@@ -9,10 +9,16 @@
 
 namespace p4d {
 
-template <typename T, bool TRANS, bool SCHUR>
+template <typename T, int NRMAX, bool TRANS, bool SCHUR>
 __global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R, const double *r, double rscale)
 {
-    rad_fwd_block<T, TRANS, SCHUR>(g, R, r, rscale, blockIdx.x);
+    rad_fwd_block<T, NRMAX, TRANS, SCHUR>(g, R, r, rscale, blockIdx.x);
+}
+
+int rad_nrmax(const Geom &g)
+{
+    const int nrm = g.nr[0] > g.nr[1] ? g.nr[0] : g.nr[1];
+    return nrm <= 8 ? 8 : (nrm <= 16 ? 16 : (nrm <= 24 ? 24 : (nrm <= 32 ? 32 : 64)));
 }
 
 template <typename T>
@@ -20,13 +26,19 @@ void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rsc
                     int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
-#define P4D_RF(TR, SC) \
-    hipLaunchKernelGGL((k_rad_fwd<T, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R, r, rscale)
-    if (schur) {
-        if (transpose) P4D_RF(true, true); else P4D_RF(false, true);
-    } else {
-        P4D_RF(false, false);
-    }
+#define P4D_RF(NR, TR, SC) \
+    hipLaunchKernelGGL((k_rad_fwd<T, NR, TR, SC>), dim3(nb), dim3(kBlock), 0, st, g, R, r, rscale)
+#define P4D_RF2(NR)                                  \
+    do {                                             \
+        if (schur) {                                 \
+            if (transpose) P4D_RF(NR, true, true);   \
+            else P4D_RF(NR, false, true);            \
+        } else {                                     \
+            P4D_RF(NR, false, false);                \
+        }                                            \
+    } while (0)
+    P4D_NR_SWITCH(rad_nrmax(g), P4D_RF2)
+#undef P4D_RF2
 #undef P4D_RF
 }
 template void launch_rad_fwd<double>(const Geom &, const RadArgs &, const double *, double, int, int,
@@ -41,11 +53,6 @@ __global__ __launch_bounds__(kBlock) void k_rad_back(Geom g, RadArgs R, const do
     rad_back_block<T, TZ, NRMAX, TRANS, SCHUR>(g, R, r, rscale, z, blockIdx.x);
 }
 
-int rad_nrmax(const Geom &g)
-{
-    const int nrm = g.nr[0] > g.nr[1] ? g.nr[0] : g.nr[1];
-    return nrm <= 8 ? 8 : (nrm <= 16 ? 16 : (nrm <= 32 ? 32 : 64));
-}
 
 template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
@@ -64,12 +71,7 @@ void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rs
             else P4D_RB(NR, false, false);           \
         }                                            \
     } while (0)
-    switch (rad_nrmax(g)) {
-    case 8: P4D_RB2(8); break;
-    case 16: P4D_RB2(16); break;
-    case 32: P4D_RB2(32); break;
-    default: P4D_RB2(64); break;
-    }
+    P4D_NR_SWITCH(rad_nrmax(g), P4D_RB2)
 #undef P4D_RB2
 #undef P4D_RB
 }

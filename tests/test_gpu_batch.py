@@ -103,7 +103,7 @@ def test_batch_autotune_keeps_results():
     x0, i0 = B.solve([p.b for p in cells])
     tiles = B.autotune()
     say(f"  tiles {tiles}")
-    assert all(t[0] in (16, 32, 64) and t[1] in (4, 8, 16) for t in tiles)
+    assert all(t[0] in (16, 32, 64) and 2 <= t[1] <= 16 for t in tiles)
     x1, i1 = B.solve([p.b for p in cells])
     for a, b, ia, ib in zip(x0, x1, i0, i1):
         assert ia.iters == ib.iters
