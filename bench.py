@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extras", action="store_true", help="only the headline solve")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 512 MiB device copy first (a reference of known size "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -138,6 +141,12 @@ def main():
     from paper_2602_07225_amd import _lib as L
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = pi.make_config(2)
     N = p.N
     log(f"[bench] C2 N={N}: building solver")

@@ -251,8 +251,12 @@ p4d_status p4d_batch_upload(p4d_batch *batch, int32_t cell, const double *d_sigm
  * preconditioner precision, coarse size and Z precision of the workspace
  * options and a restart no larger (STATE otherwise).                        */
 p4d_status p4d_batch_setup(p4d_batch *batch, const p4d_solve_opts *opts, void *stream);
-/* p4d_autotune for each distinct cell geometry; tiles (host, may be NULL)
- * receives {TX, CZ} per cell.                                               */
+/* Level-0 smoother tiles of the batch: every candidate layer depth CZ
+ * (2..16, the same for all cells; TX follows each cell's grid width) is
+ * timed on whole batched preconditioner applications and the fastest is
+ * kept (without it, CZ is chosen from the number of tiles and of resident
+ * workgroups).  Synchronizes `stream`; writes only preconditioner buffers.
+ * tiles (host, may be NULL) receives {TX, CZ} per cell.                     */
 p4d_status p4d_batch_autotune(p4d_batch *batch, void *stream, int32_t *tiles);
 /* Solves A_i x_i = b_i for every cell i.  d_b, d_x: host arrays of ncells
  * device pointers (vectors of each cell's length N_i, global layout above).

@@ -1,16 +1,21 @@
 // Batched solves of many independent cells of uneven size in lockstep:
-//  - the preconditioner of every iterating cell in one launch per stage
-//    depth;
+//  - the preconditioner of every iterating cell by a few launches per stage
+//    depth, each over all cells;
 //  - batched operator and Krylov streaming kernels over a table of cells.
 //
 // Every cell's preconditioner application is a fixed sequence of stages
 // (particle forward elimination, the V-cycle stages of its four boxes level
 // by level, particle back-substitution), recorded once with the same
 // schedule as the single-cell path.  A stage splits into workgroup-sized
-// units (tiles, 256-node blocks, 64-row blocks).  Stage d of all cells forms
-// one work list, larger cells first; one launch runs that list, one unit per
-// workgroup, so the launches of one application are ordered by the stream
-// and no workgroup ever waits for another.
+// units (tiles, 256-node blocks, 64-row blocks).  The stages are placed at
+// depths: the descending half of a V-cycle from the first depth on, the
+// ascending half (from the first prolongation) so that it ends at the last
+// depth, so the stages with the same role in cells of different depth line
+// up.  The units of one depth, split by stage family (and, for the particle
+// stages, by radial size class), form work lists, larger cells first; one
+// launch runs one list, one unit per workgroup.  The launches of one
+// application are ordered by the stream and no workgroup ever waits for
+// another.
 //
 // Each unit computes exactly what the single-cell kernels compute for the
 // same block or tile (the same device functions), so a cell solved in a
@@ -20,13 +25,11 @@
 namespace p4d {
 
 // ---------------------------------------------------------------------------
-// Batched preconditioner stages
+// Batched preconditioner stages.  Every launch runs one work list: units of
+// one stage family (see StageFamily) from the stages of one depth, one unit
+// per workgroup.  A kernel per family keeps the register and LDS footprint
+// of that family's block function only.
 // ---------------------------------------------------------------------------
-union PLds {
-    Smooth0Lds s0;
-    CoarseLds co;
-};
-
 __device__ inline int find_pos(const int *ustart, int npos, int item)
 {
     int lo = 0, hi = npos - 1;
@@ -38,63 +41,110 @@ __device__ inline int find_pos(const int *ustart, int npos, int item)
     return lo;
 }
 
-template <typename T, typename TZ, int NRMAX>
-__device__ inline void run_unit(const PStage<T> &S, const PCell &C, int k, int transpose, int unit,
-                                PLds &lds)
+struct UnitRef {
+    int si;      // stage index
+    int unit;    // unit within the stage
+};
+
+// The unit of this workgroup; the values are the same in every lane, and
+// marking them so lets the stage arguments be read into scalar registers.
+__device__ inline UnitRef unit_of(const StageRun &run)
 {
-    const Geom &g = C.g;
+    const int item = run.item0 + xcd_block(blockIdx.x, gridDim.x);
+    const int pos = __builtin_amdgcn_readfirstlane(run.pos0 + find_pos(run.ustart + run.pos0, run.npos, item));
+    const int si = __builtin_amdgcn_readfirstlane(run.order[pos]);
+    const int unit = __builtin_amdgcn_readfirstlane(item - run.ustart[pos]);
+    return UnitRef{si, unit};
+}
+
+template <typename T, int NRMAX>
+__global__ __launch_bounds__(kBlock) void k_bstage_radf(StageRun run)
+{
+    const UnitRef u = unit_of(run);
+    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    if (!((run.active >> S.cell) & 1ULL)) return;   // the cell is not iterating
+    // local copies: the cell's constants stay in registers across the
+    // unit's stores
+    const PCell &Cm = run.cells[S.cell];
+    const Geom g = Cm.g;
+    const RadArgs R = Cm.R;
+    const double *r = Cm.V + (long long)run.k * g.N;
+    const double rs = Cm.invbeta[run.k];
+    if (Cm.schur) {
+        if (run.transpose) rad_fwd_block<T, NRMAX, true, true>(g, R, r, rs, u.unit);
+        else rad_fwd_block<T, NRMAX, false, true>(g, R, r, rs, u.unit);
+    } else {
+        rad_fwd_block<T, NRMAX, false, false>(g, R, r, rs, u.unit);
+    }
+}
+
+template <typename T, typename TZ, int NRMAX>
+__global__ __launch_bounds__(kBlock) void k_bstage_radb(StageRun run)
+{
+    const UnitRef u = unit_of(run);
+    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    if (!((run.active >> S.cell) & 1ULL)) return;
+    const PCell &Cm = run.cells[S.cell];
+    const Geom g = Cm.g;
+    const RadArgs R = Cm.R;
+    const double *r = Cm.V + (long long)run.k * g.N;
+    const double rs = Cm.invbeta[run.k];
+    TZ *z = (TZ *)Cm.Z + (long long)run.k * g.N;
+    if (Cm.schur) {
+        if (run.transpose) rad_back_block<T, TZ, NRMAX, true, true>(g, R, r, rs, z, u.unit);
+        else rad_back_block<T, TZ, NRMAX, false, true>(g, R, r, rs, z, u.unit);
+    } else {
+        if (run.transpose) rad_back_block<T, TZ, NRMAX, true, false>(g, R, r, rs, z, u.unit);
+        else rad_back_block<T, TZ, NRMAX, false, false>(g, R, r, rs, z, u.unit);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bstage_sm0(StageRun run)
+{
+    __shared__ Smooth0Lds lds;
+    const UnitRef u = unit_of(run);
+    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    if (!((run.active >> S.cell) & 1ULL)) return;
+    const LevelArgs<T> A = S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, u.unit))];
+    const Geom g = run.cells[S.cell].g;
+    const int TX = S.TX, CZ = S.CZ;
+    if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, u.unit - A.blk0, TX, CZ, lds);
+    else smooth0_tile<T, true>(g, A, u.unit - A.blk0, TX, CZ, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bstage_misc(StageRun run)
+{
+    __shared__ CoarseLds lds;
+    const UnitRef u = unit_of(run);
+    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    if (!((run.active >> S.cell) & 1ULL)) return;
+    const int unit = u.unit;
     switch (S.kind) {
-    case SK_RADF: {
-        const double *r = C.V + (long long)k * g.N;
-        const double rs = C.invbeta[k];
-        if (C.schur) {
-            if (transpose) rad_fwd_block<T, NRMAX, true, true>(g, C.R, r, rs, unit);
-            else rad_fwd_block<T, NRMAX, false, true>(g, C.R, r, rs, unit);
-        } else {
-            rad_fwd_block<T, NRMAX, false, false>(g, C.R, r, rs, unit);
-        }
-        break;
-    }
-    case SK_RADB: {
-        const double *r = C.V + (long long)k * g.N;
-        const double rs = C.invbeta[k];
-        TZ *z = (TZ *)C.Z + (long long)k * g.N;
-        if (C.schur) {
-            if (transpose) rad_back_block<T, TZ, NRMAX, true, true>(g, C.R, r, rs, z, unit);
-            else rad_back_block<T, TZ, NRMAX, false, true>(g, C.R, r, rs, z, unit);
-        } else {
-            if (transpose) rad_back_block<T, TZ, NRMAX, true, false>(g, C.R, r, rs, z, unit);
-            else rad_back_block<T, TZ, NRMAX, false, false>(g, C.R, r, rs, z, unit);
-        }
-        break;
-    }
-    case SK_SM0:
-    case SK_SM0R: {
-        const LevelArgs<T> &A = S.u.lb.a[find_box(S.u.lb, unit)];
-        if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, unit - A.blk0, S.TX, S.CZ, lds.s0);
-        else smooth0_tile<T, true>(g, A, unit - A.blk0, S.TX, S.CZ, lds.s0);
-        break;
-    }
     case SK_SM:
     case SK_SMR: {
-        const LevelArgs<T> &A = S.u.lb.a[find_box(S.u.lb, unit)];
+        const LevelArgs<T> A = S.u.lb.a[find_box(S.u.lb, unit)];
         if (S.kind == SK_SM) smooth_block<T, false>(A, unit - A.blk0);
         else smooth_block<T, true>(A, unit - A.blk0);
         break;
     }
     case SK_RESTRICT: {
-        const TransferArgs<T> &A = S.u.tb.a[find_box(S.u.tb, unit)];
+        const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
         restrict_block<T>(A, unit - A.blk0);
         break;
     }
     case SK_PROLONG: {
-        const TransferArgs<T> &A = S.u.tb.a[find_box(S.u.tb, unit)];
+        const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
         prolong_block<T>(A, unit - A.blk0);
         break;
     }
     case SK_COARSE: {
         const int box = unit / S.aux, rb = unit % S.aux;
-        if (box < S.u.cb.nbox && rb * 64 < S.u.cb.a[box].n) coarse_block<T>(S.u.cb.a[box], rb, lds.co);
+        if (box < S.u.cb.nbox) {
+            const CoarseArgs<T> A = S.u.cb.a[box];
+            if (rb * 64 < A.n) coarse_block<T>(A, rb, lds);
+        }
         break;
     }
     default:
@@ -102,32 +152,51 @@ __device__ inline void run_unit(const PStage<T> &S, const PCell &C, int k, int t
     }
 }
 
-// one unit of the work list of one stage depth per workgroup
-template <typename T, typename TZ, int NRMAX>
-__global__ __launch_bounds__(kBlock) void k_batch_stage(StageRun run)
-{
-    __shared__ PLds lds;
-    const int item = run.item0 + xcd_block(blockIdx.x, gridDim.x);
-    const int pos = run.pos0 + find_pos(run.ustart + run.pos0, run.npos, item);
-    const PStage<T> &S = ((const PStage<T> *)run.stages)[run.order[pos]];
-    if (!((run.active >> S.cell) & 1ULL)) return;   // the cell is not iterating
-    run_unit<T, TZ, NRMAX>(S, run.cells[S.cell], run.k, run.transpose, item - run.ustart[pos], lds);
-}
-
 template <typename T, typename TZ>
-void launch_batch_stage(const StageRun &run, int nrmax, hipStream_t st)
+void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t st)
 {
     if (run.nitems <= 0) return;
-#define P4D_BS(NR) hipLaunchKernelGGL((k_batch_stage<T, TZ, NR>), dim3(run.nitems), dim3(kBlock), 0, st, run)
-    P4D_NR_SWITCH(nrmax, P4D_BS)
-#undef P4D_BS
+    const dim3 grid(run.nitems), block(kBlock);
+    switch (family) {
+    case SF_RADF:
+#define P4D_BF(NR) hipLaunchKernelGGL((k_bstage_radf<T, NR>), grid, block, 0, st, run)
+        P4D_NR_SWITCH(nrmax, P4D_BF)
+#undef P4D_BF
+        break;
+    case SF_RADB:
+#define P4D_BB(NR) hipLaunchKernelGGL((k_bstage_radb<T, TZ, NR>), grid, block, 0, st, run)
+        P4D_NR_SWITCH(nrmax, P4D_BB)
+#undef P4D_BB
+        break;
+    case SF_SM0:
+        hipLaunchKernelGGL((k_bstage_sm0<T>), grid, block, 0, st, run);
+        break;
+    default:
+        hipLaunchKernelGGL((k_bstage_misc<T>), grid, block, 0, st, run);
+        break;
+    }
 }
-#define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, hipStream_t);
+#define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, int, hipStream_t);
 P4D_INST(double, double)
 P4D_INST(float, double)
 P4D_INST(double, float)
 P4D_INST(float, float)
 #undef P4D_INST
+
+// workgroups of the batched level-0 smoother resident at once
+template <typename T>
+int bstage_sm0_slots()
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_bstage_sm0<T>, kBlock, 0) !=
+            hipSuccess)
+        return 1024;
+    return (per < 1 ? 1 : per) * (ncu < 1 ? 1 : ncu);
+}
+template int bstage_sm0_slots<double>();
+template int bstage_sm0_slots<float>();
 
 // ---------------------------------------------------------------------------
 // Batched operator and Krylov streaming kernels.  The workgroups of the

@@ -1323,7 +1323,13 @@ struct p4d_batch {
     // recorded schedule
     int recorded = 0, rec_prec = -1;
     int nstages = 0, nrmax = 8;
-    std::vector<int> dpos, ditem;   // per stage depth: first queue position and first unit (+ end)
+    struct WorkList {
+        int family, nr;             // stage family, radial size class
+        int pos0, npos;             // queue positions
+        int item0, nitems;          // units
+    };
+    std::vector<WorkList> lists;    // in launch order
+    int tile_cz = 0;                // level-0 tile depth of the batch (0: chosen at recording)
     std::vector<double> pc_bytes;   // per cell: level-0 and particle bytes of one application
     int pc_mode = 0;                // 0: batched stage launches, 1: per-cell launches
     Prof prof;
@@ -1405,9 +1411,35 @@ static double stage_bytes(const PStage<T> &S, const Geom &g)
     }
 }
 
-// Records every cell's preconditioner schedule and builds the work lists:
-// one per stage depth d (stage d of every cell that has one, larger cells
-// first), stored one after the other.
+// Level-0 tile depth for the whole batch: the one that minimizes (rounds of
+// resident workgroups over all cells' tiles) x (CZ + 2 halo planes).
+template <typename T>
+static int batch_default_cz(p4d_batch *B)
+{
+    const long long slots = bstage_sm0_slots<T>();
+    long long best = -1;
+    int bcz = 8;
+    for (int cz = 2; cz <= 16; cz++) {
+        long long tiles = 0;
+        for (p4d_ctx *c : B->cell)
+            for (int b = 0; b < 4; b++) {
+                const Level &L = c->box[b].lev[0];
+                tiles += smooth0_tiles(L.nx, L.ny, L.nz, c->tile_tx, cz);
+            }
+        const long long cost = ((tiles + slots - 1) / slots) * (cz + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            bcz = cz;
+        }
+    }
+    return bcz;
+}
+
+// Records every cell's preconditioner schedule and builds the work lists.
+// Depths: the stages before a cell's first prolongation keep their index,
+// the rest are placed so that every cell's last stage falls on the last
+// depth.  Per depth, one list per stage family (per radial size class for
+// the particle stages), larger cells first.
 template <typename T>
 static p4d_status batch_record(p4d_batch *B)
 {
@@ -1415,12 +1447,16 @@ static p4d_status batch_record(p4d_batch *B)
     std::vector<std::vector<PStage<T>>> per(n);
     B->pc_bytes.assign(n, 0.0);
     B->nrmax = 8;
+    const int cz = B->tile_cz > 0 ? B->tile_cz : batch_default_cz<T>(B);
     for (int i = 0; i < n; i++) {
         p4d_ctx *c = B->cell[i];
+        const int keep = c->tile_cz;
+        c->tile_cz = cz;
         c->rec = &per[i];
         c->rec_cell = i;
         apply_pc_t<T, double>(c, 0, nullptr, 0.0, (double *)nullptr, nullptr);
         c->rec = nullptr;
+        c->tile_cz = keep;
         if ((int)per[i].size() > kMaxStagesPerCell)
             return bfail(B, P4D_ERR_INVALID_ARG, "too many preconditioner stages in a cell");
         for (const PStage<T> &S : per[i]) B->pc_bytes[i] += stage_bytes(S, c->g);
@@ -1428,34 +1464,57 @@ static p4d_status batch_record(p4d_batch *B)
         B->nrmax = nr > B->nrmax ? nr : B->nrmax;
     }
     std::vector<PStage<T>> all;
-    std::vector<int> base(n);
-    size_t depth = 0;
+    std::vector<int> base(n), split(n);
+    int A = 0, Bm = 0;
     for (int i = 0; i < n; i++) {
         base[i] = (int)all.size();
         all.insert(all.end(), per[i].begin(), per[i].end());
-        depth = per[i].size() > depth ? per[i].size() : depth;
+        const int L = (int)per[i].size();
+        int p = L;
+        for (int j = 0; j < L; j++)
+            if (per[i][j].kind == SK_PROLONG) { p = j; break; }
+        split[i] = p;
+        A = p > A ? p : A;
+        Bm = L - p > Bm ? L - p : Bm;
+    }
+    const int depth = A + Bm;
+    // stage of cell i at depth d, or -1
+    std::vector<int> at((size_t)n * depth, -1);
+    for (int i = 0; i < n; i++) {
+        const int L = (int)per[i].size();
+        for (int j = 0; j < L; j++) {
+            const int d = j < split[i] ? j : depth - (L - j);
+            at[(size_t)i * depth + d] = j;
+        }
     }
     std::vector<int> bysize(n);
     for (int i = 0; i < n; i++) bysize[i] = i;
     std::stable_sort(bysize.begin(), bysize.end(),
                      [&](int a, int b) { return B->cell[a]->g.N > B->cell[b]->g.N; });
+    static const int nrclasses[5] = {8, 16, 24, 32, 64};
     std::vector<int> order, ustart;
-    B->dpos.clear();
-    B->ditem.clear();
+    B->lists.clear();
     long long items = 0;
-    for (size_t d = 0; d < depth; d++) {
-        B->dpos.push_back((int)order.size());
-        B->ditem.push_back((int)items);
-        for (int i : bysize)
-            if (d < per[i].size()) {
-                order.push_back(base[i] + (int)d);
-                ustart.push_back((int)items);
-                items += per[i][d].nunits;
+    for (int d = 0; d < depth; d++)
+        for (int fam = SF_RADF; fam <= SF_MISC; fam++) {
+            const bool radial = fam == SF_RADF || fam == SF_RADB;
+            for (int ci = 0; ci < (radial ? 5 : 1); ci++) {
+                p4d_batch::WorkList W{fam, radial ? nrclasses[ci] : 8, (int)order.size(), 0, (int)items, 0};
+                for (int i : bysize) {
+                    const int j = at[(size_t)i * depth + d];
+                    if (j < 0 || stage_family(per[i][j].kind) != fam) continue;
+                    if (radial && rad_nrmax(B->cell[i]->g) != nrclasses[ci]) continue;
+                    order.push_back(base[i] + j);
+                    ustart.push_back((int)items);
+                    items += per[i][j].nunits;
+                }
+                W.npos = (int)order.size() - W.pos0;
+                W.nitems = (int)(items - W.item0);
+                if (W.npos > 0) B->lists.push_back(W);
+                if (items >= (1LL << 31) - (1LL << 20))
+                    return bfail(B, P4D_ERR_INVALID_ARG, "work list too long");
             }
-        if (items >= (1LL << 31) - (1LL << 20)) return bfail(B, P4D_ERR_INVALID_ARG, "work list too long");
-    }
-    B->dpos.push_back((int)order.size());
-    B->ditem.push_back((int)items);
+        }
     BHIPCHK(B, hipMemcpy(B->stages, all.data(), sizeof(PStage<T>) * all.size(), hipMemcpyHostToDevice));
     BHIPCHK(B, hipMemcpy(B->order, order.data(), 4 * order.size(), hipMemcpyHostToDevice));
     BHIPCHK(B, hipMemcpy(B->ustart, ustart.data(), 4 * ustart.size(), hipMemcpyHostToDevice));
@@ -1476,17 +1535,16 @@ struct CellRun {
 };
 }  // namespace
 
-template <typename T, typename TZ>
-static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const *bv,
-                               double *const *xv, const p4d_solve_opts &o, p4d_solve_info *infos,
-                               hipStream_t st)
+// Cell tables of the batched kernels for restart length m (b and x may be
+// null when only the preconditioner is used); copied to the device.
+static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, double *const *xv,
+                               std::vector<BCell> &bc, int &opb, int &stb, hipStream_t st)
 {
-    const int n = B->n, m = o.restart;
-    auto t0 = std::chrono::steady_clock::now();
-    // cell tables for this solve
-    std::vector<BCell> bc(n);
+    const int n = B->n;
+    bc.assign(n, BCell{});
     std::vector<PCell> pcl(n);
-    int opb = 0, stb = 0;
+    opb = 0;
+    stb = 0;
     for (int i = 0; i < n; i++) {
         p4d_ctx *c = B->cell[i];
         const Geom &g = c->g;
@@ -1502,8 +1560,8 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
         stb += C.st_nblk;
         C.V = (double *)c->scratch;
         C.Z = c->scratch + align_up(8 * (size_t)(m + 1) * g.N);
-        C.x = xv[i];
-        C.b = bv[i];
+        C.x = xv ? xv[i] : nullptr;
+        C.b = bv ? bv[i] : nullptr;
         C.red = c->red;
         C.h = B->hb + 256 * (size_t)i;
         C.coef = c->cdev;
@@ -1522,6 +1580,92 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
     BHIPCHK(B, hipStreamSynchronize(st));
     BHIPCHK(B, hipMemcpy(B->bcell, bc.data(), sizeof(BCell) * n, hipMemcpyHostToDevice));
     BHIPCHK(B, hipMemcpy(B->pcell, pcl.data(), sizeof(PCell) * n, hipMemcpyHostToDevice));
+    return P4D_OK;
+}
+
+// One batched preconditioner application z_k = P^-1 V_k / beta_k for the
+// cells in `active` (work lists of the recorded schedule, in order).
+template <typename T, typename TZ>
+static void batch_apply_pc(p4d_batch *B, int transpose, int k, unsigned long long active, hipStream_t st)
+{
+    StageRun run{};
+    run.stages = B->stages;
+    run.cells = B->pcell;
+    run.order = B->order;
+    run.ustart = B->ustart;
+    run.transpose = transpose;
+    run.k = k;
+    run.active = active;
+    for (const p4d_batch::WorkList &W : B->lists) {
+        run.pos0 = W.pos0;
+        run.npos = W.npos;
+        run.item0 = W.item0;
+        run.nitems = W.nitems;
+        launch_batch_stage<T, TZ>(run, W.family, W.nr, st);
+    }
+}
+
+// Batch tile tuning: every candidate level-0 tile depth is recorded and
+// timed on whole batched preconditioner applications (all cells, step 0;
+// only preconditioner buffers and the first preconditioned direction are
+// written); the fastest is kept.
+template <typename T, typename TZ>
+static p4d_status batch_tune_t(p4d_batch *B, hipStream_t st)
+{
+    std::vector<BCell> bc;
+    int opb = 0, stb = 0;
+    const unsigned long long all = B->n == 64 ? ~0ULL : ((1ULL << B->n) - 1);
+    static const int czs[9] = {2, 3, 4, 5, 6, 8, 10, 12, 16};
+    hipEvent_t e0, e1;
+    BHIPCHK(B, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(B, P4D_ERR_HIP, "hipEventCreate");
+    }
+    float best = 0.f;
+    int bcz = 8;
+    p4d_status s = P4D_OK;
+    for (int q = 0; q < 9 && s == P4D_OK; q++) {
+        B->tile_cz = czs[q];
+        s = batch_record<T>(B);
+        if (s == P4D_OK) s = batch_tables(B, B->ws_opts.restart, nullptr, nullptr, bc, opb, stb, st);
+        if (s != P4D_OK) break;
+        batch_apply_pc<T, TZ>(B, 0, 0, all, st);   // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int rep = 0; rep < 3; rep++) batch_apply_pc<T, TZ>(B, 0, 0, all, st);
+        (void)hipEventRecord(e1, st);
+        float ms = 0.f;
+        hipError_t he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            s = bfail(B, P4D_ERR_HIP, std::string("batch tile timing: ") + hipGetErrorString(he));
+            break;
+        }
+        if (best == 0.f || ms < best) {
+            best = ms;
+            bcz = czs[q];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B->tile_cz = bcz;
+    B->recorded = 0;
+    return s;
+}
+
+template <typename T, typename TZ>
+static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const *bv,
+                               double *const *xv, const p4d_solve_opts &o, p4d_solve_info *infos,
+                               hipStream_t st)
+{
+    const int n = B->n, m = o.restart;
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<BCell> bc;
+    int opb = 0, stb = 0;
+    {
+        const p4d_status ts = batch_tables(B, m, bv, xv, bc, opb, stb, st);
+        if (ts != P4D_OK) return ts;
+    }
 
     std::vector<CellRun> S(n);
     for (auto &R : S) {
@@ -1604,21 +1748,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                     if ((act >> i) & 1ULL) bytes += B->pc_bytes[i];
                 ProfScope pr(B->prof, P4D_K_BATCH_PC, bytes, st);
                 if (B->pc_mode == 0) {
-                    StageRun run{};
-                    run.stages = B->stages;
-                    run.cells = B->pcell;
-                    run.order = B->order;
-                    run.ustart = B->ustart;
-                    run.transpose = transpose;
-                    run.k = k;
-                    run.active = act;
-                    for (size_t d = 0; d + 1 < B->dpos.size(); d++) {
-                        run.pos0 = B->dpos[d];
-                        run.npos = B->dpos[d + 1] - B->dpos[d];
-                        run.item0 = B->ditem[d];
-                        run.nitems = B->ditem[d + 1] - B->ditem[d];
-                        launch_batch_stage<T, TZ>(run, B->nrmax, st);
-                    }
+                    batch_apply_pc<T, TZ>(B, transpose, k, act, st);
                 } else {
                     for (int i = 0; i < n; i++)
                         if ((act >> i) & 1ULL) {
@@ -1888,27 +2018,17 @@ p4d_status p4d_batch_autotune(p4d_batch *B, void *stream, int32_t *tiles)
     if (!B) return P4D_ERR_INVALID_ARG;
     for (int i = 0; i < B->n; i++)
         if (!B->cell[i]->pc_ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_setup first");
-    // one timing per distinct level-0 geometry
-    for (int i = 0; i < B->n; i++) {
-        p4d_ctx *c = B->cell[i];
-        int same = -1;
-        for (int j = 0; j < i && same < 0; j++) {
-            const Geom &a = B->cell[j]->g, &b = c->g;
-            if (a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.na == b.na && a.ns == b.ns) same = j;
+    const p4d_ctx *c0 = B->cell[0];
+    const hipStream_t st = (hipStream_t)stream;
+    p4d_status s;
+    if (c0->prec) s = B->ws_opts.z_fp32 ? batch_tune_t<float, float>(B, st) : batch_tune_t<float, double>(B, st);
+    else s = B->ws_opts.z_fp32 ? batch_tune_t<double, float>(B, st) : batch_tune_t<double, double>(B, st);
+    if (s != P4D_OK) return s;
+    if (tiles)
+        for (int i = 0; i < B->n; i++) {
+            tiles[2 * i] = B->cell[i]->tile_tx;
+            tiles[2 * i + 1] = B->tile_cz;
         }
-        if (same >= 0) {
-            c->tile_tx = B->cell[same]->tile_tx;
-            c->tile_cz = B->cell[same]->tile_cz;
-        } else {
-            const p4d_status s = tune_tiles(c, (hipStream_t)stream);
-            if (s != P4D_OK) return bfail(B, s, "cell " + std::to_string(i) + ": " + c->err);
-        }
-        if (tiles) {
-            tiles[2 * i] = c->tile_tx;
-            tiles[2 * i + 1] = c->tile_cz;
-        }
-    }
-    B->recorded = 0;
     return P4D_OK;
 }
 

@@ -63,8 +63,24 @@ struct StageRun {
     unsigned long long active;
 };
 
+// Stage families: each has its own batched kernel.
+enum StageFamily : int {
+    SF_RADF = 0,     // SK_RADF
+    SF_RADB,         // SK_RADB
+    SF_SM0,          // SK_SM0, SK_SM0R
+    SF_MISC          // coarse levels: SK_SM, SK_SMR, SK_RESTRICT, SK_PROLONG, SK_COARSE
+};
+__host__ __device__ inline int stage_family(int kind)
+{
+    return kind == SK_RADF ? SF_RADF
+                           : (kind == SK_RADB ? SF_RADB
+                                              : (kind == SK_SM0 || kind == SK_SM0R ? SF_SM0 : SF_MISC));
+}
+
 template <typename T, typename TZ>
-void launch_batch_stage(const StageRun &run, int nrmax, hipStream_t st);
+void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t st);
+template <typename T>
+int bstage_sm0_slots();
 
 // Per-cell constants of the batched operator and Krylov kernels.
 struct BCell {

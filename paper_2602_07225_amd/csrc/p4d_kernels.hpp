@@ -383,7 +383,7 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
             const RadialTab &Tb = R.tabs[el];
             const int N = Tb.N;
             const long long nn = el == 0 ? g.nea : g.nec;
-            const double *rs = r + g.off_cs[el] + (je - base);
+            const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
             // all radial values first (indices clamped to the last point), so
             // the loads are in flight together
             double rv[NRMAX];
@@ -446,13 +446,13 @@ __device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const dou
     const long long klo = el == 0 ? 0 : g.na + g.ns;
     const long long je = base + n - klo * g.nx * g.ny;
     const bool dir = (k == 0);
-    const double zps = dir ? r[je] * rscale : R.x0[el][je];
+    const double zps = dir ? r[je] * rscale : (el == 0 ? R.x0[0] : R.x0[1])[je];
     z[je] = (TZ)zps;
     const RadialTab &Tb = R.tabs[el];
     const int N = Tb.N;
     const long long nn = el == 0 ? g.nea : g.nec;
-    const double *rs = r + g.off_cs[el] + (je - base);
-    TZ *zs = z + g.off_cs[el] + (je - base);
+    const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
+    TZ *zs = z + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
     const double sj = R.ss[je];
     double dw = 0.0;   // delta_j * omega_j
     if (SCHUR) {
@@ -579,8 +579,8 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         const int N = T.N;
         const long long nn = el == 0 ? g.nea : g.nec;
         const long long jl = je - base;
-        const TX *xs = x + g.off_cs[el] + jl;
-        double *ys = y + g.off_cs[el] + jl;
+        const TX *xs = x + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl;
+        double *ys = y + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl;
         const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
         // the particle column, loaded at once (indices clamped to the last point)
         double xr[NRMAX];
@@ -619,7 +619,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
                     v = T.tdia[r] * x0 + (r > 0 ? T.tsup[r > 0 ? r - 1 : 0] : 0.0) * xm +
                         (r < N - 1 ? T.tsub[r + 1 < NRMAX ? r + 1 : r] : 0.0) * xp;
                 if (r == N - 1) v += r3 * q;
-                if (RESID) v = b[g.off_cs[el] + jl + (long long)r * nn] - v;
+                if (RESID) v = b[(el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl + (long long)r * nn] - v;
                 ys[(long long)r * nn] = v;
                 sq += v * v;
             }
