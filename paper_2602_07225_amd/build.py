@@ -17,7 +17,10 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libp4d.so")
 SOURCES = ["p4d_api.hip", "operator.hip", "radial.hip", "mg.hip", "krylov.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
+# -ffp-contract=on: multiply-adds are fused only inside one source
+# expression, so an expression shared by several kernels rounds the same way
+# in each of them
+FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", os.path.join(ROOT, "include")]

@@ -205,46 +205,80 @@ template int bstage_sm0_slots<float>();
 // the work and the order of every reduction are those of the single-cell
 // kernels.
 // ---------------------------------------------------------------------------
-__device__ inline int find_cell(const BCell *cells, int ncells, int b, bool op)
+// the cell of batched workgroup b, by the offsets of one launch kind
+enum { SEL_OP = 0, SEL_ST, SEL_TILE, SEL_RAD };
+template <int SEL>
+__device__ inline int find_cell(const BCell *cells, int ncells, int b)
 {
     int lo = 0, hi = ncells - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if ((op ? cells[mid].op_blk0 : cells[mid].st_blk0) <= b) lo = mid;
+        const BCell &M = cells[mid];
+        const int b0 = SEL == SEL_OP ? M.op_blk0
+                                     : (SEL == SEL_ST ? M.st_blk0 : (SEL == SEL_TILE ? M.tile_blk0 : M.rad_blk0));
+        if (b0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// RESID: V_0 = b - A x with per-workgroup sums of squares; otherwise
-// V_{k+1} = A Z_k
-template <typename TX, int NRMAX, bool TRANS, bool RESID>
-__global__ __launch_bounds__(kBlock) void k_bop(const BCell *__restrict__ cells, int ncells,
-                                                unsigned long long active, int k)
+// V_0 = b - A x with per-workgroup sums of squares, one thread per node
+template <typename TX, int NRMAX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_bop_resid(const BCell *__restrict__ cells, int ncells,
+                                                      unsigned long long active)
 {
     __shared__ double red[4];
     const int gb = xcd_block(blockIdx.x, gridDim.x);
-    const int c = find_cell(cells, ncells, gb, true);
+    const int c = find_cell<SEL_OP>(cells, ncells, gb);
     const BCell &C = cells[c];
     if (!((active >> c) & 1ULL)) return;
     const int lb = gb - C.op_blk0;
     const long long n = (long long)lb * kBlock + threadIdx.x;
     OpArgs O = C.op;
-    if (RESID) {
-        O.x = C.x;
-        O.y = C.V;
-        O.b = C.b;
-    } else {
-        O.x = (const TX *)C.Z + (long long)k * C.g.N;
-        O.y = C.V + (long long)(k + 1) * C.g.N;
-        O.b = nullptr;
-    }
+    O.x = C.x;
+    O.y = C.V;
+    O.b = C.b;
+    const Geom g = C.g;
     double sq = 0.0;
-    if (n < C.g.nnode) sq = operator_node<TX, NRMAX, TRANS, RESID>(C.g, O, n);
-    if (RESID) {
-        const double s = block_sum(sq, red);
-        if (threadIdx.x == 0) C.red[lb] = s;
-    }
+    if (n < g.nnode) sq = operator_node<TX, NRMAX, TRANS, true>(g, O, n);
+    const double s = block_sum(sq, red);
+    if (threadIdx.x == 0) C.red[lb] = s;
+}
+
+// V_{k+1} = A Z_k: macro rows over 2.5D tiles of every cell ...
+template <typename TX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_bop_tile(const BCell *__restrict__ cells, int ncells,
+                                                     unsigned long long active, int k)
+{
+    __shared__ OpLds L;
+    const int gb = xcd_block(blockIdx.x, gridDim.x);
+    const int c = find_cell<SEL_TILE>(cells, ncells, gb);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const Geom g = C.g;
+    OpArgs O = C.op;
+    O.x = (const TX *)C.Z + (long long)k * g.N;
+    O.y = C.V + (long long)(k + 1) * g.N;
+    O.b = nullptr;
+    operator_tile<TX, TRANS>(g, O, C.qbuf, gb - C.tile_blk0, C.op_tx, C.op_cz, L);
+}
+
+// ... then the particle rows of every cell
+template <typename TX, int NRMAX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_bop_radial(const BCell *__restrict__ cells, int ncells,
+                                                       unsigned long long active, int k)
+{
+    const int c = find_cell<SEL_RAD>(cells, ncells, blockIdx.x);
+    const BCell &C = cells[c];
+    if (!((active >> c) & 1ULL)) return;
+    const Geom g = C.g;
+    const long long je = (long long)(blockIdx.x - C.rad_blk0) * kBlock + threadIdx.x;
+    if (je >= g.ne) return;
+    OpArgs O = C.op;
+    O.x = (const TX *)C.Z + (long long)k * g.N;
+    O.y = C.V + (long long)(k + 1) * g.N;
+    O.b = nullptr;
+    operator_radial<TX, NRMAX, TRANS>(g, O, C.qbuf, je);
 }
 
 template <int KMAX>
@@ -252,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_bmdot(const BCell *__restrict__ cell
                                                   unsigned long long active, int k)
 {
     __shared__ double red[4][KMAX];
-    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
     const BCell &C = cells[c];
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
@@ -307,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_borth(const BCell *__restrict__ cell
                                                   unsigned long long active, int k)
 {
     __shared__ double red[4];
-    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
     const BCell &C = cells[c];
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
@@ -356,7 +390,7 @@ template <typename TZ, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_bzy(const BCell *__restrict__ cells, int ncells,
                                                 unsigned long long active)
 {
-    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
     const BCell &C = cells[c];
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
@@ -380,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_bzy(const BCell *__restrict__ cells,
 __global__ __launch_bounds__(kBlock) void k_bstart(const BCell *__restrict__ cells, int ncells)
 {
     __shared__ double red[4];
-    const int c = find_cell(cells, ncells, blockIdx.x, false);
+    const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
     const BCell &C = cells[c];
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
     const long long N = C.g.N;
@@ -402,29 +436,44 @@ void launch_bstart(const BCell *cells, int ncells, int nblk_st, hipStream_t st)
 
 template <typename TZ>
 void launch_bop(const BCell *cells, int ncells, unsigned long long active, int k, int resid,
-                int transpose, int nblk_op, int nrmax, hipStream_t st)
+                int transpose, int nblk_op, int nblk_tile, int nblk_rad, int nrmax, hipStream_t st)
 {
-#define P4D_BO(TXT, NR, TR, RS)                                                                  \
-    hipLaunchKernelGGL((k_bop<TXT, NR, TR, RS>), dim3(nblk_op), dim3(kBlock), 0, st, cells, ncells, \
-                       active, k)
-#define P4D_BO2(NR)                                           \
-    do {                                                      \
-        if (resid) {                                          \
-            if (transpose) P4D_BO(double, NR, true, true);    \
-            else P4D_BO(double, NR, false, true);             \
-        } else {                                              \
-            if (transpose) P4D_BO(TZ, NR, true, false);       \
-            else P4D_BO(TZ, NR, false, false);                \
-        }                                                     \
+    if (resid) {
+#define P4D_BR(NR)                                                                                \
+    do {                                                                                          \
+        if (transpose)                                                                            \
+            hipLaunchKernelGGL((k_bop_resid<double, NR, true>), dim3(nblk_op), dim3(kBlock), 0, st, \
+                               cells, ncells, active);                                            \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_bop_resid<double, NR, false>), dim3(nblk_op), dim3(kBlock), 0, st,\
+                               cells, ncells, active);                                            \
     } while (0)
-    P4D_NR_SWITCH(nrmax, P4D_BO2)
-#undef P4D_BO2
-#undef P4D_BO
+        P4D_NR_SWITCH(nrmax, P4D_BR)
+#undef P4D_BR
+        return;
+    }
+    if (transpose)
+        hipLaunchKernelGGL((k_bop_tile<TZ, true>), dim3(nblk_tile), dim3(kBlock), 0, st, cells, ncells,
+                           active, k);
+    else
+        hipLaunchKernelGGL((k_bop_tile<TZ, false>), dim3(nblk_tile), dim3(kBlock), 0, st, cells, ncells,
+                           active, k);
+#define P4D_BRA(NR)                                                                                \
+    do {                                                                                           \
+        if (transpose)                                                                             \
+            hipLaunchKernelGGL((k_bop_radial<TZ, NR, true>), dim3(nblk_rad), dim3(kBlock), 0, st,     \
+                               cells, ncells, active, k);                                          \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_bop_radial<TZ, NR, false>), dim3(nblk_rad), dim3(kBlock), 0, st,    \
+                               cells, ncells, active, k);                                          \
+    } while (0)
+    P4D_NR_SWITCH(nrmax, P4D_BRA)
+#undef P4D_BRA
 }
-template void launch_bop<double>(const BCell *, int, unsigned long long, int, int, int, int, int,
-                                 hipStream_t);
-template void launch_bop<float>(const BCell *, int, unsigned long long, int, int, int, int, int,
-                                hipStream_t);
+template void launch_bop<double>(const BCell *, int, unsigned long long, int, int, int, int, int, int,
+                                 int, hipStream_t);
+template void launch_bop<float>(const BCell *, int, unsigned long long, int, int, int, int, int, int,
+                                int, hipStream_t);
 
 void launch_bmdot(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
                   int pass, hipStream_t st)

@@ -28,14 +28,68 @@ __global__ __launch_bounds__(kBlock) void k_operator(Geom g, OpArgs O, double *_
 
 int operator_blocks(const Geom &g) { return (int)((g.nnode + kBlock - 1) / kBlock); }
 
+template <typename TX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_operator_tile(Geom g, OpArgs O, double *qout, int TXn, int CZ)
+{
+    __shared__ OpLds L;
+    operator_tile<TX, TRANS>(g, O, qout, xcd_block(blockIdx.x, gridDim.x), TXn, CZ, L);
+}
+
+template <typename TX, int NRMAX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_operator_radial(Geom g, OpArgs O, const double *q)
+{
+    const long long je = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (je < g.ne) operator_radial<TX, NRMAX, TRANS>(g, O, q, je);
+}
+
+// workgroups of the tiled operator resident at once on the current device
+int operator_tile_slots()
+{
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_operator_tile<double, false>,
+                                                     kBlock, 0) != hipSuccess)
+        return 1024;
+    return (per < 1 ? 1 : per) * (ncu < 1 ? 1 : ncu);
+}
+int operator_tiles(const Geom &g, int TX, int CZ) { return op_tiles(g.nx, g.ny, g.nz, TX, CZ); }
+
+// y = A x (or A^T x): the macro rows by 2.5D tiles of TX x (256/TX) nodes by
+// CZ layers (storing the reaction q per electrode node in qbuf), then the
+// particle rows one thread per value, when tile_tx > 0.  b - A x (b given)
+// and the per-workgroup sums of squares (partial given) use one thread per
+// node for everything.
 template <typename TX>
 void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, const double *kaph,
                      const double *gg, const double *ss, const double *ee, const double *mm,
                      const TX *x, double *y, const double *b, double *partial, int transpose,
-                     hipStream_t st)
+                     int tile_tx, int tile_cz, double *qbuf, hipStream_t st)
 {
-    const int nb = operator_blocks(g);
     OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, x, y, b};
+    if (!b && !partial && tile_tx > 0 && qbuf) {
+        const int nt = operator_tiles(g, tile_tx, tile_cz);
+        const int nr = (int)((g.ne + kBlock - 1) / kBlock);
+        if (transpose)
+            hipLaunchKernelGGL((k_operator_tile<TX, true>), dim3(nt), dim3(kBlock), 0, st, g, O, qbuf,
+                               tile_tx, tile_cz);
+        else
+            hipLaunchKernelGGL((k_operator_tile<TX, false>), dim3(nt), dim3(kBlock), 0, st, g, O, qbuf,
+                               tile_tx, tile_cz);
+#define P4D_OR(NR)                                                                                  \
+    do {                                                                                            \
+        if (transpose)                                                                              \
+            hipLaunchKernelGGL((k_operator_radial<TX, NR, true>), dim3(nr), dim3(kBlock), 0, st, g, O, \
+                               qbuf);                                                               \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_operator_radial<TX, NR, false>), dim3(nr), dim3(kBlock), 0, st, g,   \
+                               O, qbuf);                                                            \
+    } while (0)
+        P4D_NR_SWITCH(rad_nrmax(g), P4D_OR)
+#undef P4D_OR
+        return;
+    }
+    const int nb = operator_blocks(g);
 #define P4D_OP(NR, TR, RS) \
     hipLaunchKernelGGL((k_operator<TX, NR, TR, RS>), dim3(nb), dim3(kBlock), 0, st, g, O, partial)
 #define P4D_OP2(NR)                                        \
@@ -55,11 +109,11 @@ void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, c
 template void launch_operator<double>(const Geom &, const RadialTab *, const double *,
                                       const double *, const double *, const double *,
                                       const double *, const double *, const double *, double *,
-                                      const double *, double *, int, hipStream_t);
+                                      const double *, double *, int, int, int, double *, hipStream_t);
 template void launch_operator<float>(const Geom &, const RadialTab *, const double *,
                                      const double *, const double *, const double *,
                                      const double *, const double *, const float *, double *,
-                                     const double *, double *, int, hipStream_t);
+                                     const double *, double *, int, int, int, double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Gradients of J = w.x:  dJ/dp = -lambda^T (dA/dp) x.

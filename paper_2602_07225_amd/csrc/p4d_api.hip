@@ -64,7 +64,7 @@ struct p4d_ctx {
     // device arrays
     RadialTab *tabs = nullptr;
     double *sigh = nullptr, *kaph = nullptr, *gg = nullptr, *ss = nullptr, *ee = nullptr,
-           *mm = nullptr, *omega = nullptr;
+           *mm = nullptr, *omega = nullptr, *qbuf = nullptr;
     double *red = nullptr;         // partial sums
     size_t red_len = 0;
     double *hdev = nullptr, *cdev = nullptr, *invbeta = nullptr, *ydev = nullptr, *scal = nullptr;
@@ -80,6 +80,7 @@ struct p4d_ctx {
     double *hhost = nullptr;       // pinned host staging
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     int tiles_tuned = 0;           // set by the autotuner; else chosen at layout time
+    int op_tx = 64, op_cz = 4;     // operator tiles (op_tx = 0: one thread per node)
     Prof prof;
     // record mode: the preconditioner schedule is appended to a stage list
     // (std::vector<PStage<T>>) instead of being launched
@@ -236,6 +237,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->ee = (double *)take(8 * g.ne);
     c->mm = (double *)take(8 * g.ne);
     c->omega = (double *)take(8 * g.ne);
+    c->qbuf = (double *)take(8 * g.ne);          // reaction q of the tiled operator
     // reduction partials: streaming (kRedBlocks x 64), operator, gradient
     size_t rl = (size_t)kRedBlocks * 64;
     const size_t opb = (size_t)operator_blocks(g) + 1;
@@ -404,7 +406,7 @@ static void apply_op(p4d_ctx *c, int transpose, const TX *x, double *y, const do
                          16.0 * g.nelem + 32.0 * g.ne;
     ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
     launch_operator<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, x, y, b,
-                        partial, transpose, st);
+                        partial, transpose, c->op_tx, c->op_cz, c->qbuf, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,6 +1069,18 @@ static void default_tiles(p4d_ctx *c)
             c->tile_cz = cz;
         }
     }
+    // operator tiles: the same rule over the whole node grid
+    c->op_tx = c->tile_tx;
+    const long long oslots = operator_tile_slots();
+    best = -1;
+    for (int cz = 2; cz <= 16; cz++) {
+        const long long tiles = operator_tiles(c->g, c->op_tx, cz);
+        const long long cost = ((tiles + oslots - 1) / oslots) * (cz + 2);
+        if (best < 0 || cost < best) {
+            best = cost;
+            c->op_cz = cz;
+        }
+    }
 }
 
 static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o)
@@ -1537,14 +1551,16 @@ struct CellRun {
 
 // Cell tables of the batched kernels for restart length m (b and x may be
 // null when only the preconditioner is used); copied to the device.
+struct BatchGrid {
+    int op = 0, st = 0, tile = 0, rad = 0;   // workgroups of each batched launch kind
+};
 static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, double *const *xv,
-                               std::vector<BCell> &bc, int &opb, int &stb, hipStream_t st)
+                               std::vector<BCell> &bc, BatchGrid &G, hipStream_t st)
 {
     const int n = B->n;
     bc.assign(n, BCell{});
     std::vector<PCell> pcl(n);
-    opb = 0;
-    stb = 0;
+    G = BatchGrid{};
     for (int i = 0; i < n; i++) {
         p4d_ctx *c = B->cell[i];
         const Geom &g = c->g;
@@ -1552,12 +1568,21 @@ static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, dou
         std::memset((void *)&C, 0, sizeof(C));
         C.g = g;
         C.op = OpArgs{c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, nullptr, nullptr, nullptr};
-        C.op_blk0 = opb;
+        C.op_blk0 = G.op;
         C.op_nblk = operator_blocks(g);
-        opb += C.op_nblk;
-        C.st_blk0 = stb;
+        G.op += C.op_nblk;
+        C.st_blk0 = G.st;
         C.st_nblk = stream_blocks(g.N);
-        stb += C.st_nblk;
+        G.st += C.st_nblk;
+        C.op_tx = c->op_tx > 0 ? c->op_tx : 64;
+        C.op_cz = c->op_cz > 0 ? c->op_cz : 4;
+        C.tile_blk0 = G.tile;
+        C.tile_n = operator_tiles(g, C.op_tx, C.op_cz);
+        G.tile += C.tile_n;
+        C.rad_blk0 = G.rad;
+        C.rad_n = (int)((g.ne + kBlock - 1) / kBlock);
+        G.rad += C.rad_n;
+        C.qbuf = c->qbuf;
         C.V = (double *)c->scratch;
         C.Z = c->scratch + align_up(8 * (size_t)(m + 1) * g.N);
         C.x = xv ? xv[i] : nullptr;
@@ -1613,7 +1638,7 @@ template <typename T, typename TZ>
 static p4d_status batch_tune_t(p4d_batch *B, hipStream_t st)
 {
     std::vector<BCell> bc;
-    int opb = 0, stb = 0;
+    BatchGrid G;
     const unsigned long long all = B->n == 64 ? ~0ULL : ((1ULL << B->n) - 1);
     static const int czs[9] = {2, 3, 4, 5, 6, 8, 10, 12, 16};
     hipEvent_t e0, e1;
@@ -1628,7 +1653,7 @@ static p4d_status batch_tune_t(p4d_batch *B, hipStream_t st)
     for (int q = 0; q < 9 && s == P4D_OK; q++) {
         B->tile_cz = czs[q];
         s = batch_record<T>(B);
-        if (s == P4D_OK) s = batch_tables(B, B->ws_opts.restart, nullptr, nullptr, bc, opb, stb, st);
+        if (s == P4D_OK) s = batch_tables(B, B->ws_opts.restart, nullptr, nullptr, bc, G, st);
         if (s != P4D_OK) break;
         batch_apply_pc<T, TZ>(B, 0, 0, all, st);   // warm-up
         (void)hipEventRecord(e0, st);
@@ -1661,11 +1686,12 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
     const int n = B->n, m = o.restart;
     auto t0 = std::chrono::steady_clock::now();
     std::vector<BCell> bc;
-    int opb = 0, stb = 0;
+    BatchGrid G;
     {
-        const p4d_status ts = batch_tables(B, m, bv, xv, bc, opb, stb, st);
+        const p4d_status ts = batch_tables(B, m, bv, xv, bc, G, st);
         if (ts != P4D_OK) return ts;
     }
+    const int opb = G.op, stb = G.st;
 
     std::vector<CellRun> S(n);
     for (auto &R : S) {
@@ -1712,7 +1738,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                         bytes += 24.0 * g.N + 16.0 * g.nelem + 32.0 * g.ne;
                     }
                 ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
-                launch_bop<double>(B->bcell, n, rmask, 0, 1, transpose, opb, B->nrmax, st);
+                launch_bop<double>(B->bcell, n, rmask, 0, 1, transpose, opb, G.tile, G.rad, B->nrmax, st);
             }
             launch_bnorm_final(B->bcell, n, rmask, 0, 1, st);
             if ((ps = fetch()) != P4D_OK) return ps;
@@ -1767,7 +1793,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                         bytes += (sizeof(TZ) + 8.0) * g.N + 16.0 * g.nelem + 32.0 * g.ne;
                     }
                 ProfScope pr(B->prof, P4D_K_OPERATOR, bytes, st);
-                launch_bop<TZ>(B->bcell, n, act, k, 0, transpose, opb, B->nrmax, st);
+                launch_bop<TZ>(B->bcell, n, act, k, 0, transpose, opb, G.tile, G.rad, B->nrmax, st);
             }
             const int nv = k + 1;
             const int passes = o.cgs2 ? 2 : 1;

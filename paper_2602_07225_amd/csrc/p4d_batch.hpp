@@ -86,8 +86,12 @@ int bstage_sm0_slots();
 struct BCell {
     Geom g;
     OpArgs op;               // tables and coefficients (x, y, b set per launch)
-    int op_blk0, op_nblk;    // operator workgroups of this cell in the batched grid
+    int op_blk0, op_nblk;    // one-thread-per-node operator workgroups in the batched grid
     int st_blk0, st_nblk;    // streaming workgroups
+    int tile_blk0, tile_n;   // tiled operator workgroups
+    int rad_blk0, rad_n;     // particle-row workgroups
+    int op_tx, op_cz;        // operator tile shape
+    double *qbuf;            // reaction q per electrode node
     double *V;
     void *Z;
     double *x;
@@ -101,9 +105,11 @@ struct BCell {
 };
 
 void launch_bstart(const BCell *cells, int ncells, int nblk_st, hipStream_t st);
+// resid: V_0 = b - A x (one thread per node, with partial sums); else
+// V_{k+1} = A Z_k (tiled macro rows, then the particle rows)
 template <typename TZ>
 void launch_bop(const BCell *cells, int ncells, unsigned long long active, int k, int resid,
-                int transpose, int nblk_op, int nrmax, hipStream_t st);
+                int transpose, int nblk_op, int nblk_tile, int nblk_rad, int nrmax, hipStream_t st);
 void launch_bmdot(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,
                   int pass, hipStream_t st);
 void launch_borth(const BCell *cells, int ncells, unsigned long long active, int k, int nblk_st,

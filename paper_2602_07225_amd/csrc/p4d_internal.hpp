@@ -108,12 +108,17 @@ struct CoarseBatch {
 
 // ---- launchers (each defined beside its kernels) ---------------------------
 // operator.hip
+// tile_tx > 0 (and qbuf, n_e doubles): macro rows by 2.5D tiles, then the
+// particle rows (for y = A x without b or partial sums)
 template <typename TX>
 void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh,
                      const double *kaph, const double *gg, const double *ss, const double *ee,
                      const double *mm, const TX *x, double *y, const double *b,
-                     double *partial, int transpose, hipStream_t st);
+                     double *partial, int transpose, int tile_tx, int tile_cz, double *qbuf,
+                     hipStream_t st);
 int operator_blocks(const Geom &g);
+int operator_tiles(const Geom &g, int TX, int CZ);
+int operator_tile_slots();
 void launch_grad(const Geom &g, const RadialTab *tabs, const double *x, const double *lam,
                  double *dsigma, double *partial, hipStream_t st);
 void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t st);

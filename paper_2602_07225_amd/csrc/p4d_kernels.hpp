@@ -522,13 +522,126 @@ __device__ inline void load_nb(const Geom &g, const TX *f, long long n, int i, i
     }
 }
 
+// Stencil parts of the operator at one node, gathered either per node from
+// memory or from an LDS tile: K_kappa phi_e, K_kappa c_e, M_eps c_e and, on
+// electrode nodes, K_sigma phi_s, with the centre values (xpsc is phi_s as a
+// neighbour value: zero on the grounded layer).
+struct OpStencil {
+    double Kpe, xpe, Kce, Mce, xce, Kps, xpsc;
+};
+
+// Reaction coupling of one electrode node: the linearized reaction q and the
+// weights with which it enters the phi_s, phi_e, c_e and surface c_s rows
+// (a = (m, -m, -tc m, Gamma), b = (g, -g, e, s); transposed: a and b swap).
+struct OpCoupling {
+    double q, r0, r1, r2, r3;
+};
+template <bool TRANS>
+__device__ inline OpCoupling op_coupling(const Geom &g, const RadialTab &T, bool dir, double m,
+                                         double gj, double sj, double ej, double xpsc, double xpe,
+                                         double xce, double xsN)
+{
+    OpCoupling c;
+    const double a0 = dir ? 0.0 : m, b0 = dir ? 0.0 : gj;
+    if (!TRANS) {
+        c.q = b0 * xpsc - gj * xpe + ej * xce + sj * xsN;
+        c.r0 = a0; c.r1 = -m; c.r2 = -g.tc * m; c.r3 = T.Gamma;
+    } else {
+        c.q = a0 * xpsc - m * xpe - g.tc * m * xce + T.Gamma * xsN;
+        c.r0 = b0; c.r1 = -gj; c.r2 = ej; c.r3 = sj;
+    }
+    return c;
+}
+
+// Row r of T0 (or T0^T) applied to a particle column, without the coupling
+__device__ inline double op_radial_row(const RadialTab &T, bool trans, int r, int N, double xm,
+                                       double x0, double xp)
+{
+    if (!trans) return T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
+    return T.tdia[r] * x0 + (r > 0 ? T.tsup[r > 0 ? r - 1 : 0] : 0.0) * xm +
+           (r < N - 1 ? T.tsub[r + 1 < kMaxNr ? r + 1 : r] : 0.0) * xp;
+}
+
+// Everything after the stencil parts: reaction coupling, radial rows and
+// the output (y, or b - A x when RESID); returns the sum of squares written.
 template <typename TX, int NRMAX, bool TRANS, bool RESID>
-__device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
+__device__ inline double operator_finish(const Geom &g, const OpArgs &O, long long n, int i, int j,
+                                         int k, const OpStencil &P)
 {
     const TX *x = (const TX *)O.x;
     double *y = O.y;
     const double *b = O.b;
     double sq = 0.0;
+    const double xpe = P.xpe, xce = P.xce;
+    double ype, yce;
+    if (!TRANS) {
+        ype = P.Kpe + g.chi * P.Kce;
+        yce = P.Mce + P.Kce;
+    } else {
+        ype = P.Kpe;
+        yce = P.Mce + P.Kce + g.chi * P.Kpe;
+    }
+    const int el = node_mat(g, k);
+    if (el >= 0) {
+        const long long base = el == 0 ? 0 : g.nea;
+        const int klo = el == 0 ? 0 : g.na + g.ns;
+        const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
+        const bool dir = (k == 0);
+        const double xps = ldx(x + je);
+        const RadialTab &T = O.tabs[el];
+        const int N = T.N;
+        const long long nn = el == 0 ? g.nea : g.nec;
+        const long long jl = je - base;
+        const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+        const TX *xs = x + offs + jl;
+        double *ys = y + offs + jl;
+        const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
+        // the particle column, loaded at once (indices clamped to the last point)
+        double xr[NRMAX];
+#pragma unroll
+        for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+        double xsN = xr[0];
+#pragma unroll
+        for (int r = 1; r < NRMAX; r++)
+            if (r == N - 1) xsN = xr[r];
+        const OpCoupling cp = op_coupling<TRANS>(g, T, dir, m, gj, sj, ej, P.xpsc, xpe, xce, xsN);
+        const double q = cp.q, r3 = cp.r3;
+        double yps = dir ? xps : P.Kps + cp.r0 * q;
+        ype += cp.r1 * q;
+        yce += cp.r2 * q;
+        if (RESID) yps = b[je] - yps;
+        y[je] = yps;
+        sq += yps * yps;
+#pragma unroll
+        for (int r = 0; r < NRMAX; r++) {
+            if (r < N) {
+                const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
+                const double x0 = xr[r];
+                const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
+                double v = op_radial_row(T, TRANS, r, N, xm, x0, xp);
+                if (r == N - 1) v += r3 * q;
+                if (RESID) v = b[offs + jl + (long long)r * nn] - v;
+                ys[(long long)r * nn] = v;
+                sq += v * v;
+            }
+        }
+    }
+    if (RESID) {
+        ype = b[g.off_pe + n] - ype;
+        yce = b[g.off_ce + n] - yce;
+    }
+    y[g.off_pe + n] = ype;
+    y[g.off_ce + n] = yce;
+    sq += ype * ype + yce * yce;
+    return sq;
+}
+
+// The operator y = A x (or A^T x, or b - A x) at one node, every stencil
+// value read from memory (paper Sec. 4.1, eq. blocks; see operator.hip).
+template <typename TX, int NRMAX, bool TRANS, bool RESID>
+__device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
+{
+    const TX *x = (const TX *)O.x;
     const int i = (int)(n % g.nx);
     const long long t = n / g.nx;
     const int j = (int)(t % g.ny), k = (int)(t / g.ny);
@@ -543,29 +656,23 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         cs[e] = ok ? O.sigh[id] : 0.0;
         cm[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
     }
+    OpStencil P;
     double X[27];
     load_nb(g, x + g.off_pe, n, i, j, k, X);
-    const double Kpe = q1_stiff(ck, X);
-    const double xpe = X[13];
+    P.Kpe = q1_stiff(ck, X);
+    P.xpe = X[13];
     load_nb(g, x + g.off_ce, n, i, j, k, X);
-    const double Kce = q1_stiff(ck, X);
-    const double Mce = q1_mass(cm, X);
-    const double xce = X[13];
-    double ype, yce;
-    if (!TRANS) {
-        ype = Kpe + g.chi * Kce;
-        yce = Mce + Kce;
-    } else {
-        ype = Kpe;
-        yce = Mce + Kce + g.chi * Kpe;
-    }
+    P.Kce = q1_stiff(ck, X);
+    P.Mce = q1_mass(cm, X);
+    P.xce = X[13];
+    P.Kps = 0.0;
+    P.xpsc = 0.0;
     const int el = node_mat(g, k);
     if (el >= 0) {
         const long long base = el == 0 ? 0 : g.nea;
         const int klo = el == 0 ? 0 : g.na + g.ns;
         const int khi = el == 0 ? g.na - 1 : g.nz - 1;
         const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
-        const bool dir = (k == 0);
         // phi_s neighbours: same electrode, grounded layer as a zero column
 #pragma unroll
         for (int o = 0; o < 27; o++) {
@@ -574,65 +681,224 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
                             (k + dz >= klo) && (k + dz <= khi) && (k + dz != 0);
             X[o] = ok ? ldx(x + je + dx + (long long)g.nx * (dy + (long long)g.ny * dz)) : 0.0;
         }
-        const double xps = ldx(x + je);
-        const RadialTab &T = O.tabs[el];
-        const int N = T.N;
-        const long long nn = el == 0 ? g.nea : g.nec;
-        const long long jl = je - base;
-        const TX *xs = x + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl;
-        double *ys = y + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl;
-        const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
-        // the particle column, loaded at once (indices clamped to the last point)
-        double xr[NRMAX];
+        P.Kps = q1_stiff(cs, X);
+        P.xpsc = X[13];
+    }
+    return operator_finish<TX, NRMAX, TRANS, RESID>(g, O, n, i, j, k, P);
+}
+
+// ---------------------------------------------------------------------------
+// The operator over a 2.5D tile (the level-0 smoother's scheme): a TX x TY
+// block of nodes marches through CZ node layers; three planes of phi_e, c_e
+// and phi_s with a one-node halo and two layers of element coefficients sit
+// in LDS rings, fetched into registers one layer ahead.  Each node's
+// arithmetic is operator_finish on the same stencil values as operator_node,
+// so both give the same result.
+// ---------------------------------------------------------------------------
+struct OpLds {
+    double pe[3][kXpLds], ce[3][kXpLds], ps[3][kXpLds];
+    double kap[2][kCkLds], sig[2][kCkLds];
+};
+
+__host__ __device__ inline int op_tiles(int nx, int ny, int nz, int TX, int CZ)
+{
+    return smooth0_box_tiles(nx, ny, nz, TX, CZ);
+}
+
+template <typename TX_T, bool TRANS>
+__device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qout, int tile, int TX,
+                                     int CZ, OpLds &L)
+{
+    const TX_T *x = (const TX_T *)O.x;
+    const int TY = kBlock / TX;
+    const int PX = TX + 2, PY = TY + 2;
+    const int EX = TX + 1, EY = TY + 1;
+    const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
+    const int tix = tile % ntx, tiy = (tile / ntx) % nty, tch = tile / (ntx * nty);
+    const int i0 = tix * TX, j0 = tiy * TY, k0 = tch * CZ;
+    const int k1 = k0 + CZ < g.nz ? k0 + CZ : g.nz;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < g.nx && j < g.ny;
+    const long long layer = (long long)g.nx * g.ny;
+
+    double pe[2], ce[2], ps[2], kp[2], sg[2];
+    auto fetch_planes = [&](int kk) {
+        const int el = (kk >= 0 && kk < g.nz) ? node_mat(g, kk) : -1;
+        const bool has_ps = el >= 0 && kk != 0;
+        const long long psb = el == 0 ? 0 : g.nea - (long long)(g.na + g.ns) * layer;
 #pragma unroll
-        for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
-        double xsN = xr[0];
-#pragma unroll
-        for (int r = 1; r < NRMAX; r++)
-            if (r == N - 1) xsN = xr[r];
-        // a = (m, -m, -tc m, Gamma) rows, b = (g, -g, e, s) columns
-        const double a0 = dir ? 0.0 : m, b0 = dir ? 0.0 : gj;
-        double q, r0, r1, r2, r3;
-        if (!TRANS) {
-            q = b0 * X[13] - gj * xpe + ej * xce + sj * xsN;
-            r0 = a0; r1 = -m; r2 = -g.tc * m; r3 = T.Gamma;
-        } else {
-            q = a0 * X[13] - m * xpe - g.tc * m * xce + T.Gamma * xsN;
-            r0 = b0; r1 = -gj; r2 = ej; r3 = sj;
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
+            const bool ok = q < PX * PY && kk >= 0 && kk < g.nz && ii >= 0 && ii < g.nx && jj >= 0 &&
+                            jj < g.ny;
+            const long long nd = ii + g.nx * (jj + (long long)g.ny * kk);
+            pe[h] = ok ? ldx(x + g.off_pe + nd) : 0.0;
+            ce[h] = ok ? ldx(x + g.off_ce + nd) : 0.0;
+            ps[h] = (ok && has_ps) ? ldx(x + (psb + nd)) : 0.0;
         }
-        double yps = dir ? xps : q1_stiff(cs, X) + r0 * q;
-        ype += r1 * q;
-        yce += r2 * q;
-        if (RESID) yps = b[je] - yps;
-        y[je] = yps;
-        sq += yps * yps;
+    };
+    auto store_planes = [&](int slot) {
 #pragma unroll
-        for (int r = 0; r < NRMAX; r++) {
-            if (r < N) {
-                const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
-                const double x0 = xr[r];
-                const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
-                double v;
-                if (!TRANS)
-                    v = T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
-                else
-                    v = T.tdia[r] * x0 + (r > 0 ? T.tsup[r > 0 ? r - 1 : 0] : 0.0) * xm +
-                        (r < N - 1 ? T.tsub[r + 1 < NRMAX ? r + 1 : r] : 0.0) * xp;
-                if (r == N - 1) v += r3 * q;
-                if (RESID) v = b[(el == 0 ? g.off_cs[0] : g.off_cs[1]) + jl + (long long)r * nn] - v;
-                ys[(long long)r * nn] = v;
-                sq += v * v;
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            if (q < PX * PY) {
+                L.pe[slot][q] = pe[h];
+                L.ce[slot][q] = ce[h];
+                L.ps[slot][q] = ps[h];
             }
         }
+    };
+    auto fetch_elems = [&](int ek) {
+        const bool lay = ek >= 0 && ek < g.nz - 1;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
+            const bool ok = q < EX * EY && lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
+            const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+            kp[h] = ok ? O.kaph[id] : 0.0;
+            sg[h] = ok ? O.sigh[id] : 0.0;
+        }
+    };
+    auto store_elems = [&](int slot) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int q = threadIdx.x + h * kBlock;
+            if (q < EX * EY) {
+                L.kap[slot][q] = kp[h];
+                L.sig[slot][q] = sg[h];
+            }
+        }
+    };
+    fetch_planes(k0 - 1);
+    store_planes((k0 + 2) % 3);
+    fetch_planes(k0);
+    store_planes(k0 % 3);
+    fetch_elems(k0 - 1);
+    store_elems((k0 + 1) & 1);
+    fetch_planes(k0 + 1);
+    fetch_elems(k0);
+    for (int k = k0; k < k1; k++) {
+        store_planes((k + 1) % 3);
+        store_elems(k & 1);
+        __syncthreads();
+        if (k + 1 < k1) {
+            fetch_planes(k + 2);
+            fetch_elems(k + 1);
+        }
+        if (own) {
+            double ck[8], cs[8], cm[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                const int q = (tx + ex) + EX * (ty + ey);
+                ck[e] = L.kap[(k - 1 + ez) & 1][q];
+                cs[e] = L.sig[(k - 1 + ez) & 1][q];
+                const int ek = k - 1 + ez;
+                // the element exists iff its kappa coefficient slot was filled;
+                // decide by the indices, as the per-node gather does
+                const int ei = i - 1 + ex, ej = j - 1 + ey;
+                const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                                ek < g.nz - 1;
+                cm[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+            }
+            OpStencil P;
+            double X[27];
+            auto gather = [&](const double (*F)[kXpLds]) {
+#pragma unroll
+                for (int dz = -1; dz <= 1; dz++) {
+                    const double *Pl = F[(k + dz + 3) % 3];
+#pragma unroll
+                    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; dx++)
+                            X[nb_index(dx, dy, dz)] = Pl[(tx + 1 + dx) + PX * (ty + 1 + dy)];
+                }
+            };
+            // one field at a time: the scheduling barriers keep the three
+            // 27-value gathers from being hoisted together (register use)
+            gather(L.pe);
+            P.Kpe = q1_stiff(ck, X);
+            P.xpe = X[13];
+            __builtin_amdgcn_sched_barrier(0);
+            gather(L.ce);
+            P.Kce = q1_stiff(ck, X);
+            P.Mce = q1_mass(cm, X);
+            P.xce = X[13];
+            __builtin_amdgcn_sched_barrier(0);
+            P.Kps = 0.0;
+            P.xpsc = 0.0;
+            if (node_mat(g, k) >= 0) {
+                gather(L.ps);
+                P.Kps = q1_stiff(cs, X);
+                P.xpsc = X[13];
+            }
+            const long long n = i + (long long)g.nx * j + layer * k;
+            double ype, yce;
+            if (!TRANS) {
+                ype = P.Kpe + g.chi * P.Kce;
+                yce = P.Mce + P.Kce;
+            } else {
+                ype = P.Kpe;
+                yce = P.Mce + P.Kce + g.chi * P.Kpe;
+            }
+            const int el = node_mat(g, k);
+            if (el >= 0) {
+                const long long base = el == 0 ? 0 : g.nea;
+                const int klo = el == 0 ? 0 : g.na + g.ns;
+                const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
+                const bool dir = (k == 0);
+                const RadialTab &T = O.tabs[el];
+                const long long nn = el == 0 ? g.nea : g.nec;
+                const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+                const double xsN = ldx(x + offs + (je - base) + (long long)(T.N - 1) * nn);
+                const OpCoupling cp = op_coupling<TRANS>(g, T, dir, O.mm[je], O.gg[je], O.ss[je],
+                                                         O.ee[je], P.xpsc, P.xpe, P.xce, xsN);
+                O.y[je] = dir ? ldx(x + je) : P.Kps + cp.r0 * cp.q;
+                ype += cp.r1 * cp.q;
+                yce += cp.r2 * cp.q;
+                qout[je] = cp.q;
+            }
+            O.y[g.off_pe + n] = ype;
+            O.y[g.off_ce + n] = yce;
+        }
+        __syncthreads();
     }
-    if (RESID) {
-        ype = b[g.off_pe + n] - ype;
-        yce = b[g.off_ce + n] - yce;
+}
+
+
+// The particle rows of y = A x (or A^T x) for one electrode node je: row r
+// of T0 applied to its column (loaded at once, indices clamped to the last
+// point), plus the coupling weight times q (stored by operator_tile) on the
+// surface row.
+template <typename TX_T, int NRMAX, bool TRANS>
+__device__ inline void operator_radial(const Geom &g, const OpArgs &O, const double *q, long long je)
+{
+    const TX_T *x = (const TX_T *)O.x;
+    const int el = je < g.nea ? 0 : 1;
+    const long long nn = el == 0 ? g.nea : g.nec;
+    const long long jl = el == 0 ? je : je - g.nea;
+    const RadialTab &T = O.tabs[el];
+    const int N = T.N;
+    const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+    const TX_T *xs = x + offs + jl;
+    double *ys = O.y + offs + jl;
+    double xr[NRMAX];
+#pragma unroll
+    for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+    const double r3 = TRANS ? O.ss[je] : T.Gamma, qj = q[je];
+#pragma unroll
+    for (int r = 0; r < NRMAX; r++) {
+        if (r < N) {
+            const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
+            const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
+            double v = op_radial_row(T, TRANS, r, N, xm, xr[r], xp);
+            if (r == N - 1) v += r3 * qj;   // the same expression as in operator_finish
+            ys[(long long)r * nn] = v;
+        }
     }
-    y[g.off_pe + n] = ype;
-    y[g.off_ce + n] = yce;
-    sq += ype * ype + yce * yce;
-    return sq;
 }
 
 }  // namespace p4d
