@@ -1053,8 +1053,18 @@ p4d_status p4d_set_workspace(p4d_ctx *c, void *d_work, size_t bytes, const p4d_s
 // so that the last round of tiles is not nearly empty.
 static void default_tiles(p4d_ctx *c)
 {
-    const int nx = c->g.nx;
-    c->tile_tx = nx >= 48 ? 64 : (nx >= 24 ? 32 : 16);
+    // tile width: the one whose tiles cover the x-y plane with the fewest
+    // idle lanes (the wider one on ties, for longer contiguous rows)
+    const int nx = c->g.nx, ny = c->g.ny;
+    double bestcov = -1.0;
+    for (int tx = 16; tx <= 64; tx *= 2) {
+        const int ty = kBlock / tx;
+        const double cov = (double)nx * ny / ((double)((nx + tx - 1) / tx) * tx * ((ny + ty - 1) / ty) * ty);
+        if (cov >= bestcov) {
+            bestcov = cov;
+            c->tile_tx = tx;
+        }
+    }
     const long long slots = smooth0_slots();
     long long best = -1;
     for (int cz = 2; cz <= 16; cz++) {
@@ -1561,6 +1571,22 @@ static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, dou
     bc.assign(n, BCell{});
     std::vector<PCell> pcl(n);
     G = BatchGrid{};
+    // operator tile depth for the batch as a whole (same rule as the
+    // single-cell default, over the tiles of all cells)
+    int opcz = 8;
+    {
+        const long long slots = operator_tile_slots();
+        long long best = -1;
+        for (int cz = 2; cz <= 16; cz++) {
+            long long tiles = 0;
+            for (p4d_ctx *c : B->cell) tiles += operator_tiles(c->g, c->op_tx > 0 ? c->op_tx : 64, cz);
+            const long long cost = ((tiles + slots - 1) / slots) * (cz + 2);
+            if (best < 0 || cost < best) {
+                best = cost;
+                opcz = cz;
+            }
+        }
+    }
     for (int i = 0; i < n; i++) {
         p4d_ctx *c = B->cell[i];
         const Geom &g = c->g;
@@ -1575,7 +1601,7 @@ static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, dou
         C.st_nblk = stream_blocks(g.N);
         G.st += C.st_nblk;
         C.op_tx = c->op_tx > 0 ? c->op_tx : 64;
-        C.op_cz = c->op_cz > 0 ? c->op_cz : 4;
+        C.op_cz = opcz;
         C.tile_blk0 = G.tile;
         C.tile_n = operator_tiles(g, C.op_tx, C.op_cz);
         G.tile += C.tile_n;
