@@ -37,6 +37,33 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 PC_SCHUR = 0
 PC_BJ = 1
+PC_BGS = 2
+
+# fields of the 4x4 block system as numbered in a block ordering
+F_PHIS, F_PHIE, F_CE, F_CS = 0, 1, 2, 3
+FIELD_NAMES = ("phi_s", "phi_e", "c_e", "c_s")
+
+
+def bgs_order(fields):
+    """Pack a field ordering (a permutation of 0..3, first block first) as
+    the preconditioner option: the field at block position p in bits
+    [2p, 2p + 2)."""
+    fields = tuple(int(f) for f in fields)
+    if sorted(fields) != [0, 1, 2, 3]:
+        raise ValueError(f"{fields} is not an ordering of the four fields")
+    return sum(f << (2 * p) for p, f in enumerate(fields))
+
+
+def bgs_order_fields(order):
+    """Inverse of bgs_order."""
+    fields = tuple((int(order) >> (2 * p)) & 3 for p in range(4))
+    if sorted(fields) != [0, 1, 2, 3] or int(order) >> 8:
+        raise ValueError(f"{order} is not a packed field ordering")
+    return fields
+
+
+# the ordering of the paper's scaling runs (Sec. 5): (phi_e, c_s, phi_s, c_e)
+BGS_PAPER = bgs_order((F_PHIE, F_CS, F_PHIS, F_CE))
 
 _dp = C.POINTER(C.c_double)
 
@@ -53,7 +80,8 @@ class Desc(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("cgs2", C.c_int32), ("rtol", C.c_double),
-                ("coarse_max", C.c_int32), ("cheb_degree", C.c_int32)]
+                ("coarse_max", C.c_int32), ("cheb_degree", C.c_int32),
+                ("bgs_order", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -223,12 +251,15 @@ class Oracle:
 
     # -- preconditioner --------------------------------------------------------
     def setup(self, pc=PC_SCHUR, restart=30, maxit=1000, rtol=1e-8, cgs2=False,
-              coarse_max=64, cheb_degree=2):
+              coarse_max=64, cheb_degree=2, bgs_order=BGS_PAPER):
         o = Opts()
         o.pc, o.restart, o.maxit, o.cgs2 = pc, restart, maxit, int(cgs2)
         o.rtol, o.coarse_max, o.cheb_degree = rtol, coarse_max, cheb_degree
+        o.bgs_order = bgs_order
         if restart > 63:
             raise ValueError("restart must be <= 63")
+        if pc == PC_BGS:
+            bgs_order_fields(bgs_order)   # raises unless a permutation
         self.opts = o
         lib().orc_setup(self.h, C.byref(o))
         return self

@@ -17,9 +17,11 @@
  *   Sec. 3.3   backward Euler.
  *   Sec. 4.1   block residual and 4x4 block Jacobian (eq. blocks), c_s
  *              block-diagonal with one tridiagonal N_c x N_c block per point.
- *   Sec. 4.2   block preconditioners: block Jacobi (eq. PJ); multigrid for
- *              the electrode-level blocks; exact element-wise block Jacobi
- *              (tridiagonal solves) for c_s.
+ *   Sec. 4.2   block preconditioners: block Jacobi (eq. PJ), block
+ *              Gauss-Seidel in any of the 24 field orderings (eq. PGS, the
+ *              ordering study of Sec. 5); multigrid for the electrode-level
+ *              blocks; exact element-wise block Jacobi (tridiagonal solves)
+ *              for c_s.
  *
  * Readings where the paper is silent or ambiguous (each also listed in the
  * design notes of the repository):
@@ -66,16 +68,20 @@ typedef struct {
     double dt, chi, tc, lambda_c, eps_elec, eps_sep;
 } orc_desc;
 
-enum { ORC_PC_SCHUR = 0, ORC_PC_BJ = 1 };
+enum { ORC_PC_SCHUR = 0, ORC_PC_BJ = 1, ORC_PC_BGS = 2 };
+
+/* fields of the 4x4 block system, as numbered in a block ordering           */
+enum { ORC_F_PHIS = 0, ORC_F_PHIE = 1, ORC_F_CE = 2, ORC_F_CS = 3 };
 
 typedef struct {
-    int32_t pc;            /* ORC_PC_SCHUR or ORC_PC_BJ                         */
+    int32_t pc;            /* ORC_PC_SCHUR, ORC_PC_BJ or ORC_PC_BGS             */
     int32_t restart;       /* FGMRES restart length m                          */
     int32_t maxit;         /* total inner iterations                           */
     int32_t cgs2;          /* 1: classical Gram-Schmidt applied twice           */
     double rtol;
     int32_t coarse_max;    /* direct solve once a grid has <= this many nodes */
     int32_t cheb_degree;
+    int32_t bgs_order;     /* BGS: field at block position p is bits [2p, 2p+2) */
 } orc_opts;
 
 typedef struct {
@@ -878,6 +884,14 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
 /* ------------------------------------------------------------------------ */
 void orc_setup(orc_problem *P, const orc_opts *o)
 {
+    if (o->pc == ORC_PC_BGS) {   /* the ordering must be a permutation */
+        int seen = 0;
+        for (int p = 0; p < 4; p++) seen |= 1 << ((o->bgs_order >> (2 * p)) & 3);
+        if (seen != 15 || (o->bgs_order >> 8) != 0) {
+            fprintf(stderr, "oracle: bgs_order %d is not a field ordering\n", o->bgs_order);
+            abort();
+        }
+    }
     P->opts = *o;
     if (P->opts.coarse_max <= 0) P->opts.coarse_max = 512;
     if (P->opts.cheb_degree <= 0) P->opts.cheb_degree = 2;
@@ -890,8 +904,8 @@ void orc_setup(orc_problem *P, const orc_opts *o)
         for (long jl = 0; jl < nn; jl++) {
             long je = base + jl;
             /* Sherman-Morrison: 1 - Gamma s (A_ss^-1)_NN = 1/(1 + Gamma s tau0) */
-            P->omega[je] = o->pc == ORC_PC_BJ ? 1.0
-                                              : 1.0 / (1.0 + P->Gamma[el] * P->s[je] * t0);
+            P->omega[je] = o->pc != ORC_PC_SCHUR ? 1.0
+                                                 : 1.0 / (1.0 + P->Gamma[el] * P->s[je] * t0);
         }
     }
     for (int b = 0; b < 4; b++) mg_build(P, b);
@@ -910,16 +924,128 @@ static void box_slice(const orc_problem *P, int box, long *off, long *n)
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Block Gauss-Seidel (eq. PGS) in a chosen field ordering o_0, ..., o_3.    */
+/* ------------------------------------------------------------------------ */
+/* Rows of field f minus the blocks A_{f,g} z_g of the fields g already solved
+ * (done[g] != 0).  The off-diagonal blocks of A are the node-local reaction
+ * terms a_f,j b_g,j (over phi_s, phi_e, c_e and the c_s surface value, the
+ * c_s row being the surface row) and chi K_kappa in the (phi_e row, c_e
+ * column) block.  Transposed, the blocks are those of A^T: the roles of a
+ * and b swap and chi K_kappa sits in the (c_e row, phi_e column) block.     */
+static void bgs_subtract(const orc_problem *P, int transpose, int f, const int *done,
+                         const double *z, double *t)
+{
+    const orc_desc *d = &P->d;
+    const double *zps = z + P->off_ps, *zpe = z + P->off_pe, *zce = z + P->off_ce;
+    for (int k = 0; k < d->nz; k++) {
+        int el = node_mat(P, k);
+        if (el < 0) continue;
+        int N = d->nr[el];
+        long nn = el == 0 ? P->nea : P->nec, base = el == 0 ? 0 : P->nea;
+        int dir = is_dirichlet(P, k);
+        for (int j = 0; j < d->ny; j++)
+            for (int i = 0; i < d->nx; i++) {
+                long n = node_id(P, i, j, k), je = enode(P, i, j, k), jl = je - base;
+                long srow = P->off_cs[el] + (long)(N - 1) * nn + jl;
+                double a[4] = { dir ? 0.0 : P->m[je], -P->m[je], -d->tc * P->m[je],
+                                P->Gamma[el] };
+                double b[4] = { dir ? 0.0 : P->g[je], -P->g[je], P->e[je], P->s[je] };
+                double zl[4] = { zps[je], zpe[n], zce[n], z[srow] };
+                const double *rowc = transpose ? b : a, *colc = transpose ? a : b;
+                double q = 0.0;
+                for (int g = 0; g < 4; g++)
+                    if (done[g]) q += colc[g] * zl[g];
+                long row = f == ORC_F_PHIS ? P->off_ps + je
+                         : f == ORC_F_PHIE ? P->off_pe + n
+                         : f == ORC_F_CE   ? P->off_ce + n : srow;
+                t[row] -= rowc[f] * q;
+            }
+    }
+    /* chi K_kappa: A_{phi_e, c_e} (A^T_{c_e, phi_e} when transposed) */
+    int krow = transpose ? ORC_F_CE : ORC_F_PHIE, kcol = transpose ? ORC_F_PHIE : ORC_F_CE;
+    if (f == krow && done[kcol]) {
+        const double *zk = kcol == ORC_F_CE ? zce : zpe;
+        double *tk = t + (krow == ORC_F_PHIE ? P->off_pe : P->off_ce);
+        for (int k = 0; k < d->nz; k++)
+            for (int j = 0; j < d->ny; j++)
+                for (int i = 0; i < d->nx; i++)
+                    tk[node_id(P, i, j, k)] -=
+                        d->chi * elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, zk);
+    }
+}
+
+/* z_f = A_{f,f}^-1 t_f (A_{f,f}^-T when transposed): a V-cycle for the
+ * electrode-level fields (omega = 1, so the multigrid operator is the
+ * diagonal block itself), the exact tridiagonal solve for each c_s block.    */
+static void bgs_block_solve(const orc_problem *P, int transpose, int f, const double *t,
+                            double *z)
+{
+    const orc_desc *d = &P->d;
+    long off, n;
+    switch (f) {
+    case ORC_F_PHIS:
+        for (long q = 0; q < (long)d->nx * d->ny; q++) z[P->off_ps + q] = t[P->off_ps + q];
+        for (int b = 0; b < 2; b++) {
+            box_slice(P, b, &off, &n);
+            vcycle(P, &P->mg[b], 0, t + off, z + off);
+        }
+        break;
+    case ORC_F_PHIE:
+    case ORC_F_CE:
+        box_slice(P, f == ORC_F_PHIE ? 2 : 3, &off, &n);
+        vcycle(P, &P->mg[f == ORC_F_PHIE ? 2 : 3], 0, t + off, z + off);
+        break;
+    default:
+        for (int el = 0; el < 2; el++) {
+            int N = d->nr[el];
+            long nn = el == 0 ? P->nea : P->nec, base = el == 0 ? 0 : P->nea;
+            double *rhs = xmalloc(sizeof(double) * N), *sol = xmalloc(sizeof(double) * N);
+            double *w = xmalloc(sizeof(double) * 4 * N);
+            for (long jl = 0; jl < nn; jl++) {
+                for (int q = 0; q < N; q++) rhs[q] = t[P->off_cs[el] + (long)q * nn + jl];
+                radial_solve(P, el, P->s[base + jl], transpose, rhs, sol, w);
+                for (int q = 0; q < N; q++) z[P->off_cs[el] + (long)q * nn + jl] = sol[q];
+            }
+            free(rhs); free(sol); free(w);
+        }
+    }
+}
+
+/* P_GS is block lower triangular in the ordering: z_{o_p} = A_{o_p,o_p}^-1
+ * (r_{o_p} - sum_{q<p} A_{o_p,o_q} z_{o_q}), p = 0..3.  P_GS^T is block upper
+ * triangular, so the transposed sweep runs p = 3..0 with the blocks of A^T.  */
+static void apply_bgs(const orc_problem *P, int transpose, const double *r, double *z)
+{
+    double *t = xmalloc(sizeof(double) * P->N);
+    memcpy(t, r, sizeof(double) * P->N);
+    memset(z, 0, sizeof(double) * P->N);
+    int done[4] = { 0, 0, 0, 0 };
+    for (int s = 0; s < 4; s++) {
+        int p = transpose ? 3 - s : s;
+        int f = (P->opts.bgs_order >> (2 * p)) & 3;
+        bgs_subtract(P, transpose, f, done, z, t);
+        bgs_block_solve(P, transpose, f, t, z);
+        done[f] = 1;
+    }
+    free(t);
+}
+
 /* z = P^-1 r (or P^-T r).  SCHUR mode, per electrode node j:
  *   1. zeta_j = (A_ss,j^-1 r_s,j)_N                (A_ss,j^-T when transposed)
  *   2. r~_y  = r_y - a_y,j s_j zeta_j              (transposed: - b_y,j Gamma zeta_j)
  *   3. z_f   = V_f(r~_f) for f in {phi_s, phi_e, c_e}
  *   4. z_s,j = A_ss,j^-1 (r_s,j - Gamma (b_y,j . z_y,j) e_N)
  *                                                  (transposed: s_j (a_y,j . z_y,j))
- * BJ mode (eq. PJ): steps 2 and the correction in 4 are skipped.            */
+ * BJ mode (eq. PJ): steps 2 and the correction in 4 are skipped.  BGS mode:
+ * apply_bgs above.                                                          */
 void orc_apply_pc(const orc_problem *P, int transpose, const double *r, double *z)
 {
     const orc_desc *d = &P->d;
+    if (P->pc_type == ORC_PC_BGS) {
+        apply_bgs(P, transpose, r, z);
+        return;
+    }
     int schur = P->pc_type == ORC_PC_SCHUR;
     long Nm = P->off_cs[0];
     double *rt = xmalloc(sizeof(double) * Nm);

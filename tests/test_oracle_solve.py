@@ -1,5 +1,8 @@
-"""Pins of the oracle's preconditioner (Sec. 4.2: eq. PJ and the exact
-elimination of the particle blocks), FGMRES solve and parameter gradients."""
+"""Pins of the oracle's preconditioner (Sec. 4.2: eq. PJ, eq. PGS in every
+field ordering, and the exact elimination of the particle blocks), FGMRES
+solve and parameter gradients."""
+import itertools
+
 import numpy as np
 import pytest
 
@@ -65,6 +68,74 @@ def test_block_jacobi_is_eq_PJ(transpose):
     assert np.allclose(orc.apply_pc(r, transpose), ref, atol=1e-10 * np.abs(ref).max())
 
 
+def field_blocks(p):
+    """Index ranges of phi_s, phi_e, c_e and c_s (both electrodes)."""
+    o = p.offsets
+    return [(o[0], o[1]), (o[1], o[2]), (o[2], o[3]), (o[3], o[5])]
+
+
+def pgs_dense(A, blocks, fields):
+    """eq. PGS written in the field ordering `fields` (first block first):
+    the blocks A_{f,g} with g at or before f in the ordering, zero after."""
+    P = np.zeros_like(A)
+    pos = {f: i for i, f in enumerate(fields)}
+    for f in range(4):
+        for g in range(4):
+            if pos[g] <= pos[f]:
+                (a, b), (c, d) = blocks[f], blocks[g]
+                P[a:b, c:d] = A[a:b, c:d]
+    return P
+
+
+ALL_ORDERINGS = list(itertools.permutations(range(4)))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_block_gauss_seidel_is_eq_PGS_in_every_ordering(transpose):
+    """Mode BGS with direct block solves applies P_GS^-1 (P_GS^-T) of eq. PGS
+    for each of the 24 orderings; P_GS is built from the assembled A."""
+    p = tiny(4, sigma_log=1.0)
+    orc = O.Oracle(p)
+    A = orc.dense()
+    blocks = field_blocks(p)
+    r = np.random.default_rng(5).standard_normal(p.N)
+    for fields in ALL_ORDERINGS:
+        orc.setup(pc=O.PC_BGS, coarse_max=512, bgs_order=O.bgs_order(fields))
+        P = pgs_dense(A, blocks, fields)
+        ref = np.linalg.solve(P.T if transpose else P, r)
+        z = orc.apply_pc(r, transpose)
+        assert np.allclose(z, ref, rtol=0, atol=1e-10 * np.abs(ref).max()), fields
+
+
+def test_block_gauss_seidel_orderings_differ():
+    """The off-diagonal blocks are not zero: orderings give different P_GS^-1,
+    and reversing the ordering is not the transpose (a mistake that swapped
+    the sweep direction would pass a symmetric test)."""
+    p = tiny(6)
+    orc = O.Oracle(p)
+    r = np.random.default_rng(7).standard_normal(p.N)
+    zs = []
+    for fields in [(1, 3, 0, 2), (2, 1, 3, 0), (0, 1, 2, 3), (3, 2, 1, 0)]:
+        orc.setup(pc=O.PC_BGS, coarse_max=512, bgs_order=O.bgs_order(fields))
+        zs.append(orc.apply_pc(r))
+    for i in range(len(zs)):
+        for j in range(i):
+            assert np.linalg.norm(zs[i] - zs[j]) > 1e-6 * np.linalg.norm(zs[i])
+    orc.setup(pc=O.PC_BGS, coarse_max=512, bgs_order=O.bgs_order((0, 1, 2, 3)))
+    zt = orc.apply_pc(r, True)
+    assert np.linalg.norm(zt - zs[3]) > 1e-6 * np.linalg.norm(zt)
+
+
+def test_bgs_order_packing():
+    assert O.BGS_PAPER == O.bgs_order((O.F_PHIE, O.F_CS, O.F_PHIS, O.F_CE))
+    for fields in ALL_ORDERINGS:
+        assert O.bgs_order_fields(O.bgs_order(fields)) == fields
+    with pytest.raises(ValueError):
+        O.bgs_order((0, 1, 1, 3))
+    with pytest.raises(ValueError):
+        O.Oracle(tiny(0)).setup(pc=O.PC_BGS, bgs_order=0)
+
+
 def test_preconditioner_transpose_identity():
     """<P^-1 x, y> = <x, P^-T y> with multilevel V-cycles."""
     p = pi.make_custom(10, 9, 30, (6, 8), seed=5, sigma_log=1.0, corr_cells=3.0)
@@ -76,7 +147,7 @@ def test_preconditioner_transpose_identity():
         assert orc.apply_pc(x) @ y == pytest.approx(x @ orc.apply_pc(y, True), rel=1e-11)
 
 
-@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ])
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ, O.PC_BGS])
 @pytest.mark.parametrize("coarse_max", [512, 20])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_L1_solution_matches_dense_lu(pc, coarse_max, transpose):
@@ -138,15 +209,19 @@ def test_zero_rhs_and_iteration_cap():
     assert info.status == 1 and info.iters == 2
 
 
-def test_schur_mode_beats_block_jacobi_on_C1():
+def test_schur_mode_beats_block_gauss_seidel_and_jacobi_on_C1():
     p = pi.make_config(1)
     o1 = O.Oracle(p).setup(pc=O.PC_SCHUR)
     x1, i1 = o1.solve(p.b)
     o2 = O.Oracle(p).setup(pc=O.PC_BJ)
     x2, i2 = o2.solve(p.b)
-    assert i1.status == 0 and i2.status == 0
-    assert i1.iters < i2.iters
+    o3 = O.Oracle(p).setup(pc=O.PC_BGS)
+    x3, i3 = o3.solve(p.b)
+    assert i1.status == 0 and i2.status == 0 and i3.status == 0
+    # Sec. 5: block Gauss-Seidel needs fewer iterations than block Jacobi
+    assert i1.iters < i3.iters < i2.iters
     assert np.linalg.norm(x1 - x2) <= 1e-6 * np.linalg.norm(x1)
+    assert np.linalg.norm(x1 - x3) <= 1e-6 * np.linalg.norm(x1)
 
 
 def test_J2_gradient_matches_finite_differences():
