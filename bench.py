@@ -57,6 +57,34 @@ def measured_traffic(kernel_class):
     return None
 
 
+FIELD_NAMES = ("phi_s", "phi_e", "c_e", "c_s")
+
+
+def bgs_sweep(s, b, base):
+    """Block Gauss-Seidel (eq. PGS) in each of the 24 field orderings (the
+    ordering study of Sec. 5): iterations and time of one step each (setup +
+    solve, after one untimed step), two-pass Gram-Schmidt."""
+    import itertools
+    from paper_2602_07225_amd import _lib as L
+    rows = []
+    for fields in itertools.permutations(range(4)):
+        order = sum(f << (2 * q) for q, f in enumerate(fields))
+        opts = dict(base, pc=L.P4D_PC_BGS, bgs_order=order, cgs2=1)
+        try:
+            _, info, it, t, _ = timed_steps(s, b, opts, 1, 1)
+            rows.append({"ordering": [FIELD_NAMES[f] for f in fields], "iters": it,
+                         "ms_per_step": round(1e3 * t, 3)})
+        except RuntimeError as ex:
+            rows.append({"ordering": [FIELD_NAMES[f] for f in fields], "error": str(ex)})
+    ok = [r for r in rows if "iters" in r]
+    ok.sort(key=lambda r: (r["iters"], r["ms_per_step"]))
+    paper = [r for r in rows if r["ordering"] == ["phi_e", "c_s", "phi_s", "c_e"]]
+    return {"best": ok[0] if ok else None, "worst": ok[-1] if ok else None,
+            "paper_ordering": paper[0] if paper else None,
+            "iters_spread": (ok[-1]["iters"] / ok[0]["iters"] - 1.0) if ok else None,
+            "all": rows}
+
+
 def timed_steps(s, b, opts, steps, warmup, profile_mask=0):
     import torch
     from paper_2602_07225_amd import _lib as L
@@ -234,6 +262,23 @@ def main():
             log(f"[bench] BJ C2: {1e3 * tbj / 2:.2f} ms/step, {itbj / 2:.1f} it")
         except RuntimeError as ex:
             extras["block_jacobi_C2"] = {"error": str(ex)}
+        # block Gauss-Seidel (eq. PGS), the paper's ordering, both precisions;
+        # then all 24 orderings
+        bgs = dict(fp64, pc=L.P4D_PC_BGS, bgs_order=L.P4D_BGS_PAPER_ORDER, cgs2=1)
+        try:
+            _, _, itg, tg, _ = timed_steps(s, b, bgs, 2, 1)
+            _, _, itg32, tg32, _ = timed_steps(s, b, dict(bgs, pc_prec=L.P4D_FP32), 2, 1)
+            extras["block_gauss_seidel_C2"] = {
+                "ordering": ["phi_e", "c_s", "phi_s", "c_e"],
+                "fp64": {"ms_per_step": 1e3 * tg / 2, "iters_per_solve": itg / 2},
+                "fp32_precond": {"ms_per_step": 1e3 * tg32 / 2, "iters_per_solve": itg32 / 2}}
+            log(f"[bench] BGS C2: {1e3 * tg / 2:.2f} ms/step, {itg / 2:.1f} it; "
+                f"FP32-PC {1e3 * tg32 / 2:.2f} ms/step")
+        except RuntimeError as ex:
+            extras["block_gauss_seidel_C2"] = {"error": str(ex)}
+        extras["bgs_orderings_C2"] = bgs_sweep(s, b, fp64)
+        log(f"[bench] BGS orderings C2: best {extras['bgs_orderings_C2']['best']}, "
+            f"worst {extras['bgs_orderings_C2']['worst']}")
         # lognormal cube, both precisions
         p3 = pi.make_config(3)
         s3 = P4DSolver(p3, restart=30)
@@ -247,6 +292,9 @@ def main():
                                  (torch.linalg.norm(xb - xa) / torch.linalg.norm(xa)).item()},
             "speedup_fp32_vs_fp64": ta / tb}
         log(f"[bench] C3: fp64 {1e3 * ta / args.steps:.2f} ms, fp32 {1e3 * tb / args.steps:.2f} ms")
+        extras["bgs_orderings_C3"] = bgs_sweep(s3, b3, fp64)
+        log(f"[bench] BGS orderings C3: best {extras['bgs_orderings_C3']['best']}, "
+            f"worst {extras['bgs_orderings_C3']['worst']}")
         del s3
         # adjoint solve + gradients on C2 (J = mean phi_s on the cathode top face)
         w = torch.as_tensor(pi.functional_weights(p), device="cuda")

@@ -66,8 +66,17 @@ typedef enum {
 typedef enum {
     P4D_PC_SCHUR = 0,   /* particle blocks eliminated exactly, field-block diagonal
                            of the Schur complement to the V-cycles                 */
-    P4D_PC_BJ = 1       /* block Jacobi, paper eq. (PJ)                            */
+    P4D_PC_BJ = 1,      /* block Jacobi, paper eq. (PJ)                            */
+    P4D_PC_BGS = 2      /* block Gauss-Seidel, paper eq. (PGS), in the field ordering
+                           of p4d_solve_opts.bgs_order (single cells only)         */
 } p4d_pc_type;
+
+/* Field codes of a block Gauss-Seidel ordering: the field solved at block
+ * position p (p = 0 first) sits in bits [2p, 2p + 2) of bgs_order.  The
+ * paper's scaling runs use (phi_e, c_s, phi_s, c_e) (Sec. 5, ordering study),
+ * packed P4D_BGS_PAPER_ORDER. */
+enum { P4D_F_PHIS = 0, P4D_F_PHIE = 1, P4D_F_CE = 2, P4D_F_CS = 3 };
+#define P4D_BGS_PAPER_ORDER (P4D_F_PHIE | (P4D_F_CS << 2) | (P4D_F_PHIS << 4) | (P4D_F_CE << 6))
 
 typedef enum { P4D_FP64 = 0, P4D_FP32 = 1 } p4d_prec;
 
@@ -96,6 +105,8 @@ typedef struct {
     int32_t cgs2;          /* 1: Gram-Schmidt applied twice                       */
     int32_t z_fp32;        /* 1: store the preconditioned basis Z in FP32         */
     double rtol;           /* stop when ||b - A x|| <= rtol ||b||                 */
+    int32_t bgs_order;     /* P4D_PC_BGS: packed field ordering (see above); fixed
+                              at p4d_setup, a solve must pass the same value     */
 } p4d_solve_opts;
 
 typedef struct {
@@ -108,7 +119,8 @@ typedef struct {
 typedef struct p4d_ctx p4d_ctx;
 
 /* Fill opts with the defaults: SCHUR, FP64, restart 30, maxit 1000, Chebyshev
- * degree 2, coarse_max 64, one Gram-Schmidt pass, FP64 Z, rtol 1e-8.        */
+ * degree 2, coarse_max 64, one Gram-Schmidt pass, FP64 Z, rtol 1e-8, block
+ * Gauss-Seidel ordering P4D_BGS_PAPER_ORDER.                                */
 void p4d_default_opts(p4d_solve_opts *opts);
 
 /* Create a context for the problem `desc` on the current device.  Computes
@@ -190,10 +202,12 @@ p4d_status p4d_param_gradient(p4d_ctx *ctx, const double *d_x, const double *d_l
 
 /* Kernel timing with HIP events recorded on `stream` around every launch of
  * the kernel classes in `class_mask` (bit 1 << p4d_kernel_class; 0 switches
- * timing off and clears the totals).                                       */
+ * timing off and clears the totals).  P4D_K_COUPLING: the block Gauss-Seidel
+ * right-hand sides (off-diagonal blocks times solved fields) and output.   */
 typedef enum {
     P4D_K_OPERATOR = 1, P4D_K_MDOT = 2, P4D_K_ORTH = 3, P4D_K_RADIAL = 4,
-    P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_BATCH_PC = 7, P4D_K_COUNT = 8
+    P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_BATCH_PC = 7, P4D_K_COUPLING = 8,
+    P4D_K_COUNT = 9
 } p4d_kernel_class;
 p4d_status p4d_profile(p4d_ctx *ctx, int class_mask);
 /* For one class: total_ms = summed kernel durations, launches, and bytes =

@@ -23,14 +23,20 @@ P4D_ERR_NONFINITE = -5
 
 P4D_PC_SCHUR = 0
 P4D_PC_BJ = 1
+P4D_PC_BGS = 2
+# field codes of a block Gauss-Seidel ordering (bits [2p, 2p + 2) hold the
+# field at block position p)
+P4D_F_PHIS, P4D_F_PHIE, P4D_F_CE, P4D_F_CS = 0, 1, 2, 3
+P4D_BGS_PAPER_ORDER = P4D_F_PHIE | (P4D_F_CS << 2) | (P4D_F_PHIS << 4) | (P4D_F_CE << 6)
 P4D_FP64 = 0
 P4D_FP32 = 1
 
 (P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY,
- P4D_K_BATCH_PC) = range(1, 8)
+ P4D_K_BATCH_PC, P4D_K_COUPLING) = range(1, 9)
+P4D_K_COUNT = 9
 KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "orth",
                   P4D_K_RADIAL: "radial", P4D_K_SMOOTH0: "smooth0", P4D_K_ZY: "zy",
-                  P4D_K_BATCH_PC: "batch_pc"}
+                  P4D_K_BATCH_PC: "batch_pc", P4D_K_COUPLING: "coupling"}
 
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
@@ -55,7 +61,8 @@ class ProblemDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("pc_prec", C.c_int32), ("restart", C.c_int32),
                 ("maxit", C.c_int32), ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
-                ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double)]
+                ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double),
+                ("bgs_order", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -14,6 +14,7 @@
 
 #include "../../include/p4d.h"
 #include "p4d_batch.hpp"
+#include "p4d_bgs.hpp"
 
 using namespace p4d;
 
@@ -81,6 +82,7 @@ struct p4d_ctx {
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     int tiles_tuned = 0;           // set by the autotuner; else chosen at layout time
     int op_tx = 64, op_cz = 4;     // operator tiles (op_tx = 0: one thread per node)
+    int box_mask = 15;             // multigrid boxes a V-cycle runs on (bit per box)
     Prof prof;
     // record mode: the preconditioner schedule is appended to a stage list
     // (std::vector<PStage<T>>) instead of being launched
@@ -326,7 +328,15 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
 
 static bool opts_valid(const p4d_solve_opts &o, std::string &why)
 {
-    if (o.pc != P4D_PC_SCHUR && o.pc != P4D_PC_BJ) { why = "pc"; return false; }
+    if (o.pc != P4D_PC_SCHUR && o.pc != P4D_PC_BJ && o.pc != P4D_PC_BGS) { why = "pc"; return false; }
+    if (o.pc == P4D_PC_BGS) {
+        int seen = 0;
+        for (int p = 0; p < 4; p++) seen |= 1 << ((o.bgs_order >> (2 * p)) & 3);
+        if (seen != 15 || (o.bgs_order >> 8) != 0) {
+            why = "bgs_order must pack an ordering of the four fields";
+            return false;
+        }
+    }
     if (o.pc_prec != P4D_FP64 && o.pc_prec != P4D_FP32) { why = "pc_prec"; return false; }
     if (o.restart < 1 || o.restart > kMaxRestart) { why = "restart must be in 1..64"; return false; }
     if (o.maxit < 0) { why = "maxit"; return false; }
@@ -550,6 +560,7 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
 {
     int act[4], na = 0, crs[4], nc = 0;
     for (int b = 0; b < 4; b++) {
+        if (!((c->box_mask >> b) & 1)) continue;
         if (c->box[b].nlev - 1 > l) act[na++] = b;
         else if (c->box[b].nlev - 1 == l) crs[nc++] = b;
     }
@@ -667,10 +678,60 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
     launch_rad_back<T, TZ>(g, R, r, rscale, z, transpose, schur, st);
 }
 
+// z = P_GS^-1 (rscale r), or P_GS^-T (eq. PGS): the fields in the chosen
+// ordering (backwards when transposed), each V-cycle on the boxes of its own
+// field only; the level-0 iterates of the fields solved stay in place (each
+// box owns its slice of the level-0 buffers) and feed the later couplings.
+template <typename T, typename TZ>
+static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+                        hipStream_t st)
+{
+    const Geom &g = c->g;
+    BgsArgs B{};
+    B.R = rad_args(c);
+    B.kaph = c->kaph;
+    B.zsN = c->qbuf;
+    VState<T> vs{};
+    for (int b = 0; b < 4; b++) {
+        vs.xcur[b][0] = 0;
+        B.R.x0[b] = (const double *)c->x0a;
+    }
+    for (int s = 0; s < 4; s++) {
+        const int p = transpose ? 3 - s : s;
+        const int f = (c->pc.bgs_order >> (2 * p)) & 3;
+        B.field = f;
+        if (f == BF_CS) {
+            ProfScope ps(c->prof, P4D_K_RADIAL, 8.0 * (g.N - g.Nm) + 56.0 * g.ne + 16.0 * g.nnode +
+                                                   sizeof(TZ) * (g.N - g.Nm), st);
+            launch_bgs_cs<T, TZ>(g, B, r, rscale, z, transpose, st);
+        } else {
+            const double n = f == BF_PHIS ? (double)g.ne : (double)g.nnode;
+            {
+                ProfScope ps(c->prof, P4D_K_COUPLING, n * (8.0 + sizeof(T) * 2 + 8.0) + 48.0 * g.ne, st);
+                launch_bgs_rhs<T>(g, B, r, rscale, transpose, st);
+            }
+            const int boxes = f == BF_PHIS ? 3 : (f == BF_PHIE ? 4 : 8);   // phi_s: both electrodes
+            c->box_mask = boxes;
+            vcycle_level<T>(c, vs, 0, st);
+            c->box_mask = 15;
+            for (int b = 0; b < 4; b++)
+                if ((boxes >> b) & 1) B.R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
+        }
+        B.done |= 1 << f;
+    }
+    ProfScope ps(c->prof, P4D_K_COUPLING, (8.0 + sizeof(TZ)) * g.Nm, st);
+    launch_bgs_out<TZ>(g, B, r, rscale, z, st);
+}
+
 template <typename TZ>
 static void apply_pc(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
                      hipStream_t st)
 {
+    if (c->pc.pc == P4D_PC_BGS) {
+        if (c->prec == 1) apply_bgs_t<float, TZ>(c, transpose, r, rscale, z, st);
+        else apply_bgs_t<double, TZ>(c, transpose, r, rscale, z, st);
+        return;
+    }
     if (c->prec == 1) apply_pc_t<float, TZ>(c, transpose, r, rscale, z, st);
     else apply_pc_t<double, TZ>(c, transpose, r, rscale, z, st);
 }
@@ -940,6 +1001,7 @@ void p4d_default_opts(p4d_solve_opts *o)
     o->cgs2 = 0;
     o->z_fp32 = 0;
     o->rtol = 1e-8;
+    o->bgs_order = 1 | (3 << 2) | (0 << 4) | (2 << 6);   // (phi_e, c_s, phi_s, c_e)
 }
 
 const char *p4d_status_string(p4d_status s)
@@ -1207,7 +1269,7 @@ static p4d_status solve_common(p4d_ctx *c, int transpose, const double *b, doubl
     std::string why;
     if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
     if (o.pc != c->pc.pc || o.pc_prec != c->pc.pc_prec || o.cheb_degree != c->pc.cheb_degree ||
-        o.coarse_max != c->pc.coarse_max)
+        o.coarse_max != c->pc.coarse_max || (o.pc == P4D_PC_BGS && o.bgs_order != c->pc.bgs_order))
         return fail(c, P4D_ERR_STATE, "preconditioner options differ from the last setup");
     if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
         return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
@@ -2054,6 +2116,8 @@ p4d_status p4d_batch_setup(p4d_batch *B, const p4d_solve_opts *opts, void *strea
     if (!B->ready) return bfail(B, P4D_ERR_STATE, "p4d_batch_set_workspace first");
     p4d_solve_opts o = B->ws_opts;
     if (opts) o = *opts;
+    if (o.pc == P4D_PC_BGS)
+        return bfail(B, P4D_ERR_INVALID_ARG, "block Gauss-Seidel is available for single cells only");
     if (o.pc_prec != B->ws_opts.pc_prec || o.coarse_max != B->ws_opts.coarse_max ||
         o.restart > B->ws_opts.restart || (!o.z_fp32 && B->ws_opts.z_fp32))
         return bfail(B, P4D_ERR_STATE, "options differ from those the workspace was carved for");

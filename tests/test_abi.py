@@ -69,3 +69,17 @@ def test_default_options(L):
     o = _lib.default_opts()
     assert (o.pc, o.pc_prec, o.restart, o.maxit, o.cheb_degree, o.coarse_max) == (0, 0, 30, 1000, 2, 64)
     assert o.rtol == 1e-8
+    # block Gauss-Seidel: the paper's ordering (phi_e, c_s, phi_s, c_e)
+    assert o.bgs_order == _lib.P4D_BGS_PAPER_ORDER == 1 | 3 << 2 | 0 << 4 | 2 << 6
+
+
+def test_header_constants_match_binding():
+    import os
+    import re
+    from paper_2602_07225_amd import _lib
+    h = open(os.path.join(os.path.dirname(__file__), "..", "include", "p4d.h")).read()
+    for name in ("P4D_PC_SCHUR", "P4D_PC_BJ", "P4D_PC_BGS", "P4D_F_PHIS", "P4D_F_PHIE",
+                 "P4D_F_CE", "P4D_F_CS", "P4D_K_OPERATOR", "P4D_K_RADIAL", "P4D_K_BATCH_PC",
+                 "P4D_K_COUPLING", "P4D_K_COUNT"):
+        m = re.search(name + r"\s*=\s*(\d+)", h)
+        assert m and int(m.group(1)) == getattr(_lib, name), name
