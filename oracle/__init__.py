@@ -39,6 +39,10 @@ PC_SCHUR = 0
 PC_BJ = 1
 PC_BGS = 2
 
+# Krylov space: all unknowns, or the Schur complement of the c_s blocks
+KRYLOV_FULL = 0
+KRYLOV_SCHUR = 1
+
 # fields of the 4x4 block system as numbered in a block ordering
 F_PHIS, F_PHIE, F_CE, F_CS = 0, 1, 2, 3
 FIELD_NAMES = ("phi_s", "phi_e", "c_e", "c_s")
@@ -81,7 +85,7 @@ class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("cgs2", C.c_int32), ("rtol", C.c_double),
                 ("coarse_max", C.c_int32), ("cheb_degree", C.c_int32),
-                ("bgs_order", C.c_int32)]
+                ("bgs_order", C.c_int32), ("krylov", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -109,6 +113,9 @@ def lib():
         L.orc_fgmres.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.POINTER(Info)]
         L.orc_fgmres.restype = C.c_int
         L.orc_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.orc_schur_apply.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_schur_rhs.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_schur_back.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_radial_mesh.argtypes = [C.c_int, C.c_double, _dp]
         L.orc_radial_rows.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, _dp]
         L.orc_radial_rows.restype = C.c_double
@@ -251,11 +258,14 @@ class Oracle:
 
     # -- preconditioner --------------------------------------------------------
     def setup(self, pc=PC_SCHUR, restart=30, maxit=1000, rtol=1e-8, cgs2=False,
-              coarse_max=64, cheb_degree=2, bgs_order=BGS_PAPER):
+              coarse_max=64, cheb_degree=2, bgs_order=BGS_PAPER, krylov=KRYLOV_FULL):
         o = Opts()
         o.pc, o.restart, o.maxit, o.cgs2 = pc, restart, maxit, int(cgs2)
         o.rtol, o.coarse_max, o.cheb_degree = rtol, coarse_max, cheb_degree
         o.bgs_order = bgs_order
+        o.krylov = krylov
+        if krylov not in (KRYLOV_FULL, KRYLOV_SCHUR) or (krylov == KRYLOV_SCHUR and pc != PC_SCHUR):
+            raise ValueError("krylov must be KRYLOV_FULL, or KRYLOV_SCHUR with PC_SCHUR")
         if restart > 63:
             raise ValueError("restart must be <= 63")
         if pc == PC_BGS:
@@ -263,6 +273,33 @@ class Oracle:
         self.opts = o
         lib().orc_setup(self.h, C.byref(o))
         return self
+
+    # -- Schur complement of the c_s blocks ------------------------------------
+    @property
+    def n_macro(self):
+        return int(self.sizes[3])
+
+    def schur_apply(self, y, transpose=False):
+        """S y (S^T y), S = A_yy - A_ys A_ss^-1 A_sy over [phi_s | phi_e | c_e]."""
+        y = _f64(y)
+        out = np.zeros(self.n_macro)
+        lib().orc_schur_apply(self.h, int(transpose), _p(y), _p(out))
+        return out
+
+    def schur_rhs(self, b, transpose=False):
+        """b_y - A_ys A_ss^-1 b_s."""
+        b = _f64(b)
+        out = np.zeros(self.n_macro)
+        lib().orc_schur_rhs(self.h, int(transpose), _p(b), _p(out))
+        return out
+
+    def schur_back(self, b, y, transpose=False):
+        """The full solution [y | A_ss^-1 (b_s - A_sy y)]."""
+        b = _f64(b)
+        x = np.zeros(self.N)
+        x[:self.n_macro] = y
+        lib().orc_schur_back(self.h, int(transpose), _p(b), _p(x))
+        return x
 
     def apply_pc(self, r, transpose=False):
         r = _f64(r)

@@ -36,7 +36,11 @@
  *   - geometric Galerkin multigrid V(2,2) with degree-2 Chebyshev smoothing
  *     on diag(S)^-1 S over [lmax/4, lmax], lmax the Gershgorin bound, dense
  *     Cholesky at <= 512 nodes, in place of BoomerAMG;
- *   - restarted right-preconditioned flexible GMRES, classical Gram-Schmidt.
+ *   - restarted right-preconditioned flexible GMRES, classical Gram-Schmidt;
+ *   - optionally FGMRES over the Schur complement of the c_s blocks only
+ *     (not a variant the paper runs: an algebraic consequence of the block
+ *     structure of Sec. 4.1, exact up to rounding), with the SCHUR-mode
+ *     V-cycles as its preconditioner.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,7 +86,12 @@ typedef struct {
     int32_t coarse_max;    /* direct solve once a grid has <= this many nodes */
     int32_t cheb_degree;
     int32_t bgs_order;     /* BGS: field at block position p is bits [2p, 2p+2) */
+    int32_t krylov;        /* ORC_KRYLOV_FULL or ORC_KRYLOV_SCHUR               */
 } orc_opts;
+
+/* Krylov space: all unknowns, or the electrode-level unknowns of the Schur
+ * complement left when the c_s blocks are eliminated exactly (SCHUR mode). */
+enum { ORC_KRYLOV_FULL = 0, ORC_KRYLOV_SCHUR = 1 };
 
 typedef struct {
     int32_t iters, restarts, status;   /* status 0 converged, 1 not, 2 breakdown */
@@ -884,6 +893,10 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
 /* ------------------------------------------------------------------------ */
 void orc_setup(orc_problem *P, const orc_opts *o)
 {
+    if (o->krylov != ORC_KRYLOV_FULL && !(o->krylov == ORC_KRYLOV_SCHUR && o->pc == ORC_PC_SCHUR)) {
+        fprintf(stderr, "oracle: krylov %d needs pc SCHUR\n", o->krylov);
+        abort();
+    }
     if (o->pc == ORC_PC_BGS) {   /* the ordering must be a permutation */
         int seen = 0;
         for (int p = 0; p < 4; p++) seen |= 1 << ((o->bgs_order >> (2 * p)) & 3);
@@ -1180,13 +1193,108 @@ static double dot(const double *a, const double *b, long n)
     return s;
 }
 
-/* Solves A x = b (A^T x = b if transpose) from x0 = 0.  Stopping rule: the
- * Givens estimate reaches rtol ||b||, after which the true residual is
- * formed; the solve stops when the true residual meets rtol ||b||.          */
-int orc_fgmres(orc_problem *P, int transpose, const double *b, double *x, orc_info *info)
+/* ------------------------------------------------------------------------ */
+/* The Schur complement of the c_s blocks (Sec. 4.1: A_cs,cs is block        */
+/* diagonal, one tridiagonal block per electrode node, and the c_s unknowns  */
+/* couple to the electrode-level fields only through the surface value).     */
+/* With y the electrode-level unknowns [phi_s | phi_e | c_e]:                 */
+/*   S = A_yy - A_ys A_ss^-1 A_sy,  b^ = b_y - A_ys A_ss^-1 b_s,              */
+/*   x_s = A_ss^-1 (b_s - A_sy y),                                           */
+/* each written out with the operator and the per-node tridiagonal solves    */
+/* (transposed: the same with the blocks of A^T).                            */
+/* ------------------------------------------------------------------------ */
+/* out_s = A_ss^-1 in_s (A_ss^-T when transposed), per electrode node        */
+static void particle_solve(const orc_problem *P, int transpose, const double *in, double *out)
+{
+    const orc_desc *d = &P->d;
+    for (int el = 0; el < 2; el++) {
+        int N = d->nr[el];
+        long nn = el == 0 ? P->nea : P->nec, base = el == 0 ? 0 : P->nea;
+#pragma omp parallel
+        {
+            double *rhs = xmalloc(sizeof(double) * N), *sol = xmalloc(sizeof(double) * N);
+            double *w = xmalloc(sizeof(double) * 4 * N);
+#pragma omp for schedule(static)
+            for (long jl = 0; jl < nn; jl++) {
+                for (int q = 0; q < N; q++) rhs[q] = in[P->off_cs[el] + (long)q * nn + jl];
+                radial_solve(P, el, P->s[base + jl], transpose, rhs, sol, w);
+                for (int q = 0; q < N; q++) out[P->off_cs[el] + (long)q * nn + jl] = sol[q];
+            }
+            free(rhs); free(sol); free(w);
+        }
+    }
+}
+
+/* out = S y (S^T y), y and out of length off_cs[0] */
+void orc_schur_apply(const orc_problem *P, int transpose, const double *y, double *out)
+{
+    long Nm = P->off_cs[0], N = P->N;
+    double *x = xmalloc(sizeof(double) * N), *t = xmalloc(sizeof(double) * N);
+    double *u = xmalloc(sizeof(double) * N);
+    memset(x, 0, sizeof(double) * N);
+    memcpy(x, y, sizeof(double) * Nm);
+    orc_apply(P, transpose, x, t);                 /* t_y = A_yy y, t_s = A_sy y */
+    memset(x, 0, sizeof(double) * N);
+    particle_solve(P, transpose, t, x);            /* x_s = A_ss^-1 A_sy y      */
+    orc_apply(P, transpose, x, u);                 /* u_y = A_ys x_s            */
+    for (long i = 0; i < Nm; i++) out[i] = t[i] - u[i];
+    free(x); free(t); free(u);
+}
+
+/* bhat = b_y - A_ys A_ss^-1 b_s (length off_cs[0]) */
+void orc_schur_rhs(const orc_problem *P, int transpose, const double *b, double *bhat)
+{
+    long Nm = P->off_cs[0], N = P->N;
+    double *x = xmalloc(sizeof(double) * N), *u = xmalloc(sizeof(double) * N);
+    memset(x, 0, sizeof(double) * N);
+    particle_solve(P, transpose, b, x);
+    orc_apply(P, transpose, x, u);
+    for (long i = 0; i < Nm; i++) bhat[i] = b[i] - u[i];
+    free(x); free(u);
+}
+
+/* x_s = A_ss^-1 (b_s - A_sy y), with y = x[0 .. off_cs[0]) given */
+void orc_schur_back(const orc_problem *P, int transpose, const double *b, double *x)
+{
+    long Nm = P->off_cs[0], N = P->N;
+    double *xy = xmalloc(sizeof(double) * N), *t = xmalloc(sizeof(double) * N);
+    memset(xy, 0, sizeof(double) * N);
+    memcpy(xy, x, sizeof(double) * Nm);
+    orc_apply(P, transpose, xy, t);                /* t_s = A_sy y */
+    for (long i = Nm; i < N; i++) t[i] = b[i] - t[i];
+    particle_solve(P, transpose, t, xy);
+    memcpy(x + Nm, xy + Nm, sizeof(double) * (N - Nm));
+    free(xy); free(t);
+}
+
+/* preconditioner of the Schur-complement iteration: the V-cycles on the
+ * field blocks S~_f (step 3 of the SCHUR mode), identity on the grounded
+ * layer of phi_s                                                            */
+static void schur_pc(const orc_problem *P, const double *r, double *z)
+{
+    const orc_desc *d = &P->d;
+    for (long q = 0; q < (long)d->nx * d->ny; q++) z[P->off_ps + q] = r[P->off_ps + q];
+    for (int b = 0; b < 4; b++) {
+        long off, n;
+        box_slice(P, b, &off, &n);
+        vcycle(P, &P->mg[b], 0, r + off, z + off);
+    }
+}
+
+typedef void (*orc_lin_fn)(const orc_problem *, int, const double *, double *);
+static void full_op(const orc_problem *P, int t, const double *x, double *y) { orc_apply(P, t, x, y); }
+static void full_pc(const orc_problem *P, int t, const double *r, double *z) { orc_apply_pc(P, t, r, z); }
+static void schur_op(const orc_problem *P, int t, const double *x, double *y) { orc_schur_apply(P, t, x, y); }
+static void schur_pcf(const orc_problem *P, int t, const double *r, double *z) { (void)t; schur_pc(P, r, z); }
+
+/* Restarted right-preconditioned FGMRES on an operator of size n from x0 = 0.
+ * Stopping rule: the Givens estimate reaches rtol * bref, after which the
+ * true residual is formed; the solve stops when the true residual meets
+ * rtol * bref.                                                             */
+static int fgmres_core(const orc_problem *P, int transpose, long N, orc_lin_fn op, orc_lin_fn pc,
+                       const double *b, double bref, double *x, orc_info *info)
 {
     const orc_opts *o = &P->opts;
-    long N = P->N;
     int m = o->restart;
     double *V = xmalloc(sizeof(double) * N * (m + 1));
     double *Z = xmalloc(sizeof(double) * N * m);
@@ -1197,14 +1305,14 @@ int orc_fgmres(orc_problem *P, int transpose, const double *b, double *x, orc_in
     double *hc = xmalloc(sizeof(double) * (m + 1));
     memset(info, 0, sizeof(*info));
     memset(x, 0, sizeof(double) * N);
-    double bnorm = sqrt(dot(b, b, N));
+    double bnorm = bref;
     int status = 1, total = 0;
     if (bnorm == 0.0) {      /* x = 0 is exact */
         status = 0;
         goto done;
     }
     for (;;) {
-        orc_apply(P, transpose, x, w);
+        op(P, transpose, x, w);
         for (long i = 0; i < N; i++) w[i] = b[i] - w[i];
         double beta = sqrt(dot(w, w, N));
         info->relres_true = beta / bnorm;
@@ -1216,8 +1324,8 @@ int orc_fgmres(orc_problem *P, int transpose, const double *b, double *x, orc_in
         int k, kused = 0, breakdown = 0;
         for (k = 0; k < m; k++) {
             double *vk = V + (long)k * N, *zk = Z + (long)k * N;
-            orc_apply_pc(P, transpose, vk, zk);
-            orc_apply(P, transpose, zk, w);
+            pc(P, transpose, vk, zk);
+            op(P, transpose, zk, w);
             for (int i = 0; i <= k; i++) hc[i] = 0.0;
             for (int pass = 0; pass < (o->cgs2 ? 2 : 1); pass++) {
                 double hp[64];
@@ -1267,7 +1375,7 @@ int orc_fgmres(orc_problem *P, int transpose, const double *b, double *x, orc_in
         }
         info->restarts++;
         if (breakdown) {
-            orc_apply(P, transpose, x, w);
+            op(P, transpose, x, w);
             for (long i = 0; i < N; i++) w[i] = b[i] - w[i];
             info->relres_true = sqrt(dot(w, w, N)) / bnorm;
             status = info->relres_true <= o->rtol ? 0 : 2;
@@ -1278,6 +1386,30 @@ done:
     info->iters = total;
     info->status = status;
     free(V); free(Z); free(w); free(H); free(cs); free(sn); free(gv); free(yv); free(hc);
+    return status;
+}
+
+/* Solves A x = b (A^T x = b if transpose) from x0 = 0 by FGMRES over all
+ * unknowns, or (krylov = SCHUR) over the Schur complement S y = b^ followed
+ * by x_s = A_ss^-1 (b_s - A_sy y).  Both stop on rtol ||b||: with the c_s
+ * rows solved exactly, b - A x is zero in the c_s rows and equals b^ - S y
+ * in the others.  relres_true is ||b - A x|| / ||b|| of the returned x.     */
+int orc_fgmres(orc_problem *P, int transpose, const double *b, double *x, orc_info *info)
+{
+    long N = P->N, Nm = P->off_cs[0];
+    double bnorm = sqrt(dot(b, b, N));
+    if (P->opts.krylov != ORC_KRYLOV_SCHUR)
+        return fgmres_core(P, transpose, N, full_op, full_pc, b, bnorm, x, info);
+    double *bhat = xmalloc(sizeof(double) * Nm);
+    orc_schur_rhs(P, transpose, b, bhat);
+    int status = fgmres_core(P, transpose, Nm, schur_op, schur_pcf, bhat, bnorm, x, info);
+    orc_schur_back(P, transpose, b, x);
+    double *r = xmalloc(sizeof(double) * N);
+    orc_apply(P, transpose, x, r);
+    for (long i = 0; i < N; i++) r[i] = b[i] - r[i];
+    if (bnorm > 0.0) info->relres_true = sqrt(dot(r, r, N)) / bnorm;
+    free(r);
+    free(bhat);
     return status;
 }
 

@@ -1,5 +1,6 @@
 """Pins of the oracle's preconditioner (Sec. 4.2: eq. PJ, eq. PGS in every
-field ordering, and the exact elimination of the particle blocks), FGMRES
+field ordering, and the exact elimination of the particle blocks), the Schur
+complement of the particle blocks and the Krylov iteration over it, FGMRES
 solve and parameter gradients."""
 import itertools
 
@@ -134,6 +135,95 @@ def test_bgs_order_packing():
         O.bgs_order((0, 1, 1, 3))
     with pytest.raises(ValueError):
         O.Oracle(tiny(0)).setup(pc=O.PC_BGS, bgs_order=0)
+
+
+def omega_closed_form(p, orc):
+    """S = A_diff,yy + sum_j omega_j a_j b_j^T with omega_j = 1/(1 + Gamma s_j
+    tau0), tau0 = (T0^-1)_NN (Sherman-Morrison on A_ss,j = T0 + Gamma s_j
+    e_N e_N^T): the reaction coupling of A_yy scaled by omega_j, built here
+    from the radial rows and the node coefficients alone."""
+    tau0, gam = [], []
+    for el in range(2):
+        rho, sub, dia, sup, G = orc.radial(el)
+        N = p.nr[el]
+        T0 = np.diag(1.0 / p.dt - dia) - np.diag(sub[1:], -1) - np.diag(sup[:-1], 1)
+        tau0.append(np.linalg.solve(T0, np.eye(N)[:, -1])[-1])
+        gam.append(G)
+    return tau0, gam
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_schur_complement_is_dense_schur_and_omega_form(transpose):
+    """S from the oracle equals A_yy - A_ys A_ss^-1 A_sy of the assembled A,
+    and the closed form A_yy + sum_j (omega_j - 1) a_j b_j^T."""
+    p = tiny(9, sigma_log=1.0)
+    orc = O.Oracle(p)
+    A = orc.dense(transpose)
+    nm = p.offsets[3]
+    Ayy, Ays, Asy, Ass = A[:nm, :nm], A[:nm, nm:], A[nm:, :nm], A[nm:, nm:]
+    S_dense = Ayy - Ays @ np.linalg.solve(Ass, Asy)
+    S = np.column_stack([orc.schur_apply(e, transpose) for e in np.eye(nm)])
+    assert np.allclose(S, S_dense, rtol=0, atol=1e-12 * np.abs(S_dense).max())
+    # closed form: per electrode node the rank-1 reaction block of A_yy,
+    # scaled by omega_j instead of 1
+    tau0, gam = omega_closed_form(p, orc)
+    m = orc.lumped_weights()
+    S_cf = Ayy.copy()
+    o = p.offsets
+    layer = p.nx * p.ny
+    for je in range(p.n_ea + p.n_ec):
+        el = 0 if je < p.n_ea else 1
+        k = je // layer if el == 0 else p.na + p.ns + (je - p.n_ea) // layer
+        n = k * layer + je % layer
+        dirn = k == 0
+        a = np.array([0.0 if dirn else m[je], -m[je], -p.tc * m[je]])
+        bb = np.array([0.0 if dirn else p.g[je], -p.g[je], p.e[je]])
+        if transpose:
+            a, bb = bb, a
+        om = 1.0 / (1.0 + gam[el] * p.s[je] * tau0[el])
+        rows = [o[0] + je, o[1] + n, o[2] + n]
+        S_cf[np.ix_(rows, rows)] += (om - 1.0) * np.outer(a, bb)
+    assert np.allclose(S, S_cf, rtol=0, atol=1e-12 * np.abs(S_cf).max())
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_schur_rhs_and_back_substitution(transpose):
+    """With y the exact solution of S y = b^, [y | back(y)] solves A x = b."""
+    p = tiny(10)
+    orc = O.Oracle(p)
+    A = orc.dense(transpose)
+    nm = p.offsets[3]
+    bhat = orc.schur_rhs(p.b, transpose)
+    S = np.column_stack([orc.schur_apply(e, transpose) for e in np.eye(nm)])
+    y = np.linalg.solve(S, bhat)
+    x = orc.schur_back(p.b, y, transpose)
+    ref = np.linalg.solve(A, p.b)
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_schur_krylov_matches_dense_lu_and_full_space(transpose):
+    """FGMRES over the Schur complement (multilevel V-cycles on its field
+    blocks) reaches the dense-LU solution, with the full residual at the
+    requested level and no more iterations than the full-space iteration
+    with the same preconditioner blocks plus one."""
+    p = tiny(7, nx=5, ny=4, nz=8, nr=(4, 6))
+    A = O.Oracle(p).dense(transpose)
+    ref = np.linalg.solve(A, p.b)
+    full = O.Oracle(p).setup(rtol=1e-10, coarse_max=20)
+    xf, inf_f = full.solve(p.b, transpose)
+    red = O.Oracle(p).setup(rtol=1e-10, coarse_max=20, krylov=O.KRYLOV_SCHUR)
+    x, info = red.solve(p.b, transpose)
+    assert info.status == 0 and inf_f.status == 0
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert np.linalg.norm(A @ x - p.b) / np.linalg.norm(p.b) == pytest.approx(info.relres_true, rel=1e-6)
+    assert info.relres_true <= 1e-10
+    assert info.iters <= inf_f.iters + 1
+
+
+def test_schur_krylov_requires_schur_mode():
+    with pytest.raises(ValueError):
+        O.Oracle(tiny(0)).setup(pc=O.PC_BJ, krylov=O.KRYLOV_SCHUR)
 
 
 def test_preconditioner_transpose_identity():
