@@ -10,9 +10,11 @@ inputs already resident in device memory.
 
 Prints one JSON line: the metric is DOF*iter/s = N * iterations / step time.
 Extra fields report the FP32-preconditioned solve on the same input and on the
-lognormal-conductivity cube, the adjoint solve with gradients, the batched
-solve of 64 uneven cells, per-kernel times and bandwidths measured with HIP
-events inside the timed region, and the CPU oracle timed on the host.
+lognormal-conductivity cube, the block-Jacobi and block Gauss-Seidel
+preconditioners (all 24 orderings of the latter), the Krylov iteration over
+the Schur complement of the particle blocks, the adjoint solve with gradients,
+the batched solve of 64 uneven cells, per-kernel times and bandwidths measured
+with HIP events inside the timed region, and the CPU oracle timed on the host.
 """
 import argparse
 import json
@@ -181,6 +183,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the headline solve")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 64-cell batched solve (prints its JSON fields; for profiling)")
+    ap.add_argument("--bgs-only", action="store_true",
+                    help="only the block Gauss-Seidel solve of the cube in the paper's ordering "
+                         "(prints its JSON fields; for profiling)")
+    ap.add_argument("--schur-only", action="store_true",
+                    help="only the cube solve with the Krylov space reduced to the Schur complement "
+                         "of the particle blocks (prints its JSON fields; for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 512 MiB device copy first (a reference of known size "
                          "for hardware byte counters)")
@@ -200,6 +208,30 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"C4_batch_64_cells": bench_batch(args.steps)}), flush=True)
+        return
+    if args.schur_only:
+        p = pi.make_config(2)
+        s = P4DSolver(p, restart=30)
+        b = torch.as_tensor(p.b, device="cuda")
+        red = dict(pc=L.P4D_PC_SCHUR, krylov=L.P4D_KRYLOV_SCHUR, rtol=1e-8, restart=30,
+                   pc_prec=L.P4D_FP64)
+        mask = sum(1 << k for k in L.KERNEL_CLASSES)
+        _, info, it, t, prof = timed_steps(s, b, red, args.steps, args.warmup, mask)
+        print(json.dumps({"schur_krylov_C2": {
+            "ms_per_step": 1e3 * t / args.steps, "iters_per_solve": it / args.steps,
+            "DOF_iter_per_s": p.N * it / t, "kernels": prof}}), flush=True)
+        return
+    if args.bgs_only:
+        p = pi.make_config(2)
+        s = P4DSolver(p, restart=30)
+        b = torch.as_tensor(p.b, device="cuda")
+        bgs = dict(pc=L.P4D_PC_BGS, bgs_order=L.P4D_BGS_PAPER_ORDER, cgs2=1, rtol=1e-8,
+                   restart=30, pc_prec=L.P4D_FP64)
+        mask = sum(1 << k for k in L.KERNEL_CLASSES)
+        _, info, it, t, prof = timed_steps(s, b, bgs, args.steps, args.warmup, mask)
+        print(json.dumps({"block_gauss_seidel_C2": {
+            "ms_per_step": 1e3 * t / args.steps, "iters_per_solve": it / args.steps,
+            "kernels": prof}}), flush=True)
         return
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
@@ -276,6 +308,27 @@ def main():
                 f"FP32-PC {1e3 * tg32 / 2:.2f} ms/step")
         except RuntimeError as ex:
             extras["block_gauss_seidel_C2"] = {"error": str(ex)}
+        # Krylov space reduced to the Schur complement of the particle blocks
+        # (the same system and tolerance; FGMRES over the 2.2 M electrode-level
+        # unknowns), both preconditioner precisions
+        sk = dict(fp64, krylov=L.P4D_KRYLOV_SCHUR)
+        xs64, is64, its64, ts64, profs = timed_steps(s, b, sk, args.steps, 1, mask)
+        xs32, is32, its32, ts32, _ = timed_steps(s, b, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
+        extras["schur_krylov_C2"] = {
+            "fp64": {"ms_per_step": 1e3 * ts64 / args.steps, "iters_per_solve": its64 / args.steps,
+                     "DOF_iter_per_s": N * its64 / ts64, "relres_true": is64.relres_true,
+                     "rel_diff_vs_full_space": (torch.linalg.norm(xs64 - x64) /
+                                                torch.linalg.norm(x64)).item()},
+            "fp32_precond": {"ms_per_step": 1e3 * ts32 / args.steps,
+                             "iters_per_solve": its32 / args.steps,
+                             "DOF_iter_per_s": N * its32 / ts32,
+                             "rel_diff_vs_full_space": (torch.linalg.norm(xs32 - x64) /
+                                                        torch.linalg.norm(x64)).item()},
+            "speedup_vs_full_space": t / ts64,
+            "kernels": profs}
+        log(f"[bench] Schur-Krylov C2: fp64 {1e3 * ts64 / args.steps:.2f} ms ({its64 / args.steps:.0f} it), "
+            f"fp32-PC {1e3 * ts32 / args.steps:.2f} ms ({its32 / args.steps:.0f} it)")
+        del xs64, xs32
         extras["bgs_orderings_C2"] = bgs_sweep(s, b, fp64)
         log(f"[bench] BGS orderings C2: best {extras['bgs_orderings_C2']['best']}, "
             f"worst {extras['bgs_orderings_C2']['worst']}")
@@ -292,6 +345,15 @@ def main():
                                  (torch.linalg.norm(xb - xa) / torch.linalg.norm(xa)).item()},
             "speedup_fp32_vs_fp64": ta / tb}
         log(f"[bench] C3: fp64 {1e3 * ta / args.steps:.2f} ms, fp32 {1e3 * tb / args.steps:.2f} ms")
+        _, _, itc, tc3, _ = timed_steps(s3, b3, dict(fp64, krylov=L.P4D_KRYLOV_SCHUR), args.steps, 1)
+        _, _, itc32, tc332, _ = timed_steps(s3, b3, dict(fp32, krylov=L.P4D_KRYLOV_SCHUR),
+                                            args.steps, 1)
+        extras["schur_krylov_C3"] = {
+            "fp64": {"ms_per_step": 1e3 * tc3 / args.steps, "iters_per_solve": itc / args.steps},
+            "fp32_precond": {"ms_per_step": 1e3 * tc332 / args.steps,
+                             "iters_per_solve": itc32 / args.steps}}
+        log(f"[bench] Schur-Krylov C3: fp64 {1e3 * tc3 / args.steps:.2f} ms, "
+            f"fp32-PC {1e3 * tc332 / args.steps:.2f} ms")
         extras["bgs_orderings_C3"] = bgs_sweep(s3, b3, fp64)
         log(f"[bench] BGS orderings C3: best {extras['bgs_orderings_C3']['best']}, "
             f"worst {extras['bgs_orderings_C3']['worst']}")
@@ -331,7 +393,28 @@ def main():
             "DOF_iter_per_s_forward": p5.N * f5.iters / (t1 - t0)}
         log(f"[bench] C5: forward {1e3 * (t1 - t0):.1f} ms ({f5.iters} it), adjoint+grad "
             f"{1e3 * (t2 - t1):.1f} ms ({a5.iters} it)")
-        del s5, x5, l5, g5
+        # the same with the Krylov space reduced to the Schur complement
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s5.setup(**fp64)
+        x5r, f5r = s5.solve(b5, krylov=L.P4D_KRYLOV_SCHUR)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        l5r, a5r = s5.solve_adjoint(w5, krylov=L.P4D_KRYLOV_SCHUR)
+        g5r, gD5r = s5.gradient(x5r, l5r)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        extras["schur_krylov_C5"] = {
+            "forward_ms": 1e3 * (t1 - t0), "forward_iters": f5r.iters,
+            "adjoint_plus_gradient_ms": 1e3 * (t2 - t1), "adjoint_iters": a5r.iters,
+            "DOF_iter_per_s_forward": p5.N * f5r.iters / (t1 - t0),
+            "rel_diff_vs_full_space": {
+                "x": (torch.linalg.norm(x5r - x5) / torch.linalg.norm(x5)).item(),
+                "lambda": (torch.linalg.norm(l5r - l5) / torch.linalg.norm(l5)).item(),
+                "dJ_dsigma": (torch.linalg.norm(g5r - g5) / torch.linalg.norm(g5)).item()}}
+        log(f"[bench] Schur-Krylov C5: forward {1e3 * (t1 - t0):.1f} ms ({f5r.iters} it), "
+            f"adjoint+grad {1e3 * (t2 - t1):.1f} ms ({a5r.iters} it)")
+        del s5, x5, l5, g5, x5r, l5r, g5r
 
     if not args.no_extras:
         extras["C4_batch_64_cells"] = bench_batch(args.steps)

@@ -80,6 +80,16 @@ enum { P4D_F_PHIS = 0, P4D_F_PHIE = 1, P4D_F_CE = 2, P4D_F_CS = 3 };
 
 typedef enum { P4D_FP64 = 0, P4D_FP32 = 1 } p4d_prec;
 
+/* Krylov space of the solve.  P4D_KRYLOV_SCHUR: the particle blocks are
+ * eliminated exactly (A_cs,cs is block diagonal with one tridiagonal block
+ * per electrode node and couples to the electrode-level fields only through
+ * the surface value, paper Sec. 4.1), FGMRES runs on the Schur complement
+ * S = A_yy - A_ys A_ss^-1 A_sy over [phi_s | phi_e | c_e] with the SCHUR-mode
+ * V-cycles as preconditioner, and c_s follows by back-substitution.  The
+ * stopping rule and the reported true residual refer to the whole system.
+ * Needs pc = P4D_PC_SCHUR. */
+typedef enum { P4D_KRYLOV_FULL = 0, P4D_KRYLOV_SCHUR = 1 } p4d_krylov;
+
 /* Problem geometry and scalars, all nondimensional.  The particle radius is
  * scaled to 1; Ds = D_s dt / R_s^2; theta_bar = last/first radial interval. */
 typedef struct {
@@ -107,6 +117,7 @@ typedef struct {
     double rtol;           /* stop when ||b - A x|| <= rtol ||b||                 */
     int32_t bgs_order;     /* P4D_PC_BGS: packed field ordering (see above); fixed
                               at p4d_setup, a solve must pass the same value     */
+    int32_t krylov;        /* p4d_krylov; may differ between solves             */
 } p4d_solve_opts;
 
 typedef struct {
@@ -120,7 +131,7 @@ typedef struct p4d_ctx p4d_ctx;
 
 /* Fill opts with the defaults: SCHUR, FP64, restart 30, maxit 1000, Chebyshev
  * degree 2, coarse_max 64, one Gram-Schmidt pass, FP64 Z, rtol 1e-8, block
- * Gauss-Seidel ordering P4D_BGS_PAPER_ORDER.                                */
+ * Gauss-Seidel ordering P4D_BGS_PAPER_ORDER, full Krylov space.            */
 void p4d_default_opts(p4d_solve_opts *opts);
 
 /* Create a context for the problem `desc` on the current device.  Computes
@@ -174,6 +185,14 @@ p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
 p4d_status p4d_apply_operator(p4d_ctx *ctx, int transpose, const double *d_x,
                               double *d_y, void *stream);
 
+/* d_w = S d_y (S^T d_y if transpose), S = A_yy - A_ys A_ss^-1 A_sy the Schur
+ * complement of the particle blocks (see p4d_krylov), formed as A_diff,yy +
+ * sum_j omega_j a_j b_j^T with omega_j = 1/(1 + Gamma s_j (T0^-1)_NN).  d_y,
+ * d_w: device, length off_cs[0] (the electrode-level unknowns), must not
+ * alias.  Needs p4d_upload.                                                */
+p4d_status p4d_apply_schur_operator(p4d_ctx *ctx, int transpose, const double *d_y,
+                                    double *d_w, void *stream);
+
 /* d_z = P^-1 d_r (P^-T if transpose) with the preconditioner of the last
  * p4d_setup (in its precision; d_r and d_z stay FP64).  Needs p4d_setup.   */
 p4d_status p4d_apply_preconditioner(p4d_ctx *ctx, int transpose, const double *d_r,
@@ -202,8 +221,9 @@ p4d_status p4d_param_gradient(p4d_ctx *ctx, const double *d_x, const double *d_l
 
 /* Kernel timing with HIP events recorded on `stream` around every launch of
  * the kernel classes in `class_mask` (bit 1 << p4d_kernel_class; 0 switches
- * timing off and clears the totals).  P4D_K_COUPLING: the block Gauss-Seidel
- * right-hand sides (off-diagonal blocks times solved fields) and output.   */
+ * timing off and clears the totals).  P4D_K_COUPLING: the kernels around the
+ * V-cycles of the block Gauss-Seidel and Schur-complement preconditioners
+ * (right-hand sides with the off-diagonal blocks, precision casts, output). */
 typedef enum {
     P4D_K_OPERATOR = 1, P4D_K_MDOT = 2, P4D_K_ORTH = 3, P4D_K_RADIAL = 4,
     P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_BATCH_PC = 7, P4D_K_COUPLING = 8,

@@ -30,6 +30,8 @@ P4D_F_PHIS, P4D_F_PHIE, P4D_F_CE, P4D_F_CS = 0, 1, 2, 3
 P4D_BGS_PAPER_ORDER = P4D_F_PHIE | (P4D_F_CS << 2) | (P4D_F_PHIS << 4) | (P4D_F_CE << 6)
 P4D_FP64 = 0
 P4D_FP32 = 1
+P4D_KRYLOV_FULL = 0
+P4D_KRYLOV_SCHUR = 1
 
 (P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY,
  P4D_K_BATCH_PC, P4D_K_COUPLING) = range(1, 9)
@@ -41,7 +43,7 @@ KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "o
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
     "p4d_set_workspace", "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
-    "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
+    "p4d_apply_schur_operator", "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
     "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
     "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_cell", "p4d_batch_workspace_size",
     "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_autotune",
@@ -62,7 +64,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("pc_prec", C.c_int32), ("restart", C.c_int32),
                 ("maxit", C.c_int32), ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
                 ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double),
-                ("bgs_order", C.c_int32)]
+                ("bgs_order", C.c_int32), ("krylov", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -106,6 +108,7 @@ def lib():
         L.p4d_set_diffusivity.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.p4d_apply_operator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.p4d_apply_schur_operator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.p4d_solve_adjoint.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.p4d_param_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -119,7 +122,7 @@ def lib():
         L.p4d_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
         for name in ["p4d_autotune", "p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
                      "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
-                     "p4d_apply_preconditioner",
+                     "p4d_apply_preconditioner", "p4d_apply_schur_operator",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
                      "p4d_profile_read"]:
             getattr(L, name).restype = C.c_int
@@ -254,6 +257,12 @@ def p4d_setup(ctx, opts: SolveOpts | None = None, stream=None):
 def p4d_apply_operator(ctx, transpose, x, y, stream=None):
     return check(lib().p4d_apply_operator(ctx, int(transpose), ptr(x), ptr(y),
                                           stream_ptr(stream)), ctx, "p4d_apply_operator")
+
+
+def p4d_apply_schur_operator(ctx, transpose, y, w, stream=None):
+    return check(lib().p4d_apply_schur_operator(ctx, int(transpose), ptr(y), ptr(w),
+                                                stream_ptr(stream)), ctx,
+                 "p4d_apply_schur_operator")
 
 
 def p4d_apply_preconditioner(ctx, transpose, r, z, stream=None):

@@ -35,6 +35,14 @@ __global__ __launch_bounds__(kBlock) void k_operator_tile(Geom g, OpArgs O, doub
     operator_tile<TX, TRANS>(g, O, qout, xcd_block(blockIdx.x, gridDim.x), TXn, CZ, L);
 }
 
+// the Schur complement of the particle blocks over the electrode-level unknowns
+template <typename TX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_operator_schur(Geom g, OpArgs O, int TXn, int CZ)
+{
+    __shared__ OpLds L;
+    operator_tile<TX, TRANS, true>(g, O, nullptr, xcd_block(blockIdx.x, gridDim.x), TXn, CZ, L);
+}
+
 template <typename TX, int NRMAX, bool TRANS>
 __global__ __launch_bounds__(kBlock) void k_operator_radial(Geom g, OpArgs O, const double *q)
 {
@@ -114,6 +122,32 @@ template void launch_operator<float>(const Geom &, const RadialTab *, const doub
                                      const double *, const double *, const double *,
                                      const double *, const double *, const float *, double *,
                                      const double *, double *, int, int, int, double *, hipStream_t);
+
+// w = S y (or S^T y), S = A_yy - A_ys A_ss^-1 A_sy: y and w hold the
+// electrode-level unknowns only (length Nm); omega per electrode node.
+template <typename TX>
+void launch_operator_schur(const Geom &g, const RadialTab *tabs, const double *sigh,
+                           const double *kaph, const double *gg, const double *ss, const double *ee,
+                           const double *mm, const double *om, const TX *y, double *w, int transpose,
+                           int tile_tx, int tile_cz, hipStream_t st)
+{
+    OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, y, w, nullptr, om};
+    const int nt = operator_tiles(g, tile_tx, tile_cz);
+    if (transpose)
+        hipLaunchKernelGGL((k_operator_schur<TX, true>), dim3(nt), dim3(kBlock), 0, st, g, O, tile_tx,
+                           tile_cz);
+    else
+        hipLaunchKernelGGL((k_operator_schur<TX, false>), dim3(nt), dim3(kBlock), 0, st, g, O, tile_tx,
+                           tile_cz);
+}
+template void launch_operator_schur<double>(const Geom &, const RadialTab *, const double *,
+                                            const double *, const double *, const double *,
+                                            const double *, const double *, const double *,
+                                            const double *, double *, int, int, int, hipStream_t);
+template void launch_operator_schur<float>(const Geom &, const RadialTab *, const double *,
+                                           const double *, const double *, const double *,
+                                           const double *, const double *, const double *,
+                                           const float *, double *, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Gradients of J = w.x:  dJ/dp = -lambda^T (dA/dp) x.

@@ -66,6 +66,7 @@ struct p4d_ctx {
     RadialTab *tabs = nullptr;
     double *sigh = nullptr, *kaph = nullptr, *gg = nullptr, *ss = nullptr, *ee = nullptr,
            *mm = nullptr, *omega = nullptr, *qbuf = nullptr;
+    double *oms = nullptr;         // omega_j of the Schur complement (whatever the preconditioner)
     double *red = nullptr;         // partial sums
     size_t red_len = 0;
     double *hdev = nullptr, *cdev = nullptr, *invbeta = nullptr, *ydev = nullptr, *scal = nullptr;
@@ -240,6 +241,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->mm = (double *)take(8 * g.ne);
     c->omega = (double *)take(8 * g.ne);
     c->qbuf = (double *)take(8 * g.ne);          // reaction q of the tiled operator
+    c->oms = (double *)take(8 * g.ne);
     // reduction partials: streaming (kRedBlocks x 64), operator, gradient
     size_t rl = (size_t)kRedBlocks * 64;
     const size_t opb = (size_t)operator_blocks(g) + 1;
@@ -320,7 +322,12 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     // Krylov basis
     const int m = o.restart;
     const size_t zs = o.z_fp32 ? sizeof(float) : sizeof(double);
-    const size_t kry = align_up(8 * (size_t)(m + 1) * g.N) + align_up(zs * (size_t)m * g.N);
+    const size_t kry_full = align_up(8 * (size_t)(m + 1) * g.N) + align_up(zs * (size_t)m * g.N);
+    // the Schur-complement iteration: V and Z over the electrode-level
+    // unknowns plus its right-hand side
+    const size_t kry_red = align_up(8 * (size_t)(m + 1) * Nm) + align_up(zs * (size_t)m * Nm) +
+                           align_up(8 * (size_t)Nm);
+    const size_t kry = kry_full > kry_red ? kry_full : kry_red;
     c->scratch_bytes = kry > s0 ? kry : s0;
     c->scratch = take(c->scratch_bytes);
     return off;
@@ -329,6 +336,11 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
 static bool opts_valid(const p4d_solve_opts &o, std::string &why)
 {
     if (o.pc != P4D_PC_SCHUR && o.pc != P4D_PC_BJ && o.pc != P4D_PC_BGS) { why = "pc"; return false; }
+    if (o.krylov != P4D_KRYLOV_FULL && o.krylov != P4D_KRYLOV_SCHUR) { why = "krylov"; return false; }
+    if (o.krylov == P4D_KRYLOV_SCHUR && o.pc != P4D_PC_SCHUR) {
+        why = "the Schur-complement Krylov space needs pc P4D_PC_SCHUR";
+        return false;
+    }
     if (o.pc == P4D_PC_BGS) {
         int seen = 0;
         for (int p = 0; p < 4; p++) seen |= 1 << ((o.bgs_order >> (2 * p)) & 3);
@@ -417,6 +429,17 @@ static void apply_op(p4d_ctx *c, int transpose, const TX *x, double *y, const do
     ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
     launch_operator<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, x, y, b,
                         partial, transpose, c->op_tx, c->op_cz, c->qbuf, st);
+}
+
+// w = S y (S^T y) over the electrode-level unknowns
+template <typename TX>
+static void apply_op_schur(p4d_ctx *c, int transpose, const TX *y, double *w, hipStream_t st)
+{
+    const Geom &g = c->g;
+    const double bytes = (double)(sizeof(TX) + 8) * g.Nm + 16.0 * g.nelem + 40.0 * g.ne;
+    ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
+    launch_operator_schur<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, c->oms, y, w,
+                              transpose, c->op_tx, c->op_cz, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -723,6 +746,34 @@ static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, double rscal
     launch_bgs_out<TZ>(g, B, r, rscale, z, st);
 }
 
+// z = P_S^-1 (rscale r) for the Schur-complement iteration: one V-cycle per
+// field on S~_f (the field blocks of S, the SCHUR-mode boxes), identity on
+// the grounded layer; r and z hold the electrode-level unknowns only.
+template <typename T, typename TZ>
+static void apply_pc_schur_t(p4d_ctx *c, const double *r, double rscale, TZ *z, hipStream_t st)
+{
+    const Geom &g = c->g;
+    BgsArgs B{};
+    B.R = rad_args(c);
+    {
+        ProfScope ps(c->prof, P4D_K_COUPLING, (8.0 + sizeof(T) + 8.0) * g.Nm, st);
+        launch_rad_fwd<T>(g, B.R, r, rscale, 0, 0, st);   // cast + first Chebyshev iterate
+    }
+    VState<T> vs{};
+    for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
+    vcycle_level<T>(c, vs, 0, st);
+    for (int b = 0; b < 4; b++) B.R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
+    ProfScope ps(c->prof, P4D_K_COUPLING, (8.0 + sizeof(TZ)) * g.Nm, st);
+    launch_bgs_out<TZ>(g, B, r, rscale, z, st);
+}
+
+template <typename TZ>
+static void apply_pc_schur(p4d_ctx *c, const double *r, double rscale, TZ *z, hipStream_t st)
+{
+    if (c->prec == 1) apply_pc_schur_t<float, TZ>(c, r, rscale, z, st);
+    else apply_pc_schur_t<double, TZ>(c, r, rscale, z, st);
+}
+
 template <typename TZ>
 static void apply_pc(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
                      hipStream_t st)
@@ -836,17 +887,27 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
 // ---------------------------------------------------------------------------
 // FGMRES (Saad's flexible variant, right preconditioned, restarted)
 // ---------------------------------------------------------------------------
+// The Krylov space is either all unknowns, or (krylov = SCHUR) the
+// electrode-level unknowns of the Schur complement S of the particle blocks:
+// FGMRES on S y = bhat, then x_s = A_ss^-1 (b_s - A_sy y).  Both stop on
+// rtol ||b|| with b the full right-hand side: with the particle rows solved
+// exactly, b - A x vanishes in them and equals bhat - S y in the others.
 template <typename TZ>
 static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
                          const p4d_solve_opts &o, p4d_solve_info *info, hipStream_t st)
 {
     const Geom &g = c->g;
-    const long long N = g.N;
+    const bool schur = o.krylov == P4D_KRYLOV_SCHUR;
+    const long long N = schur ? g.Nm : g.N;   // Krylov vector length
     const int m = o.restart;
     double *V = (double *)c->scratch;
     TZ *Z = (TZ *)(c->scratch + align_up(8 * (size_t)(m + 1) * N));
+    // the Krylov right-hand side: b, or bhat (after Z; the region is sized
+    // for the full space, which leaves room)
+    double *bk = schur ? (double *)((char *)Z + align_up(sizeof(TZ) * (size_t)m * N)) : (double *)b;
     double *red = c->red;
     const int sb = stream_blocks(N);
+    const int sbf = stream_blocks(g.N);
     const int ob = operator_blocks(g);
     double *hh = c->hhost;           // device-to-host staging
     double *hout = c->hhost + 256;   // host-to-device staging
@@ -854,14 +915,29 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         beta(m + 1);
     p4d_solve_info inf{};
     auto t0 = std::chrono::steady_clock::now();
+    // r = bk - op(x) into V_0 with its norm (restarts and breakdown)
+    auto residual = [&]() -> p4d_status {
+        if (schur) {
+            apply_op_schur<double>(c, transpose, x, V, st);
+            launch_red_resid(N, bk, V, red, sb, st);
+            launch_norm_final(red, sb, c->hdev + 200, c->invbeta, st);
+        } else {
+            apply_op<double>(c, transpose, x, V, b, red, st);
+            launch_norm_final(red, ob, c->hdev + 200, c->invbeta, st);
+        }
+        HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        prof_harvest(c->prof);
+        return P4D_OK;
+    };
 
-    // ||b||
-    launch_dot_partial(N, b, b, red, sb, st);
-    launch_norm_final(red, sb, c->hdev, nullptr, st);
+    // ||b|| over all unknowns
+    launch_dot_partial(g.N, b, b, red, sbf, st);
+    launch_norm_final(red, sbf, c->hdev, nullptr, st);
     HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     const double bnorm = hh[0];
-    HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)N, st));
+    HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
     if (!std::isfinite(bnorm)) {
         HIPCHK(c, hipStreamSynchronize(st));
         return fail(c, P4D_ERR_NONFINITE, "non-finite right-hand side");
@@ -873,20 +949,29 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         status = P4D_OK;
         goto done;
     }
+    if (schur) {
+        ProfScope ps(c->prof, P4D_K_RADIAL, 8.0 * g.N + 8.0 * g.Nm + 32.0 * g.ne, st);
+        launch_red_rhs(g, c->tabs, c->gg, c->ss, c->ee, c->mm, b, bk, transpose, st);
+    }
     for (;;) {
-        // r = b - A x into V_0 (x = 0 in the first cycle: r = b)
+        // r = bk - op(x) into V_0 (x = 0 in the first cycle: r = bk)
         if (first) {
-            HIPCHK(c, hipMemcpyAsync(V, b, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
-            hout[0] = 1.0 / bnorm;
-            HIPCHK(c, hipMemcpyAsync(c->invbeta, hout, 8, hipMemcpyHostToDevice, st));
-            beta[0] = bnorm;
+            HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
+            if (schur) {
+                launch_dot_partial(N, bk, bk, red, sb, st);
+                launch_norm_final(red, sb, c->hdev + 200, c->invbeta, st);
+                HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipStreamSynchronize(st));
+                beta[0] = hh[0];
+            } else {
+                hout[0] = 1.0 / bnorm;
+                HIPCHK(c, hipMemcpyAsync(c->invbeta, hout, 8, hipMemcpyHostToDevice, st));
+                beta[0] = bnorm;
+            }
             first = false;
         } else {
-            apply_op<double>(c, transpose, x, V, b, red, st);
-            launch_norm_final(red, ob, c->hdev + 200, c->invbeta, st);
-            HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
-            prof_harvest(c->prof);
+            const p4d_status rs = residual();
+            if (rs != P4D_OK) return rs;
             beta[0] = hh[0];
         }
         inf.relres_true = beta[0] / bnorm;
@@ -900,9 +985,14 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         for (int k = 0; k < m; k++) {
             double *vk = V + (long long)k * N;
             TZ *zk = Z + (long long)k * N;
-            apply_pc<TZ>(c, transpose, vk, 1.0 / beta[k], zk, st);
             double *w = V + (long long)(k + 1) * N;
-            apply_op<TZ>(c, transpose, zk, w, nullptr, nullptr, st);
+            if (schur) {
+                apply_pc_schur<TZ>(c, vk, 1.0 / beta[k], zk, st);
+                apply_op_schur<TZ>(c, transpose, zk, w, st);
+            } else {
+                apply_pc<TZ>(c, transpose, vk, 1.0 / beta[k], zk, st);
+                apply_op<TZ>(c, transpose, zk, w, nullptr, nullptr, st);
+            }
             const int nv = k + 1;
             const int passes = o.cgs2 ? 2 : 1;
             for (int p = 0; p < passes; p++) {
@@ -962,14 +1052,25 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         }
         inf.restarts++;
         if (breakdown) {
-            apply_op<double>(c, transpose, x, V, b, red, st);
-            launch_norm_final(red, ob, c->hdev + 200, nullptr, st);
-            HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
+            const p4d_status rs = residual();
+            if (rs != P4D_OK) return rs;
             inf.relres_true = hh[0] / bnorm;
             status = inf.relres_true <= o.rtol ? P4D_OK : P4D_BREAKDOWN;
             break;
         }
+    }
+    if (schur && status != P4D_ERR_NONFINITE) {
+        // particle unknowns from the electrode-level ones, then the true
+        // residual of the whole system (V has room for one full vector)
+        {
+            ProfScope ps(c->prof, P4D_K_RADIAL, 16.0 * (g.N - g.Nm) + 8.0 * g.Nm + 32.0 * g.ne, st);
+            launch_red_back(g, c->tabs, c->gg, c->ss, c->ee, c->mm, b, x, transpose, st);
+        }
+        apply_op<double>(c, transpose, x, V, b, red, st);
+        launch_norm_final(red, ob, c->hdev + 200, nullptr, st);
+        HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        inf.relres_true = hh[0] / bnorm;
     }
 done:
     HIPCHK(c, hipGetLastError());
@@ -1002,6 +1103,7 @@ void p4d_default_opts(p4d_solve_opts *o)
     o->z_fp32 = 0;
     o->rtol = 1e-8;
     o->bgs_order = 1 | (3 << 2) | (0 << 4) | (2 << 6);   // (phi_e, c_s, phi_s, c_e)
+    o->krylov = P4D_KRYLOV_FULL;
 }
 
 const char *p4d_status_string(p4d_status s)
@@ -1182,6 +1284,7 @@ p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, cons
     HIPCHK(c, hipMemcpyAsync(c->ss, s, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->ee, e, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
     launch_setup_nodes(c->g, c->tabs, sigma, kappa, c->sigh, c->kaph, c->mm, st);
+    launch_omega(c->g, c->tabs, c->ss, 1, c->oms, st);
     HIPCHK(c, hipGetLastError());
     // the host copy of the radial tables must outlive the async copy
     HIPCHK(c, hipStreamSynchronize(st));
@@ -1202,6 +1305,8 @@ p4d_status p4d_set_diffusivity(p4d_ctx *c, const double Ds[2], void *stream)
     radial_table(c->desc, 0, c->tabs_h[0]);
     radial_table(c->desc, 1, c->tabs_h[1]);
     HIPCHK(c, hipMemcpyAsync(c->tabs, c->tabs_h, sizeof(c->tabs_h), hipMemcpyHostToDevice, st));
+    launch_omega(c->g, c->tabs, c->ss, 1, c->oms, st);
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->pc_ready = 0;
     return P4D_OK;
@@ -1246,6 +1351,16 @@ p4d_status p4d_apply_operator(p4d_ctx *c, int transpose, const double *x, double
     if (!c || !x || !y || x == y) return P4D_ERR_INVALID_ARG;
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
     apply_op<double>(c, transpose, x, y, nullptr, nullptr, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+p4d_status p4d_apply_schur_operator(p4d_ctx *c, int transpose, const double *y, double *w,
+                                    void *stream)
+{
+    if (!c || !y || !w || y == w) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    apply_op_schur<double>(c, transpose, y, w, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return P4D_OK;
 }
@@ -2161,6 +2276,8 @@ p4d_status p4d_batch_solve(p4d_batch *B, const double *const *d_b, double *const
     p4d_solve_opts o = opts ? *opts : c0->pc;
     std::string why;
     if (!opts_valid(o, why)) return bfail(B, P4D_ERR_INVALID_ARG, why);
+    if (o.krylov != P4D_KRYLOV_FULL)
+        return bfail(B, P4D_ERR_INVALID_ARG, "the Schur-complement Krylov space is for single cells only");
     for (int i = 0; i < B->n; i++) {
         const p4d_ctx *c = B->cell[i];
         if (o.pc != c->pc.pc || o.pc_prec != c->pc.pc_prec || o.cheb_degree != c->pc.cheb_degree ||

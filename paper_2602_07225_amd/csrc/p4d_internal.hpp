@@ -205,6 +205,23 @@ void launch_cast(long long n, const double *src, T *dst, hipStream_t st);
 template <typename T>
 void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st);
 
+// operator.hip: the Schur complement of the particle blocks (electrode-level
+// vectors of length Nm)
+template <typename TX>
+void launch_operator_schur(const Geom &g, const RadialTab *tabs, const double *sigh,
+                           const double *kaph, const double *gg, const double *ss, const double *ee,
+                           const double *mm, const double *om, const TX *y, double *w, int transpose,
+                           int tile_tx, int tile_cz, hipStream_t st);
+// reduced.hip
+void launch_red_rhs(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
+                    const double *ee, const double *mm, const double *b, double *bhat, int transpose,
+                    hipStream_t st);
+void launch_red_back(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
+                     const double *ee, const double *mm, const double *b, double *x, int transpose,
+                     hipStream_t st);
+void launch_red_resid(long long n, const double *bhat, double *w, double *partial, int nblk,
+                      hipStream_t st);
+
 // krylov.hip
 int stream_blocks(long long n);
 void launch_mdot(long long n, const double *w, const double *V, long long ldv, int nv,

@@ -504,6 +504,7 @@ struct OpArgs {
     const void *x;       // TX
     double *y;
     const double *b;     // b - A x when not null
+    const double *om;    // omega per electrode node (Schur complement operator)
 };
 
 template <typename TX>
@@ -705,7 +706,11 @@ __host__ __device__ inline int op_tiles(int nx, int ny, int nz, int TX, int CZ)
     return smooth0_box_tiles(nx, ny, nz, TX, CZ);
 }
 
-template <typename TX_T, bool TRANS>
+// RED: the Schur complement S = A_yy - A_ys A_ss^-1 A_sy of the particle
+// blocks instead of A, over the electrode-level unknowns only: the reaction
+// coupling of each electrode node enters scaled by omega_j (Sherman-Morrison:
+// 1 - Gamma s_j (A_ss,j^-1)_NN = omega_j) and there is no particle column.
+template <typename TX_T, bool TRANS, bool RED = false>
 __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qout, int tile, int TX,
                                      int CZ, OpLds &L)
 {
@@ -851,15 +856,19 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
                 const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
                 const bool dir = (k == 0);
                 const RadialTab &T = O.tabs[el];
-                const long long nn = el == 0 ? g.nea : g.nec;
-                const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
-                const double xsN = ldx(x + offs + (je - base) + (long long)(T.N - 1) * nn);
+                double xsN = 0.0;
+                if (!RED) {
+                    const long long nn = el == 0 ? g.nea : g.nec;
+                    const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+                    xsN = ldx(x + offs + (je - base) + (long long)(T.N - 1) * nn);
+                }
                 const OpCoupling cp = op_coupling<TRANS>(g, T, dir, O.mm[je], O.gg[je], O.ss[je],
                                                          O.ee[je], P.xpsc, P.xpe, P.xce, xsN);
-                O.y[je] = dir ? ldx(x + je) : P.Kps + cp.r0 * cp.q;
-                ype += cp.r1 * cp.q;
-                yce += cp.r2 * cp.q;
-                qout[je] = cp.q;
+                const double q = RED ? cp.q * O.om[je] : cp.q;
+                O.y[je] = dir ? ldx(x + je) : P.Kps + cp.r0 * q;
+                ype += cp.r1 * q;
+                yce += cp.r2 * q;
+                if (!RED) qout[je] = q;
             }
             O.y[g.off_pe + n] = ype;
             O.y[g.off_ce + n] = yce;

@@ -60,6 +60,14 @@ class P4DSolver:
         L.p4d_apply_operator(self.ctx, transpose, x, y)
         return y
 
+    def apply_schur(self, y, transpose=False):
+        """S y (S^T y) over the electrode-level unknowns (the Schur complement
+        of the particle blocks)."""
+        y = self._dev(y)
+        w = torch.empty_like(y)
+        L.p4d_apply_schur_operator(self.ctx, transpose, y, w)
+        return w
+
     def apply_pc(self, r, transpose=False):
         r = self._dev(r)
         z = torch.empty_like(r)
