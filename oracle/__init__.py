@@ -78,7 +78,8 @@ class Desc(C.Structure):
                 ("Ds", C.c_double * 2), ("theta_bar", C.c_double * 2),
                 ("dt", C.c_double), ("chi", C.c_double), ("tc", C.c_double),
                 ("lambda_c", C.c_double), ("eps_elec", C.c_double),
-                ("eps_sep", C.c_double)]
+                ("eps_sep", C.c_double), ("length", C.c_double),
+                ("lambda_el", C.c_double * 2)]
 
 
 class Opts(C.Structure):
@@ -114,6 +115,7 @@ def lib():
         L.orc_fgmres.restype = C.c_int
         L.orc_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_schur_apply.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_set_transport.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_schur_rhs.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_schur_back.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_radial_mesh.argtypes = [C.c_int, C.c_double, _dp]
@@ -220,10 +222,17 @@ class Oracle:
         d.theta_bar[0], d.theta_bar[1] = prob.theta_bar
         d.dt, d.chi, d.tc, d.lambda_c = prob.dt, prob.chi, prob.tc, prob.lambda_c
         d.eps_elec, d.eps_sep = prob.eps_elec, prob.eps_sep
+        d.length = getattr(prob, "length", 0.0)
+        lel = getattr(prob, "lambda_el", (0.0, 0.0))
+        d.lambda_el[0], d.lambda_el[1] = lel
         self.desc = d
         self._keep = [_f64(prob.sigma), _f64(prob.kappa), _f64(prob.g),
                       _f64(prob.s), _f64(prob.e)]
         self.h = lib().orc_create(C.byref(d), *[_p(a) for a in self._keep])
+        kd, dc = getattr(prob, "kappa_d", None), getattr(prob, "dce", None)
+        if kd is not None or dc is not None:
+            self._keep_t = [None if a is None else _f64(a) for a in (kd, dc)]
+            lib().orc_set_transport(self.h, *[None if a is None else _p(a) for a in self._keep_t])
         sz = (C.c_int64 * 8)()
         lib().orc_sizes(self.h, sz)
         self.sizes = list(sz)

@@ -70,6 +70,8 @@ typedef struct {
     double Ds[2];          /* nondimensional particle diffusivity per electrode */
     double theta_bar[2];   /* radial grading Delta_{N-1}/Delta_1                */
     double dt, chi, tc, lambda_c, eps_elec, eps_sep;
+    double length;         /* cell edge along z (h = length / (nz - 1)); 0: 1   */
+    double lambda_el[2];   /* surface coupling scale per electrode; 0: lambda_c */
 } orc_desc;
 
 enum { ORC_PC_SCHUR = 0, ORC_PC_BJ = 1, ORC_PC_BGS = 2 };
@@ -119,6 +121,9 @@ typedef struct {
     long nnode, nelem, nea, nec, ne;
     long off_ps, off_pe, off_ce, off_cs[2], N;
     double *sigma, *kappa, *g, *s, *e, *m;
+    /* optional element coefficients of the diffusion-potential block and of
+     * the c_e diffusion (NULL: chi * kappa and kappa)                       */
+    double *kappad, *dce;
     /* radial: node coordinates and rows of L~_h (flux term excluded) */
     double *rho[2], *Lsub[2], *Ldia[2], *Lsup[2];
     double Gamma[2];
@@ -253,7 +258,9 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
 {
     orc_problem *P = xmalloc(sizeof(orc_problem));
     P->d = *d;
-    P->h = 1.0 / (d->nz - 1);
+    P->h = (d->length > 0.0 ? d->length : 1.0) / (d->nz - 1);
+    P->kappad = NULL;
+    P->dce = NULL;
     P->nc = d->nz - d->na - d->ns;
     P->nnode = (long)d->nx * d->ny * d->nz;
     P->nelem = (long)(d->nx - 1) * (d->ny - 1) * (d->nz - 1);
@@ -310,9 +317,29 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
                                       P->Ldia[el], P->Lsup[el]);
         /* R_cs,N = (c_N - c_N^old)/dt - L_h(c)_N contains -flux * i_n/F;
          * the nondimensional surface coupling scale is lambda_c            */
-        P->Gamma[el] = -flux * d->lambda_c;
+        P->Gamma[el] = -flux * (d->lambda_el[el] > 0.0 ? d->lambda_el[el] : d->lambda_c);
     }
     return P;
+}
+
+/* Element coefficients of the diffusion-potential block (kappa_d: the
+ * (phi_e row, c_e column) stiffness, chi * kappa by default) and of the c_e
+ * diffusion (dce: kappa by default), for transport coefficients that differ
+ * (Sec. 2: kappa_eff 2RT(1 - t+)/(F c_e) and D_e_eff).  NULL keeps the
+ * default.                                                                  */
+void orc_set_transport(orc_problem *P, const double *kappa_d, const double *dce)
+{
+    free(P->kappad); free(P->dce);
+    P->kappad = P->dce = NULL;
+    if (kappa_d) {
+        P->kappad = xmalloc(sizeof(double) * P->nelem);
+        memcpy(P->kappad, kappa_d, sizeof(double) * P->nelem);
+    }
+    if (dce) {
+        P->dce = xmalloc(sizeof(double) * P->nelem);
+        memcpy(P->dce, dce, sizeof(double) * P->nelem);
+    }
+    P->pc_ready = 0;
 }
 
 static void mg_free(orc_mg *M)
@@ -328,6 +355,7 @@ void orc_destroy(orc_problem *P)
 {
     if (!P) return;
     free(P->sigma); free(P->kappa); free(P->g); free(P->s); free(P->e); free(P->m);
+    free(P->kappad); free(P->dce);
     for (int el = 0; el < 2; el++) {
         free(P->rho[el]); free(P->Lsub[el]); free(P->Ldia[el]); free(P->Lsup[el]);
     }
@@ -407,6 +435,18 @@ static double cf_kappa(const orc_problem *P, int i, int j, int k, const void *c)
     (void)c;
     return P->kappa[elem_id(P, i, j, k)] * P->h;
 }
+/* diffusion-potential block and c_e diffusion (defaults chi kappa, kappa) */
+static double cf_kappad(const orc_problem *P, int i, int j, int k, const void *c)
+{
+    (void)c;
+    long id = elem_id(P, i, j, k);
+    return (P->kappad ? P->kappad[id] : P->d.chi * P->kappa[id]) * P->h;
+}
+static double cf_dce(const orc_problem *P, int i, int j, int k, const void *c)
+{
+    (void)c;
+    return (P->dce ? P->dce : P->kappa)[elem_id(P, i, j, k)] * P->h;
+}
 static double cf_mass(const orc_problem *P, int i, int j, int k, const void *c)
 {
     (void)c; (void)i; (void)j;
@@ -453,14 +493,27 @@ void orc_apply(const orc_problem *P, int transpose, const double *x, double *y)
             for (int i = 0; i < d->nx; i++) {
                 long n = node_id(P, i, j, k);
                 double Kpe = elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, xpe);
-                double Kce = elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, xce);
                 double Mce = elem_sum(P, i, j, k, 0, cf_mass, NULL, xv_node, xce);
-                if (!transpose) {
-                    ype[n] = Kpe + d->chi * Kce;
-                    yce[n] = Mce + Kce;
-                } else {
-                    ype[n] = Kpe;
-                    yce[n] = Mce + Kce + d->chi * Kpe;
+                if (!P->kappad && !P->dce) {
+                    double Kce = elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, xce);
+                    if (!transpose) {
+                        ype[n] = Kpe + d->chi * Kce;
+                        yce[n] = Mce + Kce;
+                    } else {
+                        ype[n] = Kpe;
+                        yce[n] = Mce + Kce + d->chi * Kpe;
+                    }
+                } else {   /* separate transport coefficients */
+                    double Dce = elem_sum(P, i, j, k, 1, cf_dce, NULL, xv_node, xce);
+                    double Kx = elem_sum(P, i, j, k, 1, cf_kappad, NULL, xv_node,
+                                         transpose ? xpe : xce);
+                    if (!transpose) {
+                        ype[n] = Kpe + Kx;
+                        yce[n] = Mce + Dce;
+                    } else {
+                        ype[n] = Kpe;
+                        yce[n] = Mce + Dce + Kx;
+                    }
                 }
                 long je = enode(P, i, j, k);
                 if (je >= 0) {
@@ -616,9 +669,11 @@ static void assemble_fine(const orc_problem *P, int box, double *S)
                             if (box <= 1) {
                                 if (elem_mat(P, ek) != box) continue;
                                 cK = cf_sigma(P, ei, ej, ek, NULL);
-                            } else {
+                            } else if (box == 2) {
                                 cK = cf_kappa(P, ei, ej, ek, NULL);
-                                if (box == 3) cM = cf_mass(P, ei, ej, ek, NULL);
+                            } else {
+                                cK = cf_dce(P, ei, ej, ek, NULL);
+                                cM = cf_mass(P, ei, ej, ek, NULL);
                             }
                             int a = (1 - bx) | ((1 - by) << 1) | ((1 - bz) << 2);
                             for (int b = 0; b < 8; b++) {
@@ -984,7 +1039,8 @@ static void bgs_subtract(const orc_problem *P, int transpose, int f, const int *
             for (int j = 0; j < d->ny; j++)
                 for (int i = 0; i < d->nx; i++)
                     tk[node_id(P, i, j, k)] -=
-                        d->chi * elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, zk);
+                        P->kappad ? elem_sum(P, i, j, k, 1, cf_kappad, NULL, xv_node, zk)
+                                  : d->chi * elem_sum(P, i, j, k, 1, cf_kappa, NULL, xv_node, zk);
     }
 }
 

@@ -76,6 +76,14 @@ class Problem:
     e: Optional[np.ndarray] = None
     b: Optional[np.ndarray] = None      # (N,)
     name: str = ""
+    # cell edge along z (0: 1, i.e. nondimensional), surface coupling scale
+    # per electrode (0: lambda_c), and element coefficients of the
+    # diffusion-potential block and the c_e diffusion (None: chi * kappa,
+    # kappa)
+    length: float = 0.0
+    lambda_el: Tuple[float, float] = (0.0, 0.0)
+    kappa_d: Optional[np.ndarray] = None  # (n_elem,)
+    dce: Optional[np.ndarray] = None      # (n_elem,)
 
     # ---- sizes -----------------------------------------------------------
     @property
@@ -119,7 +127,7 @@ class Problem:
 
     @property
     def h(self) -> float:
-        return 1.0 / (self.nz - 1)
+        return (self.length if self.length > 0 else 1.0) / (self.nz - 1)
 
     def with_(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)

@@ -129,6 +129,46 @@ def test_blocks_match_quadrature_assembly(seed):
     assert np.allclose(block(orc, p, 2, 1, True), p.chi * Kk.toarray(), atol=tol * h)
 
 
+def test_general_transport_coefficients_and_length():
+    """Separate element coefficients for the diffusion-potential block and
+    the c_e diffusion, a physical cell length and per-electrode coupling
+    scales: every block equals the Q1 assembly with those coefficients on the
+    scaled grid, and the surface coupling scales per electrode."""
+    p = problem(seed=13, bv=False)
+    rng = np.random.default_rng(5)
+    kd = np.exp(0.5 * rng.standard_normal(p.n_elem))
+    dc = np.exp(0.5 * rng.standard_normal(p.n_elem))
+    L = 2.25e-4
+    q = p.with_(kappa_d=kd, dce=dc, length=L, lambda_el=(0.7, 1.9))
+    orc = O.Oracle(q)
+    h = q.h
+    assert h == pytest.approx(L / (p.nz - 1))
+    emat = elem_mat_array(p)
+    eps = np.where(emat >= 0, p.eps_elec, p.eps_sep)
+    nodes = (p.nx, p.ny, p.nz)
+    coords = [np.arange(n) * h for n in nodes]
+    Kk = qref.assemble_box(*nodes, p.kappa, None, *coords).toarray()
+    Kd = qref.assemble_box(*nodes, kd, None, *coords).toarray()
+    Kc = qref.assemble_box(*nodes, dc, None, *coords).toarray()
+    Me = qref.assemble_box(*nodes, np.zeros(p.n_elem), eps / p.dt, *coords).toarray()
+    tol = 1e-13 * h
+    assert np.allclose(block(orc, q, 1, 1), Kk, atol=tol)
+    assert np.allclose(block(orc, q, 1, 2), Kd, atol=tol)
+    assert np.allclose(block(orc, q, 2, 2), Me + Kc, atol=max(tol, 1e-13 * np.abs(Me).max()))
+    assert np.allclose(block(orc, q, 2, 1, True), Kd, atol=tol)
+    assert np.abs(block(orc, q, 1, 2, True)).max() == 0.0
+    # the default coefficients reproduce the plain operator
+    q0 = p.with_(kappa_d=p.chi * p.kappa, dce=p.kappa)
+    x = rng.standard_normal(p.N)
+    ref = O.Oracle(p).apply(x)
+    assert np.allclose(O.Oracle(q0).apply(x), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    # surface coupling: lambda per electrode replaces lambda_c
+    g0 = [O.Oracle(p).radial(el)[4] for el in (0, 1)]
+    g1 = [orc.radial(el)[4] for el in (0, 1)]
+    assert g1[0] == pytest.approx(0.7 * g0[0] / p.lambda_c)
+    assert g1[1] == pytest.approx(1.9 * g0[1] / p.lambda_c)
+
+
 def test_lumped_weights_are_row_sum_lumped_electrode_mass():
     p = problem()
     orc = O.Oracle(p)

@@ -127,6 +127,39 @@ def test_block_gauss_seidel_orderings_differ():
     assert np.linalg.norm(zt - zs[3]) > 1e-6 * np.linalg.norm(zt)
 
 
+def tiny_general(seed):
+    """tiny() with separate diffusion-potential and c_e diffusion
+    coefficients, a physical length and per-electrode coupling scales."""
+    p = tiny(seed, sigma_log=1.0)
+    rng = np.random.default_rng(seed + 100)
+    return p.with_(kappa_d=np.exp(0.5 * rng.standard_normal(p.n_elem)),
+                   dce=np.exp(0.5 * rng.standard_normal(p.n_elem)), length=3.0,
+                   lambda_el=(0.6, 1.7))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_preconditioners_exact_with_general_transport(transpose):
+    """The field blocks given to the direct coarse solves follow the general
+    coefficients: SCHUR is the exact block LDU, BGS is eq. PGS."""
+    p = tiny_general(8)
+    orc = O.Oracle(p).setup(pc=O.PC_SCHUR, coarse_max=512)
+    A = orc.dense()
+    Ayy, Ays, Asy, Ass = schur_blocks(p, A)
+    S = Ayy - Ays @ np.linalg.solve(Ass, Asy)
+    St = np.zeros_like(S)
+    for a, b in field_ranges(p):
+        St[a:b, a:b] = S[a:b, a:b]
+    P = np.block([[St + Ays @ np.linalg.solve(Ass, Asy), Ays], [Asy, Ass]])
+    r = np.random.default_rng(3).standard_normal(p.N)
+    ref = np.linalg.solve(P.T if transpose else P, r)
+    assert np.allclose(orc.apply_pc(r, transpose), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    for fields in [(1, 3, 0, 2), (2, 0, 3, 1)]:
+        orc.setup(pc=O.PC_BGS, coarse_max=512, bgs_order=O.bgs_order(fields))
+        Pg = pgs_dense(A, field_blocks(p), fields)
+        ref = np.linalg.solve(Pg.T if transpose else Pg, r)
+        assert np.allclose(orc.apply_pc(r, transpose), ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+
+
 def test_bgs_order_packing():
     assert O.BGS_PAPER == O.bgs_order((O.F_PHIE, O.F_CS, O.F_PHIS, O.F_CE))
     for fields in ALL_ORDERINGS:
