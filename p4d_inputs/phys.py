@@ -1,0 +1,105 @@
+"""Physical parameters and geometry of the paper's homogeneous cube cell
+(Case I, Sec. 5; parameter tables of the appendix).  Data only: no step of
+the method is computed here (kinetics, open-circuit potentials, transport
+functions and the residual are written separately by the oracle and the GPU
+library).
+
+Geometry: a cube of edge 225 um along x, y and z; the negative electrode
+(graphite) occupies z in [0, 100 um], the separator (100, 125) and the
+positive electrode (LiCoO2) [125, 225].  The node grid is n x n x n with
+n - 1 a multiple of 9 (at least 18), so that every layer boundary falls on
+element faces: 25 um is (n - 1) / 9 elements.  phi_s = 0 on the bottom face (the negative
+collector); the applied current enters through the top face.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+import numpy as np
+
+# universal constants (table "Universal physical constants")
+F = 96485.33       # C / mol
+R_GAS = 8.31446    # J / (mol K)
+T_REF = 298.15     # K
+
+# electrolyte (table "Electrolyte parameters")
+CE0 = 1000.0       # mol / m^3
+T_PLUS = 0.4
+BRUGGEMAN = 1.5
+
+
+@dataclass(frozen=True)
+class Electrode:
+    eps_s: float       # active material volume fraction
+    eps: float         # porosity
+    sigma: float       # solid conductivity, S/m
+    k: float           # reaction rate constant, A/m^2 (m^3/mol)^1.5
+    alpha: float       # charge-transfer coefficients (anodic = cathodic)
+    cs_max: float      # mol / m^3
+    cs0: float         # initial solid concentration, mol / m^3
+    a: float           # specific interfacial area, 1/m
+    Ds: float          # solid diffusivity, m^2/s
+    Rs: float          # particle radius, m
+
+
+# tables "Anode (negative electrode) parameters" and "Cathode (positive
+# electrode) parameters"
+NEGATIVE = Electrode(eps_s=0.6, eps=0.3, sigma=100.0, k=2e-5, alpha=0.5, cs_max=2.50e4,
+                     cs0=2.00e4, a=1.8e5, Ds=3.9e-14, Rs=1.0e-5)
+POSITIVE = Electrode(eps_s=0.5, eps=0.3, sigma=10.0, k=6e-7, alpha=0.5, cs_max=5.12e4,
+                     cs0=3.07e4, a=1.5e5, Ds=1.0e-13, Rs=1.0e-5)
+SEPARATOR_EPS = 1.0
+
+CELL_EDGE = 225e-6                                 # m
+LAYERS_UM = (100.0, 25.0, 100.0)                   # negative, separator, positive
+
+
+@dataclass
+class PhysCase:
+    """The cube cell on an n^3 node grid with N_r radial points per particle."""
+    n: int
+    nr: Tuple[int, int]
+    dt: float = 60.0                   # s (one minute, Sec. 5)
+    c_rate: float = 1.0
+    theta_bar: Tuple[float, float] = (0.5, 0.5)
+    gauss_frac: float = 0.1            # spread of the applied current / collector edge
+    electrodes: Tuple[Electrode, Electrode] = field(default_factory=lambda: (NEGATIVE, POSITIVE))
+
+    def __post_init__(self):
+        if (self.n - 1) % 9 != 0 or self.n < 19:
+            raise ValueError("n - 1 must be a multiple of 9, at least 18 (two elements per 25 um)")
+
+    # node layers: elements kk with kk + 1 < na are negative-electrode
+    # elements, kk >= na + ns positive ones (the library's convention)
+    @property
+    def elems_25um(self) -> int:
+        return (self.n - 1) // 9
+
+    @property
+    def na(self) -> int:
+        return 4 * self.elems_25um + 1
+
+    @property
+    def ns(self) -> int:
+        return self.elems_25um - 1
+
+    @property
+    def nz(self) -> int:
+        return self.n
+
+    @property
+    def h(self) -> float:
+        return CELL_EDGE / (self.n - 1)
+
+    @property
+    def electrode_volume(self) -> float:
+        return CELL_EDGE * CELL_EDGE * LAYERS_UM[0] * 1e-6
+
+
+def case_desc(case: PhysCase) -> dict:
+    """Fields of the problem description that are plain data of the case:
+    grid, radial sizes, time step, porosities and the cell edge."""
+    return dict(nx=case.n, ny=case.n, nz=case.n, na=case.na, ns=case.ns, nr=tuple(case.nr),
+                theta_bar=tuple(case.theta_bar), dt=case.dt,
+                eps_elec=case.electrodes[0].eps, eps_sep=SEPARATOR_EPS, length=CELL_EDGE)

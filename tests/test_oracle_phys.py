@@ -1,0 +1,149 @@
+"""Pins of the oracle's physical model (Sec. 2 equations with the appendix
+parameters, Case I cube of Sec. 5): material functions, the rest state, the
+Newton matrix against finite differences of the residual, charge balance and
+electrolyte lithium conservation of converged steps."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import phys as P
+from p4d_inputs import phys as ph
+
+
+@pytest.fixture(scope="module")
+def cube():
+    case = ph.PhysCase(n=19, nr=(6, 7))
+    grid = P.Grid(case)
+    return case, grid
+
+
+def test_material_function_derivatives():
+    """Open-circuit potentials: the returned derivatives equal central
+    differences over the stoichiometry range; kappa stays positive and D_e
+    decreases over 0..3000 mol/m^3."""
+    th = np.linspace(0.05, 0.95, 37)
+    h = 1e-6
+    for f in (P.ocp_negative, P.ocp_positive):
+        u, du = f(th)
+        fd = (f(th + h)[0] - f(th - h)[0]) / (2 * h)
+        assert np.allclose(du, fd, rtol=1e-6, atol=1e-6)
+    c = np.linspace(1.0, 3000.0, 301)
+    assert np.all(P.kappa_bulk(c) > 0)
+    assert np.all(np.diff(P.de_bulk(c)) < 0)
+
+
+def test_layers_and_grid(cube):
+    case, grid = cube
+    # 225 um cube: 100 / 25 / 100 um on element faces
+    h = case.h
+    assert (case.na - 1) * h == pytest.approx(100e-6)
+    assert (case.na + case.ns) * h == pytest.approx(125e-6)
+    assert grid.nc == case.na
+    assert (grid.emat == 0).sum() == (grid.emat == 1).sum()
+
+
+def test_rest_state_is_a_solution_at_zero_current(cube):
+    """c_e = c_e0, c_s = c_s0 and zero overpotential: every residual row
+    vanishes (to rounding) when no current is applied."""
+    case, grid = cube
+    u0 = P.initial_state(case, grid)
+    R = P.residual(case, grid, u0, u0, 0.0)
+    q, _, _, _ = P.kinetics(case, grid, u0)
+    assert np.abs(q).max() < 1e-9
+    sc = P.Scaling(case)
+    assert np.abs(sc.rows(grid, R)).max() < 1e-9
+
+
+def _fd(case, grid, u, u_old, I, v, eps):
+    return (P.residual(case, grid, u + eps * v, u_old, I) -
+            P.residual(case, grid, u - eps * v, u_old, I)) / (2 * eps)
+
+
+def _block_errors(case, grid, a, b, rows=("phis", "phie", "ce", "cs")):
+    """Relative error per field block of the scaled rows D_r a against D_r b
+    (in SI units the blocks differ by ten orders of magnitude)."""
+    sc = P.Scaling(case)
+    ra, rb = sc.rows(grid, a), sc.rows(grid, b)
+    sl = {"phis": slice(grid.layer, grid.off_pe), "phie": slice(grid.off_pe, grid.off_ce),
+          "ce": slice(grid.off_ce, grid.off_cs[0]), "cs": slice(grid.off_cs[0], grid.N)}
+    return {k: np.linalg.norm(ra[sl[k]] - rb[sl[k]]) / np.linalg.norm(rb[sl[k]]) for k in rows}
+
+
+def _direction(grid, rng, ce=True):
+    v = rng.standard_normal(grid.N)
+    v[: grid.off_ce] *= 1e-3            # volts
+    v[grid.off_ce: grid.off_cs[0]] *= 1.0 if ce else 0.0
+    v[grid.off_cs[0]:] *= 10.0
+    v[: grid.layer] = 0.0               # grounded phi_s
+    return v
+
+
+def test_newton_matrix_is_the_jacobian_at_rest(cube):
+    """At the rest state the transport coefficients are stationary in c_e
+    (uniform c_e, no gradients), so the Newton matrix is the exact Jacobian:
+    it matches central differences of the residual to O(eps^2)."""
+    case, grid = cube
+    u0 = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    J = O.Oracle(P.linear_problem(case, grid, u0))
+    v = _direction(grid, np.random.default_rng(1))
+    Jv = J.apply(v)
+    e2 = _block_errors(case, grid, _fd(case, grid, u0, u0, I, v, 1e-2), Jv)
+    e3 = _block_errors(case, grid, _fd(case, grid, u0, u0, I, v, 1e-3), Jv)
+    for k in e3:
+        assert e3[k] < 1e-7, (k, e2, e3)
+
+
+def test_newton_matrix_exact_in_the_kinetics_after_a_step(cube):
+    """After a discharge step c_e is no longer uniform; for directions that
+    leave c_e unchanged the transport coefficients do not move, and the
+    Newton matrix still equals the Jacobian (kinetics, coupling, radial and
+    storage rows)."""
+    case, grid = cube
+    u0 = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    u1, _ = P.newton_step(case, grid, u0, I)
+    J = O.Oracle(P.linear_problem(case, grid, u1))
+    v = _direction(grid, np.random.default_rng(2), ce=False)
+    Jv = J.apply(v)
+    err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, v, 1e-3), Jv)
+    assert max(err.values()) < 1e-6, err
+    # a c_e-only direction moves the transport coefficients too, but the
+    # phi_s and c_s rows see c_e only through the kinetics (i0 ~ c_e^alpha)
+    w = np.zeros(grid.N)
+    w[grid.off_ce: grid.off_cs[0]] = np.random.default_rng(3).standard_normal(grid.nnode)
+    Jw = J.apply(w)
+    err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, w, 1e-3), Jw, rows=("phis", "cs"))
+    assert max(err.values()) < 1e-6, err
+
+
+def test_converged_step_balances_charge_and_conserves_electrolyte_lithium(cube):
+    """Two 60 s steps at 1C: Newton converges; the reaction current of each
+    electrode equals the applied current (negative electrode +|I|, positive
+    -|I|, discharge); the electrolyte lithium sum_e eps int c_e is conserved;
+    the negative particles lose lithium at the surface and the positive ones
+    gain it."""
+    case, grid = cube
+    u = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    lp = P.linear_problem(case, grid, u, with_kinetics=False)
+    mass = O.Oracle(lp.with_(kappa=0 * lp.kappa, kappa_d=0 * lp.kappa, dce=0 * lp.kappa,
+                             sigma=0 * lp.sigma))
+    m = O.Oracle(lp).lumped_weights()
+
+    def electrolyte_li(x):
+        y = np.zeros(grid.N)
+        y[grid.off_ce: grid.off_cs[0]] = x[grid.off_ce: grid.off_cs[0]]
+        return mass.apply(y)[grid.off_ce: grid.off_cs[0]].sum() * case.dt
+
+    li0 = electrolyte_li(u)
+    for _ in range(2):
+        un, hist = P.newton_step(case, grid, u, I)
+        assert hist[-1][0] <= 1e-9 and len(hist) < 15
+        q, _, _, _ = P.kinetics(case, grid, un)
+        assert (m * q)[: grid.nea].sum() == pytest.approx(-I, rel=1e-7)
+        assert (m * q)[grid.nea:].sum() == pytest.approx(I, rel=1e-7)
+        assert np.all(grid.surface(un, 0) < grid.surface(u, 0))
+        assert np.all(grid.surface(un, 1) > grid.surface(u, 1))
+        u = un
+    assert electrolyte_li(u) == pytest.approx(li0, rel=1e-10)
