@@ -174,6 +174,43 @@ def bench_batch(steps):
     return out
 
 
+def bench_newton(n=64, nr=(10, 10), steps=30):
+    """The physical cube cell (Case I: 225 um cube, 100/25/100 um layers,
+    appendix parameters, Gaussian 1C discharge current): `steps`
+    backward-Euler steps of 60 s, each by Newton iterations on the GPU."""
+    import torch
+    from p4d_inputs import phys as ph
+    from paper_2602_07225_amd import PhysCell
+    from paper_2602_07225_amd import _lib as L
+    case = ph.PhysCase(n=n, nr=nr)
+    q = [ph.F / 3600.0 * e.eps_s * case.electrode_volume * e.cs_max for e in case.electrodes]
+    current = -case.c_rate * min(q)
+    cell = PhysCell(case, current, coarse_max=64)
+    u = cell.initial_state()
+    o = cell.offsets
+    top = slice(o[1] - n * n, o[1])          # phi_s on the top face (positive collector)
+    v0 = u[top].mean().item()
+    cell.step(u)                              # warm-up (compiles nothing, touches every kernel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton, lin, worst = [], 0, 0
+    for _ in range(steps):
+        u, info = cell.step(u)
+        if info.status != 0:
+            raise RuntimeError(f"Newton did not converge: status {info.status}")
+        newton.append(info.iters)
+        lin += info.lin_iters
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out = {"nodes_per_edge": n, "nr": list(nr), "dof": cell.N, "steps": steps, "dt_s": case.dt,
+           "applied_current_A": current, "total_ms": 1e3 * t, "ms_per_step": 1e3 * t / steps,
+           "newton_iters_per_step": float(np.mean(newton)), "newton_iters_max": int(max(newton)),
+           "fgmres_iters_per_newton": lin / max(1, sum(newton)),
+           "voltage_start_V": v0, "voltage_end_V": u[top].mean().item()}
+    cell.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +226,8 @@ def main():
     ap.add_argument("--schur-only", action="store_true",
                     help="only the cube solve with the Krylov space reduced to the Schur complement "
                          "of the particle blocks (prints its JSON fields; for profiling)")
+    ap.add_argument("--newton-only", action="store_true",
+                    help="only the Newton steps of the physical cube cell (prints its JSON fields)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 512 MiB device copy first (a reference of known size "
                          "for hardware byte counters)")
@@ -198,6 +237,7 @@ def main():
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
+    global np
     import numpy as np
     import torch
 
@@ -208,6 +248,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"C4_batch_64_cells": bench_batch(args.steps)}), flush=True)
+        return
+    if args.newton_only:
+        print(json.dumps({"newton_case_I_cube": bench_newton()}), flush=True)
         return
     if args.schur_only:
         p = pi.make_config(2)
@@ -418,6 +461,14 @@ def main():
 
     if not args.no_extras:
         extras["C4_batch_64_cells"] = bench_batch(args.steps)
+        try:
+            extras["newton_case_I_cube"] = bench_newton()
+            e = extras["newton_case_I_cube"]
+            log(f"[bench] Newton Case I: {e['steps']} steps, {e['ms_per_step']:.1f} ms/step, "
+                f"{e['newton_iters_per_step']:.1f} Newton it/step, V {e['voltage_start_V']:.4f} -> "
+                f"{e['voltage_end_V']:.4f}")
+        except RuntimeError as ex:
+            extras["newton_case_I_cube"] = {"error": str(ex)}
 
     cpu = None
     if not args.no_cpu:

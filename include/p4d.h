@@ -103,6 +103,9 @@ typedef struct {
     double tc;                 /* electrolyte source factor (1 - t+)              */
     double lambda_c;           /* scale of the surface coupling                   */
     double eps_elec, eps_sep;  /* porosity in electrode and separator elements    */
+    double length;             /* cell edge along z: h = length / (nz - 1); 0: 1  */
+    double lambda_el[2];       /* surface coupling scale per electrode; 0 keeps
+                                  lambda_c                                        */
 } p4d_problem_desc;
 
 typedef struct {
@@ -179,6 +182,19 @@ p4d_status p4d_set_diffusivity(p4d_ctx *ctx, const double Ds[2], void *stream);
 /* Build the preconditioner (surface-coupling weights, Galerkin multigrid
  * hierarchies, Chebyshev bounds, dense coarse inverses).  Synchronizes.    */
 p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
+
+/* Separate element coefficients (device, one per element, caller-owned, read
+ * during the call) of the electrolyte equations (paper Sec. 2, eq. phie-weak
+ * and ce-weak): d_kappa_d for the diffusion-potential block (phi_e row, c_e
+ * column; kappa_eff 2RT(1 - t+)/(F c_e) in the physical model) and d_dce for
+ * the c_e diffusion (D_e_eff).  NULL keeps the default (chi * kappa, and
+ * kappa, the operator of p4d_upload); both NULL restores it.  Needs
+ * p4d_upload, which resets them; invalidates p4d_setup.  With separate
+ * coefficients the operator runs one thread per node, the Schur-complement
+ * Krylov space (P4D_KRYLOV_SCHUR) is not available, and batches do not
+ * apply.                                                                   */
+p4d_status p4d_set_transport(p4d_ctx *ctx, const double *d_kappa_d, const double *d_dce,
+                             void *stream);
 
 /* d_y = A d_x, or A^T d_x if transpose (eq. blocks).  d_x, d_y: length N,
  * must not alias.  Needs p4d_upload.                                       */
@@ -311,6 +327,87 @@ p4d_status p4d_batch_profile(p4d_batch *batch, int class_mask);
 p4d_status p4d_batch_profile_read(p4d_batch *batch, int kernel_class, double *total_ms,
                                   int64_t *launches, double *bytes);
 const char *p4d_batch_last_error(const p4d_batch *batch);
+
+/* ------------------------------------------------------------------------ */
+/* Physical cell: the Newton step around the linear solve (paper Sec. 4.1)   */
+/* for the cube cell of Sec. 5 (Case I) with the model of Sec. 2 and the     */
+/* appendix parameters: Butler-Volmer kinetics with the open-circuit         */
+/* potentials, kappa(c_e), D_e(c_e), Bruggeman corrections, the Gaussian     */
+/* applied current on the top face.  The state u is in SI units (V, V,       */
+/* mol/m^3, mol/m^3) in the global layout above.  The context's linear       */
+/* operator is the Newton matrix in scaled variables (unknowns divided and   */
+/* equations multiplied by per-field scales), with transport coefficients   */
+/* at the element-mean c_e of the current iterate; p4d_solve and the other  */
+/* linear calls work on it as on any context.                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double eps_s;      /* active material volume fraction                     */
+    double eps;        /* porosity (the same in both electrodes)              */
+    double sigma;      /* solid conductivity, S/m                             */
+    double k;          /* reaction rate constant                              */
+    double alpha;      /* anodic = cathodic charge-transfer coefficient       */
+    double cs_max, cs0;/* maximum and initial solid concentration, mol/m^3    */
+    double a;          /* specific interfacial area, 1/m                      */
+    double Ds;         /* solid diffusivity, m^2/s                            */
+    double Rs;         /* particle radius, m                                  */
+} p4d_electrode;
+
+typedef struct {
+    int32_t n;            /* nodes per edge of the cube: n - 1 a multiple of 9, >= 18
+                             (negative 4/9, separator 1/9, positive 4/9 of the edge) */
+    int32_t nr[2];        /* radial points, negative / positive, 3..64           */
+    double theta_bar[2];  /* radial grading                                      */
+    double dt;            /* backward-Euler step, s                              */
+    double current;       /* applied current, A (negative: discharge, the current
+                             leaves through the top face)                        */
+    double gauss_frac;    /* spread of the Gaussian current profile / cube edge  */
+    double edge;          /* cube edge, m                                        */
+    double F, R, T;       /* Faraday constant, gas constant, temperature         */
+    double t_plus, brug;  /* transference number, Bruggeman exponent            */
+    double ce0;           /* initial electrolyte concentration, mol/m^3          */
+    double eps_sep;       /* separator porosity                                  */
+    p4d_electrode el[2];  /* negative (bottom, grounded), positive (top)         */
+} p4d_phys_params;
+
+typedef struct {
+    int32_t maxit;        /* Newton iterations per step (default 30)             */
+    double tol;           /* stop when max |du_f| / scale_f <= tol (RT/F for the
+                             potentials, c_e0, c_s,max per electrode); 1e-9      */
+} p4d_newton_opts;
+
+typedef struct {
+    int32_t iters;        /* Newton iterations taken                             */
+    int32_t status;       /* 0 converged, 1 not converged, else a p4d_status     */
+    int32_t lin_iters;    /* FGMRES iterations summed over the step              */
+    double update;        /* the last scaled update                              */
+    double t_ms;          /* wall time of the step                               */
+} p4d_newton_info;
+
+/* Context for the cube cell described by prm (validated: INVALID_ARG).      */
+p4d_status p4d_phys_create(const p4d_phys_params *prm, p4d_ctx **ctx);
+/* Device bytes of the Newton buffers (four state-sized vectors and two per
+ * electrode node), beyond p4d_workspace_size.                               */
+p4d_status p4d_phys_workspace_size(const p4d_ctx *ctx, size_t *bytes);
+/* Hands the context its Newton buffers (device, caller-owned, kept until
+ * destroy); needs p4d_set_workspace first.                                  */
+p4d_status p4d_phys_set_workspace(p4d_ctx *ctx, void *d_work, size_t bytes);
+/* d_u = the rest state: c_e0, c_s0 and zero overpotential (phi_s = 0 in the
+ * negative electrode, phi_e = -U_n, phi_s = U_p - U_n in the positive one). */
+p4d_status p4d_phys_initial_state(p4d_ctx *ctx, double *d_u, void *stream);
+/* d_r = R(d_u), the residual of the backward-Euler step from d_uold in SI
+ * units per row (phi rows in A, c_e rows in mol/s, c_s rows in mol/(m^3 s);
+ * grounded phi_s rows: phi_s).  Leaves the Newton matrix at d_u in the
+ * context.                                                                 */
+p4d_status p4d_phys_residual(p4d_ctx *ctx, const double *d_u, const double *d_uold, double *d_r,
+                             void *stream);
+/* One backward-Euler step from d_uold: Newton iterations from the guess in
+ * d_u (overwritten with the result), each a p4d_setup and an FGMRES solve of
+ * the scaled Newton system with solve (may be NULL: defaults; the Krylov
+ * space must be the full one), until the scaled update meets newton->tol.
+ * Synchronizes `stream` once per iteration.                                */
+p4d_status p4d_phys_newton_step(p4d_ctx *ctx, double *d_u, const double *d_uold,
+                                const p4d_solve_opts *solve, const p4d_newton_opts *newton,
+                                p4d_newton_info *info, void *stream);
 
 #ifdef __cplusplus
 }

@@ -42,13 +42,16 @@ KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "o
 
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
-    "p4d_set_workspace", "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
+    "p4d_set_workspace", "p4d_upload", "p4d_set_transport", "p4d_set_diffusivity", "p4d_setup",
+    "p4d_apply_operator",
     "p4d_apply_schur_operator", "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
     "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
     "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_cell", "p4d_batch_workspace_size",
     "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_autotune",
     "p4d_batch_solve", "p4d_batch_set_pc_mode", "p4d_batch_profile", "p4d_batch_profile_read",
     "p4d_batch_last_error",
+    "p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace", "p4d_phys_initial_state",
+    "p4d_phys_residual", "p4d_phys_newton_step",
 ]
 
 
@@ -57,7 +60,8 @@ class ProblemDesc(C.Structure):
                 ("na", C.c_int32), ("ns", C.c_int32), ("nr", C.c_int32 * 2),
                 ("Ds", C.c_double * 2), ("theta_bar", C.c_double * 2),
                 ("dt", C.c_double), ("chi", C.c_double), ("tc", C.c_double),
-                ("lambda_c", C.c_double), ("eps_elec", C.c_double), ("eps_sep", C.c_double)]
+                ("lambda_c", C.c_double), ("eps_elec", C.c_double), ("eps_sep", C.c_double),
+                ("length", C.c_double), ("lambda_el", C.c_double * 2)]
 
 
 class SolveOpts(C.Structure):
@@ -65,6 +69,31 @@ class SolveOpts(C.Structure):
                 ("maxit", C.c_int32), ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
                 ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double),
                 ("bgs_order", C.c_int32), ("krylov", C.c_int32)]
+
+
+class Electrode(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("eps_s", "eps", "sigma", "k", "alpha", "cs_max", "cs0", "a", "Ds", "Rs")]
+
+
+class PhysParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nr", C.c_int32 * 2), ("theta_bar", C.c_double * 2),
+                ("dt", C.c_double), ("current", C.c_double), ("gauss_frac", C.c_double),
+                ("edge", C.c_double), ("F", C.c_double), ("R", C.c_double), ("T", C.c_double),
+                ("t_plus", C.c_double), ("brug", C.c_double), ("ce0", C.c_double),
+                ("eps_sep", C.c_double), ("el", Electrode * 2)]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("maxit", C.c_int32), ("tol", C.c_double)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("lin_iters", C.c_int32),
+                ("update", C.c_double), ("t_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveInfo(C.Structure):
@@ -106,6 +135,7 @@ def lib():
         L.p4d_upload.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.p4d_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
         L.p4d_set_diffusivity.argtypes = [vp, C.POINTER(C.c_double), vp]
+        L.p4d_set_transport.argtypes = [vp, vp, vp, vp]
         L.p4d_apply_operator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_schur_operator.argtypes = [vp, C.c_int, vp, vp, vp]
@@ -121,14 +151,82 @@ def lib():
         L.p4d_last_error.restype = C.c_char_p
         L.p4d_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
         for name in ["p4d_autotune", "p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
-                     "p4d_upload", "p4d_set_diffusivity", "p4d_setup", "p4d_apply_operator",
+                     "p4d_upload", "p4d_set_transport", "p4d_set_diffusivity", "p4d_setup",
+                     "p4d_apply_operator",
                      "p4d_apply_preconditioner", "p4d_apply_schur_operator",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
                      "p4d_profile_read"]:
             getattr(L, name).restype = C.c_int
         _bind_batch(L)
+        _bind_phys(L)
         _lib = L
     return _lib
+
+
+def _bind_phys(L):
+    vp = C.c_void_p
+    L.p4d_phys_create.argtypes = [C.POINTER(PhysParams), C.POINTER(vp)]
+    L.p4d_phys_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.p4d_phys_set_workspace.argtypes = [vp, vp, C.c_size_t]
+    L.p4d_phys_initial_state.argtypes = [vp, vp, vp]
+    L.p4d_phys_residual.argtypes = [vp, vp, vp, vp, vp]
+    L.p4d_phys_newton_step.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(NewtonOpts),
+                                       C.POINTER(NewtonInfo), vp]
+    for name in ("p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace",
+                 "p4d_phys_initial_state", "p4d_phys_residual", "p4d_phys_newton_step"):
+        getattr(L, name).restype = C.c_int
+
+
+def phys_params(case, current: float) -> PhysParams:
+    """PhysParams from a p4d_inputs.phys.PhysCase (data of the case) and the
+    applied current."""
+    from p4d_inputs import phys as ph
+    p = PhysParams()
+    p.n = case.n
+    p.nr[0], p.nr[1] = case.nr
+    p.theta_bar[0], p.theta_bar[1] = case.theta_bar
+    p.dt, p.current, p.gauss_frac, p.edge = case.dt, current, case.gauss_frac, ph.CELL_EDGE
+    p.F, p.R, p.T = ph.F, ph.R_GAS, ph.T_REF
+    p.t_plus, p.brug, p.ce0, p.eps_sep = ph.T_PLUS, ph.BRUGGEMAN, ph.CE0, ph.SEPARATOR_EPS
+    for i, e in enumerate(case.electrodes):
+        for k, _ in Electrode._fields_:
+            setattr(p.el[i], k, getattr(e, k))
+    return p
+
+
+def p4d_phys_create(params: PhysParams) -> int:
+    h = C.c_void_p()
+    check(lib().p4d_phys_create(C.byref(params), C.byref(h)), None, "p4d_phys_create")
+    return h.value
+
+
+def p4d_phys_workspace_size(ctx) -> int:
+    n = C.c_size_t()
+    check(lib().p4d_phys_workspace_size(ctx, C.byref(n)), ctx, "p4d_phys_workspace_size")
+    return n.value
+
+
+def p4d_phys_set_workspace(ctx, ptr_, nbytes):
+    return check(lib().p4d_phys_set_workspace(ctx, ptr_, nbytes), ctx, "p4d_phys_set_workspace")
+
+
+def p4d_phys_initial_state(ctx, u, stream=None):
+    return check(lib().p4d_phys_initial_state(ctx, ptr(u), stream_ptr(stream)), ctx,
+                 "p4d_phys_initial_state")
+
+
+def p4d_phys_residual(ctx, u, uold, r, stream=None):
+    return check(lib().p4d_phys_residual(ctx, ptr(u), ptr(uold), ptr(r), stream_ptr(stream)), ctx,
+                 "p4d_phys_residual")
+
+
+def p4d_phys_newton_step(ctx, u, uold, solve: SolveOpts | None = None, newton: NewtonOpts | None = None,
+                         stream=None):
+    info = NewtonInfo()
+    st = check(lib().p4d_phys_newton_step(ctx, ptr(u), ptr(uold), C.byref(solve) if solve else None,
+                                          C.byref(newton) if newton else None, C.byref(info),
+                                          stream_ptr(stream)), ctx, "p4d_phys_newton_step")
+    return st, info
 
 
 def _bind_batch(L):
@@ -190,6 +288,9 @@ def desc_from(p) -> ProblemDesc:
     d.theta_bar[0], d.theta_bar[1] = p.theta_bar
     d.dt, d.chi, d.tc, d.lambda_c = p.dt, p.chi, p.tc, p.lambda_c
     d.eps_elec, d.eps_sep = p.eps_elec, p.eps_sep
+    d.length = getattr(p, "length", 0.0)
+    lel = getattr(p, "lambda_el", (0.0, 0.0))
+    d.lambda_el[0], d.lambda_el[1] = lel
     return d
 
 
@@ -252,6 +353,12 @@ def p4d_set_diffusivity(ctx, Ds, stream=None):
 def p4d_setup(ctx, opts: SolveOpts | None = None, stream=None):
     return check(lib().p4d_setup(ctx, C.byref(opts) if opts else None, stream_ptr(stream)),
                  ctx, "p4d_setup")
+
+
+def p4d_set_transport(ctx, kappa_d=None, dce=None, stream=None):
+    return check(lib().p4d_set_transport(ctx, ptr(kappa_d) if kappa_d is not None else None,
+                                         ptr(dce) if dce is not None else None, stream_ptr(stream)),
+                 ctx, "p4d_set_transport")
 
 
 def p4d_apply_operator(ctx, transpose, x, y, stream=None):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libp4d.so")
-SOURCES = ["p4d_api.hip", "operator.hip", "radial.hip", "mg.hip", "krylov.hip", "batch.hip", "bgs.hip", "reduced.hip"]
+SOURCES = ["p4d_api.hip", "operator.hip", "radial.hip", "mg.hip", "krylov.hip", "batch.hip", "bgs.hip", "reduced.hip", "phys.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -ffp-contract=on: multiply-adds are fused only inside one source
 # expression, so an expression shared by several kernels rounds the same way

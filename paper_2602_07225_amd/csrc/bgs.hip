@@ -6,7 +6,8 @@
 //     b = (g, -g, e, s) over phi_s, phi_e, c_e and the c_s surface value, the
 //     phi_s entries zero on the grounded layer), entering the c_s surface row
 //     for f = c_s; transposed, a and b swap;
-//   - chi K_kappa in the (phi_e row, c_e column) block; transposed, in the
+//   - the diffusion-potential block (chi K_kappa, or its own element
+//     coefficients) in the (phi_e row, c_e column) block; transposed, in the
 //     (c_e row, phi_e column) block.
 // Solved values are read in FP64: the final level-0 V-cycle iterates of the
 // electrode-level fields and the c_s surface values kept per electrode node.
@@ -61,10 +62,10 @@ __global__ __launch_bounds__(kBlock) void k_bgs_rhs(Geom g, BgsArgs B, const dou
             const bool ok = ei >= 0 && ej2 >= 0 && ek >= 0 && ei < g.nx - 1 && ej2 < g.ny - 1 &&
                             ek < g.nz - 1;
             const long long id = ei + (long long)(g.nx - 1) * (ej2 + (long long)(g.ny - 1) * ek);
-            ck[e] = ok ? B.kaph[id] : 0.0;
+            ck[e] = ok ? B.kx[id] : 0.0;
         }
         load_nb(g, TRANS ? R.x0[2] + g.off_pe : R.x0[3] + g.off_ce, n, i, j, k, X);
-        t -= g.chi * q1_stiff(ck, X);
+        t -= B.kx_scale * q1_stiff(ck, X);
     }
     const T bt = (T)t;
     ((T *)R.b0)[slot] = bt;

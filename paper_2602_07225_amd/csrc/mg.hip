@@ -154,6 +154,21 @@ __global__ __launch_bounds__(kBlock) void k_setup_nodes(Geom g, const double *__
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_scale_elem(long long n, const double *__restrict__ in,
+                                                       double factor, const double *__restrict__ def,
+                                                       double *__restrict__ out)
+{
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) out[t] = factor * (in ? in[t] : def[t]);
+}
+
+void launch_scale_elem(const Geom &g, const double *in, double factor, const double *def, double *out,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scale_elem, dim3((int)((g.nelem + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       g.nelem, in, factor, def, out);
+}
+
 void launch_setup_nodes(const Geom &g, const RadialTab *, const double *sigma, const double *kappa,
                         double *sigh, double *kaph, double *mm, hipStream_t st)
 {

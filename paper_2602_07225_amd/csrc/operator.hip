@@ -7,19 +7,22 @@
 //   c_e rows:   M_eps/dt c_e + K_kappa c_e - tc m q        (ce-weak, backward Euler)
 //   c_s rows:   T0 c_s + Gamma q e_N                       (eq. FD with eq. LR)
 // with the linearized reaction q = g (phi_s - phi_e) + e c_e + s c_s,N of
-// the Butler-Volmer term (Sec. 2.4) and m the lumped electrode weight.
+// the Butler-Volmer term (Sec. 2.4) and m the lumped electrode weight.  With
+// separate transport coefficients (GEN) the diffusion-potential block and
+// the c_e diffusion take their own element coefficients instead of chi kappa
+// and kappa.
 #include "p4d_kernels.hpp"
 
 namespace p4d {
 
-template <typename TX, int NRMAX, bool TRANS, bool RESID>
+template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_operator(Geom g, OpArgs O, double *__restrict__ partial)
 {
     __shared__ double red[4];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const long long n = (long long)lb * kBlock + threadIdx.x;
     double sq = 0.0;
-    if (n < g.nnode) sq = operator_node<TX, NRMAX, TRANS, RESID>(g, O, n);
+    if (n < g.nnode) sq = operator_node<TX, NRMAX, TRANS, RESID, GEN>(g, O, n);
     if (partial) {
         const double s = block_sum(sq, red);
         if (threadIdx.x == 0) partial[lb] = s;
@@ -72,10 +75,12 @@ template <typename TX>
 void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, const double *kaph,
                      const double *gg, const double *ss, const double *ee, const double *mm,
                      const TX *x, double *y, const double *b, double *partial, int transpose,
-                     int tile_tx, int tile_cz, double *qbuf, hipStream_t st)
+                     int tile_tx, int tile_cz, double *qbuf, const double *kdh, const double *dch,
+                     hipStream_t st)
 {
-    OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, x, y, b};
-    if (!b && !partial && tile_tx > 0 && qbuf) {
+    OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, x, y, b, nullptr, kdh, dch};
+    const bool gen = kdh && dch;
+    if (!gen && !b && !partial && tile_tx > 0 && qbuf) {
         const int nt = operator_tiles(g, tile_tx, tile_cz);
         const int nr = (int)((g.ne + kBlock - 1) / kBlock);
         if (transpose)
@@ -98,8 +103,15 @@ void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, c
         return;
     }
     const int nb = operator_blocks(g);
-#define P4D_OP(NR, TR, RS) \
-    hipLaunchKernelGGL((k_operator<TX, NR, TR, RS>), dim3(nb), dim3(kBlock), 0, st, g, O, partial)
+#define P4D_OP(NR, TR, RS)                                                                          \
+    do {                                                                                            \
+        if (gen)                                                                                    \
+            hipLaunchKernelGGL((k_operator<TX, NR, TR, RS, true>), dim3(nb), dim3(kBlock), 0, st, g, O, \
+                               partial);                                                            \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_operator<TX, NR, TR, RS, false>), dim3(nb), dim3(kBlock), 0, st, g,   \
+                               O, partial);                                                         \
+    } while (0)
 #define P4D_OP2(NR)                                        \
     do {                                                   \
         if (!transpose) {                                  \
@@ -117,11 +129,13 @@ void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh, c
 template void launch_operator<double>(const Geom &, const RadialTab *, const double *,
                                       const double *, const double *, const double *,
                                       const double *, const double *, const double *, double *,
-                                      const double *, double *, int, int, int, double *, hipStream_t);
+                                      const double *, double *, int, int, int, double *,
+                                      const double *, const double *, hipStream_t);
 template void launch_operator<float>(const Geom &, const RadialTab *, const double *,
                                      const double *, const double *, const double *,
                                      const double *, const double *, const float *, double *,
-                                     const double *, double *, int, int, int, double *, hipStream_t);
+                                     const double *, double *, int, int, int, double *,
+                                     const double *, const double *, hipStream_t);
 
 // w = S y (or S^T y), S = A_yy - A_ys A_ss^-1 A_sy: y and w hold the
 // electrode-level unknowns only (length Nm); omega per electrode node.

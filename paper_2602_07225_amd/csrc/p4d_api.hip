@@ -15,6 +15,7 @@
 #include "../../include/p4d.h"
 #include "p4d_batch.hpp"
 #include "p4d_bgs.hpp"
+#include "p4d_phys.hpp"
 
 using namespace p4d;
 
@@ -39,6 +40,14 @@ struct Box {
     long long off = 0;       // offset of level 0 in the macro layout
     const double *cK = nullptr;
     Level lev[kMaxLevels];
+};
+
+// Newton state of a physical cell
+struct PhysState {
+    p4d_phys_params prm{};
+    PhysDev P{};
+    double *uh = nullptr, *rh = nullptr, *dh = nullptr, *old = nullptr, *fh = nullptr, *qh = nullptr;
+    bool ready = false;
 };
 
 struct Prof {
@@ -67,6 +76,9 @@ struct p4d_ctx {
     double *sigh = nullptr, *kaph = nullptr, *gg = nullptr, *ss = nullptr, *ee = nullptr,
            *mm = nullptr, *omega = nullptr, *qbuf = nullptr;
     double *oms = nullptr;         // omega_j of the Schur complement (whatever the preconditioner)
+    double *kdh = nullptr, *dch = nullptr;   // h * separate transport coefficients
+    int general = 0;               // 1: kdh / dch hold the transport coefficients
+    PhysState *phys = nullptr;     // physical cell (p4d_phys_create)
     double *red = nullptr;         // partial sums
     size_t red_len = 0;
     double *hdev = nullptr, *cdev = nullptr, *invbeta = nullptr, *ydev = nullptr, *scal = nullptr;
@@ -147,7 +159,7 @@ static void radial_table(const p4d_problem_desc &d, int el, RadialTab &T)
     di[N - 1] = -2.0 / (hl * hl);
     // surface coupling: the flux term 2 i_n/(F dr)(1 + dr/R) of eq. (LR), with
     // the sign of eq. (particleBC2), enters R_cs,N with +Gamma
-    T.Gamma = d.lambda_c * 2.0 * (1.0 + hl) / hl;
+    T.Gamma = (d.lambda_el[el] > 0.0 ? d.lambda_el[el] : d.lambda_c) * 2.0 * (1.0 + hl) / hl;
     const double D = d.Ds[el];
     for (int i = 0; i < N; i++) {
         T.hsub[i] = lo[i];
@@ -194,7 +206,7 @@ static void fill_geom(const p4d_problem_desc &d, Geom &g)
     g.off_cs[1] = g.off_cs[0] + (long long)d.nr[0] * g.nea;
     g.N = g.off_cs[1] + (long long)d.nr[1] * g.nec;
     g.Nm = g.off_cs[0];
-    g.h = 1.0 / (d.nz - 1);
+    g.h = (d.length > 0.0 ? d.length : 1.0) / (d.nz - 1);
     g.dt = d.dt;
     g.chi = d.chi;
     g.tc = d.tc;
@@ -242,6 +254,8 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->omega = (double *)take(8 * g.ne);
     c->qbuf = (double *)take(8 * g.ne);          // reaction q of the tiled operator
     c->oms = (double *)take(8 * g.ne);
+    c->kdh = (double *)take(8 * g.nelem);
+    c->dch = (double *)take(8 * g.nelem);
     // reduction partials: streaming (kRedBlocks x 64), operator, gradient
     size_t rl = (size_t)kRedBlocks * 64;
     const size_t opb = (size_t)operator_blocks(g) + 1;
@@ -274,7 +288,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
         B.ek_hi = b == 0 ? g.na - 2 : g.nz - 2;
         B.mass = b == 3;
         B.off = b == 0 ? layer : (b == 1 ? g.nea : (b == 2 ? g.off_pe : g.off_ce));
-        B.cK = b <= 1 ? c->sigh : c->kaph;
+        B.cK = b <= 1 ? c->sigh : ((b == 3 && c->general) ? c->dch : c->kaph);
         for (int l = 0; l < B.nlev; l++) {
             Level &L = B.lev[l];
             L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
@@ -428,7 +442,8 @@ static void apply_op(p4d_ctx *c, int transpose, const TX *x, double *y, const do
                          16.0 * g.nelem + 32.0 * g.ne;
     ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
     launch_operator<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, x, y, b,
-                        partial, transpose, c->op_tx, c->op_cz, c->qbuf, st);
+                        partial, transpose, c->op_tx, c->op_cz, c->qbuf,
+                        c->general ? c->kdh : nullptr, c->general ? c->dch : nullptr, st);
 }
 
 // w = S y (S^T y) over the electrode-level unknowns
@@ -712,7 +727,8 @@ static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, double rscal
     const Geom &g = c->g;
     BgsArgs B{};
     B.R = rad_args(c);
-    B.kaph = c->kaph;
+    B.kx = c->general ? c->kdh : c->kaph;
+    B.kx_scale = c->general ? 1.0 : c->g.chi;
     B.zsN = c->qbuf;
     VState<T> vs{};
     for (int b = 0; b < 4; b++) {
@@ -1086,6 +1102,104 @@ done:
 }
 
 // ---------------------------------------------------------------------------
+// physical cell: Newton iterations around the linear solve
+// ---------------------------------------------------------------------------
+namespace {
+double kappa_bulk_h(double ce)   // bulk conductivity at 298.15 K (appendix)
+{
+    const double c = ce / 1000.0;
+    return 0.0911 + c * (1.9101 + c * (-1.052 + c * 0.1554));
+}
+double de_bulk_h(double ce) { return 5.34e-10 * std::exp(-0.65 * ce / 1000.0); }
+}  // namespace
+
+// Arrays of the operator for the state u (SI): transport coefficients at the
+// element-mean c_e and the kinetics derivatives, scaled; the reaction q^.
+static void phys_coef(p4d_ctx *c, const double *u, hipStream_t st)
+{
+    PhysState &S = *c->phys;
+    launch_phys_coef(c->g, S.P, u, c->sigh, c->kaph, c->kdh, c->dch, c->gg, c->ss, c->ee, S.qh, st);
+    c->general = 1;
+    c->box[3].cK = c->dch;
+    c->uploaded = 1;
+    c->pc_ready = 0;
+}
+
+// radial tables, lumped weights (geometry only) and the applied current
+static p4d_status phys_prepare(p4d_ctx *c, hipStream_t st)
+{
+    PhysState &S = *c->phys;
+    HIPCHK(c, hipMemcpyAsync(c->tabs, c->tabs_h, sizeof(c->tabs_h), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemsetAsync(c->kdh, 0, 8 * (size_t)c->g.nelem, st));
+    launch_setup_nodes(c->g, c->tabs, c->kdh, c->kdh, c->sigh, c->kaph, c->mm, st);
+    HIPCHK(c, hipGetLastError());
+    if (!S.ready) {
+        // nodal currents of the top face: the Gaussian profile (spread
+        // gauss_frac * edge around the face centre) times the lumped face
+        // weight, normalized to the applied current, scaled by r_phi
+        const int n = c->g.nx;
+        const double h = c->g.h, L = S.prm.edge, sd = S.prm.gauss_frac * L;
+        std::vector<double> f((size_t)c->g.ne, 0.0);
+        double sum = 0.0;
+        const size_t top = (size_t)(c->g.ne - (long long)n * n);
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                const double x = i * h - 0.5 * L, y = j * h - 0.5 * L;
+                const double w = (i == 0 || i == n - 1 ? 0.5 * h : h) * (j == 0 || j == n - 1 ? 0.5 * h : h);
+                const double v = std::exp(-(x * x + y * y) / (2.0 * sd * sd)) * w;
+                f[top + i + (size_t)n * j] = v;
+                sum += v;
+            }
+        for (size_t t = top; t < f.size(); t++) f[t] *= S.prm.current * S.P.rphi / sum;
+        HIPCHK(c, hipMemcpyAsync(S.fh, f.data(), 8 * f.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        S.ready = true;
+    }
+    return P4D_OK;
+}
+
+// previous-step storage in the scaled rows: M' c_e,old^ (the operator with
+// every coefficient but the storage set to zero) and c_s,old^ / dt'
+static p4d_status phys_old(p4d_ctx *c, const double *uold, hipStream_t st)
+{
+    PhysState &S = *c->phys;
+    const Geom &g = c->g;
+    for (double *p : {c->sigh, c->kaph, c->kdh, c->dch})
+        HIPCHK(c, hipMemsetAsync(p, 0, 8 * (size_t)g.nelem, st));
+    for (double *p : {c->gg, c->ss, c->ee})
+        HIPCHK(c, hipMemsetAsync(p, 0, 8 * (size_t)g.ne, st));
+    c->general = 1;
+    c->box[3].cK = c->dch;
+    c->uploaded = 1;
+    c->pc_ready = 0;
+    launch_phys_scale(g, S.P, uold, S.dh, 0, st);
+    HIPCHK(c, hipMemsetAsync(S.dh, 0, 8 * (size_t)g.off_ce, st));
+    HIPCHK(c, hipMemsetAsync(S.dh + g.off_cs[0], 0, 8 * (size_t)(g.N - g.off_cs[0]), st));
+    apply_op<double>(c, 0, S.dh, S.old, nullptr, nullptr, st);
+    launch_phys_old_cs(g, S.P, uold, c->desc.dt, S.old, st);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+// r = R^(u) (scaled rows), or -R^ when neg; leaves the Newton matrix at u
+static p4d_status phys_residual(p4d_ctx *c, const double *u, double *r, int neg, hipStream_t st)
+{
+    PhysState &S = *c->phys;
+    const Geom &g = c->g;
+    phys_coef(c, u, st);
+    launch_phys_scale(g, S.P, u, S.uh, 0, st);
+    apply_op<double>(c, 0, S.uh, r, nullptr, nullptr, st);
+    PhysFix F{};
+    F.uh = S.uh; F.old = S.old; F.fh = S.fh; F.qh = S.qh;
+    F.gg = c->gg; F.ss = c->ss; F.ee = c->ee; F.mm = c->mm;
+    F.gam[0] = c->tabs_h[0].Gamma;
+    F.gam[1] = c->tabs_h[1].Gamma;
+    launch_phys_fix(g, F, r, neg, st);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+// ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -1138,6 +1252,9 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
     if (!(d->dt > 0.0) || !std::isfinite(d->chi) || !std::isfinite(d->tc) ||
         !std::isfinite(d->lambda_c) || !(d->eps_elec > 0.0) || !(d->eps_sep > 0.0))
         return P4D_ERR_INVALID_ARG;
+    if (!(d->length >= 0.0) || !std::isfinite(d->length) || !(d->lambda_el[0] >= 0.0) ||
+        !(d->lambda_el[1] >= 0.0) || !std::isfinite(d->lambda_el[0]) || !std::isfinite(d->lambda_el[1]))
+        return P4D_ERR_INVALID_ARG;
     if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return P4D_ERR_INVALID_ARG;
     p4d_ctx *c = new p4d_ctx();
     c->desc = *d;
@@ -1161,6 +1278,7 @@ void p4d_destroy(p4d_ctx *c)
     if (!c) return;
     prof_free(c->prof);
     if (c->hhost) hipHostFree(c->hhost);
+    delete c->phys;
     delete c;
 }
 
@@ -1285,11 +1403,34 @@ p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, cons
     HIPCHK(c, hipMemcpyAsync(c->ee, e, 8 * c->g.ne, hipMemcpyDeviceToDevice, st));
     launch_setup_nodes(c->g, c->tabs, sigma, kappa, c->sigh, c->kaph, c->mm, st);
     launch_omega(c->g, c->tabs, c->ss, 1, c->oms, st);
+    c->general = 0;
+    c->box[3].cK = c->kaph;
     HIPCHK(c, hipGetLastError());
     // the host copy of the radial tables must outlive the async copy
     HIPCHK(c, hipStreamSynchronize(st));
     c->uploaded = 1;
     c->pc_ready = 0;
+    return P4D_OK;
+}
+
+p4d_status p4d_set_transport(p4d_ctx *c, const double *kappa_d, const double *dce, void *stream)
+{
+    if (!c) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    hipStream_t st = (hipStream_t)stream;
+    c->pc_ready = 0;
+    if (!kappa_d && !dce) {
+        c->general = 0;
+        c->box[3].cK = c->kaph;
+        return P4D_OK;
+    }
+    // h * coefficient, or the default from h * kappa
+    launch_scale_elem(c->g, kappa_d, kappa_d ? c->g.h : c->g.chi, c->kaph, c->kdh, st);
+    launch_scale_elem(c->g, dce, dce ? c->g.h : 1.0, c->kaph, c->dch, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->general = 1;
+    c->box[3].cK = c->dch;
     return P4D_OK;
 }
 
@@ -1360,6 +1501,8 @@ p4d_status p4d_apply_schur_operator(p4d_ctx *c, int transpose, const double *y, 
 {
     if (!c || !y || !w || y == w) return P4D_ERR_INVALID_ARG;
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    if (c->general)
+        return fail(c, P4D_ERR_INVALID_ARG, "the Schur operator needs the default transport coefficients");
     apply_op_schur<double>(c, transpose, y, w, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return P4D_OK;
@@ -1388,6 +1531,9 @@ static p4d_status solve_common(p4d_ctx *c, int transpose, const double *b, doubl
         return fail(c, P4D_ERR_STATE, "preconditioner options differ from the last setup");
     if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
         return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
+    if (o.krylov == P4D_KRYLOV_SCHUR && c->general)
+        return fail(c, P4D_ERR_INVALID_ARG,
+                    "the Schur-complement Krylov space needs the default transport coefficients");
     hipStream_t st = (hipStream_t)stream;
     if (o.z_fp32) return fgmres<float>(c, transpose, b, x, o, info, st);
     return fgmres<double>(c, transpose, b, x, o, info, st);
@@ -1403,6 +1549,185 @@ p4d_status p4d_solve_adjoint(p4d_ctx *c, const double *g, double *lam, const p4d
                              p4d_solve_info *info, void *stream)
 {
     return solve_common(c, 1, g, lam, opts, info, stream);
+}
+
+p4d_status p4d_phys_create(const p4d_phys_params *p, p4d_ctx **out)
+{
+    if (!p || !out) return P4D_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int n = p->n;
+    if (n < 19 || (n - 1) % 9 != 0 || n > 1024) return P4D_ERR_INVALID_ARG;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(p->dt) || !pos(p->edge) || !pos(p->F) || !pos(p->R) || !pos(p->T) || !pos(p->ce0) ||
+        !pos(p->eps_sep) || !pos(p->brug) || !pos(p->gauss_frac) || !std::isfinite(p->current) ||
+        !(p->t_plus >= 0.0 && p->t_plus < 1.0))
+        return P4D_ERR_INVALID_ARG;
+    for (int el = 0; el < 2; el++) {
+        const p4d_electrode &e = p->el[el];
+        if (!pos(e.eps_s) || !pos(e.eps) || !pos(e.sigma) || !pos(e.k) || !pos(e.alpha) ||
+            !pos(e.cs_max) || !pos(e.cs0) || !(e.cs0 < e.cs_max) || !pos(e.a) || !pos(e.Ds) ||
+            !pos(e.Rs))
+            return P4D_ERR_INVALID_ARG;
+    }
+    if (p->el[0].eps != p->el[1].eps) return P4D_ERR_INVALID_ARG;
+    // scales: unknowns x (RT/F, c_e0, the mean c_s,max), equations r (inverse
+    // diagonal magnitude of the phi_e, c_e and c_s rows at the rest state)
+    PhysDev P{};
+    P.F = p->F;
+    P.RT = p->R * p->T;
+    P.tplus = p->t_plus;
+    P.brug = p->brug;
+    P.ce0 = p->ce0;
+    P.eps_el = p->el[0].eps;
+    P.eps_sep = p->eps_sep;
+    for (int el = 0; el < 2; el++) {
+        const p4d_electrode &e = p->el[el];
+        P.eps_s[el] = e.eps_s; P.sigma[el] = e.sigma; P.k[el] = e.k; P.alpha[el] = e.alpha;
+        P.csmax[el] = e.cs_max; P.cs0[el] = e.cs0; P.a[el] = e.a;
+    }
+    const double h = p->edge / (n - 1), eps = p->el[0].eps;
+    P.xphi = P.RT / P.F;
+    P.xc = p->ce0;
+    P.xs = 0.5 * (p->el[0].cs_max + p->el[1].cs_max);
+    const double kap0 = std::pow(eps, p->brug) * kappa_bulk_h(p->ce0);
+    const double d0 = std::pow(eps, p->brug) * de_bulk_h(p->ce0);
+    P.rphi = 1.0 / (kap0 * h * P.xphi);
+    P.rc = 1.0 / ((eps * h * h * h / p->dt + d0 * h) * P.xc);
+    P.rs = p->dt / P.xs;
+    const double tfac = P.rs * P.xs;
+    // the scaled Newton matrix as an operator description
+    p4d_problem_desc d{};
+    const int e25 = (n - 1) / 9;
+    d.nx = d.ny = d.nz = n;
+    d.na = 4 * e25 + 1;
+    d.ns = e25 - 1;
+    for (int el = 0; el < 2; el++) {
+        const p4d_electrode &e = p->el[el];
+        d.nr[el] = p->nr[el];
+        d.Ds[el] = e.Ds / (e.Rs * e.Rs) * tfac;
+        d.theta_bar[el] = p->theta_bar[el];
+        d.lambda_el[el] = 1.0 / (p->F * e.Rs * e.a) * P.rs / P.rphi;
+    }
+    d.dt = p->dt / tfac;
+    d.chi = 0.0;
+    d.tc = (1.0 - p->t_plus) / p->F * P.rc / P.rphi;
+    d.lambda_c = 1.0;
+    d.eps_elec = P.rc * P.xc * eps / tfac;
+    d.eps_sep = P.rc * P.xc * p->eps_sep / tfac;
+    d.length = p->edge;
+    const p4d_status s = p4d_create(&d, out);
+    if (s != P4D_OK) return s;
+    (*out)->phys = new PhysState();
+    (*out)->phys->prm = *p;
+    (*out)->phys->P = P;
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_workspace_size(const p4d_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes || !c->phys) return P4D_ERR_INVALID_ARG;
+    *bytes = 4 * align_up(8 * (size_t)c->g.N) + 2 * align_up(8 * (size_t)c->g.ne) + 256;
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_set_workspace(p4d_ctx *c, void *d_work, size_t bytes)
+{
+    if (!c || !d_work || !c->phys) return P4D_ERR_INVALID_ARG;
+    if (!c->ws) return fail(c, P4D_ERR_STATE, "p4d_set_workspace first");
+    size_t need;
+    p4d_phys_workspace_size(c, &need);
+    if (bytes < need) return fail(c, P4D_ERR_OOM, "Newton buffers too small");
+    char *p = (char *)align_up((size_t)d_work);
+    auto take = [&](size_t b) { char *q = p; p += align_up(b); return (double *)q; };
+    PhysState &S = *c->phys;
+    S.uh = take(8 * (size_t)c->g.N);
+    S.rh = take(8 * (size_t)c->g.N);
+    S.dh = take(8 * (size_t)c->g.N);
+    S.old = take(8 * (size_t)c->g.N);
+    S.fh = take(8 * (size_t)c->g.ne);
+    S.qh = take(8 * (size_t)c->g.ne);
+    S.ready = false;
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_initial_state(p4d_ctx *c, double *u, void *stream)
+{
+    if (!c || !u || !c->phys) return P4D_ERR_INVALID_ARG;
+    launch_phys_init(c->g, c->phys->P, u, (hipStream_t)stream);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_residual(p4d_ctx *c, const double *u, const double *uold, double *r, void *stream)
+{
+    if (!c || !u || !uold || !r || !c->phys) return P4D_ERR_INVALID_ARG;
+    if (!c->phys->uh) return fail(c, P4D_ERR_STATE, "p4d_phys_set_workspace first");
+    hipStream_t st = (hipStream_t)stream;
+    p4d_status s = phys_prepare(c, st);
+    if (s == P4D_OK) s = phys_old(c, uold, st);
+    if (s == P4D_OK) s = phys_residual(c, u, c->phys->rh, 0, st);
+    if (s != P4D_OK) return s;
+    launch_phys_unscale_rows(c->g, c->phys->P, c->phys->rh, r, st);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_newton_step(p4d_ctx *c, double *u, const double *uold, const p4d_solve_opts *solve,
+                                const p4d_newton_opts *newton, p4d_newton_info *info, void *stream)
+{
+    if (!c || !u || !uold || u == uold || !c->phys) return P4D_ERR_INVALID_ARG;
+    PhysState &S = *c->phys;
+    if (!S.uh) return fail(c, P4D_ERR_STATE, "p4d_phys_set_workspace first");
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (solve) o = *solve;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    if (o.krylov != P4D_KRYLOV_FULL)
+        return fail(c, P4D_ERR_INVALID_ARG, "Newton systems use the full Krylov space");
+    if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
+        return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
+    const int maxit = newton ? newton->maxit : 30;
+    const double tol = newton ? newton->tol : 1e-9;
+    if (maxit < 1 || !(tol > 0.0)) return fail(c, P4D_ERR_INVALID_ARG, "newton options");
+    hipStream_t st = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    p4d_newton_info inf{};
+    inf.status = 1;
+    p4d_status s = phys_prepare(c, st);
+    if (s == P4D_OK) s = phys_old(c, uold, st);
+    if (s != P4D_OK) return s;
+    for (int it = 0; it < maxit; it++) {
+        s = phys_residual(c, u, S.rh, 1, st);   // right-hand side -R^
+        if (s != P4D_OK) return s;
+        s = p4d_setup(c, &o, st);
+        if (s != P4D_OK) return s;
+        p4d_solve_info li{};
+        s = o.z_fp32 ? fgmres<float>(c, 0, S.rh, S.dh, o, &li, st) : fgmres<double>(c, 0, S.rh, S.dh, o, &li, st);
+        if (s != P4D_OK && s != P4D_NOT_CONVERGED) {
+            inf.status = s;
+            break;
+        }
+        inf.lin_iters += li.iters;
+        const int nb = launch_phys_update(c->g, S.P, S.dh, u, c->red, st);
+        launch_max_final(c->red, nb, c->scal + 100, st);
+        HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal + 100, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        inf.iters = it + 1;
+        inf.update = c->hhost[0];
+        if (!std::isfinite(inf.update)) {
+            inf.status = P4D_ERR_NONFINITE;
+            break;
+        }
+        if (inf.update <= tol) {
+            inf.status = 0;
+            break;
+        }
+    }
+    inf.t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    if (inf.status == 0) return P4D_OK;
+    return inf.status == 1 ? P4D_NOT_CONVERGED : (p4d_status)inf.status;
 }
 
 p4d_status p4d_param_gradient(p4d_ctx *c, const double *x, const double *lam, double *dsigma,

@@ -11,7 +11,8 @@ enum BgsField : int { BF_PHIS = 0, BF_PHIE = 1, BF_CE = 2, BF_CS = 3 };
 
 struct BgsArgs {
     RadArgs R;            // tables, coefficients, level-0 buffers, final iterates
-    const double *kaph;   // h kappa per element
+    const double *kx;     // element coefficient of the diffusion-potential block (x h) ...
+    double kx_scale;      // ... times this factor (chi with h kappa, or 1)
     double *zsN;          // solved c_s surface value per electrode node (FP64)
     int field;            // field whose right-hand side bgs_rhs forms
     int done;             // bit f set: field f solved

@@ -115,7 +115,7 @@ void launch_operator(const Geom &g, const RadialTab *tabs, const double *sigh,
                      const double *kaph, const double *gg, const double *ss, const double *ee,
                      const double *mm, const TX *x, double *y, const double *b,
                      double *partial, int transpose, int tile_tx, int tile_cz, double *qbuf,
-                     hipStream_t st);
+                     const double *kdh, const double *dch, hipStream_t st);
 int operator_blocks(const Geom &g);
 int operator_tiles(const Geom &g, int TX, int CZ);
 int operator_tile_slots();
@@ -192,6 +192,9 @@ struct InvBatch {
     double *Ainv[4];
 };
 void launch_invert(const InvBatch &ib, hipStream_t st);
+// out = factor * in per element, or factor * def where in is null
+void launch_scale_elem(const Geom &g, const double *in, double factor, const double *def, double *out,
+                       hipStream_t st);
 void launch_setup_nodes(const Geom &g, const RadialTab *tabs, const double *sigma,
                         const double *kappa, double *sigh, double *kaph, double *mm,
                         hipStream_t st);

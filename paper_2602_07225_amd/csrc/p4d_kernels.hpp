@@ -505,6 +505,8 @@ struct OpArgs {
     double *y;
     const double *b;     // b - A x when not null
     const double *om;    // omega per electrode node (Schur complement operator)
+    const double *kdh;   // h * diffusion-potential coefficient per element (GEN)
+    const double *dch;   // h * c_e diffusion coefficient per element (GEN)
 };
 
 template <typename TX>
@@ -529,6 +531,7 @@ __device__ inline void load_nb(const Geom &g, const TX *f, long long n, int i, i
 // neighbour value: zero on the grounded layer).
 struct OpStencil {
     double Kpe, xpe, Kce, Mce, xce, Kps, xpsc;
+    double Kx;   // GEN: the diffusion-potential stiffness applied to c_e (phi_e if transposed)
 };
 
 // Reaction coupling of one electrode node: the linearized reaction q and the
@@ -565,7 +568,9 @@ __device__ inline double op_radial_row(const RadialTab &T, bool trans, int r, in
 
 // Everything after the stencil parts: reaction coupling, radial rows and
 // the output (y, or b - A x when RESID); returns the sum of squares written.
-template <typename TX, int NRMAX, bool TRANS, bool RESID>
+// GEN: separate element coefficients for the diffusion-potential block
+// (P.Kx) and the c_e diffusion (P.Kce), instead of chi * kappa and kappa.
+template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false>
 __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long long n, int i, int j,
                                          int k, const OpStencil &P)
 {
@@ -575,7 +580,10 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
     double sq = 0.0;
     const double xpe = P.xpe, xce = P.xce;
     double ype, yce;
-    if (!TRANS) {
+    if (GEN) {
+        ype = TRANS ? P.Kpe : P.Kpe + P.Kx;
+        yce = TRANS ? P.Mce + P.Kce + P.Kx : P.Mce + P.Kce;
+    } else if (!TRANS) {
         ype = P.Kpe + g.chi * P.Kce;
         yce = P.Mce + P.Kce;
     } else {
@@ -639,7 +647,7 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
 
 // The operator y = A x (or A^T x, or b - A x) at one node, every stencil
 // value read from memory (paper Sec. 4.1, eq. blocks; see operator.hip).
-template <typename TX, int NRMAX, bool TRANS, bool RESID>
+template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false>
 __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
 {
     const TX *x = (const TX *)O.x;
@@ -659,11 +667,38 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
     }
     OpStencil P;
     double X[27];
+    P.Kx = 0.0;
     load_nb(g, x + g.off_pe, n, i, j, k, X);
     P.Kpe = q1_stiff(ck, X);
     P.xpe = X[13];
+    if (GEN && TRANS) {
+        double cx[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+            const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                            ek < g.nz - 1;
+            cx[e] = ok ? O.kdh[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+        }
+        P.Kx = q1_stiff(cx, X);
+    }
     load_nb(g, x + g.off_ce, n, i, j, k, X);
-    P.Kce = q1_stiff(ck, X);
+    if (GEN) {
+        double cd[8], cx[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+            const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                            ek < g.nz - 1;
+            const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+            cd[e] = ok ? O.dch[id] : 0.0;
+            cx[e] = (ok && !TRANS) ? O.kdh[id] : 0.0;
+        }
+        P.Kce = q1_stiff(cd, X);
+        if (!TRANS) P.Kx = q1_stiff(cx, X);
+    } else {
+        P.Kce = q1_stiff(ck, X);
+    }
     P.Mce = q1_mass(cm, X);
     P.xce = X[13];
     P.Kps = 0.0;
@@ -685,7 +720,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         P.Kps = q1_stiff(cs, X);
         P.xpsc = X[13];
     }
-    return operator_finish<TX, NRMAX, TRANS, RESID>(g, O, n, i, j, k, P);
+    return operator_finish<TX, NRMAX, TRANS, RESID, GEN>(g, O, n, i, j, k, P);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,9 @@ class P4DSolver:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)
         self.upload(prob.sigma, prob.kappa, prob.g, prob.s, prob.e)
+        kd, dc = getattr(prob, "kappa_d", None), getattr(prob, "dce", None)
+        if kd is not None or dc is not None:
+            self.set_transport(kd, dc)
         self.opts = None
 
     def _dev(self, a):
@@ -40,6 +43,14 @@ class P4DSolver:
         L.p4d_upload(self.ctx, *arrs)
         # kept for re-uploads with a new sigma (differentiable solves)
         self._kappa, self._g, self._s, self._e = arrs[1:]
+        self.opts = None
+
+    def set_transport(self, kappa_d=None, dce=None):
+        """Separate element coefficients of the diffusion-potential block and
+        the c_e diffusion (None: chi * kappa and kappa)."""
+        self._kd = None if kappa_d is None else self._dev(kappa_d)
+        self._dc = None if dce is None else self._dev(dce)
+        L.p4d_set_transport(self.ctx, self._kd, self._dc)
         self.opts = None
 
     def set_diffusivity(self, Ds):
@@ -209,6 +220,64 @@ class P4DBatch:
             torch.cuda.synchronize()
             L.p4d_batch_destroy(self.batch)
             self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PhysCell:
+    """The physical cube cell (``p4d_inputs.phys.PhysCase``): backward-Euler
+    steps of the P4D-DFN model by Newton iterations on the GPU
+    (``p4d_phys_*`` in the C ABI).  States are SI-unit device vectors in the
+    global layout."""
+
+    def __init__(self, case, current: float, restart: int = 30, pc_prec: int = L.P4D_FP64,
+                 coarse_max: int = 64, device: str = "cuda"):
+        self.device = torch.device(device)
+        self.case = case
+        self.params = L.phys_params(case, current)
+        self.ctx = L.p4d_phys_create(self.params)
+        self.N, self.offsets, self.n_elem, self.n_e = L.p4d_vector_size(self.ctx)
+        self.ws_opts = L.default_opts(restart=restart, pc_prec=pc_prec, coarse_max=coarse_max)
+        nbytes = L.p4d_workspace_size(self.ctx, self.ws_opts)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)
+        pbytes = L.p4d_phys_workspace_size(self.ctx)
+        self.pws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
+        L.p4d_phys_set_workspace(self.ctx, self.pws.data_ptr(), pbytes)
+
+    def _dev(self, a):
+        if isinstance(a, torch.Tensor):
+            return a.to(self.device, torch.float64).contiguous()
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    def initial_state(self):
+        u = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        L.p4d_phys_initial_state(self.ctx, u)
+        return u
+
+    def residual(self, u, u_old):
+        r = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        L.p4d_phys_residual(self.ctx, self._dev(u), self._dev(u_old), r)
+        return r
+
+    def step(self, u_old, guess=None, maxit: int = 30, tol: float = 1e-9, **solve):
+        """One backward-Euler step from u_old; returns (u, NewtonInfo)."""
+        u_old = self._dev(u_old)
+        u = (self._dev(guess) if guess is not None else u_old).clone()
+        o = self.ws_opts.__class__.from_buffer_copy(self.ws_opts)
+        for k, v in solve.items():
+            setattr(o, k, v)
+        _, info = L.p4d_phys_newton_step(self.ctx, u, u_old, o, L.NewtonOpts(maxit, tol))
+        return u, info
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.p4d_destroy(self.ctx)
+            self.ctx = None
 
     def __del__(self):
         try:

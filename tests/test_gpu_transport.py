@@ -1,0 +1,83 @@
+"""Separate transport coefficients (diffusion-potential block and c_e
+diffusion with their own element coefficients), a physical cell length and
+per-electrode surface coupling scales: operator, preconditioners and solves
+on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import p4d_inputs as pi
+from tests.gpu_util import field_errors, rel, say, solver_for, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def general(seed=51, nx=9, ny=7, nz=23, nr=(7, 11)):
+    p = pi.make_custom(nx, ny, nz, nr, seed=seed, sigma_log=1.0, corr_cells=3.0)
+    rng = np.random.default_rng(seed + 7)
+    return p.with_(kappa_d=np.exp(0.7 * rng.standard_normal(p.n_elem)),
+                   dce=np.exp(0.7 * rng.standard_normal(p.n_elem)),
+                   length=2.25e-4, lambda_el=(0.4, 2.5))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_general_operator_parity(transpose):
+    p = general()
+    orc = O.Oracle(p)
+    s = solver_for(p)
+    x = np.random.default_rng(1).standard_normal(p.N)
+    y = to_np(s.apply(to_dev(x), transpose))
+    ref = orc.apply(x, transpose)
+    say(f"general operator transpose={transpose}: max rel {np.max(np.abs(y - ref)) / np.max(np.abs(ref)):.1e}")
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ, O.PC_BGS])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_general_preconditioner_parity(pc, transpose):
+    p = general()
+    orc = O.Oracle(p).setup(pc=pc)
+    s = solver_for(p).setup(pc=pc)
+    r = np.random.default_rng(2).standard_normal(p.N)
+    errs = field_errors(p, to_np(s.apply_pc(to_dev(r), transpose)), orc.apply_pc(r, transpose))
+    say(f"  pc={pc} transpose={transpose}", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-10
+
+
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BGS])
+def test_general_solve_parity(pc):
+    p = general()
+    cgs2 = pc != O.PC_SCHUR
+    orc = O.Oracle(p).setup(pc=pc, rtol=1e-8, cgs2=cgs2)
+    xo, io = orc.solve(p.b)
+    s = solver_for(p).setup(pc=pc, rtol=1e-8, cgs2=int(cgs2))
+    x, info = s.solve(to_dev(p.b))
+    x = to_np(x)
+    errs = field_errors(p, x, xo)
+    say(f"  pc={pc} iters gpu={info.iters} oracle={io.iters}", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert info.status == 0 and io.status == 0
+    assert abs(info.iters - io.iters) <= 2
+    assert max(errs.values()) <= 1e-6
+    assert rel(orc.apply(x), p.b) <= 1.0001e-8
+
+
+def test_transport_reset_and_schur_krylov_guard():
+    from paper_2602_07225_amd import P4DError, _lib
+    p = general()
+    plain = p.with_(kappa_d=None, dce=None)
+    s = solver_for(p)
+    x = np.random.default_rng(3).standard_normal(p.N)
+    s.setup()
+    with pytest.raises(P4DError) as e:
+        s.solve(to_dev(p.b), krylov=1)
+    assert e.value.status == _lib.P4D_ERR_INVALID_ARG
+    with pytest.raises(P4DError):
+        s.apply_schur(to_dev(x[:p.offsets[3]]))
+    s.set_transport(None, None)          # back to chi * kappa and kappa
+    y = to_np(s.apply(to_dev(x)))
+    ref = O.Oracle(plain).apply(x)
+    assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # explicit defaults take the general kernels and agree
+    s.set_transport(p.chi * p.kappa, p.kappa)
+    y2 = to_np(s.apply(to_dev(x)))
+    assert np.max(np.abs(y2 - ref)) <= 1e-13 * np.max(np.abs(ref))
