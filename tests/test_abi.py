@@ -73,6 +73,37 @@ def test_default_options(L):
     assert o.bgs_order == _lib.P4D_BGS_PAPER_ORDER == 1 | 3 << 2 | 0 << 4 | 2 << 6
 
 
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors have the C layout: sizes and member offsets as the
+    host compiler lays out the header's structs."""
+    import ctypes as C
+    import os
+    import subprocess
+    from paper_2602_07225_amd import _lib
+    hdr = os.path.join(os.path.dirname(__file__), "..", "include", "p4d.h")
+    checks = {"p4d_solve_opts": (_lib.SolveOpts, ["rtol", "bgs_order", "krylov"]),
+              "p4d_problem_desc": (_lib.ProblemDesc, ["Ds", "dt", "length", "lambda_el"]),
+              "p4d_phys_params": (_lib.PhysParams, ["theta_bar", "current", "eps_sep", "el"]),
+              "p4d_newton_info": (_lib.NewtonInfo, ["update", "t_ms"])}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{os.path.abspath(hdr)}"',
+             "int main(void) {"]
+    for cname, (_, members) in checks.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for m in members:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {m}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-o", str(exe), str(src)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    expect = []
+    for cname, (cls, members) in checks.items():
+        expect.append(C.sizeof(cls))
+        expect += [getattr(cls, m).offset for m in members]
+    assert vals == expect
+
+
 def test_header_constants_match_binding():
     import os
     import re
@@ -80,6 +111,6 @@ def test_header_constants_match_binding():
     h = open(os.path.join(os.path.dirname(__file__), "..", "include", "p4d.h")).read()
     for name in ("P4D_PC_SCHUR", "P4D_PC_BJ", "P4D_PC_BGS", "P4D_F_PHIS", "P4D_F_PHIE",
                  "P4D_F_CE", "P4D_F_CS", "P4D_K_OPERATOR", "P4D_K_RADIAL", "P4D_K_BATCH_PC",
-                 "P4D_K_COUPLING", "P4D_K_COUNT"):
+                 "P4D_K_COUPLING", "P4D_K_COUNT", "P4D_KRYLOV_FULL", "P4D_KRYLOV_SCHUR"):
         m = re.search(name + r"\s*=\s*(\d+)", h)
         assert m and int(m.group(1)) == getattr(_lib, name), name

@@ -13,11 +13,16 @@ pytestmark = pytest.mark.gpu
 
 
 def general(seed=51, nx=9, ny=7, nz=23, nr=(7, 11)):
+    """Separate coefficients, a cell length and coupling scales.  (With a
+    physical length such as 225 um and unit coefficients the c_e and phi_e
+    blocks would be nearly singular, storage ~h^3 against stiffness ~h, and
+    two FP64 summation orders would differ by ~1e-5; the physical cell
+    scales its Newton systems instead.)"""
     p = pi.make_custom(nx, ny, nz, nr, seed=seed, sigma_log=1.0, corr_cells=3.0)
     rng = np.random.default_rng(seed + 7)
     return p.with_(kappa_d=np.exp(0.7 * rng.standard_normal(p.n_elem)),
                    dce=np.exp(0.7 * rng.standard_normal(p.n_elem)),
-                   length=2.25e-4, lambda_el=(0.4, 2.5))
+                   length=3.0, lambda_el=(0.4, 2.5))
 
 
 @pytest.mark.parametrize("transpose", [False, True])
