@@ -287,19 +287,27 @@ def main():
     log(f"[bench] C2 N={N}: building solver")
     s = P4DSolver(p, restart=30)
     b = torch.as_tensor(p.b, device="cuda")
-    fp64 = dict(pc=L.P4D_PC_SCHUR, pc_prec=L.P4D_FP64, rtol=1e-8, restart=30)
+    # V(3,3): degree-3 Chebyshev smoothing (8 iterations instead of 9 with
+    # degree 2 on this cube; the fastest degree measured)
+    fp64 = dict(pc=L.P4D_PC_SCHUR, pc_prec=L.P4D_FP64, rtol=1e-8, restart=30, cheb_degree=3)
     mask = sum(1 << k for k in L.KERNEL_CLASSES)
-    x64, info, iters, t, prof = timed_steps(s, b, fp64, args.steps, args.warmup, mask)
+    # a first pass with events around every launch of every kernel class
+    # gives the per-class table and the dominant class; the timed steps then
+    # record events around that class only (fewer event records in the
+    # timed region)
+    _, _, _, _, prof = timed_steps(s, b, fp64, args.steps, args.warmup, mask)
+    dom = max(prof, key=lambda k: prof[k]["ms_total"]) if prof else None
+    dom_mask = (1 << next(k for k, v in L.KERNEL_CLASSES.items() if v == dom)) if dom else 0
+    x64, info, iters, t, prof_dom = timed_steps(s, b, fp64, args.steps, 1, dom_mask)
     ms_step = 1e3 * t / args.steps
     value = N * iters / t
     log(f"[bench] FP64: {iters / args.steps:.1f} it/step, {ms_step:.2f} ms/step, "
         f"{value:.3e} DOF*iter/s")
 
     # dominant kernel class of the timed region
-    dom = max(prof, key=lambda k: prof[k]["ms_total"]) if prof else None
     roofline = None
-    if dom:
-        d = prof[dom]
+    if dom and dom in prof_dom:
+        d = prof_dom[dom]
         roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
                     "traffic": measured_traffic(dom),
@@ -354,7 +362,7 @@ def main():
         # Krylov space reduced to the Schur complement of the particle blocks
         # (the same system and tolerance; FGMRES over the 2.2 M electrode-level
         # unknowns), both preconditioner precisions
-        sk = dict(fp64, krylov=L.P4D_KRYLOV_SCHUR)
+        sk = dict(fp64, krylov=L.P4D_KRYLOV_SCHUR, cheb_degree=2)   # its fastest degree
         xs64, is64, its64, ts64, profs = timed_steps(s, b, sk, args.steps, 1, mask)
         xs32, is32, its32, ts32, _ = timed_steps(s, b, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
         extras["schur_krylov_C2"] = {
@@ -388,9 +396,8 @@ def main():
                                  (torch.linalg.norm(xb - xa) / torch.linalg.norm(xa)).item()},
             "speedup_fp32_vs_fp64": ta / tb}
         log(f"[bench] C3: fp64 {1e3 * ta / args.steps:.2f} ms, fp32 {1e3 * tb / args.steps:.2f} ms")
-        _, _, itc, tc3, _ = timed_steps(s3, b3, dict(fp64, krylov=L.P4D_KRYLOV_SCHUR), args.steps, 1)
-        _, _, itc32, tc332, _ = timed_steps(s3, b3, dict(fp32, krylov=L.P4D_KRYLOV_SCHUR),
-                                            args.steps, 1)
+        _, _, itc, tc3, _ = timed_steps(s3, b3, dict(sk), args.steps, 1)
+        _, _, itc32, tc332, _ = timed_steps(s3, b3, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
         extras["schur_krylov_C3"] = {
             "fp64": {"ms_per_step": 1e3 * tc3 / args.steps, "iters_per_solve": itc / args.steps},
             "fp32_precond": {"ms_per_step": 1e3 * tc332 / args.steps,
@@ -477,7 +484,7 @@ def main():
         t0 = time.perf_counter()
         its = 0
         for _ in range(2):
-            orc = O.Oracle(p).setup(rtol=1e-8)
+            orc = O.Oracle(p).setup(rtol=1e-8, cheb_degree=fp64["cheb_degree"])
             xo, io = orc.solve(p.b)
             its += io.iters
         tc = time.perf_counter() - t0
@@ -503,10 +510,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "homogeneous cube cell 64x64x192 nodes, Nr=20, 15,335,424 DOF; "
-                               "FP64 FGMRES(30) + particle-Schur block preconditioner to rtol 1e-8; "
-                               "step = setup + solve",
+                               "FP64 FGMRES(30) + particle-Schur block preconditioner (V(3,3) "
+                               "Chebyshev multigrid) to rtol 1e-8; step = setup + solve",
                    "nodes": [p.nx, p.ny, p.nz], "layers": [p.na, p.ns, p.nc], "nr": list(p.nr),
-                   "dof": N, "restart": 30, "rtol": 1e-8, "pc": "schur"},
+                   "dof": N, "restart": 30, "rtol": 1e-8, "pc": "schur", "cheb_degree": 3},
         "roofline": roofline,
         "cpu_baseline": cpu,
         **extras,

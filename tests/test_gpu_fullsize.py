@@ -31,11 +31,12 @@ def test_C2_operator_full(transpose):
     assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-def test_C2_preconditioner_full():
+@pytest.mark.parametrize("deg", [2, 3])
+def test_C2_preconditioner_full(deg):
     p, orc = big(2)
-    say("C2 preconditioner")
-    orc.setup()
-    s = solver_for(p).setup()
+    say(f"C2 preconditioner, Chebyshev degree {deg}")
+    orc.setup(cheb_degree=deg)
+    s = solver_for(p).setup(cheb_degree=deg)
     r = np.random.default_rng(6).standard_normal(p.N)
     errs = field_errors(p, to_np(s.apply_pc(to_dev(r))), orc.apply_pc(r))
     say("  errors", {k: f"{v:.1e}" for k, v in errs.items()})
@@ -46,12 +47,13 @@ def test_C2_preconditioner_full():
 
 
 def test_C2_solve_full():
-    """The benchmark solve: FP64, SCHUR, FGMRES(30), rtol 1e-8."""
+    """The benchmark solve: FP64, SCHUR, V(3,3) Chebyshev, FGMRES(30), rtol
+    1e-8."""
     p, orc = big(2)
     say("C2 solve (oracle ~20 s on the host)")
-    orc.setup(rtol=1e-8)
+    orc.setup(rtol=1e-8, cheb_degree=3)
     xo, io = orc.solve(p.b)
-    s = solver_for(p).setup(rtol=1e-8)
+    s = solver_for(p).setup(rtol=1e-8, cheb_degree=3)
     x, info = s.solve(to_dev(p.b))
     x = to_np(x)
     errs = field_errors(p, x, xo)
