@@ -116,6 +116,7 @@ def lib():
         L.orc_gradient.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_schur_apply.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_set_transport.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_set_storage.argtypes = [C.c_void_p, _dp]
         L.orc_schur_rhs.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_schur_back.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_radial_mesh.argtypes = [C.c_int, C.c_double, _dp]
@@ -233,6 +234,10 @@ class Oracle:
         if kd is not None or dc is not None:
             self._keep_t = [None if a is None else _f64(a) for a in (kd, dc)]
             lib().orc_set_transport(self.h, *[None if a is None else _p(a) for a in self._keep_t])
+        ep = getattr(prob, "eps_e", None)
+        if ep is not None:
+            self._keep_e = _f64(ep)
+            lib().orc_set_storage(self.h, _p(self._keep_e))
         sz = (C.c_int64 * 8)()
         lib().orc_sizes(self.h, sz)
         self.sizes = list(sz)

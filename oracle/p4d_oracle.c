@@ -124,6 +124,7 @@ typedef struct {
     /* optional element coefficients of the diffusion-potential block and of
      * the c_e diffusion (NULL: chi * kappa and kappa)                       */
     double *kappad, *dce;
+    double *epse;              /* porosity per element (NULL: per material) */
     /* radial: node coordinates and rows of L~_h (flux term excluded) */
     double *rho[2], *Lsub[2], *Ldia[2], *Lsup[2];
     double Gamma[2];
@@ -261,6 +262,7 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
     P->h = (d->length > 0.0 ? d->length : 1.0) / (d->nz - 1);
     P->kappad = NULL;
     P->dce = NULL;
+    P->epse = NULL;
     P->nc = d->nz - d->na - d->ns;
     P->nnode = (long)d->nx * d->ny * d->nz;
     P->nelem = (long)(d->nx - 1) * (d->ny - 1) * (d->nz - 1);
@@ -342,6 +344,21 @@ void orc_set_transport(orc_problem *P, const double *kappa_d, const double *dce)
     P->pc_ready = 0;
 }
 
+/* Porosity per element for the c_e storage term (Sec. 2 electrolyte mass
+ * balance; Case II of Sec. 5 draws it from volume-fraction fields): the
+ * element mass matrix becomes eps_e h^3 Mhat / dt.  NULL restores the
+ * per-material values eps_elec, eps_sep.                                    */
+void orc_set_storage(orc_problem *P, const double *eps_e)
+{
+    free(P->epse);
+    P->epse = NULL;
+    if (eps_e) {
+        P->epse = xmalloc(sizeof(double) * P->nelem);
+        memcpy(P->epse, eps_e, sizeof(double) * P->nelem);
+    }
+    P->pc_ready = 0;
+}
+
 static void mg_free(orc_mg *M)
 {
     for (int l = 0; l < M->nlev; l++) {
@@ -355,7 +372,7 @@ void orc_destroy(orc_problem *P)
 {
     if (!P) return;
     free(P->sigma); free(P->kappa); free(P->g); free(P->s); free(P->e); free(P->m);
-    free(P->kappad); free(P->dce);
+    free(P->kappad); free(P->dce); free(P->epse);
     for (int el = 0; el < 2; el++) {
         free(P->rho[el]); free(P->Lsub[el]); free(P->Ldia[el]); free(P->Lsup[el]);
     }
@@ -449,8 +466,9 @@ static double cf_dce(const orc_problem *P, int i, int j, int k, const void *c)
 }
 static double cf_mass(const orc_problem *P, int i, int j, int k, const void *c)
 {
-    (void)c; (void)i; (void)j;
-    double eps = elem_mat(P, k) >= 0 ? P->d.eps_elec : P->d.eps_sep;
+    (void)c;
+    double eps = P->epse ? P->epse[elem_id(P, i, j, k)]
+                         : (elem_mat(P, k) >= 0 ? P->d.eps_elec : P->d.eps_sep);
     return eps * P->h * P->h * P->h / P->d.dt;
 }
 

@@ -20,7 +20,12 @@ Readings (each also listed in the design notes):
     Gaussian profile, lumped per face node and normalized so that the nodal
     currents sum to the applied current; a discharge (lithium leaving the
     negative particles) has the current leave through the top face;
-  - temperature 298.15 K, so the Arrhenius factors of kappa and D_e are 1.
+  - temperature 298.15 K, so the Arrhenius factors of kappa and D_e are 1;
+  - Case II: the volume fractions vary per element; sigma_eff takes the
+    local active fraction and kappa_eff, D_e_eff and the c_e storage the
+    local porosity (Bruggeman), while the specific area a keeps its table
+    value (the tables give it as a constant) and the 1C current uses the
+    mean fractions; the current enters uniformly through the top face.
 """
 from __future__ import annotations
 
@@ -140,14 +145,16 @@ def applied_current(case: ph.PhysCase) -> float:
 def face_source(case: ph.PhysCase, grid: Grid, current: float) -> np.ndarray:
     """Nodal currents on the top face (phi_s rows of the positive electrode):
     the Gaussian profile of Sec. 5 centred on the face with spreads
-    gauss_frac * edge, lumped (face weight per node) and normalized to sum
-    to `current`."""
+    gauss_frac * edge (or a uniform one, Case II), lumped (face weight per
+    node) and normalized to sum to `current`."""
     n, h = case.n, case.h
     L = ph.CELL_EDGE
     x = np.arange(n) * h
     X, Y = np.meshgrid(x, x, indexing="xy")
     sx = sy = case.gauss_frac * L
     G = np.exp(-(X - L / 2) ** 2 / (2 * sx * sx) - (Y - L / 2) ** 2 / (2 * sy * sy))
+    if case.profile == "uniform":
+        G = np.ones_like(G)
     w1 = np.full(n, h)
     w1[0] = w1[-1] = h / 2
     W = np.outer(w1, w1)
@@ -183,11 +190,12 @@ def element_coefficients(case, grid, u):
     per element, at the element-mean c_e."""
     ce = u[grid.off_ce: grid.off_ce + grid.nnode]
     cbar = ce[grid.corners].mean(axis=1)
-    eps = np.where(grid.emat >= 0, case.electrodes[0].eps, ph.SEPARATOR_EPS)
+    eps = ph.porosity(case)
+    act = ph.active_fraction(case)
     sig = np.zeros(grid.nelem)
     for el in range(2):
-        e = case.electrodes[el]
-        sig[grid.emat == el] = e.eps_s ** ph.BRUGGEMAN * e.sigma
+        sel = grid.emat == el
+        sig[sel] = act[sel] ** ph.BRUGGEMAN * case.electrodes[el].sigma
     kap = eps ** ph.BRUGGEMAN * kappa_bulk(cbar)
     kd = kap * 2.0 * (1.0 - ph.T_PLUS) / (FRT * cbar)
     dce = eps ** ph.BRUGGEMAN * de_bulk(cbar)
@@ -242,7 +250,8 @@ def linear_problem(case, grid, u, with_kinetics=True) -> pi.Problem:
         chi=0.0, tc=(1.0 - ph.T_PLUS) / ph.F, lambda_c=1.0, eps_elec=d["eps_elec"],
         eps_sep=d["eps_sep"], sigma=sig, kappa=kap, g=g, s=s, e=e, b=np.zeros(grid.N),
         length=d["length"], lambda_el=(1.0 / (ph.F * neg.Rs * neg.a), 1.0 / (ph.F * pos.Rs * pos.a)),
-        kappa_d=kd, dce=dce, name="phys")
+        kappa_d=kd, dce=dce, eps_e=ph.porosity(case) if case.heterogeneous else None,
+        name="phys")
 
 
 # ---------------------------------------------------------------------------
@@ -317,6 +326,7 @@ class Scaling:
         return lp.with_(sigma=rp * xp * lp.sigma, kappa=rp * xp * lp.kappa,
                         kappa_d=rp * xc * lp.kappa_d, dce=rc * xc * lp.dce,
                         eps_elec=rc * xc * lp.eps_elec / tfac, eps_sep=rc * xc * lp.eps_sep / tfac,
+                        eps_e=None if lp.eps_e is None else rc * xc * lp.eps_e / tfac,
                         g=rp * xp * lp.g, e=rp * xc * lp.e, s=rp * xs * lp.s,
                         tc=lp.tc * rc / rp, lambda_el=tuple(l * rs / rp for l in lp.lambda_el),
                         dt=lp.dt / tfac, Ds=tuple(d * tfac for d in lp.Ds))

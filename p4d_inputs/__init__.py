@@ -79,11 +79,13 @@ class Problem:
     # cell edge along z (0: 1, i.e. nondimensional), surface coupling scale
     # per electrode (0: lambda_c), and element coefficients of the
     # diffusion-potential block and the c_e diffusion (None: chi * kappa,
-    # kappa)
+    # kappa); porosity per element for the c_e storage (None: eps_elec,
+    # eps_sep by material)
     length: float = 0.0
     lambda_el: Tuple[float, float] = (0.0, 0.0)
     kappa_d: Optional[np.ndarray] = None  # (n_elem,)
     dce: Optional[np.ndarray] = None      # (n_elem,)
+    eps_e: Optional[np.ndarray] = None    # (n_elem,)
 
     # ---- sizes -----------------------------------------------------------
     @property

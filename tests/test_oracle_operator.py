@@ -169,6 +169,43 @@ def test_general_transport_coefficients_and_length():
     assert g1[1] == pytest.approx(1.9 * g0[1] / p.lambda_c)
 
 
+def test_porosity_per_element():
+    """A porosity field per element (Case II volume fractions, Sec. 5) enters
+    only the c_e storage: that block equals the Q1 mass assembly of the field
+    over dt (plus the unchanged stiffness), the mass of a uniform c_e is the
+    integral of the porosity, and the per-material values reproduce the
+    default operator exactly."""
+    p = problem(seed=14, bv=False)
+    rng = np.random.default_rng(6)
+    ep = 0.1 + 0.8 * rng.random(p.n_elem)
+    q = p.with_(eps_e=ep, length=3.0)
+    orc = O.Oracle(q)
+    h = q.h
+    nodes = (p.nx, p.ny, p.nz)
+    coords = [np.arange(n) * h for n in nodes]
+    Kk = qref.assemble_box(*nodes, p.kappa, None, *coords).toarray()
+    Me = qref.assemble_box(*nodes, np.zeros(p.n_elem), ep / p.dt, *coords).toarray()
+    B = block(orc, q, 2, 2)
+    assert np.allclose(B, Me + Kk, rtol=0, atol=1e-13 * np.abs(B).max())
+    # the other blocks do not see it
+    ref = O.Oracle(p.with_(length=3.0))
+    for r, c in ((1, 1), (1, 2), (0, 0)):
+        assert np.array_equal(block(orc, q, r, c), block(ref, q, r, c))
+    # storage of c_e = 1 (no transport): sum of rows = h^3 sum(eps_e) / dt
+    z = np.zeros(p.n_elem)
+    q0 = q.with_(kappa=z, sigma=z)
+    x = np.zeros(p.N)
+    x[p.offsets[2]: p.offsets[3]] = 1.0
+    y = O.Oracle(q0).apply(x)[p.offsets[2]: p.offsets[3]]
+    assert y.sum() == pytest.approx(h ** 3 * ep.sum() / p.dt, rel=1e-13)
+    # per-material values as a field: the default operator, bit for bit
+    emat = elem_mat_array(p)
+    pm = p.with_(eps_e=np.where(emat >= 0, p.eps_elec, p.eps_sep))
+    x = rng.standard_normal(p.N)
+    assert np.array_equal(O.Oracle(pm).apply(x), O.Oracle(p).apply(x))
+    assert np.array_equal(O.Oracle(pm).apply(x, True), O.Oracle(p).apply(x, True))
+
+
 def test_lumped_weights_are_row_sum_lumped_electrode_mass():
     p = problem()
     orc = O.Oracle(p)

@@ -147,3 +147,111 @@ def test_converged_step_balances_charge_and_conserves_electrolyte_lithium(cube):
         assert np.all(grid.surface(un, 1) > grid.surface(u, 1))
         u = un
     assert electrolyte_li(u) == pytest.approx(li0, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Case II: volume fractions per element
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def hetero():
+    case = ph.case2(19, (6, 7), seed=3)
+    return case, P.Grid(case)
+
+
+def test_case2_fields_and_uniform_current(hetero):
+    """Fractions inside (0, 1) with the porosity as the remainder; the
+    uniform top-face current is the lumped face weight times I / area."""
+    case, grid = hetero
+    lay = ph.element_layers(case)
+    por = ph.porosity(case)
+    el = lay >= 0
+    assert np.all(case.eps_s_e[el] > 0) and np.all(case.eps_b_e[el] > 0) and np.all(por[el] > 0)
+    assert np.allclose(por[el], 1.0 - case.eps_s_e[el] - case.eps_b_e[el], rtol=0, atol=0)
+    assert np.all(por[~el] == ph.SEPARATOR_EPS)
+    assert np.std(por[el]) > 0.02                       # really heterogeneous
+    I = P.applied_current(case)
+    f = P.face_source(case, grid, I)
+    top = f[grid.ne - grid.layer:]
+    h, n = case.h, case.n
+    w1 = np.full(n, h)
+    w1[0] = w1[-1] = h / 2
+    assert np.allclose(top, (I / ph.CELL_EDGE ** 2) * np.outer(w1, w1).reshape(-1), rtol=1e-13, atol=0)
+    assert np.all(f[: grid.ne - grid.layer] == 0)
+
+
+def test_case2_coefficients_follow_the_local_fractions(hetero):
+    """sigma_eff = eps_s^1.5 sigma and kappa_eff = eps^1.5 kappa(c_e) per
+    element at the rest state (uniform c_e)."""
+    case, grid = hetero
+    u0 = P.initial_state(case, grid)
+    sig, kap, kd, dce = P.element_coefficients(case, grid, u0)
+    lay = ph.element_layers(case)
+    por = ph.porosity(case)
+    for el in (0, 1):
+        sel = lay == el
+        assert np.allclose(sig[sel], case.eps_s_e[sel] ** 1.5 * case.electrodes[el].sigma, rtol=1e-14)
+    assert np.all(sig[lay < 0] == 0)
+    assert np.allclose(kap, por ** 1.5 * P.kappa_bulk(ph.CE0), rtol=1e-14)
+    assert np.allclose(dce, por ** 1.5 * P.de_bulk(ph.CE0), rtol=1e-14)
+
+
+def test_case2_zero_variance_is_the_homogeneous_cell():
+    """Fractions fixed at the table means reproduce the homogeneous cell
+    (same residual up to the rounding of 1 - eps_s - eps_b)."""
+    case1 = ph.PhysCase(n=19, nr=(6, 7), profile="uniform")
+    grid = P.Grid(case1)
+    lay = ph.element_layers(case1)
+    fs = np.where(lay == 0, 0.6, 0.5)
+    fb = np.where(lay == 0, 0.1, 0.2)
+    case = ph.PhysCase(n=19, nr=(6, 7), profile="uniform", eps_s_e=fs, eps_b_e=fb)
+    u0 = P.initial_state(case1, grid)
+    rng = np.random.default_rng(4)
+    u = u0.copy()
+    u[grid.off_ce: grid.off_cs[0]] += 30.0 * rng.standard_normal(grid.nnode)
+    I = P.applied_current(case1)
+    sc = P.Scaling(case1)
+    r1 = sc.rows(grid, P.residual(case1, grid, u, u0, I))
+    r2 = sc.rows(grid, P.residual(case, grid, u, u0, I))
+    assert np.abs(r1 - r2).max() <= 1e-12 * np.abs(r1).max()
+
+
+def test_case2_newton_matrix_is_the_jacobian_at_rest(hetero):
+    """At the rest state (uniform c_e) the Newton matrix of the heterogeneous
+    cell is the exact Jacobian: central differences agree to O(eps^2)."""
+    case, grid = hetero
+    u0 = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    J = O.Oracle(P.linear_problem(case, grid, u0))
+    v = _direction(grid, np.random.default_rng(5))
+    Jv = J.apply(v)
+    e3 = _block_errors(case, grid, _fd(case, grid, u0, u0, I, v, 1e-3), Jv)
+    for k in e3:
+        assert e3[k] < 1e-7, (k, e3)
+
+
+def test_case2_step_balances_charge_and_conserves_lithium(hetero):
+    """A converged 60 s step of the heterogeneous cell: reaction currents
+    equal the applied current per electrode, and the electrolyte lithium
+    int eps c_e (mass matrix of the porosity field, assembled here by
+    quadrature) is unchanged."""
+    from tests import qref
+    case, grid = hetero
+    u = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    n, h = case.n, case.h
+    coords = [np.arange(n) * h] * 3
+    M = qref.assemble_box(n, n, n, np.zeros(grid.nelem), ph.porosity(case), *coords)
+    li = lambda x: M @ x[grid.off_ce: grid.off_cs[0]]  # noqa: E731
+    li0 = li(u).sum()
+    un, hist = P.newton_step(case, grid, u, I)
+    assert hist[-1][0] <= 1e-9 and len(hist) < 15
+    m = O.Oracle(P.linear_problem(case, grid, un)).lumped_weights()
+    q, _, _, _ = P.kinetics(case, grid, un)
+    assert (m * q)[: grid.nea].sum() == pytest.approx(-I, rel=1e-7)
+    assert (m * q)[grid.nea:].sum() == pytest.approx(I, rel=1e-7)
+    assert li(un).sum() == pytest.approx(li0, rel=1e-10)
+    # heterogeneity shows: c_e differs from the homogeneous cell's step
+    case1 = ph.PhysCase(n=19, nr=(6, 7), profile="uniform")
+    u1, _ = P.newton_step(case1, grid, P.initial_state(case1, grid), I)
+    d = np.abs(un - u1)[grid.off_ce: grid.off_cs[0]].max()
+    assert d > 1e-3 * np.abs(u1[grid.off_ce: grid.off_cs[0]] - ph.CE0).max()
