@@ -174,15 +174,17 @@ def bench_batch(steps):
     return out
 
 
-def bench_newton(n=64, nr=(10, 10), steps=30):
+def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False):
     """The physical cube cell (Case I: 225 um cube, 100/25/100 um layers,
-    appendix parameters, Gaussian 1C discharge current): `steps`
-    backward-Euler steps of 60 s, each by Newton iterations on the GPU."""
+    appendix parameters, Gaussian 1C discharge current; with hetero, Case II:
+    volume fractions per element from seeded random fields, uniform
+    current): `steps` backward-Euler steps of 60 s, each by Newton
+    iterations on the GPU."""
     import torch
     from p4d_inputs import phys as ph
     from paper_2602_07225_amd import PhysCell
     from paper_2602_07225_amd import _lib as L
-    case = ph.PhysCase(n=n, nr=nr)
+    case = ph.case2(n, nr, seed=2) if hetero else ph.PhysCase(n=n, nr=nr)
     q = [ph.F / 3600.0 * e.eps_s * case.electrode_volume * e.cs_max for e in case.electrodes]
     current = -case.c_rate * min(q)
     cell = PhysCell(case, current, coarse_max=64)
@@ -193,7 +195,7 @@ def bench_newton(n=64, nr=(10, 10), steps=30):
     cell.step(u)                              # warm-up (compiles nothing, touches every kernel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    newton, lin, worst = [], 0, 0
+    newton, lin = [], 0
     for _ in range(steps):
         u, info = cell.step(u)
         if info.status != 0:
@@ -250,7 +252,8 @@ def main():
         print(json.dumps({"C4_batch_64_cells": bench_batch(args.steps)}), flush=True)
         return
     if args.newton_only:
-        print(json.dumps({"newton_case_I_cube": bench_newton()}), flush=True)
+        print(json.dumps({"newton_case_I_cube": bench_newton(),
+                          "newton_case_II_cube": bench_newton(hetero=True)}), flush=True)
         return
     if args.schur_only:
         p = pi.make_config(2)
@@ -468,14 +471,14 @@ def main():
 
     if not args.no_extras:
         extras["C4_batch_64_cells"] = bench_batch(args.steps)
-        try:
-            extras["newton_case_I_cube"] = bench_newton()
-            e = extras["newton_case_I_cube"]
-            log(f"[bench] Newton Case I: {e['steps']} steps, {e['ms_per_step']:.1f} ms/step, "
-                f"{e['newton_iters_per_step']:.1f} Newton it/step, V {e['voltage_start_V']:.4f} -> "
-                f"{e['voltage_end_V']:.4f}")
-        except RuntimeError as ex:
-            extras["newton_case_I_cube"] = {"error": str(ex)}
+        for key, het in (("newton_case_I_cube", False), ("newton_case_II_cube", True)):
+            try:
+                extras[key] = e = bench_newton(hetero=het)
+                log(f"[bench] Newton {'Case II' if het else 'Case I'}: {e['steps']} steps, "
+                    f"{e['ms_per_step']:.1f} ms/step, {e['newton_iters_per_step']:.1f} Newton it/step, "
+                    f"V {e['voltage_start_V']:.4f} -> {e['voltage_end_V']:.4f}")
+            except RuntimeError as ex:
+                extras[key] = {"error": str(ex)}
 
     cpu = None
     if not args.no_cpu:

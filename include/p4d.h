@@ -196,6 +196,18 @@ p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
 p4d_status p4d_set_transport(p4d_ctx *ctx, const double *d_kappa_d, const double *d_dce,
                              void *stream);
 
+/* Porosity per element for the c_e storage term (paper Sec. 2 electrolyte
+ * mass balance, eq. ce-weak; Case II of Sec. 5 varies it): the element mass
+ * becomes eps_e h^3 Mhat / dt.  d_eps_e: device, one value per element
+ * (element ids x fastest), caller-owned, read during the call; NULL restores
+ * the per-material eps_elec / eps_sep.  Values are not checked (a
+ * non-positive porosity leaves S_ce indefinite).  Needs p4d_upload, which
+ * resets it; invalidates p4d_setup.  As with p4d_set_transport the operator
+ * then runs one thread per node and the Schur-complement Krylov space and
+ * batches do not apply; every preconditioner does.  INVALID_ARG on a
+ * physical cell (p4d_phys_set_fractions sets its storage).                */
+p4d_status p4d_set_storage(p4d_ctx *ctx, const double *d_eps_e, void *stream);
+
 /* d_y = A d_x, or A^T d_x if transpose (eq. blocks).  d_x, d_y: length N,
  * must not alias.  Needs p4d_upload.                                       */
 p4d_status p4d_apply_operator(p4d_ctx *ctx, int transpose, const double *d_x,
@@ -333,7 +345,8 @@ const char *p4d_batch_last_error(const p4d_batch *batch);
 /* for the cube cell of Sec. 5 (Case I) with the model of Sec. 2 and the     */
 /* appendix parameters: Butler-Volmer kinetics with the open-circuit         */
 /* potentials, kappa(c_e), D_e(c_e), Bruggeman corrections, the Gaussian     */
-/* applied current on the top face.  The state u is in SI units (V, V,       */
+/* (or uniform) applied current on the top face; Case II volume fractions   */
+/* per element by p4d_phys_set_fractions.  The state u is in SI units (V, V,       */
 /* mol/m^3, mol/m^3) in the global layout above.  The context's linear       */
 /* operator is the Newton matrix in scaled variables (unknowns divided and   */
 /* equations multiplied by per-field scales), with transport coefficients   */
@@ -367,6 +380,8 @@ typedef struct {
     double ce0;           /* initial electrolyte concentration, mol/m^3          */
     double eps_sep;       /* separator porosity                                  */
     p4d_electrode el[2];  /* negative (bottom, grounded), positive (top)         */
+    int32_t profile;      /* applied current over the top face: 0 Gaussian, 1
+                             uniform (Case II)                                   */
 } p4d_phys_params;
 
 typedef struct {
@@ -391,6 +406,16 @@ p4d_status p4d_phys_workspace_size(const p4d_ctx *ctx, size_t *bytes);
 /* Hands the context its Newton buffers (device, caller-owned, kept until
  * destroy); needs p4d_set_workspace first.                                  */
 p4d_status p4d_phys_set_workspace(p4d_ctx *ctx, void *d_work, size_t bytes);
+/* Case II (Sec. 5): active-material and binder volume fractions per element
+ * (device, element ids x fastest, caller-owned, read during the call;
+ * separator entries ignored).  sigma_eff takes eps_s^brug, kappa_eff, D_e_eff
+ * and the c_e storage the porosity 1 - eps_s - eps_b (brug for the
+ * transport); the specific area keeps el[].a.  Both NULL restores the
+ * homogeneous cell.  INVALID_ARG if only one is NULL or if a fraction is
+ * outside (0, 1) or no porosity is left (the cell is then homogeneous).
+ * Needs p4d_phys_set_workspace, which resets it; synchronizes `stream`.    */
+p4d_status p4d_phys_set_fractions(p4d_ctx *ctx, const double *d_eps_s, const double *d_eps_b,
+                                  void *stream);
 /* d_u = the rest state: c_e0, c_s0 and zero overpotential (phi_s = 0 in the
  * negative electrode, phi_e = -U_n, phi_s = U_p - U_n in the positive one). */
 p4d_status p4d_phys_initial_state(p4d_ctx *ctx, double *d_u, void *stream);

@@ -42,7 +42,8 @@ KERNEL_CLASSES = {P4D_K_OPERATOR: "operator", P4D_K_MDOT: "mdot", P4D_K_ORTH: "o
 
 EXPORTED = [
     "p4d_default_opts", "p4d_create", "p4d_destroy", "p4d_vector_size", "p4d_workspace_size",
-    "p4d_set_workspace", "p4d_upload", "p4d_set_transport", "p4d_set_diffusivity", "p4d_setup",
+    "p4d_set_workspace", "p4d_upload", "p4d_set_transport", "p4d_set_storage", "p4d_set_diffusivity",
+    "p4d_setup",
     "p4d_apply_operator",
     "p4d_apply_schur_operator", "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
     "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
@@ -51,7 +52,7 @@ EXPORTED = [
     "p4d_batch_solve", "p4d_batch_set_pc_mode", "p4d_batch_profile", "p4d_batch_profile_read",
     "p4d_batch_last_error",
     "p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace", "p4d_phys_initial_state",
-    "p4d_phys_residual", "p4d_phys_newton_step",
+    "p4d_phys_residual", "p4d_phys_newton_step", "p4d_phys_set_fractions",
 ]
 
 
@@ -81,7 +82,7 @@ class PhysParams(C.Structure):
                 ("dt", C.c_double), ("current", C.c_double), ("gauss_frac", C.c_double),
                 ("edge", C.c_double), ("F", C.c_double), ("R", C.c_double), ("T", C.c_double),
                 ("t_plus", C.c_double), ("brug", C.c_double), ("ce0", C.c_double),
-                ("eps_sep", C.c_double), ("el", Electrode * 2)]
+                ("eps_sep", C.c_double), ("el", Electrode * 2), ("profile", C.c_int32)]
 
 
 class NewtonOpts(C.Structure):
@@ -136,6 +137,7 @@ def lib():
         L.p4d_setup.argtypes = [vp, C.POINTER(SolveOpts), vp]
         L.p4d_set_diffusivity.argtypes = [vp, C.POINTER(C.c_double), vp]
         L.p4d_set_transport.argtypes = [vp, vp, vp, vp]
+        L.p4d_set_storage.argtypes = [vp, vp, vp]
         L.p4d_apply_operator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_preconditioner.argtypes = [vp, C.c_int, vp, vp, vp]
         L.p4d_apply_schur_operator.argtypes = [vp, C.c_int, vp, vp, vp]
@@ -151,7 +153,7 @@ def lib():
         L.p4d_last_error.restype = C.c_char_p
         L.p4d_autotune.argtypes = [vp, vp, C.POINTER(C.c_int32)]
         for name in ["p4d_autotune", "p4d_create", "p4d_vector_size", "p4d_workspace_size", "p4d_set_workspace",
-                     "p4d_upload", "p4d_set_transport", "p4d_set_diffusivity", "p4d_setup",
+                     "p4d_upload", "p4d_set_transport", "p4d_set_storage", "p4d_set_diffusivity", "p4d_setup",
                      "p4d_apply_operator",
                      "p4d_apply_preconditioner", "p4d_apply_schur_operator",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
@@ -172,8 +174,10 @@ def _bind_phys(L):
     L.p4d_phys_residual.argtypes = [vp, vp, vp, vp, vp]
     L.p4d_phys_newton_step.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(NewtonOpts),
                                        C.POINTER(NewtonInfo), vp]
+    L.p4d_phys_set_fractions.argtypes = [vp, vp, vp, vp]
     for name in ("p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace",
-                 "p4d_phys_initial_state", "p4d_phys_residual", "p4d_phys_newton_step"):
+                 "p4d_phys_initial_state", "p4d_phys_residual", "p4d_phys_newton_step",
+                 "p4d_phys_set_fractions"):
         getattr(L, name).restype = C.c_int
 
 
@@ -191,6 +195,7 @@ def phys_params(case, current: float) -> PhysParams:
     for i, e in enumerate(case.electrodes):
         for k, _ in Electrode._fields_:
             setattr(p.el[i], k, getattr(e, k))
+    p.profile = 1 if getattr(case, "profile", "gauss") == "uniform" else 0
     return p
 
 
@@ -359,6 +364,17 @@ def p4d_set_transport(ctx, kappa_d=None, dce=None, stream=None):
     return check(lib().p4d_set_transport(ctx, ptr(kappa_d) if kappa_d is not None else None,
                                          ptr(dce) if dce is not None else None, stream_ptr(stream)),
                  ctx, "p4d_set_transport")
+
+
+def p4d_set_storage(ctx, eps_e=None, stream=None):
+    return check(lib().p4d_set_storage(ctx, ptr(eps_e) if eps_e is not None else None,
+                                       stream_ptr(stream)), ctx, "p4d_set_storage")
+
+
+def p4d_phys_set_fractions(ctx, eps_s=None, eps_b=None, stream=None):
+    return check(lib().p4d_phys_set_fractions(ctx, ptr(eps_s) if eps_s is not None else None,
+                                              ptr(eps_b) if eps_b is not None else None,
+                                              stream_ptr(stream)), ctx, "p4d_phys_set_fractions")
 
 
 def p4d_apply_operator(ctx, transpose, x, y, stream=None):

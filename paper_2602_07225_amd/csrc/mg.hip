@@ -16,14 +16,14 @@ namespace p4d {
 // ---------------------------------------------------------------------------
 // Single-cell kernels: all four boxes of one V-cycle stage per launch
 // ---------------------------------------------------------------------------
-template <typename T, bool RESID_ONLY>
+template <typename T, bool RESID_ONLY, bool MEH>
 __global__ __launch_bounds__(kBlock) void k_smooth0(Geom g, LevelBatch<T> lb, int TX, int CZ)
 {
     __shared__ Smooth0Lds L;
     const int bx = find_box(lb, blockIdx.x);
     const LevelArgs<T> &A = lb.a[bx];
     const int nt = smooth0_box_tiles(A.nx, A.ny, A.nz, TX, CZ);
-    smooth0_tile<T, RESID_ONLY>(g, A, xcd_block(blockIdx.x - A.blk0, nt), TX, CZ, L);
+    smooth0_tile<T, RESID_ONLY, MEH>(g, A, xcd_block(blockIdx.x - A.blk0, nt), TX, CZ, L);
 }
 
 int smooth0_tiles(int nx, int ny, int nz, int TX, int CZ) { return smooth0_box_tiles(nx, ny, nz, TX, CZ); }
@@ -34,7 +34,7 @@ int smooth0_slots()
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_smooth0<double, false>,
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_smooth0<double, false, false>,
                                                      kBlock, 0) != hipSuccess)
         return 1024;
     return (per < 1 ? 1 : per) * (ncu < 1 ? 1 : ncu);
@@ -44,10 +44,16 @@ template <typename T>
 void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
                     int CZ, hipStream_t st)
 {
-    if (resid_only)
-        hipLaunchKernelGGL((k_smooth0<T, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
-    else
-        hipLaunchKernelGGL((k_smooth0<T, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
+    if (g.meh) {
+        if (resid_only)
+            hipLaunchKernelGGL((k_smooth0<T, true, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
+        else
+            hipLaunchKernelGGL((k_smooth0<T, false, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
+    } else if (resid_only) {
+        hipLaunchKernelGGL((k_smooth0<T, true, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
+    } else {
+        hipLaunchKernelGGL((k_smooth0<T, false, false>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
+    }
 }
 template void launch_smooth0<double>(const Geom &, const LevelBatch<double> &, int, int, int, int,
                                      hipStream_t);
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, i
                         ek <= ek_hi;
         const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
         const double c = ok ? cK[id] : 0.0;
-        const double cm = (ok && mass) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+        const double cm = (ok && mass) ? elem_storage(g, id, ek) : 0.0;
         const int a = (1 - ex) | ((1 - ey) << 1) | ((1 - ez) << 2);
 #pragma unroll
         for (int bb = 0; bb < 8; bb++) {

@@ -47,6 +47,7 @@ struct PhysState {
     p4d_phys_params prm{};
     PhysDev P{};
     double *uh = nullptr, *rh = nullptr, *dh = nullptr, *old = nullptr, *fh = nullptr, *qh = nullptr;
+    double *por = nullptr, *act = nullptr;   // porosity, active fraction per element (Case II)
     bool ready = false;
 };
 
@@ -77,6 +78,9 @@ struct p4d_ctx {
            *mm = nullptr, *omega = nullptr, *qbuf = nullptr;
     double *oms = nullptr;         // omega_j of the Schur complement (whatever the preconditioner)
     double *kdh = nullptr, *dch = nullptr;   // h * separate transport coefficients
+    double *meh = nullptr;         // eps_e h^3 / dt per element (when storage is set)
+    int storage = 0;               // 1: g.meh points at meh
+    int transport_set = 0;         // 1: kdh / dch hold caller coefficients
     int general = 0;               // 1: kdh / dch hold the transport coefficients
     PhysState *phys = nullptr;     // physical cell (p4d_phys_create)
     double *red = nullptr;         // partial sums
@@ -256,6 +260,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->oms = (double *)take(8 * g.ne);
     c->kdh = (double *)take(8 * g.nelem);
     c->dch = (double *)take(8 * g.nelem);
+    c->meh = (double *)take(8 * g.nelem);
     // reduction partials: streaming (kRedBlocks x 64), operator, gradient
     size_t rl = (size_t)kRedBlocks * 64;
     const size_t opb = (size_t)operator_blocks(g) + 1;
@@ -1135,8 +1140,9 @@ static p4d_status phys_prepare(p4d_ctx *c, hipStream_t st)
     HIPCHK(c, hipGetLastError());
     if (!S.ready) {
         // nodal currents of the top face: the Gaussian profile (spread
-        // gauss_frac * edge around the face centre) times the lumped face
-        // weight, normalized to the applied current, scaled by r_phi
+        // gauss_frac * edge around the face centre; or uniform) times the
+        // lumped face weight, normalized to the applied current, scaled by
+        // r_phi
         const int n = c->g.nx;
         const double h = c->g.h, L = S.prm.edge, sd = S.prm.gauss_frac * L;
         std::vector<double> f((size_t)c->g.ne, 0.0);
@@ -1146,7 +1152,7 @@ static p4d_status phys_prepare(p4d_ctx *c, hipStream_t st)
             for (int i = 0; i < n; i++) {
                 const double x = i * h - 0.5 * L, y = j * h - 0.5 * L;
                 const double w = (i == 0 || i == n - 1 ? 0.5 * h : h) * (j == 0 || j == n - 1 ? 0.5 * h : h);
-                const double v = std::exp(-(x * x + y * y) / (2.0 * sd * sd)) * w;
+                const double v = (S.prm.profile == 1 ? 1.0 : std::exp(-(x * x + y * y) / (2.0 * sd * sd))) * w;
                 f[top + i + (size_t)n * j] = v;
                 sum += v;
             }
@@ -1327,6 +1333,12 @@ p4d_status p4d_set_workspace(p4d_ctx *c, void *d_work, size_t bytes, const p4d_s
     c->ws_bytes = bytes;
     c->uploaded = 0;
     c->pc_ready = 0;
+    c->storage = 0;
+    c->g.meh = nullptr;
+    if (c->phys) {
+        c->phys->P.por = c->phys->P.act = nullptr;
+        c->phys->ready = false;
+    }
     return ensure_layout(c, o);
 }
 
@@ -1405,11 +1417,31 @@ p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, cons
     launch_omega(c->g, c->tabs, c->ss, 1, c->oms, st);
     c->general = 0;
     c->box[3].cK = c->kaph;
+    c->storage = 0;
+    c->transport_set = 0;
+    c->g.meh = nullptr;
     HIPCHK(c, hipGetLastError());
     // the host copy of the radial tables must outlive the async copy
     HIPCHK(c, hipStreamSynchronize(st));
     c->uploaded = 1;
     c->pc_ready = 0;
+    return P4D_OK;
+}
+
+// The per-node operator with its own element arrays (GEN) runs when the
+// caller set transport coefficients or a per-element storage; for storage
+// alone kdh / dch take the defaults chi h kappa and h kappa.
+static p4d_status refresh_general(p4d_ctx *c, hipStream_t st)
+{
+    const bool gen = c->transport_set || c->storage;
+    if (gen && !c->transport_set) {
+        launch_scale_elem(c->g, nullptr, c->g.chi, c->kaph, c->kdh, st);
+        launch_scale_elem(c->g, nullptr, 1.0, c->kaph, c->dch, st);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    c->general = gen ? 1 : 0;
+    c->box[3].cK = gen ? c->dch : c->kaph;
     return P4D_OK;
 }
 
@@ -1420,18 +1452,36 @@ p4d_status p4d_set_transport(p4d_ctx *c, const double *kappa_d, const double *dc
     hipStream_t st = (hipStream_t)stream;
     c->pc_ready = 0;
     if (!kappa_d && !dce) {
-        c->general = 0;
-        c->box[3].cK = c->kaph;
-        return P4D_OK;
+        c->transport_set = 0;
+        return refresh_general(c, st);
     }
     // h * coefficient, or the default from h * kappa
     launch_scale_elem(c->g, kappa_d, kappa_d ? c->g.h : c->g.chi, c->kaph, c->kdh, st);
     launch_scale_elem(c->g, dce, dce ? c->g.h : 1.0, c->kaph, c->dch, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
-    c->general = 1;
-    c->box[3].cK = c->dch;
-    return P4D_OK;
+    c->transport_set = 1;
+    return refresh_general(c, st);
+}
+
+p4d_status p4d_set_storage(p4d_ctx *c, const double *eps_e, void *stream)
+{
+    if (!c) return P4D_ERR_INVALID_ARG;
+    if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    if (c->phys) return fail(c, P4D_ERR_INVALID_ARG, "a physical cell sets its storage from its fractions");
+    hipStream_t st = (hipStream_t)stream;
+    c->pc_ready = 0;
+    if (!eps_e) {
+        c->storage = 0;
+        c->g.meh = nullptr;
+        return refresh_general(c, st);
+    }
+    launch_scale_elem(c->g, eps_e, c->g.h * c->g.h * c->g.h / c->g.dt, nullptr, c->meh, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->storage = 1;
+    c->g.meh = c->meh;
+    return refresh_general(c, st);
 }
 
 p4d_status p4d_set_diffusivity(p4d_ctx *c, const double Ds[2], void *stream)
@@ -1560,7 +1610,7 @@ p4d_status p4d_phys_create(const p4d_phys_params *p, p4d_ctx **out)
     auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
     if (!pos(p->dt) || !pos(p->edge) || !pos(p->F) || !pos(p->R) || !pos(p->T) || !pos(p->ce0) ||
         !pos(p->eps_sep) || !pos(p->brug) || !pos(p->gauss_frac) || !std::isfinite(p->current) ||
-        !(p->t_plus >= 0.0 && p->t_plus < 1.0))
+        !(p->t_plus >= 0.0 && p->t_plus < 1.0) || (p->profile != 0 && p->profile != 1))
         return P4D_ERR_INVALID_ARG;
     for (int el = 0; el < 2; el++) {
         const p4d_electrode &e = p->el[el];
@@ -1626,7 +1676,8 @@ p4d_status p4d_phys_create(const p4d_phys_params *p, p4d_ctx **out)
 p4d_status p4d_phys_workspace_size(const p4d_ctx *c, size_t *bytes)
 {
     if (!c || !bytes || !c->phys) return P4D_ERR_INVALID_ARG;
-    *bytes = 4 * align_up(8 * (size_t)c->g.N) + 2 * align_up(8 * (size_t)c->g.ne) + 256;
+    *bytes = 4 * align_up(8 * (size_t)c->g.N) + 2 * align_up(8 * (size_t)c->g.ne) +
+             2 * align_up(8 * (size_t)c->g.nelem) + 256;
     return P4D_OK;
 }
 
@@ -1646,7 +1697,38 @@ p4d_status p4d_phys_set_workspace(p4d_ctx *c, void *d_work, size_t bytes)
     S.old = take(8 * (size_t)c->g.N);
     S.fh = take(8 * (size_t)c->g.ne);
     S.qh = take(8 * (size_t)c->g.ne);
+    S.por = take(8 * (size_t)c->g.nelem);
+    S.act = take(8 * (size_t)c->g.nelem);
+    S.P.por = S.P.act = nullptr;
+    c->storage = 0;
+    c->g.meh = nullptr;
     S.ready = false;
+    return P4D_OK;
+}
+
+p4d_status p4d_phys_set_fractions(p4d_ctx *c, const double *eps_s, const double *eps_b, void *stream)
+{
+    if (!c || !c->phys || (!eps_s) != (!eps_b)) return P4D_ERR_INVALID_ARG;
+    PhysState &S = *c->phys;
+    if (!S.uh) return fail(c, P4D_ERR_STATE, "p4d_phys_set_workspace first");
+    c->pc_ready = 0;
+    S.P.por = S.P.act = nullptr;
+    c->storage = 0;
+    c->g.meh = nullptr;
+    if (!eps_s) return P4D_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const double h = c->g.h;
+    const double ms = S.P.rc * S.P.xc * h * h * h / S.prm.dt;
+    const int nb = launch_phys_fractions(c->g, S.P, eps_s, eps_b, S.por, S.act, c->meh, ms, c->red, st);
+    launch_max_final(c->red, nb, c->scal + 100, st);
+    HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal + 100, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (c->hhost[0] != 0.0)
+        return fail(c, P4D_ERR_INVALID_ARG, "volume fractions outside (0, 1) or no porosity left");
+    S.P.por = S.por;
+    S.P.act = S.act;
+    c->storage = 1;
+    c->g.meh = c->meh;
     return P4D_OK;
 }
 

@@ -19,11 +19,17 @@ struct Geom {
     long long off_pe, off_ce, off_cs[2], N, Nm;
     double h, dt, chi, tc;
     double mass_elec, mass_sep;      // eps * h^3 / dt per element material
+    const double *meh = nullptr;     // eps_e * h^3 / dt per element (device), or by material
 };
 
 __host__ __device__ inline int elem_mat(const Geom &g, int kk)
 {
     return kk + 1 < g.na ? 0 : (kk >= g.na + g.ns ? 1 : -1);
+}
+// storage coefficient eps h^3 / dt of element id (in element layer kk)
+__device__ inline double elem_storage(const Geom &g, long long id, int kk)
+{
+    return g.meh ? g.meh[id] : (elem_mat(g, kk) >= 0 ? g.mass_elec : g.mass_sep);
 }
 __host__ __device__ inline int node_mat(const Geom &g, int k)
 {

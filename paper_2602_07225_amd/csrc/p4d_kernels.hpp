@@ -74,7 +74,9 @@ __host__ __device__ inline int smooth0_box_tiles(int nx, int ny, int nz, int TX,
     return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + CZ - 1) / CZ);
 }
 
-template <typename T, bool RESID_ONLY>
+// MEH: the storage of the mass box comes per element from g.meh (a separate
+// instantiation keeps the per-material one free of its registers)
+template <typename T, bool RESID_ONLY, bool MEH = false>
 __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int tile, int TX, int CZ,
                                     Smooth0Lds &L)
 {
@@ -183,7 +185,15 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
                 const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
                 cK[e] = L.ck[(kl - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
                 const int ek = k - 1 + ez;
-                cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+                if (MEH) {
+                    const int ei = i - 1 + ex, ej = j - 1 + ey;
+                    const bool ok = A.mass && ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                                    ek >= A.ek_lo && ek <= A.ek_hi;
+                    cM[e] = ok ? g.meh[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+                } else {
+                    cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep)
+                                                     : 0.0;
+                }
             }
             double Sx = q1_stiff(cK, X) + dcn * X[13];
             if (A.mass) Sx += q1_mass(cM, X);
@@ -663,7 +673,9 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
         ck[e] = ok ? O.kaph[id] : 0.0;
         cs[e] = ok ? O.sigh[id] : 0.0;
-        cm[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+        // per-element storage only with separate coefficients (GEN)
+        cm[e] = ok ? (GEN ? elem_storage(g, id, ek) : (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep))
+                   : 0.0;
     }
     OpStencil P;
     double X[27];

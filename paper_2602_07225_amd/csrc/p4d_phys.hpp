@@ -11,6 +11,9 @@ struct PhysDev {
     double F, RT, tplus, brug, ce0, eps_el, eps_sep;
     double eps_s[2], sigma[2], k[2], alpha[2], csmax[2], cs0[2], a[2];
     double xphi, xc, xs, rphi, rc, rs;
+    // Case II: porosity and active-material fraction per element (device),
+    // or the per-material values when null
+    const double *por = nullptr, *act = nullptr;
 };
 
 // arrays of the residual correction (scaled variables)
@@ -35,6 +38,11 @@ int launch_phys_update(const Geom &g, const PhysDev &P, const double *dh, double
 void launch_phys_init(const Geom &g, const PhysDev &P, double *u, hipStream_t st);
 void launch_phys_old_cs(const Geom &g, const PhysDev &P, const double *uold, double dtp, double *old,
                         hipStream_t st);
+// por, act and the scaled storage meh = ms * por from the volume fractions
+// (device, per element); per workgroup a 1 where a fraction is out of range
+int launch_phys_fractions(const Geom &g, const PhysDev &P, const double *eps_s, const double *eps_b,
+                          double *por, double *act, double *meh, double ms, double *partial,
+                          hipStream_t st);
 void launch_phys_unscale_rows(const Geom &g, const PhysDev &P, const double *rh, double *r, hipStream_t st);
 
 }  // namespace p4d

@@ -80,14 +80,13 @@ __global__ __launch_bounds__(kBlock) void k_phys_elem(Geom g, PhysDev P, const d
         cbar += ce[(ei + (b & 1)) + (long long)g.nx * ((ej + ((b >> 1) & 1)) + (long long)g.ny * (ek + ((b >> 2) & 1)))];
     cbar *= 0.125;
     const int mat = elem_mat(g, ek);
-    const double eps = mat >= 0 ? P.eps_el : P.eps_sep;
+    const double eps = P.por ? P.por[t] : (mat >= 0 ? P.eps_el : P.eps_sep);
     const double eb = pow(eps, P.brug);
     const double kap = eb * kappa_bulk(cbar);
     const double kd = kap * 2.0 * (1.0 - P.tplus) * P.RT / (P.F * cbar);
     const double dce = eb * de_bulk(cbar);
-    const double sig = mat >= 0 ? pow(mat == 0 ? P.eps_s[0] : P.eps_s[1], P.brug) *
-                                      (mat == 0 ? P.sigma[0] : P.sigma[1])
-                                : 0.0;
+    const double act = P.act ? P.act[t] : (mat == 0 ? P.eps_s[0] : P.eps_s[1]);
+    const double sig = mat >= 0 ? pow(act, P.brug) * (mat == 0 ? P.sigma[0] : P.sigma[1]) : 0.0;
     sigh[t] = g.h * P.rphi * P.xphi * sig;
     kaph[t] = g.h * P.rphi * P.xphi * kap;
     kdh[t] = g.h * P.rphi * P.xc * kd;
@@ -125,6 +124,36 @@ __global__ __launch_bounds__(kBlock) void k_phys_node(Geom g, PhysDev P, const d
     ee[je] = P.rphi * P.xc * a * i_ce;
     ss[je] = P.rphi * P.xs * a * i_cs;
     qh[je] = P.rphi * a * in;
+}
+
+// Case II volume fractions: porosity 1 - eps_s - eps_b and active fraction
+// eps_s in electrode elements (separator: its porosity, no solid), the
+// scaled storage ms * eps (ms = r_c x_c h^3 / dt) of the c_e rows; flags fractions
+// outside (0, 1) or a porosity outside (0, 1]
+__global__ __launch_bounds__(kBlock) void k_phys_fractions(Geom g, PhysDev P, const double *__restrict__ eps_s,
+                                                           const double *__restrict__ eps_b,
+                                                           double *__restrict__ por, double *__restrict__ act,
+                                                           double *__restrict__ meh, double ms,
+                                                           double *__restrict__ partial)
+{
+    __shared__ double lds[4];
+    double bad = 0.0;
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < g.nelem;
+         t += (long long)gridDim.x * kBlock) {
+        const int ek = (int)(t / ((long long)(g.nx - 1) * (g.ny - 1)));
+        double p = P.eps_sep, a = 0.0;
+        if (elem_mat(g, ek) >= 0) {
+            const double fs = eps_s[t], fb = eps_b[t];
+            a = fs;
+            p = 1.0 - fs - fb;
+            if (!(fs > 0.0 && fs < 1.0 && fb > 0.0 && fb < 1.0 && p > 0.0 && p <= 1.0)) bad = 1.0;
+        }
+        por[t] = p;
+        act[t] = a;
+        meh[t] = ms * p;
+    }
+    bad = block_max(bad, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = bad;
 }
 
 // u^ = D_c^-1 u (or u = D_c u^ when up), per field
@@ -282,6 +311,15 @@ int launch_phys_update(const Geom &g, const PhysDev &P, const double *dh, double
 void launch_phys_init(const Geom &g, const PhysDev &P, double *u, hipStream_t st)
 {
     hipLaunchKernelGGL(k_phys_init, dim3(blocks(g.N)), dim3(kBlock), 0, st, g, P, u);
+}
+
+int launch_phys_fractions(const Geom &g, const PhysDev &P, const double *eps_s, const double *eps_b,
+                          double *por, double *act, double *meh, double ms, double *partial, hipStream_t st)
+{
+    const int nb = stream_blocks(g.nelem);
+    hipLaunchKernelGGL(k_phys_fractions, dim3(nb), dim3(kBlock), 0, st, g, P, eps_s, eps_b, por, act, meh,
+                       ms, partial);
+    return nb;
 }
 
 void launch_phys_unscale_rows(const Geom &g, const PhysDev &P, const double *rh, double *r, hipStream_t st)

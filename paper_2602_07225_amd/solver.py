@@ -25,10 +25,14 @@ class P4DSolver:
         nbytes = L.p4d_workspace_size(self.ctx, self.ws_opts)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)
+        self._kd = self._dc = self._ep = None
         self.upload(prob.sigma, prob.kappa, prob.g, prob.s, prob.e)
         kd, dc = getattr(prob, "kappa_d", None), getattr(prob, "dce", None)
         if kd is not None or dc is not None:
             self.set_transport(kd, dc)
+        ep = getattr(prob, "eps_e", None)
+        if ep is not None:
+            self.set_storage(ep)
         self.opts = None
 
     def _dev(self, a):
@@ -43,6 +47,11 @@ class P4DSolver:
         L.p4d_upload(self.ctx, *arrs)
         # kept for re-uploads with a new sigma (differentiable solves)
         self._kappa, self._g, self._s, self._e = arrs[1:]
+        # the upload resets the separate coefficients: keep those set
+        if self._kd is not None or self._dc is not None:
+            L.p4d_set_transport(self.ctx, self._kd, self._dc)
+        if self._ep is not None:
+            L.p4d_set_storage(self.ctx, self._ep)
         self.opts = None
 
     def set_transport(self, kappa_d=None, dce=None):
@@ -50,7 +59,17 @@ class P4DSolver:
         the c_e diffusion (None: chi * kappa and kappa)."""
         self._kd = None if kappa_d is None else self._dev(kappa_d)
         self._dc = None if dce is None else self._dev(dce)
+        if any(t is not None and t.numel() != self.n_elem for t in (self._kd, self._dc)):
+            raise ValueError(f"transport coefficients need {self.n_elem} values per element")
         L.p4d_set_transport(self.ctx, self._kd, self._dc)
+        self.opts = None
+
+    def set_storage(self, eps_e=None):
+        """Porosity per element for the c_e storage (None: per material)."""
+        self._ep = None if eps_e is None else self._dev(eps_e)
+        if self._ep is not None and self._ep.numel() != self.n_elem:
+            raise ValueError(f"eps_e needs {self.n_elem} values per element")
+        L.p4d_set_storage(self.ctx, self._ep)
         self.opts = None
 
     def set_diffusivity(self, Ds):
@@ -248,6 +267,16 @@ class PhysCell:
         pbytes = L.p4d_phys_workspace_size(self.ctx)
         self.pws = torch.empty(pbytes, dtype=torch.uint8, device=self.device)
         L.p4d_phys_set_workspace(self.ctx, self.pws.data_ptr(), pbytes)
+        if getattr(case, "eps_s_e", None) is not None:
+            self.set_fractions(case.eps_s_e, case.eps_b_e)
+
+    def set_fractions(self, eps_s=None, eps_b=None):
+        """Case II volume fractions per element (None, None: homogeneous)."""
+        a = None if eps_s is None else self._dev(eps_s)
+        b = None if eps_b is None else self._dev(eps_b)
+        if any(t is not None and t.numel() != self.n_elem for t in (a, b)):
+            raise ValueError(f"volume fractions need {self.n_elem} values per element")
+        L.p4d_phys_set_fractions(self.ctx, a, b)
 
     def _dev(self, a):
         if isinstance(a, torch.Tensor):

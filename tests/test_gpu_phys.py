@@ -115,3 +115,73 @@ def test_phys_argument_errors():
     prm.el[1].cs0 = prm.el[1].cs_max * 1.5
     with pytest.raises(P4DError):
         _lib.p4d_phys_create(prm)
+
+
+# ---------------------------------------------------------------------------
+# Case II: volume fractions per element, uniform current
+# ---------------------------------------------------------------------------
+def cell2(n=19, nr=(6, 7), seed=3):
+    from paper_2602_07225_amd import PhysCell
+    case = ph.case2(n, nr, seed=seed)
+    grid = P.Grid(case)
+    I = P.applied_current(case)
+    return case, grid, I, PhysCell(case, I)
+
+
+def test_case2_residual_parity():
+    case, grid, I, pc = cell2()
+    u0 = P.initial_state(case, grid)
+    for seed in (0, 1):
+        u = u0 if seed == 0 else perturbed(case, grid, u0, seed)
+        uold = u0 if seed == 0 else perturbed(case, grid, u0, seed + 10)
+        r = to_np(pc.residual(u, uold))
+        ref = P.residual(case, grid, u, uold, I)
+        e = block_errors(case, grid, r, ref)
+        say(f"  case II residual {seed}", {k: f"{v:.1e}" for k, v in e.items()})
+        # at rest only the phi rows carry the applied current (c_e and c_s
+        # rows are rounding noise there)
+        assert (e["phi"] if seed == 0 else max(e.values())) <= 1e-10
+
+
+def test_case2_newton_step_matches_oracle():
+    case, grid, I, pc = cell2()
+    u0 = P.initial_state(case, grid)
+    uo, hist = P.newton_step(case, grid, u0, I, lin_rtol=1e-10, coarse_max=64)
+    ug, info = pc.step(u0, rtol=1e-10)
+    ug = to_np(ug)
+    say(f"  case II newton gpu iters={info.iters} lin={info.lin_iters}; oracle {len(hist)}")
+    assert info.status == 0
+    assert abs(info.iters - len(hist)) <= 1
+    assert P.scaled_update(case, grid, ug - uo) <= 1e-8
+    sc = P.Scaling(case)
+    R = P.residual(case, grid, ug, u0, I)
+    assert np.abs(sc.rows(grid, R)).max() <= 1e-7
+    # back to the homogeneous cell: the Case I residual (uniform current)
+    pc.set_fractions(None, None)
+    case1 = ph.PhysCase(n=case.n, nr=case.nr, profile="uniform")
+    r = to_np(pc.residual(ug, u0))
+    e = block_errors(case1, grid, r, P.residual(case1, grid, ug, u0, I))
+    # (the c_s rows do not see the fractions: converged, they are rounding
+    # noise in both cells)
+    assert max(e["phi"], e["ce"]) <= 1e-10
+
+
+def test_case2_fraction_errors():
+    from paper_2602_07225_amd import P4DError, _lib
+    case, grid, I, pc = cell2()
+    bad = case.eps_s_e.copy()
+    lay = ph.element_layers(case)
+    bad[np.flatnonzero(lay == 1)[5]] = 0.95          # eps_s + eps_b > 1
+    with pytest.raises(P4DError) as e:
+        pc.set_fractions(bad, case.eps_b_e)
+    assert e.value.status == _lib.P4D_ERR_INVALID_ARG
+    with pytest.raises(P4DError):
+        _lib.p4d_phys_set_fractions(pc.ctx, pc._dev(case.eps_s_e), None)
+    # the failed call left the cell homogeneous: Case I residual (away from
+    # rest, so that every block is active)
+    u0 = P.initial_state(case, grid)
+    u, uold = perturbed(case, grid, u0, 1), perturbed(case, grid, u0, 11)
+    case1 = ph.PhysCase(n=case.n, nr=case.nr, profile="uniform")
+    r = to_np(pc.residual(u, uold))
+    e = block_errors(case1, grid, r, P.residual(case1, grid, u, uold, I))
+    assert max(e.values()) <= 1e-10
