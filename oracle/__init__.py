@@ -42,6 +42,10 @@ PC_BGS = 2
 # Krylov space: all unknowns, or the Schur complement of the c_s blocks
 KRYLOV_FULL = 0
 KRYLOV_SCHUR = 1
+# multigrid smoothing: Chebyshev with full coarsening, or symmetric z-line
+# block Gauss-Seidel with coarsening in x and y only
+SMOOTH_CHEB = 0
+SMOOTH_ZLINE = 1
 
 # fields of the 4x4 block system as numbered in a block ordering
 F_PHIS, F_PHIE, F_CE, F_CS = 0, 1, 2, 3
@@ -79,14 +83,14 @@ class Desc(C.Structure):
                 ("dt", C.c_double), ("chi", C.c_double), ("tc", C.c_double),
                 ("lambda_c", C.c_double), ("eps_elec", C.c_double),
                 ("eps_sep", C.c_double), ("length", C.c_double),
-                ("lambda_el", C.c_double * 2)]
+                ("lambda_el", C.c_double * 2), ("hxy", C.c_double * 2)]
 
 
 class Opts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32),
                 ("cgs2", C.c_int32), ("rtol", C.c_double),
                 ("coarse_max", C.c_int32), ("cheb_degree", C.c_int32),
-                ("bgs_order", C.c_int32), ("krylov", C.c_int32)]
+                ("bgs_order", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -131,8 +135,9 @@ def lib():
         L.orc_mg_stencil.argtypes = [C.c_void_p, C.c_int, C.c_int, _dp]
         L.orc_vcycle.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_omega.argtypes = [C.c_void_p, _dp]
-        L.orc_rap.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp]
+        L.orc_rap.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp]
         L.orc_stencil_apply.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_zline_sweep.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, _dp]
         L.orc_chebyshev.argtypes = [C.c_int, C.c_int, C.c_int, _dp, C.c_int, _dp, _dp]
         L.orc_gershgorin.argtypes = [C.c_int, C.c_int, C.c_int, _dp]
         L.orc_gershgorin.restype = C.c_double
@@ -175,11 +180,13 @@ def radial_rows(N: int, D: float, rho: np.ndarray):
 # ---------------------------------------------------------------------------
 # Stencil helpers (test pins of the multigrid pieces)
 # ---------------------------------------------------------------------------
-def rap(dims, S: np.ndarray) -> np.ndarray:
+def rap(dims, S: np.ndarray, coarsen_z: bool = True) -> np.ndarray:
     nx, ny, nz = dims
     cdim = [n if n <= 2 else n // 2 + 1 for n in dims]
+    if not coarsen_z:
+        cdim[2] = nz
     Sc = np.zeros(27 * cdim[0] * cdim[1] * cdim[2])
-    lib().orc_rap(nx, ny, nz, _p(_f64(S).reshape(-1)), _p(Sc))
+    lib().orc_rap(nx, ny, nz, int(coarsen_z), _p(_f64(S).reshape(-1)), _p(Sc))
     return Sc.reshape(-1, 27), tuple(cdim)
 
 
@@ -192,6 +199,13 @@ def stencil_apply(dims, S, x):
 def chebyshev(dims, S, deg, b, x0=None):
     x = np.zeros(len(b)) if x0 is None else _f64(x0).copy()
     lib().orc_chebyshev(*dims, _p(_f64(S).reshape(-1)), deg, _p(_f64(b)), _p(x))
+    return x
+
+
+def zline_sweep(dims, S, b, x0, backward=False):
+    """One pass of z-line block Gauss-Seidel over the four colours."""
+    x = _f64(x0).copy()
+    lib().orc_zline_sweep(*dims, _p(_f64(S).reshape(-1)), int(backward), _p(_f64(b)), _p(x))
     return x
 
 
@@ -226,6 +240,7 @@ class Oracle:
         d.length = getattr(prob, "length", 0.0)
         lel = getattr(prob, "lambda_el", (0.0, 0.0))
         d.lambda_el[0], d.lambda_el[1] = lel
+        d.hxy[0], d.hxy[1] = getattr(prob, "hxy", (0.0, 0.0))
         self.desc = d
         self._keep = [_f64(prob.sigma), _f64(prob.kappa), _f64(prob.g),
                       _f64(prob.s), _f64(prob.e)]
@@ -272,12 +287,16 @@ class Oracle:
 
     # -- preconditioner --------------------------------------------------------
     def setup(self, pc=PC_SCHUR, restart=30, maxit=1000, rtol=1e-8, cgs2=False,
-              coarse_max=64, cheb_degree=2, bgs_order=BGS_PAPER, krylov=KRYLOV_FULL):
+              coarse_max=64, cheb_degree=2, bgs_order=BGS_PAPER, krylov=KRYLOV_FULL,
+              smoother=SMOOTH_CHEB):
         o = Opts()
         o.pc, o.restart, o.maxit, o.cgs2 = pc, restart, maxit, int(cgs2)
         o.rtol, o.coarse_max, o.cheb_degree = rtol, coarse_max, cheb_degree
         o.bgs_order = bgs_order
         o.krylov = krylov
+        o.smoother = smoother
+        if smoother not in (SMOOTH_CHEB, SMOOTH_ZLINE):
+            raise ValueError("smoother must be SMOOTH_CHEB or SMOOTH_ZLINE")
         if krylov not in (KRYLOV_FULL, KRYLOV_SCHUR) or (krylov == KRYLOV_SCHUR and pc != PC_SCHUR):
             raise ValueError("krylov must be KRYLOV_FULL, or KRYLOV_SCHUR with PC_SCHUR")
         if restart > 63:

@@ -72,6 +72,7 @@ typedef struct {
     double dt, chi, tc, lambda_c, eps_elec, eps_sep;
     double length;         /* cell edge along z (h = length / (nz - 1)); 0: 1   */
     double lambda_el[2];   /* surface coupling scale per electrode; 0: lambda_c */
+    double hxy[2];         /* element edges along x and y; 0: h (isotropic)     */
 } orc_desc;
 
 enum { ORC_PC_SCHUR = 0, ORC_PC_BJ = 1, ORC_PC_BGS = 2 };
@@ -89,7 +90,13 @@ typedef struct {
     int32_t cheb_degree;
     int32_t bgs_order;     /* BGS: field at block position p is bits [2p, 2p+2) */
     int32_t krylov;        /* ORC_KRYLOV_FULL or ORC_KRYLOV_SCHUR               */
+    int32_t smoother;      /* ORC_SMOOTH_CHEB or ORC_SMOOTH_ZLINE              */
 } orc_opts;
+
+/* Multigrid smoothing: Chebyshev on diag(S)^-1 S with full coarsening, or
+ * symmetric block Gauss-Seidel over the z-lines of the box (four colours of
+ * lines by the parity of x and y) with coarsening in x and y only.          */
+enum { ORC_SMOOTH_CHEB = 0, ORC_SMOOTH_ZLINE = 1 };
 
 /* Krylov space: all unknowns, or the electrode-level unknowns of the Schur
  * complement left when the c_s blocks are eliminated exactly (SCHUR mode). */
@@ -116,7 +123,10 @@ typedef struct {
 
 typedef struct {
     orc_desc d;
-    double h;
+    double h;              /* element edge along z                          */
+    double hx, hy, vol;    /* edges along x and y, element volume            */
+    int aniso;             /* hx or hy differs from h                        */
+    double kw[3];          /* stiffness weights vol / (h_d^2 h) per axis     */
     int nc;
     long nnode, nelem, nea, nec, ne;
     long off_ps, off_pe, off_ce, off_cs[2], N;
@@ -260,6 +270,13 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
     orc_problem *P = xmalloc(sizeof(orc_problem));
     P->d = *d;
     P->h = (d->length > 0.0 ? d->length : 1.0) / (d->nz - 1);
+    P->hx = d->hxy[0] > 0.0 ? d->hxy[0] : P->h;
+    P->hy = d->hxy[1] > 0.0 ? d->hxy[1] : P->h;
+    P->aniso = P->hx != P->h || P->hy != P->h;
+    P->vol = P->hx * P->hy * P->h;
+    P->kw[0] = P->hy / P->hx;
+    P->kw[1] = P->hx / P->hy;
+    P->kw[2] = P->hx * P->hy / (P->h * P->h);
     P->kappad = NULL;
     P->dce = NULL;
     P->epse = NULL;
@@ -290,7 +307,7 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
     /* lumped reaction weight: the node's share (1/8 of each) of the volume of
      * the electrode elements that contain it                                */
     P->m = xmalloc(sizeof(double) * P->ne);
-    double h3 = P->h * P->h * P->h;
+    double h3 = P->vol;
     for (int k = 0; k < d->nz; k++)
         for (int j = 0; j < d->ny; j++)
             for (int i = 0; i < d->nx; i++) {
@@ -407,6 +424,24 @@ void orc_lumped_weights(const orc_problem *P, double *m)
 /* ------------------------------------------------------------------------ */
 /* Sec. 3.2: Q1 element sums at one node                                     */
 /* ------------------------------------------------------------------------ */
+/* Stiffness of a box element with edges hx, hy, hz over h: the sum over the
+ * axes d of (vol / h_d^2) / h times the tensor product of the 1D stiffness
+ * along d (1 on the diagonal, -1 off) with the 1D masses (1/3, 1/6) along
+ * the other two; for equal edges this is khat.                              */
+static double kelem(const orc_problem *P, int a, int b)
+{
+    if (!P->aniso) return khat(a, b);
+    int p = a ^ b;
+    double acc = 0.0;
+    for (int d = 0; d < 3; d++) {
+        double v = (p >> d) & 1 ? -1.0 : 1.0;
+        for (int q = 0; q < 3; q++)
+            if (q != d) v *= (p >> q) & 1 ? 1.0 / 6.0 : 1.0 / 3.0;
+        acc += P->kw[d] * v;
+    }
+    return acc;
+}
+
 /* sum over the elements e containing node (i,j,k) that pass `use`, of
  *   coef(e) * sum_b Ahat(a,b) * x[node b]     (a = local index of the node)
  * where x is read through `xv` (returns the value at node (i,j,k)).         */
@@ -430,7 +465,7 @@ static double elem_sum(const orc_problem *P, int i, int j, int k, int stiff,
                 int a = (1 - bx) | ((1 - by) << 1) | ((1 - bz) << 2);
                 double part = 0.0;
                 for (int b = 0; b < 8; b++) {
-                    double w = stiff ? khat(a, b) : mhat(a, b);
+                    double w = stiff ? kelem(P, a, b) : mhat(a, b);
                     if (w == 0.0) continue;
                     part += w * xv(P, ei + (b & 1), ej + ((b >> 1) & 1),
                                    ek + ((b >> 2) & 1), xctx);
@@ -469,7 +504,7 @@ static double cf_mass(const orc_problem *P, int i, int j, int k, const void *c)
     (void)c;
     double eps = P->epse ? P->epse[elem_id(P, i, j, k)]
                          : (elem_mat(P, k) >= 0 ? P->d.eps_elec : P->d.eps_sep);
-    return eps * P->h * P->h * P->h / P->d.dt;
+    return eps * P->vol / P->d.dt;
 }
 
 /* node value readers */
@@ -700,7 +735,7 @@ static void assemble_fine(const orc_problem *P, int box, double *S)
                                 int lk = gk - k0;
                                 if (lk < 0 || lk >= NZ) continue;   /* eliminated */
                                 row[st_off(gi - i, gj - j, gk - k)] +=
-                                    cK * khat(a, b) + cM * mhat(a, b);
+                                    cK * kelem(P, a, b) + cM * mhat(a, b);
                             }
                         }
                 /* reaction diagonal of the Schur-complement field block */
@@ -729,11 +764,19 @@ static int coarse_of_fine(int n, int i, int *I, double *w)
 }
 static int coarse_size(int n) { return n <= 2 ? n : n / 2 + 1; }
 
-/* Galerkin product S_c = P^T S P, P = P_x (x) P_y (x) P_z, by brute force over
- * fine rows (serial scatter, obviously correct)                             */
-void orc_rap(int nx, int ny, int nz, const double *S, double *Sc)
+/* the same along z, which z-line smoothing leaves uncoarsened (P_z = I)      */
+static int z_of_fine(int zc, int n, int i, int *I, double *w)
 {
-    int cx = coarse_size(nx), cy = coarse_size(ny), cz = coarse_size(nz);
+    if (!zc) { I[0] = i; w[0] = 1.0; return 1; }
+    return coarse_of_fine(n, i, I, w);
+}
+static int z_size(int zc, int n) { return zc ? coarse_size(n) : n; }
+
+/* Galerkin product S_c = P^T S P, P = P_x (x) P_y (x) P_z (P_z = I unless
+ * zc), by brute force over fine rows (serial scatter, obviously correct)    */
+void orc_rap(int nx, int ny, int nz, int zc, const double *S, double *Sc)
+{
+    int cx = coarse_size(nx), cy = coarse_size(ny), cz = z_size(zc, nz);
     memset(Sc, 0, sizeof(double) * 27 * (long)cx * cy * cz);
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
@@ -742,7 +785,7 @@ void orc_rap(int nx, int ny, int nz, const double *S, double *Sc)
                 double wi[2], wj[2], wk[2];
                 int ni = coarse_of_fine(nx, i, Ii, wi);
                 int nj = coarse_of_fine(ny, j, Ij, wj);
-                int nk = coarse_of_fine(nz, k, Ik, wk);
+                int nk = z_of_fine(zc, nz, k, Ik, wk);
                 const double *row = S + 27 * (i + (long)nx * (j + (long)ny * k));
                 for (int o = 0; o < 27; o++) {
                     double sv = row[o];
@@ -754,7 +797,7 @@ void orc_rap(int nx, int ny, int nz, const double *S, double *Sc)
                     double vi[2], vj[2], vk[2];
                     int mi = coarse_of_fine(nx, ii, Ji, vi);
                     int mj = coarse_of_fine(ny, jj, Jj, vj);
-                    int mk = coarse_of_fine(nz, kk, Jk, vk);
+                    int mk = z_of_fine(zc, nz, kk, Jk, vk);
                     for (int a3 = 0; a3 < nk; a3++) for (int a2 = 0; a2 < nj; a2++)
                     for (int a1 = 0; a1 < ni; a1++) {
                         double wa = wi[a1] * wj[a2] * wk[a3] * sv;
@@ -871,10 +914,11 @@ static void mg_build(orc_problem *P, int box)
     L0->S = xmalloc(sizeof(double) * 27 * L0->n);
     assemble_fine(P, box, L0->S);
     M->nlev = 1;
+    const int zc = P->opts.smoother != ORC_SMOOTH_ZLINE;
     for (;;) {
         orc_level *L = &M->lev[M->nlev - 1];
         L->lmax = gershgorin(L);
-        int cx = coarse_size(L->nx), cy = coarse_size(L->ny), cz = coarse_size(L->nz);
+        int cx = coarse_size(L->nx), cy = coarse_size(L->ny), cz = z_size(zc, L->nz);
         long cn = (long)cx * cy * cz;
         if (L->n <= P->opts.coarse_max || cn == L->n || M->nlev == 16) {
             coarse_factor(L);
@@ -883,7 +927,7 @@ static void mg_build(orc_problem *P, int box)
         orc_level *C = &M->lev[M->nlev];
         C->nx = cx; C->ny = cy; C->nz = cz; C->n = cn;
         C->S = xmalloc(sizeof(double) * 27 * cn);
-        orc_rap(L->nx, L->ny, L->nz, L->S, C->S);
+        orc_rap(L->nx, L->ny, L->nz, zc, L->S, C->S);
         M->nlev++;
     }
 }
@@ -912,6 +956,53 @@ static void chebyshev(const orc_level *L, int deg, const double *b, double *x,
     }
 }
 
+/* Block Gauss-Seidel over the z-lines of one colour (x parity cx, y parity
+ * cy): on each line (i, j) the rows' couplings to other lines are moved to
+ * the right-hand side with the current x, and the line's tridiagonal block
+ * (couplings to k-1, k, k+1 in the same column) is solved by elimination.
+ * Lines of one colour do not couple (27-point stencil), so their order does
+ * not matter.                                                               */
+static void zline_colour(const orc_level *L, int cx, int cy, const double *b, double *x)
+{
+    int nx = L->nx, ny = L->ny, nz = L->nz;
+    double *cp = xmalloc(sizeof(double) * nz), *dp = xmalloc(sizeof(double) * nz);
+    for (int j = cy; j < ny; j += 2)
+        for (int i = cx; i < nx; i += 2) {
+            for (int k = 0; k < nz; k++) {
+                long n = i + (long)nx * (j + (long)ny * k);
+                const double *row = L->S + 27 * n;
+                double rhs = b[n];
+                for (int o = 0; o < 27; o++) {
+                    int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+                    if (dx == 0 && dy == 0) continue;
+                    int ii = i + dx, jj = j + dy, kk = k + dz;
+                    if (ii < 0 || jj < 0 || kk < 0 || ii >= nx || jj >= ny || kk >= nz) continue;
+                    rhs -= row[o] * x[ii + (long)nx * (jj + (long)ny * kk)];
+                }
+                double lo = k > 0 ? row[st_off(0, 0, -1)] : 0.0;
+                double up = k < nz - 1 ? row[st_off(0, 0, 1)] : 0.0;
+                double den = row[13] - (k > 0 ? lo * cp[k - 1] : 0.0);
+                cp[k] = up / den;
+                dp[k] = (rhs - (k > 0 ? lo * dp[k - 1] : 0.0)) / den;
+            }
+            double nxt = 0.0;
+            for (int k = nz - 1; k >= 0; k--) {
+                nxt = dp[k] - (k < nz - 1 ? cp[k] * nxt : 0.0);
+                x[i + (long)nx * (j + (long)ny * k)] = nxt;
+            }
+        }
+    free(cp); free(dp);
+}
+
+/* one symmetric sweep pass: colours 0..3 (pre) or 3..0 (post)              */
+static void zline_sweep(const orc_level *L, int backward, const double *b, double *x)
+{
+    for (int q = 0; q < 4; q++) {
+        int c = backward ? 3 - q : q;
+        zline_colour(L, c & 1, c >> 1, b, x);
+    }
+}
+
 /* one V-cycle x = V_l(b), x zero on entry not required (it is overwritten)  */
 static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b, double *x)
 {
@@ -922,8 +1013,12 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
     double *r = xmalloc(sizeof(double) * n), *dv = xmalloc(sizeof(double) * n);
     double *bc = xmalloc(sizeof(double) * C->n), *xc = xmalloc(sizeof(double) * C->n);
     int deg = P->opts.cheb_degree;
+    const int line = P->opts.smoother == ORC_SMOOTH_ZLINE, zc = !line;
     memset(x, 0, sizeof(double) * n);
-    chebyshev(L, deg, b, x, r, dv);                       /* pre-smoothing  */
+    if (line)                                             /* pre-smoothing  */
+        for (int t = 0; t < deg; t++) zline_sweep(L, 0, b, x);
+    else
+        chebyshev(L, deg, b, x, r, dv);
     st_apply(L, x, r);
     for (long i = 0; i < n; i++) r[i] = b[i] - r[i];      /* residual       */
     memset(bc, 0, sizeof(double) * C->n);                 /* b_c = P^T r    */
@@ -934,7 +1029,7 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
                 double wi[2], wj[2], wk[2];
                 int ni = coarse_of_fine(L->nx, i, Ii, wi);
                 int nj = coarse_of_fine(L->ny, j, Ij, wj);
-                int nk = coarse_of_fine(L->nz, k, Ik, wk);
+                int nk = z_of_fine(zc, L->nz, k, Ik, wk);
                 double rv = r[i + (long)L->nx * (j + (long)L->ny * k)];
                 for (int c = 0; c < nk; c++) for (int bq = 0; bq < nj; bq++)
                 for (int a = 0; a < ni; a++)
@@ -949,7 +1044,7 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
                 double wi[2], wj[2], wk[2];
                 int ni = coarse_of_fine(L->nx, i, Ii, wi);
                 int nj = coarse_of_fine(L->ny, j, Ij, wj);
-                int nk = coarse_of_fine(L->nz, k, Ik, wk);
+                int nk = z_of_fine(zc, L->nz, k, Ik, wk);
                 double v = 0.0;
                 for (int c = 0; c < nk; c++) for (int bq = 0; bq < nj; bq++)
                 for (int a = 0; a < ni; a++)
@@ -957,7 +1052,10 @@ static void vcycle(const orc_problem *P, const orc_mg *M, int l, const double *b
                          xc[Ii[a] + (long)C->nx * (Ij[bq] + (long)C->ny * Ik[c])];
                 x[i + (long)L->nx * (j + (long)L->ny * k)] += v;
             }
-    chebyshev(L, deg, b, x, r, dv);                       /* post-smoothing */
+    if (line)                                             /* post-smoothing */
+        for (int t = 0; t < deg; t++) zline_sweep(L, 1, b, x);
+    else
+        chebyshev(L, deg, b, x, r, dv);
     free(r); free(dv); free(bc); free(xc);
 }
 
@@ -1238,6 +1336,12 @@ void orc_chebyshev(int nx, int ny, int nz, const double *S, int deg,
     chebyshev(&L, deg, b, x, r, dv);
     free(r); free(dv);
 }
+void orc_zline_sweep(int nx, int ny, int nz, const double *S, int backward, const double *b,
+                     double *x)
+{
+    orc_level L = {nx, ny, nz, (long)nx * ny * nz, (double *)S, 0.0, NULL};
+    zline_sweep(&L, backward, b, x);
+}
 double orc_gershgorin(int nx, int ny, int nz, const double *S)
 {
     orc_level L = { nx, ny, nz, (long)nx * ny * nz, (double *)S, 0.0, NULL };
@@ -1515,7 +1619,7 @@ void orc_gradient(const orc_problem *P, const double *x, const double *lam,
                 }
                 double acc = 0.0;
                 for (int a = 0; a < 8; a++)
-                    for (int b = 0; b < 8; b++) acc += ll[a] * P->h * khat(a, b) * xl[b];
+                    for (int b = 0; b < 8; b++) acc += ll[a] * P->h * kelem(P, a, b) * xl[b];
                 dsigma[id] = -acc;
             }
     for (int el = 0; el < 2; el++) {

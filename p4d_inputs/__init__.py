@@ -86,6 +86,8 @@ class Problem:
     kappa_d: Optional[np.ndarray] = None  # (n_elem,)
     dce: Optional[np.ndarray] = None      # (n_elem,)
     eps_e: Optional[np.ndarray] = None    # (n_elem,)
+    # element edges along x and y (0: h, the edge along z)
+    hxy: Tuple[float, float] = (0.0, 0.0)
 
     # ---- sizes -----------------------------------------------------------
     @property
