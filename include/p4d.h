@@ -90,6 +90,16 @@ typedef enum { P4D_FP64 = 0, P4D_FP32 = 1 } p4d_prec;
  * Needs pc = P4D_PC_SCHUR. */
 typedef enum { P4D_KRYLOV_FULL = 0, P4D_KRYLOV_SCHUR = 1 } p4d_krylov;
 
+/* Multigrid smoothing of the field blocks.  P4D_SMOOTH_CHEB: Chebyshev on
+ * diag(S)^-1 S of degree cheb_degree, full coarsening.  P4D_SMOOTH_ZLINE:
+ * symmetric block Gauss-Seidel over the z-lines of each box (lines coloured
+ * by the parity of x and y; colours 0..3 before the coarse correction, 3..0
+ * after; cheb_degree passes each), coarsening in x and y only: robust when
+ * the elements are much thinner along z than across, as in the flattened
+ * jelly roll of paper Sec. 5 (Case III), where point smoothers stall.  FP64
+ * preconditioner, pc SCHUR or BJ, the full Krylov space.                   */
+typedef enum { P4D_SMOOTH_CHEB = 0, P4D_SMOOTH_ZLINE = 1 } p4d_smoother;
+
 /* Problem geometry and scalars, all nondimensional.  The particle radius is
  * scaled to 1; Ds = D_s dt / R_s^2; theta_bar = last/first radial interval. */
 typedef struct {
@@ -106,6 +116,12 @@ typedef struct {
     double length;             /* cell edge along z: h = length / (nz - 1); 0: 1  */
     double lambda_el[2];       /* surface coupling scale per electrode; 0 keeps
                                   lambda_c                                        */
+    double hxy[2];             /* element edges along x and y; 0: h (cubes).  Box
+                                  elements take the Q1 stiffness sum_d (vol /
+                                  h_d^2) Khat_d and the mass vol Mhat; the
+                                  operator then runs one thread per node and the
+                                  Schur-complement Krylov space, P4D_PC_BGS,
+                                  p4d_param_gradient and batches do not apply   */
 } p4d_problem_desc;
 
 typedef struct {
@@ -121,6 +137,7 @@ typedef struct {
     int32_t bgs_order;     /* P4D_PC_BGS: packed field ordering (see above); fixed
                               at p4d_setup, a solve must pass the same value     */
     int32_t krylov;        /* p4d_krylov; may differ between solves             */
+    int32_t smoother;      /* p4d_smoother (default P4D_SMOOTH_CHEB)              */
 } p4d_solve_opts;
 
 typedef struct {

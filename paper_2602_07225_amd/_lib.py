@@ -32,6 +32,8 @@ P4D_FP64 = 0
 P4D_FP32 = 1
 P4D_KRYLOV_FULL = 0
 P4D_KRYLOV_SCHUR = 1
+P4D_SMOOTH_CHEB = 0
+P4D_SMOOTH_ZLINE = 1
 
 (P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY,
  P4D_K_BATCH_PC, P4D_K_COUPLING) = range(1, 9)
@@ -62,14 +64,14 @@ class ProblemDesc(C.Structure):
                 ("Ds", C.c_double * 2), ("theta_bar", C.c_double * 2),
                 ("dt", C.c_double), ("chi", C.c_double), ("tc", C.c_double),
                 ("lambda_c", C.c_double), ("eps_elec", C.c_double), ("eps_sep", C.c_double),
-                ("length", C.c_double), ("lambda_el", C.c_double * 2)]
+                ("length", C.c_double), ("lambda_el", C.c_double * 2), ("hxy", C.c_double * 2)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("pc", C.c_int32), ("pc_prec", C.c_int32), ("restart", C.c_int32),
                 ("maxit", C.c_int32), ("cheb_degree", C.c_int32), ("coarse_max", C.c_int32),
                 ("cgs2", C.c_int32), ("z_fp32", C.c_int32), ("rtol", C.c_double),
-                ("bgs_order", C.c_int32), ("krylov", C.c_int32)]
+                ("bgs_order", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32)]
 
 
 class Electrode(C.Structure):
@@ -296,6 +298,7 @@ def desc_from(p) -> ProblemDesc:
     d.length = getattr(p, "length", 0.0)
     lel = getattr(p, "lambda_el", (0.0, 0.0))
     d.lambda_el[0], d.lambda_el[1] = lel
+    d.hxy[0], d.hxy[1] = getattr(p, "hxy", (0.0, 0.0))
     return d
 
 

@@ -44,7 +44,7 @@ template <typename T>
 void launch_smooth0(const Geom &g, const LevelBatch<T> &lb, int nblk, int resid_only, int TX,
                     int CZ, hipStream_t st)
 {
-    if (g.meh) {
+    if (g.meh || g.aniso) {
         if (resid_only)
             hipLaunchKernelGGL((k_smooth0<T, true, true>), dim3(nblk), dim3(kBlock), 0, st, g, lb, TX, CZ);
         else
@@ -131,7 +131,7 @@ template void launch_coarse<float>(const CoarseBatch<float> &, hipStream_t);
 // Setup kernels (FP64)
 // ---------------------------------------------------------------------------
 // per element: h sigma (electrode elements only), h kappa; per electrode node:
-// the lumped weight m_j = (h^3/8) * #(electrode elements containing j)
+// the lumped weight m_j = (vol/8) * #(electrode elements containing j)
 __global__ __launch_bounds__(kBlock) void k_setup_nodes(Geom g, const double *__restrict__ sigma,
                                                         const double *__restrict__ kappa,
                                                         double *__restrict__ sigh,
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_setup_nodes(Geom g, const double *__
         int cz = 0;
         if (k - 1 >= 0 && elem_mat(g, k - 1) == el) cz++;
         if (k < g.nz - 1 && elem_mat(g, k) == el) cz++;
-        mm[t] = g.h * g.h * g.h / 8.0 * (double)(cx * cy * cz);
+        mm[t] = g.vol / 8.0 * (double)(cx * cy * cz);
     }
 }
 
@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, i
         for (int bb = 0; bb < 8; bb++) {
             const int dx = ex - 1 + (bb & 1), dy = ey - 1 + ((bb >> 1) & 1), dz = ez - 1 + ((bb >> 2) & 1);
             const int d = popc3(a ^ bb);
-            const double kab = d == 0 ? 1.0 / 3.0 : (d == 1 ? 0.0 : -1.0 / 12.0);
+            const double kab = g.aniso ? (d == 0 ? g.kw[0] : -g.kw[a ^ bb])
+                                       : (d == 0 ? 1.0 / 3.0 : (d == 1 ? 0.0 : -1.0 / 12.0));
             const double mab = d == 0 ? 8.0 / 216 : d == 1 ? 4.0 / 216 : d == 2 ? 2.0 / 216 : 1.0 / 216;
             const bool in = (kl + dz >= 0) && (kl + dz < nzb);
             if (in) row[nb_index(dx, dy, dz)] += c * kab + cm * mab;
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_rap1d(RapBatch rb)
 
 // P^T S P for up to four boxes at once; job b needs job.tmp with room for
 // 27 * (cx*fy*fz + cx*cy*fz) doubles
-void launch_rap(const RapJob *jobs, int njobs, hipStream_t st)
+void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st)
 {
     RapBatch r[3] = {};
     int blk[3] = {0, 0, 0};
@@ -370,7 +371,7 @@ void launch_rap(const RapJob *jobs, int njobs, hipStream_t st)
         double *t2 = J.tmp + 27LL * cx * J.fy * J.fz;        // (cx, cy, fz)
         const int n1 = cx * J.fy * J.fz, n2 = cx * cy * J.fz, n3 = cx * cy * cz;
         r[0].a[b] = RapArgs{J.fx, J.fy, J.fz, blk[0], J.Sf, t1};
-        r[1].a[b] = RapArgs{cx, J.fy, J.fz, blk[1], t1, t2};
+        r[1].a[b] = RapArgs{cx, J.fy, J.fz, blk[1], t1, zc ? t2 : J.Sc};
         r[2].a[b] = RapArgs{cx, cy, J.fz, blk[2], t2, J.Sc};
         blk[0] += (n1 + kBlock - 1) / kBlock;
         blk[1] += (n2 + kBlock - 1) / kBlock;
@@ -379,7 +380,94 @@ void launch_rap(const RapJob *jobs, int njobs, hipStream_t st)
     if (!njobs) return;
     hipLaunchKernelGGL(k_rap1d<0>, dim3(blk[0]), dim3(kBlock), 0, st, r[0]);
     hipLaunchKernelGGL(k_rap1d<1>, dim3(blk[1]), dim3(kBlock), 0, st, r[1]);
-    hipLaunchKernelGGL(k_rap1d<2>, dim3(blk[2]), dim3(kBlock), 0, st, r[2]);
+    if (zc) hipLaunchKernelGGL(k_rap1d<2>, dim3(blk[2]), dim3(kBlock), 0, st, r[2]);
+}
+
+// ---------------------------------------------------------------------------
+// z-line block Gauss-Seidel (boxes much thinner along z than across): one
+// thread per line of the colour; the couplings of a row to the other lines
+// go to the right-hand side with the current x (lines of one colour do not
+// couple), the line's tridiagonal block (offsets (0,0,-1), centre, (0,0,1))
+// is eliminated down the line and substituted back up.  Multipliers and
+// right-hand sides of the elimination sit in tmp, [k][line], so that the
+// threads of a wave touch consecutive addresses.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
+{
+    const LineArgs &A = lb.a[find_box(lb, blockIdx.x)];
+    const int cx = colour & 1, cy = colour >> 1;
+    const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2, nl = ncx * ncy;
+    const int t = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    if (t >= nl) return;
+    const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
+    const long long layer = (long long)A.nx * A.ny, N = A.n;
+    double *cp = A.tmp, *dp = A.tmp + (long long)A.nz * nl;
+    double cprev = 0.0, dprev = 0.0;
+    for (int k = 0; k < A.nz; k++) {
+        const long long n = i + (long long)A.nx * j + layer * k;
+        double rhs = A.b[n];
+#pragma unroll
+        for (int o = 0; o < 27; o++) {
+            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+            if (dx == 0 && dy == 0) continue;
+            const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny &&
+                            k + dz >= 0 && k + dz < A.nz;
+            if (ok) rhs -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
+        }
+        const double lo = k > 0 ? A.S[4 * N + n] : 0.0;            // offset (0,0,-1)
+        const double up = k < A.nz - 1 ? A.S[22 * N + n] : 0.0;    // offset (0,0,+1)
+        const double den = A.S[13 * N + n] - lo * cprev;
+        cprev = up / den;
+        dprev = (rhs - lo * dprev) / den;
+        cp[(long long)k * nl + t] = cprev;
+        dp[(long long)k * nl + t] = dprev;
+    }
+    double nxt = 0.0;
+    for (int k = A.nz - 1; k >= 0; k--) {
+        nxt = dp[(long long)k * nl + t] - (k < A.nz - 1 ? cp[(long long)k * nl + t] * nxt : 0.0);
+        A.x[i + (long long)A.nx * j + layer * k] = nxt;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_resid_full(LineBatch lb)
+{
+    const LineArgs &A = lb.a[find_box(lb, blockIdx.x)];
+    const int n = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    if (n >= A.n) return;
+    const int i = n % A.nx, t = n / A.nx, j = t % A.ny, k = t / A.ny;
+    const long long layer = (long long)A.nx * A.ny, N = A.n;
+    double acc = A.b[n];
+#pragma unroll
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny && k + dz >= 0 &&
+                        k + dz < A.nz;
+        if (ok) acc -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
+    }
+    A.r[n] = acc;
+}
+
+void launch_zline(LineBatch lb, int colour, hipStream_t st)
+{
+    int blk = 0;
+    for (int q = 0; q < lb.nbox; q++) {
+        LineArgs &A = lb.a[q];
+        const int cx = colour & 1, cy = colour >> 1;
+        const int nl = ((A.nx - cx + 1) / 2) * ((A.ny - cy + 1) / 2);
+        A.blk0 = blk;
+        blk += (nl + kBlock - 1) / kBlock;
+    }
+    if (blk) hipLaunchKernelGGL(k_zline, dim3(blk), dim3(kBlock), 0, st, lb, colour);
+}
+
+void launch_resid_full(LineBatch lb, hipStream_t st)
+{
+    int blk = 0;
+    for (int q = 0; q < lb.nbox; q++) {
+        lb.a[q].blk0 = blk;
+        blk += (lb.a[q].n + kBlock - 1) / kBlock;
+    }
+    if (blk) hipLaunchKernelGGL(k_resid_full, dim3(blk), dim3(kBlock), 0, st, lb);
 }
 
 // inverse diagonal and per-block maxima of the Gershgorin ratio sum|s_ij|/s_ii

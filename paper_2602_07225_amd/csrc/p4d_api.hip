@@ -78,7 +78,8 @@ struct p4d_ctx {
            *mm = nullptr, *omega = nullptr, *qbuf = nullptr;
     double *oms = nullptr;         // omega_j of the Schur complement (whatever the preconditioner)
     double *kdh = nullptr, *dch = nullptr;   // h * separate transport coefficients
-    double *meh = nullptr;         // eps_e h^3 / dt per element (when storage is set)
+    double *meh = nullptr;         // eps_e vol / dt per element (when storage is set)
+    double *ltmp = nullptr;        // z-line smoothing: elimination buffers, 2 Nm doubles
     int storage = 0;               // 1: g.meh points at meh
     int transport_set = 0;         // 1: kdh / dch hold caller coefficients
     int general = 0;               // 1: kdh / dch hold the transport coefficients
@@ -214,13 +215,32 @@ static void fill_geom(const p4d_problem_desc &d, Geom &g)
     g.dt = d.dt;
     g.chi = d.chi;
     g.tc = d.tc;
-    const double h3 = g.h * g.h * g.h;
-    g.mass_elec = d.eps_elec * h3 / d.dt;
-    g.mass_sep = d.eps_sep * h3 / d.dt;
+    const double hx = d.hxy[0] > 0.0 ? d.hxy[0] : g.h, hy = d.hxy[1] > 0.0 ? d.hxy[1] : g.h;
+    g.aniso = hx != g.h || hy != g.h;
+    g.vol = hx * hy * g.h;
+    g.mass_elec = d.eps_elec * g.vol / d.dt;
+    g.mass_sep = d.eps_sep * g.vol / d.dt;
+    if (!g.aniso) {
+        g.kw[0] = 1.0 / 3.0;
+        for (int p = 1; p < 8; p++) g.kw[p] = p == 1 || p == 2 || p == 4 ? 0.0 : 1.0 / 12.0;
+    } else {
+        const double w[3] = {hy / hx, hx / hy, hx * hy / (g.h * g.h)};
+        for (int p = 0; p < 8; p++) {
+            double k = 0.0;
+            for (int ax = 0; ax < 3; ax++) {
+                double v = (p >> ax) & 1 ? -1.0 : 1.0;
+                for (int q = 0; q < 3; q++)
+                    if (q != ax) v *= (p >> q) & 1 ? 1.0 / 6.0 : 1.0 / 3.0;
+                k += w[ax] * v;
+            }
+            g.kw[p] = p == 0 ? k : -k;
+        }
+    }
 }
 
 // level dims of the four multigrid boxes
-static void box_dims(const p4d_ctx *c, int b, int coarse_max, int *nlev, int dims[][3])
+// (z-line smoothing keeps z: coarsening in x and y only)
+static void box_dims(const p4d_ctx *c, int b, int coarse_max, int zline, int *nlev, int dims[][3])
 {
     const Geom &g = c->g;
     int nz = b == 0 ? g.na - 1 : (b == 1 ? g.nc : g.nz);
@@ -229,7 +249,8 @@ static void box_dims(const p4d_ctx *c, int b, int coarse_max, int *nlev, int dim
     for (;;) {
         dims[L][0] = d0[0]; dims[L][1] = d0[1]; dims[L][2] = d0[2];
         const long long n = (long long)d0[0] * d0[1] * d0[2];
-        const int cx = coarse_n_h(d0[0]), cy = coarse_n_h(d0[1]), cz = coarse_n_h(d0[2]);
+        const int cx = coarse_n_h(d0[0]), cy = coarse_n_h(d0[1]);
+        const int cz = zline ? d0[2] : coarse_n_h(d0[2]);
         L++;
         if (n <= coarse_max || (long long)cx * cy * cz == n || L == kMaxLevels) break;
         d0[0] = cx; d0[1] = cy; d0[2] = cz;
@@ -275,6 +296,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->ydev = (double *)take(8 * 128);
     c->scal = (double *)take(8 * 128);
     const long long Nm = g.Nm;
+    c->ltmp = o.smoother == P4D_SMOOTH_ZLINE ? (double *)take(16 * (size_t)Nm) : nullptr;
     c->b0 = take(ts * Nm);
     c->x0a = take(8 * Nm);          // iterates are FP64 in every mode
     c->x0b = take(8 * Nm);
@@ -287,7 +309,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     for (int b = 0; b < 4; b++) {
         Box &B = c->box[b];
         int dims[kMaxLevels][3];
-        box_dims(c, b, o.coarse_max, &B.nlev, dims);
+        box_dims(c, b, o.coarse_max, o.smoother == P4D_SMOOTH_ZLINE, &B.nlev, dims);
         B.k0 = b == 0 ? 1 : (b == 1 ? g.na + g.ns : 0);
         B.ek_lo = b == 0 ? 0 : (b == 1 ? g.na + g.ns : 0);
         B.ek_hi = b == 0 ? g.na - 2 : g.nz - 2;
@@ -304,7 +326,9 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
                 };
                 L.b = at(c->b0, ts); L.xa = at(c->x0a, 8); L.xb = at(c->x0b, 8);
                 L.d = at(c->d0, ts); L.r = at(c->r0, ts); L.invd = at(c->invd0, ts);
-                L.S64 = nullptr; L.S = nullptr;
+                L.S = nullptr;
+                // z-line smoothing reads the assembled level-0 stencil
+                L.S64 = o.smoother == P4D_SMOOTH_ZLINE ? (double *)take(8 * 27 * (size_t)L.n) : nullptr;
             } else {
                 L.S64 = (double *)take(8 * 27 * (size_t)L.n);
                 L.S = take(ts * 14 * (size_t)L.n);   // upper half, difference form
@@ -374,6 +398,12 @@ static bool opts_valid(const p4d_solve_opts &o, std::string &why)
     if (o.cheb_degree < 1 || o.cheb_degree > 4) { why = "cheb_degree must be in 1..4"; return false; }
     if (o.coarse_max < 8 || o.coarse_max > 1024) { why = "coarse_max must be in 8..1024"; return false; }
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) { why = "rtol must be in (0,1)"; return false; }
+    if (o.smoother != P4D_SMOOTH_CHEB && o.smoother != P4D_SMOOTH_ZLINE) { why = "smoother"; return false; }
+    if (o.smoother == P4D_SMOOTH_ZLINE &&
+        (o.pc_prec != P4D_FP64 || o.pc == P4D_PC_BGS || o.krylov != P4D_KRYLOV_FULL)) {
+        why = "z-line smoothing needs an FP64 preconditioner, pc SCHUR or BJ and the full Krylov space";
+        return false;
+    }
     return true;
 }
 
@@ -678,6 +708,100 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
     for (int t = 1; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 1, st);
 }
 
+// One V-cycle at level l with z-line smoothing (FP64; levels keep their z
+// extent): x = 0, cheb_degree passes of colours 0..3, residual, restriction,
+// the coarser level, prolongation, cheb_degree passes of colours 3..0.  The
+// iterate of every level stays in its xa buffer.
+static void vcycle_line(p4d_ctx *c, int l, hipStream_t st)
+{
+    int act[4], na = 0, crs[4], nc = 0;
+    for (int b = 0; b < 4; b++) {
+        if (!((c->box_mask >> b) & 1)) continue;
+        if (c->box[b].nlev - 1 > l) act[na++] = b;
+        else if (c->box[b].nlev - 1 == l) crs[nc++] = b;
+    }
+    if (nc) {
+        CoarseBatch<double> cb{};
+        cb.nbox = nc;
+        for (int q = 0; q < nc; q++) {
+            Level &L = c->box[crs[q]].lev[l];
+            cb.a[q].n = L.n;
+            cb.a[q].Ainv = L.Ainv;
+            cb.a[q].b = (const double *)L.b;
+            cb.a[q].x = (double *)L.xa;
+        }
+        launch_coarse<double>(cb, st);
+    }
+    if (!na) return;
+    LineBatch lb{};
+    lb.nbox = na;
+    double bytes = 0.0;
+    for (int q = 0; q < na; q++) {
+        Box &B = c->box[act[q]];
+        Level &L = B.lev[l];
+        LineArgs &A = lb.a[q];
+        A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
+        A.S = L.S64;
+        A.b = (const double *)L.b;
+        A.x = (double *)L.xa;
+        A.r = (double *)L.r;
+        A.tmp = c->ltmp + 2 * B.off;
+        hipMemsetAsync(A.x, 0, 8 * (size_t)L.n, st);
+        // stencil, b, x read and written, elimination buffers written and read
+        bytes += (27.0 * 8 + 8 + 16 + 32) * L.n;
+    }
+    const int deg = c->pc.cheb_degree;
+    auto pass = [&](bool backward) {
+        if (l == 0) {   // level-0 passes are timed as the level-0 smoother class
+            ProfScope ps(c->prof, P4D_K_SMOOTH0, bytes, st);
+            for (int q = 0; q < 4; q++) launch_zline(lb, backward ? 3 - q : q, st);
+        } else {
+            for (int q = 0; q < 4; q++) launch_zline(lb, backward ? 3 - q : q, st);
+        }
+    };
+    for (int t = 0; t < deg; t++) pass(false);
+    launch_resid_full(lb, st);
+    {
+        TransferBatch<double> tb{};
+        tb.nbox = na;
+        int blk = 0;
+        for (int q = 0; q < na; q++) {
+            Box &B = c->box[act[q]];
+            Level &F = B.lev[l], &Cl = B.lev[l + 1];
+            TransferArgs<double> &A = tb.a[q];
+            A.fx = F.nx; A.fy = F.ny; A.fz = F.nz;
+            A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz;
+            A.blk0 = blk;
+            blk += (Cl.n + kBlock - 1) / kBlock;
+            A.rf = (const double *)F.r;
+            A.bc = (double *)Cl.b;
+            A.xc1 = nullptr;
+            A.invdc = nullptr;
+            A.c2c = 0.0;
+        }
+        launch_restrict<double>(tb, blk, st);
+    }
+    vcycle_line(c, l + 1, st);
+    {
+        TransferBatch<double> tb{};
+        tb.nbox = na;
+        int blk = 0;
+        for (int q = 0; q < na; q++) {
+            Box &B = c->box[act[q]];
+            Level &F = B.lev[l], &Cl = B.lev[l + 1];
+            TransferArgs<double> &A = tb.a[q];
+            A.fx = F.nx; A.fy = F.ny; A.fz = F.nz;
+            A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz;
+            A.blk0 = blk;
+            blk += (F.n + kBlock - 1) / kBlock;
+            A.xc = (const double *)Cl.xa;
+            A.xf = (double *)F.xa;
+        }
+        launch_prolong<double>(tb, blk, st);
+    }
+    for (int t = 0; t < deg; t++) pass(true);
+}
+
 // fixed part of the particle-block arguments
 static RadArgs rad_args(const p4d_ctx *c)
 {
@@ -708,7 +832,8 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
     }
     VState<T> vs{};
     for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
-    vcycle_level<T>(c, vs, 0, st);
+    if (c->pc.smoother == P4D_SMOOTH_ZLINE) vcycle_line(c, 0, st);   // (FP64 only)
+    else vcycle_level<T>(c, vs, 0, st);
     // each box's final level-0 iterate (the two buffers alternate)
     for (int b = 0; b < 4; b++) R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
     if (c->rec) {
@@ -820,8 +945,10 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     // scratch: FP64 stencils of level 0, FP64 dcorr / inverse diagonal, dense
     char *sp = c->scratch;
     auto take = [&](size_t bytes) { char *p = sp; sp += align_up(bytes); return p; };
+    const int zline = c->pc.smoother == P4D_SMOOTH_ZLINE;
     double *S0[4];
-    for (int b = 0; b < 4; b++) S0[b] = (double *)take(8 * 27 * (size_t)c->box[b].lev[0].n);
+    for (int b = 0; b < 4; b++)
+        S0[b] = zline ? c->box[b].lev[0].S64 : (double *)take(8 * 27 * (size_t)c->box[b].lev[0].n);
     double *dc64 = (double *)take(8 * (size_t)g.Nm);
     double *id64 = (double *)take(8 * (size_t)g.Nm);
     size_t n1max = 0;
@@ -859,7 +986,7 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                                   raptmp + (size_t)nj * rapmax};
                 nj++;
             }
-            launch_rap(jobs, nj, st);
+            launch_rap(jobs, nj, !zline, st);
         }
         for (int b = 0; b < 4; b++) {
             Box &B = c->box[b];
@@ -1224,6 +1351,7 @@ void p4d_default_opts(p4d_solve_opts *o)
     o->rtol = 1e-8;
     o->bgs_order = 1 | (3 << 2) | (0 << 4) | (2 << 6);   // (phi_e, c_s, phi_s, c_e)
     o->krylov = P4D_KRYLOV_FULL;
+    o->smoother = P4D_SMOOTH_CHEB;
 }
 
 const char *p4d_status_string(p4d_status s)
@@ -1260,6 +1388,8 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
         return P4D_ERR_INVALID_ARG;
     if (!(d->length >= 0.0) || !std::isfinite(d->length) || !(d->lambda_el[0] >= 0.0) ||
         !(d->lambda_el[1] >= 0.0) || !std::isfinite(d->lambda_el[0]) || !std::isfinite(d->lambda_el[1]))
+        return P4D_ERR_INVALID_ARG;
+    if (!(d->hxy[0] >= 0.0) || !(d->hxy[1] >= 0.0) || !std::isfinite(d->hxy[0]) || !std::isfinite(d->hxy[1]))
         return P4D_ERR_INVALID_ARG;
     if ((long long)d->nx * d->ny * d->nz > (1LL << 30)) return P4D_ERR_INVALID_ARG;
     p4d_ctx *c = new p4d_ctx();
@@ -1403,6 +1533,8 @@ static p4d_status ensure_layout(p4d_ctx *c, const p4d_solve_opts &o)
     return P4D_OK;
 }
 
+static p4d_status refresh_general(p4d_ctx *c, hipStream_t st);
+
 p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, const double *g,
                       const double *s, const double *e, void *stream)
 {
@@ -1423,17 +1555,22 @@ p4d_status p4d_upload(p4d_ctx *c, const double *sigma, const double *kappa, cons
     HIPCHK(c, hipGetLastError());
     // the host copy of the radial tables must outlive the async copy
     HIPCHK(c, hipStreamSynchronize(st));
+    if (c->g.aniso) {
+        p4d_status rs = refresh_general(c, st);
+        if (rs != P4D_OK) return rs;
+    }
     c->uploaded = 1;
     c->pc_ready = 0;
     return P4D_OK;
 }
 
 // The per-node operator with its own element arrays (GEN) runs when the
-// caller set transport coefficients or a per-element storage; for storage
-// alone kdh / dch take the defaults chi h kappa and h kappa.
+// caller set transport coefficients or a per-element storage, or the
+// elements are boxes; otherwise kdh / dch take the defaults chi h kappa and
+// h kappa.
 static p4d_status refresh_general(p4d_ctx *c, hipStream_t st)
 {
-    const bool gen = c->transport_set || c->storage;
+    const bool gen = c->transport_set || c->storage || c->g.aniso;
     if (gen && !c->transport_set) {
         launch_scale_elem(c->g, nullptr, c->g.chi, c->kaph, c->kdh, st);
         launch_scale_elem(c->g, nullptr, 1.0, c->kaph, c->dch, st);
@@ -1476,7 +1613,7 @@ p4d_status p4d_set_storage(p4d_ctx *c, const double *eps_e, void *stream)
         c->g.meh = nullptr;
         return refresh_general(c, st);
     }
-    launch_scale_elem(c->g, eps_e, c->g.h * c->g.h * c->g.h / c->g.dt, nullptr, c->meh, st);
+    launch_scale_elem(c->g, eps_e, c->g.vol / c->g.dt, nullptr, c->meh, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->storage = 1;
@@ -1512,14 +1649,18 @@ p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
     std::string why;
     if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    if (o.pc == P4D_PC_BGS && c->g.aniso)
+        return fail(c, P4D_ERR_INVALID_ARG, "block Gauss-Seidel needs cube elements");
     // keep the Krylov sizing of the layout (it is set by the workspace size
     // the caller asked for); the preconditioner part must match o
     p4d_solve_opts lay = c->ws_opts;
     lay.pc_prec = o.pc_prec;
     lay.coarse_max = o.coarse_max;
+    lay.smoother = o.smoother;
     if (o.restart > lay.restart) lay.restart = o.restart;
     const bool relayout = lay.pc_prec != c->ws_opts.pc_prec || lay.coarse_max != c->ws_opts.coarse_max ||
-                          lay.restart != c->ws_opts.restart || lay.z_fp32 != c->ws_opts.z_fp32;
+                          lay.restart != c->ws_opts.restart || lay.z_fp32 != c->ws_opts.z_fp32 ||
+                          lay.smoother != c->ws_opts.smoother;
     if (relayout) {
         // coefficient arrays sit at the start of every layout, so they
         // survive a change of the preconditioner part
@@ -1577,7 +1718,8 @@ static p4d_status solve_common(p4d_ctx *c, int transpose, const double *b, doubl
     std::string why;
     if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
     if (o.pc != c->pc.pc || o.pc_prec != c->pc.pc_prec || o.cheb_degree != c->pc.cheb_degree ||
-        o.coarse_max != c->pc.coarse_max || (o.pc == P4D_PC_BGS && o.bgs_order != c->pc.bgs_order))
+        o.coarse_max != c->pc.coarse_max || o.smoother != c->pc.smoother ||
+        (o.pc == P4D_PC_BGS && o.bgs_order != c->pc.bgs_order))
         return fail(c, P4D_ERR_STATE, "preconditioner options differ from the last setup");
     if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
         return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
@@ -1817,6 +1959,7 @@ p4d_status p4d_param_gradient(p4d_ctx *c, const double *x, const double *lam, do
 {
     if (!c || !x || !lam || !dsigma || !dDs) return P4D_ERR_INVALID_ARG;
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
+    if (c->g.aniso) return fail(c, P4D_ERR_INVALID_ARG, "parameter gradients need cube elements");
     hipStream_t st = (hipStream_t)stream;
     launch_grad(c->g, c->tabs, x, lam, dsigma, c->red, st);
     const long long n = c->g.nelem > c->g.ne ? c->g.nelem : c->g.ne;
@@ -2531,6 +2674,8 @@ p4d_status p4d_batch_create(const p4d_problem_desc *descs, int32_t ncells, p4d_b
     *out = nullptr;
     p4d_batch *B = new p4d_batch();
     B->n = ncells;
+    for (int i = 0; i < ncells; i++)   // batches run the cube-element kernels
+        if (descs[i].hxy[0] != 0.0 || descs[i].hxy[1] != 0.0) return P4D_ERR_INVALID_ARG;
     for (int i = 0; i < ncells; i++) {
         p4d_ctx *c = nullptr;
         const p4d_status s = p4d_create(&descs[i], &c);

@@ -84,6 +84,30 @@ __device__ inline R q1_stiff(const R c[8], const R X[27])
     return acc * R(1.0 / 12.0);
 }
 
+// The same for box elements: kw[p] weighs the difference to the corner that
+// differs in the axes of bit pattern p (kw[0], the diagonal, is not used:
+// rows sum to zero).  With kw = {., 0, 0, 1/12, 0, 1/12, 1/12, 1/12} it is
+// q1_stiff.
+template <typename R>
+__device__ inline R q1_stiff_w(const R c[8], const R X[27], const double kw[8])
+{
+    R acc = R(0);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        const int a = (1 - ex) | ((1 - ey) << 1) | ((1 - ez) << 2);
+        R part = R(0);
+#pragma unroll
+        for (int bb = 0; bb < 8; bb++) {
+            if (bb == a) continue;
+            part += R(kw[a ^ bb]) * (X[13] - X[nb_index(ex - 1 + (bb & 1), ey - 1 + ((bb >> 1) & 1),
+                                                      ez - 1 + ((bb >> 2) & 1))]);
+        }
+        acc += c[e] * part;
+    }
+    return acc;
+}
+
 // Reference mass on the unit cube: (8, 4, 2, 1)/216 by the number of
 // differing coordinates.
 template <typename R>

@@ -18,8 +18,15 @@ struct Geom {
     long long nnode, nelem, nea, nec, ne;
     long long off_pe, off_ce, off_cs[2], N, Nm;
     double h, dt, chi, tc;
-    double mass_elec, mass_sep;      // eps * h^3 / dt per element material
-    const double *meh = nullptr;     // eps_e * h^3 / dt per element (device), or by material
+    double mass_elec, mass_sep;      // eps * vol / dt per element material
+    const double *meh = nullptr;     // eps_e * vol / dt per element (device), or by material
+    // box elements (edges hx, hy along x, y; h along z): vol = hx hy h, and
+    // the Q1 stiffness over h is sum_d (vol / (h_d^2 h)) Khat_d; kw[0] is its
+    // diagonal, kw[p] minus its entry between corners differing in the axes
+    // of bit pattern p (isotropic: 1/3, and 1/12 for two or three axes)
+    int aniso = 0;
+    double vol = 0.0;
+    double kw[8] = {};
 };
 
 __host__ __device__ inline int elem_mat(const Geom &g, int kk)
@@ -185,7 +192,28 @@ struct RapJob {
     double *Sc;
     double *tmp;
 };
-void launch_rap(const RapJob *jobs, int njobs, hipStream_t st);
+// zc = 0: z is not coarsened (P_z = I), the x and y passes only
+void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st);
+
+// z-line smoothing of up to four boxes of one level (FP64, full stencils
+// [27][n]): block Gauss-Seidel over the lines of one colour (x parity
+// colour & 1, y parity colour >> 1), in place in x; tmp holds 2 n doubles
+// (the elimination's multipliers and right-hand sides)
+struct LineArgs {
+    int nx, ny, nz, n, blk0;
+    const double *S;
+    const double *b;
+    double *x;
+    double *r;
+    double *tmp;
+};
+struct LineBatch {
+    int nbox;
+    LineArgs a[4];
+};
+void launch_zline(LineBatch lb, int colour, hipStream_t st);
+// r = b - S x on the same boxes
+void launch_resid_full(LineBatch lb, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
 void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);

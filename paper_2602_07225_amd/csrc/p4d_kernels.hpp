@@ -74,8 +74,18 @@ __host__ __device__ inline int smooth0_box_tiles(int nx, int ny, int nz, int TX,
     return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) * ((nz + CZ - 1) / CZ);
 }
 
-// MEH: the storage of the mass box comes per element from g.meh (a separate
-// instantiation keeps the per-material one free of its registers)
+// Q1 stiffness at a node: box-element weights g.kw in the general (GEN)
+// instantiations, the cube stencil otherwise
+template <bool GEN, typename R>
+__device__ inline R stiff_of(const Geom &g, const R c[8], const R X[27])
+{
+    if (GEN) return q1_stiff_w(c, X, g.kw);
+    return q1_stiff(c, X);
+}
+
+// MEH: the storage of the mass box per element (g.meh) and the box-element
+// stiffness weights (a separate instantiation keeps the per-material cube
+// one free of their registers)
 template <typename T, bool RESID_ONLY, bool MEH = false>
 __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int tile, int TX, int CZ,
                                     Smooth0Lds &L)
@@ -189,13 +199,14 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
                     const int ei = i - 1 + ex, ej = j - 1 + ey;
                     const bool ok = A.mass && ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
                                     ek >= A.ek_lo && ek <= A.ek_hi;
-                    cM[e] = ok ? g.meh[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+                    cM[e] = ok ? elem_storage(g, ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek), ek)
+                               : 0.0;
                 } else {
                     cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep)
                                                      : 0.0;
                 }
             }
-            double Sx = q1_stiff(cK, X) + dcn * X[13];
+            double Sx = stiff_of<MEH>(g, cK, X) + dcn * X[13];
             if (A.mass) Sx += q1_mass(cM, X);
             const double r = bn - Sx;
             if (RESID_ONLY) {
@@ -273,7 +284,7 @@ __device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
     double wi[3], wj[3], wk[3];
     const int ni = fine_of(A.fx, I, fi, wi);
     const int nj = fine_of(A.fy, J, fj, wj);
-    const int nk = fine_of(A.fz, K, fk, wk);
+    const int nk = fine_of(A.cz == A.fz ? 1 : A.fz, K, fk, wk);   // (z kept: identity)
     // fixed trip counts, so that the index arrays stay in registers
     double acc = 0.0;
 #pragma unroll
@@ -308,7 +319,7 @@ __device__ inline void prolong_block(const TransferArgs<T> &A, int blk)
     double wi[2], wj[2], wk[2];
     const int ni = coarse_of(A.fx, i, Ci, wi);
     const int nj = coarse_of(A.fy, j, Cj, wj);
-    const int nk = coarse_of(A.fz, k, Ck, wk);
+    const int nk = coarse_of(A.cz == A.fz ? 1 : A.fz, k, Ck, wk);
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
@@ -681,7 +692,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
     double X[27];
     P.Kx = 0.0;
     load_nb(g, x + g.off_pe, n, i, j, k, X);
-    P.Kpe = q1_stiff(ck, X);
+    P.Kpe = stiff_of<GEN>(g, ck, X);
     P.xpe = X[13];
     if (GEN && TRANS) {
         double cx[8];
@@ -692,7 +703,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
                             ek < g.nz - 1;
             cx[e] = ok ? O.kdh[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
         }
-        P.Kx = q1_stiff(cx, X);
+        P.Kx = stiff_of<GEN>(g, cx, X);
     }
     load_nb(g, x + g.off_ce, n, i, j, k, X);
     if (GEN) {
@@ -706,10 +717,10 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
             cd[e] = ok ? O.dch[id] : 0.0;
             cx[e] = (ok && !TRANS) ? O.kdh[id] : 0.0;
         }
-        P.Kce = q1_stiff(cd, X);
-        if (!TRANS) P.Kx = q1_stiff(cx, X);
+        P.Kce = stiff_of<GEN>(g, cd, X);
+        if (!TRANS) P.Kx = stiff_of<GEN>(g, cx, X);
     } else {
-        P.Kce = q1_stiff(ck, X);
+        P.Kce = stiff_of<GEN>(g, ck, X);
     }
     P.Mce = q1_mass(cm, X);
     P.xce = X[13];
@@ -729,7 +740,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
                             (k + dz >= klo) && (k + dz <= khi) && (k + dz != 0);
             X[o] = ok ? ldx(x + je + dx + (long long)g.nx * (dy + (long long)g.ny * dz)) : 0.0;
         }
-        P.Kps = q1_stiff(cs, X);
+        P.Kps = stiff_of<GEN>(g, cs, X);
         P.xpsc = X[13];
     }
     return operator_finish<TX, NRMAX, TRANS, RESID, GEN>(g, O, n, i, j, k, P);

@@ -15,13 +15,15 @@ class P4DSolver:
     electrode node), as numpy arrays or torch tensors."""
 
     def __init__(self, prob, restart: int = 30, z_fp32: bool = False, pc_prec: int = L.P4D_FP64,
-                 coarse_max: int = 512, device: str = "cuda"):
+                 coarse_max: int = 512, device: str = "cuda", smoother: int = L.P4D_SMOOTH_CHEB):
         self.device = torch.device(device)
         self.desc = L.desc_from(prob)
         self.ctx = L.p4d_create(self.desc)
         self.N, self.offsets, self.n_elem, self.n_e = L.p4d_vector_size(self.ctx)
+        # the workspace is laid out for these options (the multigrid hierarchy
+        # depends on the precision, coarse size and smoother)
         self.ws_opts = L.default_opts(restart=restart, z_fp32=int(z_fp32), pc_prec=pc_prec,
-                                      coarse_max=coarse_max)
+                                      coarse_max=coarse_max, smoother=smoother)
         nbytes = L.p4d_workspace_size(self.ctx, self.ws_opts)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)

@@ -1,0 +1,109 @@
+"""Box elements much thinner through the cell than along it (the flattened
+jelly roll of Case III, Sec. 5) and the z-line multigrid on the GPU against
+the oracle: operator, preconditioners with Chebyshev and z-line smoothing,
+solves, and the options that do not apply to box elements."""
+import numpy as np
+import pytest
+
+import oracle as O
+import p4d_inputs as pi
+from tests.gpu_util import field_errors, rel, say, solver_for, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def flat(nx=37, ny=19, nz=13, nr=(5, 7), aspect=(40.0, 30.0), seed=61):
+    """Elements aspect[0] (x) and aspect[1] (y) times longer than thick (z);
+    ragged tiles in x and y."""
+    p = pi.make_custom(nx, ny, nz, nr, seed=seed, sigma_log=0.7, corr_cells=3.0)
+    h = p.h
+    return p.with_(hxy=(aspect[0] * h, aspect[1] * h))
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_box_operator_parity(transpose):
+    p = flat()
+    x = np.random.default_rng(1).standard_normal(p.N)
+    y = to_np(solver_for(p).apply(to_dev(x), transpose))
+    ref = O.Oracle(p).apply(x, transpose)
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref))
+    say(f"box operator transpose={transpose}: max rel {err:.1e}")
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("smoother", [O.SMOOTH_CHEB, O.SMOOTH_ZLINE])
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_box_preconditioner_parity(smoother, pc, transpose):
+    p = flat()
+    orc = O.Oracle(p).setup(pc=pc, smoother=smoother)
+    s = solver_for(p, smoother=smoother).setup(pc=pc, smoother=smoother)
+    r = np.random.default_rng(2).standard_normal(p.N)
+    errs = field_errors(p, to_np(s.apply_pc(to_dev(r), transpose)), orc.apply_pc(r, transpose))
+    say(f"  box pc={pc} smoother={smoother} transpose={transpose}",
+        {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-10
+
+
+def test_zline_preconditioner_on_cubes():
+    """z-line smoothing is also defined on cube elements."""
+    p = pi.make_custom(21, 11, 17, (6, 5), seed=62, sigma_log=1.0, corr_cells=3.0)
+    orc = O.Oracle(p).setup(smoother=O.SMOOTH_ZLINE)
+    s = solver_for(p, smoother=O.SMOOTH_ZLINE).setup(smoother=O.SMOOTH_ZLINE)
+    r = np.random.default_rng(3).standard_normal(p.N)
+    errs = field_errors(p, to_np(s.apply_pc(to_dev(r))), orc.apply_pc(r))
+    assert max(errs.values()) <= 1e-10
+
+
+@pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ])
+def test_zline_solve_parity(pc):
+    p = flat()
+    orc = O.Oracle(p).setup(pc=pc, smoother=O.SMOOTH_ZLINE, rtol=1e-8, cgs2=pc != O.PC_SCHUR,
+                            maxit=3000)
+    xo, io = orc.solve(p.b)
+    s = solver_for(p, smoother=O.SMOOTH_ZLINE).setup(pc=pc, smoother=O.SMOOTH_ZLINE, rtol=1e-8,
+                                                     cgs2=int(pc != O.PC_SCHUR), maxit=3000)
+    x, info = s.solve(to_dev(p.b))
+    x = to_np(x)
+    errs = field_errors(p, x, xo)
+    say(f"  z-line pc={pc} iters gpu={info.iters} oracle={io.iters}",
+        {k: f"{v:.1e}" for k, v in errs.items()})
+    assert info.status == 0 and io.status == 0
+    assert abs(info.iters - io.iters) <= 2
+    assert max(errs.values()) <= 1e-6
+    assert rel(orc.apply(x), p.b) <= 1.0001e-8
+
+
+def test_zline_is_robust_where_point_smoothing_stalls():
+    """Iteration counts reported (not pinned): the point-smoothed hierarchy
+    needs many times more iterations on these flat elements."""
+    p = flat()
+    its = {}
+    for sm in (O.SMOOTH_CHEB, O.SMOOTH_ZLINE):
+        s = solver_for(p, smoother=sm).setup(smoother=sm, rtol=1e-8, maxit=5000)
+        x, info = s.solve(to_dev(p.b))
+        assert info.status == 0
+        its[sm] = info.iters
+    say(f"  iterations point / z-line: {its}")
+    assert its[O.SMOOTH_ZLINE] * 3 <= its[O.SMOOTH_CHEB]
+
+
+def test_box_element_option_errors():
+    from paper_2602_07225_amd import P4DError, _lib
+    p = flat(nx=9, ny=7)
+    s = solver_for(p, smoother=O.SMOOTH_ZLINE)
+    for kw in (dict(pc=O.PC_BGS),
+               dict(smoother=O.SMOOTH_ZLINE, pc_prec=_lib.P4D_FP32),
+               dict(smoother=O.SMOOTH_ZLINE, pc=O.PC_BGS)):
+        with pytest.raises(P4DError) as e:
+            s.setup(**kw)
+        assert e.value.status == _lib.P4D_ERR_INVALID_ARG
+    s.setup()
+    with pytest.raises(P4DError):
+        s.solve(to_dev(p.b), krylov=_lib.P4D_KRYLOV_SCHUR)
+    x = to_dev(np.ones(p.N))
+    with pytest.raises(P4DError):
+        s.gradient(x, x)
+    with pytest.raises(P4DError):
+        from paper_2602_07225_amd import P4DBatch
+        P4DBatch([p, p])
