@@ -213,6 +213,54 @@ def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False):
     return out
 
 
+def bench_case3(steps=2, warmup=1):
+    """Case III-like flattened roll (the paper's element edges along the
+    roll and the height, 60 elements through the 120 um stack, 1801 x 86 x
+    61 nodes, N_r = 10): FGMRES(30) to 1e-8 with the SCHUR preconditioner and
+    z-line multigrid.  Beside it, a 225 x 11-element section of the roll
+    solved with both smoothers (the point-smoothed one capped at 1000
+    iterations)."""
+    import torch
+    import p4d_inputs as pi
+    from paper_2602_07225_amd import P4DSolver
+    from paper_2602_07225_amd import _lib as L
+    p = pi.make_case3_like()
+    zl = dict(pc=L.P4D_PC_SCHUR, pc_prec=L.P4D_FP64, rtol=1e-8, restart=30,
+              smoother=L.P4D_SMOOTH_ZLINE, coarse_max=64, cheb_degree=1)
+    s = P4DSolver(p, smoother=L.P4D_SMOOTH_ZLINE, coarse_max=64)
+    b = torch.as_tensor(p.b, device="cuda")
+    t0 = time.perf_counter()
+    s.setup(**zl)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t0)
+    x, info, iters, t, prof = timed_steps(s, b, zl, steps, warmup, profile_mask=(1 << L.P4D_K_SMOOTH0))
+    out = {"nodes": [p.nx, p.ny, p.nz], "nr": list(p.nr), "dof": p.N,
+           "element_aspect": [p.hxy[0] / p.h, p.hxy[1] / p.h], "setup_ms": setup_ms,
+           "sweeps_per_side": 1, "ms_per_solve": 1e3 * t / steps, "iters_per_solve": iters / steps,
+           "DOF_iter_per_s": p.N * iters / t, "relres_true": info.relres_true,
+           "zline_level0_pass": prof.get("smooth0")}
+    _, _, it2, t2, _ = timed_steps(s, b, dict(zl, cheb_degree=2), steps, 1)
+    out["two_sweeps_per_side"] = {"ms_per_solve": 1e3 * t2 / steps, "iters_per_solve": it2 / steps}
+    del s, x, b
+    torch.cuda.empty_cache()
+    q = pi.make_case3_like(nx=226, ny=12)
+    sec = {"nodes": [q.nx, q.ny, q.nz], "dof": q.N}
+    bq = torch.as_tensor(q.b, device="cuda")
+    for name, sm in (("zline", L.P4D_SMOOTH_ZLINE), ("chebyshev", L.P4D_SMOOTH_CHEB)):
+        o = dict(zl, smoother=sm, maxit=1000, cheb_degree=2)
+        sq = P4DSolver(q, smoother=sm, coarse_max=64)
+        sq.setup(**o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = sq.solve(bq)
+        torch.cuda.synchronize()
+        sec[name] = {"iters": inf.iters, "status": inf.status, "relres_true": inf.relres_true,
+                     "ms": 1e3 * (time.perf_counter() - t0)}
+        del sq
+    out["section_225x11"] = sec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +278,8 @@ def main():
                          "of the particle blocks (prints its JSON fields; for profiling)")
     ap.add_argument("--newton-only", action="store_true",
                     help="only the Newton steps of the physical cube cell (prints its JSON fields)")
+    ap.add_argument("--case3-only", action="store_true",
+                    help="only the Case III-like flattened roll with z-line multigrid (prints its JSON)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 512 MiB device copy first (a reference of known size "
                          "for hardware byte counters)")
@@ -250,6 +300,9 @@ def main():
     torch.cuda.set_device(0)
     if args.batch_only:
         print(json.dumps({"C4_batch_64_cells": bench_batch(args.steps)}), flush=True)
+        return
+    if args.case3_only:
+        print(json.dumps({"case3_like_roll": bench_case3()}), flush=True)
         return
     if args.newton_only:
         print(json.dumps({"newton_case_I_cube": bench_newton(),
@@ -341,7 +394,8 @@ def main():
                                      "speedup_vs_fp64": t / t32}
         log(f"[bench] FP32-PC C2: {1e3 * t32 / args.steps:.2f} ms/step, {it32 / args.steps:.1f} it")
         # block-Jacobi preconditioner (the paper's eq. PJ) on the same input
-        bj = dict(fp64, pc=L.P4D_PC_BJ, cgs2=1)
+        # (Chebyshev degree 2: BJ and BGS take fewer iterations with it)
+        bj = dict(fp64, pc=L.P4D_PC_BJ, cgs2=1, cheb_degree=2)
         try:
             _, ibj, itbj, tbj, _ = timed_steps(s, b, bj, 2, 1)
             extras["block_jacobi_C2"] = {"ms_per_step": 1e3 * tbj / 2, "iters_per_solve": itbj / 2}
@@ -350,7 +404,7 @@ def main():
             extras["block_jacobi_C2"] = {"error": str(ex)}
         # block Gauss-Seidel (eq. PGS), the paper's ordering, both precisions;
         # then all 24 orderings
-        bgs = dict(fp64, pc=L.P4D_PC_BGS, bgs_order=L.P4D_BGS_PAPER_ORDER, cgs2=1)
+        bgs = dict(fp64, pc=L.P4D_PC_BGS, bgs_order=L.P4D_BGS_PAPER_ORDER, cgs2=1, cheb_degree=2)
         try:
             _, _, itg, tg, _ = timed_steps(s, b, bgs, 2, 1)
             _, _, itg32, tg32, _ = timed_steps(s, b, dict(bgs, pc_prec=L.P4D_FP32), 2, 1)
@@ -383,7 +437,7 @@ def main():
         log(f"[bench] Schur-Krylov C2: fp64 {1e3 * ts64 / args.steps:.2f} ms ({its64 / args.steps:.0f} it), "
             f"fp32-PC {1e3 * ts32 / args.steps:.2f} ms ({its32 / args.steps:.0f} it)")
         del xs64, xs32
-        extras["bgs_orderings_C2"] = bgs_sweep(s, b, fp64)
+        extras["bgs_orderings_C2"] = bgs_sweep(s, b, dict(fp64, cheb_degree=2))
         log(f"[bench] BGS orderings C2: best {extras['bgs_orderings_C2']['best']}, "
             f"worst {extras['bgs_orderings_C2']['worst']}")
         # lognormal cube, both precisions
@@ -407,7 +461,7 @@ def main():
                              "iters_per_solve": itc32 / args.steps}}
         log(f"[bench] Schur-Krylov C3: fp64 {1e3 * tc3 / args.steps:.2f} ms, "
             f"fp32-PC {1e3 * tc332 / args.steps:.2f} ms")
-        extras["bgs_orderings_C3"] = bgs_sweep(s3, b3, fp64)
+        extras["bgs_orderings_C3"] = bgs_sweep(s3, b3, dict(fp64, cheb_degree=2))
         log(f"[bench] BGS orderings C3: best {extras['bgs_orderings_C3']['best']}, "
             f"worst {extras['bgs_orderings_C3']['worst']}")
         del s3
@@ -471,6 +525,14 @@ def main():
 
     if not args.no_extras:
         extras["C4_batch_64_cells"] = bench_batch(args.steps)
+        try:
+            extras["case3_like_roll"] = e = bench_case3()
+            log(f"[bench] Case III-like roll N={e['dof']}: z-line {e['ms_per_solve']:.1f} ms/solve, "
+                f"{e['iters_per_solve']:.1f} it; section: z-line {e['section_225x11']['zline']['iters']} it, "
+                f"point {e['section_225x11']['chebyshev']['iters']} it "
+                f"(status {e['section_225x11']['chebyshev']['status']})")
+        except RuntimeError as ex:
+            extras["case3_like_roll"] = {"error": str(ex)}
         for key, het in (("newton_case_I_cube", False), ("newton_case_II_cube", True)):
             try:
                 extras[key] = e = bench_newton(hetero=het)

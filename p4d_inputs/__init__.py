@@ -232,6 +232,34 @@ def make_custom(nx: int, ny: int, nz: int, nr=(10, 10), *, seed: int = 0,
     return p
 
 
+# flattened jelly roll (Case III, Sec. 5): a stack 120 um thick (50 / 20 /
+# 50 um), 5 cm high and 1 m long on 56 x 85 x 1800 elements; here 60
+# elements through the stack so that the layers fall on element faces
+CASE3_STACK_UM = 120.0
+CASE3_HX_M = 1.0 / 1800      # element edge along the roll
+CASE3_HY_M = 0.05 / 85       # element edge along the height
+
+
+def make_case3_like(nx: int = 1801, ny: int = 86, nz: int = 61, nr=(10, 10), *,
+                    seed: int = 6) -> Problem:
+    """Linearized system on the Case III mesh: nz - 1 elements through the
+    stack (z, nondimensional thickness 1, layers 5/12, 1/6, 5/12 of it) and
+    the paper's element edges along the roll and the height (about 280x the
+    edge through the stack at nz = 61); nx - 1 by ny - 1 elements cover the
+    whole roll at the defaults, a section of it otherwise.  Coefficients,
+    Butler-Volmer derivatives and the right-hand side as make_custom with
+    uniform sigma = kappa = 1."""
+    if (nz - 1) % 12 != 0:
+        raise ValueError("nz - 1 must be a multiple of 12 (25/10/25 of 60 elements)")
+    e = (nz - 1) // 12
+    hz_m = CASE3_STACK_UM * 1e-6 / (nz - 1)
+    hx_m, hy_m = CASE3_HX_M, CASE3_HY_M
+    p = make_custom(nx, ny, nz, nr, seed=seed, na=5 * e + 1, ns=2 * e,
+                    name=f"Case III-like flattened roll {nx}x{ny}x{nz} Nr={nr[0]}")
+    h = p.h
+    return p.with_(hxy=(h * hx_m / hz_m, h * hy_m / hz_m))
+
+
 def make_config(cid: int, seed: Optional[int] = None) -> Problem:
     """Benchmark configurations C1, C2, C3, C5 (C4 is ``make_batch``)."""
     seed = cid if seed is None else seed

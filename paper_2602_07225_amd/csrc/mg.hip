@@ -384,26 +384,31 @@ void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// z-line block Gauss-Seidel (boxes much thinner along z than across): one
-// thread per line of the colour; the couplings of a row to the other lines
-// go to the right-hand side with the current x (lines of one colour do not
-// couple), the line's tridiagonal block (offsets (0,0,-1), centre, (0,0,1))
-// is eliminated down the line and substituted back up.  Multipliers and
-// right-hand sides of the elimination sit in tmp, [k][line], so that the
-// threads of a wave touch consecutive addresses.
+// z-line block Gauss-Seidel (boxes much thinner along z than across).  A
+// workgroup owns lpw lines of the colour and stages them in LDS: first all
+// its threads compute, row by row and in parallel, the right-hand side with
+// the couplings to other lines moved over (lines of one colour do not
+// couple) and copy the line's tridiagonal block (offsets (0,0,-1), centre,
+// (0,0,1)); then one thread per line eliminates down the line and
+// substitutes back up in LDS; then all threads write x.  (One thread walking
+// its line through global memory leaves every step waiting on a load, which
+// dominates on the coarse levels where there are few lines.)  LDS [k][line]
+// keeps the threads of the elimination on consecutive banks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
+__global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour, int lpw)
 {
+    extern __shared__ double lds[];
     const LineArgs &A = lb.a[find_box(lb, blockIdx.x)];
     const int cx = colour & 1, cy = colour >> 1;
     const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2, nl = ncx * ncy;
-    const int t = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
-    if (t >= nl) return;
-    const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
+    const int g0 = (blockIdx.x - A.blk0) * lpw;
+    const int nlw = nl - g0 < lpw ? nl - g0 : lpw;   // >= 1 by the grid
+    const int nz = A.nz;
     const long long layer = (long long)A.nx * A.ny, N = A.n;
-    double *cp = A.tmp, *dp = A.tmp + (long long)A.nz * nl;
-    double cprev = 0.0, dprev = 0.0;
-    for (int k = 0; k < A.nz; k++) {
+    double *Llo = lds, *Ldg = lds + lpw * nz, *Lup = Ldg + lpw * nz, *Lrh = Lup + lpw * nz;
+    for (int p = threadIdx.x; p < nlw * nz; p += kBlock) {
+        const int ll = p % nlw, k = p / nlw, t = g0 + ll;
+        const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
         const long long n = i + (long long)A.nx * j + layer * k;
         double rhs = A.b[n];
 #pragma unroll
@@ -411,21 +416,40 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
             const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
             if (dx == 0 && dy == 0) continue;
             const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny &&
-                            k + dz >= 0 && k + dz < A.nz;
+                            k + dz >= 0 && k + dz < nz;
             if (ok) rhs -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
         }
-        const double lo = k > 0 ? A.S[4 * N + n] : 0.0;            // offset (0,0,-1)
-        const double up = k < A.nz - 1 ? A.S[22 * N + n] : 0.0;    // offset (0,0,+1)
-        const double den = A.S[13 * N + n] - lo * cprev;
-        cprev = up / den;
-        dprev = (rhs - lo * dprev) / den;
-        cp[(long long)k * nl + t] = cprev;
-        dp[(long long)k * nl + t] = dprev;
+        const int q = k * lpw + ll;
+        Llo[q] = k > 0 ? A.S[4 * N + n] : 0.0;            // offset (0,0,-1)
+        Lup[q] = k < nz - 1 ? A.S[22 * N + n] : 0.0;      // offset (0,0,+1)
+        Ldg[q] = A.S[13 * N + n];
+        Lrh[q] = rhs;
     }
-    double nxt = 0.0;
-    for (int k = A.nz - 1; k >= 0; k--) {
-        nxt = dp[(long long)k * nl + t] - (k < A.nz - 1 ? cp[(long long)k * nl + t] * nxt : 0.0);
-        A.x[i + (long long)A.nx * j + layer * k] = nxt;
+    __syncthreads();
+    if (threadIdx.x < nlw) {
+        const int ll = threadIdx.x;
+        double cprev = 0.0, dprev = 0.0;
+        for (int k = 0; k < nz; k++) {
+            const int q = k * lpw + ll;
+            const double lo = Llo[q];
+            const double den = Ldg[q] - lo * cprev;
+            cprev = Lup[q] / den;
+            dprev = (Lrh[q] - lo * dprev) / den;
+            Lup[q] = cprev;
+            Lrh[q] = dprev;
+        }
+        double nxt = 0.0;
+        for (int k = nz - 1; k >= 0; k--) {
+            const int q = k * lpw + ll;
+            nxt = Lrh[q] - (k < nz - 1 ? Lup[q] * nxt : 0.0);
+            Lrh[q] = nxt;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < nlw * nz; p += kBlock) {
+        const int ll = p % nlw, k = p / nlw, t = g0 + ll;
+        const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
+        A.x[i + (long long)A.nx * j + layer * k] = Lrh[k * lpw + ll];
     }
 }
 
@@ -449,15 +473,21 @@ __global__ __launch_bounds__(kBlock) void k_resid_full(LineBatch lb)
 
 void launch_zline(LineBatch lb, int colour, hipStream_t st)
 {
+    // lines per workgroup: four doubles per row of each line in 64 KB of LDS
+    int nzmax = 1;
+    for (int q = 0; q < lb.nbox; q++) nzmax = lb.a[q].nz > nzmax ? lb.a[q].nz : nzmax;
+    int lpw = kZlineLds / (32 * nzmax);
+    lpw = lpw > 64 ? 64 : (lpw < 1 ? 1 : lpw);
     int blk = 0;
     for (int q = 0; q < lb.nbox; q++) {
         LineArgs &A = lb.a[q];
         const int cx = colour & 1, cy = colour >> 1;
         const int nl = ((A.nx - cx + 1) / 2) * ((A.ny - cy + 1) / 2);
         A.blk0 = blk;
-        blk += (nl + kBlock - 1) / kBlock;
+        blk += (nl + lpw - 1) / lpw;
     }
-    if (blk) hipLaunchKernelGGL(k_zline, dim3(blk), dim3(kBlock), 0, st, lb, colour);
+    if (blk)
+        hipLaunchKernelGGL(k_zline, dim3(blk), dim3(kBlock), (size_t)32 * lpw * nzmax, st, lb, colour, lpw);
 }
 
 void launch_resid_full(LineBatch lb, hipStream_t st)

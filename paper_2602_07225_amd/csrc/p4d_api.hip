@@ -79,7 +79,6 @@ struct p4d_ctx {
     double *oms = nullptr;         // omega_j of the Schur complement (whatever the preconditioner)
     double *kdh = nullptr, *dch = nullptr;   // h * separate transport coefficients
     double *meh = nullptr;         // eps_e vol / dt per element (when storage is set)
-    double *ltmp = nullptr;        // z-line smoothing: elimination buffers, 2 Nm doubles
     int storage = 0;               // 1: g.meh points at meh
     int transport_set = 0;         // 1: kdh / dch hold caller coefficients
     int general = 0;               // 1: kdh / dch hold the transport coefficients
@@ -296,7 +295,6 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     c->ydev = (double *)take(8 * 128);
     c->scal = (double *)take(8 * 128);
     const long long Nm = g.Nm;
-    c->ltmp = o.smoother == P4D_SMOOTH_ZLINE ? (double *)take(16 * (size_t)Nm) : nullptr;
     c->b0 = take(ts * Nm);
     c->x0a = take(8 * Nm);          // iterates are FP64 in every mode
     c->x0b = take(8 * Nm);
@@ -745,10 +743,9 @@ static void vcycle_line(p4d_ctx *c, int l, hipStream_t st)
         A.b = (const double *)L.b;
         A.x = (double *)L.xa;
         A.r = (double *)L.r;
-        A.tmp = c->ltmp + 2 * B.off;
         hipMemsetAsync(A.x, 0, 8 * (size_t)L.n, st);
-        // stencil, b, x read and written, elimination buffers written and read
-        bytes += (27.0 * 8 + 8 + 16 + 32) * L.n;
+        // stencil, b, x read and written
+        bytes += (27.0 * 8 + 8 + 16) * L.n;
     }
     const int deg = c->pc.cheb_degree;
     auto pass = [&](bool backward) {
@@ -1651,6 +1648,8 @@ p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
     if (o.pc == P4D_PC_BGS && c->g.aniso)
         return fail(c, P4D_ERR_INVALID_ARG, "block Gauss-Seidel needs cube elements");
+    if (o.smoother == P4D_SMOOTH_ZLINE && c->g.nz > kZlineMaxNz)
+        return fail(c, P4D_ERR_INVALID_ARG, "z-line smoothing takes at most 2048 node layers");
     // keep the Krylov sizing of the layout (it is set by the workspace size
     // the caller asked for); the preconditioner part must match o
     p4d_solve_opts lay = c->ws_opts;

@@ -197,15 +197,16 @@ void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st);
 
 // z-line smoothing of up to four boxes of one level (FP64, full stencils
 // [27][n]): block Gauss-Seidel over the lines of one colour (x parity
-// colour & 1, y parity colour >> 1), in place in x; tmp holds 2 n doubles
-// (the elimination's multipliers and right-hand sides)
+// colour & 1, y parity colour >> 1), in place in x.  A box's z extent is at
+// most kZlineMaxNz (a line's rows must fit the 64 KB of LDS).
+constexpr int kZlineLds = 65536;
+constexpr int kZlineMaxNz = kZlineLds / 32;
 struct LineArgs {
     int nx, ny, nz, n, blk0;
     const double *S;
     const double *b;
     double *x;
     double *r;
-    double *tmp;
 };
 struct LineBatch {
     int nbox;
