@@ -405,11 +405,16 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour, int 
     const int nlw = nl - g0 < lpw ? nl - g0 : lpw;   // >= 1 by the grid
     const int nz = A.nz;
     const long long layer = (long long)A.nx * A.ny, N = A.n;
+    // rows of this colour in Sz start after those of the lower colours
+    long long offc = 0;
+    for (int c = 0; c < colour; c++)
+        offc += (long long)((A.nx - (c & 1) + 1) / 2) * ((A.ny - (c >> 1) + 1) / 2) * nz;
     double *Llo = lds, *Ldg = lds + lpw * nz, *Lup = Ldg + lpw * nz, *Lrh = Lup + lpw * nz;
     for (int p = threadIdx.x; p < nlw * nz; p += kBlock) {
         const int ll = p % nlw, k = p / nlw, t = g0 + ll;
         const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
         const long long n = i + (long long)A.nx * j + layer * k;
+        const long long row = offc + (long long)k * nl + t;   // consecutive lines: consecutive rows
         double rhs = A.b[n];
 #pragma unroll
         for (int o = 0; o < 27; o++) {
@@ -417,12 +422,12 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour, int 
             if (dx == 0 && dy == 0) continue;
             const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny &&
                             k + dz >= 0 && k + dz < nz;
-            if (ok) rhs -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
+            if (ok) rhs -= A.Sz[o * N + row] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
         }
         const int q = k * lpw + ll;
-        Llo[q] = k > 0 ? A.S[4 * N + n] : 0.0;            // offset (0,0,-1)
-        Lup[q] = k < nz - 1 ? A.S[22 * N + n] : 0.0;      // offset (0,0,+1)
-        Ldg[q] = A.S[13 * N + n];
+        Llo[q] = k > 0 ? A.Sz[4 * N + row] : 0.0;            // offset (0,0,-1)
+        Lup[q] = k < nz - 1 ? A.Sz[22 * N + row] : 0.0;      // offset (0,0,+1)
+        Ldg[q] = A.Sz[13 * N + row];
         Lrh[q] = rhs;
     }
     __syncthreads();
@@ -469,6 +474,32 @@ __global__ __launch_bounds__(kBlock) void k_resid_full(LineBatch lb)
         if (ok) acc -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
     }
     A.r[n] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zline_order(int nx, int ny, int nz, const double *__restrict__ S,
+                                                        double *__restrict__ Sz)
+{
+    const long long N = (long long)nx * ny * nz;
+    const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const int i = (int)(n % nx);
+    const long long u = n / nx;
+    const int j = (int)(u % ny), k = (int)(u / ny);
+    const int colour = (i & 1) | ((j & 1) << 1);
+    long long offc = 0;
+    for (int c = 0; c < colour; c++)
+        offc += (long long)((nx - (c & 1) + 1) / 2) * ((ny - (c >> 1) + 1) / 2) * nz;
+    const int ncx = (nx - (i & 1) + 1) / 2, ncy = (ny - (j & 1) + 1) / 2;
+    const long long row = offc + (long long)k * ncx * ncy + (i >> 1) + (long long)ncx * (j >> 1);
+#pragma unroll
+    for (int o = 0; o < 27; o++) Sz[o * N + row] = S[o * N + n];
+}
+
+void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st)
+{
+    const long long N = (long long)nx * ny * nz;
+    hipLaunchKernelGGL(k_zline_order, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
+                       ny, nz, S, Sz);
 }
 
 void launch_zline(LineBatch lb, int colour, hipStream_t st)

@@ -28,6 +28,7 @@ struct Level {
     int nx = 0, ny = 0, nz = 0, n = 0;
     double lmax = 0.0;
     double *S64 = nullptr;   // persistent FP64 Galerkin stencil (levels >= 1)
+    double *Sz = nullptr;    // z-line smoothing: S64's rows in the sweeps' order
     void *S = nullptr;       // smoother copy in the preconditioner precision,
                              // centre slot = FP64 row sum (difference form)
     void *invd = nullptr, *b = nullptr, *xa = nullptr, *xb = nullptr, *d = nullptr, *r = nullptr;
@@ -337,6 +338,8 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
                 L.d = take(ts * L.n);
                 L.r = take(ts * L.n);
             }
+            L.Sz = o.smoother == P4D_SMOOTH_ZLINE && l < B.nlev - 1 ? (double *)take(8 * 27 * (size_t)L.n)
+                                                                     : nullptr;
             if (l == B.nlev - 1) {
                 L.Ainv = (double *)take(8 * (size_t)L.n * L.n);
                 setup_need += align_up(8 * (size_t)L.n * L.n);   // dense copy per box
@@ -740,6 +743,7 @@ static void vcycle_line(p4d_ctx *c, int l, hipStream_t st)
         LineArgs &A = lb.a[q];
         A.nx = L.nx; A.ny = L.ny; A.nz = L.nz; A.n = L.n;
         A.S = L.S64;
+        A.Sz = L.Sz;
         A.b = (const double *)L.b;
         A.x = (double *)L.xa;
         A.r = (double *)L.r;
@@ -998,6 +1002,7 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 Sl = L.S64;
                 launch_stencil_diff<T>(L.n, L.S64, (T *)L.S, st);
             }
+            if (zline && L.Sz) launch_zline_order(L.nx, L.ny, L.nz, Sl, L.Sz, st);
             const int nblk = (L.n + kBlock - 1) / kBlock;
             double *idst = l == 0 ? id64 + B.off : idl;   // FP64 inverse diagonal
             launch_diag(L.n, Sl, idst, c->red, nblk, st);

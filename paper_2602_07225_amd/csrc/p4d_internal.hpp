@@ -203,7 +203,8 @@ constexpr int kZlineLds = 65536;
 constexpr int kZlineMaxNz = kZlineLds / 32;
 struct LineArgs {
     int nx, ny, nz, n, blk0;
-    const double *S;
+    const double *S;                 // [27][n], natural node order (residual)
+    const double *Sz;                // the same rows by colour, layer, line (sweeps)
     const double *b;
     double *x;
     double *r;
@@ -215,6 +216,9 @@ struct LineBatch {
 void launch_zline(LineBatch lb, int colour, hipStream_t st);
 // r = b - S x on the same boxes
 void launch_resid_full(LineBatch lb, hipStream_t st);
+// Sz = the rows of S ([27][n] on an nx x ny x nz box) reordered as the
+// z-line sweeps read them: colour by colour, then layer k, then line
+void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
 void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);
