@@ -121,6 +121,7 @@ def lib():
         L.orc_schur_apply.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_set_transport.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_set_storage.argtypes = [C.c_void_p, _dp]
+        L.orc_set_newton.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
         L.orc_schur_rhs.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_schur_back.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
         L.orc_radial_mesh.argtypes = [C.c_int, C.c_double, _dp]
@@ -253,6 +254,10 @@ class Oracle:
         if ep is not None:
             self._keep_e = _f64(ep)
             lib().orc_set_storage(self.h, _p(self._keep_e))
+        nw = getattr(prob, "newton", None)
+        if nw is not None:
+            self._keep_n = [_f64(a) for a in nw]
+            lib().orc_set_newton(self.h, *[_p(a) for a in self._keep_n])
         sz = (C.c_int64 * 8)()
         lib().orc_sizes(self.h, sz)
         self.sizes = list(sz)

@@ -135,6 +135,10 @@ typedef struct {
      * the c_e diffusion (NULL: chi * kappa and kappa)                       */
     double *kappad, *dce;
     double *epse;              /* porosity per element (NULL: per material) */
+    /* Newton terms: state phi_e and c_e per node, per element the
+     * c_e-derivatives of kappa_eff, of the diffusion-potential coefficient
+     * and of D_eff (NULL: off)                                              */
+    double *nw_up, *nw_uc, *nw_a, *nw_b, *nw_c;
     /* radial: node coordinates and rows of L~_h (flux term excluded) */
     double *rho[2], *Lsub[2], *Ldia[2], *Lsup[2];
     double Gamma[2];
@@ -280,6 +284,7 @@ orc_problem *orc_create(const orc_desc *d, const double *sigma, const double *ka
     P->kappad = NULL;
     P->dce = NULL;
     P->epse = NULL;
+    P->nw_up = P->nw_uc = P->nw_a = P->nw_b = P->nw_c = NULL;
     P->nc = d->nz - d->na - d->ns;
     P->nnode = (long)d->nx * d->ny * d->nz;
     P->nelem = (long)(d->nx - 1) * (d->ny - 1) * (d->nz - 1);
@@ -376,6 +381,30 @@ void orc_set_storage(orc_problem *P, const double *eps_e)
     P->pc_ready = 0;
 }
 
+/* The c_e-derivative terms of the transport coefficients in the Newton
+ * matrix at a state (Sec. 4.1: the Jacobian of the residual; the element
+ * coefficients kappa_eff, kappa_eff 2RT(1-t+)/(F c) and D_eff are functions
+ * of the element's mean c_e): up, uc the state's phi_e and c_e per node,
+ * da, db, dc per element the derivatives of the three coefficients with
+ * respect to the element mean.  All NULL removes the terms (Picard matrix).
+ * The preconditioner does not use them.                                     */
+void orc_set_newton(orc_problem *P, const double *up, const double *uc, const double *da,
+                    const double *db, const double *dc)
+{
+    double **dst[5] = {&P->nw_up, &P->nw_uc, &P->nw_a, &P->nw_b, &P->nw_c};
+    const double *src[5] = {up, uc, da, db, dc};
+    for (int q = 0; q < 5; q++) {
+        free(*dst[q]);
+        *dst[q] = NULL;
+    }
+    if (!up) return;
+    for (int q = 0; q < 5; q++) {
+        long n = q < 2 ? P->nnode : P->nelem;
+        *dst[q] = xmalloc(sizeof(double) * n);
+        memcpy(*dst[q], src[q], sizeof(double) * n);
+    }
+}
+
 static void mg_free(orc_mg *M)
 {
     for (int l = 0; l < M->nlev; l++) {
@@ -390,6 +419,7 @@ void orc_destroy(orc_problem *P)
     if (!P) return;
     free(P->sigma); free(P->kappa); free(P->g); free(P->s); free(P->e); free(P->m);
     free(P->kappad); free(P->dce); free(P->epse);
+    free(P->nw_up); free(P->nw_uc); free(P->nw_a); free(P->nw_b); free(P->nw_c);
     for (int el = 0; el < 2; el++) {
         free(P->rho[el]); free(P->Lsub[el]); free(P->Ldia[el]); free(P->Lsup[el]);
     }
@@ -576,6 +606,46 @@ void orc_apply(const orc_problem *P, int transpose, const double *x, double *y)
                         yps[je] = elem_sum(P, i, j, k, 1, cf_sigma, NULL, xv_phis, xps);
                 }
             }
+
+    /* c_e-derivatives of the transport coefficients (Newton terms): element
+     * e adds to its corner rows a the rank-one terms
+     *   (h K_e (da_e up + db_e uc))_a * mean_e(x_ce)     (phi_e rows)
+     *   (h K_e  dc_e uc)_a            * mean_e(x_ce)     (c_e rows)
+     * (up, uc the state); the transpose returns w_e^T (...) / 8 to the c_e
+     * columns of the corners.  Element by element, serially.               */
+    if (P->nw_up) {
+        for (int ek = 0; ek < d->nz - 1; ek++)
+            for (int ej = 0; ej < d->ny - 1; ej++)
+                for (int ei = 0; ei < d->nx - 1; ei++) {
+                    long id = elem_id(P, ei, ej, ek), cn[8];
+                    for (int b = 0; b < 8; b++)
+                        cn[b] = node_id(P, ei + (b & 1), ej + ((b >> 1) & 1), ek + ((b >> 2) & 1));
+                    double sp[8], sc[8];
+                    for (int a = 0; a < 8; a++) {
+                        sp[a] = sc[a] = 0.0;
+                        for (int b = 0; b < 8; b++) {
+                            double w = P->h * kelem(P, a, b);
+                            sp[a] += w * P->nw_up[cn[b]];
+                            sc[a] += w * P->nw_uc[cn[b]];
+                        }
+                    }
+                    double A = P->nw_a[id], B = P->nw_b[id], Cc = P->nw_c[id];
+                    if (!transpose) {
+                        double xm = 0.0;
+                        for (int b = 0; b < 8; b++) xm += xce[cn[b]];
+                        xm /= 8.0;
+                        for (int a = 0; a < 8; a++) {
+                            ype[cn[a]] += (A * sp[a] + B * sc[a]) * xm;
+                            yce[cn[a]] += Cc * sc[a] * xm;
+                        }
+                    } else {
+                        double t = 0.0;
+                        for (int a = 0; a < 8; a++)
+                            t += xpe[cn[a]] * (A * sp[a] + B * sc[a]) + xce[cn[a]] * Cc * sc[a];
+                        for (int b = 0; b < 8; b++) yce[cn[b]] += t / 8.0;
+                    }
+                }
+    }
 
     /* radial blocks: c_s rows = c/dt - L~_h c (backward Euler of (FD)) */
     for (int el = 0; el < 2; el++) {

@@ -11,10 +11,11 @@ Readings (each also listed in the design notes):
   - the transport coefficients of an element are evaluated at the mean of
     its eight nodal c_e (kappa_eff, D_e_eff and the diffusion-potential
     factor kappa_eff 2RT(1 - t+) / (F c_e));
-  - the Newton matrix keeps the transport coefficients of the current
-    iterate fixed (their c_e-derivatives are left out) and is exact in the
-    kinetics; at uniform c_e with a uniform potential gradient-free state it
-    is the exact Jacobian;
+  - the Newton matrix is the exact Jacobian: besides the transport
+    coefficients at the iterate and the kinetics derivatives it holds the
+    derivative of each element's coefficients with respect to its mean c_e,
+    applied to the state (rank-one terms per element); the preconditioner
+    is built without those terms;
   - the reaction is lumped per node (weight m_j), as in the linear model;
   - the applied current enters through the top face with the paper's
     Gaussian profile, lumped per face node and normalized so that the nodal
@@ -80,8 +81,18 @@ def kappa_bulk(ce):
     return 0.0911 + 1.9101 * c - 1.052 * c * c + 0.1554 * c * c * c
 
 
+def dkappa_bulk(ce):
+    """d kappa / d c_e (S/m per mol/m^3)."""
+    c = np.asarray(ce, dtype=float) / 1000.0
+    return (1.9101 - 2.0 * 1.052 * c + 3.0 * 0.1554 * c * c) / 1000.0
+
+
 def de_bulk(ce):
     return 5.34e-10 * np.exp(-0.65 * np.asarray(ce, dtype=float) / 1000.0)
+
+
+def dde_bulk(ce):
+    return -0.65 / 1000.0 * de_bulk(ce)
 
 
 OCP = (ocp_negative, ocp_positive)
@@ -185,9 +196,10 @@ def initial_state(case: ph.PhysCase, grid: Grid) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # coefficients of one state
 # ---------------------------------------------------------------------------
-def element_coefficients(case, grid, u):
+def element_coefficients(case, grid, u, derivatives=False):
     """sigma_eff, kappa_eff, the diffusion-potential coefficient and D_e_eff
-    per element, at the element-mean c_e."""
+    per element, at the element-mean c_e (and, with derivatives, the
+    derivatives of the last three with respect to that mean)."""
     ce = u[grid.off_ce: grid.off_ce + grid.nnode]
     cbar = ce[grid.corners].mean(axis=1)
     eps = ph.porosity(case)
@@ -199,7 +211,12 @@ def element_coefficients(case, grid, u):
     kap = eps ** ph.BRUGGEMAN * kappa_bulk(cbar)
     kd = kap * 2.0 * (1.0 - ph.T_PLUS) / (FRT * cbar)
     dce = eps ** ph.BRUGGEMAN * de_bulk(cbar)
-    return sig, kap, kd, dce
+    if not derivatives:
+        return sig, kap, kd, dce
+    dkap = eps ** ph.BRUGGEMAN * dkappa_bulk(cbar)
+    dkd = 2.0 * (1.0 - ph.T_PLUS) / FRT * (dkap * cbar - kap) / (cbar * cbar)
+    ddce = eps ** ph.BRUGGEMAN * dde_bulk(cbar)
+    return sig, kap, kd, dce, (dkap, dkd, ddce)
 
 
 def kinetics(case, grid, u):
@@ -234,10 +251,13 @@ def kinetics(case, grid, u):
     return q, g, e, s
 
 
-def linear_problem(case, grid, u, with_kinetics=True) -> pi.Problem:
+def linear_problem(case, grid, u, with_kinetics=True, exact=None) -> pi.Problem:
     """The Newton matrix at u as a linear-operator description: transport
-    coefficients at u, kinetics derivatives (or zero)."""
-    sig, kap, kd, dce = element_coefficients(case, grid, u)
+    coefficients at u, kinetics derivatives (or zero) and, when exact (by
+    default with the kinetics), the c_e-derivative terms of the transport
+    coefficients applied to the state."""
+    exact = with_kinetics if exact is None else exact
+    sig, kap, kd, dce, der = element_coefficients(case, grid, u, derivatives=True)
     if with_kinetics:
         _, g, e, s = kinetics(case, grid, u)
     else:
@@ -251,6 +271,8 @@ def linear_problem(case, grid, u, with_kinetics=True) -> pi.Problem:
         eps_sep=d["eps_sep"], sigma=sig, kappa=kap, g=g, s=s, e=e, b=np.zeros(grid.N),
         length=d["length"], lambda_el=(1.0 / (ph.F * neg.Rs * neg.a), 1.0 / (ph.F * pos.Rs * pos.a)),
         kappa_d=kd, dce=dce, eps_e=ph.porosity(case) if case.heterogeneous else None,
+        newton=(u[grid.off_pe: grid.off_ce].copy(), u[grid.off_ce: grid.off_cs[0]].copy()) + der
+        if exact else None,
         name="phys")
 
 
@@ -327,6 +349,9 @@ class Scaling:
                         kappa_d=rp * xc * lp.kappa_d, dce=rc * xc * lp.dce,
                         eps_elec=rc * xc * lp.eps_elec / tfac, eps_sep=rc * xc * lp.eps_sep / tfac,
                         eps_e=None if lp.eps_e is None else rc * xc * lp.eps_e / tfac,
+                        newton=None if lp.newton is None else
+                        lp.newton[:2] + (rp * xc * lp.newton[2], rp * xc * lp.newton[3],
+                                         rc * xc * lp.newton[4]),
                         g=rp * xp * lp.g, e=rp * xc * lp.e, s=rp * xs * lp.s,
                         tc=lp.tc * rc / rp, lambda_el=tuple(l * rs / rp for l in lp.lambda_el),
                         dt=lp.dt / tfac, Ds=tuple(d * tfac for d in lp.Ds))

@@ -88,6 +88,9 @@ class Problem:
     eps_e: Optional[np.ndarray] = None    # (n_elem,)
     # element edges along x and y (0: h, the edge along z)
     hxy: Tuple[float, float] = (0.0, 0.0)
+    # Newton terms of a state (phi_e, c_e per node; per element the c_e-
+    # derivatives of kappa_eff, the diffusion-potential coefficient, D_eff)
+    newton: Optional[Tuple[np.ndarray, ...]] = None
 
     # ---- sizes -----------------------------------------------------------
     @property

@@ -94,27 +94,52 @@ def test_newton_matrix_is_the_jacobian_at_rest(cube):
         assert e3[k] < 1e-7, (k, e2, e3)
 
 
-def test_newton_matrix_exact_in_the_kinetics_after_a_step(cube):
-    """After a discharge step c_e is no longer uniform; for directions that
-    leave c_e unchanged the transport coefficients do not move, and the
-    Newton matrix still equals the Jacobian (kinetics, coupling, radial and
-    storage rows)."""
+def test_newton_matrix_is_the_jacobian_after_a_step(cube):
+    """After a discharge step c_e is no longer uniform and the transport
+    coefficients move with it: the Newton matrix, with the c_e-derivative
+    terms of the element coefficients, still equals central differences of
+    the residual in every direction (c_e-only directions included), and its
+    transpose is the adjoint of it."""
     case, grid = cube
     u0 = P.initial_state(case, grid)
     I = P.applied_current(case)
     u1, _ = P.newton_step(case, grid, u0, I)
     J = O.Oracle(P.linear_problem(case, grid, u1))
-    v = _direction(grid, np.random.default_rng(2), ce=False)
-    Jv = J.apply(v)
-    err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, v, 1e-3), Jv)
-    assert max(err.values()) < 1e-6, err
-    # a c_e-only direction moves the transport coefficients too, but the
-    # phi_s and c_s rows see c_e only through the kinetics (i0 ~ c_e^alpha)
+    for seed, ce in ((2, True), (3, False)):
+        v = _direction(grid, np.random.default_rng(seed), ce=ce)
+        Jv = J.apply(v)
+        err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, v, 1e-3), Jv)
+        assert max(err.values()) < 1e-7, err
     w = np.zeros(grid.N)
-    w[grid.off_ce: grid.off_cs[0]] = np.random.default_rng(3).standard_normal(grid.nnode)
-    Jw = J.apply(w)
-    err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, w, 1e-3), Jw, rows=("phis", "cs"))
-    assert max(err.values()) < 1e-6, err
+    w[grid.off_ce: grid.off_cs[0]] = np.random.default_rng(4).standard_normal(grid.nnode)
+    err = _block_errors(case, grid, _fd(case, grid, u1, u0, I, w, 1e-3), J.apply(w),
+                        rows=("phie", "ce"))
+    assert max(err.values()) < 1e-7, err
+    # without the derivative terms the c_e rows miss the transport derivative
+    Jp = O.Oracle(P.linear_problem(case, grid, u1, exact=False))
+    errp = _block_errors(case, grid, _fd(case, grid, u1, u0, I, w, 1e-3), Jp.apply(w),
+                         rows=("phie", "ce"))
+    assert max(errp.values()) > 1e-4, errp
+    # adjoint: <J x, y> = <x, J^T y>
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(grid.N), rng.standard_normal(grid.N)
+    lhs, rhs = J.apply(x) @ y, x @ J.apply(y, True)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(J.apply(x)) * np.linalg.norm(y)
+
+
+def test_newton_converges_quadratically(cube):
+    """The second 60 s step from the first converges quadratically: each
+    scaled update is at most a constant times the square of the previous."""
+    case, grid = cube
+    u0 = P.initial_state(case, grid)
+    I = P.applied_current(case)
+    u1, _ = P.newton_step(case, grid, u0, I)
+    _, hist = P.newton_step(case, grid, u1, I)
+    d = [h[0] for h in hist]
+    assert len(d) <= 5 and d[-1] <= 1e-9
+    for a, b in zip(d[:-1], d[1:]):
+        if a < 1e-2:
+            assert b <= 10.0 * a * a, d
 
 
 def test_converged_step_balances_charge_and_conserves_electrolyte_lithium(cube):
