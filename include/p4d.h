@@ -442,9 +442,17 @@ p4d_status p4d_phys_initial_state(p4d_ctx *ctx, double *d_u, void *stream);
  * context.                                                                 */
 p4d_status p4d_phys_residual(p4d_ctx *ctx, const double *d_u, const double *d_uold, double *d_r,
                              void *stream);
+/* d_y = J(d_u) d_x (J^T if transpose): the Newton matrix of the cell at the
+ * state d_u in the scaled variables (D_r J D_c, see above), with the
+ * c_e-derivatives of the transport coefficients; d_x, d_y length N, must not
+ * alias.  Leaves the coefficients of d_u in the context.                   */
+p4d_status p4d_phys_jacobian_apply(p4d_ctx *ctx, const double *d_u, int transpose, const double *d_x,
+                                   double *d_y, void *stream);
 /* One backward-Euler step from d_uold: Newton iterations from the guess in
  * d_u (overwritten with the result), each a p4d_setup and an FGMRES solve of
- * the scaled Newton system with solve (may be NULL: defaults; the Krylov
+ * the scaled Newton system (the exact Jacobian; its preconditioner is built
+ * from the transport coefficients at the iterate without their
+ * c_e-derivatives) with solve (may be NULL: defaults; the Krylov
  * space must be the full one), until the scaled update meets newton->tol.
  * Synchronizes `stream` once per iteration.                                */
 p4d_status p4d_phys_newton_step(p4d_ctx *ctx, double *d_u, const double *d_uold,

@@ -54,7 +54,7 @@ EXPORTED = [
     "p4d_batch_solve", "p4d_batch_set_pc_mode", "p4d_batch_profile", "p4d_batch_profile_read",
     "p4d_batch_last_error",
     "p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace", "p4d_phys_initial_state",
-    "p4d_phys_residual", "p4d_phys_newton_step", "p4d_phys_set_fractions",
+    "p4d_phys_residual", "p4d_phys_newton_step", "p4d_phys_set_fractions", "p4d_phys_jacobian_apply",
 ]
 
 
@@ -177,9 +177,10 @@ def _bind_phys(L):
     L.p4d_phys_newton_step.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(NewtonOpts),
                                        C.POINTER(NewtonInfo), vp]
     L.p4d_phys_set_fractions.argtypes = [vp, vp, vp, vp]
+    L.p4d_phys_jacobian_apply.argtypes = [vp, vp, C.c_int, vp, vp, vp]
     for name in ("p4d_phys_create", "p4d_phys_workspace_size", "p4d_phys_set_workspace",
                  "p4d_phys_initial_state", "p4d_phys_residual", "p4d_phys_newton_step",
-                 "p4d_phys_set_fractions"):
+                 "p4d_phys_set_fractions", "p4d_phys_jacobian_apply"):
         getattr(L, name).restype = C.c_int
 
 
@@ -372,6 +373,11 @@ def p4d_set_transport(ctx, kappa_d=None, dce=None, stream=None):
 def p4d_set_storage(ctx, eps_e=None, stream=None):
     return check(lib().p4d_set_storage(ctx, ptr(eps_e) if eps_e is not None else None,
                                        stream_ptr(stream)), ctx, "p4d_set_storage")
+
+
+def p4d_phys_jacobian_apply(ctx, u, transpose, x, y, stream=None):
+    return check(lib().p4d_phys_jacobian_apply(ctx, ptr(u), int(transpose), ptr(x), ptr(y),
+                                               stream_ptr(stream)), ctx, "p4d_phys_jacobian_apply")
 
 
 def p4d_phys_set_fractions(ctx, eps_s=None, eps_b=None, stream=None):

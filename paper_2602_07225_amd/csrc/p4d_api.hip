@@ -49,6 +49,7 @@ struct PhysState {
     PhysDev P{};
     double *uh = nullptr, *rh = nullptr, *dh = nullptr, *old = nullptr, *fh = nullptr, *qh = nullptr;
     double *por = nullptr, *act = nullptr;   // porosity, active fraction per element (Case II)
+    double *nwa = nullptr, *nwb = nullptr, *nwc = nullptr;   // Newton-term coefficients per element
     bool ready = false;
 };
 
@@ -1247,12 +1248,23 @@ double kappa_bulk_h(double ce)   // bulk conductivity at 298.15 K (appendix)
 double de_bulk_h(double ce) { return 5.34e-10 * std::exp(-0.65 * ce / 1000.0); }
 }  // namespace
 
+// Newton terms of the physical cell in the operator (u = null: off)
+static void newton_terms_on(p4d_ctx *c, const double *u)
+{
+    PhysState &S = *c->phys;
+    c->g.nwu = u;
+    c->g.nwa = u ? S.nwa : nullptr;
+    c->g.nwb = u ? S.nwb : nullptr;
+    c->g.nwc = u ? S.nwc : nullptr;
+}
+
 // Arrays of the operator for the state u (SI): transport coefficients at the
 // element-mean c_e and the kinetics derivatives, scaled; the reaction q^.
 static void phys_coef(p4d_ctx *c, const double *u, hipStream_t st)
 {
     PhysState &S = *c->phys;
-    launch_phys_coef(c->g, S.P, u, c->sigh, c->kaph, c->kdh, c->dch, c->gg, c->ss, c->ee, S.qh, st);
+    launch_phys_coef(c->g, S.P, u, c->sigh, c->kaph, c->kdh, c->dch, c->gg, c->ss, c->ee, S.qh, S.nwa, S.nwb,
+                     S.nwc, st);
     c->general = 1;
     c->box[3].cK = c->dch;
     c->uploaded = 1;
@@ -1823,7 +1835,7 @@ p4d_status p4d_phys_workspace_size(const p4d_ctx *c, size_t *bytes)
 {
     if (!c || !bytes || !c->phys) return P4D_ERR_INVALID_ARG;
     *bytes = 4 * align_up(8 * (size_t)c->g.N) + 2 * align_up(8 * (size_t)c->g.ne) +
-             2 * align_up(8 * (size_t)c->g.nelem) + 256;
+             5 * align_up(8 * (size_t)c->g.nelem) + 256;
     return P4D_OK;
 }
 
@@ -1845,6 +1857,9 @@ p4d_status p4d_phys_set_workspace(p4d_ctx *c, void *d_work, size_t bytes)
     S.qh = take(8 * (size_t)c->g.ne);
     S.por = take(8 * (size_t)c->g.nelem);
     S.act = take(8 * (size_t)c->g.nelem);
+    S.nwa = take(8 * (size_t)c->g.nelem);
+    S.nwb = take(8 * (size_t)c->g.nelem);
+    S.nwc = take(8 * (size_t)c->g.nelem);
     S.P.por = S.P.act = nullptr;
     c->storage = 0;
     c->g.meh = nullptr;
@@ -1900,6 +1915,22 @@ p4d_status p4d_phys_residual(p4d_ctx *c, const double *u, const double *uold, do
     return P4D_OK;
 }
 
+p4d_status p4d_phys_jacobian_apply(p4d_ctx *c, const double *u, int transpose, const double *x, double *y,
+                                   void *stream)
+{
+    if (!c || !u || !x || !y || x == y || !c->phys) return P4D_ERR_INVALID_ARG;
+    if (!c->phys->uh) return fail(c, P4D_ERR_STATE, "p4d_phys_set_workspace first");
+    hipStream_t st = (hipStream_t)stream;
+    p4d_status s = phys_prepare(c, st);
+    if (s != P4D_OK) return s;
+    phys_coef(c, u, st);
+    newton_terms_on(c, u);
+    apply_op<double>(c, transpose, x, y, nullptr, nullptr, st);
+    newton_terms_on(c, nullptr);
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
 p4d_status p4d_phys_newton_step(p4d_ctx *c, double *u, const double *uold, const p4d_solve_opts *solve,
                                 const p4d_newton_opts *newton, p4d_newton_info *info, void *stream)
 {
@@ -1931,7 +1962,11 @@ p4d_status p4d_phys_newton_step(p4d_ctx *c, double *u, const double *uold, const
         s = p4d_setup(c, &o, st);
         if (s != P4D_OK) return s;
         p4d_solve_info li{};
+        // the exact Newton matrix: with the c_e-derivative terms at u (the
+        // preconditioner above is built without them)
+        newton_terms_on(c, u);
         s = o.z_fp32 ? fgmres<float>(c, 0, S.rh, S.dh, o, &li, st) : fgmres<double>(c, 0, S.rh, S.dh, o, &li, st);
+        newton_terms_on(c, nullptr);
         if (s != P4D_OK && s != P4D_NOT_CONVERGED) {
             inf.status = s;
             break;

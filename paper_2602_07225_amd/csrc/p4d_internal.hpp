@@ -27,6 +27,11 @@ struct Geom {
     int aniso = 0;
     double vol = 0.0;
     double kw[8] = {};
+    // Newton terms of a physical cell, set only for its linear solves: the
+    // state (SI; phi_e at nwu + off_pe, c_e at nwu + off_ce) and per element
+    // h times the scaled c_e-derivatives of kappa_eff, of the
+    // diffusion-potential coefficient and of D_eff (null: none)
+    const double *nwu = nullptr, *nwa = nullptr, *nwb = nullptr, *nwc = nullptr;
 };
 
 __host__ __device__ inline int elem_mat(const Geom &g, int kk)

@@ -553,7 +553,68 @@ __device__ inline void load_nb(const Geom &g, const TX *f, long long n, int i, i
 struct OpStencil {
     double Kpe, xpe, Kce, Mce, xce, Kps, xpsc;
     double Kx;   // GEN: the diffusion-potential stiffness applied to c_e (phi_e if transposed)
+    double Npe = 0.0, Nce = 0.0;   // GEN: Newton terms of the phi_e and c_e rows
 };
+
+// Newton terms at one node (GEN, g.nwu set): each element e of the node
+// has coefficients that depend on its mean c_e, so it adds to its corner
+// rows (K_e u)_a times the mean of x_ce over its corners, with K_e the
+// element stiffness (over h) and u the state: phi_e rows da_e (K_e phi_e) +
+// db_e (K_e c_e), c_e rows dc_e (K_e c_e).  Transposed, the node (a c_e
+// column) collects w_e^T (...) / 8 from each of its elements, w the input's
+// phi_e and c_e on the element's corners.  Xc: the input's c_e around the
+// node (the forward form).  (K_e u)_a = sum_{b != a} kw[a^b] (u_a - u_b).
+template <typename TX, bool TRANS>
+__device__ inline void newton_terms(const Geom &g, const TX *x, long long n, int i, int j, int k,
+                                    const double Xc[27], OpStencil &P)
+{
+    const double *up = g.nwu + g.off_pe, *uc = g.nwu + g.off_ce;
+    const long long layer = (long long)g.nx * g.ny;
+    double npe = 0.0, nce = 0.0;
+    for (int e = 0; e < 8; e++) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        const int ei = i - 1 + ex, ej = j - 1 + ey, ek = k - 1 + ez;
+        if (ei < 0 || ej < 0 || ek < 0 || ei >= g.nx - 1 || ej >= g.ny - 1 || ek >= g.nz - 1) continue;
+        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+        // corner b of the element is node n + off(b); this node is corner a
+        const long long c0 = ei + (long long)g.nx * ej + layer * ek;
+        auto node = [&](int b) { return c0 + (b & 1) + (long long)g.nx * ((b >> 1) & 1) + layer * ((b >> 2) & 1); };
+        const double A = g.nwa[id], B = g.nwb[id], C = g.nwc[id];
+        if (!TRANS) {
+            const int a = (1 - ex) | ((1 - ey) << 1) | ((1 - ez) << 2);
+            double sp = 0.0, sc = 0.0, xm = 0.0;
+            const double upa = up[n], uca = uc[n];
+            for (int b = 0; b < 8; b++) {
+                xm += Xc[nb_index(ex - 1 + (b & 1), ey - 1 + ((b >> 1) & 1), ez - 1 + ((b >> 2) & 1))];
+                if (b == a) continue;
+                const long long nb = node(b);
+                const double w = g.kw[a ^ b];
+                sp += w * (upa - up[nb]);
+                sc += w * (uca - uc[nb]);
+            }
+            xm *= 0.125;
+            npe += (A * sp + B * sc) * xm;
+            nce += C * sc * xm;
+        } else {
+            double t = 0.0;
+            for (int a = 0; a < 8; a++) {
+                const long long na = node(a);
+                double kup = 0.0, kuc = 0.0;
+                for (int b = 0; b < 8; b++) {
+                    if (b == a) continue;
+                    const long long nb = node(b);
+                    const double w = g.kw[a ^ b];
+                    kup += w * (up[na] - up[nb]);
+                    kuc += w * (uc[na] - uc[nb]);
+                }
+                t += ldx(x + g.off_pe + na) * (A * kup + B * kuc) + ldx(x + g.off_ce + na) * C * kuc;
+            }
+            nce += 0.125 * t;
+        }
+    }
+    P.Npe = npe;
+    P.Nce = nce;
+}
 
 // Reaction coupling of one electrode node: the linearized reaction q and the
 // weights with which it enters the phi_s, phi_e, c_e and surface c_s rows
@@ -602,8 +663,8 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
     const double xpe = P.xpe, xce = P.xce;
     double ype, yce;
     if (GEN) {
-        ype = TRANS ? P.Kpe : P.Kpe + P.Kx;
-        yce = TRANS ? P.Mce + P.Kce + P.Kx : P.Mce + P.Kce;
+        ype = (TRANS ? P.Kpe : P.Kpe + P.Kx) + P.Npe;
+        yce = (TRANS ? P.Mce + P.Kce + P.Kx : P.Mce + P.Kce) + P.Nce;
     } else if (!TRANS) {
         ype = P.Kpe + g.chi * P.Kce;
         yce = P.Mce + P.Kce;
@@ -724,6 +785,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
     }
     P.Mce = q1_mass(cm, X);
     P.xce = X[13];
+    if (GEN && g.nwu) newton_terms<TX, TRANS>(g, x, n, i, j, k, X, P);
     P.Kps = 0.0;
     P.xpsc = 0.0;
     const int el = node_mat(g, k);

@@ -26,9 +26,11 @@ struct PhysFix {
     double gam[2];         // scaled surface coupling per electrode
 };
 
+// also the scaled c_e-derivatives of the transport coefficients (times h)
+// per element, for the Newton terms
 void launch_phys_coef(const Geom &g, const PhysDev &P, const double *u, double *sigh, double *kaph,
                       double *kdh, double *dch, double *gg, double *ss, double *ee, double *qh,
-                      hipStream_t st);
+                      double *nwa, double *nwb, double *nwc, hipStream_t st);
 void launch_phys_scale(const Geom &g, const PhysDev &P, const double *in, double *out, int up,
                        hipStream_t st);
 void launch_phys_fix(const Geom &g, const PhysFix &F, double *r, int neg, hipStream_t st);

@@ -63,10 +63,17 @@ __device__ inline double kappa_bulk(double ce)
     return 0.0911 + c * (1.9101 + c * (-1.052 + c * 0.1554));
 }
 __device__ inline double de_bulk(double ce) { return 5.34e-10 * exp(-0.65 * ce / 1000.0); }
+__device__ inline double dkappa_bulk(double ce)   // d kappa / d c_e
+{
+    const double c = ce / 1000.0;
+    return (1.9101 + c * (-2.0 * 1.052 + c * 3.0 * 0.1554)) / 1000.0;
+}
 
 __global__ __launch_bounds__(kBlock) void k_phys_elem(Geom g, PhysDev P, const double *__restrict__ u,
                                                       double *__restrict__ sigh, double *__restrict__ kaph,
-                                                      double *__restrict__ kdh, double *__restrict__ dch)
+                                                      double *__restrict__ kdh, double *__restrict__ dch,
+                                                      double *__restrict__ nwa, double *__restrict__ nwb,
+                                                      double *__restrict__ nwc)
 {
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= g.nelem) return;
@@ -91,6 +98,14 @@ __global__ __launch_bounds__(kBlock) void k_phys_elem(Geom g, PhysDev P, const d
     kaph[t] = g.h * P.rphi * P.xphi * kap;
     kdh[t] = g.h * P.rphi * P.xc * kd;
     dch[t] = g.h * P.rc * P.xc * dce;
+    // derivatives with respect to the element mean c_e (Newton terms; the
+    // column scale x_c of c_e and the row scales)
+    const double dkap = eb * dkappa_bulk(cbar);
+    const double dkd = 2.0 * (1.0 - P.tplus) * P.RT / P.F * (dkap * cbar - kap) / (cbar * cbar);
+    const double ddce = eb * (-0.65 / 1000.0) * de_bulk(cbar);
+    nwa[t] = g.h * P.rphi * P.xc * dkap;
+    nwb[t] = g.h * P.rphi * P.xc * dkd;
+    nwc[t] = g.h * P.rc * P.xc * ddce;
 }
 
 __global__ __launch_bounds__(kBlock) void k_phys_node(Geom g, PhysDev P, const double *__restrict__ u,
@@ -282,10 +297,10 @@ void launch_phys_old_cs(const Geom &g, const PhysDev &P, const double *uold, dou
 
 void launch_phys_coef(const Geom &g, const PhysDev &P, const double *u, double *sigh, double *kaph,
                       double *kdh, double *dch, double *gg, double *ss, double *ee, double *qh,
-                      hipStream_t st)
+                      double *nwa, double *nwb, double *nwc, hipStream_t st)
 {
     hipLaunchKernelGGL(k_phys_elem, dim3(blocks(g.nelem)), dim3(kBlock), 0, st, g, P, u, sigh, kaph, kdh,
-                       dch);
+                       dch, nwa, nwb, nwc);
     hipLaunchKernelGGL(k_phys_node, dim3(blocks(g.ne)), dim3(kBlock), 0, st, g, P, u, gg, ss, ee, qh);
 }
 

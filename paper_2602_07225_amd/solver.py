@@ -290,6 +290,12 @@ class PhysCell:
         L.p4d_phys_initial_state(self.ctx, u)
         return u
 
+    def jacobian_apply(self, u, x, transpose=False):
+        """J(u) x (J^T x) in the scaled variables of the Newton system."""
+        y = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        L.p4d_phys_jacobian_apply(self.ctx, self._dev(u), transpose, self._dev(x), y)
+        return y
+
     def residual(self, u, u_old):
         r = torch.empty(self.N, dtype=torch.float64, device=self.device)
         L.p4d_phys_residual(self.ctx, self._dev(u), self._dev(u_old), r)

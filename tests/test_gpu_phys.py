@@ -185,3 +185,23 @@ def test_case2_fraction_errors():
     r = to_np(pc.residual(u, uold))
     e = block_errors(case1, grid, r, P.residual(case1, grid, u, uold, I))
     assert max(e.values()) <= 1e-10
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_exact_jacobian_apply_parity(transpose):
+    """The Newton matrix with the c_e-derivative terms at a state with
+    non-uniform c_e, in the scaled variables, against the oracle's."""
+    case, grid, I, pc = cell()
+    u0 = P.initial_state(case, grid)
+    u = perturbed(case, grid, u0, 3)
+    sc = P.Scaling(case)
+    ref_orc = O.Oracle(sc.problem(P.linear_problem(case, grid, u)))
+    x = np.random.default_rng(4).standard_normal(grid.N)
+    y = to_np(pc.jacobian_apply(u, x, transpose))
+    ref = ref_orc.apply(x, transpose)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    say(f"  exact Jacobian transpose={transpose}: max rel {err:.1e}")
+    assert err <= 1e-12
+    # the derivative terms are really there
+    plain = O.Oracle(sc.problem(P.linear_problem(case, grid, u, exact=False))).apply(x, transpose)
+    assert np.abs(plain - ref).max() > 1e3 * err * np.abs(ref).max()
