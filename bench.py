@@ -174,12 +174,13 @@ def bench_batch(steps):
     return out
 
 
-def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False):
+def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False, krylov=0):
     """The physical cube cell (Case I: 225 um cube, 100/25/100 um layers,
     appendix parameters, Gaussian 1C discharge current; with hetero, Case II:
     volume fractions per element from seeded random fields, uniform
     current): `steps` backward-Euler steps of 60 s, each by Newton
-    iterations on the GPU."""
+    iterations on the GPU (FGMRES over all unknowns, or with krylov = 1 over
+    the Schur complement of the particle blocks)."""
     import torch
     from p4d_inputs import phys as ph
     from paper_2602_07225_amd import PhysCell
@@ -197,7 +198,7 @@ def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False):
     t0 = time.perf_counter()
     newton, lin = [], 0
     for _ in range(steps):
-        u, info = cell.step(u)
+        u, info = cell.step(u, krylov=krylov)
         if info.status != 0:
             raise RuntimeError(f"Newton did not converge: status {info.status}")
         newton.append(info.iters)
@@ -208,7 +209,8 @@ def bench_newton(n=64, nr=(10, 10), steps=30, hetero=False):
            "applied_current_A": current, "total_ms": 1e3 * t, "ms_per_step": 1e3 * t / steps,
            "newton_iters_per_step": float(np.mean(newton)), "newton_iters_max": int(max(newton)),
            "fgmres_iters_per_newton": lin / max(1, sum(newton)),
-           "voltage_start_V": v0, "voltage_end_V": u[top].mean().item()}
+           "voltage_start_V": v0, "voltage_end_V": u[top].mean().item(),
+           "krylov": "schur_complement" if krylov else "full"}
     cell.close()
     return out
 
@@ -241,6 +243,9 @@ def bench_case3(steps=2, warmup=1):
            "zline_level0_pass": prof.get("smooth0")}
     _, _, it2, t2, _ = timed_steps(s, b, dict(zl, cheb_degree=2), steps, 1)
     out["two_sweeps_per_side"] = {"ms_per_solve": 1e3 * t2 / steps, "iters_per_solve": it2 / steps}
+    _, i3, it3, t3, _ = timed_steps(s, b, dict(zl, krylov=L.P4D_KRYLOV_SCHUR), steps, 1)
+    out["schur_krylov"] = {"ms_per_solve": 1e3 * t3 / steps, "iters_per_solve": it3 / steps,
+                           "relres_true": i3.relres_true}
     del s, x, b
     torch.cuda.empty_cache()
     q = pi.make_case3_like(nx=226, ny=12)
@@ -306,6 +311,7 @@ def main():
         return
     if args.newton_only:
         print(json.dumps({"newton_case_I_cube": bench_newton(),
+                          "newton_case_I_cube_schur_krylov": bench_newton(krylov=1),
                           "newton_case_II_cube": bench_newton(hetero=True)}), flush=True)
         return
     if args.schur_only:
@@ -528,15 +534,18 @@ def main():
         try:
             extras["case3_like_roll"] = e = bench_case3()
             log(f"[bench] Case III-like roll N={e['dof']}: z-line {e['ms_per_solve']:.1f} ms/solve, "
-                f"{e['iters_per_solve']:.1f} it; section: z-line {e['section_225x11']['zline']['iters']} it, "
+                f"{e['iters_per_solve']:.1f} it (Schur-Krylov {e['schur_krylov']['ms_per_solve']:.1f} ms); "
+                f"section: z-line {e['section_225x11']['zline']['iters']} it, "
                 f"point {e['section_225x11']['chebyshev']['iters']} it "
                 f"(status {e['section_225x11']['chebyshev']['status']})")
         except RuntimeError as ex:
             extras["case3_like_roll"] = {"error": str(ex)}
-        for key, het in (("newton_case_I_cube", False), ("newton_case_II_cube", True)):
+        for key, het, kry in (("newton_case_I_cube", False, 0), ("newton_case_I_cube_schur_krylov", False, 1),
+                              ("newton_case_II_cube", True, 0)):
             try:
-                extras[key] = e = bench_newton(hetero=het)
-                log(f"[bench] Newton {'Case II' if het else 'Case I'}: {e['steps']} steps, "
+                extras[key] = e = bench_newton(hetero=het, krylov=kry)
+                log(f"[bench] Newton {'Case II' if het else 'Case I'}{' (Schur-Krylov)' if kry else ''}: "
+                    f"{e['steps']} steps, "
                     f"{e['ms_per_step']:.1f} ms/step, {e['newton_iters_per_step']:.1f} Newton it/step, "
                     f"V {e['voltage_start_V']:.4f} -> {e['voltage_end_V']:.4f}")
             except RuntimeError as ex:

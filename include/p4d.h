@@ -97,7 +97,7 @@ typedef enum { P4D_KRYLOV_FULL = 0, P4D_KRYLOV_SCHUR = 1 } p4d_krylov;
  * after; cheb_degree passes each), coarsening in x and y only: robust when
  * the elements are much thinner along z than across, as in the flattened
  * jelly roll of paper Sec. 5 (Case III), where point smoothers stall.  FP64
- * preconditioner, pc SCHUR or BJ, the full Krylov space.                   */
+ * preconditioner, pc SCHUR or BJ; either Krylov space.                     */
 typedef enum { P4D_SMOOTH_CHEB = 0, P4D_SMOOTH_ZLINE = 1 } p4d_smoother;
 
 /* Problem geometry and scalars, all nondimensional.  The particle radius is
@@ -119,8 +119,8 @@ typedef struct {
     double hxy[2];             /* element edges along x and y; 0: h (cubes).  Box
                                   elements take the Q1 stiffness sum_d (vol /
                                   h_d^2) Khat_d and the mass vol Mhat; the
-                                  operator then runs one thread per node and the
-                                  Schur-complement Krylov space, P4D_PC_BGS,
+                                  operator then runs one thread per node, and
+                                  block Gauss-Seidel (P4D_PC_BGS),
                                   p4d_param_gradient and batches do not apply   */
 } p4d_problem_desc;
 
@@ -207,9 +207,8 @@ p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
  * the c_e diffusion (D_e_eff).  NULL keeps the default (chi * kappa, and
  * kappa, the operator of p4d_upload); both NULL restores it.  Needs
  * p4d_upload, which resets them; invalidates p4d_setup.  With separate
- * coefficients the operator runs one thread per node, the Schur-complement
- * Krylov space (P4D_KRYLOV_SCHUR) is not available, and batches do not
- * apply.                                                                   */
+ * coefficients the operator runs one thread per node (also in its
+ * Schur-complement form) and batches do not apply.                          */
 p4d_status p4d_set_transport(p4d_ctx *ctx, const double *d_kappa_d, const double *d_dce,
                              void *stream);
 
@@ -220,8 +219,8 @@ p4d_status p4d_set_transport(p4d_ctx *ctx, const double *d_kappa_d, const double
  * the per-material eps_elec / eps_sep.  Values are not checked (a
  * non-positive porosity leaves S_ce indefinite).  Needs p4d_upload, which
  * resets it; invalidates p4d_setup.  As with p4d_set_transport the operator
- * then runs one thread per node and the Schur-complement Krylov space and
- * batches do not apply; every preconditioner does.  INVALID_ARG on a
+ * then runs one thread per node and batches do not apply; every
+ * preconditioner and Krylov space does.  INVALID_ARG on a
  * physical cell (p4d_phys_set_fractions sets its storage).                */
 p4d_status p4d_set_storage(p4d_ctx *ctx, const double *d_eps_e, void *stream);
 
@@ -452,8 +451,8 @@ p4d_status p4d_phys_jacobian_apply(p4d_ctx *ctx, const double *d_u, int transpos
  * d_u (overwritten with the result), each a p4d_setup and an FGMRES solve of
  * the scaled Newton system (the exact Jacobian; its preconditioner is built
  * from the transport coefficients at the iterate without their
- * c_e-derivatives) with solve (may be NULL: defaults; the Krylov
- * space must be the full one), until the scaled update meets newton->tol.
+ * c_e-derivatives) with solve (may be NULL: defaults; either Krylov space),
+ * until the scaled update meets newton->tol.
  * Synchronizes `stream` once per iteration.                                */
 p4d_status p4d_phys_newton_step(p4d_ctx *ctx, double *d_u, const double *d_uold,
                                 const p4d_solve_opts *solve, const p4d_newton_opts *newton,

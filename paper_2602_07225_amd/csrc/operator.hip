@@ -137,15 +137,35 @@ template void launch_operator<float>(const Geom &, const RadialTab *, const doub
                                      const double *, double *, int, int, int, double *,
                                      const double *, const double *, hipStream_t);
 
+// the Schur-complement operator one thread per node, with the separate
+// element arrays (GEN: transport coefficients, storage, box elements,
+// Newton terms)
+template <typename TX, bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_operator_schur_gen(Geom g, OpArgs O)
+{
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const long long n = (long long)lb * kBlock + threadIdx.x;
+    if (n < g.nnode) operator_node<TX, 1, TRANS, false, true, true>(g, O, n);
+}
+
 // w = S y (or S^T y), S = A_yy - A_ys A_ss^-1 A_sy: y and w hold the
 // electrode-level unknowns only (length Nm); omega per electrode node.
+// kdh, dch given: the per-node form with the separate element arrays.
 template <typename TX>
 void launch_operator_schur(const Geom &g, const RadialTab *tabs, const double *sigh,
                            const double *kaph, const double *gg, const double *ss, const double *ee,
                            const double *mm, const double *om, const TX *y, double *w, int transpose,
-                           int tile_tx, int tile_cz, hipStream_t st)
+                           int tile_tx, int tile_cz, const double *kdh, const double *dch, hipStream_t st)
 {
-    OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, y, w, nullptr, om};
+    OpArgs O{tabs, sigh, kaph, gg, ss, ee, mm, y, w, nullptr, om, kdh, dch};
+    if (kdh && dch) {
+        const int nb = operator_blocks(g);
+        if (transpose)
+            hipLaunchKernelGGL((k_operator_schur_gen<TX, true>), dim3(nb), dim3(kBlock), 0, st, g, O);
+        else
+            hipLaunchKernelGGL((k_operator_schur_gen<TX, false>), dim3(nb), dim3(kBlock), 0, st, g, O);
+        return;
+    }
     const int nt = operator_tiles(g, tile_tx, tile_cz);
     if (transpose)
         hipLaunchKernelGGL((k_operator_schur<TX, true>), dim3(nt), dim3(kBlock), 0, st, g, O, tile_tx,
@@ -157,11 +177,13 @@ void launch_operator_schur(const Geom &g, const RadialTab *tabs, const double *s
 template void launch_operator_schur<double>(const Geom &, const RadialTab *, const double *,
                                             const double *, const double *, const double *,
                                             const double *, const double *, const double *,
-                                            const double *, double *, int, int, int, hipStream_t);
+                                            const double *, double *, int, int, int, const double *,
+                                            const double *, hipStream_t);
 template void launch_operator_schur<float>(const Geom &, const RadialTab *, const double *,
                                            const double *, const double *, const double *,
                                            const double *, const double *, const double *,
-                                           const float *, double *, int, int, int, hipStream_t);
+                                           const float *, double *, int, int, int, const double *,
+                                           const double *, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Gradients of J = w.x:  dJ/dp = -lambda^T (dA/dp) x.

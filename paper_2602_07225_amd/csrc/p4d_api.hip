@@ -401,9 +401,8 @@ static bool opts_valid(const p4d_solve_opts &o, std::string &why)
     if (o.coarse_max < 8 || o.coarse_max > 1024) { why = "coarse_max must be in 8..1024"; return false; }
     if (!(o.rtol > 0.0) || !(o.rtol < 1.0)) { why = "rtol must be in (0,1)"; return false; }
     if (o.smoother != P4D_SMOOTH_CHEB && o.smoother != P4D_SMOOTH_ZLINE) { why = "smoother"; return false; }
-    if (o.smoother == P4D_SMOOTH_ZLINE &&
-        (o.pc_prec != P4D_FP64 || o.pc == P4D_PC_BGS || o.krylov != P4D_KRYLOV_FULL)) {
-        why = "z-line smoothing needs an FP64 preconditioner, pc SCHUR or BJ and the full Krylov space";
+    if (o.smoother == P4D_SMOOTH_ZLINE && (o.pc_prec != P4D_FP64 || o.pc == P4D_PC_BGS)) {
+        why = "z-line smoothing needs an FP64 preconditioner and pc SCHUR or BJ";
         return false;
     }
     return true;
@@ -491,7 +490,8 @@ static void apply_op_schur(p4d_ctx *c, int transpose, const TX *y, double *w, hi
     const double bytes = (double)(sizeof(TX) + 8) * g.Nm + 16.0 * g.nelem + 40.0 * g.ne;
     ProfScope ps(c->prof, P4D_K_OPERATOR, bytes, st);
     launch_operator_schur<TX>(g, c->tabs, c->sigh, c->kaph, c->gg, c->ss, c->ee, c->mm, c->oms, y, w,
-                              transpose, c->op_tx, c->op_cz, st);
+                              transpose, c->op_tx, c->op_cz, c->general ? c->kdh : nullptr,
+                              c->general ? c->dch : nullptr, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -909,7 +909,8 @@ static void apply_pc_schur_t(p4d_ctx *c, const double *r, double rscale, TZ *z, 
     }
     VState<T> vs{};
     for (int b = 0; b < 4; b++) vs.xcur[b][0] = 0;
-    vcycle_level<T>(c, vs, 0, st);
+    if (c->pc.smoother == P4D_SMOOTH_ZLINE) vcycle_line(c, 0, st);   // (FP64 only)
+    else vcycle_level<T>(c, vs, 0, st);
     for (int b = 0; b < 4; b++) B.R.x0[b] = (const double *)(vs.xcur[b][0] ? c->x0b : c->x0a);
     ProfScope ps(c->prof, P4D_K_COUPLING, (8.0 + sizeof(TZ)) * g.Nm, st);
     launch_bgs_out<TZ>(g, B, r, rscale, z, st);
@@ -1265,6 +1266,7 @@ static void phys_coef(p4d_ctx *c, const double *u, hipStream_t st)
     PhysState &S = *c->phys;
     launch_phys_coef(c->g, S.P, u, c->sigh, c->kaph, c->kdh, c->dch, c->gg, c->ss, c->ee, S.qh, S.nwa, S.nwb,
                      S.nwc, st);
+    launch_omega(c->g, c->tabs, c->ss, 1, c->oms, st);   // the Schur-complement operator's weights
     c->general = 1;
     c->box[3].cK = c->dch;
     c->uploaded = 1;
@@ -1708,8 +1710,6 @@ p4d_status p4d_apply_schur_operator(p4d_ctx *c, int transpose, const double *y, 
 {
     if (!c || !y || !w || y == w) return P4D_ERR_INVALID_ARG;
     if (!c->uploaded) return fail(c, P4D_ERR_STATE, "p4d_upload first");
-    if (c->general)
-        return fail(c, P4D_ERR_INVALID_ARG, "the Schur operator needs the default transport coefficients");
     apply_op_schur<double>(c, transpose, y, w, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return P4D_OK;
@@ -1739,9 +1739,6 @@ static p4d_status solve_common(p4d_ctx *c, int transpose, const double *b, doubl
         return fail(c, P4D_ERR_STATE, "preconditioner options differ from the last setup");
     if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
         return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
-    if (o.krylov == P4D_KRYLOV_SCHUR && c->general)
-        return fail(c, P4D_ERR_INVALID_ARG,
-                    "the Schur-complement Krylov space needs the default transport coefficients");
     hipStream_t st = (hipStream_t)stream;
     if (o.z_fp32) return fgmres<float>(c, transpose, b, x, o, info, st);
     return fgmres<double>(c, transpose, b, x, o, info, st);
@@ -1942,8 +1939,6 @@ p4d_status p4d_phys_newton_step(p4d_ctx *c, double *u, const double *uold, const
     if (solve) o = *solve;
     std::string why;
     if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
-    if (o.krylov != P4D_KRYLOV_FULL)
-        return fail(c, P4D_ERR_INVALID_ARG, "Newton systems use the full Krylov space");
     if (o.restart > c->ws_opts.restart || (!o.z_fp32 && c->ws_opts.z_fp32))
         return fail(c, P4D_ERR_OOM, "workspace sized for a smaller restart or an FP32 Z basis");
     const int maxit = newton ? newton->maxit : 30;

@@ -258,7 +258,7 @@ template <typename TX>
 void launch_operator_schur(const Geom &g, const RadialTab *tabs, const double *sigh,
                            const double *kaph, const double *gg, const double *ss, const double *ee,
                            const double *mm, const double *om, const TX *y, double *w, int transpose,
-                           int tile_tx, int tile_cz, hipStream_t st);
+                           int tile_tx, int tile_cz, const double *kdh, const double *dch, hipStream_t st);
 // reduced.hip
 void launch_red_rhs(const Geom &g, const RadialTab *tabs, const double *gg, const double *ss,
                     const double *ee, const double *mm, const double *b, double *bhat, int transpose,

@@ -652,7 +652,10 @@ __device__ inline double op_radial_row(const RadialTab &T, bool trans, int r, in
 // the output (y, or b - A x when RESID); returns the sum of squares written.
 // GEN: separate element coefficients for the diffusion-potential block
 // (P.Kx) and the c_e diffusion (P.Kce), instead of chi * kappa and kappa.
-template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false>
+// RED: the Schur complement of the particle blocks (see operator_tile): the
+// reaction enters scaled by omega_j, no particle column (x, y hold the
+// electrode-level unknowns only)
+template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false, bool RED = false>
 __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long long n, int i, int j,
                                          int k, const OpStencil &P)
 {
@@ -689,14 +692,17 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
         const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
         // the particle column, loaded at once (indices clamped to the last point)
         double xr[NRMAX];
+        double xsN = 0.0;
+        if (!RED) {
 #pragma unroll
-        for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
-        double xsN = xr[0];
+            for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+            xsN = xr[0];
 #pragma unroll
-        for (int r = 1; r < NRMAX; r++)
-            if (r == N - 1) xsN = xr[r];
+            for (int r = 1; r < NRMAX; r++)
+                if (r == N - 1) xsN = xr[r];
+        }
         const OpCoupling cp = op_coupling<TRANS>(g, T, dir, m, gj, sj, ej, P.xpsc, xpe, xce, xsN);
-        const double q = cp.q, r3 = cp.r3;
+        const double q = RED ? cp.q * O.om[je] : cp.q, r3 = cp.r3;
         double yps = dir ? xps : P.Kps + cp.r0 * q;
         ype += cp.r1 * q;
         yce += cp.r2 * q;
@@ -705,6 +711,7 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
         sq += yps * yps;
 #pragma unroll
         for (int r = 0; r < NRMAX; r++) {
+            if (RED) break;
             if (r < N) {
                 const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
                 const double x0 = xr[r];
@@ -729,7 +736,7 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
 
 // The operator y = A x (or A^T x, or b - A x) at one node, every stencil
 // value read from memory (paper Sec. 4.1, eq. blocks; see operator.hip).
-template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false>
+template <typename TX, int NRMAX, bool TRANS, bool RESID, bool GEN = false, bool RED = false>
 __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long n)
 {
     const TX *x = (const TX *)O.x;
@@ -805,7 +812,7 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         P.Kps = stiff_of<GEN>(g, cs, X);
         P.xpsc = X[13];
     }
-    return operator_finish<TX, NRMAX, TRANS, RESID, GEN>(g, O, n, i, j, k, P);
+    return operator_finish<TX, NRMAX, TRANS, RESID, GEN, RED>(g, O, n, i, j, k, P);
 }
 
 // ---------------------------------------------------------------------------

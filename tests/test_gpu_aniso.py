@@ -74,6 +74,24 @@ def test_zline_solve_parity(pc):
     assert rel(orc.apply(x), p.b) <= 1.0001e-8
 
 
+def test_zline_schur_krylov_solve_parity():
+    """Krylov over the Schur complement of the particle blocks on box
+    elements with z-line multigrid."""
+    p = flat()
+    orc = O.Oracle(p).setup(smoother=O.SMOOTH_ZLINE, rtol=1e-8, krylov=O.KRYLOV_SCHUR)
+    xo, io = orc.solve(p.b)
+    s = solver_for(p, smoother=O.SMOOTH_ZLINE).setup(smoother=O.SMOOTH_ZLINE, rtol=1e-8)
+    x, info = s.solve(to_dev(p.b), krylov=O.KRYLOV_SCHUR)
+    x = to_np(x)
+    errs = field_errors(p, x, xo)
+    say(f"  z-line Schur-Krylov iters gpu={info.iters} oracle={io.iters}",
+        {k: f"{v:.1e}" for k, v in errs.items()})
+    assert info.status == 0 and io.status == 0
+    assert abs(info.iters - io.iters) <= 2
+    assert max(errs.values()) <= 1e-6
+    assert rel(orc.apply(x), p.b) <= 1.0001e-8
+
+
 def test_zline_is_robust_where_point_smoothing_stalls():
     """Iteration counts reported (not pinned): the point-smoothed hierarchy
     needs many times more iterations on these flat elements."""
@@ -99,8 +117,6 @@ def test_box_element_option_errors():
             s.setup(**kw)
         assert e.value.status == _lib.P4D_ERR_INVALID_ARG
     s.setup()
-    with pytest.raises(P4DError):
-        s.solve(to_dev(p.b), krylov=_lib.P4D_KRYLOV_SCHUR)
     x = to_dev(np.ones(p.N))
     with pytest.raises(P4DError):
         s.gradient(x, x)

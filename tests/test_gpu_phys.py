@@ -205,3 +205,17 @@ def test_exact_jacobian_apply_parity(transpose):
     # the derivative terms are really there
     plain = O.Oracle(sc.problem(P.linear_problem(case, grid, u, exact=False))).apply(x, transpose)
     assert np.abs(plain - ref).max() > 1e3 * err * np.abs(ref).max()
+
+
+def test_newton_step_schur_krylov_matches_oracle():
+    """Newton steps with FGMRES over the Schur complement of the particle
+    blocks (exact Newton matrix, its particle blocks eliminated exactly)."""
+    case, grid, I, pc = cell()
+    u0 = P.initial_state(case, grid)
+    uo, hist = P.newton_step(case, grid, u0, I, lin_rtol=1e-10, coarse_max=64)
+    ug, info = pc.step(u0, rtol=1e-10, krylov=1)
+    ug = to_np(ug)
+    say(f"  newton (Schur-Krylov) gpu iters={info.iters} lin={info.lin_iters}; oracle {len(hist)}")
+    assert info.status == 0
+    assert abs(info.iters - len(hist)) <= 1
+    assert P.scaled_update(case, grid, ug - uo) <= 1e-8

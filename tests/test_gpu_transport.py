@@ -66,18 +66,40 @@ def test_general_solve_parity(pc):
     assert rel(orc.apply(x), p.b) <= 1.0001e-8
 
 
-def test_transport_reset_and_schur_krylov_guard():
-    from paper_2602_07225_amd import P4DError, _lib
+@pytest.mark.parametrize("transpose", [False, True])
+def test_general_schur_operator_parity(transpose):
+    """The Schur complement of the particle blocks in its per-node form
+    (separate coefficients, per-element storage)."""
+    p = general().with_(eps_e=0.1 + 0.8 * np.random.default_rng(8).random(general().n_elem))
+    orc = O.Oracle(p)
+    s = solver_for(p)
+    y = np.random.default_rng(9).standard_normal(orc.n_macro)
+    w = to_np(s.apply_schur(to_dev(y), transpose))
+    ref = orc.schur_apply(y, transpose)
+    assert np.max(np.abs(w - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_general_schur_krylov_solve_parity():
+    p = general()
+    orc = O.Oracle(p).setup(rtol=1e-8, krylov=O.KRYLOV_SCHUR)
+    xo, io = orc.solve(p.b)
+    s = solver_for(p).setup(rtol=1e-8)
+    x, info = s.solve(to_dev(p.b), krylov=1)
+    x = to_np(x)
+    errs = field_errors(p, x, xo)
+    say(f"  general Schur-Krylov iters gpu={info.iters} oracle={io.iters}",
+        {k: f"{v:.1e}" for k, v in errs.items()})
+    assert info.status == 0 and io.status == 0
+    assert abs(info.iters - io.iters) <= 2
+    assert max(errs.values()) <= 1e-6
+    assert rel(orc.apply(x), p.b) <= 1.0001e-8
+
+
+def test_transport_reset():
     p = general()
     plain = p.with_(kappa_d=None, dce=None)
     s = solver_for(p)
     x = np.random.default_rng(3).standard_normal(p.N)
-    s.setup()
-    with pytest.raises(P4DError) as e:
-        s.solve(to_dev(p.b), krylov=1)
-    assert e.value.status == _lib.P4D_ERR_INVALID_ARG
-    with pytest.raises(P4DError):
-        s.apply_schur(to_dev(x[:p.offsets[3]]))
     s.set_transport(None, None)          # back to chi * kappa and kappa
     y = to_np(s.apply(to_dev(x)))
     ref = O.Oracle(plain).apply(x)
@@ -145,15 +167,10 @@ def test_storage_solve_parity(with_transport):
 
 
 def test_storage_reset_restores_the_tiled_path():
-    """Clearing the storage returns to the per-material operator, and with
-    it the Schur-complement Krylov space."""
-    from paper_2602_07225_amd import P4DError
+    """Clearing the storage returns to the per-material (tiled) operator."""
     p = porous()
     plain = p.with_(eps_e=None)
     s = solver_for(p)
-    s.setup()
-    with pytest.raises(P4DError):
-        s.solve(to_dev(p.b), krylov=1)
     s.set_storage(None)
     x = np.random.default_rng(6).standard_normal(p.N)
     ref = O.Oracle(plain).apply(x)
