@@ -87,6 +87,19 @@ def bgs_sweep(s, b, base):
             "all": rows}
 
 
+def event_pair_us(n=200):
+    """Mean elapsed time of an event pair with nothing between them, on the
+    stream the library's launches use (the current torch stream)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for e0, e1 in evs:
+        e0.record()
+        e1.record()
+    torch.cuda.synchronize()
+    return 1e3 * sum(e0.elapsed_time(e1) for e0, e1 in evs) / n
+
+
 def timed_steps(s, b, opts, steps, warmup, profile_mask=0):
     import torch
     from paper_2602_07225_amd import _lib as L
@@ -374,6 +387,12 @@ def main():
                     "unit": "GB/s", "frac": d["GBps"] / HBM_PEAK_GBS,
                     "traffic": measured_traffic(dom),
                     "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]}
+        # an event pair around a launch also times the pair's own processing
+        # on the queue: measured here with nothing between the events (the
+        # kernel-trace duration of the same kernel is avg_launch_us minus it)
+        pair = event_pair_us()
+        roofline["event_pair_us"] = pair
+        roofline["avg_launch_us_net"] = d["avg_us"] - pair
 
     # setup and solve split (one extra, untimed-in-the-headline run)
     torch.cuda.synchronize()
