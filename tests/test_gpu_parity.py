@@ -181,3 +181,29 @@ def test_edge_cases():
     # single-iteration restart cycles still converge
     x, info = s.solve(to_dev(p.b), restart=2, maxit=5000)
     assert info.status == 0
+
+
+@pytest.mark.parametrize("smoother", [O.SMOOTH_CHEB, O.SMOOTH_ZLINE])
+def test_smallest_grid_and_radial_extremes(smoother):
+    """The smallest admissible cell (2 x 2 x 5 nodes, two anode layers, one
+    separator layer, two cathode layers) with the fewest and the most radial
+    points (3 and 64): operator, preconditioner and solve against the
+    oracle."""
+    p = pi.make_custom(2, 2, 5, (3, 64), seed=24, na=2, ns=1)
+    assert p.nc == 2
+    orc = O.Oracle(p)
+    s = solver_for(p, smoother=smoother)
+    x = np.random.default_rng(7).standard_normal(p.N)
+    for tr in (False, True):
+        y, ref = to_np(s.apply(to_dev(x), tr)), orc.apply(x, tr)
+        assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # (1e-8: with 64 graded radial points the attainable relative residual
+    # is ~3e-10)
+    orc.setup(smoother=smoother, rtol=1e-8)
+    s.setup(smoother=smoother, rtol=1e-8)
+    errs = field_errors(p, to_np(s.apply_pc(to_dev(x))), orc.apply_pc(x))
+    assert max(errs.values()) <= 1e-10
+    xo, io = orc.solve(p.b)
+    xg, info = s.solve(to_dev(p.b))
+    assert info.status == 0 and io.status == 0
+    assert max(field_errors(p, to_np(xg), xo).values()) <= 1e-6
