@@ -743,19 +743,19 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
     const int i = (int)(n % g.nx);
     const long long t = n / g.nx;
     const int j = (int)(t % g.ny), k = (int)(t / g.ny);
-    double ck[8], cs[8], cm[8];
+    // element coefficients of the node's eight elements; each set is read
+    // beside the neighbourhood that uses it, so only one set is live at a time
+    auto elem_of = [&](const double *C, double c[8]) {
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
-        const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
-        const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
-                        ek < g.nz - 1;
-        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
-        ck[e] = ok ? O.kaph[id] : 0.0;
-        cs[e] = ok ? O.sigh[id] : 0.0;
-        // per-element storage only with separate coefficients (GEN)
-        cm[e] = ok ? (GEN ? elem_storage(g, id, ek) : (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep))
-                   : 0.0;
-    }
+        for (int e = 0; e < 8; e++) {
+            const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+            const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                            ek < g.nz - 1;
+            c[e] = ok ? C[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+        }
+    };
+    double ck[8], cs[8], cm[8];
+    elem_of(O.kaph, ck);
     OpStencil P;
     double X[27];
     P.Kx = 0.0;
@@ -773,6 +773,10 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
         }
         P.Kx = stiff_of<GEN>(g, cx, X);
     }
+    // an empty statement that takes the finished sums: they may not be
+    // deferred past it nor the next neighbourhood's loads hoisted above it,
+    // so one 27-value neighbourhood is live at a time (register use)
+    __asm__ volatile("" : "+v"(P.Kpe), "+v"(P.Kx) : : "memory");
     load_nb(g, x + g.off_ce, n, i, j, k, X);
     if (GEN) {
         double cd[8], cx[8];
@@ -790,13 +794,25 @@ __device__ inline double operator_node(const Geom &g, const OpArgs &O, long long
     } else {
         P.Kce = stiff_of<GEN>(g, ck, X);
     }
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ei = i - 1 + (e & 1), ej = j - 1 + ((e >> 1) & 1), ek = k - 1 + ((e >> 2) & 1);
+        const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                        ek < g.nz - 1;
+        const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
+        // per-element storage only with separate coefficients (GEN)
+        cm[e] = ok ? (GEN ? elem_storage(g, id, ek) : (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep))
+                   : 0.0;
+    }
     P.Mce = q1_mass(cm, X);
     P.xce = X[13];
     if (GEN && g.nwu) newton_terms<TX, TRANS>(g, x, n, i, j, k, X, P);
+    __asm__ volatile("" : "+v"(P.Kce), "+v"(P.Mce), "+v"(P.Kx), "+v"(P.Npe), "+v"(P.Nce) : : "memory");
     P.Kps = 0.0;
     P.xpsc = 0.0;
     const int el = node_mat(g, k);
     if (el >= 0) {
+        elem_of(O.sigh, cs);
         const long long base = el == 0 ? 0 : g.nea;
         const int klo = el == 0 ? 0 : g.na + g.ns;
         const int khi = el == 0 ? g.na - 1 : g.nz - 1;
@@ -921,21 +937,30 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             fetch_elems(k + 1);
         }
         if (own) {
-            double ck[8], cs[8], cm[8];
+            // element coefficients are read from LDS (or formed) just before
+            // the field that uses them, so only one set is live at a time
+            auto elem_coef = [&](const double (*C)[kCkLds], double c[8]) {
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-                const int q = (tx + ex) + EX * (ty + ey);
-                ck[e] = L.kap[(k - 1 + ez) & 1][q];
-                cs[e] = L.sig[(k - 1 + ez) & 1][q];
-                const int ek = k - 1 + ez;
-                // the element exists iff its kappa coefficient slot was filled;
-                // decide by the indices, as the per-node gather does
-                const int ei = i - 1 + ex, ej = j - 1 + ey;
-                const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
-                                ek < g.nz - 1;
-                cm[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
-            }
+                for (int e = 0; e < 8; e++) {
+                    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                    c[e] = C[(k - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
+                }
+            };
+            auto mass_coef = [&](double c[8]) {
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                    const int ek = k - 1 + ez;
+                    // the element exists iff its kappa coefficient slot was
+                    // filled; decide by the indices, as the per-node gather does
+                    const int ei = i - 1 + ex, ej = j - 1 + ey;
+                    const bool ok = ei >= 0 && ej >= 0 && ek >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
+                                    ek < g.nz - 1;
+                    c[e] = ok ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
+                }
+            };
+            double ck[8], cs[8], cm[8];
+            elem_coef(L.kap, ck);
             OpStencil P;
             double X[27];
             auto gather = [&](const double (*F)[kXpLds]) {
@@ -954,15 +979,20 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             gather(L.pe);
             P.Kpe = q1_stiff(ck, X);
             P.xpe = X[13];
-            __builtin_amdgcn_sched_barrier(0);
+            // an empty statement that takes the finished sum: the compiler
+            // may neither defer the sum nor hoist the next gather above it,
+            // so only one 27-value neighbourhood is live at a time
+            __asm__ volatile("" : "+v"(P.Kpe) : : "memory");
             gather(L.ce);
             P.Kce = q1_stiff(ck, X);
+            mass_coef(cm);
             P.Mce = q1_mass(cm, X);
             P.xce = X[13];
-            __builtin_amdgcn_sched_barrier(0);
+            __asm__ volatile("" : "+v"(P.Kce), "+v"(P.Mce) : : "memory");
             P.Kps = 0.0;
             P.xpsc = 0.0;
             if (node_mat(g, k) >= 0) {
+                elem_coef(L.sig, cs);
                 gather(L.ps);
                 P.Kps = q1_stiff(cs, X);
                 P.xpsc = X[13];
