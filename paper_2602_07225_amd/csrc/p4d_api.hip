@@ -2276,19 +2276,18 @@ static p4d_status batch_record(p4d_batch *B)
     for (int i = 0; i < n; i++) bysize[i] = i;
     std::stable_sort(bysize.begin(), bysize.end(),
                      [&](int a, int b) { return B->cell[a]->g.N > B->cell[b]->g.N; });
-    static const int nrclasses[5] = {8, 16, 24, 32, 64};
     std::vector<int> order, ustart;
     B->lists.clear();
     long long items = 0;
     for (int d = 0; d < depth; d++)
         for (int fam = SF_RADF; fam <= SF_MISC; fam++) {
             const bool radial = fam == SF_RADF || fam == SF_RADB;
-            for (int ci = 0; ci < (radial ? 5 : 1); ci++) {
-                p4d_batch::WorkList W{fam, radial ? nrclasses[ci] : 8, (int)order.size(), 0, (int)items, 0};
+            for (int ci = 0; ci < (radial ? kNrClasses : 1); ci++) {
+                p4d_batch::WorkList W{fam, radial ? kNrClass[ci] : 8, (int)order.size(), 0, (int)items, 0};
                 for (int i : bysize) {
                     const int j = at[(size_t)i * depth + d];
                     if (j < 0 || stage_family(per[i][j].kind) != fam) continue;
-                    if (radial && rad_nrmax(B->cell[i]->g) != nrclasses[ci]) continue;
+                    if (radial && rad_nrmax(B->cell[i]->g) != kNrClass[ci]) continue;
                     order.push_back(base[i] + j);
                     ustart.push_back((int)items);
                     items += per[i][j].nunits;

@@ -150,12 +150,16 @@ template <typename T, typename TZ>
 void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
                      int transpose, int schur, hipStream_t st);
 // size class of the per-thread radial register arrays: the largest N_r of
-// the two electrodes rounded up to 8, 16, 24, 32 or 64
+// the two electrodes rounded up to 8, 12, 16, 20, 24, 32 or 64
 int rad_nrmax(const Geom &g);
+constexpr int kNrClasses = 7;
+constexpr int kNrClass[kNrClasses] = {8, 12, 16, 20, 24, 32, 64};
 #define P4D_NR_SWITCH(nr, M)   \
     switch (nr) {              \
     case 8: M(8); break;       \
+    case 12: M(12); break;     \
     case 16: M(16); break;     \
+    case 20: M(20); break;     \
     case 24: M(24); break;     \
     case 32: M(32); break;     \
     default: M(64); break;     \

@@ -18,7 +18,9 @@ __global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R, const dou
 int rad_nrmax(const Geom &g)
 {
     const int nrm = g.nr[0] > g.nr[1] ? g.nr[0] : g.nr[1];
-    return nrm <= 8 ? 8 : (nrm <= 16 ? 16 : (nrm <= 24 ? 24 : (nrm <= 32 ? 32 : 64)));
+    for (int c = 0; c < kNrClasses - 1; c++)
+        if (nrm <= kNrClass[c]) return kNrClass[c];
+    return kNrClass[kNrClasses - 1];
 }
 
 template <typename T>
