@@ -108,24 +108,24 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
     // ahead and written to LDS after the layer that used the slot is done,
     // so the global loads overlap the arithmetic of the previous layer.
     double px[2], pc[2];
-    auto fetch_plane = [&](int kl) {
+    auto fetch_plane_to = [&](int kl, double v[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
             const int ii = i0 - 1 + q % PX, jj = j0 - 1 + q / PX;
             const bool ok = q < PX * PY && kl >= 0 && kl < A.nz && ii >= 0 && ii < A.nx && jj >= 0 &&
                             jj < A.ny;
-            px[h] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
+            v[h] = ok ? A.xin[ii + A.nx * (jj + A.ny * kl)] : 0.0;
         }
     };
-    auto store_plane = [&](int slot) {
+    auto store_plane_from = [&](int slot, const double v[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
-            if (q < PX * PY) L.xp[slot][q] = px[h];
+            if (q < PX * PY) L.xp[slot][q] = v[h];
         }
     };
-    auto fetch_elems = [&](int kl) {
+    auto fetch_elems_to = [&](int kl, double v[2]) {
         const int ek = kl + A.k0;
         const bool lay = ek >= A.ek_lo && ek <= A.ek_hi;
 #pragma unroll
@@ -133,16 +133,20 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
             const int q = threadIdx.x + h * kBlock;
             const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
             const bool ok = q < EX * EY && lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
-            pc[h] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
+            v[h] = ok ? A.cK[ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek)] : 0.0;
         }
     };
-    auto store_elems = [&](int slot) {
+    auto store_elems_from = [&](int slot, const double v[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
-            if (q < EX * EY) L.ck[slot][q] = pc[h];
+            if (q < EX * EY) L.ck[slot][q] = v[h];
         }
     };
+    auto fetch_plane = [&](int kl) { fetch_plane_to(kl, px); };
+    auto store_plane = [&](int slot) { store_plane_from(slot, px); };
+    auto fetch_elems = [&](int kl) { fetch_elems_to(kl, pc); };
+    auto store_elems = [&](int slot) { store_elems_from(slot, pc); };
     // per-node data of a layer (right-hand side, reaction diagonal, inverse
     // diagonal, previous direction), also fetched one layer ahead
     double nb[4] = {0.0, 0.0, 0.0, 0.0};
@@ -157,15 +161,19 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
             }
         }
     };
-    fetch_plane(k0l - 1);
-    store_plane((k0l + 2) % 3);
-    fetch_plane(k0l);
-    store_plane(k0l % 3);
-    fetch_elems(k0l - 1);
-    store_elems((k0l + 1) & 1);
-    fetch_plane(k0l + 1);
-    fetch_elems(k0l);
-    fetch_node(k0l);
+    {   // prologue: every load of the first layer is issued before any of
+        // them is stored, so the tile waits for one memory latency, not four
+        double p0[2], p1[2], e0[2];
+        fetch_plane_to(k0l - 1, p0);
+        fetch_plane_to(k0l, p1);
+        fetch_elems_to(k0l - 1, e0);
+        fetch_plane(k0l + 1);
+        fetch_elems(k0l);
+        fetch_node(k0l);
+        store_plane_from((k0l + 2) % 3, p0);
+        store_plane_from(k0l % 3, p1);
+        store_elems_from((k0l + 1) & 1, e0);
+    }
     for (int kl = k0l; kl < k1l; kl++) {
         store_plane((kl + 1) % 3);
         store_elems(kl & 1);
@@ -871,7 +879,7 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
     const long long layer = (long long)g.nx * g.ny;
 
     double pe[2], ce[2], ps[2], kp[2], sg[2];
-    auto fetch_planes = [&](int kk) {
+    auto fetch_planes_to = [&](int kk, double pe[2], double ce[2], double ps[2]) {
         const int el = (kk >= 0 && kk < g.nz) ? node_mat(g, kk) : -1;
         const bool has_ps = el >= 0 && kk != 0;
         const long long psb = el == 0 ? 0 : g.nea - (long long)(g.na + g.ns) * layer;
@@ -887,7 +895,7 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             ps[h] = (ok && has_ps) ? ldx(x + (psb + nd)) : 0.0;
         }
     };
-    auto store_planes = [&](int slot) {
+    auto store_planes_from = [&](int slot, const double pe[2], const double ce[2], const double ps[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
@@ -898,7 +906,7 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             }
         }
     };
-    auto fetch_elems = [&](int ek) {
+    auto fetch_elems_to = [&](int ek, double kp[2], double sg[2]) {
         const bool lay = ek >= 0 && ek < g.nz - 1;
 #pragma unroll
         for (int h = 0; h < 2; h++) {
@@ -910,7 +918,7 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             sg[h] = ok ? O.sigh[id] : 0.0;
         }
     };
-    auto store_elems = [&](int slot) {
+    auto store_elems_from = [&](int slot, const double kp[2], const double sg[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
@@ -920,14 +928,22 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             }
         }
     };
-    fetch_planes(k0 - 1);
-    store_planes((k0 + 2) % 3);
-    fetch_planes(k0);
-    store_planes(k0 % 3);
-    fetch_elems(k0 - 1);
-    store_elems((k0 + 1) & 1);
-    fetch_planes(k0 + 1);
-    fetch_elems(k0);
+    auto fetch_planes = [&](int kk) { fetch_planes_to(kk, pe, ce, ps); };
+    auto store_planes = [&](int slot) { store_planes_from(slot, pe, ce, ps); };
+    auto fetch_elems = [&](int ek) { fetch_elems_to(ek, kp, sg); };
+    auto store_elems = [&](int slot) { store_elems_from(slot, kp, sg); };
+    {   // prologue: every load of the first layer is issued before any of
+        // them is stored, so the tile waits for one memory latency, not four
+        double pe0[2], ce0[2], ps0[2], pe1[2], ce1[2], ps1[2], kp0[2], sg0[2];
+        fetch_planes_to(k0 - 1, pe0, ce0, ps0);
+        fetch_planes_to(k0, pe1, ce1, ps1);
+        fetch_elems_to(k0 - 1, kp0, sg0);
+        fetch_planes(k0 + 1);
+        fetch_elems(k0);
+        store_planes_from((k0 + 2) % 3, pe0, ce0, ps0);
+        store_planes_from(k0 % 3, pe1, ce1, ps1);
+        store_elems_from((k0 + 1) & 1, kp0, sg0);
+    }
     for (int k = k0; k < k1; k++) {
         store_planes((k + 1) % 3);
         store_elems(k & 1);

@@ -23,6 +23,7 @@ def small_cells():
         pi.make_custom(24, 24, 72, (32, 8), seed=43, sigma_log=0.5),
         pi.make_custom(9, 12, 25, (16, 32), seed=44, sigma_log=1.0, corr_cells=3.0),
         pi.make_custom(37, 29, 61, (13, 8), seed=45, sigma_log=1.0),
+        pi.make_custom(11, 10, 30, (18, 20), seed=47, sigma_log=0.5, corr_cells=3.0),
         pi.make_custom(6, 9, 16, (5, 12), seed=46, sigma_log=0.5, corr_cells=2.0),
     ]
     cells[-1].b = np.zeros_like(cells[-1].b)   # converged before the first iteration
