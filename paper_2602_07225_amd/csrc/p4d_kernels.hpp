@@ -293,6 +293,9 @@ __device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
     const int ni = fine_of(A.fx, I, fi, wi);
     const int nj = fine_of(A.fy, J, fj, wj);
     const int nk = fine_of(A.cz == A.fz ? 1 : A.fz, K, fk, wk);   // (z kept: identity)
+    // issued with the residual loads (after the store below it would wait
+    // for them first)
+    const double idc = A.xc1 ? (double)A.invdc[n] : 0.0;
     // fixed trip counts, so that the index arrays stay in registers
     double acc = 0.0;
 #pragma unroll
@@ -311,7 +314,7 @@ __device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
     }
     const T bc = (T)acc;
     A.bc[n] = bc;
-    if (A.xc1) A.xc1[n] = A.c2c * (double)A.invdc[n] * (double)bc;
+    if (A.xc1) A.xc1[n] = A.c2c * idc * (double)bc;
 }
 
 // x_f += P x_c
@@ -401,6 +404,9 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
     const int k = (int)(n / ((long long)g.nx * g.ny));
     double rpe = r[g.off_pe + n] * rscale;
     double rce = r[g.off_ce + n] * rscale;
+    // every load is issued before the first store (a load after a store of
+    // a computed value would wait for that computation's loads first)
+    const double idpe = (double)invd0[g.off_pe + n], idce = (double)invd0[g.off_ce + n];
     const int el = node_mat(g, k);
     if (el >= 0) {
         const long long base = el == 0 ? 0 : g.nea;
@@ -408,6 +414,7 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
         const long long je = base + n - klo * g.nx * g.ny;
         const bool dir = (k == 0);
         double rps = r[je] * rscale;
+        const double idps = dir ? 0.0 : (double)invd0[je];
         if (SCHUR) {
             const RadialTab &Tb = R.tabs[el];
             const int N = Tb.N;
@@ -445,13 +452,13 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
         }
         const T bps = (T)rps;
         b0[je] = bps;
-        if (!dir) R.x1[je] = (el == 0 ? R.c2box[0] : R.c2box[1]) * (double)invd0[je] * (double)bps;
+        if (!dir) R.x1[je] = (el == 0 ? R.c2box[0] : R.c2box[1]) * idps * (double)bps;
     }
     const T bpe = (T)rpe, bce = (T)rce;
     b0[g.off_pe + n] = bpe;
     b0[g.off_ce + n] = bce;
-    R.x1[g.off_pe + n] = R.c2box[2] * (double)invd0[g.off_pe + n] * (double)bpe;
-    R.x1[g.off_ce + n] = R.c2box[3] * (double)invd0[g.off_ce + n] * (double)bce;
+    R.x1[g.off_pe + n] = R.c2box[2] * idpe * (double)bpe;
+    R.x1[g.off_ce + n] = R.c2box[3] * idce * (double)bce;
 }
 
 // z_s,j = A_ss,j^-1 r_s,j - delta_j A_ss,j^-1 e_N, and by Sherman-Morrison
@@ -468,15 +475,16 @@ __device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const dou
     const int el = node_mat(g, k);
     const double zpe = R.x0[2][g.off_pe + n];
     const double zce = R.x0[3][g.off_ce + n];
-    z[g.off_pe + n] = (TZ)zpe;
-    z[g.off_ce + n] = (TZ)zce;
-    if (el < 0) return;
+    if (el < 0) {
+        z[g.off_pe + n] = (TZ)zpe;
+        z[g.off_ce + n] = (TZ)zce;
+        return;
+    }
     const long long base = el == 0 ? 0 : g.nea;
     const long long klo = el == 0 ? 0 : g.na + g.ns;
     const long long je = base + n - klo * g.nx * g.ny;
     const bool dir = (k == 0);
     const double zps = dir ? r[je] * rscale : (el == 0 ? R.x0[0] : R.x0[1])[je];
-    z[je] = (TZ)zps;
     const RadialTab &Tb = R.tabs[el];
     const int N = Tb.N;
     const long long nn = el == 0 ? g.nea : g.nec;
@@ -499,6 +507,11 @@ __device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const dou
     double rv[NRMAX];
 #pragma unroll
     for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
+    // the electrode-level outputs are stored only now, after every load is
+    // issued (a load after them would wait for the loads they depend on)
+    z[g.off_pe + n] = (TZ)zpe;
+    z[g.off_ce + n] = (TZ)zce;
+    z[je] = (TZ)zps;
     T y[NRMAX];
     y[0] = (T)(rv[0] * rscale);
     T ylast = y[0];
