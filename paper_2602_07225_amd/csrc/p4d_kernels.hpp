@@ -685,6 +685,14 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
     const double *b = O.b;
     double sq = 0.0;
     const double xpe = P.xpe, xce = P.xce;
+    // b - A x: every value of b this node needs is loaded before its first
+    // store (a load after a store may not be hoisted above it, pointers may
+    // alias, and would wait for the loads the stored value depends on)
+    double bpe = 0.0, bce = 0.0;
+    if (RESID) {
+        bpe = b[g.off_pe + n];
+        bce = b[g.off_ce + n];
+    }
     double ype, yce;
     if (GEN) {
         ype = (TRANS ? P.Kpe : P.Kpe + P.Kx) + P.Npe;
@@ -712,22 +720,27 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
         double *ys = y + offs + jl;
         const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
         // the particle column, loaded at once (indices clamped to the last point)
-        double xr[NRMAX];
-        double xsN = 0.0;
+        double xr[NRMAX], bv[NRMAX];
+        double xsN = 0.0, bps = 0.0;
         if (!RED) {
 #pragma unroll
             for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+            if (RESID) {
+#pragma unroll
+                for (int r = 0; r < NRMAX; r++) bv[r] = b[offs + jl + (long long)(r < N ? r : N - 1) * nn];
+            }
             xsN = xr[0];
 #pragma unroll
             for (int r = 1; r < NRMAX; r++)
                 if (r == N - 1) xsN = xr[r];
         }
+        if (RESID) bps = b[je];
         const OpCoupling cp = op_coupling<TRANS>(g, T, dir, m, gj, sj, ej, P.xpsc, xpe, xce, xsN);
         const double q = RED ? cp.q * O.om[je] : cp.q, r3 = cp.r3;
         double yps = dir ? xps : P.Kps + cp.r0 * q;
         ype += cp.r1 * q;
         yce += cp.r2 * q;
-        if (RESID) yps = b[je] - yps;
+        if (RESID) yps = bps - yps;
         y[je] = yps;
         sq += yps * yps;
 #pragma unroll
@@ -739,15 +752,15 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
                 const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
                 double v = op_radial_row(T, TRANS, r, N, xm, x0, xp);
                 if (r == N - 1) v += r3 * q;
-                if (RESID) v = b[offs + jl + (long long)r * nn] - v;
+                if (RESID) v = bv[r] - v;
                 ys[(long long)r * nn] = v;
                 sq += v * v;
             }
         }
     }
     if (RESID) {
-        ype = b[g.off_pe + n] - ype;
-        yce = b[g.off_ce + n] - yce;
+        ype = bpe - ype;
+        yce = bce - yce;
     }
     y[g.off_pe + n] = ype;
     y[g.off_ce + n] = yce;
