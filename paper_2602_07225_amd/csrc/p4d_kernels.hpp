@@ -1097,16 +1097,22 @@ __device__ inline void operator_radial(const Geom &g, const OpArgs &O, const dou
 #pragma unroll
     for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
     const double r3 = TRANS ? O.ss[je] : T.Gamma, qj = q[je];
+    // all rows first, then the stores: a table read after a store may not be
+    // hoisted above it (the pointers may alias), which would chain the rows'
+    // cache latencies
+    double v[NRMAX];
 #pragma unroll
     for (int r = 0; r < NRMAX; r++) {
         if (r < N) {
             const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
             const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
-            double v = op_radial_row(T, TRANS, r, N, xm, xr[r], xp);
-            if (r == N - 1) v += r3 * qj;   // the same expression as in operator_finish
-            ys[(long long)r * nn] = v;
+            v[r] = op_radial_row(T, TRANS, r, N, xm, xr[r], xp);
+            if (r == N - 1) v[r] += r3 * qj;   // the same expression as in operator_finish
         }
     }
+#pragma unroll
+    for (int r = 0; r < NRMAX; r++)
+        if (r < N) ys[(long long)r * nn] = v[r];
 }
 
 }  // namespace p4d
