@@ -905,7 +905,7 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
     const long long layer = (long long)g.nx * g.ny;
 
     double pe[2], ce[2], ps[2], kp[2], sg[2];
-    auto fetch_planes_to = [&](int kk, double pe[2], double ce[2], double ps[2]) {
+    auto fetch_planes_to = [&](int kk, double vpe[2], double vce[2], double vps[2]) {
         const int el = (kk >= 0 && kk < g.nz) ? node_mat(g, kk) : -1;
         const bool has_ps = el >= 0 && kk != 0;
         const long long psb = el == 0 ? 0 : g.nea - (long long)(g.na + g.ns) * layer;
@@ -916,23 +916,23 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             const bool ok = q < PX * PY && kk >= 0 && kk < g.nz && ii >= 0 && ii < g.nx && jj >= 0 &&
                             jj < g.ny;
             const long long nd = ii + g.nx * (jj + (long long)g.ny * kk);
-            pe[h] = ok ? ldx(x + g.off_pe + nd) : 0.0;
-            ce[h] = ok ? ldx(x + g.off_ce + nd) : 0.0;
-            ps[h] = (ok && has_ps) ? ldx(x + (psb + nd)) : 0.0;
+            vpe[h] = ok ? ldx(x + g.off_pe + nd) : 0.0;
+            vce[h] = ok ? ldx(x + g.off_ce + nd) : 0.0;
+            vps[h] = (ok && has_ps) ? ldx(x + (psb + nd)) : 0.0;
         }
     };
-    auto store_planes_from = [&](int slot, const double pe[2], const double ce[2], const double ps[2]) {
+    auto store_planes_from = [&](int slot, const double vpe[2], const double vce[2], const double vps[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
             if (q < PX * PY) {
-                L.pe[slot][q] = pe[h];
-                L.ce[slot][q] = ce[h];
-                L.ps[slot][q] = ps[h];
+                L.pe[slot][q] = vpe[h];
+                L.ce[slot][q] = vce[h];
+                L.ps[slot][q] = vps[h];
             }
         }
     };
-    auto fetch_elems_to = [&](int ek, double kp[2], double sg[2]) {
+    auto fetch_elems_to = [&](int ek, double vkp[2], double vsg[2]) {
         const bool lay = ek >= 0 && ek < g.nz - 1;
 #pragma unroll
         for (int h = 0; h < 2; h++) {
@@ -940,17 +940,17 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
             const int ei = i0 - 1 + q % EX, ej = j0 - 1 + q / EX;
             const bool ok = q < EX * EY && lay && ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1;
             const long long id = ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek);
-            kp[h] = ok ? O.kaph[id] : 0.0;
-            sg[h] = ok ? O.sigh[id] : 0.0;
+            vkp[h] = ok ? O.kaph[id] : 0.0;
+            vsg[h] = ok ? O.sigh[id] : 0.0;
         }
     };
-    auto store_elems_from = [&](int slot, const double kp[2], const double sg[2]) {
+    auto store_elems_from = [&](int slot, const double vkp[2], const double vsg[2]) {
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int q = threadIdx.x + h * kBlock;
             if (q < EX * EY) {
-                L.kap[slot][q] = kp[h];
-                L.sig[slot][q] = sg[h];
+                L.kap[slot][q] = vkp[h];
+                L.sig[slot][q] = vsg[h];
             }
         }
     };
