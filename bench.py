@@ -304,7 +304,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the solver has no multi-GPU sharding)", file=sys.stderr)
         sys.exit(2)
 
     global np
