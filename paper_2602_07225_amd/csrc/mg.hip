@@ -237,19 +237,14 @@ template void launch_dcorr<double>(const Geom &, const double *, const double *,
 template void launch_dcorr<float>(const Geom &, const double *, const double *, const double *,
                                   const double *, float *, hipStream_t);
 
-// 27-point stencil (SoA [27][n]) of the level-0 operator of one box
-__global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, int ek_lo, int ek_hi,
-                                                      int mass, const double *__restrict__ cK,
-                                                      const double *__restrict__ dcorr,
-                                                      double *__restrict__ S)
+// row n (box-local) of the level-0 operator of one box, 27-point pattern
+__device__ inline void assemble0_row(const Geom &g, const Elem0 &E, int n, double row[27])
 {
-    const int n = blockIdx.x * kBlock + threadIdx.x;
-    const int nb = g.nx * g.ny * nzb;
-    if (n >= nb) return;
+    const int nzb = E.nzb, k0 = E.k0, ek_lo = E.ek_lo, ek_hi = E.ek_hi, mass = E.mass;
+    const double *cK = E.cK, *dcorr = E.dcorr;
     const int i = n % g.nx, t = n / g.nx;
     const int j = t % g.ny, kl = t / g.ny;
     const int k = kl + k0;
-    double row[27];
 #pragma unroll
     for (int o = 0; o < 27; o++) row[o] = 0.0;
 #pragma unroll
@@ -274,6 +269,19 @@ __global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, i
         }
     }
     row[13] += dcorr[n];
+}
+
+// 27-point stencil (SoA [27][n]) of the level-0 operator of one box
+__global__ __launch_bounds__(kBlock) void k_assemble0(Geom g, int nzb, int k0, int ek_lo, int ek_hi,
+                                                      int mass, const double *__restrict__ cK,
+                                                      const double *__restrict__ dcorr,
+                                                      double *__restrict__ S)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const int nb = g.nx * g.ny * nzb;
+    if (n >= nb) return;
+    double row[27];
+    assemble0_row(g, Elem0{nzb, k0, ek_lo, ek_hi, mass, cK, dcorr}, n, row);
 #pragma unroll
     for (int o = 0; o < 27; o++) S[(long long)o * nb + n] = row[o];
 }
@@ -311,8 +319,10 @@ __device__ constexpr int slot_ax(int a, int d1, int d2)
     return nb_index(AX == 0 ? a : d1, AX == 0 ? d1 : (AX == 1 ? a : d2), AX == 2 ? a : d2);
 }
 
-template <int AX>
-__global__ __launch_bounds__(kBlock) void k_rap1d(RapBatch rb)
+// ELEM (x pass of the first coarsening only): the fine rows are formed from
+// the level-0 element data instead of read from a stored stencil
+template <int AX, bool ELEM>
+__global__ __launch_bounds__(kBlock) void k_rap1d(Geom g, RapBatch rb)
 {
     const RapArgs &A = rb.a[find_box(rb, blockIdx.x)];
     const int nx = A.nx, ny = A.ny, nz = A.nz;
@@ -337,8 +347,12 @@ __global__ __launch_bounds__(kBlock) void k_rap1d(RapBatch rb)
         const long long row = i + (long long)nx * (j + (long long)ny * k);
         const double *__restrict__ S = A.Sf;
         double sv[27];
+        if (ELEM) {
+            assemble0_row(g, A.e0, (int)row, sv);
+        } else {
 #pragma unroll
-        for (int o = 0; o < 27; o++) sv[o] = S[(long long)o * nf + row];
+            for (int o = 0; o < 27; o++) sv[o] = S[(long long)o * nf + row];
+        }
 #pragma unroll
         for (int da = -1; da <= 1; da++) {
             double W[3];
@@ -359,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_rap1d(RapBatch rb)
 
 // P^T S P for up to four boxes at once; job b needs job.tmp with room for
 // 27 * (cx*fy*fz + cx*cy*fz) doubles
-void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st)
+void launch_rap(const Geom &g, const RapJob *jobs, int njobs, int zc, hipStream_t st)
 {
     RapBatch r[3] = {};
     int blk[3] = {0, 0, 0};
@@ -370,17 +384,18 @@ void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st)
         double *t1 = J.tmp;                                  // (cx, fy, fz)
         double *t2 = J.tmp + 27LL * cx * J.fy * J.fz;        // (cx, cy, fz)
         const int n1 = cx * J.fy * J.fz, n2 = cx * cy * J.fz, n3 = cx * cy * cz;
-        r[0].a[b] = RapArgs{J.fx, J.fy, J.fz, blk[0], J.Sf, t1};
-        r[1].a[b] = RapArgs{cx, J.fy, J.fz, blk[1], t1, zc ? t2 : J.Sc};
-        r[2].a[b] = RapArgs{cx, cy, J.fz, blk[2], t2, J.Sc};
+        r[0].a[b] = RapArgs{J.fx, J.fy, J.fz, blk[0], J.Sf, t1, J.e0};
+        r[1].a[b] = RapArgs{cx, J.fy, J.fz, blk[1], t1, zc ? t2 : J.Sc, Elem0{}};
+        r[2].a[b] = RapArgs{cx, cy, J.fz, blk[2], t2, J.Sc, Elem0{}};
         blk[0] += (n1 + kBlock - 1) / kBlock;
         blk[1] += (n2 + kBlock - 1) / kBlock;
         blk[2] += (n3 + kBlock - 1) / kBlock;
     }
     if (!njobs) return;
-    hipLaunchKernelGGL(k_rap1d<0>, dim3(blk[0]), dim3(kBlock), 0, st, r[0]);
-    hipLaunchKernelGGL(k_rap1d<1>, dim3(blk[1]), dim3(kBlock), 0, st, r[1]);
-    if (zc) hipLaunchKernelGGL(k_rap1d<2>, dim3(blk[2]), dim3(kBlock), 0, st, r[2]);
+    if (jobs[0].Sf) hipLaunchKernelGGL((k_rap1d<0, false>), dim3(blk[0]), dim3(kBlock), 0, st, g, r[0]);
+    else hipLaunchKernelGGL((k_rap1d<0, true>), dim3(blk[0]), dim3(kBlock), 0, st, g, r[0]);
+    hipLaunchKernelGGL((k_rap1d<1, false>), dim3(blk[1]), dim3(kBlock), 0, st, g, r[1]);
+    if (zc) hipLaunchKernelGGL((k_rap1d<2, false>), dim3(blk[2]), dim3(kBlock), 0, st, g, r[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,6 +578,31 @@ __global__ __launch_bounds__(kBlock) void k_max_final(const double *__restrict__
 void launch_diag(int n, const double *S, double *invd, double *part, int nblk, hipStream_t st)
 {
     hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(kBlock), 0, st, n, S, invd, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag0(Geom g, Elem0 E, int n, double *__restrict__ invd,
+                                                  double *__restrict__ part)
+{
+    __shared__ double red[4];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double ratio = 0.0;
+    if (t < n) {
+        double row[27];
+        assemble0_row(g, E, t, row);
+        double sum = 0.0;
+        for (int o = 0; o < 27; o++) sum += fabs(row[o]);
+        const double dg = row[13];
+        invd[t] = 1.0 / dg;
+        ratio = sum / dg;
+    }
+    const double m = block_max(ratio, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+void launch_diag0(const Geom &g, const Elem0 &E, int n, double *invd, double *part, int nblk,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag0, dim3(nblk), dim3(kBlock), 0, st, g, E, n, invd, part);
 }
 void launch_max_final(const double *part, int nblk, double *out, hipStream_t st)
 {

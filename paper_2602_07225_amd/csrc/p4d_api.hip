@@ -970,6 +970,11 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     }
     double *raptmp = (double *)take(8 * 4 * (rapmax ? rapmax : 1));   // one slice per box
     InvBatch ib{};
+    Elem0 E0[4];
+    for (int b = 0; b < 4; b++) {
+        const Box &B = c->box[b];
+        E0[b] = Elem0{B.lev[0].nz, B.k0, B.ek_lo, B.ek_hi, B.mass, B.cK, dc64 + B.off};
+    }
     launch_dcorr<double>(g, c->gg, c->ee, c->mm, c->omega, dc64, st);
     launch_cast<T>(g.Nm, dc64, (T *)c->dcorr0, st);
     // inverse diagonal of level 0 defaults to 0 outside the boxes (the
@@ -985,11 +990,11 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 Box &B = c->box[b];
                 if (B.nlev <= l) continue;
                 const Level &F = B.lev[l - 1];
-                jobs[nj] = RapJob{F.nx, F.ny, F.nz, l == 1 ? S0[b] : F.S64, B.lev[l].S64,
-                                  raptmp + (size_t)nj * rapmax};
+                jobs[nj] = RapJob{F.nx, F.ny, F.nz, l == 1 ? (zline ? S0[b] : nullptr) : F.S64,
+                                  B.lev[l].S64, raptmp + (size_t)nj * rapmax, l == 1 ? E0[b] : Elem0{}};
                 nj++;
             }
-            launch_rap(jobs, nj, !zline, st);
+            launch_rap(g, jobs, nj, !zline, st);
         }
         for (int b = 0; b < 4; b++) {
             Box &B = c->box[b];
@@ -997,8 +1002,12 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
             Level &L = B.lev[l];
             const double *Sl;
             if (l == 0) {
-                launch_assemble0(g, b, L.nz, B.k0, B.ek_lo, B.ek_hi, B.mass, B.cK, dc64 + B.off,
-                                 S0[b], st);
+                // the stored level-0 stencil is needed only by z-line smoothing
+                // and by a level-0 coarsest grid; otherwise its rows are formed
+                // where they are used (diagonal, first Galerkin product)
+                if (zline || B.nlev == 1)
+                    launch_assemble0(g, b, L.nz, B.k0, B.ek_lo, B.ek_hi, B.mass, B.cK, dc64 + B.off,
+                                     S0[b], st);
                 Sl = S0[b];
             } else {
                 Sl = L.S64;
@@ -1007,7 +1016,8 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
             if (zline && L.Sz) launch_zline_order(L.nx, L.ny, L.nz, Sl, L.Sz, st);
             const int nblk = (L.n + kBlock - 1) / kBlock;
             double *idst = l == 0 ? id64 + B.off : idl;   // FP64 inverse diagonal
-            launch_diag(L.n, Sl, idst, c->red, nblk, st);
+            if (l == 0 && !zline && B.nlev > 1) launch_diag0(g, E0[b], L.n, idst, c->red, nblk, st);
+            else launch_diag(L.n, Sl, idst, c->red, nblk, st);
             launch_max_final(c->red, nblk, c->scal + 16 * b + l, st);
             if (l > 0) launch_cast<T>(L.n, idl, (T *)L.invd, st);
             if (l == B.nlev - 1) {

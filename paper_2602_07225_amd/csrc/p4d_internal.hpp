@@ -185,11 +185,19 @@ void launch_assemble0(const Geom &g, int box, int nz, int k0, int ek_lo, int ek_
                       const double *cK, const double *dcorr, double *S, hipStream_t st);
 // Galerkin product P^T S P as three 1D coarsenings (x, y, z), for up to four
 // boxes per launch; tmp of each job needs 27 * (cx*fy*fz + cx*cy*fz) doubles
+// Level-0 rows of one multigrid box from its element data (the arguments of
+// the level-0 assembly): formed on the fly where the stored stencil would
+// only be read once
+struct Elem0 {
+    int nzb, k0, ek_lo, ek_hi, mass;
+    const double *cK, *dcorr;
+};
 struct RapArgs {
     int nx, ny, nz;          // input dims of this 1D coarsening
     int blk0;
-    const double *Sf;
+    const double *Sf;        // null: level-0 rows from e0
     double *Sc;
+    Elem0 e0;
 };
 struct RapBatch {
     int nbox;
@@ -197,12 +205,14 @@ struct RapBatch {
 };
 struct RapJob {
     int fx, fy, fz;
-    const double *Sf;
+    const double *Sf;        // null: level-0 rows formed from e0
     double *Sc;
     double *tmp;
+    Elem0 e0;
 };
-// zc = 0: z is not coarsened (P_z = I), the x and y passes only
-void launch_rap(const RapJob *jobs, int njobs, int zc, hipStream_t st);
+// zc = 0: z is not coarsened (P_z = I), the x and y passes only; the jobs
+// either all read a stored stencil or all form level-0 rows
+void launch_rap(const Geom &g, const RapJob *jobs, int njobs, int zc, hipStream_t st);
 
 // z-line smoothing of up to four boxes of one level (FP64, full stencils
 // [27][n]): block Gauss-Seidel over the lines of one colour (x parity
@@ -230,6 +240,9 @@ void launch_resid_full(LineBatch lb, hipStream_t st);
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
+// the same for level 0 with its rows formed from the element data
+void launch_diag0(const Geom &g, const Elem0 &E, int n, double *invd, double *ratio_partial, int nblk,
+                  hipStream_t st);
 void launch_max_final(const double *partial, int nblk, double *out, hipStream_t st);
 void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *A,
                                hipStream_t st);
