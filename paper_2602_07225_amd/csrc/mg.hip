@@ -710,30 +710,44 @@ void launch_invert(const InvBatch &ib, hipStream_t st)
         hipLaunchKernelGGL(k_invert, dim3(ib.nbox), dim3(1024), 0, st, ib);
 }
 
-// stored stencil for the smoother: off-diagonal entries as they are, the
-// centre slot replaced by the row sum formed in FP64
+
+// A coarse level's smoother data in one pass over its stored Galerkin
+// stencil: the difference form in T (slot 0 the row sum formed in FP64,
+// slots 1..13 the upper half as they are), the inverse diagonal in T (formed
+// in FP64), and the block maximum of the Gershgorin ratio
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_stencil_diff(int n, const double *__restrict__ S,
-                                                        T *__restrict__ D)
+__global__ __launch_bounds__(kBlock) void k_level_prep(int n, const double *__restrict__ S,
+                                                       T *__restrict__ D, T *__restrict__ invd,
+                                                       double *__restrict__ part)
 {
+    __shared__ double red[4];
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n) return;
-    double rs = 0.0;
-    for (int o = 0; o < 27; o++) {
-        const double v = S[(long long)o * n + t];
-        rs += v;
-        if (o > 13) D[(long long)(o - 13) * n + t] = (T)v;
+    double ratio = 0.0;
+    if (t < n) {
+        double rs = 0.0, sum = 0.0;
+        for (int o = 0; o < 27; o++) {
+            const double v = S[(long long)o * n + t];
+            rs += v;
+            sum += fabs(v);
+            if (o > 13) D[(long long)(o - 13) * n + t] = (T)v;
+        }
+        D[t] = (T)rs;
+        const double dg = S[13LL * n + t];
+        invd[t] = (T)(1.0 / dg);
+        ratio = sum / dg;
     }
-    D[t] = (T)rs;
+    const double m = block_max(ratio, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = m;
 }
 template <typename T>
-void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st)
+void launch_level_prep(int n, const double *S, T *D, T *invd, double *part, int nblk, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_stencil_diff<T>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, n,
-                       S, D);
+    hipLaunchKernelGGL((k_level_prep<T>), dim3(nblk), dim3(kBlock), 0, st, n, S, D, invd, part);
 }
-template void launch_stencil_diff<double>(int, const double *, double *, hipStream_t);
-template void launch_stencil_diff<float>(int, const double *, float *, hipStream_t);
+template void launch_level_prep<double>(int, const double *, double *, double *, double *, int,
+                                        hipStream_t);
+template void launch_level_prep<float>(int, const double *, float *, float *, double *, int,
+                                       hipStream_t);
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cast(long long n, const double *__restrict__ s,

@@ -351,10 +351,9 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
     // inverse diagonal + dense coarse matrix
     size_t s0 = 0;
     for (int b = 0; b < 4; b++) s0 += align_up(8 * 27 * (size_t)c->box[b].lev[0].n);
-    size_t n1max = 0, rapmax = 0;
+    size_t rapmax = 0;
     for (int b = 0; b < 4; b++) {
         const Box &B = c->box[b];
-        if (B.nlev > 1 && (size_t)B.lev[1].n > n1max) n1max = B.lev[1].n;
         for (int l = 0; l + 1 < B.nlev; l++) {
             const Level &F = B.lev[l];
             const size_t cx = coarse_n_h(F.nx), cy = coarse_n_h(F.ny);
@@ -362,8 +361,7 @@ static size_t carve(p4d_ctx *c, const p4d_solve_opts &o, char *base)
             rapmax = t > rapmax ? t : rapmax;
         }
     }
-    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * n1max) + align_up(8 * 4 * rapmax) +
-          align_up(setup_need);
+    s0 += 2 * align_up(8 * (size_t)Nm) + align_up(8 * 4 * rapmax) + align_up(setup_need);
     // Krylov basis
     const int m = o.restart;
     const size_t zs = o.z_fp32 ? sizeof(float) : sizeof(double);
@@ -954,10 +952,6 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
         S0[b] = zline ? c->box[b].lev[0].S64 : (double *)take(8 * 27 * (size_t)c->box[b].lev[0].n);
     double *dc64 = (double *)take(8 * (size_t)g.Nm);
     double *id64 = (double *)take(8 * (size_t)g.Nm);
-    size_t n1max = 0;
-    for (int b = 0; b < 4; b++)
-        if (c->box[b].nlev > 1 && (size_t)c->box[b].lev[1].n > n1max) n1max = c->box[b].lev[1].n;
-    double *idl = (double *)take(8 * (n1max ? n1max : 1));   // FP64 inverse diagonal, l >= 1
     size_t rapmax = 0;
     for (int b = 0; b < 4; b++) {
         const Box &B = c->box[b];
@@ -1011,15 +1005,16 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 Sl = S0[b];
             } else {
                 Sl = L.S64;
-                launch_stencil_diff<T>(L.n, L.S64, (T *)L.S, st);
             }
             if (zline && L.Sz) launch_zline_order(L.nx, L.ny, L.nz, Sl, L.Sz, st);
             const int nblk = (L.n + kBlock - 1) / kBlock;
-            double *idst = l == 0 ? id64 + B.off : idl;   // FP64 inverse diagonal
-            if (l == 0 && !zline && B.nlev > 1) launch_diag0(g, E0[b], L.n, idst, c->red, nblk, st);
-            else launch_diag(L.n, Sl, idst, c->red, nblk, st);
+            if (l > 0)   // difference form, inverse diagonal and bound in one pass
+                launch_level_prep<T>(L.n, Sl, (T *)L.S, (T *)L.invd, c->red, nblk, st);
+            else if (!zline && B.nlev > 1)
+                launch_diag0(g, E0[b], L.n, id64 + B.off, c->red, nblk, st);
+            else
+                launch_diag(L.n, Sl, id64 + B.off, c->red, nblk, st);
             launch_max_final(c->red, nblk, c->scal + 16 * b + l, st);
-            if (l > 0) launch_cast<T>(L.n, idl, (T *)L.invd, st);
             if (l == B.nlev - 1) {
                 if (L.n > 1024) return fail(c, P4D_ERR_INVALID_ARG, "coarsest grid above 1024 nodes");
                 double *dense = (double *)take(8 * (size_t)L.n * L.n);

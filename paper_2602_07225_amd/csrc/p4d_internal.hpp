@@ -240,6 +240,12 @@ void launch_resid_full(LineBatch lb, hipStream_t st);
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
                  hipStream_t st);
+// levels >= 1 in one pass: the smoother's stored stencil D in T (slot 0 the
+// row sum formed in FP64, slots 1..13 the upper half), the inverse diagonal
+// in T, Gershgorin ratio block maxima in ratio_partial
+template <typename T>
+void launch_level_prep(int n, const double *S, T *D, T *invd, double *ratio_partial, int nblk,
+                       hipStream_t st);
 // the same for level 0 with its rows formed from the element data
 void launch_diag0(const Geom &g, const Elem0 &E, int n, double *invd, double *ratio_partial, int nblk,
                   hipStream_t st);
@@ -266,8 +272,6 @@ void launch_omega(const Geom &g, const RadialTab *tabs, const double *ss, int sc
                   double *omega, hipStream_t st);
 template <typename T>
 void launch_cast(long long n, const double *src, T *dst, hipStream_t st);
-template <typename T>
-void launch_stencil_diff(int n, const double *S, T *D, hipStream_t st);
 
 // operator.hip: the Schur complement of the particle blocks (electrode-level
 // vectors of length Nm)
