@@ -17,7 +17,9 @@ Parity status of each oracle function (pins in ``tests/test_oracle_*.py``):
   full operator / transpose       pinned (above + dot-product identity)
   Galerkin RAP                    pinned (equals coarse-grid Q1 assembly)
   Chebyshev smoother              pinned (closed-form Chebyshev polynomial)
-  V-cycle                         pinned (symmetry, convergence as iteration)
+  V-cycle                         pinned (symmetry, convergence as iteration,
+                                  two-grid cycle equal to the dense composed
+                                  error propagation)
   preconditioner                  pinned (dense block-LDU with exact Schur
                                   diagonal blocks on tiny meshes)
   FGMRES solve                    pinned (dense LU; manufactured solution)

@@ -7,6 +7,13 @@ TEST INFRASTRUCTURE ONLY: nothing in the product path imports this module.
 Plain numpy loops over nodes and elements; the linear algebra is the C
 oracle (pinned separately).
 
+Parity status: the material functions (open-circuit potentials, bulk
+conductivity and diffusivity, their derivatives) and the 1C current are
+pinned against the appendix's printed formulas and tables read by a separate
+LaTeX reader (tests/test_oracle_appendix.py); the residual and Newton matrix
+against central differences, the rest state, charge balance and lithium
+conservation (tests/test_oracle_phys.py).
+
 Readings (each also listed in the design notes):
   - the transport coefficients of an element are evaluated at the mean of
     its eight nodal c_e (kappa_eff, D_e_eff and the diffusion-potential

@@ -166,3 +166,54 @@ def test_fine_operator_is_schur_block():
     S3 = qref.stencil_to_dense(nodes, orc.mg_stencil(3, 0))
     assert np.allclose(S2, Kk + np.diag(dg), atol=1e-14 * np.abs(Kk).max())
     assert np.allclose(S3, Me + Kk + np.diag(de), atol=1e-14 * np.abs(Kk).max())
+
+
+def _interp_1d(n):
+    """Linear interpolation from the coarse points ('even indices plus the
+    last') to the n fine points, from the coarse coordinates."""
+    xc = qref.coarse_coords(np.arange(n, dtype=float))
+    P = np.zeros((n, len(xc)))
+    for i in range(n):
+        I = min(np.searchsorted(xc, i, side="right") - 1, len(xc) - 2)
+        t = (i - xc[I]) / (xc[I + 1] - xc[I])
+        P[i, I] += 1 - t
+        P[i, I + 1] += t
+    return P
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3])
+def test_two_grid_vcycle_is_the_composed_error_propagation(deg):
+    """With the coarse level solved exactly, the V-cycle from x = 0 is
+    V = (I - E) S^-1 with the error propagation
+        E = q(D^-1 S) (I - P S_c^-1 P^T S) q(D^-1 S),   S_c = P^T S P,
+    q the degree-k Chebyshev polynomial on [lmax/4, lmax] (lmax the
+    Gershgorin bound of D^-1 S), P the tensor-product linear interpolation.
+    Everything on the right is built densely here from the fine stencil
+    alone, so a restriction that is not P^T (a scaled one), a coarse
+    operator that is not the Galerkin product, or a post-smoother that
+    differs from the pre-smoother fails, although each keeps V symmetric."""
+    p = pi.make_custom(6, 5, 13, (6, 6), seed=3, sigma_log=1.0, corr_cells=3.0)
+    orc = O.Oracle(p)
+    orc.setup(coarse_max=100, cheb_degree=deg)
+    for box in range(4):
+        lv = orc.mg_levels(box)
+        assert len(lv) == 2, lv
+        dims = lv[0][0]
+        n = dims[0] * dims[1] * dims[2]
+        S = qref.stencil_to_dense(dims, orc.mg_stencil(box, 0))
+        d = np.diag(S)
+        lmax = np.max(np.abs(S).sum(axis=1) / d)
+        lmin = lmax / 4
+        theta, delta = (lmax + lmin) / 2, (lmax - lmin) / 2
+        C = S / np.sqrt(np.outer(d, d))
+        lam, Q = np.linalg.eigh(C)
+        Tk = np.zeros(deg + 1); Tk[-1] = 1.0
+        q = npcheb.chebval((theta - lam) / delta, Tk) / npcheb.chebval(theta / delta, Tk)
+        Qp = np.diag(1 / np.sqrt(d)) @ ((Q * q) @ Q.T) @ np.diag(np.sqrt(d))
+        P = np.kron(_interp_1d(dims[2]), np.kron(_interp_1d(dims[1]), _interp_1d(dims[0])))
+        Sc = P.T @ S @ P
+        cgc = np.eye(n) - P @ np.linalg.solve(Sc, P.T @ S)
+        E = Qp @ cgc @ Qp
+        ref = (np.eye(n) - E) @ np.linalg.inv(S)
+        got = np.stack([orc.vcycle(box, e) for e in np.eye(n)], axis=1)
+        assert np.allclose(got, ref, atol=1e-11 * np.abs(ref).max()), (box, np.abs(got - ref).max())
