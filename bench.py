@@ -62,6 +62,36 @@ def measured_traffic(kernel_class):
 FIELD_NAMES = ("phi_s", "phi_e", "c_e", "c_s")
 
 
+def cpu_model():
+    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def field_errors(p, x, ref):
+    """Relative error of x against ref overall and per field block."""
+    o = list(p.offsets)
+    names = ("phi_s", "phi_e", "c_e", "c_s_anode", "c_s_cathode")
+    out = {"all": float(np.linalg.norm(x - ref) / np.linalg.norm(ref))}
+    for nm, a, b in zip(names, o[:-1], o[1:]):
+        nb = np.linalg.norm(ref[a:b])
+        out[nm] = float(np.linalg.norm(x[a:b] - ref[a:b]) / (nb if nb > 0 else 1.0))
+    return out
+
+
 def bgs_sweep(s, b, base):
     """Block Gauss-Seidel (eq. PGS) in each of the 24 field orderings (the
     ordering study of Sec. 5): iterations and time of one step each (setup +
@@ -183,6 +213,14 @@ def bench_batch(steps):
     B.set_pc_mode(0)
     out["speedup_batched_vs_per_cell"] = (out["per_cell_launches"]["solve_ms"] /
                                           out["batched_stage_launches"]["solve_ms"])
+    # per mesh side, the cell with the fewest unknowns: its FP32-preconditioned
+    # solution, for the comparison with the oracle in the CPU leg
+    xs, _ = B.solve(bs)
+    pick = {}
+    for i, p in enumerate(cells):
+        if p.nx not in pick or p.N < cells[pick[p.nx]].N:
+            pick[p.nx] = i
+    out["_sample"] = [(i, xs[i].cpu().numpy()) for i in sorted(pick.values())]
     B.close()
     return out
 
@@ -317,7 +355,9 @@ def main():
 
     torch.cuda.set_device(0)
     if args.batch_only:
-        print(json.dumps({"C4_batch_64_cells": bench_batch(args.steps)}), flush=True)
+        bat = bench_batch(args.steps)
+        bat.pop("_sample", None)
+        print(json.dumps({"C4_batch_64_cells": bat}), flush=True)
         return
     if args.case3_only:
         print(json.dumps({"case3_like_roll": bench_case3()}), flush=True)
@@ -400,6 +440,8 @@ def main():
     s.setup(**fp64)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    # GPU solutions kept on the host for the comparison with the oracle
+    keep = {"C2_fp64": x64.cpu().numpy()}
     extras = {"setup_ms": 1e3 * t_setup,
               "solve_ms": ms_step - 1e3 * t_setup,
               "iters_per_solve": iters / args.steps,
@@ -411,6 +453,7 @@ def main():
         # basis stays FP64 (its near-null component would swamp FP32 storage)
         fp32 = dict(fp64, pc_prec=L.P4D_FP32)
         x32, i32, it32, t32, _ = timed_steps(s, b, fp32, args.steps, 1)
+        keep["C2_fp32"] = x32.cpu().numpy()
         err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
         extras["fp32_precond_C2"] = {"ms_per_step": 1e3 * t32 / args.steps,
                                      "iters_per_solve": it32 / args.steps,
@@ -447,6 +490,8 @@ def main():
         sk = dict(fp64, krylov=L.P4D_KRYLOV_SCHUR, cheb_degree=2)   # its fastest degree
         xs64, is64, its64, ts64, profs = timed_steps(s, b, sk, args.steps, 1, mask)
         xs32, is32, its32, ts32, _ = timed_steps(s, b, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
+        keep["C2_schur_krylov_fp64"] = xs64.cpu().numpy()
+        keep["C2_schur_krylov_fp32"] = xs32.cpu().numpy()
         extras["schur_krylov_C2"] = {
             "fp64": {"ms_per_step": 1e3 * ts64 / args.steps, "iters_per_solve": its64 / args.steps,
                      "DOF_iter_per_s": N * its64 / ts64, "relres_true": is64.relres_true,
@@ -471,6 +516,7 @@ def main():
         b3 = torch.as_tensor(p3.b, device="cuda")
         xa, ia, ita, ta, _ = timed_steps(s3, b3, fp64, args.steps, 1)
         xb, ib, itb, tb, _ = timed_steps(s3, b3, fp32, args.steps, 1)
+        keep["C3_fp64"], keep["C3_fp32"] = xa.cpu().numpy(), xb.cpu().numpy()
         extras["C3_lognormal"] = {
             "fp64": {"ms_per_step": 1e3 * ta / args.steps, "iters_per_solve": ita / args.steps},
             "fp32_precond": {"ms_per_step": 1e3 * tb / args.steps, "iters_per_solve": itb / args.steps,
@@ -478,8 +524,11 @@ def main():
                                  (torch.linalg.norm(xb - xa) / torch.linalg.norm(xa)).item()},
             "speedup_fp32_vs_fp64": ta / tb}
         log(f"[bench] C3: fp64 {1e3 * ta / args.steps:.2f} ms, fp32 {1e3 * tb / args.steps:.2f} ms")
-        _, _, itc, tc3, _ = timed_steps(s3, b3, dict(sk), args.steps, 1)
-        _, _, itc32, tc332, _ = timed_steps(s3, b3, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
+        xc, _, itc, tc3, _ = timed_steps(s3, b3, dict(sk), args.steps, 1)
+        xc32, _, itc32, tc332, _ = timed_steps(s3, b3, dict(sk, pc_prec=L.P4D_FP32), args.steps, 1)
+        keep["C3_schur_krylov_fp64"] = xc.cpu().numpy()
+        keep["C3_schur_krylov_fp32"] = xc32.cpu().numpy()
+        del xc, xc32
         extras["schur_krylov_C3"] = {
             "fp64": {"ms_per_step": 1e3 * tc3 / args.steps, "iters_per_solve": itc / args.steps},
             "fp32_precond": {"ms_per_step": 1e3 * tc332 / args.steps,
@@ -581,13 +630,40 @@ def main():
             xo, io = orc.solve(p.b)
             its += io.iters
         tc = time.perf_counter() - t0
-        err = float(np.linalg.norm(x64.cpu().numpy() - xo) / np.linalg.norm(xo))
+        vs = {k: field_errors(p, v, xo) for k, v in keep.items() if k.startswith("C2")}
         cpu = {"value": N * its / tc, "unit": "DOF*iter/s", "cores": O.num_threads(),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"two full steps of the same workload (setup + {io.iters} FGMRES iterations "
                          f"to rtol 1e-8, each), {tc:.1f} s",
-               "gpu_vs_oracle_rel_err": err}
-        log(f"[bench] oracle: {tc:.1f} s, {io.iters} it, rel err gpu vs oracle {err:.2e}")
+               "gpu_vs_oracle_rel_err": vs["C2_fp64"]["all"],
+               "gpu_vs_oracle_rel_err_per_field": vs}
+        log(f"[bench] oracle: {tc:.1f} s, {io.iters} it, rel err gpu vs oracle {vs['C2_fp64']['all']:.2e}")
+        if "C3_fp64" in keep:
+            # the lognormal cube: one oracle step (timed), and the error of
+            # every GPU solution of it against the oracle's
+            p3 = pi.make_config(3)
+            t0 = time.perf_counter()
+            orc = O.Oracle(p3).setup(rtol=1e-8, cheb_degree=fp64["cheb_degree"])
+            xo3, io3 = orc.solve(p3.b)
+            tc3 = time.perf_counter() - t0
+            extras["oracle_C3"] = {
+                "value": p3.N * io3.iters / tc3, "unit": "DOF*iter/s", "cores": O.num_threads(),
+                "iters": io3.iters, "seconds": tc3,
+                "gpu_vs_oracle_rel_err_per_field": {k: field_errors(p3, v, xo3) for k, v in keep.items()
+                                                    if k.startswith("C3")}}
+            log(f"[bench] oracle C3: {tc3:.1f} s, {io3.iters} it")
+        bat = extras.get("C4_batch_64_cells", {})
+        if bat.get("_sample"):
+            # a sample of the batch: per mesh side, the cell with the fewest
+            # unknowns, against its oracle solve
+            rows = []
+            for i, xc in bat.pop("_sample"):
+                pc = pi.make_batch(64)[i]
+                xoc, _ = O.Oracle(pc).setup(rtol=1e-8).solve(pc.b)
+                rows.append({"cell": i, "side": pc.nx, "nr": list(pc.nr), "dof": pc.N,
+                             **field_errors(pc, xc, xoc)})
+            bat["fp32_vs_oracle_sample"] = rows
+    extras.get("C4_batch_64_cells", {}).pop("_sample", None)
 
     out = {
         "metric": "P4D Jacobian solve time & DOF*iter/s; FP32-precond vs FP64; HBM GB/s",

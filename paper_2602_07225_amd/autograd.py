@@ -6,8 +6,15 @@ preconditioner and solves (p4d_setup + p4d_solve).  Backward: one adjoint
 solve ``A^T lambda = dL/dx`` with the transposed operator and transposed
 preconditioner (p4d_solve_adjoint), then ``dL/dp = -lambda^T (dA/dp) x``
 (p4d_param_gradient) and ``dL/db = lambda``.  All arithmetic runs in the HIP
-library.  The electrolyte conductivity and the Butler-Volmer derivatives are
-held fixed at their uploaded values."""
+library.  The electrolyte conductivity, the separate transport coefficients,
+the per-element porosity and the Butler-Volmer derivatives are held fixed at
+their uploaded values.
+
+The forward pass records the solver's state (coefficients, diffusivities,
+preconditioner options) and its version counter.  If anything changed the
+context between this forward and its backward (another forward, an upload,
+a new setup), the backward first restores the recorded state, so the
+adjoint solve and the gradient use the operator of this forward pass."""
 from __future__ import annotations
 
 import torch
@@ -20,8 +27,10 @@ class P4DSolve(torch.autograd.Function):
     def forward(ctx, solver, sigma, Ds, b, opts=None):
         opts = dict(opts or {})
         dev = solver.device
-        sig = sigma.detach().to(dev, torch.float64).contiguous()
-        L.p4d_upload(solver.ctx, sig, solver._kappa, solver._g, solver._s, solver._e)
+        sig = sigma.detach().to(dev, torch.float64).contiguous().clone()
+        # upload() re-applies the separate transport coefficients and the
+        # porosity that the library's upload resets
+        solver.upload(sig, solver._kappa, solver._g, solver._s, solver._e)
         Dh = [float(v) for v in Ds.detach().cpu().tolist()]
         solver.set_diffusivity(Dh)
         solver.setup(**opts)
@@ -30,6 +39,8 @@ class P4DSolve(torch.autograd.Function):
             raise L.P4DError(info.status, "forward solve did not converge")
         ctx.solver = solver
         ctx.opts = opts
+        ctx.state = solver.state()
+        ctx.version = solver.version
         ctx.devs = (sigma.device, Ds.device, b.device)
         ctx.save_for_backward(x)
         return x
@@ -38,6 +49,8 @@ class P4DSolve(torch.autograd.Function):
     def backward(ctx, grad_x):
         (x,) = ctx.saved_tensors
         s = ctx.solver
+        if s.version != ctx.version:
+            s.restore(ctx.state, **ctx.opts)
         lam, info = s.solve_adjoint(grad_x.contiguous())
         if info.status != L.P4D_OK:
             raise L.P4DError(info.status, "adjoint solve did not converge")

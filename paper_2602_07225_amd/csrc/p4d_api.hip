@@ -2710,10 +2710,10 @@ p4d_status p4d_batch_create(const p4d_problem_desc *descs, int32_t ncells, p4d_b
 {
     if (!descs || !out || ncells < 1 || ncells > kMaxBatch) return P4D_ERR_INVALID_ARG;
     *out = nullptr;
-    p4d_batch *B = new p4d_batch();
-    B->n = ncells;
     for (int i = 0; i < ncells; i++)   // batches run the cube-element kernels
         if (descs[i].hxy[0] != 0.0 || descs[i].hxy[1] != 0.0) return P4D_ERR_INVALID_ARG;
+    p4d_batch *B = new p4d_batch();
+    B->n = ncells;
     for (int i = 0; i < ncells; i++) {
         p4d_ctx *c = nullptr;
         const p4d_status s = p4d_create(&descs[i], &c);

@@ -1,7 +1,8 @@
 // Block-level device functions of the operator and the preconditioner.  The
-// single-cell kernels (operator.hip, radial.hip, mg.hip) and the persistent
-// batched preconditioner (batch.hip) call the same functions, each for one
-// workgroup-sized unit of work given by an explicit block or tile index.
+// single-cell kernels (operator.hip, radial.hip, mg.hip) and the batched stage
+// kernels (batch.hip, one launch per stage depth over work lists spanning all
+// cells) call the same functions, each for one workgroup-sized unit of work
+// given by an explicit block or tile index.
 #pragma once
 #include "p4d_device.hpp"
 
@@ -101,6 +102,9 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
     const int i = i0 + tx, j = j0 + ty;
     const bool own = i < A.nx && j < A.ny;
     const int planeN = A.nx * A.ny;
+    // elements on either side of the node in x and y (the box spans the
+    // whole node plane)
+    const bool inx0 = i > 0, inx1 = i < g.nx - 1, iny0 = j > 0, iny1 = j < g.ny - 1;
 
     // One plane of x with its halo (PX*PY <= 2*kBlock values) and one layer
     // of element coefficients (EX*EY <= 2*kBlock) per workgroup: each thread
@@ -202,16 +206,17 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
             for (int e = 0; e < 8; e++) {
                 const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
                 cK[e] = L.ck[(kl - 1 + ez) & 1][(tx + ex) + EX * (ty + ey)];
+                // storage of the elements inside the box, whatever their
+                // stiffness coefficient (which may be zero)
                 const int ek = k - 1 + ez;
+                const bool in = A.mass && (ex ? inx1 : inx0) && (ey ? iny1 : iny0) &&
+                                ek >= A.ek_lo && ek <= A.ek_hi;
                 if (MEH) {
                     const int ei = i - 1 + ex, ej = j - 1 + ey;
-                    const bool ok = A.mass && ei >= 0 && ej >= 0 && ei < g.nx - 1 && ej < g.ny - 1 &&
-                                    ek >= A.ek_lo && ek <= A.ek_hi;
-                    cM[e] = ok ? elem_storage(g, ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek), ek)
+                    cM[e] = in ? elem_storage(g, ei + (long long)(g.nx - 1) * (ej + (long long)(g.ny - 1) * ek), ek)
                                : 0.0;
                 } else {
-                    cM[e] = (A.mass && cK[e] != 0.0) ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep)
-                                                     : 0.0;
+                    cM[e] = in ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
                 }
             }
             double Sx = stiff_of<MEH>(g, cK, X) + dcn * X[13];

@@ -28,6 +28,10 @@ class P4DSolver:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.p4d_set_workspace(self.ctx, self.ws.data_ptr(), nbytes, self.ws_opts)
         self._kd = self._dc = self._ep = None
+        # bumped by every call that changes the operator or the
+        # preconditioner, so that a differentiable solve can tell whether the
+        # context still holds the state of its forward pass
+        self.version = 0
         self.upload(prob.sigma, prob.kappa, prob.g, prob.s, prob.e)
         kd, dc = getattr(prob, "kappa_d", None), getattr(prob, "dce", None)
         if kd is not None or dc is not None:
@@ -48,13 +52,14 @@ class P4DSolver:
         assert all(a.numel() == self.n_e for a in arrs[2:])
         L.p4d_upload(self.ctx, *arrs)
         # kept for re-uploads with a new sigma (differentiable solves)
-        self._kappa, self._g, self._s, self._e = arrs[1:]
+        self._sigma, self._kappa, self._g, self._s, self._e = arrs
         # the upload resets the separate coefficients: keep those set
         if self._kd is not None or self._dc is not None:
             L.p4d_set_transport(self.ctx, self._kd, self._dc)
         if self._ep is not None:
             L.p4d_set_storage(self.ctx, self._ep)
         self.opts = None
+        self.version += 1
 
     def set_transport(self, kappa_d=None, dce=None):
         """Separate element coefficients of the diffusion-potential block and
@@ -65,6 +70,7 @@ class P4DSolver:
             raise ValueError(f"transport coefficients need {self.n_elem} values per element")
         L.p4d_set_transport(self.ctx, self._kd, self._dc)
         self.opts = None
+        self.version += 1
 
     def set_storage(self, eps_e=None):
         """Porosity per element for the c_e storage (None: per material)."""
@@ -73,18 +79,35 @@ class P4DSolver:
             raise ValueError(f"eps_e needs {self.n_elem} values per element")
         L.p4d_set_storage(self.ctx, self._ep)
         self.opts = None
+        self.version += 1
 
     def set_diffusivity(self, Ds):
         """Particle diffusivities (nondimensional, anode/cathode)."""
         L.p4d_set_diffusivity(self.ctx, Ds)
         self.desc.Ds[0], self.desc.Ds[1] = float(Ds[0]), float(Ds[1])
         self.opts = None
+        self.version += 1
 
     def setup(self, **kw):
         o = L.default_opts(**kw)
         L.p4d_setup(self.ctx, o)
         self.opts = o
+        self.version += 1
         return self
+
+    def state(self):
+        """The uploaded coefficients and diffusivities (device tensors held
+        by reference; every upload makes new ones)."""
+        return dict(sigma=self._sigma, kappa=self._kappa, g=self._g, s=self._s, e=self._e,
+                    kappa_d=self._kd, dce=self._dc, eps_e=self._ep,
+                    Ds=(float(self.desc.Ds[0]), float(self.desc.Ds[1])))
+
+    def restore(self, st, **setup_kw):
+        """Upload a state taken by ``state()`` and build its preconditioner."""
+        self._kd, self._dc, self._ep = st["kappa_d"], st["dce"], st["eps_e"]
+        self.upload(st["sigma"], st["kappa"], st["g"], st["s"], st["e"])
+        self.set_diffusivity(st["Ds"])
+        return self.setup(**setup_kw)
 
     def apply(self, x, transpose=False):
         x = self._dev(x)

@@ -76,13 +76,13 @@ def test_batch_equals_single_and_oracle(pc_prec, z_fp32):
     xs, infos = B.solve([p.b for p in cells])
     check_against_single(B, cells, xs, infos)
     assert infos[-1].iters == 0 and not np.any(to_np(xs[-1]))
-    tol = 1e-6 if pc_prec == 0 else 1e-5
     for i, p in enumerate(cells[:-1]):
-        orc = O.Oracle(p).setup(rtol=1e-8)
+        # reference at rtol 1e-11 (its near-null error stays out of the count)
+        orc = O.Oracle(p).setup(rtol=1e-11)
         xo, _ = orc.solve(p.b)
         err = rel(to_np(xs[i]), xo)
         say(f"  cell {i}: rel err vs oracle {err:.2e}")
-        assert err <= tol
+        assert err <= 1e-6
 
 
 def test_batch_restarts_in_lockstep():
@@ -111,11 +111,14 @@ def test_batch_autotune_keeps_results():
         assert np.array_equal(to_np(a), to_np(b))
 
 
+@pytest.mark.timeout(900)
 def test_C4_batch_64_cells():
     """The 64-cell workload (sides 16..48, N_r in {8, 16, 32}, lognormal
     conductivities), FP32 preconditioner with autotuned tiles: every cell
     converges to rtol 1e-8 (residual confirmed with the oracle operator),
-    equals the single-cell solve, and two cells match the oracle's solve."""
+    equals the single-cell solve, and one cell of every (side, anode N_r,
+    cathode N_r) class present matches the oracle's FP64 solve (rtol 1e-11)
+    to 1e-6."""
     from paper_2602_07225_amd import P4DBatch
     cells = pi.make_batch(64)
     Ntot = sum(p.N for p in cells)
@@ -131,9 +134,15 @@ def test_C4_batch_64_cells():
     for i, p in enumerate(cells):
         r = rel(O.Oracle(p).apply(to_np(xs[i])), p.b)
         assert r <= 1.0001e-8, f"cell {i}: residual {r:.2e}"
-    for i in (int(np.argmin([p.N for p in cells])), int(np.argmax([p.N for p in cells]))):
-        xo, _ = O.Oracle(cells[i]).setup(rtol=1e-8).solve(cells[i].b)
+    first = {}
+    for i, p in enumerate(cells):
+        first.setdefault((p.nx, tuple(p.nr)), i)
+    say(f"  {len(first)} (side, N_r pair) classes")
+    worst = 0.0
+    for (side, nr), i in sorted(first.items()):
+        xo, _ = O.Oracle(cells[i]).setup(rtol=1e-11).solve(cells[i].b)
         err = rel(to_np(xs[i]), xo)
-        say(f"  cell {i} N={cells[i].N}: rel err vs oracle {err:.2e}")
-        assert err <= 1e-5
+        worst = max(worst, err)
+        say(f"  cell {i} side {side} N_r {nr} N={cells[i].N}: rel err vs oracle {err:.2e}")
+    assert worst <= 1e-6
     B.close()

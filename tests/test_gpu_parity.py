@@ -102,11 +102,13 @@ def test_solve_parity_fp64(name, pc):
 @pytest.mark.parametrize("name", ["C1", "odd_lognormal", "ragged_multilevel"])
 @pytest.mark.parametrize("zfp32", [False, True])
 def test_solve_fp32_preconditioner(name, zfp32):
-    """FP32 preconditioner (and optionally FP32 Z basis) inside FP64 FGMRES:
-    error against the FP64 oracle solution, both at rtol 1e-8."""
+    """FP32 preconditioner (and optionally FP32 Z basis) inside FP64 FGMRES at
+    rtol 1e-8: error per field against the FP64 oracle solution, taken at
+    rtol 1e-11 so that the reference's own error along the near-null modes
+    (up to ~cond(A) * rtol) does not count against the GPU."""
     p, orc = case(name)
     say(f"fp32 solve {name} z_fp32={zfp32}")
-    orc.setup(rtol=1e-8)
+    orc.setup(rtol=1e-11)
     xo, io = orc.solve(p.b)
     s = solver_for(p, pc_prec=1, z_fp32=zfp32).setup(pc_prec=1, rtol=1e-8, z_fp32=int(zfp32))
     x, info = s.solve(to_dev(p.b))
@@ -116,9 +118,7 @@ def test_solve_fp32_preconditioner(name, zfp32):
         {k: f"{v:.1e}" for k, v in errs.items()})
     assert info.status == 0 and info.relres_true <= 1e-8
     assert rel(orc.apply(x), p.b) <= 1.0001e-8
-    # both solutions meet the 1e-8 residual; they differ by at most
-    # ~cond(A) * rtol along near-null modes since their Krylov paths differ
-    assert max(errs.values()) <= 1e-5
+    assert max(errs.values()) <= 1e-6
 
 
 @pytest.mark.parametrize("name", ["C1", "odd_lognormal"])
@@ -207,3 +207,43 @@ def test_smallest_grid_and_radial_extremes(smoother):
     xg, info = s.solve(to_dev(p.b))
     assert info.status == 0 and io.status == 0
     assert max(field_errors(p, to_np(xg), xo).values()) <= 1e-6
+
+
+@pytest.mark.parametrize("variant", ["per_material", "separate_transport", "storage"])
+def test_zero_coefficient_elements(variant):
+    """Elements with a zero conductivity (solid or electrolyte) keep their
+    storage term in the c_e block: operator, preconditioner and solve
+    against the oracle, with the per-material, separate-transport and
+    per-element-storage forms of the operator."""
+    p = pi.make_custom(9, 7, 25, (6, 8), seed=27, sigma_log=0.5, corr_cells=3.0)
+    rng = np.random.default_rng(27)
+    kappa, sigma = p.kappa.copy(), p.sigma.copy()
+    kappa[rng.choice(p.n_elem, 12, replace=False)] = 0.0
+    kk = np.arange(p.n_elem) // ((p.nx - 1) * (p.ny - 1))
+    elec = np.flatnonzero((kk + 1 < p.na) | (kk >= p.na + p.ns))   # electrode elements
+    sigma[rng.choice(elec, 6, replace=False)] = 0.0
+    q = p.with_(kappa=kappa, sigma=sigma)
+    if variant == "separate_transport":
+        dce = np.exp(0.5 * rng.standard_normal(p.n_elem))
+        dce[rng.choice(p.n_elem, 9, replace=False)] = 0.0
+        q = q.with_(kappa_d=1.2 * kappa, dce=dce)
+    elif variant == "storage":
+        q = q.with_(eps_e=0.2 + 0.6 * rng.random(p.n_elem))
+    say(f"zero coefficients, {variant}, N={q.N}")
+    orc = O.Oracle(q)
+    s = solver_for(q)
+    x = rng.standard_normal(q.N)
+    for tr in (False, True):
+        y, ref = to_np(s.apply(to_dev(x), tr)), orc.apply(x, tr)
+        assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+    orc.setup(rtol=1e-8)
+    s.setup(rtol=1e-8)
+    errs = field_errors(q, to_np(s.apply_pc(to_dev(x))), orc.apply_pc(x))
+    say("  preconditioner", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-10
+    xo, io = orc.solve(q.b)
+    xg, info = s.solve(to_dev(q.b))
+    errs = field_errors(q, to_np(xg), xo)
+    say(f"  iters gpu={info.iters} oracle={io.iters}", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert info.status == 0 and io.status == 0 and abs(info.iters - io.iters) <= 2
+    assert max(errs.values()) <= 1e-6

@@ -68,7 +68,8 @@ def test_schur_krylov_solve_parity(name):
 @pytest.mark.parametrize("pc_prec,zfp32", [(1, False), (1, True)])
 def test_schur_krylov_fp32_preconditioner(pc_prec, zfp32):
     p, orc = case("ragged_multilevel")
-    orc.setup(rtol=1e-8)
+    # reference at rtol 1e-11: its own near-null error stays out of the count
+    orc.setup(rtol=1e-11)
     xo, _ = orc.solve(p.b)
     s = solver_for(p, pc_prec=pc_prec, z_fp32=zfp32).setup(pc_prec=pc_prec, rtol=1e-8,
                                                             z_fp32=int(zfp32))
@@ -78,7 +79,7 @@ def test_schur_krylov_fp32_preconditioner(pc_prec, zfp32):
     say(f"  fp32 pc z_fp32={zfp32}: iters {info.iters}", {k: f"{v:.1e}" for k, v in errs.items()})
     assert info.status == 0 and info.relres_true <= 1.0001e-8
     assert rel(orc.apply(x), p.b) <= 1.0001e-8
-    assert max(errs.values()) <= 1e-5
+    assert max(errs.values()) <= 1e-6
 
 
 @pytest.mark.parametrize("name", ["C1", "odd_lognormal"])
