@@ -104,11 +104,12 @@ def test_solve_parity_fp64(name, pc):
 def test_solve_fp32_preconditioner(name, zfp32):
     """FP32 preconditioner (and optionally FP32 Z basis) inside FP64 FGMRES at
     rtol 1e-8: error per field against the FP64 oracle solution, taken at
-    rtol 1e-11 so that the reference's own error along the near-null modes
-    (up to ~cond(A) * rtol) does not count against the GPU."""
+    rtol 1e-9 so that the reference's own error along the near-null modes
+    (up to ~cond(A) * rtol) does not count against the GPU (the oracle stops
+    at its residual floor if that lies above 1e-9)."""
     p, orc = case(name)
     say(f"fp32 solve {name} z_fp32={zfp32}")
-    orc.setup(rtol=1e-11)
+    orc.setup(rtol=1e-9, maxit=150)
     xo, io = orc.solve(p.b)
     s = solver_for(p, pc_prec=1, z_fp32=zfp32).setup(pc_prec=1, rtol=1e-8, z_fp32=int(zfp32))
     x, info = s.solve(to_dev(p.b))

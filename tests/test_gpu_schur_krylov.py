@@ -68,8 +68,8 @@ def test_schur_krylov_solve_parity(name):
 @pytest.mark.parametrize("pc_prec,zfp32", [(1, False), (1, True)])
 def test_schur_krylov_fp32_preconditioner(pc_prec, zfp32):
     p, orc = case("ragged_multilevel")
-    # reference at rtol 1e-11: its own near-null error stays out of the count
-    orc.setup(rtol=1e-11)
+    # reference at rtol 1e-9: its own near-null error stays out of the count
+    orc.setup(rtol=1e-9, maxit=150)
     xo, _ = orc.solve(p.b)
     s = solver_for(p, pc_prec=pc_prec, z_fp32=zfp32).setup(pc_prec=pc_prec, rtol=1e-8,
                                                             z_fp32=int(zfp32))
