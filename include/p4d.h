@@ -256,6 +256,29 @@ p4d_status p4d_solve_adjoint(p4d_ctx *ctx, const double *d_g, double *d_lambda,
                              const p4d_solve_opts *opts, p4d_solve_info *info,
                              void *stream);
 
+/* Upload + setup + solve in one call with no workspace argument, for callers
+ * that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as p4d_upload(d_sigma,
+ * d_kappa, d_g, d_s, d_e) then p4d_setup(opts) then p4d_solve(d_b, d_x,
+ * opts, info) on the problem of `ctx`, with the per-material operator (no
+ * separate transport coefficients or per-element porosity).  The workspace
+ * is carved from a device array of P4D_NOALLOC_MAX_BYTES that the library
+ * holds statically, one copy per GPU until the process ends: the call makes
+ * no hipMalloc, hipFree or pinned-memory allocation (only small host-heap
+ * bookkeeping).  A problem whose workspace for `opts` exceeds that size is
+ * rejected with P4D_ERR_OOM before any device work (p4d_workspace_size gives
+ * the size, plus 256 bytes of alignment).  `ctx` itself is left as it was:
+ * its workspace, uploads and setup are neither used nor changed (only its
+ * error message).  All calls on one GPU share that GPU's scratch array and
+ * the last call's contents stay in it: calls that overlap on one GPU (other
+ * threads, other streams) race.  Nothing in it needs to start at zero.
+ * Synchronizes `stream`.                                                   */
+#define P4D_NOALLOC_MAX_BYTES (64u << 20)
+p4d_status p4d_solve_noalloc(p4d_ctx *ctx, const double *d_sigma, const double *d_kappa,
+                             const double *d_g, const double *d_s, const double *d_e,
+                             const double *d_b, double *d_x, const p4d_solve_opts *opts,
+                             p4d_solve_info *info, void *stream);
+
 /* Gradients of J = w.x for A x = b, given x and lambda = A^-T w:
  * dJ/dp = -lambda^T (dA/dp) x.  d_dsigma: per element (zero on separator
  * elements); d_dDs: 2 values (anode, cathode), derivative with respect to Ds.

@@ -34,6 +34,8 @@ P4D_KRYLOV_FULL = 0
 P4D_KRYLOV_SCHUR = 1
 P4D_SMOOTH_CHEB = 0
 P4D_SMOOTH_ZLINE = 1
+# size of the static scratch of p4d_solve_noalloc (per GPU)
+P4D_NOALLOC_MAX_BYTES = 64 << 20
 
 (P4D_K_OPERATOR, P4D_K_MDOT, P4D_K_ORTH, P4D_K_RADIAL, P4D_K_SMOOTH0, P4D_K_ZY,
  P4D_K_BATCH_PC, P4D_K_COUPLING) = range(1, 9)
@@ -48,6 +50,7 @@ EXPORTED = [
     "p4d_setup",
     "p4d_apply_operator",
     "p4d_apply_schur_operator", "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
+    "p4d_solve_noalloc",
     "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
     "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_cell", "p4d_batch_workspace_size",
     "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_autotune",
@@ -146,6 +149,8 @@ def lib():
         L.p4d_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.p4d_solve_adjoint.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.p4d_param_gradient.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.p4d_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts),
+                                        C.POINTER(SolveInfo), vp]
         L.p4d_profile.argtypes = [vp, C.c_int]
         L.p4d_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -159,7 +164,7 @@ def lib():
                      "p4d_apply_operator",
                      "p4d_apply_preconditioner", "p4d_apply_schur_operator",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
-                     "p4d_profile_read"]:
+                     "p4d_profile_read", "p4d_solve_noalloc"]:
             getattr(L, name).restype = C.c_int
         _bind_batch(L)
         _bind_phys(L)
@@ -415,6 +420,15 @@ def p4d_solve_adjoint(ctx, g, lam, opts: SolveOpts | None = None, stream=None):
     st = check(lib().p4d_solve_adjoint(ctx, ptr(g), ptr(lam), C.byref(opts) if opts else None,
                                        C.byref(info), stream_ptr(stream)), ctx,
                "p4d_solve_adjoint")
+    return st, info
+
+
+def p4d_solve_noalloc(ctx, sigma, kappa, g, s, e, b, x, opts: SolveOpts | None = None, stream=None):
+    """Upload + setup + solve on the library's static scratch (no workspace)."""
+    info = SolveInfo()
+    st = check(lib().p4d_solve_noalloc(ctx, ptr(sigma), ptr(kappa), ptr(g), ptr(s), ptr(e), ptr(b),
+                                       ptr(x), C.byref(opts) if opts else None, C.byref(info),
+                                       stream_ptr(stream)), ctx, "p4d_solve_noalloc")
     return st, info
 
 

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1759,6 +1760,90 @@ p4d_status p4d_solve_adjoint(p4d_ctx *c, const double *g, double *lam, const p4d
                              p4d_solve_info *info, void *stream)
 {
     return solve_common(c, 1, g, lam, opts, info, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// upload + setup + solve with no workspace argument: the whole workspace is
+// carved from a file-scope device array (one copy per GPU, held until the
+// process ends), so the call allocates no device or pinned memory.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char noalloc_scratch[P4D_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[kMaxDevices];   // device address of noalloc_scratch, per device
+}  // namespace
+
+// The device address of the scratch array on the current device, looked up
+// once per device with that device current (in host code the array's name
+// is only a host-side stand-in).
+static p4d_status noalloc_base(p4d_ctx *c, char **out)
+{
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, P4D_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess || !p)
+            return fail(c, P4D_ERR_HIP, std::string("hipGetSymbolAddress(noalloc_scratch): ") +
+                                            hipGetErrorString(e));
+        noalloc_ptr[dev] = p;
+    }
+    *out = (char *)noalloc_ptr[dev];
+    return P4D_OK;
+}
+
+extern "C" {
+
+p4d_status p4d_solve_noalloc(p4d_ctx *c, const double *sigma, const double *kappa, const double *g,
+                             const double *s, const double *e, const double *b, double *x,
+                             const p4d_solve_opts *opts, p4d_solve_info *info, void *stream)
+{
+    if (!c || !sigma || !kappa || !g || !s || !e || !b || !x || b == x) return P4D_ERR_INVALID_ARG;
+    if (c->phys) return fail(c, P4D_ERR_INVALID_ARG, "a physical cell solves through p4d_phys_newton_step");
+    p4d_solve_opts o;
+    p4d_default_opts(&o);
+    if (opts) o = *opts;
+    std::string why;
+    if (!opts_valid(o, why)) return fail(c, P4D_ERR_INVALID_ARG, why);
+    // a context of its own, on the caller's problem, bound to the scratch:
+    // the caller's context (its workspace, uploads and setup) is untouched
+    p4d_ctx t;
+    t.desc = c->desc;
+    t.g = c->g;
+    t.g.meh = nullptr;
+    t.tabs_h[0] = c->tabs_h[0];
+    t.tabs_h[1] = c->tabs_h[1];
+    t.tile_tx = c->tile_tx;
+    t.tile_cz = c->tile_cz;
+    t.tiles_tuned = c->tiles_tuned;
+    t.op_tx = c->op_tx;
+    t.op_cz = c->op_cz;
+    const size_t need = carve(&t, o, nullptr) + kAlign;
+    if (need > (size_t)P4D_NOALLOC_MAX_BYTES)
+        return fail(c, P4D_ERR_OOM, "p4d_solve_noalloc: this problem needs " + std::to_string(need) +
+                                        " bytes of scratch, more than the " +
+                                        std::to_string((size_t)P4D_NOALLOC_MAX_BYTES) + " it holds");
+    char *base = nullptr;
+    p4d_status st = noalloc_base(c, &base);
+    if (st != P4D_OK) return st;
+    t.hhost = c->hhost;   // the caller context's pinned staging (no allocation)
+    t.ws = base;
+    t.ws_bytes = P4D_NOALLOC_MAX_BYTES;
+    // every array of the layout is written before it is read (as with a
+    // fresh caller workspace), so nothing in the scratch is cleared here
+    st = ensure_layout(&t, o);
+    if (st == P4D_OK) st = p4d_upload(&t, sigma, kappa, g, s, e, stream);
+    if (st == P4D_OK) st = p4d_setup(&t, &o, stream);
+    if (st == P4D_OK) st = p4d_solve(&t, b, x, &o, info, stream);
+    if (st != P4D_OK) c->err = t.err;
+    t.hhost = nullptr;
+    return st;
 }
 
 p4d_status p4d_phys_create(const p4d_phys_params *p, p4d_ctx **out)
