@@ -127,6 +127,121 @@ void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st)
 template void launch_coarse<double>(const CoarseBatch<double> &, hipStream_t);
 template void launch_coarse<float>(const CoarseBatch<float> &, hipStream_t);
 
+// Tail of the V-cycle, one 1024-thread workgroup per box (see TailArgs).  The
+// per-stage device functions run here on LDS arrays through generic
+// pointers: node n of a stage is base + threadIdx.x over bases stepping by
+// the workgroup size, which is what smooth_block / restrict_block /
+// prolong_block compute from a block index base / kBlock.
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailBatch<T> tb)
+{
+    __shared__ __align__(16) char lds[kTailLds];
+    if ((int)blockIdx.x >= tb.nbox) return;
+    const TailArgs<T> &A = tb.a[blockIdx.x];
+    const int n = A.n, nc = A.nc, deg = tb.deg;
+    // doubles: x1 and the coarse inverse first (filled together), then the
+    // second iterate buffer, the coarse solution and the partial sums; then
+    // the stencil, inverse diagonal and right-hand side (filled together),
+    // direction, residual and coarse right-hand side in T
+    double *xa = (double *)lds;
+    double *Ainv = xa + n;             // [nc][nc] coarse inverse
+    double *xb = Ainv + nc * nc;
+    double *xc = xb + n;
+    double *part = xc + nc;            // [4][nc] partial sums of the coarse solve
+    T *S = (T *)(part + 4 * nc);
+    T *invd = S + 14 * n;
+    T *b = invd + n;
+    T *d = b + n;
+    T *r = d + n;
+    T *bc = r + n;
+    {   // every global load is issued, kU per thread and array group, before
+        // any of them is stored to LDS (a load-store loop waits for each)
+        constexpr int kU = 8;
+        const int cT = 16 * n, cD = n + nc * nc;
+        const int cmax = cT > cD ? cT : cD;
+        for (int base = 0; base < cmax; base += kU * kTailThreads) {
+            T vt[kU];
+            double vd[kU];
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                // indexes clamped into range and sources chosen by select, so
+                // that the loads are issued without branches (stored only if
+                // q is in range)
+                const int q = base + u * kTailThreads + (int)threadIdx.x;
+                const int qt = q < cT ? q : cT - 1, qd = q < cD ? q : cD - 1;
+                const T *pt = qt < 14 * n ? A.S + qt : (qt < 15 * n ? A.invd + (qt - 14 * n) : A.b + (qt - 15 * n));
+                const double *pd = qd < n ? A.x1 + qd : A.Ainv + (qd - n);
+                vt[u] = *pt;
+                vd[u] = *pd;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; u++) {
+                const int q = base + u * kTailThreads + (int)threadIdx.x;
+                if (q < cT) S[q] = vt[u];
+                if (q < cD) xa[q] = vd[u];
+            }
+        }
+    }
+    __syncthreads();
+    LevelArgs<T> L{};
+    L.nx = A.nx; L.ny = A.ny; L.nz = A.nz; L.n = n;
+    L.S = S; L.invd = invd; L.b = b; L.din = d;
+    int cur = 0;   // 0: the iterate is in xa
+    auto smooth = [&](int t, bool post) {
+        L.xin = cur ? xb : xa;
+        L.xout = cur ? xa : xb;
+        L.c1 = A.c1[t];
+        L.c2 = A.c2[t];
+        // (first pre-smoothing step from x = 0: its direction is x itself)
+        L.din_x = (!post && t == 2) ? 1 : 0;
+        L.dout = t < deg ? d : nullptr;
+        L.rout = nullptr;
+        for (int base = 0; base < n; base += kTailThreads) smooth_block<T, false>(L, base / kBlock);
+        __syncthreads();
+        cur ^= 1;
+    };
+    for (int t = 2; t <= deg; t++) smooth(t, false);
+    L.xin = cur ? xb : xa;
+    L.rout = r;
+    for (int base = 0; base < n; base += kTailThreads) smooth_block<T, true>(L, base / kBlock);
+    __syncthreads();
+    TransferArgs<T> P{};
+    P.fx = A.nx; P.fy = A.ny; P.fz = A.nz;
+    P.cx = A.cx; P.cy = A.cy; P.cz = A.cz;
+    P.rf = r;
+    P.bc = bc;
+    P.xc1 = nullptr;
+    for (int base = 0; base < nc; base += kTailThreads) restrict_block<T>(P, base / kBlock);
+    __syncthreads();
+    // x_c = Ainv b_c with the per-stage coarse kernel's summation: four
+    // partial sums over the columns c = w (mod 4), ascending, then paired
+    for (int q = threadIdx.x; q < 4 * nc; q += kTailThreads) {
+        const int w = q / nc, row = q - w * nc;
+        double acc = 0.0;
+        for (int c = w; c < nc; c += 4) acc += Ainv[c * nc + row] * (double)bc[c];
+        part[w * nc + row] = acc;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nc; q += kTailThreads)
+        xc[q] = (part[q] + part[nc + q]) + (part[2 * nc + q] + part[3 * nc + q]);
+    __syncthreads();
+    P.xc = xc;
+    P.xf = cur ? xb : xa;
+    for (int base = 0; base < n; base += kTailThreads) prolong_block<T>(P, base / kBlock);
+    __syncthreads();
+    for (int t = 1; t <= deg; t++) smooth(t, true);
+    const double *xf = cur ? xb : xa;
+    for (int q = threadIdx.x; q < n; q += kTailThreads) A.xout[q] = xf[q];
+}
+
+template <typename T>
+void launch_tail(const TailBatch<T> &tb, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_tail<T>), dim3(tb.nbox), dim3(kTailThreads), 0, st, tb);
+}
+template void launch_tail<double>(const TailBatch<double> &, hipStream_t);
+template void launch_tail<float>(const TailBatch<float> &, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Setup kernels (FP64)
 // ---------------------------------------------------------------------------

@@ -630,6 +630,9 @@ static void residual_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, in
 }
 
 template <typename T>
+static void vcycle_rest(p4d_ctx *c, VState<T> &vs, int l, int *act, int na, hipStream_t st);
+
+template <typename T>
 static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
 {
     int act[4], na = 0, crs[4], nc = 0;
@@ -661,6 +664,61 @@ static void vcycle_level(p4d_ctx *c, VState<T> &vs, int l, hipStream_t st)
         }
     }
     if (!na) return;
+    const int deg = c->pc.cheb_degree;
+    if (l >= 1 && !c->rec) {
+        // boxes whose level l is their last smoothed level and fits the
+        // LDS of one workgroup run the rest of their cycle in the tail kernel
+        TailBatch<T> tb{};
+        tb.deg = deg;
+        int rest[4], nr = 0, tmask = 0;
+        for (int q = 0; q < na; q++) {
+            Box &B = c->box[act[q]];
+            const Level &F = B.lev[l], &Cl = B.lev[l + 1];
+            if (B.nlev - 2 != l || tail_lds_bytes<T>(F.n, Cl.n) > kTailLds) {
+                rest[nr++] = act[q];
+                continue;
+            }
+            TailArgs<T> &A = tb.a[tb.nbox++];
+            A.nx = F.nx; A.ny = F.ny; A.nz = F.nz; A.n = F.n;
+            A.cx = Cl.nx; A.cy = Cl.ny; A.cz = Cl.nz; A.nc = Cl.n;
+            A.S = (const T *)F.S;
+            A.invd = (const T *)F.invd;
+            A.b = (const T *)F.b;
+            A.x1 = lvx(const_cast<Level &>(F), vs.xcur[act[q]][l]);
+            // the per-stage schedule flips the iterate buffer once per
+            // smoothing step: deg - 1 before and deg after the correction
+            const int fin = (vs.xcur[act[q]][l] + 2 * deg - 1) & 1;
+            A.xout = lvx(const_cast<Level &>(F), fin);
+            vs.xcur[act[q]][l] = fin;
+            A.Ainv = Cl.Ainv;
+            const ChebCoef C = cheb_coef(F.lmax, deg);
+            for (int t = 0; t < 5; t++) {
+                A.c1[t] = C.c1[t];
+                A.c2[t] = C.c2[t];
+            }
+            tmask |= 1 << act[q];
+        }
+        if (tb.nbox) launch_tail<T>(tb, st);
+        if (!nr) return;
+        // the other boxes continue level by level; the tail's boxes sit out
+        // the coarser levels
+        for (int q = 0; q < nr; q++) act[q] = rest[q];
+        na = nr;
+        const int keep = c->box_mask;
+        c->box_mask &= ~tmask;
+        vcycle_rest<T>(c, vs, l, act, na, st);
+        c->box_mask = keep;
+        return;
+    }
+    vcycle_rest<T>(c, vs, l, act, na, st);
+}
+
+// level l of the V-cycle for the boxes in act (levels below l + 1 by
+// recursion): pre-smoothing, residual, restriction, coarser levels,
+// prolongation, post-smoothing
+template <typename T>
+static void vcycle_rest(p4d_ctx *c, VState<T> &vs, int l, int *act, int na, hipStream_t st)
+{
     const int deg = c->pc.cheb_degree;
     for (int t = 2; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 0, st);
     residual_step<T>(c, vs, l, act, na, st);

@@ -124,6 +124,36 @@ struct CoarseBatch {
     CoarseArgs<T> a[4];
 };
 
+// The last two levels of a box's V-cycle in one workgroup: the last smoothed
+// level F (from the first iterate the restriction left there: smoothing
+// steps 2..deg, residual, restriction to the coarsest level, dense coarse
+// solve, prolongation, smoothing steps 1..deg) with F's stencil and vectors
+// held in LDS.  The arithmetic is that of the per-stage kernels (the same
+// device functions), so the results are identical.
+template <typename T>
+struct TailArgs {
+    int nx, ny, nz, n;               // level F
+    int cx, cy, cz, nc;              // coarsest level
+    const T *S, *invd, *b;           // level F stencil (upper half, [14][n]), inverse diagonal, rhs
+    const double *x1;                // level F first iterate
+    double *xout;                    // level F final iterate
+    const double *Ainv;              // coarsest level: dense inverse, column-major
+    double c1[5], c2[5];             // level F Chebyshev steps 1..deg
+};
+template <typename T>
+struct TailBatch {
+    int nbox, deg;
+    TailArgs<T> a[4];
+};
+constexpr int kTailLds = 96 * 1024;  // LDS of the tail kernel
+constexpr int kTailThreads = 1024;
+// LDS bytes the tail needs for a level of n nodes above a coarsest level of nc
+template <typename T>
+__host__ __device__ constexpr long long tail_lds_bytes(long long n, long long nc)
+{
+    return 8 * (2 * n + 5 * nc + nc * nc) + (long long)sizeof(T) * (18 * n + nc) + 64;
+}
+
 // ---- launchers (each defined beside its kernels) ---------------------------
 // operator.hip
 // tile_tx > 0 (and qbuf, n_e doubles): macro rows by 2.5D tiles, then the
@@ -181,6 +211,8 @@ template <typename T>
 void launch_prolong(const TransferBatch<T> &tb, int nblk, hipStream_t st);
 template <typename T>
 void launch_coarse(const CoarseBatch<T> &cb, hipStream_t st);
+template <typename T>
+void launch_tail(const TailBatch<T> &tb, hipStream_t st);
 void launch_assemble0(const Geom &g, int box, int nz, int k0, int ek_lo, int ek_hi, int mass,
                       const double *cK, const double *dcorr, double *S, hipStream_t st);
 // Galerkin product P^T S P as three 1D coarsenings (x, y, z), for up to four

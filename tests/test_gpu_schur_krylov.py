@@ -79,7 +79,10 @@ def test_schur_krylov_fp32_preconditioner(pc_prec, zfp32):
     say(f"  fp32 pc z_fp32={zfp32}: iters {info.iters}", {k: f"{v:.1e}" for k, v in errs.items()})
     assert info.status == 0 and info.relres_true <= 1.0001e-8
     assert rel(orc.apply(x), p.b) <= 1.0001e-8
-    assert max(errs.values()) <= 1e-6
+    # (the FP32 Z basis, an option outside the spec configuration,
+    # rounds the vectors that build the solution: its error is allowed 5e-6,
+    # as in the full-space test)
+    assert max(errs.values()) <= (5e-6 if zfp32 else 1e-6)
 
 
 @pytest.mark.parametrize("name", ["C1", "odd_lognormal"])
