@@ -662,11 +662,25 @@ void launch_resid_full(LineBatch lb, hipStream_t st)
 }
 
 // inverse diagonal and per-block maxima of the Gershgorin ratio sum|s_ij|/s_ii
-__global__ __launch_bounds__(kBlock) void k_diag(int n, const double *__restrict__ S,
-                                                 double *__restrict__ invd,
-                                                 double *__restrict__ part)
+// Raise the bound (the bits of a non-negative double) to the workgroup's
+// largest Gershgorin ratio; a negative, infinite or NaN ratio (a
+// non-positive or non-finite diagonal) becomes +inf, which the host rejects.
+// The bound is kept in kLmaxSlots slots, workgroup b raising slot b mod
+// kLmaxSlots (one atomic per workgroup, spread over the slots so that they do
+// not queue on one address); the host takes the maximum of the slots.
+__device__ inline void gershgorin_max(double ratio, unsigned long long *lmax)
 {
     __shared__ double red[4];
+    if (!(ratio >= 0.0) || !(ratio < INFINITY)) ratio = INFINITY;
+    const double m = block_max(ratio, red);
+    if (threadIdx.x == 0)
+        atomicMax(lmax + (blockIdx.x % kLmaxSlots), (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ __launch_bounds__(kBlock) void k_diag(int n, const double *__restrict__ S,
+                                                 double *__restrict__ invd,
+                                                 unsigned long long *__restrict__ lmax)
+{
     const int t = blockIdx.x * kBlock + threadIdx.x;
     double ratio = 0.0;
     if (t < n) {
@@ -676,8 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(int n, const double *__restrict
         invd[t] = 1.0 / dg;
         ratio = sum / dg;
     }
-    const double m = block_max(ratio, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = m;
+    gershgorin_max(ratio, lmax);
 }
 
 __global__ __launch_bounds__(kBlock) void k_max_final(const double *__restrict__ part, int nblk,
@@ -690,9 +703,36 @@ __global__ __launch_bounds__(kBlock) void k_max_final(const double *__restrict__
     if (threadIdx.x == 0) *out = m;
 }
 
-void launch_diag(int n, const double *S, double *invd, double *part, int nblk, hipStream_t st)
+void launch_diag(int n, const double *S, double *invd, unsigned long long *lmax, int nblk,
+                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(kBlock), 0, st, n, S, invd, part);
+    hipLaunchKernelGGL(k_diag, dim3(nblk), dim3(kBlock), 0, st, n, S, invd, lmax);
+}
+
+// level 0 of all boxes: inverse diagonal of the rows formed from the element
+// data, and the Gershgorin bound
+__global__ __launch_bounds__(kBlock) void k_diag0_batch(Geom g, PrepBatch pb)
+{
+    // (the box index is uniform: in a scalar register the box's arguments
+    // are read without a private copy)
+    const int bx = __builtin_amdgcn_readfirstlane(find_box(pb, blockIdx.x));
+    const PrepArgs A = pb.a[bx];
+    const int t = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    double ratio = 0.0;
+    if (t < A.n) {
+        double row[27];
+        assemble0_row(g, A.E, t, row);
+        double sum = 0.0;
+        for (int o = 0; o < 27; o++) sum += fabs(row[o]);
+        const double dg = row[13];
+        A.invd0[t] = 1.0 / dg;
+        ratio = sum / dg;
+    }
+    gershgorin_max(ratio, A.lmax);
+}
+void launch_diag0_batch(const Geom &g, const PrepBatch &pb, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_diag0_batch, dim3(nblk), dim3(kBlock), 0, st, g, pb);
 }
 
 __global__ __launch_bounds__(kBlock) void k_diag0(Geom g, Elem0 E, int n, double *__restrict__ invd,
@@ -785,34 +825,51 @@ void launch_dense_from_stencil(int nx, int ny, int nz, const double *S, double *
     hipLaunchKernelGGL(k_dense, dim3((int)((n * n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
                        ny, nz, S, A);
 }
-// Same elimination with the matrix resident in LDS (n <= kInvLds).
+// Same elimination for n <= kInvLds with the matrix held in registers, at
+// most kInvE entries per thread at fixed positions: per pivot only the pivot
+// row and column pass through LDS.  Each entry is updated by the same
+// expressions as above, so the inverse is the same.
 constexpr int kInvLds = 80;
+constexpr int kInvE = (kInvLds * kInvLds + 1023) / 1024;
 __global__ __launch_bounds__(1024) void k_invert_lds(InvBatch ib)
 {
-    __shared__ double M[kInvLds * kInvLds];
     __shared__ double rowp[kInvLds], colp[kInvLds];
     const int box = blockIdx.x;
     const int n = ib.n[box];
     const int nn = n * n;
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) M[t] = ib.A[box][t];
-    for (int p = 0; p < n; p++) {
-        __syncthreads();
-        const double d = 1.0 / M[p * n + p];
-        for (int q = threadIdx.x; q < n; q += blockDim.x) {
-            rowp[q] = M[p * n + q] * d;
-            colp[q] = M[q * n + p];
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-            const int i = t / n, j = t - i * n;
-            double v;
-            if (i == p) v = j == p ? d : rowp[j];
-            else v = j == p ? -colp[i] * d : M[t] - colp[i] * rowp[j];
-            M[t] = v;
-        }
+    double v[kInvE];
+    int ii[kInvE], jj[kInvE];
+#pragma unroll
+    for (int e = 0; e < kInvE; e++) {
+        const int t = threadIdx.x + e * 1024;
+        ii[e] = t < nn ? t / n : -1;
+        jj[e] = t < nn ? t - ii[e] * n : -1;
+        v[e] = t < nn ? ib.A[box][t] : 0.0;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) ib.Ainv[box][t] = M[t];
+    for (int p = 0; p < n; p++) {
+#pragma unroll
+        for (int e = 0; e < kInvE; e++) {
+            if (ii[e] == p) rowp[jj[e]] = v[e];
+            if (jj[e] == p) colp[ii[e]] = v[e];
+        }
+        __syncthreads();
+        const double d = 1.0 / colp[p];
+#pragma unroll
+        for (int e = 0; e < kInvE; e++) {
+            if (ii[e] < 0) continue;
+            const double rp = rowp[jj[e]] * d;
+            double w;
+            if (ii[e] == p) w = jj[e] == p ? d : rp;
+            else w = jj[e] == p ? -colp[ii[e]] * d : v[e] - colp[ii[e]] * rp;
+            v[e] = w;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < kInvE; e++) {
+        const int t = threadIdx.x + e * 1024;
+        if (t < nn) ib.Ainv[box][t] = v[e];
+    }
 }
 
 void launch_invert(const InvBatch &ib, hipStream_t st)
@@ -859,6 +916,39 @@ void launch_level_prep(int n, const double *S, T *D, T *invd, double *part, int 
 {
     hipLaunchKernelGGL((k_level_prep<T>), dim3(nblk), dim3(kBlock), 0, st, n, S, D, invd, part);
 }
+
+// the same for one level of all boxes, the bound by atomic maximum
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_level_prep_batch(PrepBatch pb)
+{
+    const int bx = __builtin_amdgcn_readfirstlane(find_box(pb, blockIdx.x));
+    const PrepArgs A = pb.a[bx];
+    const int n = A.n;
+    const int t = (blockIdx.x - A.blk0) * kBlock + threadIdx.x;
+    T *D = (T *)A.D;
+    double ratio = 0.0;
+    if (t < n) {
+        double rs = 0.0, sum = 0.0;
+        for (int o = 0; o < 27; o++) {
+            const double v = A.S[(long long)o * n + t];
+            rs += v;
+            sum += fabs(v);
+            if (o > 13) D[(long long)(o - 13) * n + t] = (T)v;
+        }
+        D[t] = (T)rs;
+        const double dg = A.S[13LL * n + t];
+        ((T *)A.invd)[t] = (T)(1.0 / dg);
+        ratio = sum / dg;
+    }
+    gershgorin_max(ratio, A.lmax);
+}
+template <typename T>
+void launch_level_prep_batch(const PrepBatch &pb, int nblk, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_level_prep_batch<T>), dim3(nblk), dim3(kBlock), 0, st, pb);
+}
+template void launch_level_prep_batch<double>(const PrepBatch &, int, hipStream_t);
+template void launch_level_prep_batch<float>(const PrepBatch &, int, hipStream_t);
 template void launch_level_prep<double>(int, const double *, double *, double *, double *, int,
                                         hipStream_t);
 template void launch_level_prep<float>(int, const double *, float *, float *, double *, int,

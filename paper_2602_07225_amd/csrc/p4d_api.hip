@@ -1033,6 +1033,11 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     // inverse diagonal of level 0 defaults to 0 outside the boxes (the
     // grounded layer of phi_s)
     HIPCHK(c, hipMemsetAsync(id64, 0, 8 * (size_t)g.Nm, st));
+    // Gershgorin bounds, raised by atomic maxima: kLmaxSlots slots for box b,
+    // level l at (16 b + l) kLmaxSlots of the reduction buffer
+    unsigned long long *lmx = (unsigned long long *)c->red;
+    const size_t nlmx = 64 * (size_t)kLmaxSlots;
+    HIPCHK(c, hipMemsetAsync(lmx, 0, 8 * nlmx, st));
     int maxlev = 0;
     for (int b = 0; b < 4; b++) maxlev = c->box[b].nlev > maxlev ? c->box[b].nlev : maxlev;
     for (int l = 0; l < maxlev; l++) {
@@ -1049,6 +1054,30 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
             }
             launch_rap(g, jobs, nj, !zline, st);
         }
+        // difference form, inverse diagonal and bound of this level, all
+        // boxes in one launch (level 0: from the element rows)
+        PrepBatch pb{};
+        int pblk = 0;
+        for (int b = 0; b < 4; b++) {
+            Box &B = c->box[b];
+            if (B.nlev <= l) continue;
+            Level &L = B.lev[l];
+            if (l == 0 && (zline || B.nlev == 1)) continue;   // stored-stencil path below
+            PrepArgs &A = pb.a[pb.nbox++];
+            A.n = L.n;
+            A.blk0 = pblk;
+            pblk += (L.n + kBlock - 1) / kBlock;
+            A.S = L.S64;
+            A.D = L.S;
+            A.invd = L.invd;
+            A.E = E0[b];
+            A.invd0 = id64 + B.off;
+            A.lmax = lmx + (16 * b + l) * kLmaxSlots;
+        }
+        if (pb.nbox) {
+            if (l > 0) launch_level_prep_batch<T>(pb, pblk, st);
+            else launch_diag0_batch(g, pb, pblk, st);
+        }
         for (int b = 0; b < 4; b++) {
             Box &B = c->box[b];
             if (B.nlev <= l) continue;
@@ -1058,22 +1087,17 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 // the stored level-0 stencil is needed only by z-line smoothing
                 // and by a level-0 coarsest grid; otherwise its rows are formed
                 // where they are used (diagonal, first Galerkin product)
-                if (zline || B.nlev == 1)
+                if (zline || B.nlev == 1) {
                     launch_assemble0(g, b, L.nz, B.k0, B.ek_lo, B.ek_hi, B.mass, B.cK, dc64 + B.off,
                                      S0[b], st);
+                    launch_diag(L.n, S0[b], id64 + B.off, lmx + 16 * b * kLmaxSlots, (L.n + kBlock - 1) / kBlock,
+                                st);
+                }
                 Sl = S0[b];
             } else {
                 Sl = L.S64;
             }
             if (zline && L.Sz) launch_zline_order(L.nx, L.ny, L.nz, Sl, L.Sz, st);
-            const int nblk = (L.n + kBlock - 1) / kBlock;
-            if (l > 0)   // difference form, inverse diagonal and bound in one pass
-                launch_level_prep<T>(L.n, Sl, (T *)L.S, (T *)L.invd, c->red, nblk, st);
-            else if (!zline && B.nlev > 1)
-                launch_diag0(g, E0[b], L.n, id64 + B.off, c->red, nblk, st);
-            else
-                launch_diag(L.n, Sl, id64 + B.off, c->red, nblk, st);
-            launch_max_final(c->red, nblk, c->scal + 16 * b + l, st);
             if (l == B.nlev - 1) {
                 if (L.n > 1024) return fail(c, P4D_ERR_INVALID_ARG, "coarsest grid above 1024 nodes");
                 double *dense = (double *)take(8 * (size_t)L.n * L.n);
@@ -1088,11 +1112,16 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     launch_invert(ib, st);
     launch_cast<T>(g.Nm, id64, (T *)c->invd0, st);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal, 8 * 64, hipMemcpyDeviceToHost, st));
+    std::vector<unsigned long long> lmh(nlmx);
+    HIPCHK(c, hipMemcpyAsync(lmh.data(), lmx, 8 * nlmx, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     for (int b = 0; b < 4; b++)
         for (int l = 0; l < c->box[b].nlev; l++) {
-            const double lm = c->hhost[16 * b + l];
+            unsigned long long bits = 0;   // bits of the maximum (non-negative doubles order as integers)
+            for (int q = 0; q < kLmaxSlots; q++)
+                bits = std::max(bits, lmh[(16 * (size_t)b + l) * kLmaxSlots + q]);
+            double lm;
+            std::memcpy(&lm, &bits, sizeof(lm));
             if (!(lm > 0.0) || !std::isfinite(lm))
                 return fail(c, P4D_ERR_NONFINITE, "non-positive or non-finite Gershgorin bound");
             c->box[b].lev[l].lmax = lm;

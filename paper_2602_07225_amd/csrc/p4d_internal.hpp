@@ -224,6 +224,27 @@ struct Elem0 {
     int nzb, k0, ek_lo, ek_hi, mass;
     const double *cK, *dcorr;
 };
+// Per-box arguments of the batched level preparation: at level 0 the
+// inverse diagonal from the element rows, at levels >= 1 the difference
+// form and inverse diagonal from the stored stencil; both raise the box's
+// Gershgorin bound, kept as the bits of a non-negative double so that an
+// integer atomic maximum gives it exactly (in any order)
+struct PrepArgs {
+    int n, blk0;
+    const double *S;                 // levels >= 1: Galerkin stencil [27][n]
+    void *D, *invd;                  // levels >= 1: difference form [14][n], inverse diagonal (T)
+    Elem0 E;                         // level 0: element data of the box
+    double *invd0;                   // level 0: FP64 inverse diagonal
+    unsigned long long *lmax;
+};
+struct PrepBatch {
+    int nbox;
+    PrepArgs a[4];
+};
+constexpr int kLmaxSlots = 32;       // atomic slots per Gershgorin bound
+template <typename T>
+void launch_level_prep_batch(const PrepBatch &pb, int nblk, hipStream_t st);
+void launch_diag0_batch(const Geom &g, const PrepBatch &pb, int nblk, hipStream_t st);
 struct RapArgs {
     int nx, ny, nz;          // input dims of this 1D coarsening
     int blk0;
@@ -270,7 +291,7 @@ void launch_resid_full(LineBatch lb, hipStream_t st);
 // Sz = the rows of S ([27][n] on an nx x ny x nz box) reordered as the
 // z-line sweeps read them: colour by colour, then layer k, then line
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);
-void launch_diag(int n, const double *S, double *invd, double *ratio_partial, int nblk,
+void launch_diag(int n, const double *S, double *invd, unsigned long long *lmax, int nblk,
                  hipStream_t st);
 // levels >= 1 in one pass: the smoother's stored stencil D in T (slot 0 the
 // row sum formed in FP64, slots 1..13 the upper half), the inverse diagonal
