@@ -183,7 +183,7 @@ def bench_batch(steps):
     tiles = B.autotune()
     out = {"cells": len(cells), "dof_total": ntot, "setup_ms": 1e3 * t_setup,
            "tiles": sorted(set(tiles))}
-    for mode, name in ((0, "batched_stage_launches"), (1, "per_cell_launches")):
+    for mode, name in ((0, "batched_stage_launches"), (2, "persistent_launch"), (1, "per_cell_launches")):
         B.set_pc_mode(mode)
         B.solve(bs)
         torch.cuda.synchronize()
@@ -213,6 +213,8 @@ def bench_batch(steps):
     B.set_pc_mode(0)
     out["speedup_batched_vs_per_cell"] = (out["per_cell_launches"]["solve_ms"] /
                                           out["batched_stage_launches"]["solve_ms"])
+    out["speedup_persistent_vs_stage_launches"] = (out["batched_stage_launches"]["solve_ms"] /
+                                                   out["persistent_launch"]["solve_ms"])
     # per mesh side, the cell with the fewest unknowns: its FP32-preconditioned
     # solution, for the comparison with the oracle in the CPU leg
     xs, _ = B.solve(bs)

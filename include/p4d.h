@@ -367,8 +367,12 @@ p4d_status p4d_batch_autotune(p4d_batch *batch, void *stream, int32_t *tiles);
  * Synchronizes `stream` once per Arnoldi step.                              */
 p4d_status p4d_batch_solve(p4d_batch *batch, const double *const *d_b, double *const *d_x,
                            const p4d_solve_opts *opts, p4d_solve_info *infos, void *stream);
-/* mode 0 (default): batched stage launches; mode 1: the single-cell
- * preconditioner launches, cell after cell (a reference for mode 0).        */
+/* mode 0 (default): batched stage launches, one per stage depth; mode 1: the
+ * single-cell preconditioner launches, cell after cell (a reference); mode 2:
+ * one persistent launch per application (workgroups take chunks of stage
+ * units from a queue and wait, bounded, for the cell's previous stage; if a
+ * wait gives up, p4d_batch_solve returns P4D_ERR_HIP).  The three give the
+ * same results bit for bit.                                                 */
 p4d_status p4d_batch_set_pc_mode(p4d_batch *batch, int32_t mode);
 /* Kernel timing of the batched launches, as p4d_profile / p4d_profile_read;
  * P4D_K_BATCH_PC times all preconditioner launches of one Arnoldi step

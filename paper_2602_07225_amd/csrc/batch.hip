@@ -20,6 +20,8 @@
 // Each unit computes exactly what the single-cell kernels compute for the
 // same block or tile (the same device functions), so a cell solved in a
 // batch follows the same arithmetic as the cell solved alone.
+#include <hip/hip_cooperative_groups.h>
+
 #include "p4d_batch.hpp"
 
 namespace p4d {
@@ -177,6 +179,150 @@ void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t 
     }
 }
 #define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, int, hipStream_t);
+P4D_INST(double, double)
+P4D_INST(float, double)
+P4D_INST(double, float)
+P4D_INST(float, float)
+#undef P4D_INST
+
+// ---------------------------------------------------------------------------
+// Persistent application (see PersistRun)
+// ---------------------------------------------------------------------------
+union PersistLds {
+    Smooth0Lds s0;
+    CoarseLds co;
+};
+
+// one unit of a stage: the device function of its family, as in the
+// per-depth kernels above
+template <typename T, typename TZ, int NRMAX>
+__device__ inline void persist_unit(const PersistRun &run, const PStage<T> &S, int unit, PersistLds &L)
+{
+    const PCell &Cm = run.cells[S.cell];
+    switch (stage_family(S.kind)) {
+    case SF_RADF: {
+        const Geom g = Cm.g;
+        const RadArgs R = Cm.R;
+        const double *r = Cm.V + (long long)run.k * g.N;
+        const double rs = Cm.invbeta[run.k];
+        if (Cm.schur) {
+            if (run.transpose) rad_fwd_block<T, NRMAX, true, true>(g, R, r, rs, unit);
+            else rad_fwd_block<T, NRMAX, false, true>(g, R, r, rs, unit);
+        } else {
+            rad_fwd_block<T, NRMAX, false, false>(g, R, r, rs, unit);
+        }
+        break;
+    }
+    case SF_RADB: {
+        const Geom g = Cm.g;
+        const RadArgs R = Cm.R;
+        const double *r = Cm.V + (long long)run.k * g.N;
+        const double rs = Cm.invbeta[run.k];
+        TZ *z = (TZ *)Cm.Z + (long long)run.k * g.N;
+        if (Cm.schur) {
+            if (run.transpose) rad_back_block<T, TZ, NRMAX, true, true>(g, R, r, rs, z, unit);
+            else rad_back_block<T, TZ, NRMAX, false, true>(g, R, r, rs, z, unit);
+        } else {
+            if (run.transpose) rad_back_block<T, TZ, NRMAX, true, false>(g, R, r, rs, z, unit);
+            else rad_back_block<T, TZ, NRMAX, false, false>(g, R, r, rs, z, unit);
+        }
+        break;
+    }
+    case SF_SM0: {
+        const LevelArgs<T> A = S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, unit))];
+        const Geom g = Cm.g;
+        if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, unit - A.blk0, S.TX, S.CZ, L.s0);
+        else smooth0_tile<T, true>(g, A, unit - A.blk0, S.TX, S.CZ, L.s0);
+        break;
+    }
+    default:
+        switch (S.kind) {
+        case SK_SM:
+        case SK_SMR: {
+            const LevelArgs<T> A = S.u.lb.a[find_box(S.u.lb, unit)];
+            if (S.kind == SK_SM) smooth_block<T, false>(A, unit - A.blk0);
+            else smooth_block<T, true>(A, unit - A.blk0);
+            break;
+        }
+        case SK_RESTRICT: {
+            const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+            restrict_block<T>(A, unit - A.blk0);
+            break;
+        }
+        case SK_PROLONG: {
+            const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+            prolong_block<T>(A, unit - A.blk0);
+            break;
+        }
+        case SK_COARSE: {
+            const int box = unit / S.aux, rb = unit % S.aux;
+            if (box < S.u.cb.nbox) {
+                const CoarseArgs<T> A = S.u.cb.a[box];
+                if (rb * 64 < A.n) coarse_block<T>(A, rb, L.co);
+            }
+            break;
+        }
+        default:
+            break;
+        }
+        break;
+    }
+}
+
+// All stage depths of one application in one cooperative launch: the grid
+// walks the work items of a depth (item = workgroup + j x grid size, every
+// family in one list), then meets at the runtime's grid barrier before the
+// next depth, so each depth sees the whole previous depth complete, as with
+// one launch per depth.  No workgroup waits for another except at that
+// barrier, which every workgroup reaches once per depth.
+template <typename T, typename TZ, int NRMAX>
+__global__ __launch_bounds__(kBlock) void k_bpc_persist(PersistRun run)
+{
+    __shared__ PersistLds lds;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int d = 0; d < run.ndepth; d++) {
+        const int i0 = run.dstart[d], i1 = run.dstart[d + 1];
+        for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
+            const int pos = __builtin_amdgcn_readfirstlane(find_pos(run.ustart, run.npos, item));
+            const int si = __builtin_amdgcn_readfirstlane(run.order[pos]);
+            const PStage<T> &S = ((const PStage<T> *)run.stages)[si];
+            if (!((run.active >> S.cell) & 1ULL)) continue;   // (uniform in the workgroup)
+            persist_unit<T, TZ, NRMAX>(run, S, item - run.ustart[pos], lds);
+        }
+        grid.sync();
+    }
+}
+
+template <typename T, typename TZ>
+hipError_t launch_batch_persist(const PersistRun &run, int nrmax, int grid, hipStream_t st)
+{
+    void *args[] = {(void *)&run};
+    const void *f = nullptr;
+#define P4D_BPF(NR) f = (const void *)k_bpc_persist<T, TZ, NR>
+    P4D_NR_SWITCH(nrmax, P4D_BPF)
+#undef P4D_BPF
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kBlock), args, 0, st);
+}
+
+// workgroups of the cooperative kernel resident at once (its grid size)
+template <typename T, typename TZ>
+int batch_persist_slots(int nrmax)
+{
+    int dev = 0, ncu = 0, per = 0, coop = 0;
+    const void *f = nullptr;
+#define P4D_BPF(NR) f = (const void *)k_bpc_persist<T, TZ, NR>
+    P4D_NR_SWITCH(nrmax, P4D_BPF)
+#undef P4D_BPF
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kBlock, 0) != hipSuccess || per < 1)
+        return 0;
+    return per * ncu;
+}
+#define P4D_INST(T, TZ)                                                                           \
+    template hipError_t launch_batch_persist<T, TZ>(const PersistRun &, int, int, hipStream_t);  \
+    template int batch_persist_slots<T, TZ>(int);
 P4D_INST(double, double)
 P4D_INST(float, double)
 P4D_INST(double, float)

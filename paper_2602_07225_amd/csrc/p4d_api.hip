@@ -2289,11 +2289,17 @@ struct p4d_batch {
         int family, nr;             // stage family, radial size class
         int pos0, npos;             // queue positions
         int item0, nitems;          // units
+        int depth;                  // stage depth
     };
     std::vector<WorkList> lists;    // in launch order
     int tile_cz = 0;                // level-0 tile depth of the batch (0: chosen at recording)
     std::vector<double> pc_bytes;   // per cell: level-0 and particle bytes of one application
-    int pc_mode = 0;                // 0: batched stage launches, 1: per-cell launches
+    int pc_mode = 0;                // 0: batched stage launches, 1: per-cell launches,
+                                    // 2: one persistent launch per application
+    // persistent application: first item of every stage depth, grid size
+    int *dstart = nullptr;
+    int npos = 0, ndepth = 0, pgrid = 0;
+    hipError_t plaunch = hipSuccess;   // status of the last cooperative launch
     Prof prof;
 };
 
@@ -2344,6 +2350,7 @@ static size_t batch_carve(p4d_batch *B, const p4d_solve_opts &o, char *base, p4d
     B->stages = take(sizeof(PStage<double>) * maxst);
     B->order = (int *)take(4 * maxst);
     B->ustart = (int *)take(4 * maxst);
+    B->dstart = (int *)take(4 * (maxst + 1));
     B->hb = (double *)take(8 * 256 * (size_t)B->n);
     B->yb = (double *)take(8 * 64 * (size_t)B->n);
     B->kused = (int *)take(4 * (size_t)B->n);
@@ -2460,7 +2467,7 @@ static p4d_status batch_record(p4d_batch *B)
         for (int fam = SF_RADF; fam <= SF_MISC; fam++) {
             const bool radial = fam == SF_RADF || fam == SF_RADB;
             for (int ci = 0; ci < (radial ? kNrClasses : 1); ci++) {
-                p4d_batch::WorkList W{fam, radial ? kNrClass[ci] : 8, (int)order.size(), 0, (int)items, 0};
+                p4d_batch::WorkList W{fam, radial ? kNrClass[ci] : 8, (int)order.size(), 0, (int)items, 0, d};
                 for (int i : bysize) {
                     const int j = at[(size_t)i * depth + d];
                     if (j < 0 || stage_family(per[i][j].kind) != fam) continue;
@@ -2479,6 +2486,17 @@ static p4d_status batch_record(p4d_batch *B)
     BHIPCHK(B, hipMemcpy(B->stages, all.data(), sizeof(PStage<T>) * all.size(), hipMemcpyHostToDevice));
     BHIPCHK(B, hipMemcpy(B->order, order.data(), 4 * order.size(), hipMemcpyHostToDevice));
     BHIPCHK(B, hipMemcpy(B->ustart, ustart.data(), 4 * ustart.size(), hipMemcpyHostToDevice));
+    // the persistent application walks the same items depth by depth: the
+    // first item of every depth (the work lists are in depth order)
+    std::vector<int> dstart(depth + 1, (int)items);
+    for (int d = depth - 1, li = (int)B->lists.size() - 1; d >= 0; d--) {
+        dstart[d] = dstart[d + 1];
+        for (; li >= 0 && B->lists[li].depth == d; li--) dstart[d] = B->lists[li].item0;
+    }
+    BHIPCHK(B, hipMemcpy(B->dstart, dstart.data(), 4 * dstart.size(), hipMemcpyHostToDevice));
+    B->npos = (int)order.size();
+    B->ndepth = depth;
+    B->pgrid = batch_persist_slots<T, double>(B->nrmax);
     B->nstages = (int)all.size();
     B->recorded = 1;
     B->rec_prec = B->cell[0]->prec;
@@ -2576,6 +2594,21 @@ static p4d_status batch_tables(p4d_batch *B, int m, const double *const *bv, dou
 template <typename T, typename TZ>
 static void batch_apply_pc(p4d_batch *B, int transpose, int k, unsigned long long active, hipStream_t st)
 {
+    if (B->pc_mode == 2) {   // one cooperative launch for all depths
+        PersistRun pr{};
+        pr.stages = B->stages;
+        pr.cells = B->pcell;
+        pr.order = B->order;
+        pr.ustart = B->ustart;
+        pr.dstart = B->dstart;
+        pr.npos = B->npos;
+        pr.ndepth = B->ndepth;
+        pr.transpose = transpose;
+        pr.k = k;
+        pr.active = active;
+        B->plaunch = launch_batch_persist<T, TZ>(pr, B->nrmax, B->pgrid, st);
+        return;
+    }
     StageRun run{};
     run.stages = B->stages;
     run.cells = B->pcell;
@@ -2663,10 +2696,14 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
         R.yv.assign(m, 0.0); R.hc.assign(m + 2, 0.0); R.beta.assign(m + 1, 0.0);
     }
     const size_t hcopy = 8 * 256 * (size_t)n;
+    if (B->pc_mode == 2 && B->pgrid < 1)
+        return bfail(B, P4D_ERR_HIP, "this device runs no cooperative launch of the persistent kernel");
+    B->plaunch = hipSuccess;
     auto fetch = [&]() -> p4d_status {
         BHIPCHK(B, hipMemcpyAsync(B->hb_h, B->hb, hcopy, hipMemcpyDeviceToHost, st));
         BHIPCHK(B, hipStreamSynchronize(st));
         prof_harvest(B->prof);
+        BHIPCHK(B, B->plaunch);
         return P4D_OK;
     };
     auto sum_n = [&](unsigned long long mk, double per_cell_factor, bool stream_len) {
@@ -2736,7 +2773,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                 for (int i = 0; i < n; i++)
                     if ((act >> i) & 1ULL) bytes += B->pc_bytes[i];
                 ProfScope pr(B->prof, P4D_K_BATCH_PC, bytes, st);
-                if (B->pc_mode == 0) {
+                if (B->pc_mode != 1) {
                     batch_apply_pc<T, TZ>(B, transpose, k, act, st);
                 } else {
                     for (int i = 0; i < n; i++)
@@ -3063,7 +3100,7 @@ p4d_status p4d_batch_solve(p4d_batch *B, const double *const *d_b, double *const
 
 p4d_status p4d_batch_set_pc_mode(p4d_batch *B, int32_t mode)
 {
-    if (!B || (mode != 0 && mode != 1)) return P4D_ERR_INVALID_ARG;
+    if (!B || mode < 0 || mode > 2) return P4D_ERR_INVALID_ARG;
     B->pc_mode = mode;
     return P4D_OK;
 }

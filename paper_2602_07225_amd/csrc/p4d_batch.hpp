@@ -79,6 +79,25 @@ __host__ __device__ inline int stage_family(int kind)
 
 template <typename T, typename TZ>
 void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t st);
+
+// One launch for a whole preconditioner application of all cells: the work
+// items of all stage depths (the units of the per-depth work lists, depth
+// after depth), walked depth by depth by a cooperative grid with a grid
+// barrier between depths.
+struct PersistRun {
+    const void *stages;          // PStage<T>[]
+    const PCell *cells;
+    const int *order;            // queue position -> stage index
+    const int *ustart;           // queue position -> first item of that stage
+    const int *dstart;           // depth -> first item; [ndepth]: item count
+    int npos, ndepth;
+    int transpose, k;
+    unsigned long long active;
+};
+template <typename T, typename TZ>
+hipError_t launch_batch_persist(const PersistRun &run, int nrmax, int grid, hipStream_t st);
+template <typename T, typename TZ>
+int batch_persist_slots(int nrmax);   // 0: no cooperative launch
 template <typename T>
 int bstage_sm0_slots();
 

@@ -250,7 +250,8 @@ class P4DBatch:
         return y
 
     def set_pc_mode(self, mode: int):
-        """0: batched stage launches (default); 1: per-cell launches."""
+        """0: batched stage launches, one per stage depth (default); 1: per-cell
+        launches; 2: one persistent launch per preconditioner application."""
         L.p4d_batch_set_pc_mode(self.batch, mode)
 
     def profile(self, class_mask: int):

@@ -85,6 +85,31 @@ def test_batch_equals_single_and_oracle(pc_prec, z_fp32):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("pc_prec", [0, 1])
+def test_batch_persistent_launch_equals_single(pc_prec):
+    """One cooperative launch per preconditioner application (the stage
+    depths walked one after another by the whole grid, with a grid barrier
+    between depths): every cell equals the cell solved alone, also with
+    restarts, and a repeated solve equals the first."""
+    cells, B = batch_for(("small", pc_prec, 0), pc_prec=pc_prec)
+    say(f"persistent launch, pc_prec={pc_prec}")
+    B.setup(rtol=1e-8, maxit=200)
+    B.set_pc_mode(2)
+    try:
+        say("  solve 1")
+        xs, infos = B.solve([p.b for p in cells])
+        say("  solve 2 (restart 5)")
+        xs2, infos2 = B.solve([p.b for p in cells], restart=5, maxit=300)
+        say("  solve 3")
+        xs3, infos3 = B.solve([p.b for p in cells])
+    finally:
+        B.set_pc_mode(0)
+    check_against_single(B, cells, xs, infos)
+    check_against_single(B, cells, xs2, infos2, restart=5, maxit=300)
+    for a, b in zip(xs, xs3):
+        assert np.array_equal(to_np(a), to_np(b))
+
+
 def test_batch_restarts_in_lockstep():
     """Restart length 3: every cell runs several cycles, finishing them at
     different steps."""
@@ -138,6 +163,16 @@ def test_C4_batch_64_cells():
     for i, p in enumerate(cells):
         r = rel(O.Oracle(p).apply(to_np(xs[i])), p.b)
         assert r <= 1.0001e-8, f"cell {i}: residual {r:.2e}"
+    # one persistent launch per application: the same results, bit for bit
+    B.set_pc_mode(2)
+    try:
+        xp, ip = B.solve([p.b for p in cells])
+    finally:
+        B.set_pc_mode(0)
+    say(f"  persistent launch: batch time {ip[0].t_solve_ms:.1f} ms")
+    for i in range(len(cells)):
+        assert ip[i].iters == infos[i].iters
+        assert np.array_equal(to_np(xp[i]), to_np(xs[i])), f"cell {i}"
     first = {}
     for i, p in enumerate(cells):
         first.setdefault((p.nx, tuple(p.nr)), i)
