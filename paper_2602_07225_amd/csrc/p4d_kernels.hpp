@@ -385,6 +385,11 @@ __device__ inline void coarse_block(const CoarseArgs<T> &A, int rowblk, CoarseLd
 // exactly).  A_ss,j = T0 + Gamma s_j e_N e_N^T shares the LU of T0; only the
 // last pivot depends on the node.
 // ---------------------------------------------------------------------------
+// A radial table read through the constant address space: loads from a
+// wave-uniform address become scalar loads (the tables do not change while
+// a kernel runs)
+typedef __attribute__((address_space(4))) const RadialTab ConstTab;
+
 struct RadArgs {
     const RadialTab *tabs;
     const double *gg, *ss, *ee, *mm, *om;
@@ -421,39 +426,46 @@ __device__ inline void rad_fwd_block(const Geom &g, const RadArgs &R, const doub
         double rps = r[je] * rscale;
         const double idps = dir ? 0.0 : (double)invd0[je];
         if (SCHUR) {
-            const RadialTab &Tb = R.tabs[el];
-            const int N = Tb.N;
-            const long long nn = el == 0 ? g.nea : g.nec;
-            const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
-            // all radial values first (indices clamped to the last point), so
-            // the loads are in flight together
-            double rv[NRMAX];
+            auto elim = [&](const auto &Tb) {
+                const int N = Tb.N;
+                const long long nn = el == 0 ? g.nea : g.nec;
+                const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
+                // all radial values first (indices clamped to the last point), so
+                // the loads are in flight together
+                double rv[NRMAX];
 #pragma unroll
-            for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
-            T y = (T)(rv[0] * rscale);
+                for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
+                T y = (T)(rv[0] * rscale);
 #pragma unroll
-            for (int q = 1; q < NRMAX; q++) {
-                if (q < N) {
-                    const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
-                    y = (T)(rv[q] * rscale) - lq * y;
+                for (int q = 1; q < NRMAX; q++) {
+                    if (q < N) {
+                        const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+                        y = (T)(rv[q] * rscale) - lq * y;
+                    }
                 }
-            }
-            const double sj = R.ss[je];
-            const T pivN = (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
-            const double zeta = (double)(y / pivN);
-            const double m = R.mm[je];
-            if (!TRANS) {   // a_y s_j zeta, a_y = (m, -m, -tc m)
-                const double f = sj * zeta;
-                if (!dir) rps -= m * f;
-                rpe += m * f;
-                rce += g.tc * m * f;
-            } else {        // Gamma b_y zeta, b_y = (g, -g, e)
-                const double f = Tb.Gamma * zeta;
-                const double gj = R.gg[je];
-                if (!dir) rps -= gj * f;
-                rpe += gj * f;
-                rce -= R.ee[je] * f;
-            }
+                const double sj = R.ss[je];
+                const T pivN = (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+                const double zeta = (double)(y / pivN);
+                const double m = R.mm[je];
+                if (!TRANS) {   // a_y s_j zeta, a_y = (m, -m, -tc m)
+                    const double f = sj * zeta;
+                    if (!dir) rps -= m * f;
+                    rpe += m * f;
+                    rce += g.tc * m * f;
+                } else {        // Gamma b_y zeta, b_y = (g, -g, e)
+                    const double f = Tb.Gamma * zeta;
+                    const double gj = R.gg[je];
+                    if (!dir) rps -= gj * f;
+                    rpe += gj * f;
+                    rce -= R.ee[je] * f;
+                }
+            };
+            // the tables of the node's electrode: through a wave-uniform pointer
+            // in the constant address space (scalar loads) when the whole wave
+            // lies in one electrode, per lane otherwise
+            const int elw = __builtin_amdgcn_readfirstlane(el);
+            if (__builtin_amdgcn_ballot_w64(el != elw) == 0) elim(*(const ConstTab *)(R.tabs + elw));
+            else elim(R.tabs[el]);
         }
         const T bps = (T)rps;
         b0[je] = bps;
@@ -490,54 +502,61 @@ __device__ inline void rad_back_block(const Geom &g, const RadArgs &R, const dou
     const long long je = base + n - klo * g.nx * g.ny;
     const bool dir = (k == 0);
     const double zps = dir ? r[je] * rscale : (el == 0 ? R.x0[0] : R.x0[1])[je];
-    const RadialTab &Tb = R.tabs[el];
-    const int N = Tb.N;
-    const long long nn = el == 0 ? g.nea : g.nec;
-    const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
-    TZ *zs = z + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
-    const double sj = R.ss[je];
-    double dw = 0.0;   // delta_j * omega_j
-    if (SCHUR) {
-        const double m = R.mm[je];
-        double delta;
-        if (!TRANS)
-            delta = Tb.Gamma * ((dir ? 0.0 : R.gg[je]) * zps - R.gg[je] * zpe + R.ee[je] * zce);
-        else
-            delta = sj * ((dir ? 0.0 : m) * zps - m * zpe - g.tc * m * zce);
-        dw = delta * R.om[je];
-    }
-    // forward elimination; the register arrays are only indexed by unrolled
-    // constants, the last entry is carried separately; all radial values are
-    // loaded first (indices clamped to the last point)
-    double rv[NRMAX];
-#pragma unroll
-    for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
-    // the electrode-level outputs are stored only now, after every load is
-    // issued (a load after them would wait for the loads they depend on)
-    z[g.off_pe + n] = (TZ)zpe;
-    z[g.off_ce + n] = (TZ)zce;
-    z[je] = (TZ)zps;
-    T y[NRMAX];
-    y[0] = (T)(rv[0] * rscale);
-    T ylast = y[0];
-#pragma unroll
-    for (int q = 1; q < NRMAX; q++) {
-        if (q < N) {
-            const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
-            y[q] = (T)(rv[q] * rscale) - lq * y[q - 1];
-            ylast = y[q];
+    auto solve = [&](const auto &Tb) {
+        const int N = Tb.N;
+        const long long nn = el == 0 ? g.nea : g.nec;
+        const double *rs = r + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
+        TZ *zs = z + (el == 0 ? g.off_cs[0] : g.off_cs[1]) + (je - base);
+        const double sj = R.ss[je];
+        double dw = 0.0;   // delta_j * omega_j
+        if (SCHUR) {
+            const double m = R.mm[je];
+            double delta;
+            if (!TRANS)
+                delta = Tb.Gamma * ((dir ? 0.0 : R.gg[je]) * zps - R.gg[je] * zpe + R.ee[je] * zce);
+            else
+                delta = sj * ((dir ? 0.0 : m) * zps - m * zpe - g.tc * m * zce);
+            dw = delta * R.om[je];
         }
-    }
-    T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
-    zs[(long long)(N - 1) * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]));
+        // forward elimination; the register arrays are only indexed by unrolled
+        // constants, the last entry is carried separately; all radial values are
+        // loaded first (indices clamped to the last point)
+        double rv[NRMAX];
 #pragma unroll
-    for (int q = NRMAX - 2; q >= 0; q--) {
-        if (q < N - 1) {
-            const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
-            zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
-            zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
+        for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
+        // the electrode-level outputs are stored only now, after every load is
+        // issued (a load after them would wait for the loads they depend on)
+        z[g.off_pe + n] = (TZ)zpe;
+        z[g.off_ce + n] = (TZ)zce;
+        z[je] = (TZ)zps;
+        T y[NRMAX];
+        y[0] = (T)(rv[0] * rscale);
+        T ylast = y[0];
+#pragma unroll
+        for (int q = 1; q < NRMAX; q++) {
+            if (q < N) {
+                const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+                y[q] = (T)(rv[q] * rscale) - lq * y[q - 1];
+                ylast = y[q];
+            }
         }
-    }
+        T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+        zs[(long long)(N - 1) * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]));
+#pragma unroll
+        for (int q = NRMAX - 2; q >= 0; q--) {
+            if (q < N - 1) {
+                const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
+                zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
+                zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
+            }
+        }
+    };
+    // the tables of the node's electrode: through a wave-uniform pointer in the
+    // constant address space (scalar loads) when the whole wave lies in one
+    // electrode, per lane otherwise
+    const int elw = __builtin_amdgcn_readfirstlane(el);
+    if (__builtin_amdgcn_ballot_w64(el != elw) == 0) solve(*(const ConstTab *)(R.tabs + elw));
+    else solve(R.tabs[el]);
 }
 
 // ---------------------------------------------------------------------------
@@ -648,8 +667,8 @@ __device__ inline void newton_terms(const Geom &g, const TX *x, long long n, int
 struct OpCoupling {
     double q, r0, r1, r2, r3;
 };
-template <bool TRANS>
-__device__ inline OpCoupling op_coupling(const Geom &g, const RadialTab &T, bool dir, double m,
+template <bool TRANS, typename Tab>
+__device__ inline OpCoupling op_coupling(const Geom &g, const Tab &T, bool dir, double m,
                                          double gj, double sj, double ej, double xpsc, double xpe,
                                          double xce, double xsN)
 {
@@ -666,8 +685,9 @@ __device__ inline OpCoupling op_coupling(const Geom &g, const RadialTab &T, bool
 }
 
 // Row r of T0 (or T0^T) applied to a particle column, without the coupling
-__device__ inline double op_radial_row(const RadialTab &T, bool trans, int r, int N, double xm,
-                                       double x0, double xp)
+template <typename Tab>
+__device__ inline double op_radial_row(const Tab &T, bool trans, int r, int N, double xm, double x0,
+                                       double xp)
 {
     if (!trans) return T.tdia[r] * x0 + T.tsub[r] * xm + T.tsup[r] * xp;
     return T.tdia[r] * x0 + (r > 0 ? T.tsup[r > 0 ? r - 1 : 0] : 0.0) * xm +
@@ -716,52 +736,58 @@ __device__ inline double operator_finish(const Geom &g, const OpArgs &O, long lo
         const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
         const bool dir = (k == 0);
         const double xps = ldx(x + je);
-        const RadialTab &T = O.tabs[el];
-        const int N = T.N;
-        const long long nn = el == 0 ? g.nea : g.nec;
-        const long long jl = je - base;
-        const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
-        const TX *xs = x + offs + jl;
-        double *ys = y + offs + jl;
-        const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
-        // the particle column, loaded at once (indices clamped to the last point)
-        double xr[NRMAX], bv[NRMAX];
-        double xsN = 0.0, bps = 0.0;
-        if (!RED) {
+        auto rows = [&](const auto &T) {
+            const int N = T.N;
+            const long long nn = el == 0 ? g.nea : g.nec;
+            const long long jl = je - base;
+            const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+            const TX *xs = x + offs + jl;
+            double *ys = y + offs + jl;
+            const double m = O.mm[je], gj = O.gg[je], sj = O.ss[je], ej = O.ee[je];
+            // the particle column, loaded at once (indices clamped to the last point)
+            double xr[NRMAX], bv[NRMAX];
+            double xsN = 0.0, bps = 0.0;
+            if (!RED) {
 #pragma unroll
-            for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
-            if (RESID) {
+                for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+                if (RESID) {
 #pragma unroll
-                for (int r = 0; r < NRMAX; r++) bv[r] = b[offs + jl + (long long)(r < N ? r : N - 1) * nn];
+                    for (int r = 0; r < NRMAX; r++) bv[r] = b[offs + jl + (long long)(r < N ? r : N - 1) * nn];
+                }
+                xsN = xr[0];
+#pragma unroll
+                for (int r = 1; r < NRMAX; r++)
+                    if (r == N - 1) xsN = xr[r];
             }
-            xsN = xr[0];
+            if (RESID) bps = b[je];
+            const OpCoupling cp = op_coupling<TRANS>(g, T, dir, m, gj, sj, ej, P.xpsc, xpe, xce, xsN);
+            const double q = RED ? cp.q * O.om[je] : cp.q, r3 = cp.r3;
+            double yps = dir ? xps : P.Kps + cp.r0 * q;
+            ype += cp.r1 * q;
+            yce += cp.r2 * q;
+            if (RESID) yps = bps - yps;
+            y[je] = yps;
+            sq += yps * yps;
 #pragma unroll
-            for (int r = 1; r < NRMAX; r++)
-                if (r == N - 1) xsN = xr[r];
-        }
-        if (RESID) bps = b[je];
-        const OpCoupling cp = op_coupling<TRANS>(g, T, dir, m, gj, sj, ej, P.xpsc, xpe, xce, xsN);
-        const double q = RED ? cp.q * O.om[je] : cp.q, r3 = cp.r3;
-        double yps = dir ? xps : P.Kps + cp.r0 * q;
-        ype += cp.r1 * q;
-        yce += cp.r2 * q;
-        if (RESID) yps = bps - yps;
-        y[je] = yps;
-        sq += yps * yps;
-#pragma unroll
-        for (int r = 0; r < NRMAX; r++) {
-            if (RED) break;
-            if (r < N) {
-                const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
-                const double x0 = xr[r];
-                const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
-                double v = op_radial_row(T, TRANS, r, N, xm, x0, xp);
-                if (r == N - 1) v += r3 * q;
-                if (RESID) v = bv[r] - v;
-                ys[(long long)r * nn] = v;
-                sq += v * v;
+            for (int r = 0; r < NRMAX; r++) {
+                if (RED) break;
+                if (r < N) {
+                    const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
+                    const double x0 = xr[r];
+                    const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
+                    double v = op_radial_row(T, TRANS, r, N, xm, x0, xp);
+                    if (r == N - 1) v += r3 * q;
+                    if (RESID) v = bv[r] - v;
+                    ys[(long long)r * nn] = v;
+                    sq += v * v;
+                }
             }
-        }
+        };
+        // the electrode's table through a wave-uniform pointer (scalar loads)
+        // when the whole wave lies in one electrode, per lane otherwise
+        const int elw = __builtin_amdgcn_readfirstlane(el);
+        if (__builtin_amdgcn_ballot_w64(el != elw) == 0) rows(*(const ConstTab *)(O.tabs + elw));
+        else rows(O.tabs[el]);
     }
     if (RESID) {
         ype = bpe - ype;
@@ -1093,31 +1119,37 @@ __device__ inline void operator_radial(const Geom &g, const OpArgs &O, const dou
     const int el = je < g.nea ? 0 : 1;
     const long long nn = el == 0 ? g.nea : g.nec;
     const long long jl = el == 0 ? je : je - g.nea;
-    const RadialTab &T = O.tabs[el];
-    const int N = T.N;
     const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
     const TX_T *xs = x + offs + jl;
     double *ys = O.y + offs + jl;
-    double xr[NRMAX];
+    auto rows = [&](const auto &T) {
+        const int N = T.N;
+        double xr[NRMAX];
 #pragma unroll
-    for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
-    const double r3 = TRANS ? O.ss[je] : T.Gamma, qj = q[je];
-    // all rows first, then the stores: a table read after a store may not be
-    // hoisted above it (the pointers may alias), which would chain the rows'
-    // cache latencies
-    double v[NRMAX];
+        for (int r = 0; r < NRMAX; r++) xr[r] = ldx(xs + (long long)(r < N ? r : N - 1) * nn);
+        const double r3 = TRANS ? O.ss[je] : T.Gamma, qj = q[je];
+        // all rows first, then the stores: a table read after a store may not
+        // be hoisted above it (the pointers may alias), which would chain the
+        // rows' cache latencies
+        double v[NRMAX];
 #pragma unroll
-    for (int r = 0; r < NRMAX; r++) {
-        if (r < N) {
-            const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
-            const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
-            v[r] = op_radial_row(T, TRANS, r, N, xm, xr[r], xp);
-            if (r == N - 1) v[r] += r3 * qj;   // the same expression as in operator_finish
+        for (int r = 0; r < NRMAX; r++) {
+            if (r < N) {
+                const double xm = r > 0 ? xr[r > 0 ? r - 1 : 0] : 0.0;
+                const double xp = r < N - 1 ? xr[r + 1 < NRMAX ? r + 1 : r] : 0.0;
+                v[r] = op_radial_row(T, TRANS, r, N, xm, xr[r], xp);
+                if (r == N - 1) v[r] += r3 * qj;   // the same expression as in operator_finish
+            }
         }
-    }
 #pragma unroll
-    for (int r = 0; r < NRMAX; r++)
-        if (r < N) ys[(long long)r * nn] = v[r];
+        for (int r = 0; r < NRMAX; r++)
+            if (r < N) ys[(long long)r * nn] = v[r];
+    };
+    // the electrode's table through a wave-uniform pointer (scalar loads) when
+    // the whole wave lies in one electrode, per lane otherwise
+    const int elw = __builtin_amdgcn_readfirstlane(el);
+    if (__builtin_amdgcn_ballot_w64(el != elw) == 0) rows(*(const ConstTab *)(O.tabs + elw));
+    else rows(O.tabs[el]);
 }
 
 }  // namespace p4d
