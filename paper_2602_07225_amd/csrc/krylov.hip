@@ -201,4 +201,26 @@ void launch_dot_partial(long long n, const double *a, const double *b, double *p
     hipLaunchKernelGGL(k_dot, dim3(nblk), dim3(kBlock), 0, st, n, a, b, partial);
 }
 
+// Hand n device values (the bits of doubles or of 64-bit integers) to the
+// host: copied into mapped host memory, then the sequence number is raised.
+// Every thread releases its copies at system scope before the barrier, after
+// which one thread stores the number; a host that sees the number sees the
+// values.
+__global__ __launch_bounds__(kBlock) void k_publish(const unsigned long long *__restrict__ src, int n,
+                                                    unsigned long long *dst, unsigned long long *seq_out,
+                                                    unsigned long long seq)
+{
+    for (int i = threadIdx.x; i < n; i += kBlock) dst[i] = src[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const void *src, int n, void *dst, unsigned long long *seq_out, unsigned long long seq,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(kBlock), 0, st, (const unsigned long long *)src, n,
+                       (unsigned long long *)dst, seq_out, seq);
+}
+
 }  // namespace p4d

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -99,6 +100,10 @@ struct p4d_ctx {
     char *scratch = nullptr;       // Krylov basis region, also setup scratch
     size_t scratch_bytes = 0;
     double *hhost = nullptr;       // pinned host staging
+    // values handed from the device to the host (launch_publish): mapped,
+    // coherent pinned memory (kPubMax values, then the sequence number)
+    unsigned long long *hpub = nullptr, *hpub_dev = nullptr;
+    unsigned long long pub_seq = 0;
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     int tiles_tuned = 0;           // set by the autotuner; else chosen at layout time
     int op_tx = 64, op_cz = 4;     // operator tiles (op_tx = 0: one thread per node)
@@ -131,6 +136,52 @@ static p4d_status hipchk(p4d_ctx *c, hipError_t e, const char *where)
     } while (0)
 
 static int coarse_n_h(int n) { return n <= 2 ? n : n / 2 + 1; }
+
+// Device values the host waits for (norms, Hessenberg columns, Gershgorin
+// bounds): a one-workgroup kernel copies them into mapped host memory and
+// then raises a sequence number, on which the host spins.  The handoff costs
+// a few microseconds less than a copy and a stream synchronization, and the
+// solve makes one per Arnoldi step.
+constexpr int kPubMax = 2048;
+static p4d_status alloc_pub(p4d_ctx *c)
+{
+    void *h = nullptr, *d = nullptr;
+    if (hipHostMalloc(&h, 8 * (kPubMax + 16), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return P4D_ERR_HIP;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        hipHostFree(h);
+        return P4D_ERR_HIP;
+    }
+    c->hpub = (unsigned long long *)h;
+    c->hpub_dev = (unsigned long long *)d;
+    c->hpub[kPubMax] = 0;
+    c->pub_seq = 0;
+    return P4D_OK;
+}
+
+// n (<= kPubMax) 64-bit values at src (device) to c->hpub, after the work
+// already on st; returns once they are there.  An error of the stream ends
+// the wait with that error.
+static p4d_status pull(p4d_ctx *c, const void *src, int n, hipStream_t st)
+{
+    const unsigned long long seq = ++c->pub_seq;
+    launch_publish(src, n, c->hpub_dev, c->hpub_dev + kPubMax, seq, st);
+    HIPCHK(c, hipGetLastError());
+    volatile unsigned long long *flag = c->hpub + kPubMax;
+    for (long long polls = 1; *flag != seq; polls++) {
+        if ((polls & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) {
+                if (*flag == seq) break;
+                return fail(c, P4D_ERR_HIP, "a value handed to the host did not arrive");
+            }
+            if (e != hipErrorNotReady) return hipchk(c, e, "hipStreamQuery");
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return P4D_OK;
+}
 
 // Geometric radial mesh on [0, 1] with Delta_{i+1} = q Delta_i and
 // Delta_{N-1} / Delta_1 = theta_bar (Sec. 3.1, after Remark 3.1).
@@ -1112,9 +1163,12 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     launch_invert(ib, st);
     launch_cast<T>(g.Nm, id64, (T *)c->invd0, st);
     HIPCHK(c, hipGetLastError());
-    std::vector<unsigned long long> lmh(nlmx);
-    HIPCHK(c, hipMemcpyAsync(lmh.data(), lmx, 8 * nlmx, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    static_assert(4 * kMaxLevels * kLmaxSlots <= kPubMax, "Gershgorin slots exceed the handoff buffer");
+    {
+        const p4d_status ps = pull(c, lmx, (int)nlmx, st);
+        if (ps != P4D_OK) return ps;
+    }
+    const unsigned long long *lmh = c->hpub;
     for (int b = 0; b < 4; b++)
         for (int l = 0; l < c->box[b].nlev; l++) {
             unsigned long long bits = 0;   // bits of the maximum (non-negative doubles order as integers)
@@ -1154,8 +1208,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
     const int sb = stream_blocks(N);
     const int sbf = stream_blocks(g.N);
     const int ob = operator_blocks(g);
-    double *hh = c->hhost;           // device-to-host staging
-    double *hout = c->hhost + 256;   // host-to-device staging
+    const double *hh = (const double *)c->hpub;   // values handed to the host (pull)
+    double *hout = c->hhost + 256;                 // host-to-device staging
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m), hc(m + 2),
         beta(m + 1);
     p4d_solve_info inf{};
@@ -1170,8 +1224,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             apply_op<double>(c, transpose, x, V, b, red, st);
             launch_norm_final(red, ob, c->hdev + 200, c->invbeta, st);
         }
-        HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
+        const p4d_status ps = pull(c, c->hdev + 200, 1, st);
+        if (ps != P4D_OK) return ps;
         prof_harvest(c->prof);
         return P4D_OK;
     };
@@ -1179,8 +1233,10 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
     // ||b|| over all unknowns
     launch_dot_partial(g.N, b, b, red, sbf, st);
     launch_norm_final(red, sbf, c->hdev, nullptr, st);
-    HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    {
+        const p4d_status ps = pull(c, c->hdev, 1, st);
+        if (ps != P4D_OK) return ps;
+    }
     const double bnorm = hh[0];
     HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
     if (!std::isfinite(bnorm)) {
@@ -1205,8 +1261,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             if (schur) {
                 launch_dot_partial(N, bk, bk, red, sb, st);
                 launch_norm_final(red, sb, c->hdev + 200, c->invbeta, st);
-                HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
-                HIPCHK(c, hipStreamSynchronize(st));
+                const p4d_status ps = pull(c, c->hdev + 200, 1, st);
+                if (ps != P4D_OK) return ps;
                 beta[0] = hh[0];
             } else {
                 hout[0] = 1.0 / bnorm;
@@ -1252,8 +1308,10 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
                 }
             }
             launch_norm_final(red, sb, c->hdev + 128, c->invbeta + k + 1, st);
-            HIPCHK(c, hipMemcpyAsync(hh, c->hdev, 8 * 129, hipMemcpyDeviceToHost, st));
-            HIPCHK(c, hipStreamSynchronize(st));
+            {
+                const p4d_status ps = pull(c, c->hdev, 129, st);
+                if (ps != P4D_OK) return ps;
+            }
             prof_harvest(c->prof);
             for (int i = 0; i <= k; i++) hc[i] = hh[i] + (o.cgs2 ? hh[64 + i] : 0.0);
             const double hn = hh[128];
@@ -1313,13 +1371,16 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         }
         apply_op<double>(c, transpose, x, V, b, red, st);
         launch_norm_final(red, ob, c->hdev + 200, nullptr, st);
-        HIPCHK(c, hipMemcpyAsync(hh, c->hdev + 200, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
+        const p4d_status ps = pull(c, c->hdev + 200, 1, st);
+        if (ps != P4D_OK) return ps;
         inf.relres_true = hh[0] / bnorm;
     }
 done:
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, hipStreamSynchronize(st));
+    {   // the solution is complete when the handoff after it arrives
+        const p4d_status ps = pull(c, c->hdev, 0, st);
+        if (ps != P4D_OK) return ps;
+    }
     prof_harvest(c->prof);
     inf.iters = total;
     inf.status = status;
@@ -1510,6 +1571,11 @@ p4d_status p4d_create(const p4d_problem_desc *d, p4d_ctx **out)
         delete c;
         return P4D_ERR_HIP;
     }
+    if (alloc_pub(c) != P4D_OK) {
+        hipHostFree(c->hhost);
+        delete c;
+        return P4D_ERR_HIP;
+    }
     c->tile_tx = d->nx >= 48 ? 64 : (d->nx >= 24 ? 32 : 16);
     c->tile_cz = 8;
     prof_init(c->prof);
@@ -1523,6 +1589,7 @@ void p4d_destroy(p4d_ctx *c)
     if (!c) return;
     prof_free(c->prof);
     if (c->hhost) hipHostFree(c->hhost);
+    if (c->hpub) hipHostFree(c->hpub);
     delete c->phys;
     delete c;
 }
@@ -1920,6 +1987,9 @@ p4d_status p4d_solve_noalloc(p4d_ctx *c, const double *sigma, const double *kapp
     p4d_status st = noalloc_base(c, &base);
     if (st != P4D_OK) return st;
     t.hhost = c->hhost;   // the caller context's pinned staging (no allocation)
+    t.hpub = c->hpub;
+    t.hpub_dev = c->hpub_dev;
+    t.pub_seq = c->pub_seq;
     t.ws = base;
     t.ws_bytes = P4D_NOALLOC_MAX_BYTES;
     // every array of the layout is written before it is read (as with a
@@ -1929,7 +1999,9 @@ p4d_status p4d_solve_noalloc(p4d_ctx *c, const double *sigma, const double *kapp
     if (st == P4D_OK) st = p4d_setup(&t, &o, stream);
     if (st == P4D_OK) st = p4d_solve(&t, b, x, &o, info, stream);
     if (st != P4D_OK) c->err = t.err;
+    c->pub_seq = t.pub_seq;
     t.hhost = nullptr;
+    t.hpub = t.hpub_dev = nullptr;
     return st;
 }
 
@@ -2146,10 +2218,12 @@ p4d_status p4d_phys_newton_step(p4d_ctx *c, double *u, const double *uold, const
         inf.lin_iters += li.iters;
         const int nb = launch_phys_update(c->g, S.P, S.dh, u, c->red, st);
         launch_max_final(c->red, nb, c->scal + 100, st);
-        HIPCHK(c, hipMemcpyAsync(c->hhost, c->scal + 100, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
+        {
+            const p4d_status ps = pull(c, c->scal + 100, 1, st);
+            if (ps != P4D_OK) return ps;
+        }
         inf.iters = it + 1;
-        inf.update = c->hhost[0];
+        inf.update = *(const double *)c->hpub;
         if (!std::isfinite(inf.update)) {
             inf.status = P4D_ERR_NONFINITE;
             break;

@@ -358,5 +358,9 @@ void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const
                hipStream_t st);
 void launch_dot_partial(long long n, const double *a, const double *b, double *partial,
                         int nblk, hipStream_t st);
+// n 64-bit values from src (device) to dst (mapped host memory, its device
+// address), then seq to seq_out (mapped host memory) once they are visible
+void launch_publish(const void *src, int n, void *dst, unsigned long long *seq_out, unsigned long long seq,
+                    hipStream_t st);
 
 }  // namespace p4d
