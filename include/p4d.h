@@ -197,7 +197,11 @@ p4d_status p4d_upload(p4d_ctx *ctx, const double *d_sigma, const double *d_kappa
 p4d_status p4d_set_diffusivity(p4d_ctx *ctx, const double Ds[2], void *stream);
 
 /* Build the preconditioner (surface-coupling weights, Galerkin multigrid
- * hierarchies, Chebyshev bounds, dense coarse inverses).  Synchronizes.    */
+ * hierarchies, Chebyshev bounds, dense coarse inverses) on `stream`.  Returns
+ * without waiting for its kernels: the Chebyshev bounds reach the host at
+ * the first use of the preconditioner (p4d_solve, p4d_solve_adjoint,
+ * p4d_apply_preconditioner, p4d_autotune, batch solves), which then reports
+ * a non-positive or non-finite bound as P4D_ERR_NONFINITE.                  */
 p4d_status p4d_setup(p4d_ctx *ctx, const p4d_solve_opts *opts, void *stream);
 
 /* Separate element coefficients (device, one per element, caller-owned, read
@@ -297,6 +301,12 @@ typedef enum {
     P4D_K_COUNT = 9
 } p4d_kernel_class;
 p4d_status p4d_profile(p4d_ctx *ctx, int class_mask);
+/* Time only one launch in `every` (>= 1, default 1) of each class in the
+ * mask, counted per class from this call or the last p4d_profile: fewer
+ * event pairs on the stream while the average over the timed launches stays
+ * that of the class (a pair costs a few microseconds of the stream's time).
+ * The totals of p4d_profile_read then cover the timed launches only.       */
+p4d_status p4d_profile_every(p4d_ctx *ctx, int every);
 /* For one class: total_ms = summed kernel durations, launches, and bytes =
  * algorithmic bytes of those launches (the data each launch must read and
  * write once).                                                              */
@@ -369,10 +379,10 @@ p4d_status p4d_batch_solve(p4d_batch *batch, const double *const *d_b, double *c
                            const p4d_solve_opts *opts, p4d_solve_info *infos, void *stream);
 /* mode 0 (default): batched stage launches, one per stage depth; mode 1: the
  * single-cell preconditioner launches, cell after cell (a reference); mode 2:
- * one persistent launch per application (workgroups take chunks of stage
- * units from a queue and wait, bounded, for the cell's previous stage; if a
- * wait gives up, p4d_batch_solve returns P4D_ERR_HIP).  The three give the
- * same results bit for bit.                                                 */
+ * one cooperative launch per application: the whole grid walks the stage
+ * depths with a grid barrier between depths (P4D_ERR_HIP where the device
+ * cannot launch it cooperatively).  The three give the same results bit for
+ * bit.                                                                      */
 p4d_status p4d_batch_set_pc_mode(p4d_batch *batch, int32_t mode);
 /* Kernel timing of the batched launches, as p4d_profile / p4d_profile_read;
  * P4D_K_BATCH_PC times all preconditioner launches of one Arnoldi step

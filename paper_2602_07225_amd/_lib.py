@@ -51,7 +51,7 @@ EXPORTED = [
     "p4d_apply_operator",
     "p4d_apply_schur_operator", "p4d_apply_preconditioner", "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient",
     "p4d_solve_noalloc",
-    "p4d_profile", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
+    "p4d_profile", "p4d_profile_every", "p4d_profile_read", "p4d_status_string", "p4d_last_error", "p4d_autotune",
     "p4d_batch_create", "p4d_batch_destroy", "p4d_batch_cell", "p4d_batch_workspace_size",
     "p4d_batch_set_workspace", "p4d_batch_upload", "p4d_batch_setup", "p4d_batch_autotune",
     "p4d_batch_solve", "p4d_batch_set_pc_mode", "p4d_batch_profile", "p4d_batch_profile_read",
@@ -152,6 +152,7 @@ def lib():
         L.p4d_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts),
                                         C.POINTER(SolveInfo), vp]
         L.p4d_profile.argtypes = [vp, C.c_int]
+        L.p4d_profile_every.argtypes = [vp, C.c_int]
         L.p4d_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.p4d_status_string.argtypes = [C.c_int]
@@ -164,7 +165,7 @@ def lib():
                      "p4d_apply_operator",
                      "p4d_apply_preconditioner", "p4d_apply_schur_operator",
                      "p4d_solve", "p4d_solve_adjoint", "p4d_param_gradient", "p4d_profile",
-                     "p4d_profile_read", "p4d_solve_noalloc"]:
+                     "p4d_profile_every", "p4d_profile_read", "p4d_solve_noalloc"]:
             getattr(L, name).restype = C.c_int
         _bind_batch(L)
         _bind_phys(L)
@@ -439,6 +440,10 @@ def p4d_param_gradient(ctx, x, lam, dsigma, dDs, stream=None):
 
 def p4d_profile(ctx, class_mask: int):
     return check(lib().p4d_profile(ctx, class_mask), ctx, "p4d_profile")
+
+
+def p4d_profile_every(ctx, every: int):
+    return check(lib().p4d_profile_every(ctx, every), ctx, "p4d_profile_every")
 
 
 def p4d_profile_read(ctx, kernel_class: int):

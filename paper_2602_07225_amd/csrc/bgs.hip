@@ -17,8 +17,9 @@ namespace p4d {
 
 template <typename T, bool TRANS>
 __global__ __launch_bounds__(kBlock) void k_bgs_rhs(Geom g, BgsArgs B, const double *__restrict__ r,
-                                                    double rscale)
+                                                    const double *rscale_p)
 {
+    const double rscale = rscale_p ? *rscale_p : 1.0;
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
     const int f = B.field, done = B.done;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs_rhs(Geom g, BgsArgs B, const dou
 }
 
 template <typename T>
-void launch_bgs_rhs(const Geom &g, const BgsArgs &B, const double *r, double rscale, int transpose,
+void launch_bgs_rhs(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, int transpose,
                     hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
@@ -86,9 +87,9 @@ void launch_bgs_rhs(const Geom &g, const BgsArgs &B, const double *r, double rsc
     else
         hipLaunchKernelGGL((k_bgs_rhs<T, false>), dim3(nb), dim3(kBlock), 0, st, g, B, r, rscale);
 }
-template void launch_bgs_rhs<double>(const Geom &, const BgsArgs &, const double *, double, int,
+template void launch_bgs_rhs<double>(const Geom &, const BgsArgs &, const double *, const double *, int,
                                      hipStream_t);
-template void launch_bgs_rhs<float>(const Geom &, const BgsArgs &, const double *, double, int,
+template void launch_bgs_rhs<float>(const Geom &, const BgsArgs &, const double *, const double *, int,
                                     hipStream_t);
 
 // A_ss,j = T0 + Gamma s_j e_N e_N^T, so A_ss,j^-1 e_N = omega_j T0^-1 e_N with
@@ -96,8 +97,9 @@ template void launch_bgs_rhs<float>(const Geom &, const BgsArgs &, const double 
 // precision T sees r_s only and the coupling delta_j is applied in FP64.
 template <typename T, typename TZ, int NRMAX, bool TRANS>
 __global__ __launch_bounds__(kBlock) void k_bgs_cs(Geom g, BgsArgs B, const double *__restrict__ r,
-                                                   double rscale, TZ *__restrict__ z)
+                                                   const double *rscale_p, TZ *__restrict__ z)
 {
+    const double rscale = rscale_p ? *rscale_p : 1.0;
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
     const int k = (int)(n / ((long long)g.nx * g.ny));
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs_cs(Geom g, BgsArgs B, const doub
 }
 
 template <typename T, typename TZ>
-void launch_bgs_cs(const Geom &g, const BgsArgs &B, const double *r, double rscale, TZ *z,
+void launch_bgs_cs(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, TZ *z,
                    int transpose, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
@@ -166,19 +168,20 @@ void launch_bgs_cs(const Geom &g, const BgsArgs &B, const double *r, double rsca
 #undef P4D_BC2
 #undef P4D_BC
 }
-template void launch_bgs_cs<double, double>(const Geom &, const BgsArgs &, const double *, double,
+template void launch_bgs_cs<double, double>(const Geom &, const BgsArgs &, const double *, const double *,
                                             double *, int, hipStream_t);
-template void launch_bgs_cs<float, double>(const Geom &, const BgsArgs &, const double *, double,
+template void launch_bgs_cs<float, double>(const Geom &, const BgsArgs &, const double *, const double *,
                                            double *, int, hipStream_t);
-template void launch_bgs_cs<double, float>(const Geom &, const BgsArgs &, const double *, double,
+template void launch_bgs_cs<double, float>(const Geom &, const BgsArgs &, const double *, const double *,
                                            float *, int, hipStream_t);
-template void launch_bgs_cs<float, float>(const Geom &, const BgsArgs &, const double *, double,
+template void launch_bgs_cs<float, float>(const Geom &, const BgsArgs &, const double *, const double *,
                                           float *, int, hipStream_t);
 
 template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_bgs_out(Geom g, BgsArgs B, const double *__restrict__ r,
-                                                    double rscale, TZ *__restrict__ z)
+                                                    const double *rscale_p, TZ *__restrict__ z)
 {
+    const double rscale = rscale_p ? *rscale_p : 1.0;
     const long long n = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.nnode) return;
     const RadArgs &R = B.R;
@@ -194,15 +197,15 @@ __global__ __launch_bounds__(kBlock) void k_bgs_out(Geom g, BgsArgs B, const dou
 }
 
 template <typename TZ>
-void launch_bgs_out(const Geom &g, const BgsArgs &B, const double *r, double rscale, TZ *z,
+void launch_bgs_out(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, TZ *z,
                     hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
     hipLaunchKernelGGL((k_bgs_out<TZ>), dim3(nb), dim3(kBlock), 0, st, g, B, r, rscale, z);
 }
-template void launch_bgs_out<double>(const Geom &, const BgsArgs &, const double *, double, double *,
+template void launch_bgs_out<double>(const Geom &, const BgsArgs &, const double *, const double *, double *,
                                      hipStream_t);
-template void launch_bgs_out<float>(const Geom &, const BgsArgs &, const double *, double, float *,
+template void launch_bgs_out<float>(const Geom &, const BgsArgs &, const double *, const double *, float *,
                                     hipStream_t);
 
 }  // namespace p4d

@@ -57,6 +57,8 @@ struct PhysState {
 
 struct Prof {
     int mask = 0;
+    int every = 1;                // time one launch in `every` of each class
+    long long seen[P4D_K_COUNT] = {};
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<double> bytes;    // per pair
     std::vector<int> cls;         // per pair
@@ -101,9 +103,13 @@ struct p4d_ctx {
     size_t scratch_bytes = 0;
     double *hhost = nullptr;       // pinned host staging
     // values handed from the device to the host (launch_publish): mapped,
-    // coherent pinned memory (kPubMax values, then the sequence number)
+    // coherent pinned memory (slots of kPubMax values and a sequence number)
     unsigned long long *hpub = nullptr, *hpub_dev = nullptr;
     unsigned long long pub_seq = 0;
+    // Gershgorin bounds of the last setup still on their way (finish_setup)
+    int lmax_pending = 0;
+    unsigned long long lmax_seq = 0;
+    hipStream_t lmax_stream = nullptr;
     int tile_tx = 64, tile_cz = 8; // level-0 smoother tiles
     int tiles_tuned = 0;           // set by the autotuner; else chosen at layout time
     int op_tx = 64, op_cz = 4;     // operator tiles (op_tx = 0: one thread per node)
@@ -141,12 +147,18 @@ static int coarse_n_h(int n) { return n <= 2 ? n : n / 2 + 1; }
 // bounds): a one-workgroup kernel copies them into mapped host memory and
 // then raises a sequence number, on which the host spins.  The handoff costs
 // a few microseconds less than a copy and a stream synchronization, and the
-// solve makes one per Arnoldi step.
+// solve makes one per Arnoldi step.  Two slots for the solve, so that the
+// values of one step can be on their way while the host still reads the
+// previous step's, and one for the setup.
 constexpr int kPubMax = 2048;
+constexpr int kPubStride = kPubMax + 16;   // slot: kPubMax values, then the sequence number
+constexpr int kPubSlots = 3;               // 0, 1: the solve; 2: the setup's bounds
+constexpr int kPubSetup = 2;
 static p4d_status alloc_pub(p4d_ctx *c)
 {
     void *h = nullptr, *d = nullptr;
-    if (hipHostMalloc(&h, 8 * (kPubMax + 16), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    if (hipHostMalloc(&h, 8 * kPubSlots * kPubStride, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         return P4D_ERR_HIP;
     if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
         hipHostFree(h);
@@ -154,20 +166,27 @@ static p4d_status alloc_pub(p4d_ctx *c)
     }
     c->hpub = (unsigned long long *)h;
     c->hpub_dev = (unsigned long long *)d;
-    c->hpub[kPubMax] = 0;
+    for (int q = 0; q < kPubSlots; q++) c->hpub[q * kPubStride + kPubMax] = 0;
     c->pub_seq = 0;
     return P4D_OK;
 }
 
-// n (<= kPubMax) 64-bit values at src (device) to c->hpub, after the work
-// already on st; returns once they are there.  An error of the stream ends
-// the wait with that error.
-static p4d_status pull(p4d_ctx *c, const void *src, int n, hipStream_t st)
+// n (<= kPubMax) 64-bit values at src (device) to slot `slot` of c->hpub,
+// after the work already on st; returns the sequence number to wait for
+static unsigned long long publish(p4d_ctx *c, const void *src, int n, int slot, hipStream_t st)
 {
     const unsigned long long seq = ++c->pub_seq;
-    launch_publish(src, n, c->hpub_dev, c->hpub_dev + kPubMax, seq, st);
+    launch_publish(src, n, c->hpub_dev + slot * kPubStride, c->hpub_dev + slot * kPubStride + kPubMax, seq,
+                   st);
+    return seq;
+}
+
+// Wait until slot `slot` holds the values of publish number seq.  An error
+// of the stream ends the wait with that error.
+static p4d_status await_pub(p4d_ctx *c, int slot, unsigned long long seq, hipStream_t st)
+{
     HIPCHK(c, hipGetLastError());
-    volatile unsigned long long *flag = c->hpub + kPubMax;
+    volatile unsigned long long *flag = c->hpub + slot * kPubStride + kPubMax;
     for (long long polls = 1; *flag != seq; polls++) {
         if ((polls & 1023) == 0) {
             const hipError_t e = hipStreamQuery(st);
@@ -181,6 +200,12 @@ static p4d_status pull(p4d_ctx *c, const void *src, int n, hipStream_t st)
     }
     std::atomic_thread_fence(std::memory_order_acquire);
     return P4D_OK;
+}
+
+// publish into slot 0 and wait: the values are then at c->hpub
+static p4d_status pull(p4d_ctx *c, const void *src, int n, hipStream_t st)
+{
+    return await_pub(c, 0, publish(c, src, n, 0, st), st);
 }
 
 // Geometric radial mesh on [0, 1] with Delta_{i+1} = q Delta_i and
@@ -493,6 +518,7 @@ static void prof_reset(Prof &P, int mask)
         P.total_ms[k] = 0.0;
         P.total_bytes[k] = 0.0;
         P.launches[k] = 0;
+        P.seen[k] = 0;
     }
 }
 struct ProfScope {
@@ -502,6 +528,7 @@ struct ProfScope {
     ProfScope(Prof &P_, int cls, double bytes, hipStream_t s) : P(P_), on(false), st(s)
     {
         if (!(P.mask & (1 << cls))) return;
+        if (P.seen[cls]++ % P.every) return;
         if (P.used * 2 + 2 > (int)P.ev.size()) prof_harvest(P);
         P.bytes[P.used] = bytes;
         P.cls[P.used] = cls;
@@ -925,9 +952,10 @@ static RadArgs rad_args(const p4d_ctx *c)
     return R;
 }
 
-// z = P^-1 (rscale r), or P^-T
+// z = P^-1 (s r), or P^-T, with the scale s read from device memory (rscale;
+// null: 1)
 template <typename T, typename TZ>
-static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, const double *rscale, TZ *z,
                        hipStream_t st)
 {
     const Geom &g = c->g;
@@ -961,7 +989,7 @@ static void apply_pc_t(p4d_ctx *c, int transpose, const double *r, double rscale
 // field only; the level-0 iterates of the fields solved stay in place (each
 // box owns its slice of the level-0 buffers) and feed the later couplings.
 template <typename T, typename TZ>
-static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, const double *rscale, TZ *z,
                         hipStream_t st)
 {
     const Geom &g = c->g;
@@ -1006,7 +1034,7 @@ static void apply_bgs_t(p4d_ctx *c, int transpose, const double *r, double rscal
 // field on S~_f (the field blocks of S, the SCHUR-mode boxes), identity on
 // the grounded layer; r and z hold the electrode-level unknowns only.
 template <typename T, typename TZ>
-static void apply_pc_schur_t(p4d_ctx *c, const double *r, double rscale, TZ *z, hipStream_t st)
+static void apply_pc_schur_t(p4d_ctx *c, const double *r, const double *rscale, TZ *z, hipStream_t st)
 {
     const Geom &g = c->g;
     BgsArgs B{};
@@ -1025,14 +1053,14 @@ static void apply_pc_schur_t(p4d_ctx *c, const double *r, double rscale, TZ *z, 
 }
 
 template <typename TZ>
-static void apply_pc_schur(p4d_ctx *c, const double *r, double rscale, TZ *z, hipStream_t st)
+static void apply_pc_schur(p4d_ctx *c, const double *r, const double *rscale, TZ *z, hipStream_t st)
 {
     if (c->prec == 1) apply_pc_schur_t<float, TZ>(c, r, rscale, z, st);
     else apply_pc_schur_t<double, TZ>(c, r, rscale, z, st);
 }
 
 template <typename TZ>
-static void apply_pc(p4d_ctx *c, int transpose, const double *r, double rscale, TZ *z,
+static void apply_pc(p4d_ctx *c, int transpose, const double *r, const double *rscale, TZ *z,
                      hipStream_t st)
 {
     if (c->pc.pc == P4D_PC_BGS) {
@@ -1163,12 +1191,29 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
     launch_invert(ib, st);
     launch_cast<T>(g.Nm, id64, (T *)c->invd0, st);
     HIPCHK(c, hipGetLastError());
+    // the Gershgorin maxima go to the host in a slot of their own; the first
+    // use of the preconditioner waits for them (finish_setup), so the setup
+    // returns without waiting for its kernels
     static_assert(4 * kMaxLevels * kLmaxSlots <= kPubMax, "Gershgorin slots exceed the handoff buffer");
-    {
-        const p4d_status ps = pull(c, lmx, (int)nlmx, st);
-        if (ps != P4D_OK) return ps;
+    c->lmax_seq = publish(c, lmx, (int)nlmx, kPubSetup, st);
+    c->lmax_stream = st;
+    c->lmax_pending = 1;
+    HIPCHK(c, hipGetLastError());
+    return P4D_OK;
+}
+
+// The Chebyshev bounds of the last setup (the largest Gershgorin ratio of
+// every level), once its kernels have handed them over
+static p4d_status finish_setup(p4d_ctx *c)
+{
+    if (!c->lmax_pending) return P4D_OK;
+    c->lmax_pending = 0;
+    const p4d_status ps = await_pub(c, kPubSetup, c->lmax_seq, c->lmax_stream);
+    if (ps != P4D_OK) {
+        c->pc_ready = 0;
+        return ps;
     }
-    const unsigned long long *lmh = c->hpub;
+    const unsigned long long *lmh = c->hpub + kPubSetup * kPubStride;
     for (int b = 0; b < 4; b++)
         for (int l = 0; l < c->box[b].nlev; l++) {
             unsigned long long bits = 0;   // bits of the maximum (non-negative doubles order as integers)
@@ -1176,8 +1221,10 @@ static p4d_status setup_t(p4d_ctx *c, hipStream_t st)
                 bits = std::max(bits, lmh[(16 * (size_t)b + l) * kLmaxSlots + q]);
             double lm;
             std::memcpy(&lm, &bits, sizeof(lm));
-            if (!(lm > 0.0) || !std::isfinite(lm))
+            if (!(lm > 0.0) || !std::isfinite(lm)) {
+                c->pc_ready = 0;
                 return fail(c, P4D_ERR_NONFINITE, "non-positive or non-finite Gershgorin bound");
+            }
             c->box[b].lev[l].lmax = lm;
         }
     return P4D_OK;
@@ -1211,9 +1258,16 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
     const double *hh = (const double *)c->hpub;   // values handed to the host (pull)
     double *hout = c->hhost + 256;                 // host-to-device staging
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m), hc(m + 2),
-        beta(m + 1);
+        beta(m + 1), res(m + 1);
     p4d_solve_info inf{};
     auto t0 = std::chrono::steady_clock::now();
+    // the setup's bounds: waited for before the first preconditioner
+    // application, or now if the setup ran on another stream (this stream
+    // does not follow its kernels)
+    if (c->lmax_pending && c->lmax_stream != st) {
+        const p4d_status fs = finish_setup(c);
+        if (fs != P4D_OK) return fs;
+    }
     // r = bk - op(x) into V_0 with its norm (restarts and breakdown)
     auto residual = [&]() -> p4d_status {
         if (schur) {
@@ -1281,17 +1335,22 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         if (total >= o.maxit) { status = P4D_NOT_CONVERGED; break; }
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta[0];
+        res[0] = beta[0];
         int kused = 0;
         bool breakdown = false, nonfinite = false;
-        for (int k = 0; k < m; k++) {
+        // one Arnoldi step on the device: z_k = P^-1 v_k / beta_k, w = A z_k,
+        // Gram-Schmidt against V_0..V_k, ||w|| and 1 / ||w|| (every input it
+        // needs is in device memory), then its Hessenberg column to the host
+        unsigned long long step_seq[2] = {0, 0};
+        auto enqueue_step = [&](int k) {
             double *vk = V + (long long)k * N;
             TZ *zk = Z + (long long)k * N;
             double *w = V + (long long)(k + 1) * N;
             if (schur) {
-                apply_pc_schur<TZ>(c, vk, 1.0 / beta[k], zk, st);
+                apply_pc_schur<TZ>(c, vk, c->invbeta + k, zk, st);
                 apply_op_schur<TZ>(c, transpose, zk, w, st);
             } else {
-                apply_pc<TZ>(c, transpose, vk, 1.0 / beta[k], zk, st);
+                apply_pc<TZ>(c, transpose, vk, c->invbeta + k, zk, st);
                 apply_op<TZ>(c, transpose, zk, w, nullptr, nullptr, st);
             }
             const int nv = k + 1;
@@ -1308,11 +1367,35 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
                 }
             }
             launch_norm_final(red, sb, c->hdev + 128, c->invbeta + k + 1, st);
+            step_seq[k & 1] = publish(c, c->hdev, 129, k & 1, st);
+        };
+        // The next step is enqueued before the host reads this step's column
+        // when the residual estimate is expected to stay above the tolerance
+        // (its rate of decrease so far, with a margin): the device then runs
+        // on while the host waits.  If the solve stops after all, the extra
+        // step's results are never used.
+        {
+            const p4d_status fs = finish_setup(c);
+            if (fs != P4D_OK) return fs;
+        }
+        int ahead = -1;   // the step already enqueued, if any
+        for (int k = 0; k < m; k++) {
+            if (ahead != k) enqueue_step(k);
+            ahead = -1;
+            const double est = res[k];   // residual estimate after k steps
+            const double prev = k > 0 ? res[k - 1] : est;
+            const double rate = prev > 0.0 && est < prev ? est / prev : 1.0;
+            if (k + 1 < m && total + 1 < o.maxit && est * rate > 2.0 * o.rtol * bnorm) {
+                enqueue_step(k + 1);
+                ahead = k + 1;
+            }
             {
-                const p4d_status ps = pull(c, c->hdev, 129, st);
+                const p4d_status ps = await_pub(c, k & 1, step_seq[k & 1], st);
                 if (ps != P4D_OK) return ps;
             }
-            prof_harvest(c->prof);
+            // (with a step in flight its events are still pending)
+            if (ahead < 0) prof_harvest(c->prof);
+            const double *hh = (const double *)c->hpub + (k & 1) * kPubStride;
             for (int i = 0; i <= k; i++) hc[i] = hh[i] + (o.cgs2 ? hh[64 + i] : 0.0);
             const double hn = hh[128];
             hc[k + 1] = hn;
@@ -1336,6 +1419,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             kused = k + 1;
             beta[k + 1] = hn;
             inf.relres_est = std::fabs(gv[k + 1]) / bnorm;
+            res[k + 1] = std::fabs(gv[k + 1]);
             if (hn <= 1e-14 * colnorm) { breakdown = true; break; }
             if (std::fabs(gv[k + 1]) <= o.rtol * bnorm || total >= o.maxit) break;
         }
@@ -1345,8 +1429,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             for (int j = i + 1; j < kused; j++) v -= H[(size_t)i * m + j] * yv[j];
             yv[i] = v / H[(size_t)i * m + i];
         }
-        // the previous host-to-device copy from hout has completed: every
-        // iteration synchronizes the stream before this point
+        // the previous host-to-device copy from hout has completed: the host
+        // has since waited for a handoff enqueued after it
         for (int i = 0; i < kused; i++) hout[i] = yv[i];
         HIPCHK(c, hipMemcpyAsync(c->ydev, hout, 8 * kused, hipMemcpyHostToDevice, st));
         {
@@ -1847,6 +1931,7 @@ p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
     }
     c->pc = o;
     c->prec = o.pc_prec == P4D_FP32 ? 1 : 0;
+    c->lmax_pending = 0;
     hipStream_t st = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     p4d_status s = c->prec ? setup_t<float>(c, st) : setup_t<double>(c, st);
@@ -1880,7 +1965,9 @@ p4d_status p4d_apply_preconditioner(p4d_ctx *c, int transpose, const double *r, 
 {
     if (!c || !r || !z || r == z) return P4D_ERR_INVALID_ARG;
     if (!c->pc_ready) return fail(c, P4D_ERR_STATE, "p4d_setup first");
-    apply_pc<double>(c, transpose, r, 1.0, z, (hipStream_t)stream);
+    const p4d_status fs = finish_setup(c);
+    if (fs != P4D_OK) return fs;
+    apply_pc<double>(c, transpose, r, nullptr, z, (hipStream_t)stream);
     HIPCHK(c, hipGetLastError());
     return P4D_OK;
 }
@@ -2260,6 +2347,14 @@ p4d_status p4d_profile(p4d_ctx *c, int mask)
     return P4D_OK;
 }
 
+p4d_status p4d_profile_every(p4d_ctx *c, int every)
+{
+    if (!c || every < 1) return P4D_ERR_INVALID_ARG;
+    c->prof.every = every;
+    for (int k = 0; k < P4D_K_COUNT; k++) c->prof.seen[k] = 0;
+    return P4D_OK;
+}
+
 p4d_status p4d_profile_read(p4d_ctx *c, int cls, double *total_ms, int64_t *launches,
                             double *bytes)
 {
@@ -2325,6 +2420,8 @@ static p4d_status tune_tiles_t(p4d_ctx *c, hipStream_t st)
 
 static p4d_status tune_tiles(p4d_ctx *c, hipStream_t st)
 {
+    const p4d_status fs = finish_setup(c);
+    if (fs != P4D_OK) return fs;
     return c->prec ? tune_tiles_t<float>(c, st) : tune_tiles_t<double>(c, st);
 }
 
@@ -2492,12 +2589,16 @@ static p4d_status batch_record(p4d_batch *B)
     B->nrmax = 8;
     const int cz = B->tile_cz > 0 ? B->tile_cz : batch_default_cz<T>(B);
     for (int i = 0; i < n; i++) {
+        const p4d_status fs = finish_setup(B->cell[i]);
+        if (fs != P4D_OK) return bfail(B, fs, "cell " + std::to_string(i) + ": " + B->cell[i]->err);
+    }
+    for (int i = 0; i < n; i++) {
         p4d_ctx *c = B->cell[i];
         const int keep = c->tile_cz;
         c->tile_cz = cz;
         c->rec = &per[i];
         c->rec_cell = i;
-        apply_pc_t<T, double>(c, 0, nullptr, 0.0, (double *)nullptr, nullptr);
+        apply_pc_t<T, double>(c, 0, nullptr, nullptr, (double *)nullptr, nullptr);
         c->rec = nullptr;
         c->tile_cz = keep;
         if ((int)per[i].size() > kMaxStagesPerCell)
@@ -2854,7 +2955,7 @@ static p4d_status batch_fgmres(p4d_batch *B, int transpose, const double *const 
                         if ((act >> i) & 1ULL) {
                             p4d_ctx *c = B->cell[i];
                             apply_pc_t<T, TZ>(c, transpose, bc[i].V + (long long)k * c->g.N,
-                                              1.0 / S[i].beta[k],
+                                              bc[i].invbeta + k,
                                               (TZ *)bc[i].Z + (long long)k * c->g.N, st);
                         }
                 }

@@ -22,17 +22,17 @@ struct BgsArgs {
 // (precision T, level-0 multigrid layout) with the first Chebyshev iterate of
 // its boxes.
 template <typename T>
-void launch_bgs_rhs(const Geom &g, const BgsArgs &B, const double *r, double rscale, int transpose,
+void launch_bgs_rhs(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, int transpose,
                     hipStream_t st);
 // z_s,j = A_ss,j^-1 (r_s,j - delta_j e_N), delta_j the coupling to the
 // electrode-level fields solved before; keeps z_s,N in FP64 in zsN.
 template <typename T, typename TZ>
-void launch_bgs_cs(const Geom &g, const BgsArgs &B, const double *r, double rscale, TZ *z,
+void launch_bgs_cs(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, TZ *z,
                    int transpose, hipStream_t st);
 // phi_s (identity rows on the grounded layer), phi_e and c_e of z from the
 // final level-0 iterates.
 template <typename TZ>
-void launch_bgs_out(const Geom &g, const BgsArgs &B, const double *r, double rscale, TZ *z,
+void launch_bgs_out(const Geom &g, const BgsArgs &B, const double *r, const double *rscale, TZ *z,
                     hipStream_t st);
 
 }  // namespace p4d

@@ -174,10 +174,10 @@ void launch_grad_final(const double *partial, int nblk, double *dDs, hipStream_t
 // radial.hip (RadArgs in p4d_kernels.hpp)
 struct RadArgs;
 template <typename T>
-void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rscale, int transpose,
+void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, const double *rscale, int transpose,
                     int schur, hipStream_t st);
 template <typename T, typename TZ>
-void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
+void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, const double *rscale, TZ *z,
                      int transpose, int schur, hipStream_t st);
 // size class of the per-thread radial register arrays: the largest N_r of
 // the two electrodes rounded up to 8, 12, 16, 20, 24, 32 or 64

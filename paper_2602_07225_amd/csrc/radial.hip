@@ -10,9 +10,9 @@
 namespace p4d {
 
 template <typename T, int NRMAX, bool TRANS, bool SCHUR>
-__global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R, const double *r, double rscale)
+__global__ __launch_bounds__(kBlock) void k_rad_fwd(Geom g, RadArgs R, const double *r, const double *rscale)
 {
-    rad_fwd_block<T, NRMAX, TRANS, SCHUR>(g, R, r, rscale, blockIdx.x);
+    rad_fwd_block<T, NRMAX, TRANS, SCHUR>(g, R, r, rscale ? *rscale : 1.0, blockIdx.x);
 }
 
 int rad_nrmax(const Geom &g)
@@ -24,7 +24,7 @@ int rad_nrmax(const Geom &g)
 }
 
 template <typename T>
-void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rscale, int transpose,
+void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, const double *rscale, int transpose,
                     int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
@@ -43,21 +43,21 @@ void launch_rad_fwd(const Geom &g, const RadArgs &R, const double *r, double rsc
 #undef P4D_RF2
 #undef P4D_RF
 }
-template void launch_rad_fwd<double>(const Geom &, const RadArgs &, const double *, double, int, int,
-                                     hipStream_t);
-template void launch_rad_fwd<float>(const Geom &, const RadArgs &, const double *, double, int, int,
+template void launch_rad_fwd<double>(const Geom &, const RadArgs &, const double *, const double *, int,
+                                     int, hipStream_t);
+template void launch_rad_fwd<float>(const Geom &, const RadArgs &, const double *, const double *, int, int,
                                     hipStream_t);
 
 template <typename T, typename TZ, int NRMAX, bool TRANS, bool SCHUR>
-__global__ __launch_bounds__(kBlock) void k_rad_back(Geom g, RadArgs R, const double *r, double rscale,
-                                                    TZ *z)
+__global__ __launch_bounds__(kBlock) void k_rad_back(Geom g, RadArgs R, const double *r,
+                                                    const double *rscale, TZ *z)
 {
-    rad_back_block<T, TZ, NRMAX, TRANS, SCHUR>(g, R, r, rscale, z, blockIdx.x);
+    rad_back_block<T, TZ, NRMAX, TRANS, SCHUR>(g, R, r, rscale ? *rscale : 1.0, z, blockIdx.x);
 }
 
 
 template <typename T, typename TZ>
-void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rscale, TZ *z,
+void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, const double *rscale, TZ *z,
                      int transpose, int schur, hipStream_t st)
 {
     const int nb = (int)((g.nnode + kBlock - 1) / kBlock);
@@ -77,13 +77,13 @@ void launch_rad_back(const Geom &g, const RadArgs &R, const double *r, double rs
 #undef P4D_RB2
 #undef P4D_RB
 }
-template void launch_rad_back<double, double>(const Geom &, const RadArgs &, const double *, double,
+template void launch_rad_back<double, double>(const Geom &, const RadArgs &, const double *, const double *,
                                                 double *, int, int, hipStream_t);
-template void launch_rad_back<float, double>(const Geom &, const RadArgs &, const double *, double,
+template void launch_rad_back<float, double>(const Geom &, const RadArgs &, const double *, const double *,
                                                 double *, int, int, hipStream_t);
-template void launch_rad_back<double, float>(const Geom &, const RadArgs &, const double *, double,
+template void launch_rad_back<double, float>(const Geom &, const RadArgs &, const double *, const double *,
                                                 float *, int, int, hipStream_t);
-template void launch_rad_back<float, float>(const Geom &, const RadArgs &, const double *, double,
+template void launch_rad_back<float, float>(const Geom &, const RadArgs &, const double *, const double *,
                                                 float *, int, int, hipStream_t);
 
 }  // namespace p4d
