@@ -134,6 +134,23 @@ def event_pair_us(n=200):
     return 1e3 * sum(e0.elapsed_time(e1) for e0, e1 in evs) / n
 
 
+def byte_split(p64, p32, steps):
+    """Per timed kernel class (coarse multigrid levels are not a class): the
+    algorithmic bytes and time per step with the FP64 and the FP32
+    preconditioner, and the class's share of the FP64 step's timed bytes
+    (the part FP32 storage can shrink is the preconditioner's)."""
+    def per_step(p, k, key):
+        return p[k][key] * (p[k]["launches"] if key == "bytes_per_launch" else 1) / steps if k in p else 0.0
+    tot64 = sum(per_step(p64, k, "bytes_per_launch") for k in p64)
+    out = {}
+    for k in sorted(set(p64) | set(p32)):
+        b64, b32 = per_step(p64, k, "bytes_per_launch"), per_step(p32, k, "bytes_per_launch")
+        out[k] = {"fp64_MB": b64 / 1e6, "fp32_MB": b32 / 1e6,
+                  "fp64_ms": per_step(p64, k, "ms_total"), "fp32_ms": per_step(p32, k, "ms_total"),
+                  "share_of_fp64_bytes": b64 / tot64 if tot64 else None}
+    return out
+
+
 def timed_steps(s, b, opts, steps, warmup, profile_mask=0, every=1):
     """Time `steps` setup + solve steps; with profile_mask, HIP event pairs
     around one launch in `every` of those kernel classes (a pair costs the
@@ -468,11 +485,15 @@ def main():
         x32, i32, it32, t32, _ = timed_steps(s, b, fp32, args.steps, 1)
         keep["C2_fp32"] = x32.cpu().numpy()
         err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+        # per kernel class: the bytes each precision moves per step (a pass
+        # with events around every launch, as for the FP64 table)
+        _, _, _, _, prof32 = timed_steps(s, b, fp32, args.steps, 1, mask)
         extras["fp32_precond_C2"] = {"ms_per_step": 1e3 * t32 / args.steps,
                                      "iters_per_solve": it32 / args.steps,
                                      "DOF_iter_per_s": N * it32 / t32,
                                      "rel_err_vs_fp64_gpu": err,
-                                     "speedup_vs_fp64": t / t32}
+                                     "speedup_vs_fp64": t / t32,
+                                     "byte_split": byte_split(prof, prof32, args.steps)}
         log(f"[bench] FP32-PC C2: {1e3 * t32 / args.steps:.2f} ms/step, {it32 / args.steps:.1f} it")
         # block-Jacobi preconditioner (the paper's eq. PJ) on the same input
         # (Chebyshev degree 2: BJ and BGS take fewer iterations with it)

@@ -111,45 +111,51 @@ __global__ __launch_bounds__(kBlock) void k_bgs_cs(Geom g, BgsArgs B, const doub
     const long long klo = el == 0 ? 0 : g.na + g.ns;
     const long long je = base + n - klo * g.nx * g.ny;
     const bool dir = (k == 0);
-    const RadialTab &Tb = R.tabs[el];
-    const int N = Tb.N;
-    const long long nn = el == 0 ? g.nea : g.nec;
-    const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
-    const double *rs = r + offs + (je - base);
-    TZ *zs = z + offs + (je - base);
-    const double sj = R.ss[je], m = R.mm[je], gj = R.gg[je];
-    double pz = 0.0;   // column coefficients times the solved values
-    if ((done & (1 << BF_PHIS)) && !dir) pz += (TRANS ? m : gj) * (el == 0 ? R.x0[0] : R.x0[1])[je];
-    if (done & (1 << BF_PHIE)) pz += (TRANS ? -m : -gj) * R.x0[2][g.off_pe + n];
-    if (done & (1 << BF_CE)) pz += (TRANS ? -g.tc * m : R.ee[je]) * R.x0[3][g.off_ce + n];
-    const double delta = (TRANS ? sj : Tb.Gamma) * pz;
-    const double dw = delta / (1.0 + Tb.Gamma * sj * Tb.tau0);
-    double rv[NRMAX];
+    auto solve = [&](const auto &Tb) {
+        const int N = Tb.N;
+        const long long nn = el == 0 ? g.nea : g.nec;
+        const long long offs = el == 0 ? g.off_cs[0] : g.off_cs[1];
+        const double *rs = r + offs + (je - base);
+        TZ *zs = z + offs + (je - base);
+        const double sj = R.ss[je], m = R.mm[je], gj = R.gg[je];
+        double pz = 0.0;   // column coefficients times the solved values
+        if ((done & (1 << BF_PHIS)) && !dir) pz += (TRANS ? m : gj) * (el == 0 ? R.x0[0] : R.x0[1])[je];
+        if (done & (1 << BF_PHIE)) pz += (TRANS ? -m : -gj) * R.x0[2][g.off_pe + n];
+        if (done & (1 << BF_CE)) pz += (TRANS ? -g.tc * m : R.ee[je]) * R.x0[3][g.off_ce + n];
+        const double delta = (TRANS ? sj : Tb.Gamma) * pz;
+        const double dw = delta / (1.0 + Tb.Gamma * sj * Tb.tau0);
+        double rv[NRMAX];
 #pragma unroll
-    for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
-    T y[NRMAX];
-    y[0] = (T)(rv[0] * rscale);
-    T ylast = y[0];
+        for (int q = 0; q < NRMAX; q++) rv[q] = rs[(long long)(q < N ? q : N - 1) * nn];
+        T y[NRMAX];
+        y[0] = (T)(rv[0] * rscale);
+        T ylast = y[0];
 #pragma unroll
-    for (int q = 1; q < NRMAX; q++) {
-        if (q < N) {
-            const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
-            y[q] = (T)(rv[q] * rscale) - lq * y[q - 1];
-            ylast = y[q];
+        for (int q = 1; q < NRMAX; q++) {
+            if (q < N) {
+                const T lq = (T)(TRANS ? Tb.lT[q] : Tb.l[q]);
+                y[q] = (T)(rv[q] * rscale) - lq * y[q - 1];
+                ylast = y[q];
+            }
         }
-    }
-    T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
-    const double zN = (double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]);
-    zs[(long long)(N - 1) * nn] = (TZ)zN;
-    B.zsN[je] = zN;
+        T zn = ylast / (T)(Tb.piv[N - 1] + Tb.Gamma * sj);
+        const double zN = (double)zn - dw * (TRANS ? Tb.tNT[N - 1] : Tb.tN[N - 1]);
+        zs[(long long)(N - 1) * nn] = (TZ)zN;
+        B.zsN[je] = zN;
 #pragma unroll
-    for (int q = NRMAX - 2; q >= 0; q--) {
-        if (q < N - 1) {
-            const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
-            zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
-            zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
+        for (int q = NRMAX - 2; q >= 0; q--) {
+            if (q < N - 1) {
+                const T u = (T)(TRANS ? Tb.tsub[q + 1] : Tb.tsup[q]);
+                zn = (y[q] - u * zn) * (T)Tb.ipiv[q];
+                zs[(long long)q * nn] = (TZ)((double)zn - dw * (TRANS ? Tb.tNT[q] : Tb.tN[q]));
+            }
         }
-    }
+    };
+    // the electrode's table through a wave-uniform pointer (scalar loads) when
+    // the whole wave lies in one electrode, per lane otherwise
+    const int elw = __builtin_amdgcn_readfirstlane(el);
+    if (__builtin_amdgcn_ballot_w64(el != elw) == 0) solve(*(const ConstTab *)(R.tabs + elw));
+    else solve(R.tabs[el]);
 }
 
 template <typename T, typename TZ>

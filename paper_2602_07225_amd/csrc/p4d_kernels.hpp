@@ -1085,7 +1085,9 @@ __device__ inline void operator_tile(const Geom &g, const OpArgs &O, double *qou
                 const int klo = el == 0 ? 0 : g.na + g.ns;
                 const long long je = base + i + (long long)g.nx * (j + (long long)g.ny * (k - klo));
                 const bool dir = (k == 0);
-                const RadialTab &T = O.tabs[el];
+                // the tile's layer lies in one electrode: its table through a
+                // wave-uniform pointer (scalar loads)
+                const ConstTab &T = *(const ConstTab *)(O.tabs + __builtin_amdgcn_readfirstlane(el));
                 double xsN = 0.0;
                 if (!RED) {
                     const long long nn = el == 0 ? g.nea : g.nec;
