@@ -97,7 +97,8 @@ typedef enum { P4D_KRYLOV_FULL = 0, P4D_KRYLOV_SCHUR = 1 } p4d_krylov;
  * after; cheb_degree passes each), coarsening in x and y only: robust when
  * the elements are much thinner along z than across, as in the flattened
  * jelly roll of paper Sec. 5 (Case III), where point smoothers stall.  FP64
- * preconditioner, pc SCHUR or BJ; either Krylov space.                     */
+ * preconditioner, pc SCHUR or BJ; either Krylov space; at most 2016 node
+ * layers (p4d_setup returns P4D_ERR_INVALID_ARG above).                   */
 typedef enum { P4D_SMOOTH_CHEB = 0, P4D_SMOOTH_ZLINE = 1 } p4d_smoother;
 
 /* Problem geometry and scalars, all nondimensional.  The particle radius is

@@ -514,58 +514,98 @@ void launch_rap(const Geom &g, const RapJob *jobs, int njobs, int zc, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// z-line block Gauss-Seidel (boxes much thinner along z than across).  A
-// workgroup owns lpw lines of the colour and stages them in LDS: first all
-// its threads compute, row by row and in parallel, the right-hand side with
+// z-line block Gauss-Seidel (boxes much thinner along z than across).  The
+// lines of a colour (every other line in x and y) are cut into tiles of LT
+// lines that are consecutive along x; Sz holds a tile's rows together,
+// layer by layer, and in a layer the 27 coefficients of its lines one after
+// the other, so that a workgroup streams one contiguous block of the stencil
+// (runs of a few lines per coefficient and layer read back poorly from HBM).
+// The workgroup marches through z in chunks of KC layers: it stages the x
+// planes around the tile (2 LT + 1 by 3 nodes, layers k0 - 1 .. k0 + KC) in
+// LDS; its threads form, one (line, layer) each, the right-hand side with
 // the couplings to other lines moved over (lines of one colour do not
 // couple) and copy the line's tridiagonal block (offsets (0,0,-1), centre,
-// (0,0,1)); then one thread per line eliminates down the line and
-// substitutes back up in LDS; then all threads write x.  (One thread walking
-// its line through global memory leaves every step waiting on a load, which
-// dominates on the coarse levels where there are few lines.)  LDS [k][line]
-// keeps the threads of the elimination on consecutive banks.
+// (0,0,1)).  Then one thread per line eliminates down the line and
+// substitutes back up in LDS, and all threads write x.  LDS [k][line] keeps
+// the threads of the elimination on consecutive banks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour, int lpw)
+// Sz index of coefficient o of the row of line (a, bl) of a colour in layer
+// k; base = 27 x the rows of the lower colours, ncx the colour's lines
+// along x, LT the tile width
+__device__ inline long long zline_index(long long base, int ncx, int nz, int LT, int a, int bl, int k, int o)
+{
+    const int a0 = a - a % LT;
+    const int w = ncx - a0 < LT ? ncx - a0 : LT;
+    return base + ((long long)bl * ncx + a0) * 27 * nz + (long long)(k * 27 + o) * w + (a - a0);
+}
+
+__device__ inline long long zline_rows_below(int nx, int ny, int nz, int colour)
+{
+    long long offc = 0;
+    for (int c = 0; c < colour; c++)
+        offc += (long long)((nx - (c & 1) + 1) / 2) * ((ny - (c >> 1) + 1) / 2) * nz;
+    return offc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
 {
     extern __shared__ double lds[];
     const LineArgs &A = lb.a[find_box(lb, blockIdx.x)];
+    const int LT = A.lt, KC = A.kc;   // KC * LT <= kBlock
     const int cx = colour & 1, cy = colour >> 1;
-    const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2, nl = ncx * ncy;
-    const int g0 = (blockIdx.x - A.blk0) * lpw;
-    const int nlw = nl - g0 < lpw ? nl - g0 : lpw;   // >= 1 by the grid
+    const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2;
+    const int tX = (ncx + LT - 1) / LT;
+    const int tile = blockIdx.x - A.blk0;
+    const int a0 = (tile % tX) * LT, bl = tile / tX;
+    const int w = ncx - a0 < LT ? ncx - a0 : LT;   // lines in this tile
+    const int FX = 2 * LT + 1, plane = 3 * FX;
+    const int fi0 = cx + 2 * a0 - 1, fj0 = cy + 2 * bl - 1;   // footprint origin (node indices)
     const int nz = A.nz;
-    const long long layer = (long long)A.nx * A.ny, N = A.n;
-    // rows of this colour in Sz start after those of the lower colours
-    long long offc = 0;
-    for (int c = 0; c < colour; c++)
-        offc += (long long)((A.nx - (c & 1) + 1) / 2) * ((A.ny - (c >> 1) + 1) / 2) * nz;
-    double *Llo = lds, *Ldg = lds + lpw * nz, *Lup = Ldg + lpw * nz, *Lrh = Lup + lpw * nz;
-    for (int p = threadIdx.x; p < nlw * nz; p += kBlock) {
-        const int ll = p % nlw, k = p / nlw, t = g0 + ll;
-        const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
-        const long long n = i + (long long)A.nx * j + layer * k;
-        const long long row = offc + (long long)k * nl + t;   // consecutive lines: consecutive rows
-        double rhs = A.b[n];
-#pragma unroll
-        for (int o = 0; o < 27; o++) {
-            const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-            if (dx == 0 && dy == 0) continue;
-            const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny &&
-                            k + dz >= 0 && k + dz < nz;
-            if (ok) rhs -= A.Sz[o * N + row] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
+    const long long layer = (long long)A.nx * A.ny;
+    const double *Z = A.Sz + 27 * zline_rows_below(A.nx, A.ny, nz, colour) + ((long long)bl * ncx + a0) * 27 * nz;
+    double *Llo = lds, *Ldg = lds + LT * nz, *Lup = Ldg + LT * nz, *Lrh = Lup + LT * nz;
+    double *Lx = Lrh + LT * nz;   // [KC + 2][3][FX]
+    const int j = cy + 2 * bl;
+    for (int k0 = 0; k0 < nz; k0 += KC) {
+        for (int q = threadIdx.x; q < (KC + 2) * plane; q += kBlock) {
+            const int pl = q / plane, r = q - pl * plane;
+            const int ii = fi0 + r % FX, jj = fj0 + r / FX, kk = k0 - 1 + pl;
+            const bool ok = ii >= 0 && ii < A.nx && jj >= 0 && jj < A.ny && kk >= 0 && kk < nz;
+            Lx[q] = ok ? A.x[ii + (long long)A.nx * jj + layer * kk] : 0.0;
         }
-        const int q = k * lpw + ll;
-        Llo[q] = k > 0 ? A.Sz[4 * N + row] : 0.0;            // offset (0,0,-1)
-        Lup[q] = k < nz - 1 ? A.Sz[22 * N + row] : 0.0;      // offset (0,0,+1)
-        Ldg[q] = A.Sz[13 * N + row];
-        Lrh[q] = rhs;
+        __syncthreads();
+        {
+            const int l = threadIdx.x % LT, kk = threadIdx.x / LT, k = k0 + kk;
+            if (kk < KC && k < nz && l < w) {
+                const int i = cx + 2 * (a0 + l);
+                const long long n = i + (long long)A.nx * j + layer * k;
+                const double *Zr = Z + (long long)k * 27 * w + l;   // coefficient o at Zr[o * w]
+                const double *P = Lx + (kk + 1) * plane + (i - fi0) + FX;
+                double rhs = A.b[n];
+                // no bounds tests: Sz holds +0 for a neighbour off the box and
+                // the staged x is +0 there, so that such a term subtracts an
+                // exact -0 and leaves rhs as it is, bit for bit; unguarded,
+                // the loads are all in flight at once
+#pragma unroll
+                for (int o = 0; o < 27; o++) {
+                    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+                    if (dx == 0 && dy == 0) continue;
+                    rhs -= Zr[o * w] * P[dx + FX * dy + plane * dz];
+                }
+                const int q = k * LT + l;
+                Llo[q] = Zr[4 * w];    // offset (0,0,-1), +0 in the bottom layer
+                Lup[q] = Zr[22 * w];   // offset (0,0,+1), +0 in the top layer
+                Ldg[q] = Zr[13 * w];
+                Lrh[q] = rhs;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < nlw) {
+    if (threadIdx.x < w) {
         const int ll = threadIdx.x;
         double cprev = 0.0, dprev = 0.0;
         for (int k = 0; k < nz; k++) {
-            const int q = k * lpw + ll;
+            const int q = k * LT + ll;
             const double lo = Llo[q];
             const double den = Ldg[q] - lo * cprev;
             cprev = Lup[q] / den;
@@ -575,16 +615,16 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour, int 
         }
         double nxt = 0.0;
         for (int k = nz - 1; k >= 0; k--) {
-            const int q = k * lpw + ll;
+            const int q = k * LT + ll;
             nxt = Lrh[q] - (k < nz - 1 ? Lup[q] * nxt : 0.0);
             Lrh[q] = nxt;
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < nlw * nz; p += kBlock) {
-        const int ll = p % nlw, k = p / nlw, t = g0 + ll;
-        const int i = cx + 2 * (t % ncx), j = cy + 2 * (t / ncx);
-        A.x[i + (long long)A.nx * j + layer * k] = Lrh[k * lpw + ll];
+    for (int p = threadIdx.x; p < LT * nz; p += kBlock) {
+        const int l = p % LT, k = p / LT;
+        if (l >= w) continue;
+        A.x[cx + 2 * (a0 + l) + (long long)A.nx * j + layer * k] = Lrh[k * LT + l];
     }
 }
 
@@ -599,14 +639,17 @@ __global__ __launch_bounds__(kBlock) void k_resid_full(LineBatch lb)
 #pragma unroll
     for (int o = 0; o < 27; o++) {
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        const bool ok = i + dx >= 0 && i + dx < A.nx && j + dy >= 0 && j + dy < A.ny && k + dz >= 0 &&
-                        k + dz < A.nz;
-        if (ok) acc -= A.S[o * N + n] * A.x[n + dx + (long long)A.nx * dy + layer * dz];
+        const bool ok = ((unsigned)(i + dx) < (unsigned)A.nx) & ((unsigned)(j + dy) < (unsigned)A.ny) &
+                        ((unsigned)(k + dz) < (unsigned)A.nz);
+        // loads at valid addresses (the node itself off the box) and a select
+        const double sv = A.S[o * N + n];
+        const double xv = A.x[ok ? n + dx + (long long)A.nx * dy + layer * dz : (long long)n];
+        acc = ok ? acc - sv * xv : acc;
     }
     A.r[n] = acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_zline_order(int nx, int ny, int nz, const double *__restrict__ S,
+__global__ __launch_bounds__(kBlock) void k_zline_order(int nx, int ny, int nz, int LT, const double *__restrict__ S,
                                                         double *__restrict__ Sz)
 {
     const long long N = (long long)nx * ny * nz;
@@ -616,39 +659,56 @@ __global__ __launch_bounds__(kBlock) void k_zline_order(int nx, int ny, int nz, 
     const long long u = n / nx;
     const int j = (int)(u % ny), k = (int)(u / ny);
     const int colour = (i & 1) | ((j & 1) << 1);
-    long long offc = 0;
-    for (int c = 0; c < colour; c++)
-        offc += (long long)((nx - (c & 1) + 1) / 2) * ((ny - (c >> 1) + 1) / 2) * nz;
-    const int ncx = (nx - (i & 1) + 1) / 2, ncy = (ny - (j & 1) + 1) / 2;
-    const long long row = offc + (long long)k * ncx * ncy + (i >> 1) + (long long)ncx * (j >> 1);
+    const long long base = 27 * zline_rows_below(nx, ny, nz, colour);
+    const int ncx = (nx - (i & 1) + 1) / 2;
 #pragma unroll
-    for (int o = 0; o < 27; o++) Sz[o * N + row] = S[o * N + n];
+    for (int o = 0; o < 27; o++) {
+        const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+        const bool ok = i + dx >= 0 && i + dx < nx && j + dy >= 0 && j + dy < ny && k + dz >= 0 && k + dz < nz;
+        Sz[zline_index(base, ncx, nz, LT, i >> 1, j >> 1, k, o)] = ok ? S[o * N + n] : 0.0;   // +0 off the box
+    }
+}
+
+// Tile width LT (lines along x, a power of two, at most 32) and chunk depth
+// KC (layers, KC * LT <= kBlock) for a z extent: the widest tile whose
+// line rows (four doubles each) and staged x planes fit the 64 KB LDS
+// budget, then the deepest chunk that still fits
+static size_t zline_lds(int LT, int KC, int nz)
+{
+    return (size_t)32 * LT * nz + (size_t)8 * (KC + 2) * (2 * LT + 1) * 3;
+}
+static bool zline_tile(int nz, int &LT, int &KC)
+{
+    for (LT = 32; LT >= 1; LT /= 2)
+        for (KC = kBlock / LT; KC >= 1; KC /= 2)
+            if (zline_lds(LT, KC, nz) <= (size_t)kZlineLds) return true;
+    return false;
 }
 
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st)
 {
+    int LT, KC;
+    if (!zline_tile(nz, LT, KC)) return;   // z extents beyond the limit are refused at setup
     const long long N = (long long)nx * ny * nz;
     hipLaunchKernelGGL(k_zline_order, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
-                       ny, nz, S, Sz);
+                       ny, nz, LT, S, Sz);
 }
 
 void launch_zline(LineBatch lb, int colour, hipStream_t st)
 {
-    // lines per workgroup: four doubles per row of each line in 64 KB of LDS
-    int nzmax = 1;
-    for (int q = 0; q < lb.nbox; q++) nzmax = lb.a[q].nz > nzmax ? lb.a[q].nz : nzmax;
-    int lpw = kZlineLds / (32 * nzmax);
-    lpw = lpw > 64 ? 64 : (lpw < 1 ? 1 : lpw);
     int blk = 0;
+    size_t lds = 0;
     for (int q = 0; q < lb.nbox; q++) {
         LineArgs &A = lb.a[q];
+        if (!zline_tile(A.nz, A.lt, A.kc)) return;
+        const size_t need = zline_lds(A.lt, A.kc, A.nz);
+        lds = need > lds ? need : lds;
         const int cx = colour & 1, cy = colour >> 1;
-        const int nl = ((A.nx - cx + 1) / 2) * ((A.ny - cy + 1) / 2);
+        const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2;
         A.blk0 = blk;
-        blk += (nl + lpw - 1) / lpw;
+        blk += ((ncx + A.lt - 1) / A.lt) * ncy;
     }
-    if (blk)
-        hipLaunchKernelGGL(k_zline, dim3(blk), dim3(kBlock), (size_t)32 * lpw * nzmax, st, lb, colour, lpw);
+    if (blk) hipLaunchKernelGGL(k_zline, dim3(blk), dim3(kBlock), lds, st, lb, colour);
 }
 
 void launch_resid_full(LineBatch lb, hipStream_t st)

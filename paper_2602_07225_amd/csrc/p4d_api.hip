@@ -1912,7 +1912,7 @@ p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
     if (o.pc == P4D_PC_BGS && c->g.aniso)
         return fail(c, P4D_ERR_INVALID_ARG, "block Gauss-Seidel needs cube elements");
     if (o.smoother == P4D_SMOOTH_ZLINE && c->g.nz > kZlineMaxNz)
-        return fail(c, P4D_ERR_INVALID_ARG, "z-line smoothing takes at most 2048 node layers");
+        return fail(c, P4D_ERR_INVALID_ARG, "z-line smoothing takes at most 2016 node layers");
     // keep the Krylov sizing of the layout (it is set by the workspace size
     // the caller asked for); the preconditioner part must match o
     p4d_solve_opts lay = c->ws_opts;

@@ -270,13 +270,15 @@ void launch_rap(const Geom &g, const RapJob *jobs, int njobs, int zc, hipStream_
 // z-line smoothing of up to four boxes of one level (FP64, full stencils
 // [27][n]): block Gauss-Seidel over the lines of one colour (x parity
 // colour & 1, y parity colour >> 1), in place in x.  A box's z extent is at
-// most kZlineMaxNz (a line's rows must fit the 64 KB of LDS).
+// most kZlineMaxNz (a line's rows and a chunk of staged x planes must fit
+// the 64 KB of LDS).
 constexpr int kZlineLds = 65536;
-constexpr int kZlineMaxNz = kZlineLds / 32;
+constexpr int kZlineMaxNz = 2016;
 struct LineArgs {
     int nx, ny, nz, n, blk0;
+    int lt, kc;                      // sweep tile width and chunk depth (set by launch_zline)
     const double *S;                 // [27][n], natural node order (residual)
-    const double *Sz;                // the same rows by colour, layer, line (sweeps)
+    const double *Sz;                // the same rows in the sweeps' order (launch_zline_order)
     const double *b;
     double *x;
     double *r;
@@ -289,7 +291,9 @@ void launch_zline(LineBatch lb, int colour, hipStream_t st);
 // r = b - S x on the same boxes
 void launch_resid_full(LineBatch lb, hipStream_t st);
 // Sz = the rows of S ([27][n] on an nx x ny x nz box) reordered as the
-// z-line sweeps read them: colour by colour, then layer k, then line
+// z-line sweeps read them: colour by colour, then by tiles of up to 32 lines
+// consecutive along x, then layer k, coefficient and line; a coefficient
+// whose neighbour lies off the box is stored as +0
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);
 void launch_diag(int n, const double *S, double *invd, unsigned long long *lmax, int nblk,
                  hipStream_t st);

@@ -16,16 +16,18 @@ __host__ __device__ inline int coarse_n(int n) { return n <= 2 ? n : n / 2 + 1; 
 // coarse points (and weights) that fine point i interpolates from
 __device__ inline int coarse_of(int n, int i, int I[2], double w[2])
 {
-    if (n <= 2) { I[0] = i; w[0] = 1.0; return 1; }
-    if (!(i & 1)) { I[0] = i >> 1; w[0] = 1.0; return 1; }
-    if (i == n - 1) { I[0] = n / 2; w[0] = 1.0; return 1; }
+    // (an unused second slot repeats the first point with weight 0)
+    if (n <= 2) { I[0] = I[1] = i; w[0] = 1.0; w[1] = 0.0; return 1; }
+    if (!(i & 1)) { I[0] = I[1] = i >> 1; w[0] = 1.0; w[1] = 0.0; return 1; }
+    if (i == n - 1) { I[0] = I[1] = n / 2; w[0] = 1.0; w[1] = 0.0; return 1; }
     I[0] = (i - 1) >> 1; w[0] = 0.5;
     I[1] = (i + 1) >> 1; w[1] = 0.5;
     return 2;
 }
 // fine points (and weights) that interpolate from coarse point I, in the
 // order: the coincident point, its odd left neighbour, its odd right
-// neighbour (selects instead of a running index keep the arrays in registers)
+// neighbour; unused slots repeat the coincident point with weight 0
+// (selects instead of a running index keep the arrays in registers)
 __device__ inline int fine_of(int n, int I, int f[3], double w[3])
 {
     if (n <= 2) {
@@ -298,22 +300,23 @@ __device__ inline void restrict_block(const TransferArgs<T> &A, int blk)
     const int ni = fine_of(A.fx, I, fi, wi);
     const int nj = fine_of(A.fy, J, fj, wj);
     const int nk = fine_of(A.cz == A.fz ? 1 : A.fz, K, fk, wk);   // (z kept: identity)
+    (void)ni; (void)nj; (void)nk;
     // issued with the residual loads (after the store below it would wait
     // for them first)
     const double idc = A.xc1 ? (double)A.invdc[n] : 0.0;
-    // fixed trip counts, so that the index arrays stay in registers
+    // all 27 slots, without tests: an unused slot reads a point that a used
+    // slot reads too and adds an exact zero to a sum that starts at +0 (and
+    // so never holds -0), leaving it as it is bit for bit; unguarded, the
+    // loads are all in flight at once
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        if (c >= nk) break;
 #pragma unroll
         for (int bq = 0; bq < 3; bq++) {
-            if (bq >= nj) break;
             const long long row = (long long)A.fx * (fj[bq] + (long long)A.fy * fk[c]);
             double part = 0.0;
 #pragma unroll
-            for (int a = 0; a < 3; a++)
-                if (a < ni) part += wi[a] * (double)A.rf[row + fi[a]];
+            for (int a = 0; a < 3; a++) part += wi[a] * (double)A.rf[row + fi[a]];
             acc += wj[bq] * wk[c] * part;
         }
     }
@@ -336,18 +339,18 @@ __device__ inline void prolong_block(const TransferArgs<T> &A, int blk)
     const int ni = coarse_of(A.fx, i, Ci, wi);
     const int nj = coarse_of(A.fy, j, Cj, wj);
     const int nk = coarse_of(A.cz == A.fz ? 1 : A.fz, k, Ck, wk);
+    (void)ni; (void)nj; (void)nk;
+    // all 8 slots, without tests (an unused slot adds an exact zero; see
+    // restrict_block)
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; c++) {
-        if (c >= nk) break;
 #pragma unroll
         for (int bq = 0; bq < 2; bq++) {
-            if (bq >= nj) break;
             const long long row = (long long)A.cx * (Cj[bq] + (long long)A.cy * Ck[c]);
             double part = 0.0;
 #pragma unroll
-            for (int a = 0; a < 2; a++)
-                if (a < ni) part += wi[a] * A.xc[row + Ci[a]];
+            for (int a = 0; a < 2; a++) part += wi[a] * A.xc[row + Ci[a]];
             acc += wj[bq] * wk[c] * part;
         }
     }
