@@ -1284,15 +1284,20 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         return P4D_OK;
     };
 
-    // ||b|| over all unknowns
+    // ||b|| over all unknowns; x = 0 and (full space) V_0 = b are enqueued
+    // behind its handoff, so that the device runs them while the host waits
     launch_dot_partial(g.N, b, b, red, sbf, st);
     launch_norm_final(red, sbf, c->hdev, nullptr, st);
     {
-        const p4d_status ps = pull(c, c->hdev, 1, st);
+        const unsigned long long bseq = publish(c, c->hdev, 1, 0, st);
+        HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
+        if (!schur) HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
+        const p4d_status ps = await_pub(c, 0, bseq, st);
         if (ps != P4D_OK) return ps;
     }
     const double bnorm = hh[0];
-    HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
+    // set when the last handoff follows every write to x (no final one needed)
+    bool synced = false;
     if (!std::isfinite(bnorm)) {
         HIPCHK(c, hipStreamSynchronize(st));
         return fail(c, P4D_ERR_NONFINITE, "non-finite right-hand side");
@@ -1311,8 +1316,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
     for (;;) {
         // r = bk - op(x) into V_0 (x = 0 in the first cycle: r = bk)
         if (first) {
-            HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
             if (schur) {
+                HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
                 launch_dot_partial(N, bk, bk, red, sb, st);
                 launch_norm_final(red, sb, c->hdev + 200, c->invbeta, st);
                 const p4d_status ps = pull(c, c->hdev + 200, 1, st);
@@ -1328,11 +1333,13 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             const p4d_status rs = residual();
             if (rs != P4D_OK) return rs;
             beta[0] = hh[0];
+            synced = true;
         }
         inf.relres_true = beta[0] / bnorm;
         if (!std::isfinite(beta[0])) { status = P4D_ERR_NONFINITE; break; }
         if (beta[0] <= o.rtol * bnorm) { status = P4D_OK; break; }
         if (total >= o.maxit) { status = P4D_NOT_CONVERGED; break; }
+        synced = false;
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta[0];
         res[0] = beta[0];
@@ -1441,6 +1448,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         if (breakdown) {
             const p4d_status rs = residual();
             if (rs != P4D_OK) return rs;
+            synced = true;
             inf.relres_true = hh[0] / bnorm;
             status = inf.relres_true <= o.rtol ? P4D_OK : P4D_BREAKDOWN;
             break;
@@ -1457,11 +1465,12 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         launch_norm_final(red, ob, c->hdev + 200, nullptr, st);
         const p4d_status ps = pull(c, c->hdev + 200, 1, st);
         if (ps != P4D_OK) return ps;
+        synced = true;
         inf.relres_true = hh[0] / bnorm;
     }
 done:
     HIPCHK(c, hipGetLastError());
-    {   // the solution is complete when the handoff after it arrives
+    if (!synced) {   // the solution is complete when the handoff after it arrives
         const p4d_status ps = pull(c, c->hdev, 0, st);
         if (ps != P4D_OK) return ps;
     }
