@@ -55,6 +55,20 @@ def test_zline_preconditioner_on_cubes():
     assert max(errs.values()) <= 1e-10
 
 
+@pytest.mark.parametrize("nz", [120, 250])
+def test_zline_preconditioner_tall_lines(nz):
+    """Longer z-lines take narrower tiles and thinner chunks in the sweep
+    (120 layers: 16 lines, chunks of 2 layers; 250: 8 lines, one layer per
+    chunk), ragged in x; the preconditioner still matches the oracle."""
+    p = flat(nx=23, ny=7, nz=nz, nr=(4, 5), seed=63)
+    orc = O.Oracle(p).setup(smoother=O.SMOOTH_ZLINE)
+    s = solver_for(p, smoother=O.SMOOTH_ZLINE).setup(smoother=O.SMOOTH_ZLINE)
+    r = np.random.default_rng(4).standard_normal(p.N)
+    errs = field_errors(p, to_np(s.apply_pc(to_dev(r))), orc.apply_pc(r))
+    say(f"  z-line pc, {nz} layers", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-10
+
+
 @pytest.mark.parametrize("pc", [O.PC_SCHUR, O.PC_BJ])
 def test_zline_solve_parity(pc):
     p = flat()
