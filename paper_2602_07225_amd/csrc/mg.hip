@@ -602,22 +602,32 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
         __syncthreads();
     }
     if (threadIdx.x < w) {
+        // the next row's values are read one step ahead (ahead of this
+        // step's stores), so that the LDS latency leaves the chain of
+        // dependent divisions
         const int ll = threadIdx.x;
         double cprev = 0.0, dprev = 0.0;
+        double lo = Llo[ll], dg = Ldg[ll], up = Lup[ll], rh = Lrh[ll];
         for (int k = 0; k < nz; k++) {
             const int q = k * LT + ll;
-            const double lo = Llo[q];
-            const double den = Ldg[q] - lo * cprev;
-            cprev = Lup[q] / den;
-            dprev = (Lrh[q] - lo * dprev) / den;
+            const int qn = k + 1 < nz ? q + LT : q;
+            const double lo1 = Llo[qn], dg1 = Ldg[qn], up1 = Lup[qn], rh1 = Lrh[qn];
+            const double den = dg - lo * cprev;
+            cprev = up / den;
+            dprev = (rh - lo * dprev) / den;
             Lup[q] = cprev;
             Lrh[q] = dprev;
+            lo = lo1; dg = dg1; up = up1; rh = rh1;
         }
         double nxt = 0.0;
+        double c = Lup[(nz - 1) * LT + ll], d = Lrh[(nz - 1) * LT + ll];
         for (int k = nz - 1; k >= 0; k--) {
             const int q = k * LT + ll;
-            nxt = Lrh[q] - (k < nz - 1 ? Lup[q] * nxt : 0.0);
+            const int qn = k > 0 ? q - LT : q;
+            const double c1 = Lup[qn], d1 = Lrh[qn];
+            nxt = d - (k < nz - 1 ? c * nxt : 0.0);
             Lrh[q] = nxt;
+            c = c1; d = d1;
         }
     }
     __syncthreads();
@@ -669,18 +679,24 @@ __global__ __launch_bounds__(kBlock) void k_zline_order(int nx, int ny, int nz, 
     }
 }
 
-// Tile width LT (lines along x, a power of two, at most 32) and chunk depth
-// KC (layers, KC * LT <= kBlock) for a z extent: the widest tile whose
-// line rows (four doubles each) and staged x planes fit the 64 KB LDS
-// budget, then the deepest chunk that still fits
+// Tile width LT (lines along x, a power of two) and chunk depth KC (layers,
+// a power of two, KC * LT <= kBlock) of an nx x ny x nz box: 8-line tiles on
+// boxes with many lines (HBM-bound sweeps), 2-line tiles on boxes with few
+// (latency-bound sweeps, where one deep chunk per workgroup pays); then the
+// widest tile and deepest chunk, at most the z extent rounded up, whose line
+// rows (four doubles each) and staged x planes fit the 64 KB LDS budget.
+// The stencil reordering and the sweeps both take the tile from here.
 static size_t zline_lds(int LT, int KC, int nz)
 {
     return (size_t)32 * LT * nz + (size_t)8 * (KC + 2) * (2 * LT + 1) * 3;
 }
-static bool zline_tile(int nz, int &LT, int &KC)
+static bool zline_tile(int nx, int ny, int nz, int &LT, int &KC)
 {
-    for (LT = 32; LT >= 1; LT /= 2)
-        for (KC = kBlock / LT; KC >= 1; KC /= 2)
+    const long long lines = (long long)((nx + 1) / 2) * ((ny + 1) / 2);   // colour 0, the most
+    int kfull = 1;
+    while (kfull < nz && kfull < kBlock) kfull *= 2;
+    for (LT = lines >= 4096 ? 8 : 2; LT >= 1; LT /= 2)
+        for (KC = kfull < kBlock / LT ? kfull : kBlock / LT; KC >= 1; KC /= 2)
             if (zline_lds(LT, KC, nz) <= (size_t)kZlineLds) return true;
     return false;
 }
@@ -688,7 +704,7 @@ static bool zline_tile(int nz, int &LT, int &KC)
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st)
 {
     int LT, KC;
-    if (!zline_tile(nz, LT, KC)) return;   // z extents beyond the limit are refused at setup
+    if (!zline_tile(nx, ny, nz, LT, KC)) return;   // z extents beyond the limit are refused at setup
     const long long N = (long long)nx * ny * nz;
     hipLaunchKernelGGL(k_zline_order, dim3((unsigned)((N + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, nx,
                        ny, nz, LT, S, Sz);
@@ -700,7 +716,7 @@ void launch_zline(LineBatch lb, int colour, hipStream_t st)
     size_t lds = 0;
     for (int q = 0; q < lb.nbox; q++) {
         LineArgs &A = lb.a[q];
-        if (!zline_tile(A.nz, A.lt, A.kc)) return;
+        if (!zline_tile(A.nx, A.ny, A.nz, A.lt, A.kc)) return;
         const size_t need = zline_lds(A.lt, A.kc, A.nz);
         lds = need > lds ? need : lds;
         const int cx = colour & 1, cy = colour >> 1;

@@ -291,7 +291,7 @@ void launch_zline(LineBatch lb, int colour, hipStream_t st);
 // r = b - S x on the same boxes
 void launch_resid_full(LineBatch lb, hipStream_t st);
 // Sz = the rows of S ([27][n] on an nx x ny x nz box) reordered as the
-// z-line sweeps read them: colour by colour, then by tiles of up to 32 lines
+// z-line sweeps read them: colour by colour, then by tiles of up to 8 lines
 // consecutive along x, then layer k, coefficient and line; a coefficient
 // whose neighbour lies off the box is stored as +0
 void launch_zline_order(int nx, int ny, int nz, const double *S, double *Sz, hipStream_t st);

@@ -55,17 +55,19 @@ def test_zline_preconditioner_on_cubes():
     assert max(errs.values()) <= 1e-10
 
 
-@pytest.mark.parametrize("nz", [120, 250])
-def test_zline_preconditioner_tall_lines(nz):
-    """Longer z-lines take narrower tiles and thinner chunks in the sweep
-    (120 layers: 16 lines, chunks of 2 layers; 250: 8 lines, one layer per
-    chunk), ragged in x; the preconditioner still matches the oracle."""
-    p = flat(nx=23, ny=7, nz=nz, nr=(4, 5), seed=63)
+@pytest.mark.parametrize("nx,ny,nz", [(23, 7, 120), (23, 7, 250), (161, 101, 9), (161, 101, 40)])
+def test_zline_preconditioner_tile_shapes(nx, ny, nz):
+    """The sweep's tile follows the box: boxes with few lines take 2-line
+    tiles with one deep chunk (120 layers) or two (250 layers), boxes with
+    more than 4096 lines per colour 8-line tiles, in one chunk (9 layers)
+    or two (40 layers); ragged in x.  The preconditioner matches the
+    oracle on each."""
+    p = flat(nx=nx, ny=ny, nz=nz, nr=(4, 5), seed=63)
     orc = O.Oracle(p).setup(smoother=O.SMOOTH_ZLINE)
     s = solver_for(p, smoother=O.SMOOTH_ZLINE).setup(smoother=O.SMOOTH_ZLINE)
     r = np.random.default_rng(4).standard_normal(p.N)
     errs = field_errors(p, to_np(s.apply_pc(to_dev(r))), orc.apply_pc(r))
-    say(f"  z-line pc, {nz} layers", {k: f"{v:.1e}" for k, v in errs.items()})
+    say(f"  z-line pc, {nx} x {ny} x {nz}", {k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) <= 1e-10
 
 
