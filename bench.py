@@ -33,9 +33,10 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_cube64x64x192_hbm_traffic.txt")
-# the timed headline steps time one launch in SAMPLE_EVERY of the dominant
-# kernel class (coprime with the five level-0 smoothing launches of an
-# application, so every position in the V-cycle is sampled)
+# the timed headline steps time one event pair in SAMPLE_EVERY of the
+# dominant kernel class (a pair of the level-0 smoother spans its launches
+# on one side of a V-cycle's coarse correction; odd, so both sides are
+# sampled)
 SAMPLE_EVERY = 13
 
 
@@ -436,9 +437,9 @@ def main():
     mask = sum(1 << k for k in L.KERNEL_CLASSES)
     # a first pass with events around every launch of every kernel class
     # gives the per-class table and the dominant class; the timed steps then
-    # record events around one launch in SAMPLE_EVERY of that class only
-    # (every launch of that class does the same work; all its pairs would
-    # add about 0.3 ms per step to the headline)
+    # record one event pair in SAMPLE_EVERY of that class only (every
+    # launch of that class does the same work; all its pairs would add to
+    # the headline step)
     _, _, _, _, prof = timed_steps(s, b, fp64, args.steps, args.warmup, mask)
     dom = max(prof, key=lambda k: prof[k]["ms_total"]) if prof else None
     dom_mask = (1 << next(k for k, v in L.KERNEL_CLASSES.items() if v == dom)) if dom else 0
@@ -457,12 +458,12 @@ def main():
                     "traffic": measured_traffic(dom),
                     "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"],
                     "timed_launches": d["launches"], "sampled_every": SAMPLE_EVERY}
-        # an event pair around a launch also times the pair's own processing
-        # on the queue: measured here with nothing between the events (the
-        # kernel-trace duration of the same kernel is avg_launch_us minus it)
-        pair = event_pair_us()
-        roofline["event_pair_us"] = pair
-        roofline["avg_launch_us_net"] = d["avg_us"] - pair
+        # an event pair also times its own processing on the queue, shared by
+        # the launches it spans (for the level-0 smoother the steps on one
+        # side of a coarse correction): measured here with nothing between
+        # the events, for context; avg_launch_us keeps it (the conservative
+        # figure; the kernel trace in profiles/ gives the durations alone)
+        roofline["event_pair_us"] = event_pair_us()
 
     # setup and solve split (one extra, untimed-in-the-headline run)
     torch.cuda.synchronize()

@@ -293,20 +293,24 @@ p4d_status p4d_param_gradient(p4d_ctx *ctx, const double *d_x, const double *d_l
 
 /* Kernel timing with HIP events recorded on `stream` around every launch of
  * the kernel classes in `class_mask` (bit 1 << p4d_kernel_class; 0 switches
- * timing off and clears the totals).  P4D_K_COUPLING: the kernels around the
- * V-cycles of the block Gauss-Seidel and Schur-complement preconditioners
- * (right-hand sides with the off-diagonal blocks, precision casts, output). */
+ * timing off and clears the totals); the level-0 smoothing steps on one side
+ * of a V-cycle's coarse correction, which run back to back, share one event
+ * pair (an interval of cheb_degree - 1 or cheb_degree launches).
+ * P4D_K_COUPLING: the kernels around the V-cycles of the block Gauss-Seidel
+ * and Schur-complement preconditioners (right-hand sides with the
+ * off-diagonal blocks, precision casts, output).                          */
 typedef enum {
     P4D_K_OPERATOR = 1, P4D_K_MDOT = 2, P4D_K_ORTH = 3, P4D_K_RADIAL = 4,
     P4D_K_SMOOTH0 = 5, P4D_K_ZY = 6, P4D_K_BATCH_PC = 7, P4D_K_COUPLING = 8,
     P4D_K_COUNT = 9
 } p4d_kernel_class;
 p4d_status p4d_profile(p4d_ctx *ctx, int class_mask);
-/* Time only one launch in `every` (>= 1, default 1) of each class in the
- * mask, counted per class from this call or the last p4d_profile: fewer
- * event pairs on the stream while the average over the timed launches stays
- * that of the class (a pair costs a few microseconds of the stream's time).
- * The totals of p4d_profile_read then cover the timed launches only.       */
+/* Time only one interval (event pair) in `every` (>= 1, default 1) of each
+ * class in the mask, counted per class from this call or the last
+ * p4d_profile: fewer event pairs on the stream while the average over the
+ * timed launches stays that of the class (a pair costs a few microseconds
+ * of the stream's time).  The totals of p4d_profile_read then cover the
+ * launches of the timed intervals only.                                    */
 p4d_status p4d_profile_every(p4d_ctx *ctx, int every);
 /* For one class: total_ms = summed kernel durations, launches, and bytes =
  * algorithmic bytes of those launches (the data each launch must read and

@@ -62,6 +62,7 @@ struct Prof {
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<double> bytes;    // per pair
     std::vector<int> cls;         // per pair
+    std::vector<int> count;       // launches per pair
     int used = 0;
     double total_ms[P4D_K_COUNT] = {}, total_bytes[P4D_K_COUNT] = {};
     long long launches[P4D_K_COUNT] = {};
@@ -494,7 +495,7 @@ static void prof_harvest(Prof &P)
         hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]);
         P.total_ms[P.cls[i]] += ms;
         P.total_bytes[P.cls[i]] += P.bytes[i];
-        P.launches[P.cls[i]]++;
+        P.launches[P.cls[i]] += P.count[i];
     }
     P.used = 0;
 }
@@ -503,6 +504,7 @@ static void prof_init(Prof &P)
     P.ev.resize(2 * 512);
     P.bytes.resize(512);
     P.cls.resize(512);
+    P.count.resize(512);
     for (auto &e : P.ev) hipEventCreate(&e);
 }
 static void prof_free(Prof &P)
@@ -521,19 +523,27 @@ static void prof_reset(Prof &P, int mask)
         P.seen[k] = 0;
     }
 }
+// An event pair around `count` back-to-back launches of one class (their
+// bytes added with add() when the pair is opened with bytes 0); one pair in
+// P.every of each class is recorded
 struct ProfScope {
     Prof &P;
     bool on;
     hipStream_t st;
-    ProfScope(Prof &P_, int cls, double bytes, hipStream_t s) : P(P_), on(false), st(s)
+    ProfScope(Prof &P_, int cls, double bytes, hipStream_t s, int count = 1) : P(P_), on(false), st(s)
     {
-        if (!(P.mask & (1 << cls))) return;
+        if (!(P.mask & (1 << cls)) || count < 1) return;
         if (P.seen[cls]++ % P.every) return;
         if (P.used * 2 + 2 > (int)P.ev.size()) prof_harvest(P);
         P.bytes[P.used] = bytes;
         P.cls[P.used] = cls;
+        P.count[P.used] = count;
         hipEventRecord(P.ev[2 * P.used], st);
         on = true;
+    }
+    void add(double bytes)
+    {
+        if (on) P.bytes[P.used] += bytes;
     }
     ~ProfScope()
     {
@@ -619,9 +629,11 @@ static PStage<T> &rec_stage(p4d_ctx *c, int kind, int nunits)
     return S;
 }
 
+// grp: the event pair of the level-0 steps it belongs to (or null: a pair
+// of its own)
 template <typename T>
 static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int nb, int step,
-                        int post, hipStream_t st)
+                        int post, hipStream_t st, ProfScope *grp = nullptr)
 {
     // step index t (1-based); post-smoothing step 1 starts from a nonzero x
     LevelBatch<T> lb{};
@@ -670,8 +682,13 @@ static void smooth_step(p4d_ctx *c, VState<T> &vs, int l, const int *boxes, int 
             const double per = 16.0 + 8.0 + sizeof(T) * (3 + (A.c1 != 0.0 && !A.din_x) + (A.dout != nullptr));
             bytes += per * A.n;
         }
-        ProfScope ps(c->prof, P4D_K_SMOOTH0, bytes, st);
-        launch_smooth0<T>(c->g, lb, blk, 0, c->tile_tx, c->tile_cz, st);
+        if (grp) {
+            grp->add(bytes);
+            launch_smooth0<T>(c->g, lb, blk, 0, c->tile_tx, c->tile_cz, st);
+        } else {
+            ProfScope ps(c->prof, P4D_K_SMOOTH0, bytes, st);
+            launch_smooth0<T>(c->g, lb, blk, 0, c->tile_tx, c->tile_cz, st);
+        }
     } else {
         launch_smooth<T>(lb, blk, 0, st);
     }
@@ -798,7 +815,13 @@ template <typename T>
 static void vcycle_rest(p4d_ctx *c, VState<T> &vs, int l, int *act, int na, hipStream_t st)
 {
     const int deg = c->pc.cheb_degree;
-    for (int t = 2; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 0, st);
+    // the level-0 smoothing steps on either side of the coarse correction
+    // run back to back: each side is one timed interval
+    const bool grouped = l == 0 && !c->rec;
+    {
+        ProfScope grp(c->prof, P4D_K_SMOOTH0, 0.0, st, grouped ? deg - 1 : 0);
+        for (int t = 2; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 0, st, grouped ? &grp : nullptr);
+    }
     residual_step<T>(c, vs, l, act, na, st);
     {   // restriction (+ first smoothing iterate of the coarse level)
         TransferBatch<T> tb{};
@@ -842,7 +865,10 @@ static void vcycle_rest(p4d_ctx *c, VState<T> &vs, int l, int *act, int na, hipS
         if (c->rec) rec_stage<T>(c, SK_PROLONG, blk).u.tb = tb;
         else launch_prolong<T>(tb, blk, st);
     }
-    for (int t = 1; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 1, st);
+    {
+        ProfScope grp(c->prof, P4D_K_SMOOTH0, 0.0, st, grouped ? deg : 0);
+        for (int t = 1; t <= deg; t++) smooth_step<T>(c, vs, l, act, na, t, 1, st, grouped ? &grp : nullptr);
+    }
 }
 
 // One V-cycle at level l with z-line smoothing (FP64; levels keep their z

@@ -80,16 +80,20 @@ def test_nonfinite_bound_reported_at_first_use():
     assert info.status == 0 and np.all(np.isfinite(to_np(x)))
 
 
-def test_sampled_profiling_counts_every_nth_launch():
-    """p4d_profile_every(n): one launch in n of each class is timed, and the
-    solve's result does not depend on it."""
+@pytest.mark.parametrize("degree", [2, 3])
+def test_sampled_profiling_counts_every_nth_interval(degree):
+    """p4d_profile_every(n): one event pair in n of each class is timed, and
+    the solve's result does not depend on it.  The level-0 smoothing steps
+    share a pair per side of the coarse correction: degree - 1 launches
+    before, degree after, so the timed launches are those of every n-th of
+    these intervals."""
     p = problem()
     s = solver_for(p)
     b = to_dev(p.b)
-    s.setup(rtol=1e-8)
+    s.setup(rtol=1e-8, cheb_degree=degree)
     x0, _ = s.solve(b)
     cls = next(k for k, v in L.KERNEL_CLASSES.items() if v == "smooth0")
-    counts = {}
+    counts, per = {}, {}
     for every in (1, 3, 7):
         L.p4d_profile(s.ctx, 1 << cls)
         L.p4d_profile_every(s.ctx, every)
@@ -98,9 +102,14 @@ def test_sampled_profiling_counts_every_nth_launch():
         L.p4d_profile(s.ctx, 0)
         L.p4d_profile_every(s.ctx, 1)
         counts[every] = n
-        say(f"every {every}: {n} timed launches, {ms:.3f} ms")
+        per[every] = ms / n
+        say(f"degree {degree}, every {every}: {n} timed launches, {ms:.3f} ms")
         assert n > 0 and ms > 0.0 and by > 0.0
         assert np.array_equal(to_np(x), to_np(x0))
-    assert counts[3] == -(-counts[1] // 3) and counts[7] == -(-counts[1] // 7)
+    cycles, rem = divmod(counts[1], 2 * degree - 1)
+    assert rem == 0
+    sizes = [n for _ in range(cycles) for n in (degree - 1, degree) if n > 0]
+    for every in (3, 7):
+        assert counts[every] == sum(sizes[::every])
     with pytest.raises(P4DError):
         L.p4d_profile_every(s.ctx, 0)
