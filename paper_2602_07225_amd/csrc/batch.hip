@@ -26,13 +26,36 @@
 
 namespace p4d {
 
+// The stage, cell and queue tables do not change while a kernel runs.  Read
+// through the constant address space, their fields arrive by scalar loads
+// and the compiler knows that the pointers among them address global
+// memory; read through a generic pointer, every access through those
+// pointers stays a flat access, which also holds every LDS and scalar-load
+// wait behind the outstanding memory operations.
+template <typename X>
+using Ctab = __attribute__((address_space(4))) const X;
+template <typename X>
+__device__ inline Ctab<X> *ctab(const X *p)
+{
+    return (Ctab<X> *)p;
+}
+// a copy of a table entry (for types whose copy constructor does not take a
+// constant-address-space source)
+template <typename X>
+__device__ inline X ld(Ctab<X> &r)
+{
+    X v;
+    __builtin_memcpy(&v, (const void *)&r, sizeof(X));
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Batched preconditioner stages.  Every launch runs one work list: units of
 // one stage family (see StageFamily) from the stages of one depth, one unit
 // per workgroup.  A kernel per family keeps the register and LDS footprint
 // of that family's block function only.
 // ---------------------------------------------------------------------------
-__device__ inline int find_pos(const int *ustart, int npos, int item)
+__device__ inline int find_pos(Ctab<int> *ustart, int npos, int item)
 {
     int lo = 0, hi = npos - 1;
     while (lo < hi) {
@@ -53,9 +76,9 @@ struct UnitRef {
 __device__ inline UnitRef unit_of(const StageRun &run)
 {
     const int item = run.item0 + xcd_block(blockIdx.x, gridDim.x);
-    const int pos = __builtin_amdgcn_readfirstlane(run.pos0 + find_pos(run.ustart + run.pos0, run.npos, item));
-    const int si = __builtin_amdgcn_readfirstlane(run.order[pos]);
-    const int unit = __builtin_amdgcn_readfirstlane(item - run.ustart[pos]);
+    const int pos = __builtin_amdgcn_readfirstlane(run.pos0 + find_pos(ctab(run.ustart + run.pos0), run.npos, item));
+    const int si = __builtin_amdgcn_readfirstlane(ctab(run.order)[pos]);
+    const int unit = __builtin_amdgcn_readfirstlane(item - ctab(run.ustart)[pos]);
     return UnitRef{si, unit};
 }
 
@@ -63,11 +86,11 @@ template <typename T, int NRMAX>
 __global__ __launch_bounds__(kBlock) void k_bstage_radf(StageRun run)
 {
     const UnitRef u = unit_of(run);
-    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    Ctab<PStage<T>> &S = ctab((const PStage<T> *)run.stages)[u.si];
     if (!((run.active >> S.cell) & 1ULL)) return;   // the cell is not iterating
     // local copies: the cell's constants stay in registers across the
     // unit's stores
-    const PCell &Cm = run.cells[S.cell];
+    const PCell Cm = ld(ctab(run.cells)[S.cell]);
     const Geom g = Cm.g;
     const RadArgs R = Cm.R;
     const double *r = Cm.V + (long long)run.k * g.N;
@@ -84,9 +107,9 @@ template <typename T, typename TZ, int NRMAX>
 __global__ __launch_bounds__(kBlock) void k_bstage_radb(StageRun run)
 {
     const UnitRef u = unit_of(run);
-    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    Ctab<PStage<T>> &S = ctab((const PStage<T> *)run.stages)[u.si];
     if (!((run.active >> S.cell) & 1ULL)) return;
-    const PCell &Cm = run.cells[S.cell];
+    const PCell Cm = ld(ctab(run.cells)[S.cell]);
     const Geom g = Cm.g;
     const RadArgs R = Cm.R;
     const double *r = Cm.V + (long long)run.k * g.N;
@@ -101,17 +124,20 @@ __global__ __launch_bounds__(kBlock) void k_bstage_radb(StageRun run)
     }
 }
 
-template <typename T>
+// KINDS: the stage kinds in the list (1: smoothing steps only, 2: residuals
+// only, 3: both), so that a list of one kind carries the registers of that
+// kind's tile function only
+template <typename T, int KINDS>
 __global__ __launch_bounds__(kBlock) void k_bstage_sm0(StageRun run)
 {
     __shared__ Smooth0Lds lds;
     const UnitRef u = unit_of(run);
-    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    Ctab<PStage<T>> &S = ctab((const PStage<T> *)run.stages)[u.si];
     if (!((run.active >> S.cell) & 1ULL)) return;
-    const LevelArgs<T> A = S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, u.unit))];
-    const Geom g = run.cells[S.cell].g;
+    const LevelArgs<T> A = ld(S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, u.unit))]);
+    const Geom g = ld(ctab(run.cells)[S.cell]).g;
     const int TX = S.TX, CZ = S.CZ;
-    if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, u.unit - A.blk0, TX, CZ, lds);
+    if (KINDS == 1 || (KINDS == 3 && S.kind == SK_SM0)) smooth0_tile<T, false>(g, A, u.unit - A.blk0, TX, CZ, lds);
     else smooth0_tile<T, true>(g, A, u.unit - A.blk0, TX, CZ, lds);
 }
 
@@ -120,31 +146,31 @@ __global__ __launch_bounds__(kBlock) void k_bstage_misc(StageRun run)
 {
     __shared__ CoarseLds lds;
     const UnitRef u = unit_of(run);
-    const PStage<T> &S = ((const PStage<T> *)run.stages)[u.si];
+    Ctab<PStage<T>> &S = ctab((const PStage<T> *)run.stages)[u.si];
     if (!((run.active >> S.cell) & 1ULL)) return;
     const int unit = u.unit;
     switch (S.kind) {
     case SK_SM:
     case SK_SMR: {
-        const LevelArgs<T> A = S.u.lb.a[find_box(S.u.lb, unit)];
+        const LevelArgs<T> A = ld(S.u.lb.a[find_box(S.u.lb, unit)]);
         if (S.kind == SK_SM) smooth_block<T, false>(A, unit - A.blk0);
         else smooth_block<T, true>(A, unit - A.blk0);
         break;
     }
     case SK_RESTRICT: {
-        const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+        const TransferArgs<T> A = ld(S.u.tb.a[find_box(S.u.tb, unit)]);
         restrict_block<T>(A, unit - A.blk0);
         break;
     }
     case SK_PROLONG: {
-        const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+        const TransferArgs<T> A = ld(S.u.tb.a[find_box(S.u.tb, unit)]);
         prolong_block<T>(A, unit - A.blk0);
         break;
     }
     case SK_COARSE: {
         const int box = unit / S.aux, rb = unit % S.aux;
         if (box < S.u.cb.nbox) {
-            const CoarseArgs<T> A = S.u.cb.a[box];
+            const CoarseArgs<T> A = ld(S.u.cb.a[box]);
             if (rb * 64 < A.n) coarse_block<T>(A, rb, lds);
         }
         break;
@@ -155,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_bstage_misc(StageRun run)
 }
 
 template <typename T, typename TZ>
-void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t st)
+void launch_batch_stage(const StageRun &run, int family, int nrmax, int kinds, hipStream_t st)
 {
     if (run.nitems <= 0) return;
     const dim3 grid(run.nitems), block(kBlock);
@@ -171,14 +197,16 @@ void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t 
 #undef P4D_BB
         break;
     case SF_SM0:
-        hipLaunchKernelGGL((k_bstage_sm0<T>), grid, block, 0, st, run);
+        if (kinds == 1) hipLaunchKernelGGL((k_bstage_sm0<T, 1>), grid, block, 0, st, run);
+        else if (kinds == 2) hipLaunchKernelGGL((k_bstage_sm0<T, 2>), grid, block, 0, st, run);
+        else hipLaunchKernelGGL((k_bstage_sm0<T, 3>), grid, block, 0, st, run);
         break;
     default:
         hipLaunchKernelGGL((k_bstage_misc<T>), grid, block, 0, st, run);
         break;
     }
 }
-#define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, int, hipStream_t);
+#define P4D_INST(T, TZ) template void launch_batch_stage<T, TZ>(const StageRun &, int, int, int, hipStream_t);
 P4D_INST(double, double)
 P4D_INST(float, double)
 P4D_INST(double, float)
@@ -196,9 +224,9 @@ union PersistLds {
 // one unit of a stage: the device function of its family, as in the
 // per-depth kernels above
 template <typename T, typename TZ, int NRMAX>
-__device__ inline void persist_unit(const PersistRun &run, const PStage<T> &S, int unit, PersistLds &L)
+__device__ inline void persist_unit(const PersistRun &run, Ctab<PStage<T>> &S, int unit, PersistLds &L)
 {
-    const PCell &Cm = run.cells[S.cell];
+    const PCell Cm = ld(ctab(run.cells)[S.cell]);
     switch (stage_family(S.kind)) {
     case SF_RADF: {
         const Geom g = Cm.g;
@@ -229,7 +257,7 @@ __device__ inline void persist_unit(const PersistRun &run, const PStage<T> &S, i
         break;
     }
     case SF_SM0: {
-        const LevelArgs<T> A = S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, unit))];
+        const LevelArgs<T> A = ld(S.u.lb.a[__builtin_amdgcn_readfirstlane(find_box(S.u.lb, unit))]);
         const Geom g = Cm.g;
         if (S.kind == SK_SM0) smooth0_tile<T, false>(g, A, unit - A.blk0, S.TX, S.CZ, L.s0);
         else smooth0_tile<T, true>(g, A, unit - A.blk0, S.TX, S.CZ, L.s0);
@@ -239,25 +267,25 @@ __device__ inline void persist_unit(const PersistRun &run, const PStage<T> &S, i
         switch (S.kind) {
         case SK_SM:
         case SK_SMR: {
-            const LevelArgs<T> A = S.u.lb.a[find_box(S.u.lb, unit)];
+            const LevelArgs<T> A = ld(S.u.lb.a[find_box(S.u.lb, unit)]);
             if (S.kind == SK_SM) smooth_block<T, false>(A, unit - A.blk0);
             else smooth_block<T, true>(A, unit - A.blk0);
             break;
         }
         case SK_RESTRICT: {
-            const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+            const TransferArgs<T> A = ld(S.u.tb.a[find_box(S.u.tb, unit)]);
             restrict_block<T>(A, unit - A.blk0);
             break;
         }
         case SK_PROLONG: {
-            const TransferArgs<T> A = S.u.tb.a[find_box(S.u.tb, unit)];
+            const TransferArgs<T> A = ld(S.u.tb.a[find_box(S.u.tb, unit)]);
             prolong_block<T>(A, unit - A.blk0);
             break;
         }
         case SK_COARSE: {
             const int box = unit / S.aux, rb = unit % S.aux;
             if (box < S.u.cb.nbox) {
-                const CoarseArgs<T> A = S.u.cb.a[box];
+                const CoarseArgs<T> A = ld(S.u.cb.a[box]);
                 if (rb * 64 < A.n) coarse_block<T>(A, rb, L.co);
             }
             break;
@@ -283,9 +311,9 @@ __global__ __launch_bounds__(kBlock) void k_bpc_persist(PersistRun run)
     for (int d = 0; d < run.ndepth; d++) {
         const int i0 = run.dstart[d], i1 = run.dstart[d + 1];
         for (int item = i0 + (int)blockIdx.x; item < i1; item += (int)gridDim.x) {
-            const int pos = __builtin_amdgcn_readfirstlane(find_pos(run.ustart, run.npos, item));
-            const int si = __builtin_amdgcn_readfirstlane(run.order[pos]);
-            const PStage<T> &S = ((const PStage<T> *)run.stages)[si];
+            const int pos = __builtin_amdgcn_readfirstlane(find_pos(ctab(run.ustart), run.npos, item));
+            const int si = __builtin_amdgcn_readfirstlane(ctab(run.order)[pos]);
+            Ctab<PStage<T>> &S = ctab((const PStage<T> *)run.stages)[si];
             if (!((run.active >> S.cell) & 1ULL)) continue;   // (uniform in the workgroup)
             persist_unit<T, TZ, NRMAX>(run, S, item - run.ustart[pos], lds);
         }
@@ -329,14 +357,14 @@ P4D_INST(double, float)
 P4D_INST(float, float)
 #undef P4D_INST
 
-// workgroups of the batched level-0 smoother resident at once
+// workgroups of the batched level-0 smoother (its smoothing steps) resident at once
 template <typename T>
 int bstage_sm0_slots()
 {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_bstage_sm0<T>, kBlock, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)k_bstage_sm0<T, 1>, kBlock, 0) !=
             hipSuccess)
         return 1024;
     return (per < 1 ? 1 : per) * (ncu < 1 ? 1 : ncu);
@@ -359,7 +387,7 @@ __device__ inline int find_cell(const BCell *cells, int ncells, int b)
     int lo = 0, hi = ncells - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const BCell &M = cells[mid];
+        Ctab<BCell> &M = ctab(cells)[mid];
         const int b0 = SEL == SEL_OP ? M.op_blk0
                                      : (SEL == SEL_ST ? M.st_blk0 : (SEL == SEL_TILE ? M.tile_blk0 : M.rad_blk0));
         if (b0 <= b) lo = mid;
@@ -376,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_bop_resid(const BCell *__restrict__ 
     __shared__ double red[4];
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const int c = find_cell<SEL_OP>(cells, ncells, gb);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int lb = gb - C.op_blk0;
     const long long n = (long long)lb * kBlock + threadIdx.x;
@@ -399,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_bop_tile(const BCell *__restrict__ c
     __shared__ OpLds L;
     const int gb = xcd_block(blockIdx.x, gridDim.x);
     const int c = find_cell<SEL_TILE>(cells, ncells, gb);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const Geom g = C.g;
     OpArgs O = C.op;
@@ -415,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_bop_radial(const BCell *__restrict__
                                                        unsigned long long active, int k)
 {
     const int c = find_cell<SEL_RAD>(cells, ncells, blockIdx.x);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const Geom g = C.g;
     const long long je = (long long)(blockIdx.x - C.rad_blk0) * kBlock + threadIdx.x;
@@ -433,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_bmdot(const BCell *__restrict__ cell
 {
     __shared__ double red[4][KMAX];
     const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
     const long long N = C.g.N;
@@ -469,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_bmdot_final(const BCell *__restrict_
 {
     __shared__ double red[4];
     const int q = blockIdx.x, c = blockIdx.y;
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int nb = C.st_nblk;
     double s = 0.0;
@@ -488,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_borth(const BCell *__restrict__ cell
 {
     __shared__ double red[4];
     const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
     const long long N = C.g.N;
@@ -519,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_bnorm_final(const BCell *__restrict_
 {
     __shared__ double red[4];
     const int c = blockIdx.x;
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int nb = op ? C.op_nblk : C.st_nblk;
     double s = 0.0;
@@ -537,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_bzy(const BCell *__restrict__ cells,
                                                 unsigned long long active)
 {
     const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     if (!((active >> c) & 1ULL)) return;
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
     const long long N = C.g.N;
@@ -561,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_bstart(const BCell *__restrict__ cel
 {
     __shared__ double red[4];
     const int c = find_cell<SEL_ST>(cells, ncells, blockIdx.x);
-    const BCell &C = cells[c];
+    const BCell C = ld(ctab(cells)[c]);
     const int lb = blockIdx.x - C.st_blk0, nb = C.st_nblk;
     const long long N = C.g.N;
     double s = 0.0;

@@ -2493,6 +2493,7 @@ struct p4d_batch {
     int nstages = 0, nrmax = 8;
     struct WorkList {
         int family, nr;             // stage family, radial size class
+        int kinds = 0;              // level-0 smoothing lists: 1 steps, 2 residuals, 3 both
         int pos0, npos;             // queue positions
         int item0, nitems;          // units
         int depth;                  // stage depth
@@ -2677,11 +2678,12 @@ static p4d_status batch_record(p4d_batch *B)
         for (int fam = SF_RADF; fam <= SF_MISC; fam++) {
             const bool radial = fam == SF_RADF || fam == SF_RADB;
             for (int ci = 0; ci < (radial ? kNrClasses : 1); ci++) {
-                p4d_batch::WorkList W{fam, radial ? kNrClass[ci] : 8, (int)order.size(), 0, (int)items, 0, d};
+                p4d_batch::WorkList W{fam, radial ? kNrClass[ci] : 8, 0, (int)order.size(), 0, (int)items, 0, d};
                 for (int i : bysize) {
                     const int j = at[(size_t)i * depth + d];
                     if (j < 0 || stage_family(per[i][j].kind) != fam) continue;
                     if (radial && rad_nrmax(B->cell[i]->g) != kNrClass[ci]) continue;
+                    if (fam == SF_SM0) W.kinds |= per[i][j].kind == SK_SM0 ? 1 : 2;
                     order.push_back(base[i] + j);
                     ustart.push_back((int)items);
                     items += per[i][j].nunits;
@@ -2832,7 +2834,7 @@ static void batch_apply_pc(p4d_batch *B, int transpose, int k, unsigned long lon
         run.npos = W.npos;
         run.item0 = W.item0;
         run.nitems = W.nitems;
-        launch_batch_stage<T, TZ>(run, W.family, W.nr, st);
+        launch_batch_stage<T, TZ>(run, W.family, W.nr, W.kinds, st);
     }
 }
 

@@ -78,7 +78,7 @@ __host__ __device__ inline int stage_family(int kind)
 }
 
 template <typename T, typename TZ>
-void launch_batch_stage(const StageRun &run, int family, int nrmax, hipStream_t st);
+void launch_batch_stage(const StageRun &run, int family, int nrmax, int kinds, hipStream_t st);
 
 // One launch for a whole preconditioner application of all cells: the work
 // items of all stage depths (the units of the per-depth work lists, depth
