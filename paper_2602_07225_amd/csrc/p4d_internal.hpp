@@ -38,10 +38,13 @@ __host__ __device__ inline int elem_mat(const Geom &g, int kk)
 {
     return kk + 1 < g.na ? 0 : (kk >= g.na + g.ns ? 1 : -1);
 }
-// storage coefficient eps h^3 / dt of element id (in element layer kk)
+// storage coefficient eps h^3 / dt of element id (in element layer kk); the
+// array is device memory, read as such (through the generic pointer the
+// compiler would emit a flat load, which also holds up every LDS wait)
 __device__ inline double elem_storage(const Geom &g, long long id, int kk)
 {
-    return g.meh ? g.meh[id] : (elem_mat(g, kk) >= 0 ? g.mass_elec : g.mass_sep);
+    return g.meh ? ((const __attribute__((address_space(1))) double *)g.meh)[id]
+                 : (elem_mat(g, kk) >= 0 ? g.mass_elec : g.mass_sep);
 }
 __host__ __device__ inline int node_mat(const Geom &g, int k)
 {
