@@ -18,7 +18,8 @@ int stream_blocks(long long n)
 
 template <int KMAX>
 __global__ __launch_bounds__(kBlock) void k_mdot(long long n, const double *__restrict__ w,
-                                                 const double *__restrict__ V, long long ldv,
+                                                 const double *__restrict__ V,
+                                                 const double *__restrict__ v0, long long ldv,
                                                  int nv, double *__restrict__ partial)
 {
     __shared__ double red[4][KMAX];
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(long long n, const double *__re
         const double wi = w[i];
 #pragma unroll
         for (int q = 0; q < KMAX; q++)
-            if (q < nv) acc[q] += wi * V[(long long)q * ldv + i];
+            if (q < nv) acc[q] += wi * (q == 0 ? v0 : V + (long long)q * ldv)[i];
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -48,11 +49,11 @@ __global__ __launch_bounds__(kBlock) void k_mdot(long long n, const double *__re
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-void launch_mdot(long long n, const double *w, const double *V, long long ldv, int nv,
+void launch_mdot(long long n, const double *w, const double *V, const double *v0, long long ldv, int nv,
                  double *partial, int nblk, hipStream_t st)
 {
 #define P4D_MD(K) \
-    hipLaunchKernelGGL((k_mdot<K>), dim3(nblk), dim3(kBlock), 0, st, n, w, V, ldv, nv, partial)
+    hipLaunchKernelGGL((k_mdot<K>), dim3(nblk), dim3(kBlock), 0, st, n, w, V, v0, ldv, nv, partial)
     if (nv <= 4) P4D_MD(4);
     else if (nv <= 8) P4D_MD(8);
     else if (nv <= 16) P4D_MD(16);
@@ -88,7 +89,8 @@ void launch_mdot_final(int nv, const double *partial, int nblk, const double *in
 
 template <int KMAX>
 __global__ __launch_bounds__(kBlock) void k_orth(long long n, double *__restrict__ w,
-                                                 const double *__restrict__ V, long long ldv,
+                                                 const double *__restrict__ V,
+                                                 const double *__restrict__ v0, long long ldv,
                                                  int nv, const double *__restrict__ c,
                                                  double *__restrict__ partial)
 {
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_orth(long long n, double *__restrict
         double wi = w[i];
 #pragma unroll
         for (int q = 0; q < KMAX; q++)
-            if (q < nv) wi -= cq[q] * V[(long long)q * ldv + i];
+            if (q < nv) wi -= cq[q] * (q == 0 ? v0 : V + (long long)q * ldv)[i];
         w[i] = wi;
         sq += wi * wi;
     }
@@ -110,11 +112,11 @@ __global__ __launch_bounds__(kBlock) void k_orth(long long n, double *__restrict
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-void launch_orth(long long n, double *w, const double *V, long long ldv, int nv, const double *c,
-                 double *partial, int nblk, hipStream_t st)
+void launch_orth(long long n, double *w, const double *V, const double *v0, long long ldv, int nv,
+                 const double *c, double *partial, int nblk, hipStream_t st)
 {
 #define P4D_OR(K) \
-    hipLaunchKernelGGL((k_orth<K>), dim3(nblk), dim3(kBlock), 0, st, n, w, V, ldv, nv, c, partial)
+    hipLaunchKernelGGL((k_orth<K>), dim3(nblk), dim3(kBlock), 0, st, n, w, V, v0, ldv, nv, c, partial)
     if (nv <= 4) P4D_OR(4);
     else if (nv <= 8) P4D_OR(8);
     else if (nv <= 16) P4D_OR(16);
@@ -145,17 +147,18 @@ void launch_norm_final(const double *partial, int nblk, double *beta, double *in
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, partial, nblk, beta, invbeta);
 }
 
+// assign: x = Z y (x not read; the first update from x = 0), else x += Z y
 template <typename TZ, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_zy(long long n, double *__restrict__ x,
                                                const TZ *__restrict__ Z, long long ldz, int nv,
-                                               const double *__restrict__ y)
+                                               const double *__restrict__ y, int assign)
 {
     double yq[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; q++) yq[q] = q < nv ? y[q] : 0.0;
     const long long stride = (long long)gridDim.x * kBlock;
     for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        double xi = x[i];
+        double xi = assign ? 0.0 : x[i];
 #pragma unroll
         for (int q = 0; q < KMAX; q++)
             if (q < nv) xi += yq[q] * (double)Z[(long long)q * ldz + i];
@@ -164,12 +167,12 @@ __global__ __launch_bounds__(kBlock) void k_zy(long long n, double *__restrict__
 }
 
 template <typename TZ>
-void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const double *y,
+void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const double *y, int assign,
                hipStream_t st)
 {
     const int nblk = stream_blocks(n);
 #define P4D_ZY(K) \
-    hipLaunchKernelGGL((k_zy<TZ, K>), dim3(nblk), dim3(kBlock), 0, st, n, x, Z, ldz, nv, y)
+    hipLaunchKernelGGL((k_zy<TZ, K>), dim3(nblk), dim3(kBlock), 0, st, n, x, Z, ldz, nv, y, assign)
     if (nv <= 4) P4D_ZY(4);
     else if (nv <= 8) P4D_ZY(8);
     else if (nv <= 16) P4D_ZY(16);
@@ -177,9 +180,9 @@ void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const
     else P4D_ZY(64);
 #undef P4D_ZY
 }
-template void launch_zy<double>(long long, double *, const double *, long long, int, const double *,
+template void launch_zy<double>(long long, double *, const double *, long long, int, const double *, int,
                                 hipStream_t);
-template void launch_zy<float>(long long, double *, const float *, long long, int, const double *,
+template void launch_zy<float>(long long, double *, const float *, long long, int, const double *, int,
                                hipStream_t);
 
 __global__ __launch_bounds__(kBlock) void k_dot(long long n, const double *__restrict__ a,

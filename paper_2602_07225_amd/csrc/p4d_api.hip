@@ -1310,21 +1310,24 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         return P4D_OK;
     };
 
-    // ||b|| over all unknowns; x = 0 and (full space) V_0 = b are enqueued
-    // behind its handoff, so that the device runs them while the host waits
+    // ||b|| over all unknowns
     launch_dot_partial(g.N, b, b, red, sbf, st);
     launch_norm_final(red, sbf, c->hdev, nullptr, st);
     {
-        const unsigned long long bseq = publish(c, c->hdev, 1, 0, st);
-        HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
-        if (!schur) HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
-        const p4d_status ps = await_pub(c, 0, bseq, st);
+        const p4d_status ps = pull(c, c->hdev, 1, st);
         if (ps != P4D_OK) return ps;
     }
     const double bnorm = hh[0];
     // set when the last handoff follows every write to x (no final one needed)
     bool synced = false;
+    // x = 0 until the first update, which assigns x = Z y instead of adding
+    // (a solve that stops before it clears x at the end)
+    bool x_zero = true;
+    // the first basis vector: the first cycle reads the right-hand side in
+    // place, later cycles their residual in V
+    const double *v0 = bk;
     if (!std::isfinite(bnorm)) {
+        HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
         HIPCHK(c, hipStreamSynchronize(st));
         return fail(c, P4D_ERR_NONFINITE, "non-finite right-hand side");
     }
@@ -1343,7 +1346,6 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         // r = bk - op(x) into V_0 (x = 0 in the first cycle: r = bk)
         if (first) {
             if (schur) {
-                HIPCHK(c, hipMemcpyAsync(V, bk, 8 * (size_t)N, hipMemcpyDeviceToDevice, st));
                 launch_dot_partial(N, bk, bk, red, sb, st);
                 launch_norm_final(red, sb, c->hdev + 200, c->invbeta, st);
                 const p4d_status ps = pull(c, c->hdev + 200, 1, st);
@@ -1360,6 +1362,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             if (rs != P4D_OK) return rs;
             beta[0] = hh[0];
             synced = true;
+            v0 = V;
         }
         inf.relres_true = beta[0] / bnorm;
         if (!std::isfinite(beta[0])) { status = P4D_ERR_NONFINITE; break; }
@@ -1376,7 +1379,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         // needs is in device memory), then its Hessenberg column to the host
         unsigned long long step_seq[2] = {0, 0};
         auto enqueue_step = [&](int k) {
-            double *vk = V + (long long)k * N;
+            const double *vk = k == 0 ? v0 : V + (long long)k * N;
             TZ *zk = Z + (long long)k * N;
             double *w = V + (long long)(k + 1) * N;
             if (schur) {
@@ -1391,12 +1394,12 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             for (int p = 0; p < passes; p++) {
                 {
                     ProfScope ps(c->prof, P4D_K_MDOT, 8.0 * (nv + 1) * N, st);
-                    launch_mdot(N, w, V, N, nv, red, sb, st);
+                    launch_mdot(N, w, V, v0, N, nv, red, sb, st);
                 }
                 launch_mdot_final(nv, red, sb, c->invbeta, c->hdev + 64 * p, c->cdev, st);
                 {
                     ProfScope ps(c->prof, P4D_K_ORTH, 8.0 * (nv + 2) * N, st);
-                    launch_orth(N, w, V, N, nv, c->cdev, red, sb, st);
+                    launch_orth(N, w, V, v0, N, nv, c->cdev, red, sb, st);
                 }
             }
             launch_norm_final(red, sb, c->hdev + 128, c->invbeta + k + 1, st);
@@ -1468,8 +1471,9 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         HIPCHK(c, hipMemcpyAsync(c->ydev, hout, 8 * kused, hipMemcpyHostToDevice, st));
         {
             ProfScope ps(c->prof, P4D_K_ZY, (8.0 * 2 + sizeof(TZ) * kused) * N, st);
-            launch_zy<TZ>(N, x, Z, N, kused, c->ydev, st);
+            launch_zy<TZ>(N, x, Z, N, kused, c->ydev, x_zero ? 1 : 0, st);
         }
+        if (kused > 0) x_zero = false;
         inf.restarts++;
         if (breakdown) {
             const p4d_status rs = residual();
@@ -1479,6 +1483,10 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
             status = inf.relres_true <= o.rtol ? P4D_OK : P4D_BREAKDOWN;
             break;
         }
+    }
+    if (x_zero) {   // no update happened
+        HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));
+        x_zero = false;
     }
     if (schur && status != P4D_ERR_NONFINITE) {
         // particle unknowns from the electrode-level ones, then the true
@@ -1495,6 +1503,7 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         inf.relres_true = hh[0] / bnorm;
     }
 done:
+    if (x_zero) HIPCHK(c, hipMemsetAsync(x, 0, 8 * (size_t)g.N, st));   // (b = 0)
     HIPCHK(c, hipGetLastError());
     if (!synced) {   // the solution is complete when the handoff after it arrives
         const p4d_status ps = pull(c, c->hdev, 0, st);

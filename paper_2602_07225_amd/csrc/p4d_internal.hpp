@@ -352,16 +352,19 @@ void launch_red_resid(long long n, const double *bhat, double *w, double *partia
 
 // krylov.hip
 int stream_blocks(long long n);
-void launch_mdot(long long n, const double *w, const double *V, long long ldv, int nv,
+// basis vector q at V + q ldv, except vector 0 at v0 (the first cycle's
+// right-hand side, read in place)
+void launch_mdot(long long n, const double *w, const double *V, const double *v0, long long ldv, int nv,
                  double *partial, int nblk, hipStream_t st);
 void launch_mdot_final(int nv, const double *partial, int nblk, const double *invbeta,
                        double *h, double *c, hipStream_t st);
-void launch_orth(long long n, double *w, const double *V, long long ldv, int nv,
+void launch_orth(long long n, double *w, const double *V, const double *v0, long long ldv, int nv,
                  const double *c, double *partial, int nblk, hipStream_t st);
 void launch_norm_final(const double *partial, int nblk, double *beta_out, double *invbeta_out,
                        hipStream_t st);
+// x += Z y, or x = Z y with assign (x is not read)
 template <typename TZ>
-void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const double *y,
+void launch_zy(long long n, double *x, const TZ *Z, long long ldz, int nv, const double *y, int assign,
                hipStream_t st);
 void launch_dot_partial(long long n, const double *a, const double *b, double *partial,
                         int nblk, hipStream_t st);
