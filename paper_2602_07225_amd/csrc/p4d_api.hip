@@ -1470,7 +1470,8 @@ static p4d_status fgmres(p4d_ctx *c, int transpose, const double *b, double *x,
         for (int i = 0; i < kused; i++) hout[i] = yv[i];
         HIPCHK(c, hipMemcpyAsync(c->ydev, hout, 8 * kused, hipMemcpyHostToDevice, st));
         {
-            ProfScope ps(c->prof, P4D_K_ZY, (8.0 * 2 + sizeof(TZ) * kused) * N, st);
+            // x written, and read unless this update assigns it
+            ProfScope ps(c->prof, P4D_K_ZY, ((x_zero ? 8.0 : 16.0) + sizeof(TZ) * kused) * N, st);
             launch_zy<TZ>(N, x, Z, N, kused, c->ydev, x_zero ? 1 : 0, st);
         }
         if (kused > 0) x_zero = false;
