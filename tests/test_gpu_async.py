@@ -57,6 +57,27 @@ def test_solve_stopped_at_maxit_equals_one_cycle(maxit):
     assert np.array_equal(to_np(xa), to_np(xb))
 
 
+@pytest.mark.parametrize("krylov", [0, 1])
+def test_solve_without_an_update_leaves_x_zero(krylov):
+    """The first update assigns x = Z y (x is not cleared before it): a solve
+    that stops before any update (maxit = 0) returns x = 0 in the Krylov
+    space (all unknowns, or the electrode-level ones over the Schur
+    complement, whose particle unknowns then follow from them), and the
+    next solve is unaffected."""
+    p = problem()
+    s = solver_for(p)
+    b = to_dev(p.b)
+    s.setup(rtol=1e-10)
+    x1, i1 = s.solve(b, krylov=krylov)
+    x0, i0 = s.solve(b, maxit=0, krylov=krylov)
+    say(f"krylov {krylov}: maxit 0 status {i0.status} iters {i0.iters}")
+    assert i0.iters == 0 and i0.status == L.P4D_NOT_CONVERGED
+    nk = p.N if krylov == 0 else p.offsets[3]   # phi_s, phi_e, c_e
+    assert not np.any(to_np(x0)[:nk])
+    x2, i2 = s.solve(b, krylov=krylov)
+    assert i2.status == 0 and np.array_equal(to_np(x2), to_np(x1))
+
+
 def test_nonfinite_bound_reported_at_first_use():
     """A coefficient that makes a Gershgorin bound non-finite: the setup
     returns (it does not wait for its kernels), the first solve reports
