@@ -553,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_zline(LineBatch lb, int colour)
     const LineArgs &A = lb.a[find_box(lb, blockIdx.x)];
     const int LT = A.lt, KC = A.kc;   // KC * LT <= kBlock
     const int cx = colour & 1, cy = colour >> 1;
-    const int ncx = (A.nx - cx + 1) / 2, ncy = (A.ny - cy + 1) / 2;
+    const int ncx = (A.nx - cx + 1) / 2;
     const int tX = (ncx + LT - 1) / LT;
     const int tile = blockIdx.x - A.blk0;
     const int a0 = (tile % tX) * LT, bl = tile / tX;

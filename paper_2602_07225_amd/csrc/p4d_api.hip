@@ -1978,10 +1978,8 @@ p4d_status p4d_setup(p4d_ctx *c, const p4d_solve_opts *opts, void *stream)
     c->prec = o.pc_prec == P4D_FP32 ? 1 : 0;
     c->lmax_pending = 0;
     hipStream_t st = (hipStream_t)stream;
-    auto t0 = std::chrono::steady_clock::now();
     p4d_status s = c->prec ? setup_t<float>(c, st) : setup_t<double>(c, st);
     if (s != P4D_OK) return s;
-    (void)t0;
     c->pc_ready = 1;
     return P4D_OK;
 }
