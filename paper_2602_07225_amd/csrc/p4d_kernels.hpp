@@ -86,6 +86,35 @@ __device__ inline R stiff_of(const Geom &g, const R c[8], const R X[27])
     return q1_stiff(c, X);
 }
 
+// The cube stencil as the level-0 smoother evaluates it.  The rows sum to
+// zero, so the node's row is (4 x_i sum_e c_e - sum_e c_e F_e) / 12, with
+// F_e the sum of x over the four corners of element e that differ from the
+// node in at least two axes.  That is ~41 FP64 operations per node against
+// ~72 for the difference form; the rounding differs by a few ulps of
+// |x_i| sum_e c_e, which is far below what a smoothing step resolves.
+template <typename R>
+__device__ inline R q1_stiff_sum(const R c[8], const R X[27])
+{
+    R acc = R(0), cs = R(0);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        const int a = (1 - ex) | ((1 - ey) << 1) | ((1 - ez) << 2);
+        R far = R(0);
+        bool first = true;
+#pragma unroll
+        for (int bb = 0; bb < 8; bb++) {
+            if (popc3(a ^ bb) < 2) continue;
+            const R v = X[nb_index(ex - 1 + (bb & 1), ey - 1 + ((bb >> 1) & 1), ez - 1 + ((bb >> 2) & 1))];
+            far = first ? v : far + v;
+            first = false;
+        }
+        acc = e == 0 ? c[e] * far : acc + c[e] * far;
+        cs = e == 0 ? c[e] : cs + c[e];
+    }
+    return (R(4) * X[13] * cs - acc) * R(1.0 / 12.0);
+}
+
 // MEH: the storage of the mass box per element (g.meh) and the box-element
 // stiffness weights (a separate instantiation keeps the per-material cube
 // one free of their registers)
@@ -221,7 +250,7 @@ __device__ inline void smooth0_tile(const Geom &g, const LevelArgs<T> &A, int ti
                     cM[e] = in ? (elem_mat(g, ek) >= 0 ? g.mass_elec : g.mass_sep) : 0.0;
                 }
             }
-            double Sx = stiff_of<MEH>(g, cK, X) + dcn * X[13];
+            double Sx = (MEH ? q1_stiff_w(cK, X, g.kw) : q1_stiff_sum(cK, X)) + dcn * X[13];
             if (A.mass) Sx += q1_mass(cM, X);
             const double r = bn - Sx;
             if (RESID_ONLY) {
