@@ -948,11 +948,74 @@ __global__ __launch_bounds__(1024) void k_invert_lds(InvBatch ib)
     }
 }
 
+// The same elimination for n <= 64, laid out so that publishing a pivot row
+// and column needs no search: thread t holds column j = t % 64 in rows
+// t / 64 + 16 s (s = 0..3).  Row and column p + 1 and the reciprocal of
+// their diagonal entry are stored, into the other of two buffers, by their
+// holders right after the update of pivot p (wave t / 64 = (p + 1) % 16 the
+// row, lane j = p + 1 of every wave its part of the column), so that one
+// barrier per pivot suffices.  Each entry is updated by the expressions
+// above, so the inverse is the same.
+constexpr int kInvW = 64;
+__global__ __launch_bounds__(1024) void k_invert_w64(InvBatch ib)
+{
+    __shared__ double rowp[2][kInvW], colp[2][kInvW], dp[2];
+    const int box = blockIdx.x;
+    const int n = ib.n[box];
+    const int j = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    double v[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int i = r0 + 16 * s;
+        v[s] = i < n && j < n ? ib.A[box][i * n + j] : 0.0;
+    }
+    // row, column and diagonal reciprocal of pivot q into buffer q & 1
+    auto publish = [&](int q) {
+        const int b = q & 1;
+        if (r0 == (q & 15) && j < n) {
+            const int sq = q >> 4;   // row q's slot in its wave
+            const double a = sq == 0 ? v[0] : (sq == 1 ? v[1] : (sq == 2 ? v[2] : v[3]));
+            rowp[b][j] = a;
+            if (j == q) dp[b] = 1.0 / a;
+        }
+        if (j == q) {
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+                if (r0 + 16 * s < n) colp[b][r0 + 16 * s] = v[s];
+        }
+    };
+    if (n > 0) publish(0);
+    __syncthreads();
+    for (int p = 0; p < n; p++) {
+        const int b = p & 1;
+        const double d = dp[b];
+        const double rp = rowp[b][j] * d;   // (unused where j >= n)
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int i = r0 + 16 * s;
+            if (i >= n || j >= n) continue;
+            double w;
+            if (i == p) w = j == p ? d : rp;
+            else w = j == p ? -colp[b][i] * d : v[s] - colp[b][i] * rp;
+            v[s] = w;
+        }
+        if (p + 1 < n) publish(p + 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+        const int i = r0 + 16 * s;
+        if (i < n && j < n) ib.Ainv[box][i * n + j] = v[s];
+    }
+}
+
 void launch_invert(const InvBatch &ib, hipStream_t st)
 {
     int nmax = 0;
     for (int b = 0; b < ib.nbox; b++) nmax = ib.n[b] > nmax ? ib.n[b] : nmax;
-    if (nmax <= kInvLds)
+    if (nmax <= kInvW)
+        hipLaunchKernelGGL(k_invert_w64, dim3(ib.nbox), dim3(1024), 0, st, ib);
+    else if (nmax <= kInvLds)
         hipLaunchKernelGGL(k_invert_lds, dim3(ib.nbox), dim3(1024), 0, st, ib);
     else
         hipLaunchKernelGGL(k_invert, dim3(ib.nbox), dim3(1024), 0, st, ib);
